@@ -1,0 +1,128 @@
+"""Named synthetic workloads (inputs only).
+
+* ``config_tiny``   -- 0.02 m square plate, 8 x 8 square elements, n_b = 8,
+  N_r = 16, c = 3000 m/s, rho0 = 2700, dt = 5e-8 s, 200 steps, one Ricker
+  source (500 kHz) at mid-top, 8 receivers at the odd top-edge nodes.
+* ``config_paper``  -- 0.1 x 0.05 m plate, 128 x 64 elements, n_b = 16,
+  N_r = 32, dt = 2e-8 s, 4000 steps, 4 sources and 32 receivers on the top
+  edge.
+* ``config_small``  -- a reduced plate used by parity tests at sizes that
+  span several tiles and a ragged tail.
+
+Every model is sampled on the fine grid (one density per element, radial
+level and boundary node).  Seeds are 1000 * config_index + item_index.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, nearest_top_node
+from .models import (fine_point_positions, homogeneous, smoothed_voids, smooth_random_field,
+                     seeded_circle, seeded_ellipses)
+from .signals import ricker
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    c: float
+    rho0: float
+    dt: float
+    n_steps: int
+    src_nodes: np.ndarray          # [n_shots] int64
+    wavelets: np.ndarray           # [n_shots, n_steps] float64
+    rec_nodes: np.ndarray          # [n_rec] int64
+    models: dict = field(default_factory=dict)   # name -> rho [n_params]
+    beta: float = 0.25
+    gamma: float = 0.5
+    xi0: float = 1e-3
+    f0: float = 5e5
+
+    @property
+    def n_shots(self) -> int:
+        return int(self.src_nodes.shape[0])
+
+    def units_per_pass(self) -> int:
+        """Element x radial-level x step x shot count of one forward pass."""
+        return int(self.mesh.n_r.astype(np.int64).sum()) * self.n_steps * self.n_shots
+
+
+def config_tiny(n_steps: int = 200) -> Workload:
+    lx = ly = 0.02
+    mesh = uniform_rect_mesh(lx, ly, 8, 8, segs=2, n_r=16)
+    top = top_edge_nodes(mesh)
+    src = np.asarray([nearest_top_node(mesh, 0.01)], dtype=np.int64)
+    rec = top[1::2].astype(np.int64)
+    dt, f0 = 5e-8, 5e5
+    wav = ricker(n_steps, dt, f0)[None, :]
+    pts = fine_point_positions(mesh)
+    le = lx / 8
+    void = seeded_circle(0 * 1000 + 0, [0.004, 0.004], [0.016, 0.016], 0.002)
+    models = {
+        "homogeneous": homogeneous(mesh, 2700.0),
+        "void_floor_half": smoothed_voids(pts, void, 2700.0, 0.5, le / 16),
+        "random30": smooth_random_field(pts, 0 * 1000 + 1, 2700.0, 0.3),
+        "void_data": smoothed_voids(pts, void, 2700.0, 1e-5, le / 16),
+    }
+    return Workload("tiny-8x8-nb8-nr16", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models)
+
+
+def config_paper(n_steps: int = 4000, n_shots: int = 4) -> Workload:
+    lx, ly = 0.1, 0.05
+    mesh = uniform_rect_mesh(lx, ly, 128, 64, segs=4, n_r=32)
+    xs = [lx * (k + 0.5) / n_shots for k in range(n_shots)]
+    src = np.asarray([nearest_top_node(mesh, x) for x in xs], dtype=np.int64)
+    rec = np.asarray([nearest_top_node(mesh, lx * (k + 0.5) / 32) for k in range(32)], dtype=np.int64)
+    dt, f0 = 2e-8, 5e5
+    wav = np.repeat(ricker(n_steps, dt, f0)[None, :], n_shots, axis=0)
+    pts = fine_point_positions(mesh)
+    le = lx / 128
+    ell = seeded_ellipses(1 * 1000 + 0, 2, (lx, ly), 0.002, 0.006, 2 * le)
+    models = {
+        "homogeneous": homogeneous(mesh, 2700.0),
+        "voids_floor_half": smoothed_voids(pts, ell, 2700.0, 0.5, le / 32),
+        "random30": smooth_random_field(pts, 1 * 1000 + 1, 2700.0, 0.3),
+    }
+    return Workload("paper-128x64-nb16-nr32", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models)
+
+
+def config_small(nx: int = 12, ny: int = 6, segs: int = 3, n_r: int = 12, n_steps: int = 60,
+                 n_shots: int = 3, dt: float = 2e-8) -> Workload:
+    """Reduced plate: several element tiles, n_b = 4 * segs, a few shots."""
+    lx, ly = 0.1 * nx / 128 * 4, 0.05 * ny / 64 * 4
+    mesh = uniform_rect_mesh(lx, ly, nx, ny, segs=segs, n_r=n_r)
+    xs = [lx * (k + 0.5) / n_shots for k in range(n_shots)]
+    src = np.asarray([nearest_top_node(mesh, x) for x in xs], dtype=np.int64)
+    top = top_edge_nodes(mesh)
+    rec = top[1::3].astype(np.int64)
+    f0 = 5e5
+    wav = np.stack([ricker(n_steps, dt, f0, t0=(1.5 + 0.1 * s) / f0) for s in range(n_shots)])
+    pts = fine_point_positions(mesh)
+    models = {
+        "homogeneous": homogeneous(mesh, 2700.0),
+        "random30": smooth_random_field(pts, 2 * 1000 + 1, 2700.0, 0.3, wavelength=lx / 3),
+    }
+    return Workload(f"small-{nx}x{ny}-nb{4*segs}-nr{n_r}", mesh, 3000.0, 2700.0, dt, n_steps,
+                    src, wav, rec, models)
+
+
+def config_quadtree_tiny(n_steps: int = 40) -> Workload:
+    """A small ragged quadtree (n_b and N_r vary per element) for parity tests."""
+    lx, ly = 0.02, 0.01
+    mesh = quadtree_mesh(lx, ly, base_level=2, max_level=4, refine_centres=[(0.011, 0.004)],
+                         refine_radius=0.003, n_b_max=24, n_r_max=12, n_r_min=4)
+    src = np.asarray([nearest_top_node(mesh, 0.008)], dtype=np.int64)
+    top = top_edge_nodes(mesh)
+    rec = top[::2].astype(np.int64)
+    dt, f0 = 2e-8, 5e5
+    wav = ricker(n_steps, dt, f0)[None, :]
+    pts = fine_point_positions(mesh)
+    models = {
+        "homogeneous": homogeneous(mesh, 2700.0),
+        "random30": smooth_random_field(pts, 3 * 1000 + 1, 2700.0, 0.3, wavelength=0.006),
+    }
+    return Workload("quadtree-tiny", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models)
