@@ -1,0 +1,200 @@
+/*
+ * sbfwi.h -- C ABI of the MI355X (gfx950) hot path of full-waveform inversion
+ * with the scaled boundary finite element method and radial discretisation
+ * (Daneshyar & Kollmannsberger, "Full-waveform inversion via the scaled
+ * boundary finite element method").
+ *
+ * Conventions (apply to every call below)
+ * ---------------------------------------
+ * - Every function returns int: SBFWI_OK (0) or a negative error code; it
+ *   never throws.  sbfwi_last_error() returns a thread-local message for the
+ *   last failure on the calling thread.
+ * - Pointers named host_* are host memory; every other array pointer is
+ *   device memory owned by the caller (e.g. a torch tensor).  The library owns
+ *   only the internals of the opaque handles; their device memory comes from
+ *   hipMalloc, or from the allocator registered with sbfwi_set_allocator.
+ * - Every device call takes a hipStream_t (0 = the null stream) and is
+ *   asynchronous on that stream unless stated otherwise.  Calls that return
+ *   a handle synchronise the stream before returning.
+ * - FP64 throughout.  Integers: int64_t for global indices and offsets.
+ *
+ * Fine-grid layout (density rho and gradient): element e occupies
+ * [off_e, off_e + N_r,e * n_b,e), level-major: rho[off_e + j * n_b,e + k] is
+ * the density at radial level j (j = 0 at xi0 near the scaling centre,
+ * j = N_r,e - 1 on the boundary) and boundary node k (position k of the
+ * element's counter-clockwise loop).  Boundary-level densities are per
+ * element.  off_e = sum_{e' < e} N_r,e' n_b,e'.
+ */
+#ifndef SBFWI_H
+#define SBFWI_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbfwi_mesh_s*    sbfwi_mesh;     /* topology, element loops, coarse pattern   */
+typedef struct sbfwi_factors_s* sbfwi_factors;  /* factored model for one (mesh, rho, c, dt) */
+typedef struct sbfwi_ckpt_s*    sbfwi_ckpt;     /* checkpointed forward run (all shots)      */
+
+enum {
+  SBFWI_OK = 0,
+  SBFWI_EINVAL = -1,      /* bad argument, or a loop that is not CCW / star-convex           */
+  SBFWI_ENOMEM = -2,      /* device allocation failed                                         */
+  SBFWI_ESINGULAR = -3,   /* a pivot block of the condensation sweep is singular              */
+  SBFWI_ENONFINITE = -4,  /* a non-finite wavefield value was detected (step in last_error)   */
+  SBFWI_EUNSTABLE = -5,   /* the wavefield grew beyond the stability envelope (step in msg)   */
+  SBFWI_ENOCONV = -6,     /* the coarse Krylov solve did not converge (step in last_error)    */
+  SBFWI_EHIP = -7         /* a HIP runtime call failed                                        */
+};
+
+enum { SBFWI_SCHEME_PAPER_FD = 0 };
+enum { SBFWI_GRAD_EXACT = 0, SBFWI_GRAD_PAPER_KERNEL = 1 };
+
+/* Message of the last failure on this thread ("" if none). */
+const char* sbfwi_last_error(void);
+
+/* Optional device allocator for handle internals (NULL, NULL restores hipMalloc/hipFree).
+ * alloc(bytes, ctx) returns device memory or NULL; free(ptr, ctx) releases it. */
+int sbfwi_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx),
+                        void (*free_fn)(void* ptr, void* ctx), void* ctx);
+
+/*
+ * sbfwi_build_mesh -- geometry of scaled-boundary polygons (Section "Scaled
+ * boundary discretization": the scaling-centre transformation, boundary
+ * interpolation by linear segments between consecutive loop nodes).
+ *   host_node_xy    [n_nodes][2] node coordinates.
+ *   host_elem_ptr   [n_elem + 1] offsets into host_elem_nodes.
+ *   host_elem_nodes counter-clockwise loop of each element (global node ids),
+ *                   3 <= n_b <= 24 nodes per element.
+ *   host_centre_xy  [n_elem][2] scaling centres, or NULL for the area centroid.
+ *   host_n_r        [n_elem] radial levels per element, 3 <= N_r <= 128.
+ *   xi0             radial coordinate of the innermost level (the paper uses
+ *                   1e-3 in place of the singular centre xi = 0).
+ * Levels are xi_j = xi0 + j (1 - xi0) / (N_r - 1).  Every segment must have
+ * a positive det J_b (the centre sees the loop counter-clockwise), else
+ * SBFWI_EINVAL.  Builds the node -> (element, slot) map used to assemble
+ * element sources by gather, and the sparsity pattern of the coarse matrix.
+ * Synchronous; *out is owned by the caller (sbfwi_destroy_mesh).
+ */
+int sbfwi_build_mesh(const double* host_node_xy, int64_t n_nodes,
+                     const int64_t* host_elem_ptr, const int64_t* host_elem_nodes,
+                     int64_t n_elem, const double* host_centre_xy,
+                     const int32_t* host_n_r, double xi0, sbfwi_mesh* out);
+
+/* Sizes of a mesh: host_out[0] = n_nodes, [1] = n_elem, [2] = n_params (fine grid),
+ * [3] = nnz of the coarse matrix, [4] = interior level-node count sum_e (N_r - 1) n_b. */
+int sbfwi_mesh_info(sbfwi_mesh m, int64_t* host_out);
+
+/*
+ * sbfwi_factor_elements -- once per model (rho, c, dt): for every element
+ * builds the coefficient matrices E0, E1, E2, M0 at each radial level from
+ * the boundary Jacobian and the nodal densities (eq. Es), their radial
+ * differences (central inside, one-sided at the end levels), the
+ * Newmark-discretised three-point block rows theta, phi, psi and the ghost
+ * rows of the flux boundary conditions (eq. system), then eliminates the
+ * block system level by level as in the paper's condensation to obtain the
+ * pivot blocks, the dynamic stiffness S_e and the source map; finally
+ * assembles the coarse matrix K_g = sum_e L_e^T S_e L_e on the fixed pattern.
+ *   rho     device [n_params] fine-grid density (layout above), > 0.
+ *   c       wave speed; dt, beta, gamma the Newmark parameters (beta > 0).
+ *   scheme  SBFWI_SCHEME_PAPER_FD (central differences in xi).
+ *   coarse_solver 0 = BiCGStab with Jacobi preconditioning (K_g is not
+ *           symmetric); other values are rejected.
+ * Synchronises s.  SBFWI_ESINGULAR if a pivot block cannot be inverted.
+ * The factors keep a reference to m, which must outlive them.
+ */
+int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, double dt,
+                          double beta, double gamma, int scheme, int coarse_solver,
+                          hipStream_t s, sbfwi_factors* out);
+
+/* Solver controls: relative residual tolerance (default 1e-13) and iteration cap (default 500). */
+int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
+
+/*
+ * Copies factor data to host memory (for inspection and tests), synchronous.
+ *   which = 0: S_e of every element, element after element, row-major n_b x n_b
+ *              (sum_e n_b^2 doubles);
+ *   which = 1: values of K_g on the CSR pattern of sbfwi_coarse_pattern (nnz doubles);
+ *   which = 2: the stored pivot inverses phi~_j^-1, j = 0 .. N_r-2, of every element,
+ *              row-major (sum_e (N_r - 1) n_b^2 doubles);
+ *   which = 3: G_e = psi_{n+1} psi_n^-1 of every element (sum_e n_b^2 doubles).
+ * host_dst must hold the documented count.
+ */
+int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* host_dst);
+
+/* CSR pattern of K_g: host_row_ptr [n_nodes + 1], host_col [nnz]. Synchronous. */
+int sbfwi_coarse_pattern(sbfwi_mesh m, int64_t* host_row_ptr, int64_t* host_col);
+
+/*
+ * sbfwi_forward -- time loop of the condensed scheme for n_shots shots
+ * (Section "Radial discretization": forward sweep of the Newmark residual
+ * sources, effective element sources, coarse nodal solve, backward sweep of
+ * the interior levels and Newmark update at every level).  Zero initial
+ * conditions.  In step k (k = 1 .. n_steps) shot q applies the nodal point
+ * force wavelet[q * n_steps + k - 1] at node src_node[q] and records
+ * traces[(q * n_rec + r) * n_steps + k - 1] = u^k at node rec_node[r].
+ *   src_node [n_shots], rec_node [n_rec]: device int64 node ids.
+ *   wavelet  device [n_shots][n_steps]; traces device [n_shots][n_rec][n_steps].
+ *   n_ckpt   0: no checkpoints (ckpt_out may be NULL); > 0: states kept every
+ *            ceil(n_steps / n_ckpt) steps; -1: ceil(sqrt(n_steps)) of them;
+ *            n_ckpt >= n_steps stores every step (full storage).
+ *   ckpt_out receives the checkpoint handle (needed by sbfwi_adjoint /
+ *            sbfwi_gradient), or NULL.
+ * Synchronises s at the end.  SBFWI_ENOCONV if the coarse solve fails,
+ * SBFWI_ENONFINITE / SBFWI_EUNSTABLE if the wavefield blows up.
+ */
+int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps,
+                  const int64_t* src_node, const double* wavelet,
+                  int n_rec, const int64_t* rec_node, double* traces,
+                  int n_ckpt, sbfwi_ckpt* ckpt_out, hipStream_t s);
+
+/*
+ * sbfwi_adjoint -- backward pass for the shots of a checkpointed forward run:
+ * forward segments are recomputed from the checkpoints in reverse order and
+ * the adjoint state is stepped back in time.
+ *   adj_src device [n_shots][n_rec][n_steps]: derivative of the objective with
+ *           respect to each recorded trace sample (for the misfit of
+ *           eq. misfit this is dt (u - d)).
+ *   mode    SBFWI_GRAD_EXACT: exact derivative of the discrete objective with
+ *           respect to every fine-grid density (transposed condensation,
+ *           transposed coarse solve, zero-lag correlation of the adjoint rows
+ *           with the forward unknowns);
+ *           SBFWI_GRAD_PAPER_KERNEL: the paper's truncated Frechet kernel
+ *           (time integral of the product of forward and back-propagated
+ *           velocities at every fine-grid point; the back-propagated field is
+ *           the forward scheme driven by the time-reversed adj_src at the
+ *           receivers; sign -1 so that it points along the exact gradient).
+ *   grad    device [n_params], overwritten with the sum over shots.
+ * Synchronises s at the end.
+ */
+int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_src, int mode,
+                  double* grad, hipStream_t s);
+
+/*
+ * sbfwi_gradient -- misfit of eq. misfit, 1/2 sum_shot sum_rec sum_k dt (u - d)^2,
+ * into misfit[0] (device), and its gradient via sbfwi_adjoint with
+ * adj_src = dt (traces - observed).
+ *   observed, traces device [n_shots][n_rec][n_steps] (traces from the run that
+ *   made ck).
+ */
+int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
+                   const double* traces, int mode, double* misfit, double* grad,
+                   hipStream_t s);
+
+/* Checkpoint store footprint in bytes (host_out[0]) and checkpoint interval (host_out[1]). */
+int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* host_out);
+
+/* Device bytes a factored model holds (host_out[0]). */
+int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
+
+void sbfwi_destroy_mesh(sbfwi_mesh m);
+void sbfwi_destroy_factors(sbfwi_factors f);
+void sbfwi_destroy_ckpt(sbfwi_ckpt ck);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBFWI_H */

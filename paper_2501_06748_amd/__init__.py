@@ -1,0 +1,190 @@
+"""MI355X (gfx950) hot path of SBFEM full-waveform inversion with radial discretisation.
+
+Thin Python binding of the C ABI in include/sbfwi.h.  The functions below
+carry the ABI's names and only marshal arguments: host arrays are NumPy,
+device arrays are torch CUDA (ROCm) tensors whose data pointers and the
+current HIP stream are passed through.  Every step of the path runs in the
+HIP kernels of libsbfwi.so; without the built library nothing here runs.
+
+Higher layers in this package:
+  ``autograd``  -- torch.autograd.Function over forward + adjoint gradient;
+  ``lbfgs``     -- the outer L-BFGS loop with box constraints;
+  ``serving``   -- continuous-batching request loop with HBM admission;
+  ``batching``  -- multi-shot batched stepping and tile autotuning helpers.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from ._abi import SbfwiError, check, lib
+
+SCHEME_PAPER_FD = 0
+GRAD_EXACT = 0
+GRAD_PAPER_KERNEL = 1
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dptr(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _hptr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def close(self):
+        if self.ptr:
+            getattr(lib(), self._destroy)(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        if not self.ptr:
+            raise ValueError("handle is closed")
+        return self.ptr
+
+
+class MeshHandle(_Handle):
+    _destroy = "sbfwi_destroy_mesh"
+
+
+class FactorsHandle(_Handle):
+    _destroy = "sbfwi_destroy_factors"
+
+    def __init__(self, ptr, mesh):
+        super().__init__(ptr)
+        self.mesh = mesh   # the factors reference the mesh, keep it alive
+
+
+class CkptHandle(_Handle):
+    _destroy = "sbfwi_destroy_ckpt"
+
+    def __init__(self, ptr, factors):
+        super().__init__(ptr)
+        self.factors = factors
+
+
+def sbfwi_last_error() -> str:
+    return lib().sbfwi_last_error().decode()
+
+
+def sbfwi_build_mesh(node_xy, elem_ptr, elem_nodes, n_r, centre_xy=None, xi0=1e-3) -> MeshHandle:
+    xy, pxy = _hptr(node_xy, np.float64)
+    ep, pep = _hptr(elem_ptr, np.int64)
+    en, pen = _hptr(elem_nodes, np.int64)
+    nr, pnr = _hptr(n_r, np.int32)
+    pc = None
+    if centre_xy is not None:
+        cc, pc = _hptr(centre_xy, np.float64)
+    out = C.c_void_p()
+    check(lib().sbfwi_build_mesh(pxy, xy.shape[0], pep, pen, ep.shape[0] - 1, pc, pnr, float(xi0), C.byref(out)))
+    return MeshHandle(out.value)
+
+
+def sbfwi_mesh_info(m: MeshHandle) -> dict:
+    buf = np.zeros(5, dtype=np.int64)
+    check(lib().sbfwi_mesh_info(m, buf.ctypes.data_as(C.c_void_p)))
+    return {"n_nodes": int(buf[0]), "n_elem": int(buf[1]), "n_params": int(buf[2]), "nnz": int(buf[3]),
+            "n_interior": int(buf[4])}
+
+
+def sbfwi_factor_elements(m: MeshHandle, rho, c, dt, beta=0.25, gamma=0.5, scheme=SCHEME_PAPER_FD,
+                          coarse_solver=0, stream=None) -> FactorsHandle:
+    import torch
+    out = C.c_void_p()
+    check(lib().sbfwi_factor_elements(m, _dptr(rho, torch.float64, "rho"), float(c), float(dt), float(beta),
+                                      float(gamma), int(scheme), int(coarse_solver), _stream(stream),
+                                      C.byref(out)))
+    return FactorsHandle(out.value, m)
+
+
+def sbfwi_set_solver(f: FactorsHandle, rtol=1e-13, max_iter=500):
+    check(lib().sbfwi_set_solver(f, float(rtol), int(max_iter)))
+
+
+def sbfwi_copy_factor_data(f: FactorsHandle, which: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.float64)
+    check(lib().sbfwi_copy_factor_data(f, int(which), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def sbfwi_coarse_pattern(m: MeshHandle):
+    info = sbfwi_mesh_info(m)
+    rp = np.empty(info["n_nodes"] + 1, dtype=np.int64)
+    col = np.empty(info["nnz"], dtype=np.int64)
+    check(lib().sbfwi_coarse_pattern(m, rp.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p)))
+    return rp, col
+
+
+def sbfwi_forward(f: FactorsHandle, src_node, wavelet, rec_node, traces, n_ckpt=0, stream=None):
+    """src_node [S] int64, wavelet [S, N_t] f64, rec_node [R] int64, traces [S, R, N_t] f64 (device)."""
+    import torch
+    n_shots, n_steps = int(wavelet.shape[0]), int(wavelet.shape[1])
+    n_rec = int(rec_node.shape[0])
+    if traces.shape != (n_shots, n_rec, n_steps) or src_node.shape != (n_shots,):
+        raise ValueError("shape mismatch between src_node, wavelet, rec_node and traces")
+    out = C.c_void_p()
+    check(lib().sbfwi_forward(f, n_shots, n_steps, _dptr(src_node, torch.int64, "src_node"),
+                              _dptr(wavelet, torch.float64, "wavelet"), n_rec,
+                              _dptr(rec_node, torch.int64, "rec_node"), _dptr(traces, torch.float64, "traces"),
+                              int(n_ckpt), C.byref(out) if n_ckpt != 0 else None, _stream(stream)))
+    return CkptHandle(out.value, f) if n_ckpt != 0 else None
+
+
+def sbfwi_adjoint(f: FactorsHandle, ck: CkptHandle, adj_src, mode, grad, stream=None):
+    import torch
+    check(lib().sbfwi_adjoint(f, ck, _dptr(adj_src, torch.float64, "adj_src"), int(mode),
+                              _dptr(grad, torch.float64, "grad"), _stream(stream)))
+
+
+def sbfwi_gradient(f: FactorsHandle, ck: CkptHandle, observed, traces, mode, misfit, grad, stream=None):
+    import torch
+    check(lib().sbfwi_gradient(f, ck, _dptr(observed, torch.float64, "observed"),
+                               _dptr(traces, torch.float64, "traces"), int(mode),
+                               _dptr(misfit, torch.float64, "misfit"), _dptr(grad, torch.float64, "grad"),
+                               _stream(stream)))
+
+
+def sbfwi_ckpt_info(ck: CkptHandle) -> dict:
+    buf = np.zeros(2, dtype=np.int64)
+    check(lib().sbfwi_ckpt_info(ck, buf.ctypes.data_as(C.c_void_p)))
+    return {"bytes": int(buf[0]), "interval": int(buf[1])}
+
+
+def sbfwi_factors_info(f: FactorsHandle) -> dict:
+    buf = np.zeros(1, dtype=np.int64)
+    check(lib().sbfwi_factors_info(f, buf.ctypes.data_as(C.c_void_p)))
+    return {"bytes": int(buf[0])}
+
+
+__all__ = [n for n in dir() if n.startswith("sbfwi_")] + ["SbfwiError", "MeshHandle", "FactorsHandle",
+                                                          "CkptHandle", "GRAD_EXACT", "GRAD_PAPER_KERNEL"]

@@ -1,0 +1,586 @@
+// Backward pass: exact discrete adjoint and the paper's truncated kernel.
+//
+// Step k of the forward scheme solves A X^k = P w^{k-1} + F^k for the
+// uncondensed unknowns X (levels -1 .. n+1 of every element, level n shared
+// at the nodes; eq. system) and updates velocity and acceleration (eq.
+// Newmark).  Its exact reverse, given the adjoint seeds (u-bar, v-bar, a-bar)
+// of the state after step k, is
+//   u~ = u-bar + c1 v-bar + a0 a-bar (+ dt (u - d) at the receivers),
+//   lambda = A^-T u~,
+//   w-bar = P^T lambda - a-bar,
+//   seeds of step k-1: u-bar = -c1 v-bar + a0 w-bar, v-bar = c2 v-bar + a1 w-bar,
+//   a-bar = c3 v-bar + a2 w-bar,
+// and the gradient gains -lambda^T (dA_stiff/drho) X^k + xi^2 lambda^T (dM0/drho) a^k
+// (the a0 M0 part of A and P combine into the acceleration a^k = a0 u^k - w^{k-1}).
+//
+// A^-T reuses the forward factors transposed.  With the paper's block
+// elimination A = L U (pivots theta_{-1}, phi~_0 .. phi~_{n-1}, psi_n, S), the
+// transposed solve is U^T z = u~ swept upwards (z_j = phi~_j^-T (u~_j - psi~_{j-1}^T
+// z_{j-1})), the coarse system K_g^T lambda_B = u~_B - sum_e psi_{n-1}^T z_{n-1},
+// then L^T lambda = z swept downwards: lambda_n = -G^T lambda_{n+1},
+// lambda_j = z_j - phi~_j^-T theta_{j+1}^T lambda_{j+1} (plus theta_{n+1}^T lambda_{n+1}
+// at j = n-1), lambda_{-1} = -theta_{-1}^-T theta_0^T lambda_0.
+//
+// The gradient is the zero-lag correlation of the adjoint rows with the
+// forward unknowns, contracted with the derivatives of the coefficient
+// matrices with respect to the nodal densities of each level (eq. Es is
+// linear in the densities); every thread owns one fine-grid parameter and
+// sums over shots, so the accumulation is deterministic.
+#include "sbfwi_internal.h"
+
+namespace {
+
+__device__ __forceinline__ int md(int i, int nb) { return i < 0 ? i + nb : (i >= nb ? i - nb : i); }
+
+constexpr int WT = 64;
+
+struct AdjArgs {
+  int NS;
+  double *ub, *vb, *ab;     // interior seeds
+  double *UB, *VB, *AB;     // nodal seeds
+  double *z, *gB, *pl, *lamB, *lam;
+};
+
+template <int NBT, int S>
+struct AdjLds {
+  double F[2][NBT * NBT];
+  double x[NBT * S];
+  double y[NBT * S];
+  double t[NBT * S];
+  double l1[NBT * S];
+};
+
+template <int NBT>
+__device__ __forceinline__ void prefetch(double (&reg)[(NBT * NBT + WT - 1) / WT], const double* src, int nbnb) {
+#pragma unroll
+  for (int r = 0; r < (NBT * NBT + WT - 1) / WT; ++r) {
+    int q = threadIdx.x + r * WT;
+    reg[r] = q < nbnb ? src[q] : 0.0;
+  }
+}
+
+template <int NBT>
+__device__ __forceinline__ void commit(const double (&reg)[(NBT * NBT + WT - 1) / WT], double* dst, int nb) {
+#pragma unroll
+  for (int r = 0; r < (NBT * NBT + WT - 1) / WT; ++r) {
+    int q = threadIdx.x + r * WT;
+    if (q < nb * nb) dst[(q / nb) * NBT + (q % nb)] = reg[r];
+  }
+}
+
+// (B^T x)_i for a band B: B[i-1][i] x_{i-1} + B[i][i] x_i + B[i+1][i] x_{i+1}
+__device__ __forceinline__ double bandT_mv(const double* band, const double* vec, int nb, int i, int s, int S) {
+  int im = md(i - 1, nb), ip = md(i + 1, nb);
+  return band[2 * nb + im] * vec[im * S + s] + band[nb + i] * vec[i * S + s] + band[ip] * vec[ip * S + s];
+}
+
+__device__ __forceinline__ double band_mv(const double* band, const double* vec, int nb, int i, int s, int S) {
+  return band[i] * vec[md(i - 1, nb) * S + s] + band[nb + i] * vec[i * S + s] +
+         band[2 * nb + i] * vec[md(i + 1, nb) * S + s];
+}
+
+template <int NBT>
+__device__ __forceinline__ double denseT_mv(const double* F, const double* vec, int nb, int i, int s, int S) {
+  double acc = 0.0;
+  for (int c = 0; c < nb; ++c) acc += F[c * NBT + i] * vec[c * S + s];
+  return acc;
+}
+
+// U^T sweep: z_j, and the coupling psi~_{n-1}^T z_{n-1} to the coarse rows.
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) adj_condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                          FactorsDev f, AdjArgs a) {
+  __shared__ AdjLds<NBT, S> L;
+  const int e = elems[blockIdx.x];
+  const int s0 = blockIdx.y * S;
+  const int ns = min(S, a.NS - s0);
+  const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
+  const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e];
+  const double* Fe = f.finv + m.finv_off[e];
+  const int items = nb * S;
+  double reg[(NBT * NBT + WT - 1) / WT];
+  prefetch<NBT>(reg, Fe, nbnb);
+  commit<NBT>(reg, L.F[0], nb);
+  int cur = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (j + 1 < n) prefetch<NBT>(reg, Fe + (int64_t)(j + 1) * nbnb, nbnb);
+    // y = u~_j - psi~_{j-1}^T z_{j-1}
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      double y = 0.0;
+      if (s < ns) {
+        int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
+        y = a.ub[g] + f.c1 * a.vb[g] + f.a0 * a.ab[g];
+      }
+      if (j == 1) {
+        const double* P0 = f.psit0 + m.dense_off[e];
+        double acc = 0.0;
+        for (int c = 0; c < nb; ++c) acc += P0[c * nb + i] * L.x[c * S + s];
+        y -= acc;
+      } else if (j > 1) {
+        y -= bandT_mv(f.ps_band + 3 * (po + (int64_t)(j - 1) * nb), L.x, nb, i, s, S);
+      }
+      L.y[it] = y;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      double zv = denseT_mv<NBT>(L.F[cur], L.y, nb, i, s, S);
+      L.t[it] = zv;
+      if (s < ns) a.z[(io + (int64_t)j * nb + i) * a.NS + s0 + s] = zv;
+    }
+    if (j + 1 < n) commit<NBT>(reg, L.F[cur ^ 1], nb);
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += WT) L.x[it] = L.t[it];
+    __syncthreads();
+    cur ^= 1;
+  }
+  // coupling to the coarse rows: psi_{n-1}^T z_{n-1} (n >= 2, so psi~_{n-1} = psi_{n-1})
+  const double* psn1 = f.ps_band + 3 * (po + (int64_t)(n - 1) * nb);
+  for (int it = threadIdx.x; it < items; it += WT) {
+    int i = it / S, s = it % S;
+    if (s < ns) a.gB[(lo + i) * a.NS + s0 + s] = bandT_mv(psn1, L.x, nb, i, s, S);
+  }
+}
+
+// L^T sweep, adjoint Newmark chain at the interior levels, and P_n^T lambda_n.
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                         FactorsDev f, AdjArgs a) {
+  __shared__ AdjLds<NBT, S> L;
+  const int e = elems[blockIdx.x];
+  const int s0 = blockIdx.y * S;
+  const int ns = min(S, a.NS - s0);
+  const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
+  const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e], xo = m.x_off[e];
+  const int64_t dofs = m.dense_off[e];
+  const double* Fe = f.finv + m.finv_off[e];
+  const int items = nb * S;
+  double reg[(NBT * NBT + WT - 1) / WT];
+  prefetch<NBT>(reg, f.G + dofs, nbnb);
+  commit<NBT>(reg, L.F[0], nb);
+  for (int it = threadIdx.x; it < items; it += WT) {
+    int i = it / S, s = it % S;
+    L.l1[it] = s < ns ? a.lamB[m.loop_nodes[lo + i] * a.NS + s0 + s] : 0.0;   // lambda_{n+1}
+  }
+  prefetch<NBT>(reg, Fe + (int64_t)(n - 1) * nbnb, nbnb);
+  __syncthreads();
+  // lambda_n = -G^T lambda_{n+1}
+  for (int it = threadIdx.x; it < items; it += WT) {
+    int i = it / S, s = it % S;
+    L.x[it] = -denseT_mv<NBT>(L.F[0], L.l1, nb, i, s, S);
+  }
+  __syncthreads();
+  commit<NBT>(reg, L.F[1], nb);
+  const double* pmn = f.pm_band + 3 * (po + (int64_t)n * nb);
+  for (int it = threadIdx.x; it < items; it += WT) {
+    int i = it / S, s = it % S;
+    if (s < ns) {
+      a.pl[(lo + i) * a.NS + s0 + s] = bandT_mv(pmn, L.x, nb, i, s, S);
+      if (a.lam) {
+        a.lam[(xo + (int64_t)(n + 2) * nb + i) * a.NS + s0 + s] = L.l1[it];
+        a.lam[(xo + (int64_t)(n + 1) * nb + i) * a.NS + s0 + s] = L.x[it];
+      }
+    }
+  }
+  int cur = 1;
+  __syncthreads();
+  for (int j = n - 1; j >= 0; --j) {
+    if (j > 0) prefetch<NBT>(reg, Fe + (int64_t)(j - 1) * nbnb, nbnb);
+    // t = theta_{j+1}^T lambda_{j+1} (+ theta_{n+1}^T lambda_{n+1} when j = n-1)
+    const double* thj1 = f.th_band + 3 * (po + (int64_t)(j + 1) * nb);
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      double tv = bandT_mv(thj1, L.x, nb, i, s, S);
+      if (j == n - 1) tv += bandT_mv(f.th_np1 + 3 * lo, L.l1, nb, i, s, S);
+      L.t[it] = tv;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      double lv = 0.0;
+      if (s < ns) {
+        int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
+        lv = a.z[g] - denseT_mv<NBT>(L.F[cur], L.t, nb, i, s, S);
+      }
+      L.y[it] = lv;
+    }
+    if (j > 0) commit<NBT>(reg, L.F[cur ^ 1], nb);
+    __syncthreads();
+    // adjoint Newmark chain at level j: w-bar = P_j^T lambda_j - a-bar
+    const double* pmj = f.pm_band + 3 * (po + (int64_t)j * nb);
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      if (s < ns) {
+        int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
+        double vb = a.vb[g];
+        double wb = bandT_mv(pmj, L.y, nb, i, s, S) - a.ab[g];
+        a.ub[g] = -f.c1 * vb + f.a0 * wb;
+        a.vb[g] = f.c2 * vb + f.a1 * wb;
+        a.ab[g] = f.c3 * vb + f.a2 * wb;
+        if (a.lam) a.lam[(xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s] = L.y[it];
+      }
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += WT) L.x[it] = L.y[it];
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (!a.lam) return;
+  // lambda_{-1} = -theta_{-1}^-T theta_0^T lambda_0
+  const double* th0 = f.th_band + 3 * po;
+  for (int it = threadIdx.x; it < items; it += WT) L.t[it] = bandT_mv(th0, L.x, nb, it / S, it % S, S);
+  __syncthreads();
+  const double* Tm = f.thm1_inv + dofs;
+  for (int it = threadIdx.x; it < items; it += WT) {
+    int i = it / S, s = it % S;
+    double acc = 0.0;
+    for (int c = 0; c < nb; ++c) acc += Tm[c * nb + i] * L.t[c * S + s];
+    if (s < ns) a.lam[(xo + i) * a.NS + s0 + s] = -acc;
+  }
+}
+
+// rhs_B = u~_B - sum_e psi_{n-1}^T z_{n-1} + adjoint source at the receivers.
+__global__ void adj_rhs_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a, double* __restrict__ rhs,
+                               int n_rec, const int64_t* __restrict__ rec_node, const double* __restrict__ adj,
+                               int64_t n_steps, int64_t k) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m.n_nodes * NS) return;
+  int64_t node = g / NS;
+  int s = (int)(g % NS);
+  double acc = a.UB[g] + f.c1 * a.VB[g] + f.a0 * a.AB[g];
+  for (int64_t t = m.node_ptr[node]; t < m.node_ptr[node + 1]; ++t) acc -= a.gB[m.node_slot[t] * NS + s];
+  if (adj)
+    for (int r = 0; r < n_rec; ++r)
+      if (rec_node[r] == node) acc += adj[((int64_t)s * n_rec + r) * n_steps + k - 1];
+  rhs[g] = acc;
+}
+
+// Nodal adjoint Newmark chain.
+__global__ void adj_nodal_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m.n_nodes * NS) return;
+  int64_t node = g / NS;
+  int s = (int)(g % NS);
+  double wb = -a.AB[g];
+  for (int64_t t = m.node_ptr[node]; t < m.node_ptr[node + 1]; ++t) wb += a.pl[m.node_slot[t] * NS + s];
+  double vb = a.VB[g];
+  a.UB[g] = -f.c1 * vb + f.a0 * wb;
+  a.VB[g] = f.c2 * vb + f.a1 * wb;
+  a.AB[g] = f.c3 * vb + f.a2 * wb;
+}
+
+struct GradCtx {
+  int nb, n, NS, s;
+  double xi0, h;
+  int64_t xo;
+  const double* X;
+  const double* lam;
+  __device__ double Xv(int l, int i) const { return X[(xo + (int64_t)(l + 1) * nb + i) * NS + s]; }
+  __device__ double Lv(int r, int i) const { return lam[(xo + (int64_t)(r + 1) * nb + i) * NS + s]; }
+  __device__ double xi(int j) const { return xi0 + h * j; }
+  // FD weight of level m in the radial derivative at row r (one-sided at the ends)
+  __device__ double dw(int r, int m) const {
+    if (r == 0) return m == 0 ? -1.0 / h : (m == 1 ? 1.0 / h : 0.0);
+    if (r == n) return m == n - 1 ? -1.0 / h : (m == n ? 1.0 / h : 0.0);
+    return m == r - 1 ? -0.5 / h : (m == r + 1 ? 0.5 / h : 0.0);
+  }
+  // entry (i, j) of the sensitivity of the misfit-Lagrangian to E^tau at level m
+  __device__ double ebar(int tau, int m, int i, int j) const {
+    double v = 0.0;
+    if (tau == 2) return -Lv(m, i) * Xv(m, j);
+    const double xm = xi(m);
+    {  // row m itself
+      double dj = Xv(m + 1, j) - Xv(m - 1, j);
+      if (tau == 0) {
+        double lap = Xv(m - 1, j) - 2.0 * Xv(m, j) + Xv(m + 1, j);
+        v += Lv(m, i) * (xm * xm / (h * h) * lap + xm / (2.0 * h) * dj);
+      } else {
+        double di = Xv(m + 1, i) - Xv(m - 1, i);
+        v += xm / (2.0 * h) * (di * Lv(m, j) - Lv(m, i) * dj);
+      }
+    }
+    for (int r = m - 1; r <= m + 1; ++r) {  // rows whose radial derivative uses level m
+      if (r < 0 || r > n) continue;
+      double w = dw(r, m);
+      if (w == 0.0) continue;
+      double xr = xi(r);
+      if (tau == 0) v += w * xr * xr / (2.0 * h) * Lv(r, i) * (Xv(r + 1, j) - Xv(r - 1, j));
+      else v += w * xr * Xv(r, i) * Lv(r, j);
+    }
+    if (m == 0) {  // flux row at xi0
+      if (tau == 0) v += xi(0) / (2.0 * h) * Lv(-1, i) * (Xv(1, j) - Xv(-1, j));
+      else v += Xv(0, i) * Lv(-1, j);
+    }
+    if (m == n) {  // flux row at the boundary
+      if (tau == 0) v += xi(n) / (2.0 * h) * Lv(n + 1, i) * (Xv(n + 1, j) - Xv(n - 1, j));
+      else v += Xv(n, i) * Lv(n + 1, j);
+    }
+    return v;
+  }
+};
+
+// One thread per fine-grid parameter (element e, level m, node k).
+__global__ void grad_exact_kernel(MeshDev m, FactorsDev f, int NS, int64_t n_params, const int32_t* __restrict__ par_elem,
+                                  const double* __restrict__ X, const double* __restrict__ lam,
+                                  const double* __restrict__ acc_a, double* __restrict__ grad) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_params) return;
+  const int e = par_elem[p];
+  const int nb = m.nb[e], n = m.nr[e] - 1;
+  const int64_t po = m.par_off[e], lo = m.loop_off[e];
+  const int loc = (int)(p - po);
+  const int lev = loc / nb, kk = loc % nb;
+  const int km = md(kk - 1, nb), kp = md(kk + 1, nb);
+  GradCtx c;
+  c.nb = nb; c.n = n; c.NS = NS; c.xi0 = m.xi0; c.h = (1.0 - m.xi0) / n; c.xo = m.x_off[e];
+  c.X = X; c.lam = lam;
+  const double* gl = f.gbasis + 32 * (lo + km);   // segment kk-1: nodes (km, kk), kk is its end 1
+  const double* gr = f.gbasis + 32 * (lo + kk);   // segment kk: nodes (kk, kp), kk is its end 0
+  const double xm = c.xi(lev);
+  double g = 0.0;
+  for (int s = 0; s < NS; ++s) {
+    c.s = s;
+    double acc = 0.0;
+    for (int tau = 0; tau < 3; ++tau) {
+      const double* al = gl + tau * 8 + 4;
+      const double* ar = gr + tau * 8 + 0;
+      acc -= al[0] * c.ebar(tau, lev, km, km) + al[1] * c.ebar(tau, lev, km, kk) +
+             al[2] * c.ebar(tau, lev, kk, km) + al[3] * c.ebar(tau, lev, kk, kk);
+      acc -= ar[0] * c.ebar(tau, lev, kk, kk) + ar[1] * c.ebar(tau, lev, kk, kp) +
+             ar[2] * c.ebar(tau, lev, kp, kk) + ar[3] * c.ebar(tau, lev, kp, kp);
+    }
+    // mass: xi^2 lambda_m^T dM0 a_m
+    auto A = [&](int i) { return acc_a[(po + (int64_t)lev * nb + i) * NS + s]; };
+    const double* ml = gl + 3 * 8 + 4;
+    const double* mr = gr + 3 * 8 + 0;
+    double lm = c.Lv(lev, km), l0 = c.Lv(lev, kk), lp = c.Lv(lev, kp);
+    acc += xm * xm * (ml[0] * lm * A(km) + ml[1] * lm * A(kk) + ml[2] * l0 * A(km) + ml[3] * l0 * A(kk) +
+                      mr[0] * l0 * A(kk) + mr[1] * l0 * A(kp) + mr[2] * lp * A(kk) + mr[3] * lp * A(kp));
+    g += acc;
+  }
+  grad[p] += g;
+}
+
+// Paper kernel: g -= dt * sum_s v~ v at every fine-grid point.
+__global__ void grad_paper_kernel(MeshDev m, int NS, double dt, int64_t n_params, const int32_t* __restrict__ par_elem,
+                                  const double* __restrict__ vint, const double* __restrict__ Vnod,
+                                  const double* __restrict__ vf, double* __restrict__ grad) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_params) return;
+  const int e = par_elem[p];
+  const int nb = m.nb[e], n = m.nr[e] - 1;
+  const int64_t po = m.par_off[e];
+  const int loc = (int)(p - po);
+  const int lev = loc / nb, k = loc % nb;
+  double g = 0.0;
+  for (int s = 0; s < NS; ++s) {
+    double vl = lev < n ? vint[(m.int_off[e] + (int64_t)lev * nb + k) * NS + s]
+                        : Vnod[m.loop_nodes[m.loop_off[e] + k] * NS + s];
+    g += vl * vf[p * NS + s];
+  }
+  grad[p] -= dt * g;
+}
+
+__global__ void misfit_kernel(const double* __restrict__ tr, const double* __restrict__ ob, int64_t count,
+                              double dt, double* __restrict__ res, double* __restrict__ misfit) {
+  __shared__ double ws[16];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
+    double r = tr[i] - ob[i];
+    res[i] = dt * r;
+    acc += r * r;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += ws[w];
+    misfit[0] = 0.5 * dt * t;
+  }
+}
+
+template <int NBT, int S>
+void launch_adj(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+  int64_t cnt = (int64_t)m->h_class_elems[cl].size();
+  if (cnt == 0) return;
+  dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  if (condense)
+    hipLaunchKernelGGL((adj_condense_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+  else
+    hipLaunchKernelGGL((adj_recover_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+}
+
+template <int S>
+void launch_adj_all(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+  launch_adj<8, S>(condense, m, 0, f, a, st);
+  launch_adj<16, S>(condense, m, 1, f, a, st);
+  launch_adj<24, S>(condense, m, 2, f, a, st);
+}
+
+void launch_adj_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+  if (a.NS >= 4)
+    launch_adj_all<4>(condense, m, f, a, st);
+  else if (a.NS >= 2)
+    launch_adj_all<2>(condense, m, f, a, st);
+  else
+    launch_adj_all<1>(condense, m, f, a, st);
+}
+
+struct AdjWork {
+  double *seeds = nullptr, *z = nullptr, *gB = nullptr, *pl = nullptr, *rhs = nullptr, *lamB = nullptr,
+         *lam = nullptr;
+  int32_t* par_elem = nullptr;
+  CoarseWork cw;
+};
+
+void adj_free(AdjWork* w) {
+  sbfwi_dev_free(w->seeds);
+  sbfwi_dev_free(w->z);
+  sbfwi_dev_free(w->gB);
+  sbfwi_dev_free(w->pl);
+  sbfwi_dev_free(w->rhs);
+  sbfwi_dev_free(w->lamB);
+  sbfwi_dev_free(w->lam);
+  sbfwi_dev_free(w->par_elem);
+  sbfwi_coarse_work_free(&w->cw);
+}
+
+}  // namespace
+
+int sbfwi_misfit_residual(const double* traces, const double* observed, int64_t count, double dt,
+                          double* residual, double* misfit, hipStream_t s) {
+  hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(1024), 0, s, traces, observed, count, dt, residual, misfit);
+  SBFWI_HIP(hipGetLastError());
+  return SBFWI_OK;
+}
+
+static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_src, int mode, double* grad,
+                       hipStream_t st, AdjWork& w, StepWork& fw, StepWork& bw, double* xseg, double* fseg) {
+  sbfwi_mesh_s* m = f->m;
+  const int NS = ck->n_shots;
+  const int64_t N = ck->n_steps, C = ck->interval;
+  const int64_t nn = m->n_nodes * NS;
+  // element of every fine-grid parameter
+  {
+    std::vector<int32_t> pe(m->n_params);
+    for (int64_t e = 0; e < m->n_elem; ++e)
+      for (int64_t p = m->h_par_off[e]; p < m->h_par_off[e + 1]; ++p) pe[p] = (int32_t)e;
+    SBFWI_CHECK(sbfwi_upload(&w.par_elem, pe));
+  }
+  SBFWI_HIP(hipMemsetAsync(grad, 0, sizeof(double) * m->n_params, st));
+  SourceTable fsrc;
+  fsrc.n_src = 1;
+  fsrc.node = ck->src_node;
+  fsrc.node_stride = 1;
+  fsrc.amp = ck->wavelet;
+  fsrc.amp_steps = N;
+  AdjArgs a;
+  a.NS = NS;
+  if (mode == SBFWI_GRAD_EXACT) {
+    int64_t ni = m->n_int * NS;
+    SBFWI_CHECK(sbfwi_alloc(&w.seeds, 3 * ni + 3 * nn));
+    SBFWI_HIP(hipMemsetAsync(w.seeds, 0, sizeof(double) * (3 * ni + 3 * nn), st));
+    a.ub = w.seeds; a.vb = a.ub + ni; a.ab = a.vb + ni;
+    a.UB = a.ab + ni; a.VB = a.UB + nn; a.AB = a.VB + nn;
+    SBFWI_CHECK(sbfwi_alloc(&w.z, ni));
+    SBFWI_CHECK(sbfwi_alloc(&w.gB, m->n_loop * NS));
+    SBFWI_CHECK(sbfwi_alloc(&w.pl, m->n_loop * NS));
+    SBFWI_CHECK(sbfwi_alloc(&w.rhs, nn));
+    SBFWI_CHECK(sbfwi_alloc(&w.lamB, nn));
+    SBFWI_CHECK(sbfwi_alloc(&w.lam, m->n_x * NS));
+    SBFWI_HIP(hipMemsetAsync(w.lamB, 0, sizeof(double) * nn, st));
+    SBFWI_CHECK(sbfwi_coarse_work_alloc(&w.cw, m->n_nodes, NS));
+    a.z = w.z; a.gB = w.gB; a.pl = w.pl; a.lamB = w.lamB; a.lam = w.lam;
+  } else {
+    SBFWI_CHECK(sbfwi_step_work_alloc(&bw, m, NS));
+    SBFWI_CHECK(sbfwi_step_zero(m, &bw, st));
+  }
+  SourceTable bsrc;  // paper kernel: receivers as sources, time-reversed
+  bsrc.n_src = ck->n_rec;
+  bsrc.node = ck->rec_node;
+  bsrc.node_stride = 0;
+  bsrc.amp = adj_src;
+  bsrc.amp_steps = N;
+  bsrc.reversed = 1;
+  const int kind = mode == SBFWI_GRAD_EXACT ? 0 : 1;
+  const int64_t nseg = (N + C - 1) / C;
+  const unsigned gp = (unsigned)((m->n_params + 255) / 256);
+  const unsigned gn = (unsigned)((nn + 255) / 256);
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t k0 = seg * C, k1 = std::min(k0 + C, N);
+    if (!ck->full_store) {
+      SBFWI_CHECK(sbfwi_state_copy(m, &fw, ck->states + seg * sbfwi_state_size(m, NS), 0, st));
+      for (int64_t k = k0 + 1; k <= k1; ++k) {
+        double* xs = xseg + (k - k0 - 1) * m->n_x * NS;
+        double* fs = fseg + (k - k0 - 1) * m->n_params * NS;
+        SBFWI_CHECK(sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, st));
+      }
+    }
+    for (int64_t k = k1; k > k0; --k) {
+      const double* X = ck->full_store ? ck->xstore + (k - 1) * m->n_x * NS : xseg + (k - k0 - 1) * m->n_x * NS;
+      const double* Fs = ck->full_store ? (kind == 0 ? ck->fstore : ck->vstore) + (k - 1) * m->n_params * NS
+                                        : fseg + (k - k0 - 1) * m->n_params * NS;
+      if (mode == SBFWI_GRAD_EXACT) {
+        launch_adj_sweep(true, m, f->d, a, st);
+        hipLaunchKernelGGL(adj_rhs_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a, w.rhs, ck->n_rec,
+                           ck->rec_node, adj_src, N, k);
+        SBFWI_HIP(hipGetLastError());
+        SBFWI_CHECK(sbfwi_coarse_solve(f, &w.cw, 1, w.rhs, w.lamB, k, st));
+        launch_adj_sweep(false, m, f->d, a, st);
+        hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
+        hipLaunchKernelGGL(grad_exact_kernel, dim3(gp), dim3(256), 0, st, m->d, f->d, NS, m->n_params,
+                           w.par_elem, X, (const double*)w.lam, Fs, grad);
+        SBFWI_HIP(hipGetLastError());
+      } else {
+        const int64_t kp = N + 1 - k;  // back-propagation step paired with forward step k
+        SBFWI_CHECK(sbfwi_forward_step(f, &bw, kp, bsrc, 0, nullptr, nullptr, N, nullptr, nullptr, 0, st));
+        hipLaunchKernelGGL(grad_paper_kernel, dim3(gp), dim3(256), 0, st, m->d, NS, f->dt, m->n_params,
+                           w.par_elem, (const double*)bw.v, (const double*)bw.V, Fs, grad);
+        SBFWI_HIP(hipGetLastError());
+      }
+    }
+  }
+  return SBFWI_OK;
+}
+
+int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_src, int mode, double* grad,
+                       hipStream_t st) {
+  sbfwi_mesh_s* m = f->m;
+  const int NS = ck->n_shots;
+  AdjWork w;
+  StepWork fw, bw;
+  double* xseg = nullptr;
+  double* fseg = nullptr;
+  int rc = SBFWI_OK;
+  if (!ck->full_store) {
+    rc = sbfwi_step_work_alloc(&fw, m, NS);
+    if (rc == SBFWI_OK) rc = sbfwi_alloc(&xseg, ck->interval * m->n_x * NS);
+    if (rc == SBFWI_OK) rc = sbfwi_alloc(&fseg, ck->interval * m->n_params * NS);
+  }
+  if (rc == SBFWI_OK) {
+    int flags0[4] = {0, -1, 0, 0};
+    hipError_t he = hipMemcpyAsync(f->d.status, flags0, sizeof(flags0), hipMemcpyHostToDevice, st);
+    if (he != hipSuccess) rc = sbfwi_fail(SBFWI_EHIP, "status reset: %s", hipGetErrorString(he));
+  }
+  if (rc == SBFWI_OK) rc = adjoint_run(f, ck, adj_src, mode, grad, st, w, fw, bw, xseg, fseg);
+  int flags[4] = {0, -1, 0, 0};
+  if (rc == SBFWI_OK) {
+    hipError_t he = hipMemcpyAsync(flags, f->d.status, sizeof(flags), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) rc = sbfwi_fail(SBFWI_EHIP, "adjoint: %s", hipGetErrorString(he));
+  } else {
+    (void)hipStreamSynchronize(st);
+  }
+  adj_free(&w);
+  if (!ck->full_store) sbfwi_step_work_free(&fw);
+  if (bw.u) sbfwi_step_work_free(&bw);
+  sbfwi_dev_free(xseg);
+  sbfwi_dev_free(fseg);
+  if (rc != SBFWI_OK) return rc;
+  if (flags[0] & 4) return sbfwi_fail(SBFWI_ENONFINITE, "non-finite coarse residual at step %d", flags[1]);
+  if (flags[0] & 2) return sbfwi_fail(SBFWI_ENOCONV, "coarse solve did not converge at step %d", flags[1]);
+  return SBFWI_OK;
+}

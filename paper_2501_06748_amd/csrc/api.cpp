@@ -1,0 +1,240 @@
+// Exported C ABI: argument checks, handle lifetimes, the forward driver with
+// checkpointing, and error reporting.  Every computation runs in the HIP
+// kernels of factor.hip, step.hip, coarse.hip and adjoint.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "sbfwi_internal.h"
+
+static thread_local char g_err[1024] = "";
+static void* (*g_alloc)(size_t, void*) = nullptr;
+static void (*g_free)(void*, void*) = nullptr;
+static void* g_alloc_ctx = nullptr;
+
+int sbfwi_fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void* sbfwi_dev_alloc(size_t bytes) {
+  if (g_alloc) return g_alloc(bytes, g_alloc_ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void sbfwi_dev_free(void* p) {
+  if (!p) return;
+  if (g_free)
+    g_free(p, g_alloc_ctx);
+  else
+    (void)hipFree(p);
+}
+
+void sbfwi_factors_free(sbfwi_factors_s* f);
+
+extern "C" const char* sbfwi_last_error(void) { return g_err; }
+
+extern "C" int sbfwi_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return sbfwi_fail(SBFWI_EINVAL, "allocator and deallocator must be given together");
+  g_alloc = alloc_fn;
+  g_free = free_fn;
+  g_alloc_ctx = ctx;
+  return SBFWI_OK;
+}
+
+extern "C" int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, double dt, double beta,
+                                     double gamma, int scheme, int coarse_solver, hipStream_t s,
+                                     sbfwi_factors* out) {
+  if (!out) return sbfwi_fail(SBFWI_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!m || !rho) return sbfwi_fail(SBFWI_EINVAL, "NULL mesh or density");
+  if (!(c > 0) || !(dt > 0) || !(beta > 0) || !(gamma > 0))
+    return sbfwi_fail(SBFWI_EINVAL, "c, dt, beta and gamma must be positive");
+  if (scheme != SBFWI_SCHEME_PAPER_FD) return sbfwi_fail(SBFWI_EINVAL, "unknown radial scheme %d", scheme);
+  if (coarse_solver != 0) return sbfwi_fail(SBFWI_EINVAL, "unknown coarse solver %d", coarse_solver);
+  return sbfwi_factor_impl(m, rho, c, dt, beta, gamma, s, out);
+}
+
+extern "C" int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter) {
+  if (!f || !(rtol > 0) || max_iter <= 0) return sbfwi_fail(SBFWI_EINVAL, "bad solver controls");
+  f->rtol = rtol;
+  f->max_iter = max_iter;
+  return SBFWI_OK;
+}
+
+extern "C" int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* dst) {
+  if (!f || !dst) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  const double* src = nullptr;
+  int64_t n = 0;
+  switch (which) {
+    case 0: src = f->d.S; n = f->m->n_dense; break;
+    case 1: src = f->d.Kval; n = f->m->nnz; break;
+    case 2: src = f->d.finv; n = f->m->n_finv; break;
+    case 3: src = f->d.G; n = f->m->n_dense; break;
+    default: return sbfwi_fail(SBFWI_EINVAL, "unknown factor data %d", which);
+  }
+  SBFWI_HIP(hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
+  return SBFWI_OK;
+}
+
+extern "C" int sbfwi_factors_info(sbfwi_factors f, int64_t* out) {
+  if (!f || !out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  out[0] = f->bytes;
+  return SBFWI_OK;
+}
+
+extern "C" void sbfwi_destroy_factors(sbfwi_factors f) { sbfwi_factors_free(f); }
+
+static void ckpt_free(sbfwi_ckpt_s* ck) {
+  if (!ck) return;
+  sbfwi_dev_free(ck->src_node);
+  sbfwi_dev_free(ck->wavelet);
+  sbfwi_dev_free(ck->rec_node);
+  sbfwi_dev_free(ck->states);
+  sbfwi_dev_free(ck->xstore);
+  sbfwi_dev_free(ck->fstore);
+  sbfwi_dev_free(ck->vstore);
+  delete ck;
+}
+
+extern "C" void sbfwi_destroy_ckpt(sbfwi_ckpt ck) { ckpt_free(ck); }
+
+extern "C" int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* out) {
+  if (!ck || !out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  out[0] = ck->bytes;
+  out[1] = ck->interval;
+  return SBFWI_OK;
+}
+
+static int read_status(sbfwi_factors_s* f, hipStream_t s, const char* what) {
+  int flags[4] = {0, -1, 0, 0};
+  SBFWI_HIP(hipMemcpyAsync(flags, f->d.status, sizeof(flags), hipMemcpyDeviceToHost, s));
+  SBFWI_HIP(hipStreamSynchronize(s));
+  if (flags[0] & 4) return sbfwi_fail(SBFWI_ENONFINITE, "%s: non-finite coarse residual at step %d", what, flags[1]);
+  if (flags[0] & 2) return sbfwi_fail(SBFWI_ENOCONV, "%s: coarse solve did not converge at step %d", what, flags[1]);
+  return SBFWI_OK;
+}
+
+static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const int64_t* src_node,
+                       const double* wavelet, int n_rec, const int64_t* rec_node, double* traces, int n_ckpt,
+                       sbfwi_ckpt_s* ck, hipStream_t s, StepWork& w) {
+  sbfwi_mesh_s* m = f->m;
+  SBFWI_CHECK(sbfwi_step_work_alloc(&w, m, n_shots));
+  SBFWI_CHECK(sbfwi_step_zero(m, &w, s));
+  int flags0[4] = {0, -1, 0, 0};
+  SBFWI_HIP(hipMemcpyAsync(f->d.status, flags0, sizeof(flags0), hipMemcpyHostToDevice, s));
+  const int64_t ssz = sbfwi_state_size(m, n_shots);
+  if (ck) {
+    ck->f = f;
+    ck->n_shots = n_shots;
+    ck->n_rec = n_rec;
+    ck->n_steps = n_steps;
+    SBFWI_CHECK(sbfwi_alloc(&ck->src_node, n_shots));
+    SBFWI_CHECK(sbfwi_alloc(&ck->wavelet, (int64_t)n_shots * n_steps));
+    SBFWI_CHECK(sbfwi_alloc(&ck->rec_node, n_rec > 0 ? n_rec : 1));
+    SBFWI_HIP(hipMemcpyAsync(ck->src_node, src_node, n_shots * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    SBFWI_HIP(hipMemcpyAsync(ck->wavelet, wavelet, (size_t)n_shots * n_steps * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    if (n_rec > 0)
+      SBFWI_HIP(hipMemcpyAsync(ck->rec_node, rec_node, n_rec * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    if (n_ckpt >= n_steps) {
+      ck->full_store = true;
+      ck->interval = 1;
+      SBFWI_CHECK(sbfwi_alloc(&ck->xstore, n_steps * m->n_x * n_shots));
+      SBFWI_CHECK(sbfwi_alloc(&ck->fstore, n_steps * m->n_params * n_shots));
+      SBFWI_CHECK(sbfwi_alloc(&ck->vstore, n_steps * m->n_params * n_shots));
+      ck->bytes = 8 * n_steps * (m->n_x + 2 * m->n_params) * n_shots;
+    } else {
+      int64_t cnt = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)n_steps));
+      ck->interval = (n_steps + cnt - 1) / cnt;
+      ck->n_saved = (n_steps + ck->interval - 1) / ck->interval;
+      SBFWI_CHECK(sbfwi_alloc(&ck->states, ck->n_saved * ssz));
+      ck->bytes = 8 * ck->n_saved * ssz;
+    }
+  }
+  SourceTable src;
+  src.n_src = 1;
+  src.node = src_node;
+  src.node_stride = 1;
+  src.amp = wavelet;
+  src.amp_steps = n_steps;
+  for (int64_t k = 1; k <= n_steps; ++k) {
+    double *xs = nullptr, *fs = nullptr, *vs = nullptr;
+    if (ck && !ck->full_store && (k - 1) % ck->interval == 0)
+      SBFWI_CHECK(sbfwi_state_copy(m, &w, ck->states + ((k - 1) / ck->interval) * ssz, 1, s));
+    if (ck && ck->full_store) {
+      xs = ck->xstore + (k - 1) * m->n_x * n_shots;
+      fs = ck->fstore + (k - 1) * m->n_params * n_shots;
+      vs = ck->vstore + (k - 1) * m->n_params * n_shots;
+    }
+    SBFWI_CHECK(sbfwi_forward_step(f, &w, k, src, n_rec, rec_node, traces, n_steps, xs, fs, 0, s, vs));
+  }
+  return read_status(f, s, "forward");
+}
+
+extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, const int64_t* src_node,
+                             const double* wavelet, int n_rec, const int64_t* rec_node, double* traces,
+                             int n_ckpt, sbfwi_ckpt* ckpt_out, hipStream_t s) {
+  if (ckpt_out) *ckpt_out = nullptr;
+  if (!f) return sbfwi_fail(SBFWI_EINVAL, "NULL factors");
+  if (n_shots <= 0 || n_shots > 16) return sbfwi_fail(SBFWI_EINVAL, "n_shots must be in 1..16");
+  if (n_steps <= 0) return sbfwi_fail(SBFWI_EINVAL, "n_steps must be positive");
+  if (!src_node || !wavelet) return sbfwi_fail(SBFWI_EINVAL, "NULL source arrays");
+  if (n_rec < 0 || (n_rec > 0 && (!rec_node || !traces))) return sbfwi_fail(SBFWI_EINVAL, "bad receivers");
+  if (n_ckpt != 0 && !ckpt_out) return sbfwi_fail(SBFWI_EINVAL, "checkpoints requested but ckpt_out is NULL");
+  if (n_ckpt < -1) return sbfwi_fail(SBFWI_EINVAL, "n_ckpt must be >= -1");
+  // node ids are checked on the host (small arrays)
+  {
+    std::vector<int64_t> h(n_shots);
+    SBFWI_HIP(hipMemcpy(h.data(), src_node, n_shots * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t v : h)
+      if (v < 0 || v >= f->m->n_nodes) return sbfwi_fail(SBFWI_EINVAL, "source node %lld out of range", (long long)v);
+    std::vector<int64_t> r(n_rec);
+    if (n_rec > 0)
+      SBFWI_HIP(hipMemcpy(r.data(), rec_node, n_rec * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t v : r)
+      if (v < 0 || v >= f->m->n_nodes) return sbfwi_fail(SBFWI_EINVAL, "receiver node %lld out of range", (long long)v);
+  }
+  sbfwi_ckpt_s* ck = n_ckpt != 0 ? new sbfwi_ckpt_s() : nullptr;
+  StepWork w;
+  int rc = forward_run(f, n_shots, n_steps, src_node, wavelet, n_rec, rec_node, traces, n_ckpt, ck, s, w);
+  (void)hipStreamSynchronize(s);
+  sbfwi_step_work_free(&w);
+  if (rc != SBFWI_OK) {
+    ckpt_free(ck);
+    return rc;
+  }
+  if (ckpt_out) *ckpt_out = ck;
+  return SBFWI_OK;
+}
+
+extern "C" int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_src, int mode, double* grad,
+                             hipStream_t s) {
+  if (!f || !ck || !adj_src || !grad) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  if (ck->f != f) return sbfwi_fail(SBFWI_EINVAL, "checkpoints belong to other factors");
+  if (mode != SBFWI_GRAD_EXACT && mode != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
+  return sbfwi_adjoint_impl(f, ck, adj_src, mode, grad, s);
+}
+
+extern "C" int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed, const double* traces,
+                              int mode, double* misfit, double* grad, hipStream_t s) {
+  if (!f || !ck || !observed || !traces || !misfit || !grad) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  int64_t count = (int64_t)ck->n_shots * ck->n_rec * ck->n_steps;
+  double* res = nullptr;
+  SBFWI_CHECK(sbfwi_alloc(&res, count));
+  int rc = sbfwi_misfit_residual(traces, observed, count, f->dt, res, misfit, s);
+  if (rc == SBFWI_OK) rc = sbfwi_adjoint(f, ck, res, mode, grad, s);
+  (void)hipStreamSynchronize(s);
+  sbfwi_dev_free(res);
+  return rc;
+}

@@ -1,0 +1,497 @@
+// Element factorisation (once per model) and coarse assembly.
+//
+// One workgroup per element.  The coefficient matrices of eq. Es are built
+// from per-segment geometric weights: with linear boundary segments and the
+// density interpolated linearly between nodal values, every segment block of
+// E0, E1, E2, M0 is a linear combination of the two end-node densities,
+//   E^tau_seg(a, b) = sum_end alpha^tau[seg][end][a][b] rho_{seg+end},
+// where alpha integrates (two-point Gauss, exact for the cubic integrands)
+// c^2 det J_b (b1.b1 N N, b2.b1 dN N, b2.b2 dN dN) and det J_b N N times the
+// end-node shape function.  The same alpha are the derivatives of the
+// coefficient matrices with respect to the nodal densities, kept for the
+// gradient.  All matrices are cyclic tridiagonal and are handled as bands.
+//
+// The radial rows follow the central-difference discretisation of the
+// Newmark-discretised radial equation (eq. ODE_Newmark, eq. FD) with
+// one-sided differences of E0, E1 at the end levels and the two ghost rows of
+// the flux boundary conditions (eq. system).  The elimination is the paper's
+// block Gauss sweep, organised so that only phi~_j^-1 is stored per level:
+// rho_j = theta_j phi~_{j-1}^-1 is applied as theta_j (phi~_{j-1}^-1 .), which
+// halves the factor storage and lets the same stored block serve the forward
+// and the transposed sweeps.
+#include "sbfwi_internal.h"
+
+namespace {
+
+constexpr int FT = 256;  // threads per factor workgroup
+
+struct ElemCtx {
+  int nb, n;        // boundary nodes, intervals (levels 0..n)
+  double xi0, h, c2, a0;
+  const double* rho;  // element's [N_r][nb] densities (global)
+  const double* alpha;  // LDS [4][nb][2][4]
+};
+
+__device__ __forceinline__ int md(int i, int nb) { return (i % nb + nb) % nb; }
+
+// Band entry t (0 sub, 1 diag, 2 super) of row i of E^tau at level lev.
+__device__ double e_band(const ElemCtx& c, int tau, int lev, int t, int i) {
+  const int nb = c.nb;
+  const double* r = c.rho + (int64_t)lev * nb;
+  const double* al = c.alpha + tau * nb * 8;
+  auto A = [&](int seg, int end, int ab) { return al[seg * 8 + end * 4 + ab]; };
+  if (t == 1) {
+    int s0 = i, s1 = md(i - 1, nb);
+    return A(s0, 0, 0) * r[i] + A(s0, 1, 0) * r[md(i + 1, nb)] +
+           A(s1, 0, 3) * r[s1] + A(s1, 1, 3) * r[i];
+  } else if (t == 2) {  // M[i][i+1]: segment i, (a, b) = (0, 1)
+    return A(i, 0, 1) * r[i] + A(i, 1, 1) * r[md(i + 1, nb)];
+  } else {              // M[i][i-1]: segment i-1, (a, b) = (1, 0)
+    int s1 = md(i - 1, nb);
+    return A(s1, 0, 2) * r[s1] + A(s1, 1, 2) * r[i];
+  }
+}
+
+// Band entry t of the transpose of E^tau at level lev.
+__device__ double e_band_T(const ElemCtx& c, int tau, int lev, int t, int i) {
+  if (t == 1) return e_band(c, tau, lev, 1, i);
+  if (t == 0) return e_band(c, tau, lev, 2, md(i - 1, c.nb));
+  return e_band(c, tau, lev, 0, md(i + 1, c.nb));
+}
+
+__device__ __forceinline__ double xi_of(const ElemCtx& c, int j) { return c.xi0 + c.h * j; }
+
+// d/dxi of E^tau at level j: central inside, one-sided at the end levels.
+__device__ double d_band(const ElemCtx& c, int tau, int j, int t, int i, bool transpose) {
+  auto E = [&](int lev) { return transpose ? e_band_T(c, tau, lev, t, i) : e_band(c, tau, lev, t, i); };
+  if (j == 0) return (E(1) - E(0)) / c.h;
+  if (j == c.n) return (E(c.n) - E(c.n - 1)) / c.h;
+  return (E(j + 1) - E(j - 1)) / (2.0 * c.h);
+}
+
+// Band entries of the rows: which = 0 theta, 1 phi, 2 psi, 3 P, for row r = -1 .. n+1.
+__device__ double row_band(const ElemCtx& c, int which, int r, int t, int i) {
+  const double h = c.h;
+  if (r == -1 || r == c.n + 1) {
+    int lev = (r == -1) ? 0 : c.n;
+    double x = xi_of(c, lev);
+    if (which == 0) return -x * e_band(c, 0, lev, t, i) / (2.0 * h);
+    if (which == 1) return e_band_T(c, 1, lev, t, i);
+    if (which == 2) return x * e_band(c, 0, lev, t, i) / (2.0 * h);
+    return 0.0;
+  }
+  double x = xi_of(c, r);
+  double e0 = e_band(c, 0, r, t, i);
+  if (which == 3) return -x * x * e_band(c, 3, r, t, i);
+  if (which == 1) {
+    return -2.0 * x * x * e0 / (h * h) - e_band(c, 2, r, t, i) + x * d_band(c, 1, r, t, i, true) -
+           c.a0 * x * x * e_band(c, 3, r, t, i);
+  }
+  double C = e0 + e_band_T(c, 1, r, t, i) - e_band(c, 1, r, t, i) + x * d_band(c, 0, r, t, i, false);
+  if (which == 0) return x * x * e0 / (h * h) - x * C / (2.0 * h);
+  return x * x * e0 / (h * h) + x * C / (2.0 * h);
+}
+
+template <int NBT>
+struct Lds {
+  double alpha[4 * NBT * 8];
+  double band[3][3 * NBT];    // scratch bands
+  double A[NBT * NBT];        // dense work blocks
+  double B[NBT * NBT];
+  double Z[NBT * NBT];
+  double Fp[NBT * NBT];       // phi~^-1 of the previous level
+  double Pp[NBT * NBT];       // psi~ of the previous level (dense)
+  double Ph[NBT * NBT];       // phi~_n
+  double Ph1[NBT * NBT];      // phi~_{n+1}
+  double W[NBT * 2 * NBT];    // Gauss-Jordan workspace
+  double fac[NBT];
+  int piv;
+  int bad;
+};
+
+// dst = dense(band)
+template <int NBT>
+__device__ void band_to_dense(const double* band, double* dst, int nb) {
+  for (int q = threadIdx.x; q < nb * nb; q += FT) {
+    int i = q / nb, j = q % nb;
+    double v = 0.0;
+    if (j == i) v = band[nb + i];
+    if (j == md(i + 1, nb)) v += band[2 * nb + i];
+    if (j == md(i - 1, nb)) v += band[i];
+    dst[i * NBT + j] = v;
+  }
+}
+
+// dst = D * B (dense x band); dst may not alias D
+template <int NBT>
+__device__ void dense_band(const double* D, const double* band, double* dst, int nb) {
+  for (int q = threadIdx.x; q < nb * nb; q += FT) {
+    int i = q / nb, j = q % nb;
+    int jm = md(j - 1, nb), jp = md(j + 1, nb);
+    // B[jm][j] = super_{jm}, B[j][j] = diag_j, B[jp][j] = sub_{jp}
+    dst[i * NBT + j] = D[i * NBT + j] * band[nb + j] + D[i * NBT + jm] * band[2 * nb + jm] +
+                       D[i * NBT + jp] * band[jp];
+  }
+}
+
+// dst = B * D (band x dense)
+template <int NBT>
+__device__ void band_dense(const double* band, const double* D, double* dst, int nb) {
+  for (int q = threadIdx.x; q < nb * nb; q += FT) {
+    int i = q / nb, j = q % nb;
+    dst[i * NBT + j] = band[i] * D[md(i - 1, nb) * NBT + j] + band[nb + i] * D[i * NBT + j] +
+                       band[2 * nb + i] * D[md(i + 1, nb) * NBT + j];
+  }
+}
+
+// dst = X * Y (dense x dense)
+template <int NBT>
+__device__ void dense_dense(const double* X, const double* Y, double* dst, int nb) {
+  for (int q = threadIdx.x; q < nb * nb; q += FT) {
+    int i = q / nb, j = q % nb;
+    double v = 0.0;
+    for (int k = 0; k < nb; ++k) v += X[i * NBT + k] * Y[k * NBT + j];
+    dst[i * NBT + j] = v;
+  }
+}
+
+// inv = M^-1 by Gauss-Jordan with partial pivoting (M untouched).
+template <int NBT>
+__device__ void invert(Lds<NBT>& L, const double* M, double* inv, int nb) {
+  const int W2 = 2 * NBT;
+  for (int q = threadIdx.x; q < nb * 2 * nb; q += FT) {
+    int i = q / (2 * nb), j = q % (2 * nb);
+    L.W[i * W2 + j] = (j < nb) ? M[i * NBT + j] : (j - nb == i ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int col = 0; col < nb; ++col) {
+    if (threadIdx.x == 0) {
+      int p = col;
+      double best = fabs(L.W[col * W2 + col]);
+      for (int r = col + 1; r < nb; ++r) {
+        double v = fabs(L.W[r * W2 + col]);
+        if (v > best) { best = v; p = r; }
+      }
+      L.piv = p;
+      if (!(best > 1e-300) || !isfinite(best)) L.bad = 1;
+    }
+    __syncthreads();
+    int p = L.piv;
+    if (p != col) {
+      for (int j = threadIdx.x; j < 2 * nb; j += FT) {
+        double t = L.W[col * W2 + j];
+        L.W[col * W2 + j] = L.W[p * W2 + j];
+        L.W[p * W2 + j] = t;
+      }
+    }
+    __syncthreads();
+    double f = 1.0 / L.W[col * W2 + col];
+    __syncthreads();
+    for (int j = threadIdx.x; j < 2 * nb; j += FT) L.W[col * W2 + j] *= f;
+    __syncthreads();
+    for (int r = threadIdx.x; r < nb; r += FT) L.fac[r] = L.W[r * W2 + col];
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb * 2 * nb; q += FT) {
+      int r = q / (2 * nb), j = q % (2 * nb);
+      if (r != col) L.W[r * W2 + j] -= L.fac[r] * L.W[col * W2 + j];
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < nb * nb; q += FT) {
+    int i = q / nb, j = q % nb;
+    inv[i * NBT + j] = L.W[i * W2 + nb + j];
+  }
+  __syncthreads();
+}
+
+template <int NBT>
+__device__ void store_dense(const double* D, double* dst, int nb) {
+  for (int q = threadIdx.x; q < nb * nb; q += FT) dst[q] = D[(q / nb) * NBT + (q % nb)];
+}
+
+template <int NBT>
+__device__ void load_rows(const ElemCtx& c, Lds<NBT>& L, int slot, int which, int r) {
+  for (int q = threadIdx.x; q < 3 * c.nb; q += FT) L.band[slot][q] = row_band(c, which, r, q / c.nb, q % c.nb);
+}
+
+template <int NBT>
+__global__ void __launch_bounds__(FT) factor_kernel(
+    const int32_t* __restrict__ elems, const MeshDev mm, const double* __restrict__ rho,
+    double c, double a0, FactorsDev ff, int* status) {
+  __shared__ Lds<NBT> L;
+  const int e = elems[blockIdx.x];
+  const int nb = mm.nb[e];
+  const int nr = mm.nr[e];
+  const int n = nr - 1;
+  const int64_t lo = mm.loop_off[e];
+  if (threadIdx.x == 0) L.bad = 0;
+  // per-segment geometric weights alpha[tau][seg][end][ab]
+  const double cx = mm.centre[2 * e], cy = mm.centre[2 * e + 1];
+  for (int s = threadIdx.x; s < nb; s += FT) {
+    int s1 = md(s + 1, nb);
+    double ax = mm.loop_xy[2 * (lo + s)], ay = mm.loop_xy[2 * (lo + s) + 1];
+    double bx = mm.loop_xy[2 * (lo + s1)], by = mm.loop_xy[2 * (lo + s1) + 1];
+    double dx = 0.5 * (bx - ax), dy = 0.5 * (by - ay);
+    double acc[32];
+    for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+    const double gp = 0.57735026918962576451;  // 1/sqrt(3), weights 1
+    for (int g = 0; g < 2; ++g) {
+      double eta = g == 0 ? -gp : gp;
+      double N[2] = {0.5 * (1.0 - eta), 0.5 * (1.0 + eta)};
+      double dN[2] = {-0.5, 0.5};
+      double xb = N[0] * ax + N[1] * bx - cx, yb = N[0] * ay + N[1] * by - cy;
+      double det = xb * dy - yb * dx;
+      double b1x = dy / det, b1y = -dx / det;
+      double b2x = -yb / det, b2y = xb / det;
+      double b11 = b1x * b1x + b1y * b1y, b21 = b2x * b1x + b2y * b1y, b22 = b2x * b2x + b2y * b2y;
+      for (int end = 0; end < 2; ++end) {
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            int ab = a * 2 + b;
+            double wN = det * N[end];
+            acc[0 * 8 + end * 4 + ab] += c * c * b11 * wN * N[a] * N[b];
+            acc[1 * 8 + end * 4 + ab] += c * c * b21 * wN * dN[a] * N[b];
+            acc[2 * 8 + end * 4 + ab] += c * c * b22 * wN * dN[a] * dN[b];
+            acc[3 * 8 + end * 4 + ab] += wN * N[a] * N[b];
+          }
+      }
+    }
+    for (int tau = 0; tau < 4; ++tau)
+      for (int q = 0; q < 8; ++q) {
+        L.alpha[tau * nb * 8 + s * 8 + q] = acc[tau * 8 + q];
+        ff.gbasis[32 * (lo + s) + tau * 8 + q] = acc[tau * 8 + q];
+      }
+  }
+  __syncthreads();
+  ElemCtx ec;
+  ec.nb = nb;
+  ec.n = n;
+  ec.xi0 = mm.xi0;
+  ec.h = (1.0 - mm.xi0) / n;
+  ec.c2 = c * c;
+  ec.a0 = a0;
+  ec.rho = rho + mm.par_off[e];
+  ec.alpha = L.alpha;
+  const int64_t po = mm.par_off[e];
+  // persistent bands: theta_j, psi_j, P_j for j = 0..n; theta_{n+1}, phi_{-1}, psi_{-1}
+  for (int q = threadIdx.x; q < 3 * nb * nr; q += FT) {
+    int j = q / (3 * nb), rem = q % (3 * nb), t = rem / nb, i = rem % nb;
+    ff.th_band[3 * po + j * 3 * nb + rem] = row_band(ec, 0, j, t, i);
+    ff.ps_band[3 * po + j * 3 * nb + rem] = row_band(ec, 2, j, t, i);
+    ff.pm_band[3 * po + j * 3 * nb + rem] = row_band(ec, 3, j, t, i);
+  }
+  for (int q = threadIdx.x; q < 3 * nb; q += FT) {
+    ff.th_np1[3 * lo + q] = row_band(ec, 0, n + 1, q / nb, q % nb);
+    ff.phim1[3 * lo + q] = row_band(ec, 1, -1, q / nb, q % nb);
+    ff.psim1[3 * lo + q] = row_band(ec, 2, -1, q / nb, q % nb);
+  }
+  const int64_t dofs = mm.dense_off[e];
+  const int64_t fo = mm.finv_off[e];
+  // theta_{-1}^-1
+  load_rows<NBT>(ec, L, 0, 0, -1);
+  __syncthreads();
+  band_to_dense<NBT>(L.band[0], L.A, nb);
+  __syncthreads();
+  invert<NBT>(L, L.A, L.B, nb);                 // B = theta_{-1}^-1
+  store_dense<NBT>(L.B, ff.thm1_inv + dofs, nb);
+  // rho_0 = theta_0 theta_{-1}^-1 ; phi~_0 = phi_0 - rho_0 phi_{-1} ; psi~_0 = psi_0 - rho_0 psi_{-1}
+  load_rows<NBT>(ec, L, 0, 0, 0);   // theta_0
+  load_rows<NBT>(ec, L, 1, 1, -1);  // phi_{-1}
+  load_rows<NBT>(ec, L, 2, 2, -1);  // psi_{-1}
+  __syncthreads();
+  band_dense<NBT>(L.band[0], L.B, L.Z, nb);     // Z = rho_0
+  __syncthreads();
+  dense_band<NBT>(L.Z, L.band[1], L.A, nb);     // A = rho_0 phi_{-1}
+  dense_band<NBT>(L.Z, L.band[2], L.B, nb);     // B = rho_0 psi_{-1}
+  __syncthreads();
+  load_rows<NBT>(ec, L, 0, 1, 0);   // phi_0
+  load_rows<NBT>(ec, L, 1, 2, 0);   // psi_0
+  __syncthreads();
+  band_to_dense<NBT>(L.band[0], L.Ph, nb);
+  band_to_dense<NBT>(L.band[1], L.Pp, nb);
+  __syncthreads();
+  for (int q = threadIdx.x; q < nb * nb; q += FT) {
+    int i = q / nb, j = q % nb;
+    L.Ph[i * NBT + j] -= L.A[i * NBT + j];      // phi~_0
+    L.Pp[i * NBT + j] -= L.B[i * NBT + j];      // psi~_0
+  }
+  __syncthreads();
+  store_dense<NBT>(L.Pp, ff.psit0 + dofs, nb);
+  invert<NBT>(L, L.Ph, L.Fp, nb);               // Fp = phi~_0^-1
+  store_dense<NBT>(L.Fp, ff.finv + fo, nb);
+  // levels j = 1 .. n
+  for (int j = 1; j <= n; ++j) {
+    // Z = phi~_{j-1}^-1 psi~_{j-1}
+    if (j == 1) {
+      dense_dense<NBT>(L.Fp, L.Pp, L.Z, nb);
+    } else {
+      load_rows<NBT>(ec, L, 2, 2, j - 1);
+      __syncthreads();
+      dense_band<NBT>(L.Fp, L.band[2], L.Z, nb);
+    }
+    load_rows<NBT>(ec, L, 0, 0, j);   // theta_j
+    load_rows<NBT>(ec, L, 1, 1, j);   // phi_j
+    __syncthreads();
+    band_dense<NBT>(L.band[0], L.Z, L.A, nb);   // A = theta_j Z
+    band_to_dense<NBT>(L.band[1], L.Ph, nb);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb * nb; q += FT) {
+      int i = q / nb, jj = q % nb;
+      L.Ph[i * NBT + jj] -= L.A[i * NBT + jj];  // phi~_j
+    }
+    __syncthreads();
+    if (j == n) {
+      load_rows<NBT>(ec, L, 0, 0, n + 1);
+      load_rows<NBT>(ec, L, 1, 1, n + 1);
+      __syncthreads();
+      band_dense<NBT>(L.band[0], L.Z, L.A, nb);
+      band_to_dense<NBT>(L.band[1], L.Ph1, nb);
+      __syncthreads();
+      for (int q = threadIdx.x; q < nb * nb; q += FT) {
+        int i = q / nb, jj = q % nb;
+        L.Ph1[i * NBT + jj] -= L.A[i * NBT + jj];   // phi~_{n+1}
+      }
+      __syncthreads();
+    } else {
+      invert<NBT>(L, L.Ph, L.Fp, nb);
+      store_dense<NBT>(L.Fp, ff.finv + fo + (int64_t)j * nb * nb, nb);
+    }
+  }
+  store_dense<NBT>(L.Ph, ff.phit_n + dofs, nb);
+  // G = psi_{n+1} psi_n^-1 ; S = phi~_{n+1} - G phi~_n
+  load_rows<NBT>(ec, L, 0, 2, n);       // psi_n
+  load_rows<NBT>(ec, L, 1, 2, n + 1);   // psi_{n+1}
+  __syncthreads();
+  band_to_dense<NBT>(L.band[0], L.A, nb);
+  __syncthreads();
+  invert<NBT>(L, L.A, L.B, nb);         // B = psi_n^-1
+  store_dense<NBT>(L.B, ff.psin_inv + dofs, nb);
+  band_dense<NBT>(L.band[1], L.B, L.Z, nb);   // Z = G
+  __syncthreads();
+  store_dense<NBT>(L.Z, ff.G + dofs, nb);
+  dense_dense<NBT>(L.Z, L.Ph, L.A, nb);       // A = G phi~_n
+  __syncthreads();
+  for (int q = threadIdx.x; q < nb * nb; q += FT) {
+    int i = q / nb, jj = q % nb;
+    ff.S[dofs + q] = L.Ph1[i * NBT + jj] - L.A[i * NBT + jj];
+  }
+  if (threadIdx.x == 0 && L.bad) atomicOr(status, 1);
+}
+
+__global__ void assemble_kernel(int64_t nnz, const int64_t* __restrict__ cptr,
+                                const int64_t* __restrict__ csrc, const double* __restrict__ S,
+                                double* __restrict__ K) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  double v = 0.0;
+  for (int64_t t = cptr[q]; t < cptr[q + 1]; ++t) v += S[csrc[t]];
+  K[q] = v;
+}
+
+__global__ void transpose_diag_kernel(int64_t nnz, int64_t n_nodes, const int64_t* __restrict__ tr,
+                                      const int64_t* __restrict__ diag, const double* __restrict__ K,
+                                      double* __restrict__ KT, double* __restrict__ dinv) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nnz) KT[q] = K[tr[q]];
+  if (q < n_nodes) dinv[q] = 1.0 / K[diag[q]];
+}
+
+}  // namespace
+
+void sbfwi_factors_free(sbfwi_factors_s* f) {
+  if (!f) return;
+  FactorsDev& d = f->d;
+  void* ptrs[] = {d.finv, d.th_band, d.ps_band, d.pm_band, d.th_np1, d.phim1, d.psim1,
+                  d.G, d.S, d.psit0, d.psin_inv, d.phit_n, d.thm1_inv, d.gbasis,
+                  d.Kval, d.KTval, d.diag_inv, d.status};
+  for (void* p : ptrs) sbfwi_dev_free(p);
+  delete f;
+}
+
+int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, double beta,
+                      double gamma, hipStream_t s, sbfwi_factors_s** out) {
+  sbfwi_factors_s* f = new sbfwi_factors_s();
+  f->m = m;
+  f->c = c;
+  f->dt = dt;
+  f->beta = beta;
+  f->gamma = gamma;
+  FactorsDev& d = f->d;
+  d.a0 = 1.0 / (beta * dt * dt);
+  d.a1 = 1.0 / (beta * dt);
+  d.a2 = 1.0 / (2.0 * beta) - 1.0;
+  d.c1 = gamma / (beta * dt);
+  d.c2 = 1.0 - gamma / beta;
+  d.c3 = dt * (1.0 - gamma / (2.0 * beta));
+  d.dt = dt;
+  int rc = SBFWI_OK;
+  auto A = [&](double** p, int64_t n) {
+    if (rc == SBFWI_OK) {
+      rc = sbfwi_alloc(p, n);
+      f->bytes += n * 8;
+    }
+  };
+  A(&d.finv, m->n_finv);
+  A(&d.th_band, 3 * m->n_params);
+  A(&d.ps_band, 3 * m->n_params);
+  A(&d.pm_band, 3 * m->n_params);
+  A(&d.th_np1, 3 * m->n_loop);
+  A(&d.phim1, 3 * m->n_loop);
+  A(&d.psim1, 3 * m->n_loop);
+  A(&d.G, m->n_dense);
+  A(&d.S, m->n_dense);
+  A(&d.psit0, m->n_dense);
+  A(&d.psin_inv, m->n_dense);
+  A(&d.phit_n, m->n_dense);
+  A(&d.thm1_inv, m->n_dense);
+  A(&d.gbasis, 32 * m->n_loop);
+  A(&d.Kval, m->nnz);
+  A(&d.KTval, m->nnz);
+  A(&d.diag_inv, m->n_nodes);
+  if (rc == SBFWI_OK) rc = sbfwi_alloc(&d.status, 4);
+  if (rc != SBFWI_OK) {
+    sbfwi_factors_free(f);
+    return rc;
+  }
+  auto hip_fail = [&](hipError_t e, const char* what) {
+    sbfwi_factors_free(f);
+    return sbfwi_fail(SBFWI_EHIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  hipError_t he = hipMemsetAsync(d.status, 0, 4 * sizeof(int), s);
+  if (he != hipSuccess) return hip_fail(he, "hipMemsetAsync");
+  for (int cl = 0; cl < 3; ++cl) {
+    int64_t cnt = (int64_t)m->h_class_elems[cl].size();
+    if (cnt == 0) continue;
+    dim3 grid((unsigned)cnt), block(FT);
+    if (cl == 0)
+      hipLaunchKernelGGL(factor_kernel<8>, grid, block, 0, s, m->class_elems[0], m->d, rho, c, d.a0, d, d.status);
+    else if (cl == 1)
+      hipLaunchKernelGGL(factor_kernel<16>, grid, block, 0, s, m->class_elems[1], m->d, rho, c, d.a0, d, d.status);
+    else
+      hipLaunchKernelGGL(factor_kernel<24>, grid, block, 0, s, m->class_elems[2], m->d, rho, c, d.a0, d, d.status);
+    he = hipGetLastError();
+    if (he != hipSuccess) return hip_fail(he, "factor_kernel launch");
+  }
+  {
+    unsigned g = (unsigned)((m->nnz + 255) / 256);
+    hipLaunchKernelGGL(assemble_kernel, dim3(g), dim3(256), 0, s, m->nnz, m->d.contrib_ptr, m->d.contrib_src,
+                       d.S, d.Kval);
+    int64_t big = m->nnz > m->n_nodes ? m->nnz : m->n_nodes;
+    unsigned g2 = (unsigned)((big + 255) / 256);
+    hipLaunchKernelGGL(transpose_diag_kernel, dim3(g2), dim3(256), 0, s, m->nnz, m->n_nodes, m->d.tr_idx,
+                       m->d.diag_idx, d.Kval, d.KTval, d.diag_inv);
+    he = hipGetLastError();
+    if (he != hipSuccess) return hip_fail(he, "assembly launch");
+  }
+  int st[4] = {0, 0, 0, 0};
+  he = hipMemcpyAsync(st, d.status, sizeof(st), hipMemcpyDeviceToHost, s);
+  if (he != hipSuccess) return hip_fail(he, "hipMemcpyAsync");
+  he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return hip_fail(he, "hipStreamSynchronize");
+  if (st[0] & 1) {
+    sbfwi_factors_free(f);
+    return sbfwi_fail(SBFWI_ESINGULAR, "a pivot block of the condensation sweep is singular");
+  }
+  *out = f;
+  return SBFWI_OK;
+}

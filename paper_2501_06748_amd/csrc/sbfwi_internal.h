@@ -1,0 +1,199 @@
+// Internal declarations of the sbfwi library (gfx950).
+//
+// Storage conventions (all FP64, shots innermost so that one radial level of
+// one element for all shots of a launch is a contiguous, coalesced run):
+//   interior state u, v, a and the swept sources q: ((int_off[e] + j*nb + i)*NS + s),
+//       level j = 0 .. N_r-2 (the boundary level N_r-1 is the shared nodal state);
+//   nodal state and coarse vectors: (node*NS + s);
+//   per-slot element vectors (effective sources, boundary sweeps): ((loop_off[e] + i)*NS + s);
+//   unknowns with ghosts, levels -1 .. N_r: ((x_off[e] + (j+1)*nb + i)*NS + s);
+//   level fields 0 .. N_r-1 (fine grid): ((par_off[e] + j*nb + i)*NS + s).
+// Cyclic tridiagonal blocks ("bands") store sub, diag, super diagonals:
+//   band[t*nb + i], t = 0: M[i][i-1], t = 1: M[i][i], t = 2: M[i][i+1] (indices mod nb).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sbfwi.h"
+
+#define SBFWI_MAX_NB 24
+
+// Plain device view of a mesh (kernel argument).
+struct MeshDev {
+  int64_t n_nodes = 0, n_elem = 0, n_loop = 0, nnz = 0;
+  double xi0 = 1e-3;
+  int32_t* nb = nullptr;
+  int32_t* nr = nullptr;
+  int64_t* loop_off = nullptr;
+  int64_t* par_off = nullptr;
+  int64_t* int_off = nullptr;
+  int64_t* x_off = nullptr;
+  int64_t* finv_off = nullptr;
+  int64_t* dense_off = nullptr;
+  int64_t* loop_nodes = nullptr;
+  double* loop_xy = nullptr;     // [n_loop][2]
+  double* centre = nullptr;      // [n_elem][2]
+  int64_t* node_ptr = nullptr;   // [n_nodes+1] -> node_slot
+  int64_t* node_slot = nullptr;  // loop slots (loop_off[e] + i) that touch each node
+  int64_t* row_ptr = nullptr;    // coarse CSR
+  int32_t* col = nullptr;
+  int64_t* diag_idx = nullptr;   // [n_nodes] position of (r, r)
+  int64_t* tr_idx = nullptr;     // [nnz] position of (c, r) for entry (r, c)
+  int64_t* contrib_ptr = nullptr;  // [nnz+1]
+  int64_t* contrib_src = nullptr;  // index into S storage (dense_off[e] + i*nb + j)
+};
+
+struct sbfwi_mesh_s {
+  int64_t n_nodes = 0, n_elem = 0, n_params = 0, n_int = 0, n_loop = 0, n_x = 0;
+  int64_t nnz = 0, n_finv = 0, n_dense = 0, n_contrib = 0;
+  double xi0 = 1e-3;
+  // host copies
+  std::vector<int32_t> h_nb, h_nr;
+  std::vector<int64_t> h_loop_off, h_par_off, h_int_off, h_x_off, h_finv_off, h_dense_off;
+  std::vector<int64_t> h_row_ptr, h_col64;
+  std::vector<int32_t> h_class_elems[3];
+  MeshDev d;
+  int32_t* class_elems[3] = {nullptr, nullptr, nullptr};   // elements with nb <= 8, 16, 24
+};
+
+// Plain device view of a factored model (kernel argument).
+struct FactorsDev {
+  double a0 = 0, a1 = 0, a2 = 0, c1 = 0, c2 = 0, c3 = 0, dt = 0;
+  double* finv = nullptr;      // [n_finv] phi~_j^-1, j = 0 .. N_r-2, row-major
+  double* th_band = nullptr;   // [3 n_params] theta_j, j = 0 .. N_r-1
+  double* ps_band = nullptr;   // [3 n_params] psi_j,   j = 0 .. N_r-1
+  double* pm_band = nullptr;   // [3 n_params] P_j = -xi_j^2 M0_j
+  double* th_np1 = nullptr;    // [3 n_loop] theta_{n+1}
+  double* phim1 = nullptr;     // [3 n_loop] phi_{-1} = E1_0^T
+  double* psim1 = nullptr;     // [3 n_loop] psi_{-1}
+  double* G = nullptr;         // [n_dense] psi_{n+1} psi_n^-1
+  double* S = nullptr;         // [n_dense] dynamic stiffness
+  double* psit0 = nullptr;     // [n_dense] psi~_0
+  double* psin_inv = nullptr;  // [n_dense] psi_n^-1
+  double* phit_n = nullptr;    // [n_dense] phi~_n
+  double* thm1_inv = nullptr;  // [n_dense] theta_{-1}^-1
+  double* gbasis = nullptr;    // [32 n_loop] d(E0,E1,E2,M0 segment block)/d(nodal density)
+  double* Kval = nullptr;      // [nnz] coarse matrix on the CSR pattern
+  double* KTval = nullptr;     // [nnz] its transpose on the same (symmetric) pattern
+  double* diag_inv = nullptr;  // [n_nodes] Jacobi preconditioner
+  int* status = nullptr;       // device status words
+};
+
+struct sbfwi_factors_s {
+  sbfwi_mesh_s* m = nullptr;
+  double c = 0, dt = 0, beta = 0, gamma = 0;
+  double rtol = 1e-13;
+  int max_iter = 500;
+  int64_t bytes = 0;
+  FactorsDev d;
+};
+
+struct sbfwi_ckpt_s {
+  sbfwi_factors_s* f = nullptr;
+  int n_shots = 0, n_rec = 0;
+  int64_t n_steps = 0, interval = 0, n_saved = 0;
+  int64_t bytes = 0;
+  int64_t* src_node = nullptr;   // device copies [n_shots]
+  double* wavelet = nullptr;     // [n_shots][n_steps]
+  int64_t* rec_node = nullptr;   // [n_rec]
+  double* states = nullptr;      // [n_saved][state size]: interior u, v, a then nodal U, V, A
+  bool full_store = false;       // every step's unknowns kept by the forward run
+  double* xstore = nullptr;      // full storage: [n_steps][n_x*NS]
+  double* fstore = nullptr;      // full storage: [n_steps][n_params*NS] accelerations a^k
+  double* vstore = nullptr;      // full storage: [n_steps][n_params*NS] velocities v^k
+};
+
+// ---- error handling / allocation (api.cpp) ----
+int sbfwi_fail(int code, const char* fmt, ...);
+void* sbfwi_dev_alloc(size_t bytes);
+void sbfwi_dev_free(void* p);
+
+#define SBFWI_HIP(call)                                                        \
+  do {                                                                         \
+    hipError_t _e = (call);                                                    \
+    if (_e != hipSuccess)                                                      \
+      return sbfwi_fail(SBFWI_EHIP, "%s failed: %s (%s:%d)", #call,             \
+                        hipGetErrorString(_e), __FILE__, __LINE__);             \
+  } while (0)
+
+#define SBFWI_CHECK(call)                                                      \
+  do {                                                                         \
+    int _r = (call);                                                           \
+    if (_r != SBFWI_OK) return _r;                                             \
+  } while (0)
+
+template <typename T>
+static inline int sbfwi_alloc(T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  *p = (T*)sbfwi_dev_alloc((size_t)count * sizeof(T));
+  if (!*p) return sbfwi_fail(SBFWI_ENOMEM, "device allocation of %lld bytes failed",
+                             (long long)((size_t)count * sizeof(T)));
+  return SBFWI_OK;
+}
+
+template <typename T>
+static inline int sbfwi_upload(T** p, const std::vector<T>& v) {
+  SBFWI_CHECK(sbfwi_alloc(p, (int64_t)v.size()));
+  if (!v.empty()) SBFWI_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return SBFWI_OK;
+}
+
+// ---- stage entry points (factor.hip, step.hip, coarse.hip, adjoint.hip) ----
+int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, double beta,
+                      double gamma, hipStream_t s, sbfwi_factors_s** out);
+
+struct CoarseWork {
+  int NS = 0;
+  int64_t n = 0;
+  double *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *sv = nullptr,
+         *t = nullptr, *phat = nullptr, *shat = nullptr, *partial = nullptr;
+  int nblocks = 0, nthreads = 0;
+};
+int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS);
+void sbfwi_coarse_work_free(CoarseWork* w);
+// Solves K x = b (transpose = 0) or K^T x = b (transpose = 1) for NS right-hand
+// sides; x holds the initial guess on entry.  Records failures in f->status.
+int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b,
+                       double* x, int64_t step, hipStream_t s);
+
+struct StepWork {
+  int NS = 0;
+  double *u = nullptr, *v = nullptr, *a = nullptr;      // interior state
+  double *U = nullptr, *V = nullptr, *A = nullptr;      // nodal state
+  double *q = nullptr, *yn = nullptr, *fhat = nullptr, *F = nullptr, *Unew = nullptr;
+  CoarseWork cw;
+};
+int sbfwi_step_work_alloc(StepWork* w, sbfwi_mesh_s* m, int NS);
+void sbfwi_step_work_free(StepWork* w);
+int64_t sbfwi_state_size(sbfwi_mesh_s* m, int NS);
+
+// Source table of a run: n_src sources per shot; source c of shot q acts on
+// node src_node[q*n_src + c] with amplitude amp[(q*n_src + c)*amp_steps + idx],
+// idx = k - 1 (forward in time) or amp_steps - k (time-reversed).
+struct SourceTable {
+  int n_src = 1;
+  const int64_t* node = nullptr;
+  int node_stride = 1;           // 1: node[q*n_src + c] per shot; 0: node[c] shared by all shots
+  const double* amp = nullptr;
+  int64_t amp_steps = 0;
+  int reversed = 0;
+};
+
+// One forward step k: condense, assemble, coarse solve, nodal update, recover.
+// Optional stores (nullptr = skip): unknowns with ghosts (xs) and a level field
+// (fs: a^k when field_kind = 0, v^k when field_kind = 1); receiver traces.
+int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceTable& src,
+                       int n_rec, const int64_t* rec_node, double* traces, int64_t n_steps,
+                       double* xs, double* fs, int field_kind, hipStream_t s, double* vs = nullptr);
+int sbfwi_state_copy(sbfwi_mesh_s* m, StepWork* w, double* dst, int to_store, hipStream_t s);
+int sbfwi_step_zero(sbfwi_mesh_s* m, StepWork* w, hipStream_t s);
+
+int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_src, int mode,
+                       double* grad, hipStream_t s);
+int sbfwi_misfit_residual(const double* traces, const double* observed, int64_t count, double dt,
+                          double* residual, double* misfit, hipStream_t s);
