@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Throughput of the SBFEM radial-condensation FWI hot path on one MI355X.
+
+One *step* is one full gradient evaluation of the inversion on the paper-size
+synthetic plate: factorisation of every element (coefficient matrices,
+radial rows, block elimination, coarse assembly), the forward run of all
+shots with sqrt(T) checkpoints (condense, coarse solve, recover, Newmark per
+time step), the misfit, and the exact adjoint run with segment recompute and
+the zero-lag gradient correlation.  The metric counts element x radial level
+x time step x shot units of forward + adjoint per second.
+
+Workload (synthetic, seeded): 0.1 x 0.05 m plate, 128 x 64 square elements,
+16 boundary nodes and 32 radial levels per element, c = 3000 m/s,
+rho0 = 2700 kg/m^3, dt = 2e-8 s, 4000 steps, 4 Ricker shots (500 kHz) and 32
+receivers on the top edge.  The gradient is evaluated at the homogeneous
+starting model against data simulated (before the timed region) on a model
+with two smoothed elliptical voids of half density.
+
+    python bench.py [--steps K] [--warmup W] [--nt N_t] [--shots S]
+
+Prints one JSON line.  --gpus above 1 is not supported (one GPU only).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(mesh, NS):
+    """Algorithmic HBM bytes per launch of each sweep kernel: every input and
+    output of the kernel read or written once (FP64).  Per element with n
+    interior levels, nb boundary nodes and NS shots."""
+    nb = mesh.n_b().astype("int64")
+    n = mesh.n_r.astype("int64") - 1
+    blk = n * nb * nb + nb * nb                   # stored pivot inverses + one per-element dense block
+    band = lambda levels: 3 * nb * levels         # cyclic tridiagonal blocks
+    out = {
+        # reads phi~^-1 (n blocks), G, bands P (n+1), theta (n+1); state u,v,a (n levels) and the
+        # nodal state on the loop; writes q (n levels), y_n and f_hat on the loop
+        "condense": blk + band(n + 1) + band(n + 2) + NS * (3 * n * nb + 3 * nb + n * nb + 2 * nb),
+        # reads phi~^-1, psi~_0, bands psi (n-1); q, u, v, a, u_n; writes u, v, a
+        "recover": blk + band(n - 1) + NS * (n * nb + 3 * n * nb + nb + 3 * n * nb),
+        # reads phi~^-1, psi~_0, bands psi; seeds (3 n); writes z (n) and the coupling (1)
+        "adj_condense": blk + band(n - 1) + NS * (3 * n * nb + n * nb + nb),
+        # reads G, phi~^-1, theta (n+2), P (n+1), theta_-1^-1; lambda_B, z, seeds (2 n);
+        # writes seeds (3 n), P_n^T lambda_n, adjoint rows (n+3)
+        "adj_recover": blk + 2 * nb * nb + band(n + 2) + band(n + 1) +
+                       NS * (nb + n * nb + 2 * n * nb + 3 * n * nb + nb + (n + 3) * nb),
+        # reads unknowns and adjoint rows (n+3 levels each), accelerations (n+1), alpha; grad RMW
+        "grad_exact": 32 * nb + 2 * (n + 1) * nb + NS * (2 * (n + 3) * nb + (n + 1) * nb),
+    }
+    return {k: int(8 * v.sum()) for k, v in out.items()}
+
+
+def src_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"condense": ["paper_2501_06748_amd/csrc/step.hip"],
+                  "recover": ["paper_2501_06748_amd/csrc/step.hip"],
+                  "adj_condense": ["paper_2501_06748_amd/csrc/adjoint.hip"],
+                  "adj_recover": ["paper_2501_06748_amd/csrc/adjoint.hip"],
+                  "grad_exact": ["paper_2501_06748_amd/csrc/adjoint.hip"],
+                  "coarse_solve": ["paper_2501_06748_amd/csrc/coarse.hip"]}
+
+
+def measured_traffic(kernel, wl_name):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tab = json.load(fh)
+    ent = tab.get(f"{kernel}@{wl_name}")
+    if not ent or ent.get("source_sha") != src_hash(KERNEL_SOURCES.get(kernel, [])):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(n_steps_target, short=6, long=18):
+    """The oracle, as it stands, on a bounded sample with the benchmark's element
+    type: an 8 x 4 patch of the same elements (n_b 16, N_r 32, dt 2e-8), one
+    shot, factor + forward + exact adjoint gradient, timed at two step counts;
+    the time is fitted as a + b N_t and the rate reported for the workload's N_t
+    (the gradient contraction is a per-parameter cost independent of N_t)."""
+    import numpy as np
+    import workloads as W
+    from oracle import adjoint as oadj
+    from oracle import stepper as ostp
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    le = 0.1 / 128
+    mesh = W.uniform_rect_mesh(8 * le, 4 * le, 8, 4, segs=4, n_r=32)
+    dt = 2e-8
+    src = np.asarray([W.nearest_top_node(mesh, 4 * le)], dtype=np.int64)
+    rec = W.top_edge_nodes(mesh)[::2]
+    times = {}
+    for nt in (short, long):
+        wav = W.ricker(nt, dt, 5e5, t0=20 * dt)[None]
+        t0 = time.perf_counter()
+        model = ostp.Model(mesh, W.homogeneous(mesh), 3000.0, dt)
+        oadj.exact_gradient(model, src, wav, rec, np.zeros((1, len(rec), nt)), nt)
+        times[nt] = time.perf_counter() - t0
+    b = max((times[long] - times[short]) / (long - short), 1e-12)
+    a = max(times[short] - b * short, 0.0)
+    per_step_units = int(mesh.n_r.sum())
+    rate = per_step_units * n_steps_target / (a + b * n_steps_target)
+    return {"value": rate, "unit": "element*radial*steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle factor+forward+exact gradient on an 8x4 patch of the benchmark's elements "
+                      f"(n_b 16, N_r 32, dt 2e-8, 1 shot): {times[short]:.2f} s at {short} steps, "
+                      f"{times[long]:.2f} s at {long} steps; fitted a + b*N_t with a = {a:.2f} s, "
+                      f"b = {b * 1e3:.2f} ms/step, rate extrapolated to N_t = {n_steps_target}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=4000, help="time steps of the workload")
+    ap.add_argument("--shots", type=int, default=4)
+    ap.add_argument("--solver-blocks", type=int, default=0, help="coarse-solve grid (0 = tuned default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(shots shard across GPUs by design, but it is not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2501_06748_amd as sb
+
+    dev = torch.device("cuda:0")
+    wl = W.config_paper(n_steps=args.nt, n_shots=args.shots)
+    mesh = wl.mesh
+    mh = sb.sbfwi_build_mesh(mesh.node_xy, mesh.elem_ptr, mesh.elem_nodes, mesh.n_r, xi0=wl.xi0)
+    info = sb.sbfwi_mesh_info(mh)
+    rho0 = torch.tensor(wl.models["homogeneous"], dtype=torch.float64, device=dev)
+    rho_true = torch.tensor(wl.models["voids_floor_half"], dtype=torch.float64, device=dev)
+    src = torch.tensor(wl.src_nodes, dtype=torch.int64, device=dev)
+    wav = torch.tensor(wl.wavelets, dtype=torch.float64, device=dev)
+    rec = torch.tensor(wl.rec_nodes, dtype=torch.int64, device=dev)
+    S, R, N = wl.n_shots, len(wl.rec_nodes), wl.n_steps
+    traces = torch.zeros((S, R, N), dtype=torch.float64, device=dev)
+    observed = torch.zeros((S, R, N), dtype=torch.float64, device=dev)
+    misfit = torch.zeros(1, dtype=torch.float64, device=dev)
+    grad = torch.zeros(info["n_params"], dtype=torch.float64, device=dev)
+
+    def factor(rho):
+        f = sb.sbfwi_factor_elements(mh, rho, wl.c, wl.dt, wl.beta, wl.gamma)
+        if args.solver_blocks:
+            sb.sbfwi_set_launch(f, 0, args.solver_blocks)
+        return f
+
+    # observed data (outside the timed region)
+    ft = factor(rho_true)
+    sb.sbfwi_forward(ft, src, wav, rec, observed)
+    ft.close()
+    torch.cuda.synchronize()
+    print(f"[bench] observed data simulated ({wl.name}, {S} shots, {N} steps)", file=sys.stderr, flush=True)
+
+    def step():
+        f = factor(rho0)
+        ck = sb.sbfwi_forward(f, src, wav, rec, traces, n_ckpt=-1)
+        sb.sbfwi_gradient(f, ck, observed, traces, sb.GRAD_EXACT, misfit, grad)
+        stats = sb.sbfwi_solver_stats(f)
+        ck.close()
+        f.close()
+        return stats
+
+    sb.sbfwi_profile(0xFFF)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    warm = sb.sbfwi_profile_read(reset=True)
+    print(f"[bench] warmup done: {json.dumps({k: round(v['ms'], 1) for k, v in warm.items()})}", file=sys.stderr,
+          flush=True)
+    dominant = max((k for k in warm if k != "factor"), key=lambda k: warm[k]["ms"]) if warm else "recover"
+    sb.sbfwi_profile([dominant])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        stats = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    live = sb.sbfwi_profile_read(reset=True)
+    print(f"[bench] timed {args.steps} step(s) in {el:.3f} s", file=sys.stderr, flush=True)
+    sb.sbfwi_profile(0)
+
+    units = int(mesh.n_r.astype(np.int64).sum()) * N * S
+    value = units * args.steps / el
+    kb = kernel_bytes(mesh, S)
+    d_launches = live.get(dominant, {}).get("launches", 0)
+    d_ms = live.get(dominant, {}).get("ms", 0.0)
+    avg_s = d_ms / 1e3 / max(d_launches, 1)
+    if dominant in kb:
+        achieved = kb[dominant] / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant, wl.name),
+                "kernel": dominant, "avg_launch_us": avg_s * 1e6, "launches": d_launches,
+                "algorithmic_bytes_per_launch": kb[dominant]}
+    else:
+        roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
+                "kernel": dominant, "avg_launch_us": avg_s * 1e6, "launches": d_launches}
+    breakdown = {k: round(v["ms"] / max(args.warmup, 1), 3) for k, v in warm.items()}
+    out = {
+        "metric": "element*radial*steps/s fwd+adj FP64",
+        "value": value,
+        "unit": "element*radial*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "elements": mesh.n_elem, "n_b": 16, "n_r": 32, "time_steps": N,
+                   "shots": S, "receivers": R, "dt": wl.dt, "checkpoints": "sqrt(T)", "gradient": "exact",
+                   "units_per_step": units},
+        "roofline": roof,
+        "kernel_ms_per_step_warmup": breakdown,
+        "coarse_solver": stats,
+        "misfit": float(misfit.item()),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

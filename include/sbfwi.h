@@ -113,6 +113,10 @@ int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, double dt,
 /* Solver controls: relative residual tolerance (default 1e-13) and iteration cap (default 500). */
 int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
 
+/* Launch-shape controls (results do not depend on them beyond rounding order):
+ *   param 0: blocks of 1024 threads in the cooperative coarse-solve grid (1 .. 256, default 32). */
+int sbfwi_set_launch(sbfwi_factors f, int param, int value);
+
 /*
  * Copies factor data to host memory (for inspection and tests), synchronous.
  *   which = 0: S_e of every element, element after element, row-major n_b x n_b
@@ -187,8 +191,27 @@ int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
 /* Checkpoint store footprint in bytes (host_out[0]) and checkpoint interval (host_out[1]). */
 int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* host_out);
 
+/* Coarse-solve statistics accumulated on these factors (synchronous):
+ * host_out[0] = solves, [1] = total Krylov iterations, [2] = largest iteration count.
+ * reset != 0 clears them afterwards. */
+int sbfwi_solver_stats(sbfwi_factors f, int64_t* host_out, int reset);
+
 /* Device bytes a factored model holds (host_out[0]). */
 int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
+
+/*
+ * Live kernel timing.  sbfwi_profile(mask) brackets every launch of the kernels
+ * whose bit is set with HIP events on the launch stream (bit ids: 0 condense,
+ * 1 recover, 2 coarse solve, 3 source gather, 4 nodal update, 5 transposed
+ * condense, 6 transposed recover, 7 adjoint gather, 8 adjoint nodal update,
+ * 9 exact-gradient contraction, 10 paper-kernel correlation, 11 factorisation).
+ * A sweep over elements of several n_b classes counts as one launch.
+ * sbfwi_profile_read waits for the recorded events and writes, for each of
+ * the 16 ids, host_out[2 id] = launches and host_out[2 id + 1] = total ms;
+ * reset != 0 clears the totals.  One host thread only.
+ */
+int sbfwi_profile(uint32_t kernel_mask);
+int sbfwi_profile_read(double* host_out, int reset);
 
 void sbfwi_destroy_mesh(sbfwi_mesh m);
 void sbfwi_destroy_factors(sbfwi_factors f);

@@ -131,6 +131,10 @@ def sbfwi_set_solver(f: FactorsHandle, rtol=1e-13, max_iter=500):
     check(lib().sbfwi_set_solver(f, float(rtol), int(max_iter)))
 
 
+def sbfwi_set_launch(f: FactorsHandle, param: int, value: int):
+    check(lib().sbfwi_set_launch(f, int(param), int(value)))
+
+
 def sbfwi_copy_factor_data(f: FactorsHandle, which: int, count: int) -> np.ndarray:
     out = np.empty(count, dtype=np.float64)
     check(lib().sbfwi_copy_factor_data(f, int(which), out.ctypes.data_as(C.c_void_p)))
@@ -178,6 +182,29 @@ def sbfwi_ckpt_info(ck: CkptHandle) -> dict:
     buf = np.zeros(2, dtype=np.int64)
     check(lib().sbfwi_ckpt_info(ck, buf.ctypes.data_as(C.c_void_p)))
     return {"bytes": int(buf[0]), "interval": int(buf[1])}
+
+
+def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:
+    buf = np.zeros(3, dtype=np.int64)
+    check(lib().sbfwi_solver_stats(f, buf.ctypes.data_as(C.c_void_p), int(bool(reset))))
+    return {"solves": int(buf[0]), "iterations": int(buf[1]), "max_iterations": int(buf[2])}
+
+
+PROFILE_KERNELS = ["condense", "recover", "coarse_solve", "source_gather", "nodal_update", "adj_condense",
+                   "adj_recover", "adj_gather", "adj_nodal_update", "grad_exact", "grad_paper", "factor"]
+
+
+def sbfwi_profile(kernels):
+    """Enable live event timing for the named kernels (or an int mask)."""
+    mask = kernels if isinstance(kernels, int) else sum(1 << PROFILE_KERNELS.index(k) for k in kernels)
+    check(lib().sbfwi_profile(mask))
+
+
+def sbfwi_profile_read(reset=False) -> dict:
+    buf = np.zeros(32, dtype=np.float64)
+    check(lib().sbfwi_profile_read(buf.ctypes.data_as(C.c_void_p), int(bool(reset))))
+    return {name: {"launches": int(buf[2 * i]), "ms": float(buf[2 * i + 1])}
+            for i, name in enumerate(PROFILE_KERNELS) if buf[2 * i] > 0}
 
 
 def sbfwi_factors_info(f: FactorsHandle) -> dict:

@@ -30,6 +30,7 @@ SIGNATURES = {
     "sbfwi_mesh_info": (i32, [vp, vp]),
     "sbfwi_factor_elements": (i32, [vp, vp, dbl, dbl, dbl, dbl, i32, i32, vp, C.POINTER(vp)]),
     "sbfwi_set_solver": (i32, [vp, dbl, i32]),
+    "sbfwi_set_launch": (i32, [vp, i32, i32]),
     "sbfwi_copy_factor_data": (i32, [vp, i32, vp]),
     "sbfwi_coarse_pattern": (i32, [vp, vp, vp]),
     "sbfwi_forward": (i32, [vp, i32, i64, vp, vp, i32, vp, vp, i32, C.POINTER(vp), vp]),
@@ -37,6 +38,9 @@ SIGNATURES = {
     "sbfwi_gradient": (i32, [vp, vp, vp, vp, i32, vp, vp, vp]),
     "sbfwi_ckpt_info": (i32, [vp, vp]),
     "sbfwi_factors_info": (i32, [vp, vp]),
+    "sbfwi_solver_stats": (i32, [vp, vp, i32]),
+    "sbfwi_profile": (i32, [C.c_uint32]),
+    "sbfwi_profile_read": (i32, [vp, i32]),
     "sbfwi_destroy_mesh": (None, [vp]),
     "sbfwi_destroy_factors": (None, [vp]),
     "sbfwi_destroy_ckpt": (None, [vp]),

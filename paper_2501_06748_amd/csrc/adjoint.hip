@@ -271,96 +271,136 @@ __global__ void adj_nodal_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a) {
   a.AB[g] = f.c3 * vb + f.a2 * wb;
 }
 
-struct GradCtx {
-  int nb, n, NS, s;
-  double xi0, h;
-  int64_t xo;
-  const double* X;
-  const double* lam;
-  __device__ double Xv(int l, int i) const { return X[(xo + (int64_t)(l + 1) * nb + i) * NS + s]; }
-  __device__ double Lv(int r, int i) const { return lam[(xo + (int64_t)(r + 1) * nb + i) * NS + s]; }
-  __device__ double xi(int j) const { return xi0 + h * j; }
-  // FD weight of level m in the radial derivative at row r (one-sided at the ends)
-  __device__ double dw(int r, int m) const {
-    if (r == 0) return m == 0 ? -1.0 / h : (m == 1 ? 1.0 / h : 0.0);
-    if (r == n) return m == n - 1 ? -1.0 / h : (m == n ? 1.0 / h : 0.0);
-    return m == r - 1 ? -0.5 / h : (m == r + 1 ? 0.5 / h : 0.0);
-  }
-  // entry (i, j) of the sensitivity of the misfit-Lagrangian to E^tau at level m
-  __device__ double ebar(int tau, int m, int i, int j) const {
-    double v = 0.0;
-    if (tau == 2) return -Lv(m, i) * Xv(m, j);
-    const double xm = xi(m);
-    {  // row m itself
-      double dj = Xv(m + 1, j) - Xv(m - 1, j);
-      if (tau == 0) {
-        double lap = Xv(m - 1, j) - 2.0 * Xv(m, j) + Xv(m + 1, j);
-        v += Lv(m, i) * (xm * xm / (h * h) * lap + xm / (2.0 * h) * dj);
-      } else {
-        double di = Xv(m + 1, i) - Xv(m - 1, i);
-        v += xm / (2.0 * h) * (di * Lv(m, j) - Lv(m, i) * dj);
-      }
-    }
-    for (int r = m - 1; r <= m + 1; ++r) {  // rows whose radial derivative uses level m
-      if (r < 0 || r > n) continue;
-      double w = dw(r, m);
-      if (w == 0.0) continue;
-      double xr = xi(r);
-      if (tau == 0) v += w * xr * xr / (2.0 * h) * Lv(r, i) * (Xv(r + 1, j) - Xv(r - 1, j));
-      else v += w * xr * Xv(r, i) * Lv(r, j);
-    }
-    if (m == 0) {  // flux row at xi0
-      if (tau == 0) v += xi(0) / (2.0 * h) * Lv(-1, i) * (Xv(1, j) - Xv(-1, j));
-      else v += Xv(0, i) * Lv(-1, j);
-    }
-    if (m == n) {  // flux row at the boundary
-      if (tau == 0) v += xi(n) / (2.0 * h) * Lv(n + 1, i) * (Xv(n + 1, j) - Xv(n - 1, j));
-      else v += Xv(n, i) * Lv(n + 1, j);
-    }
-    return v;
-  }
+// Exact gradient for one step: one wavefront per (element, shot group).  The
+// forward unknowns X (levels m-2 .. m+2) and adjoint rows lambda (m-1 .. m+1)
+// live in rolling LDS windows; for every level m the band entries of the
+// sensitivities E-bar of E0, E1, E2 (and lambda_m a_m^T for M0) are formed per
+// item (i, s), then contracted with the per-segment density derivatives alpha
+// and summed over the shots of the group.
+template <int NBT, int S>
+struct GradLds {
+  double X[5][NBT * S];
+  double L[3][NBT * S];
+  double A[NBT * S];
+  double E[3][3][NBT * S];   // [tau][sub, diag, super][item]
+  double M[3][NBT * S];
+  double g[NBT * S];
 };
 
-// One thread per fine-grid parameter (element e, level m, node k).
-__global__ void grad_exact_kernel(MeshDev m, FactorsDev f, int NS, int64_t n_params, const int32_t* __restrict__ par_elem,
-                                  const double* __restrict__ X, const double* __restrict__ lam,
-                                  const double* __restrict__ acc_a, double* __restrict__ grad) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_params) return;
-  const int e = par_elem[p];
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                        FactorsDev f, int NS, const double* __restrict__ X,
+                                                        const double* __restrict__ lam,
+                                                        const double* __restrict__ acc_a,
+                                                        double* __restrict__ grad, int s0) {
+  __shared__ GradLds<NBT, S> L;
+  const int e = elems[blockIdx.x];
+  const int ns = min(S, NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1;
-  const int64_t po = m.par_off[e], lo = m.loop_off[e];
-  const int loc = (int)(p - po);
-  const int lev = loc / nb, kk = loc % nb;
-  const int km = md(kk - 1, nb), kp = md(kk + 1, nb);
-  GradCtx c;
-  c.nb = nb; c.n = n; c.NS = NS; c.xi0 = m.xi0; c.h = (1.0 - m.xi0) / n; c.xo = m.x_off[e];
-  c.X = X; c.lam = lam;
-  const double* gl = f.gbasis + 32 * (lo + km);   // segment kk-1: nodes (km, kk), kk is its end 1
-  const double* gr = f.gbasis + 32 * (lo + kk);   // segment kk: nodes (kk, kp), kk is its end 0
-  const double xm = c.xi(lev);
-  double g = 0.0;
-  for (int s = 0; s < NS; ++s) {
-    c.s = s;
-    double acc = 0.0;
-    for (int tau = 0; tau < 3; ++tau) {
-      const double* al = gl + tau * 8 + 4;
-      const double* ar = gr + tau * 8 + 0;
-      acc -= al[0] * c.ebar(tau, lev, km, km) + al[1] * c.ebar(tau, lev, km, kk) +
-             al[2] * c.ebar(tau, lev, kk, km) + al[3] * c.ebar(tau, lev, kk, kk);
-      acc -= ar[0] * c.ebar(tau, lev, kk, kk) + ar[1] * c.ebar(tau, lev, kk, kp) +
-             ar[2] * c.ebar(tau, lev, kp, kk) + ar[3] * c.ebar(tau, lev, kp, kp);
+  const int64_t po = m.par_off[e], lo = m.loop_off[e], xo = m.x_off[e];
+  const double h = (1.0 - m.xi0) / n, xi0 = m.xi0;
+  const int items = nb * S;
+  auto xs = [&](int l) { return (l + 2) % 5; };
+  auto ls = [&](int r) { return (r + 1) % 3; };
+  auto load_x = [&](int l) {
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      L.X[xs(l)][it] = s < ns ? X[(xo + (int64_t)(l + 1) * nb + i) * NS + s0 + s] : 0.0;
     }
-    // mass: xi^2 lambda_m^T dM0 a_m
-    auto A = [&](int i) { return acc_a[(po + (int64_t)lev * nb + i) * NS + s]; };
-    const double* ml = gl + 3 * 8 + 4;
-    const double* mr = gr + 3 * 8 + 0;
-    double lm = c.Lv(lev, km), l0 = c.Lv(lev, kk), lp = c.Lv(lev, kp);
-    acc += xm * xm * (ml[0] * lm * A(km) + ml[1] * lm * A(kk) + ml[2] * l0 * A(km) + ml[3] * l0 * A(kk) +
-                      mr[0] * l0 * A(kk) + mr[1] * l0 * A(kp) + mr[2] * lp * A(kk) + mr[3] * lp * A(kp));
-    g += acc;
+  };
+  auto load_l = [&](int r) {
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      L.L[ls(r)][it] = s < ns ? lam[(xo + (int64_t)(r + 1) * nb + i) * NS + s0 + s] : 0.0;
+    }
+  };
+  // FD weight of level mm in the radial derivative at row r (one-sided at the ends)
+  auto dw = [&](int r, int mm) -> double {
+    if (r == 0) return mm == 0 ? -1.0 / h : (mm == 1 ? 1.0 / h : 0.0);
+    if (r == n) return mm == n - 1 ? -1.0 / h : (mm == n ? 1.0 / h : 0.0);
+    return mm == r - 1 ? -0.5 / h : (mm == r + 1 ? 0.5 / h : 0.0);
+  };
+  load_x(-1);
+  load_x(0);
+  load_x(1);
+  load_l(-1);
+  load_l(0);
+  for (int lev = 0; lev <= n; ++lev) {
+    if (lev + 2 <= n + 1) load_x(lev + 2);
+    if (lev + 1 <= n + 1) load_l(lev + 1);
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      L.A[it] = s < ns ? acc_a[(po + (int64_t)lev * nb + i) * NS + s0 + s] : 0.0;
+    }
+    __syncthreads();
+    const double xm = xi0 + h * lev;
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int i = it / S, s = it % S;
+      auto Xv = [&](int l, int node) { return L.X[xs(l)][node * S + s]; };
+      auto Lv = [&](int r, int node) { return L.L[ls(r)][node * S + s]; };
+      const int jn[3] = {md(i - 1, nb), i, md(i + 1, nb)};   // sub, diag, super columns
+      for (int t = 0; t < 3; ++t) {
+        const int j = jn[t];
+        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+        {  // row lev itself
+          double dj = Xv(lev + 1, j) - Xv(lev - 1, j);
+          double di = Xv(lev + 1, i) - Xv(lev - 1, i);
+          double lap = Xv(lev - 1, j) - 2.0 * Xv(lev, j) + Xv(lev + 1, j);
+          e0 += Lv(lev, i) * (xm * xm / (h * h) * lap + xm / (2.0 * h) * dj);
+          e1 += xm / (2.0 * h) * (di * Lv(lev, j) - Lv(lev, i) * dj);
+          e2 -= Lv(lev, i) * Xv(lev, j);
+        }
+        for (int r = lev - 1; r <= lev + 1; ++r) {  // rows whose radial derivative uses this level
+          if (r < 0 || r > n) continue;
+          double w = dw(r, lev);
+          if (w == 0.0) continue;
+          double xr = xi0 + h * r;
+          e0 += w * xr * xr / (2.0 * h) * Lv(r, i) * (Xv(r + 1, j) - Xv(r - 1, j));
+          e1 += w * xr * Xv(r, i) * Lv(r, j);
+        }
+        if (lev == 0) {  // flux row at xi0
+          e0 += xi0 / (2.0 * h) * Lv(-1, i) * (Xv(1, j) - Xv(-1, j));
+          e1 += Xv(0, i) * Lv(-1, j);
+        }
+        if (lev == n) {  // flux row at the boundary
+          e0 += (xi0 + h * n) / (2.0 * h) * Lv(n + 1, i) * (Xv(n + 1, j) - Xv(n - 1, j));
+          e1 += Xv(n, i) * Lv(n + 1, j);
+        }
+        L.E[0][t][it] = e0;
+        L.E[1][t][it] = e1;
+        L.E[2][t][it] = e2;
+        L.M[t][it] = Lv(lev, i) * L.A[j * S + s];
+      }
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += WT) {
+      int k = it / S, s = it % S;
+      int km = md(k - 1, nb), kp = md(k + 1, nb);
+      const double* gl = f.gbasis + 32 * (lo + km);   // segment (km, k): k is its end 1
+      const double* gr = f.gbasis + 32 * (lo + k);    // segment (k, kp): k is its end 0
+      auto D = [&](const double (*T)[NBT * S], int node, int t) { return T[t][node * S + s]; };
+      double acc = 0.0;
+      for (int tau = 0; tau < 3; ++tau) {
+        const double (*T)[NBT * S] = L.E[tau];
+        const double* al = gl + tau * 8 + 4;
+        const double* ar = gr + tau * 8;
+        acc -= al[0] * D(T, km, 1) + al[1] * D(T, km, 2) + al[2] * D(T, k, 0) + al[3] * D(T, k, 1);
+        acc -= ar[0] * D(T, k, 1) + ar[1] * D(T, k, 2) + ar[2] * D(T, kp, 0) + ar[3] * D(T, kp, 1);
+      }
+      const double* ml = gl + 24 + 4;
+      const double* mr = gr + 24;
+      acc += xm * xm * (ml[0] * D(L.M, km, 1) + ml[1] * D(L.M, km, 2) + ml[2] * D(L.M, k, 0) + ml[3] * D(L.M, k, 1) +
+                        mr[0] * D(L.M, k, 1) + mr[1] * D(L.M, k, 2) + mr[2] * D(L.M, kp, 0) + mr[3] * D(L.M, kp, 1));
+      L.g[it] = s < ns ? acc : 0.0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += WT) {
+      double t = 0.0;
+      for (int s = 0; s < S; ++s) t += L.g[k * S + s];
+      grad[po + (int64_t)lev * nb + k] += t;
+    }
+    __syncthreads();
   }
-  grad[p] += g;
 }
 
 // Paper kernel: g -= dt * sum_s v~ v at every fine-grid point.
@@ -421,12 +461,42 @@ void launch_adj_all(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const A
 }
 
 void launch_adj_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+  ProfScope ps(condense ? PK_ADJ_CONDENSE : PK_ADJ_RECOVER, st);
   if (a.NS >= 4)
     launch_adj_all<4>(condense, m, f, a, st);
   else if (a.NS >= 2)
     launch_adj_all<2>(condense, m, f, a, st);
   else
     launch_adj_all<1>(condense, m, f, a, st);
+}
+
+template <int NBT, int S>
+void launch_grad_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, int NS, const double* X, const double* lam,
+                     const double* acc, double* grad, hipStream_t st) {
+  int64_t cnt = (int64_t)m->h_class_elems[cl].size();
+  if (cnt == 0) return;
+  // shot groups run one after another on the stream, so every gradient entry
+  // has a single writer at a time and the sum over shots is deterministic
+  for (int s0 = 0; s0 < NS; s0 += S)
+    hipLaunchKernelGGL((grad_exact_kernel<NBT, S>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl], m->d,
+                       f, NS, X, lam, acc, grad, s0);
+}
+
+template <int S>
+void launch_grad_all(sbfwi_mesh_s* m, const FactorsDev& f, int NS, const double* X, const double* lam,
+                     const double* acc, double* grad, hipStream_t st) {
+  launch_grad_cls<8, S>(m, 0, f, NS, X, lam, acc, grad, st);
+  launch_grad_cls<16, S>(m, 1, f, NS, X, lam, acc, grad, st);
+  launch_grad_cls<24, S>(m, 2, f, NS, X, lam, acc, grad, st);
+}
+
+void launch_grad(sbfwi_mesh_s* m, const FactorsDev& f, int NS, const double* X, const double* lam,
+                 const double* acc, double* grad, hipStream_t st) {
+  ProfScope ps(PK_GRAD_EXACT, st);
+  if (NS <= 1) launch_grad_all<1>(m, f, NS, X, lam, acc, grad, st);
+  else if (NS <= 2) launch_grad_all<2>(m, f, NS, X, lam, acc, grad, st);
+  else if (NS <= 4) launch_grad_all<4>(m, f, NS, X, lam, acc, grad, st);
+  else launch_grad_all<8>(m, f, NS, X, lam, acc, grad, st);
 }
 
 struct AdjWork {
@@ -525,18 +595,24 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
                                         : fseg + (k - k0 - 1) * m->n_params * NS;
       if (mode == SBFWI_GRAD_EXACT) {
         launch_adj_sweep(true, m, f->d, a, st);
+        {
+        ProfScope ps(PK_ADJ_RHS, st);
         hipLaunchKernelGGL(adj_rhs_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a, w.rhs, ck->n_rec,
                            ck->rec_node, adj_src, N, k);
+        }
         SBFWI_HIP(hipGetLastError());
         SBFWI_CHECK(sbfwi_coarse_solve(f, &w.cw, 1, w.rhs, w.lamB, k, st));
         launch_adj_sweep(false, m, f->d, a, st);
-        hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
-        hipLaunchKernelGGL(grad_exact_kernel, dim3(gp), dim3(256), 0, st, m->d, f->d, NS, m->n_params,
-                           w.par_elem, X, (const double*)w.lam, Fs, grad);
+        {
+          ProfScope ps(PK_ADJ_NODAL, st);
+          hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
+        }
+        launch_grad(m, f->d, NS, X, (const double*)w.lam, Fs, grad, st);
         SBFWI_HIP(hipGetLastError());
       } else {
         const int64_t kp = N + 1 - k;  // back-propagation step paired with forward step k
         SBFWI_CHECK(sbfwi_forward_step(f, &bw, kp, bsrc, 0, nullptr, nullptr, N, nullptr, nullptr, 0, st));
+        ProfScope ps(PK_GRAD_PAPER, st);
         hipLaunchKernelGGL(grad_paper_kernel, dim3(gp), dim3(256), 0, st, m->d, NS, f->dt, m->n_params,
                            w.par_elem, (const double*)bw.v, (const double*)bw.V, Fs, grad);
         SBFWI_HIP(hipGetLastError());
@@ -562,7 +638,7 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   }
   if (rc == SBFWI_OK) {
     int flags0[4] = {0, -1, 0, 0};
-    hipError_t he = hipMemcpyAsync(f->d.status, flags0, sizeof(flags0), hipMemcpyHostToDevice, st);
+    hipError_t he = hipMemcpyAsync(f->d.status, flags0, 2 * sizeof(int), hipMemcpyHostToDevice, st);
     if (he != hipSuccess) rc = sbfwi_fail(SBFWI_EHIP, "status reset: %s", hipGetErrorString(he));
   }
   if (rc == SBFWI_OK) rc = adjoint_run(f, ck, adj_src, mode, grad, st, w, fw, bw, xseg, fseg);

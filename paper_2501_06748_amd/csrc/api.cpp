@@ -72,6 +72,18 @@ extern "C" int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter) {
   return SBFWI_OK;
 }
 
+extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
+  if (!f) return sbfwi_fail(SBFWI_EINVAL, "NULL factors");
+  switch (param) {
+    case 0:
+      if (value < 1 || value > 256) return sbfwi_fail(SBFWI_EINVAL, "solver blocks must be in 1..256");
+      f->solver_blocks = value;
+      return SBFWI_OK;
+    default:
+      return sbfwi_fail(SBFWI_EINVAL, "unknown launch parameter %d", param);
+  }
+}
+
 extern "C" int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* dst) {
   if (!f || !dst) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   const double* src = nullptr;
@@ -84,6 +96,20 @@ extern "C" int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* dst) {
     default: return sbfwi_fail(SBFWI_EINVAL, "unknown factor data %d", which);
   }
   SBFWI_HIP(hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
+  return SBFWI_OK;
+}
+
+extern "C" int sbfwi_solver_stats(sbfwi_factors f, int64_t* out, int reset) {
+  if (!f || !out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  int st[8];
+  SBFWI_HIP(hipMemcpy(st, f->d.status, sizeof(st), hipMemcpyDeviceToHost));
+  out[0] = st[5];
+  out[1] = st[4];
+  out[2] = st[3];
+  if (reset) {
+    int z[3] = {0, 0, 0};
+    SBFWI_HIP(hipMemcpy(f->d.status + 3, z, sizeof(z), hipMemcpyHostToDevice));
+  }
   return SBFWI_OK;
 }
 
@@ -132,7 +158,7 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
   SBFWI_CHECK(sbfwi_step_work_alloc(&w, m, n_shots));
   SBFWI_CHECK(sbfwi_step_zero(m, &w, s));
   int flags0[4] = {0, -1, 0, 0};
-  SBFWI_HIP(hipMemcpyAsync(f->d.status, flags0, sizeof(flags0), hipMemcpyHostToDevice, s));
+  SBFWI_HIP(hipMemcpyAsync(f->d.status, flags0, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   const int64_t ssz = sbfwi_state_size(m, n_shots);
   if (ck) {
     ck->f = f;

@@ -18,7 +18,7 @@ namespace cg = cooperative_groups;
 
 namespace {
 
-constexpr int CT = 256;     // threads per block
+constexpr int CT = 1024;    // threads per block
 constexpr int MAXS = 16;    // max right-hand sides per solve
 constexpr int NQ = 2;       // max quantities per reduction phase
 
@@ -35,7 +35,7 @@ struct SolveArgs {
   double* partial;   // [4 phases][NQ][nblocks][NS]
   double rtol;
   int max_iter;
-  int* status;       // [0] flags, [1] step of failure, [2] last iteration count
+  int* status;       // [0] flags, [1] step of failure, [2] last, [3] max, [4] total iterations, [5] solves
   int64_t step;
 };
 
@@ -53,46 +53,70 @@ __device__ __forceinline__ void spmv_row(const SolveArgs& a, int64_t r, const do
   }
 }
 
-// Sum of v over the block in a fixed order (wavefront shuffle tree, then the
-// waves in index order); the result is returned to every thread.
-__device__ double block_sum(double v, double* wsum) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// Block sums of nv values held by every thread, in a fixed order (wavefront
+// shuffle tree, then the waves in index order); results land in tot[0..nv).
+template <int NV>
+__device__ void block_sums(double (&v)[NV], int nv, double* wsum /*[CT/64][NV]*/, double* tot /*[NV]*/) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if (q >= nv) break;
+    double x = v[q];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) wsum[wave * NV + q] = x;
+  }
   __syncthreads();
-  if (lane == 0) wsum[wave] = v;
+  if (threadIdx.x < nv) {
+    double t = 0.0;
+    for (int w = 0; w < CT / 64; ++w) t += wsum[w * NV + threadIdx.x];
+    tot[threadIdx.x] = t;
+  }
   __syncthreads();
-  double t = 0.0;
-  for (int w = 0; w < CT / 64; ++w) t += wsum[w];
-  return t;
 }
 
 // Block partials of nq quantities x NS shots into this block's slot of a phase.
 template <int NSM>
-__device__ void block_partial(double (&loc)[NQ][NSM], int nq, const SolveArgs& a, int phase, double* wsum) {
-  for (int q = 0; q < nq; ++q)
-    for (int s = 0; s < a.NS; ++s) {
-      double t = block_sum(loc[q][s], wsum);
-      if (threadIdx.x == 0)
-        a.partial[(((int64_t)phase * NQ + q) * gridDim.x + blockIdx.x) * a.NS + s] = t;
-    }
+__device__ void block_partial(double (&loc)[NQ][NSM], int nq, const SolveArgs& a, int phase, double* wsum,
+                              double* tot) {
+  double v[NQ * NSM];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) v[q * NSM + s] = loc[q][s];
+  block_sums<NQ * NSM>(v, nq * NSM, wsum, tot);
+  if (threadIdx.x < nq * NSM) {
+    int q = threadIdx.x / NSM, s = threadIdx.x % NSM;
+    if (s < a.NS) a.partial[(((int64_t)phase * NQ + q) * gridDim.x + blockIdx.x) * a.NS + s] = tot[threadIdx.x];
+  }
 }
 
 // Every block sums all block partials of a phase in the same fixed order.
 template <int NSM>
-__device__ void grid_total(int nq, const SolveArgs& a, int phase, double* wsum, double (&out)[NQ][NSM]) {
+__device__ void grid_total(int nq, const SolveArgs& a, int phase, double* wsum, double* tots,
+                           double (&out)[NQ][NSM]) {
   const int nbk = gridDim.x;
-  for (int q = 0; q < nq; ++q)
+  double v[NQ * NSM];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
     for (int s = 0; s < NSM; ++s) {
-      if (s >= a.NS) { out[q][s] = 0.0; continue; }
       double acc = 0.0;
-      for (int b = threadIdx.x; b < nbk; b += CT) acc += a.partial[(((int64_t)phase * NQ + q) * nbk + b) * a.NS + s];
-      out[q][s] = block_sum(acc, wsum);
+      if (q < nq && s < a.NS)
+        for (int b = threadIdx.x; b < nbk; b += CT) acc += a.partial[(((int64_t)phase * NQ + q) * nbk + b) * a.NS + s];
+      v[q * NSM + s] = acc;
     }
+  block_sums<NQ * NSM>(v, nq * NSM, wsum, tots);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) out[q][s] = (q < nq && s < a.NS) ? tots[q * NSM + s] : 0.0;
+  __syncthreads();
 }
 
 template <int NSM>
 __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
-  __shared__ double red[CT / 64];
+  __shared__ double red[(CT / 64) * NQ * NSM];
+  __shared__ double tsh[NQ * NSM];
   double tot[NQ][NSM];
   cg::grid_group grid = cg::this_grid();
   const int64_t gsz = (int64_t)gridDim.x * CT;
@@ -120,9 +144,9 @@ __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
       loc[1][s] += rv * rv;
     }
   }
-  block_partial<NSM>(loc, 2, a, 0, red);
+  block_partial<NSM>(loc, 2, a, 0, red, tsh);
   grid.sync();
-  grid_total<NSM>(2, a, 0, red, tot);
+  grid_total<NSM>(2, a, 0, red, tsh, tot);
   bool any = false;
 #pragma unroll
   for (int s = 0; s < NSM; ++s) {
@@ -176,9 +200,9 @@ __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
         loc[0][s] += a.rhat[g] * kx[s];
       }
     }
-    block_partial<NSM>(loc, 1, a, 1, red);
+    block_partial<NSM>(loc, 1, a, 1, red, tsh);
     grid.sync();
-    grid_total<NSM>(1, a, 1, red, tot);
+    grid_total<NSM>(1, a, 1, red, tsh, tot);
 #pragma unroll
     for (int s = 0; s < NSM; ++s)
       if (s < NS && active[s]) alpha[s] = rho_old[s] / tot[0][s];
@@ -196,9 +220,9 @@ __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
         loc[0][s] += sv * sv;
       }
     }
-    block_partial<NSM>(loc, 1, a, 2, red);
+    block_partial<NSM>(loc, 1, a, 2, red, tsh);
     grid.sync();
-    grid_total<NSM>(1, a, 2, red, tot);
+    grid_total<NSM>(1, a, 2, red, tsh, tot);
     bool sdone[NSM];
 #pragma unroll
     for (int s = 0; s < NSM; ++s) sdone[s] = (s < NS && active[s]) && (tot[0][s] <= a.rtol * a.rtol * bn2[s]);
@@ -221,9 +245,9 @@ __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
         loc[1][s] += kx[s] * kx[s];
       }
     }
-    block_partial<NSM>(loc, 2, a, 3, red);
+    block_partial<NSM>(loc, 2, a, 3, red, tsh);
     grid.sync();
-    grid_total<NSM>(2, a, 3, red, tot);
+    grid_total<NSM>(2, a, 3, red, tsh, tot);
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
       if (sdone[s]) active[s] = false;
@@ -244,9 +268,9 @@ __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
         loc[1][s] += rv * rv;
       }
     }
-    block_partial<NSM>(loc, 2, a, 0, red);
+    block_partial<NSM>(loc, 2, a, 0, red, tsh);
     grid.sync();
-    grid_total<NSM>(2, a, 0, red, tot);
+    grid_total<NSM>(2, a, 0, red, tsh, tot);
     any = false;
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
@@ -274,6 +298,9 @@ __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.status[2] = it;
+    atomicMax(&a.status[3], it);
+    atomicAdd(&a.status[4], it);
+    atomicAdd(&a.status[5], 1);
     if (any) {
       atomicOr(&a.status[0], 2);
       atomicCAS(&a.status[1], -1, (int)a.step);
@@ -284,7 +311,7 @@ __global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
 int g_coop_blocks[5] = {0, 0, 0, 0, 0};
 
 template <int NSM>
-int coop_grid(int idx, int64_t n) {
+int coop_grid(int idx, int64_t n, int want_blocks) {
   if (g_coop_blocks[idx] == 0) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -292,7 +319,10 @@ int coop_grid(int idx, int64_t n) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bicgstab_kernel<NSM>, CT, 0) != hipSuccess) return 0;
     g_coop_blocks[idx] = per * cus;
   }
+  // the cooperative grid barrier costs about 0.13 us per block on MI355X, so a
+  // small grid of large blocks is faster than filling the chip
   int64_t want = (n + CT - 1) / CT;
+  if (want > want_blocks) want = want_blocks;
   int64_t cap = g_coop_blocks[idx] < 256 ? g_coop_blocks[idx] : 256;
   if (want < 1) want = 1;
   return (int)(want < cap ? want : cap);
@@ -347,13 +377,14 @@ int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
   const void* fn;
   int blocks;
   switch (nsm) {
-    case 1: fn = (const void*)bicgstab_kernel<1>; blocks = coop_grid<1>(0, a.n); break;
-    case 2: fn = (const void*)bicgstab_kernel<2>; blocks = coop_grid<2>(1, a.n); break;
-    case 4: fn = (const void*)bicgstab_kernel<4>; blocks = coop_grid<4>(2, a.n); break;
-    case 8: fn = (const void*)bicgstab_kernel<8>; blocks = coop_grid<8>(3, a.n); break;
-    default: fn = (const void*)bicgstab_kernel<16>; blocks = coop_grid<16>(4, a.n); break;
+    case 1: fn = (const void*)bicgstab_kernel<1>; blocks = coop_grid<1>(0, a.n, f->solver_blocks); break;
+    case 2: fn = (const void*)bicgstab_kernel<2>; blocks = coop_grid<2>(1, a.n, f->solver_blocks); break;
+    case 4: fn = (const void*)bicgstab_kernel<4>; blocks = coop_grid<4>(2, a.n, f->solver_blocks); break;
+    case 8: fn = (const void*)bicgstab_kernel<8>; blocks = coop_grid<8>(3, a.n, f->solver_blocks); break;
+    default: fn = (const void*)bicgstab_kernel<16>; blocks = coop_grid<16>(4, a.n, f->solver_blocks); break;
   }
   if (blocks <= 0) return sbfwi_fail(SBFWI_EHIP, "cannot size the cooperative coarse-solve grid");
+  ProfScope ps(PK_SOLVE, s);
   SBFWI_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(CT), args, 0, s));
   return SBFWI_OK;
 }

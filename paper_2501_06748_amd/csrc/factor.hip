@@ -448,7 +448,7 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   A(&d.Kval, m->nnz);
   A(&d.KTval, m->nnz);
   A(&d.diag_inv, m->n_nodes);
-  if (rc == SBFWI_OK) rc = sbfwi_alloc(&d.status, 4);
+  if (rc == SBFWI_OK) rc = sbfwi_alloc(&d.status, 8);
   if (rc != SBFWI_OK) {
     sbfwi_factors_free(f);
     return rc;
@@ -457,8 +457,9 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
     sbfwi_factors_free(f);
     return sbfwi_fail(SBFWI_EHIP, "%s: %s", what, hipGetErrorString(e));
   };
-  hipError_t he = hipMemsetAsync(d.status, 0, 4 * sizeof(int), s);
+  hipError_t he = hipMemsetAsync(d.status, 0, 8 * sizeof(int), s);
   if (he != hipSuccess) return hip_fail(he, "hipMemsetAsync");
+  ProfScope ps_factor(PK_FACTOR, s);
   for (int cl = 0; cl < 3; ++cl) {
     int64_t cnt = (int64_t)m->h_class_elems[cl].size();
     if (cnt == 0) continue;

@@ -88,6 +88,7 @@ struct sbfwi_factors_s {
   double c = 0, dt = 0, beta = 0, gamma = 0;
   double rtol = 1e-13;
   int max_iter = 500;
+  int solver_blocks = 32;        // cooperative grid size of the coarse solve (tunable)
   int64_t bytes = 0;
   FactorsDev d;
 };
@@ -105,6 +106,23 @@ struct sbfwi_ckpt_s {
   double* xstore = nullptr;      // full storage: [n_steps][n_x*NS]
   double* fstore = nullptr;      // full storage: [n_steps][n_params*NS] accelerations a^k
   double* vstore = nullptr;      // full storage: [n_steps][n_params*NS] velocities v^k
+};
+
+// ---- live kernel timing (profiler.cpp) ----
+#define SBFWI_PROF_KERNELS 16
+enum {
+  PK_CONDENSE = 0, PK_RECOVER = 1, PK_SOLVE = 2, PK_RHS = 3, PK_NODAL = 4, PK_ADJ_CONDENSE = 5,
+  PK_ADJ_RECOVER = 6, PK_ADJ_RHS = 7, PK_ADJ_NODAL = 8, PK_GRAD_EXACT = 9, PK_GRAD_PAPER = 10,
+  PK_FACTOR = 11, PK_ASSEMBLE = 12
+};
+// Brackets the launches made during its lifetime with events on stream s when
+// kernel id is enabled by sbfwi_profile.
+struct ProfScope {
+  ProfScope(int id, hipStream_t s);
+  ~ProfScope();
+  int id_;
+  hipStream_t s_;
+  void* a_ = nullptr;
 };
 
 // ---- error handling / allocation (api.cpp) ----

@@ -317,6 +317,7 @@ void launch_all(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const StepA
 }
 
 void launch_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
+  ProfScope ps(condense ? PK_CONDENSE : PK_RECOVER, st);
   if (a.NS >= 4)
     launch_all<4>(condense, m, f, a, st);
   else if (a.NS == 3 || a.NS == 2)
@@ -384,13 +385,19 @@ int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceT
   a.xs = xs; a.fs = fs; a.field_kind = field_kind; a.vs = vs;
   launch_sweep(true, m, f->d, a, st);
   int64_t nn = m->n_nodes * w->NS;
+  {
+  ProfScope ps(PK_RHS, st);
   hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, m->d, w->NS, w->fhat,
                      w->F, w->U, w->V, w->A, w->Unew, f->dt, src, k);
+  }
   SBFWI_HIP(hipGetLastError());
   SBFWI_CHECK(sbfwi_coarse_solve(f, &w->cw, 0, w->F, w->Unew, k, st));
   int64_t tot = nn + (int64_t)n_rec * w->NS;
+  {
+  ProfScope ps(PK_NODAL, st);
   hipLaunchKernelGGL(nodal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m->n_nodes, w->NS,
                      f->d, w->Unew, w->U, w->V, w->A, n_rec, rec_node, traces, n_steps, k);
+  }
   launch_sweep(false, m, f->d, a, st);
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;
