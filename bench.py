@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nt", type=int, default=4000, help="time steps of the workload")
     ap.add_argument("--shots", type=int, default=4)
-    ap.add_argument("--solver-blocks", type=int, default=0, help="coarse-solve grid (0 = tuned default)")
+    ap.add_argument("--solver-iters", type=int, default=0, help="BiCGStab iterations enqueued per solve (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -168,8 +168,8 @@ def main():
 
     def factor(rho):
         f = sb.sbfwi_factor_elements(mh, rho, wl.c, wl.dt, wl.beta, wl.gamma)
-        if args.solver_blocks:
-            sb.sbfwi_set_launch(f, 0, args.solver_blocks)
+        if args.solver_iters:
+            sb.sbfwi_set_launch(f, 0, args.solver_iters)
         return f
 
     # observed data (outside the timed region)

@@ -114,7 +114,9 @@ int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, double dt,
 int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
 
 /* Launch-shape controls (results do not depend on them beyond rounding order):
- *   param 0: blocks of 1024 threads in the cooperative coarse-solve grid (1 .. 256, default 32). */
+ *   param 0: BiCGStab iterations enqueued as separate kernels per coarse solve (1 .. 1000,
+ *            default 13); iterations after convergence are no-ops, and a solve that needs
+ *            more continues in one cooperative kernel up to the limit of sbfwi_set_solver. */
 int sbfwi_set_launch(sbfwi_factors f, int param, int value);
 
 /*

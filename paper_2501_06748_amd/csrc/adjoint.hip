@@ -656,6 +656,7 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   sbfwi_dev_free(xseg);
   sbfwi_dev_free(fseg);
   if (rc != SBFWI_OK) return rc;
+  if (flags[0] & 8) return sbfwi_fail(SBFWI_EHIP, "adjoint: coarse-solve grid barrier timed out");
   if (flags[0] & 4) return sbfwi_fail(SBFWI_ENONFINITE, "non-finite coarse residual at step %d", flags[1]);
   if (flags[0] & 2) return sbfwi_fail(SBFWI_ENOCONV, "coarse solve did not converge at step %d", flags[1]);
   return SBFWI_OK;

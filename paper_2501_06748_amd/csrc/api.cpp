@@ -76,8 +76,8 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
   if (!f) return sbfwi_fail(SBFWI_EINVAL, "NULL factors");
   switch (param) {
     case 0:
-      if (value < 1 || value > 256) return sbfwi_fail(SBFWI_EINVAL, "solver blocks must be in 1..256");
-      f->solver_blocks = value;
+      if (value < 1 || value > 1000) return sbfwi_fail(SBFWI_EINVAL, "enqueued iterations must be in 1..1000");
+      f->enqueued_iters = value;
       return SBFWI_OK;
     default:
       return sbfwi_fail(SBFWI_EINVAL, "unknown launch parameter %d", param);
@@ -146,6 +146,7 @@ static int read_status(sbfwi_factors_s* f, hipStream_t s, const char* what) {
   int flags[4] = {0, -1, 0, 0};
   SBFWI_HIP(hipMemcpyAsync(flags, f->d.status, sizeof(flags), hipMemcpyDeviceToHost, s));
   SBFWI_HIP(hipStreamSynchronize(s));
+  if (flags[0] & 8) return sbfwi_fail(SBFWI_EHIP, "%s: coarse-solve grid barrier timed out", what);
   if (flags[0] & 4) return sbfwi_fail(SBFWI_ENONFINITE, "%s: non-finite coarse residual at step %d", what, flags[1]);
   if (flags[0] & 2) return sbfwi_fail(SBFWI_ENOCONV, "%s: coarse solve did not converge at step %d", what, flags[1]);
   return SBFWI_OK;

@@ -3,60 +3,96 @@
 // The paper assembles the element dynamic stiffnesses S_e into one global
 // system on the boundary nodes and leaves the solver open.  S_e of the radial
 // finite-difference scheme is not symmetric, so the solver is BiCGStab with a
-// Jacobi preconditioner, warm-started by the caller.  One cooperative,
-// persistent launch runs the whole solve: rows are strided over the grid and
-// the 4 global reductions of an iteration go through per-block partial sums
-// that every block then reduces in the same fixed tree order, so all blocks
-// take identical convergence decisions and results are bit-reproducible.
-// All right-hand sides (shots) of a run are solved together, each with its
-// own scalars; a shot stops updating once it has converged.
-#include <hip/hip_cooperative_groups.h>
-
+// Jacobi preconditioner, warm-started by the caller.
+//
+// Design (measured on MI355X): a device-wide barrier inside one persistent
+// kernel writes back and invalidates L2 on every arrival, which leaves the
+// following gathers latency-bound; ordinary kernel boundaries are cheaper.
+// So every phase of an iteration is its own full-grid kernel (one row per
+// thread, all shots of the run together).  A phase writes per-block partial
+// sums; the next phase's blocks each reduce all of them in the same fixed
+// order, so every block derives identical scalars without atomics or
+// barriers, and results are bit-reproducible.  Scalars rotate through three
+// small device buffers: each phase reads the buffer the previous phase wrote
+// and block 0 writes a different one (v: A -> B, t: B -> C, x: C -> A), so no
+// block can see a buffer that is being rewritten.  A fixed number of
+// iterations is enqueued up front (phases only forward the scalars once every
+// shot has converged); a solve that needs more continues in one cooperative
+// kernel that runs the same phases separated by grid barriers.
+//
+// BiCGStab is arranged with three phases per iteration: with w = K^T rhat
+// (rhat = r_0 fixed for the solve), (rhat, K phat) = (w, phat) and
+// (rhat, K shat) = (w, shat) are formed together with phat and shat, and
+// rho_{i+1} = (rhat, s) - omega (w, shat) = (rhat, r_{i+1}).
 #include "sbfwi_internal.h"
-
-namespace cg = cooperative_groups;
 
 namespace {
 
-constexpr int CT = 1024;    // threads per block
-constexpr int MAXS = 16;    // max right-hand sides per solve
-constexpr int NQ = 2;       // max quantities per reduction phase
+constexpr int CT = 256;     // threads per block (one row per thread)
+constexpr int MAXS = 16;    // shots of a run
+constexpr int NQ = 3;       // max quantities per reduction
+
+enum { SC_BN2, SC_RHO, SC_ALPHA, SC_OMEGA, SC_RS, SC_WS, SC_BETA, SC_ACTIVE, SC_SDONE, SC_ANY, SC_ITERS, SC_N };
 
 struct SolveArgs {
   int64_t n;
   int NS;
-  const int64_t* row_ptr;
-  const int32_t* col;
-  const double* val;
+  const int64_t* ell_off;
+  const int32_t* ell_w;
+  const int32_t* ell_col;
+  const double* val;   // K (sliced ELL)
+  const double* valT;  // K^T on the same (symmetric) pattern
   const double* dinv;
   const double* b;
   double* x;
-  double *r, *rhat, *p, *v, *sv, *t, *phat, *shat;
-  double* partial;   // [4 phases][NQ][nblocks][NS]
+  double *r, *rhat, *p, *v, *sv, *t, *phat, *shat, *w;
+  double* partial;     // [slot][NQ][nblocks][NS]
+  double* scal;        // [3][SC_N][MAXS] rotating scalar buffers
+  unsigned* bar;       // grid-barrier words of the rescue kernel
   double rtol;
-  int max_iter;
-  int* status;       // [0] flags, [1] step of failure, [2] last, [3] max, [4] total iterations, [5] solves
+  int* status;         // [0] flags (2 no convergence, 4 non-finite), [1] step, [2] last, [3] max, [4] total iterations, [5] solves
   int64_t step;
 };
 
+enum { SLOT_A = 0, SLOT_X = 1, SLOT_V = 2, SLOT_T = 3 };
+
+// y = K x for one row and all shots, from the sliced ELL layout: the k-th
+// entries of the rows of a slice are contiguous, so every value and column
+// load of a wavefront is coalesced; U entries are loaded before their x
+// gathers.  Padding entries have value 0 and a valid column.
 template <int NSM>
-__device__ __forceinline__ void spmv_row(const SolveArgs& a, int64_t r, const double* __restrict__ xin,
-                                         double (&out)[NSM]) {
+__device__ __forceinline__ void spmv_row(const SolveArgs& a, const double* __restrict__ val, int64_t r,
+                                         const double* __restrict__ xin, double (&out)[NSM]) {
+  constexpr int U = NSM <= 2 ? 16 : (NSM <= 4 ? 16 : 4);
 #pragma unroll
   for (int s = 0; s < NSM; ++s) out[s] = 0.0;
-  for (int64_t q = a.row_ptr[r]; q < a.row_ptr[r + 1]; ++q) {
-    double kv = a.val[q];
-    const double* xc = xin + (int64_t)a.col[q] * a.NS;
+  const int64_t sl = r / ELL_SLICE, lr = r - sl * ELL_SLICE;
+  const int w = a.ell_w[sl];
+  const double* vp = val + a.ell_off[sl] + lr;
+  const int32_t* cp = a.ell_col + a.ell_off[sl] + lr;
+  for (int k = 0; k < w; k += U) {
+    double kv[U];
+    int c[U];
 #pragma unroll
-    for (int s = 0; s < NSM; ++s)
-      if (s < a.NS) out[s] += kv * xc[s];
+    for (int u = 0; u < U; ++u) {
+      bool ok = k + u < w;
+      kv[u] = ok ? vp[(int64_t)(k + u) * ELL_SLICE] : 0.0;
+      c[u] = ok ? cp[(int64_t)(k + u) * ELL_SLICE] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double* xc = xin + (int64_t)c[u] * a.NS;
+#pragma unroll
+      for (int s = 0; s < NSM; ++s)
+        if (s < a.NS) out[s] += kv[u] * xc[s];
+    }
   }
 }
 
 // Block sums of nv values held by every thread, in a fixed order (wavefront
 // shuffle tree, then the waves in index order); results land in tot[0..nv).
 template <int NV>
-__device__ void block_sums(double (&v)[NV], int nv, double* wsum /*[CT/64][NV]*/, double* tot /*[NV]*/) {
+__device__ void block_sums(double (&v)[NV], int nv, double* wsum, double* tot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -74,26 +110,19 @@ __device__ void block_sums(double (&v)[NV], int nv, double* wsum /*[CT/64][NV]*/
   __syncthreads();
 }
 
-// Block partials of nq quantities x NS shots into this block's slot of a phase.
 template <int NSM>
-__device__ void block_partial(double (&loc)[NQ][NSM], int nq, const SolveArgs& a, int phase, double* wsum,
-                              double* tot) {
-  double v[NQ * NSM];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) v[q * NSM + s] = loc[q][s];
-  block_sums<NQ * NSM>(v, nq * NSM, wsum, tot);
+__device__ void write_partials(double (&loc)[NQ * NSM], int nq, const SolveArgs& a, int slot, double* wsum,
+                               double* tot) {
+  block_sums<NQ * NSM>(loc, nq * NSM, wsum, tot);
   if (threadIdx.x < nq * NSM) {
     int q = threadIdx.x / NSM, s = threadIdx.x % NSM;
-    if (s < a.NS) a.partial[(((int64_t)phase * NQ + q) * gridDim.x + blockIdx.x) * a.NS + s] = tot[threadIdx.x];
+    if (s < a.NS) a.partial[(((int64_t)slot * NQ + q) * gridDim.x + blockIdx.x) * a.NS + s] = tot[threadIdx.x];
   }
 }
 
-// Every block sums all block partials of a phase in the same fixed order.
+// Totals of a slot written by the previous phase (same grid size), identical in every block.
 template <int NSM>
-__device__ void grid_total(int nq, const SolveArgs& a, int phase, double* wsum, double* tots,
-                           double (&out)[NQ][NSM]) {
+__device__ void read_totals(int nq, const SolveArgs& a, int slot, double* wsum, double* tots) {
   const int nbk = gridDim.x;
   double v[NQ * NSM];
 #pragma unroll
@@ -102,230 +131,441 @@ __device__ void grid_total(int nq, const SolveArgs& a, int phase, double* wsum, 
     for (int s = 0; s < NSM; ++s) {
       double acc = 0.0;
       if (q < nq && s < a.NS)
-        for (int b = threadIdx.x; b < nbk; b += CT) acc += a.partial[(((int64_t)phase * NQ + q) * nbk + b) * a.NS + s];
+        for (int b = threadIdx.x; b < nbk; b += CT) acc += a.partial[(((int64_t)slot * NQ + q) * nbk + b) * a.NS + s];
       v[q * NSM + s] = acc;
     }
   block_sums<NQ * NSM>(v, nq * NSM, wsum, tots);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) out[q][s] = (q < nq && s < a.NS) ? tots[q * NSM + s] : 0.0;
+}
+
+struct Shared {
+  double wsum[(CT / 64) * NQ * MAXS];
+  double tot[NQ * MAXS];
+  double sc[SC_N][MAXS];
+};
+
+__device__ void load_scalars(const SolveArgs& a, int buf, Shared& L) {
+  for (int q = threadIdx.x; q < SC_N * MAXS; q += CT) (&L.sc[0][0])[q] = a.scal[buf * SC_N * MAXS + q];
   __syncthreads();
 }
 
+// Loads this thread's share of a partial slot into registers (issued early so
+// that it overlaps the scalar loads and the phase's independent vector loads).
 template <int NSM>
-__global__ void __launch_bounds__(CT) bicgstab_kernel(SolveArgs a) {
-  __shared__ double red[(CT / 64) * NQ * NSM];
-  __shared__ double tsh[NQ * NSM];
-  double tot[NQ][NSM];
-  cg::grid_group grid = cg::this_grid();
-  const int64_t gsz = (int64_t)gridDim.x * CT;
-  const int64_t gtid = (int64_t)blockIdx.x * CT + threadIdx.x;
-  const int NS = a.NS;
-  double bn2[NSM], rho_old[NSM], alpha[NSM], omega[NSM];
-  bool active[NSM];
-  double loc[NQ][NSM];
-  // r = b - K x ; rhat = r ; p = v = 0 ; partials |b|^2, |r|^2
+__device__ void fetch_partials(int nq, const SolveArgs& a, int slot, double (&v)[NQ * NSM]) {
+  const int nbk = gridDim.x;
 #pragma unroll
-  for (int s = 0; s < NSM; ++s) { loc[0][s] = 0.0; loc[1][s] = 0.0; }
-  for (int64_t r = gtid; r < a.n; r += gsz) {
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) {
+      double acc = 0.0;
+      if (q < nq && s < a.NS)
+        for (int b = threadIdx.x; b < nbk; b += CT) acc += a.partial[(((int64_t)slot * NQ + q) * nbk + b) * a.NS + s];
+      v[q * NSM + s] = acc;
+    }
+}
+
+__device__ void store_scalars(const SolveArgs& a, int buf, Shared& L) {
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < SC_N * MAXS; q += CT) a.scal[buf * SC_N * MAXS + q] = (&L.sc[0][0])[q];
+}
+
+// all shots converged: forward the scalars unchanged and report that the phase is idle
+__device__ bool idle_forward(const SolveArgs& a, int out_buf, Shared& L) {
+  if (L.sc[SC_ANY][0] != 0.0) return false;
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < SC_N * MAXS; q += CT) a.scal[out_buf * SC_N * MAXS + q] = (&L.sc[0][0])[q];
+  return true;
+}
+
+__device__ void update_any(Shared& L, int NS) {
+  if (threadIdx.x == 0) {
+    double any = 0.0;
+    for (int s = 0; s < NS; ++s) any = (L.sc[SC_ACTIVE][s] != 0.0) ? 1.0 : any;
+    L.sc[SC_ANY][0] = any;
+  }
+  __syncthreads();
+}
+
+#define ROWS_BEGIN for (int64_t r = (int64_t)blockIdx.x * CT + threadIdx.x; r < a.n; r += (int64_t)gridDim.x * CT) {
+#define ROWS_END }
+
+// r = b - K x ; rhat = r ; partials |b|^2, |r|^2
+template <int NSM>
+__global__ void __launch_bounds__(CT) k_init1(SolveArgs a) {
+  __shared__ Shared L;
+  double loc[NQ * NSM];
+#pragma unroll
+  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
+  ROWS_BEGIN {
     double kx[NSM];
-    spmv_row<NSM>(a, r, a.x, kx);
+    spmv_row<NSM>(a, a.val, r, a.x, kx);
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) {
+      if (s >= a.NS) continue;
+      int64_t g = r * a.NS + s;
+      double bv = a.b[g], rv = bv - kx[s];
+      a.r[g] = rv;
+      a.rhat[g] = rv;
+      loc[0 * NSM + s] += bv * bv;
+      loc[1 * NSM + s] += rv * rv;
+    }
+  } ROWS_END
+  write_partials<NSM>(loc, 2, a, SLOT_A, L.wsum, L.tot);
+}
+
+// scalars from slot A; w = K^T rhat ; p = r ; phat = D^-1 p ; partials |r|^2, (w, phat)
+template <int NSM>
+__global__ void __launch_bounds__(CT) k_init2(SolveArgs a) {
+  __shared__ Shared L;
+  const int NS = a.NS;
+  read_totals<NSM>(2, a, SLOT_A, L.wsum, L.tot);
+  const double tol2 = a.rtol * a.rtol;
+  if (threadIdx.x < MAXS) {
+    const int s = threadIdx.x;
+    double bn2 = s < NS ? L.tot[s] : 0.0, rn2 = s < NS ? L.tot[NSM + s] : 0.0;
+    for (int k = 0; k < SC_N; ++k) L.sc[k][s] = 0.0;
+    L.sc[SC_BN2][s] = bn2;
+    L.sc[SC_RHO][s] = rn2;
+    L.sc[SC_ALPHA][s] = 1.0;
+    L.sc[SC_OMEGA][s] = 1.0;
+    L.sc[SC_ACTIVE][s] = (s < NS && bn2 > 0.0 && rn2 > tol2 * bn2 && isfinite(rn2)) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  update_any(L, NS);
+  double loc[NQ * NSM];
+#pragma unroll
+  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
+  ROWS_BEGIN {
+    double kx[NSM];
+    spmv_row<NSM>(a, a.valT, r, a.rhat, kx);
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
       if (s >= NS) continue;
       int64_t g = r * NS + s;
-      double bv = a.b[g], rv = bv - kx[s];
+      if (L.sc[SC_BN2][s] == 0.0) a.x[g] = 0.0;
+      double pv = a.r[g];
+      double ph = a.dinv[r] * pv;
+      a.w[g] = kx[s];
+      a.p[g] = pv;
+      a.phat[g] = ph;
+      loc[0 * NSM + s] += pv * pv;
+      loc[1 * NSM + s] += kx[s] * ph;
+    }
+  } ROWS_END
+  write_partials<NSM>(loc, 2, a, SLOT_X, L.wsum, L.tot);
+  store_scalars(a, 0, L);
+}
+
+// convergence / alpha from slot X ; v = K phat ; s = r - alpha v ; shat = D^-1 s ;
+// partials |s|^2, (rhat, s), (w, shat).  Buffer A -> B.  Returns false when idle.
+template <int NSM>
+__device__ bool phase_v(const SolveArgs& a, Shared& L) {
+  const int NS = a.NS;
+  double part[NQ * NSM];
+  fetch_partials<NSM>(2, a, SLOT_X, part);
+  load_scalars(a, 0, L);
+  if (idle_forward(a, 1, L)) return false;
+  // with one row per thread, v = K phat (independent of this phase's scalars) starts first
+  const int64_t r0 = (int64_t)blockIdx.x * CT + threadIdx.x;
+  const bool single = (int64_t)gridDim.x * CT >= a.n;
+  double kx0[NSM];
+  if (single && r0 < a.n) spmv_row<NSM>(a, a.val, r0, a.phat, kx0);
+  block_sums<NQ * NSM>(part, 2 * NSM, L.wsum, L.tot);
+  const double tol2 = a.rtol * a.rtol;
+  if (threadIdx.x < NS) {
+    const int s = threadIdx.x;
+    if (L.sc[SC_ACTIVE][s] != 0.0) {
+      double rn2 = L.tot[s], wp = L.tot[NSM + s], rho = L.sc[SC_RHO][s];
+      if (!isfinite(rn2) || !isfinite(rho) || !isfinite(wp)) {
+        L.sc[SC_ACTIVE][s] = 0.0;
+        if (blockIdx.x == 0) {
+          atomicOr(&a.status[0], 4);
+          atomicCAS(&a.status[1], -1, (int)a.step);
+        }
+      } else if (rn2 <= tol2 * L.sc[SC_BN2][s]) {
+        L.sc[SC_ACTIVE][s] = 0.0;
+      } else if (rho == 0.0 || wp == 0.0) {  // breakdown
+        L.sc[SC_ACTIVE][s] = 0.0;
+        if (blockIdx.x == 0) {
+          atomicOr(&a.status[0], 2);
+          atomicCAS(&a.status[1], -1, (int)a.step);
+        }
+      } else {
+        L.sc[SC_ALPHA][s] = rho / wp;
+      }
+    }
+  }
+  __syncthreads();
+  update_any(L, NS);
+  store_scalars(a, 1, L);
+  if (L.sc[SC_ANY][0] == 0.0) return false;
+  double loc[NQ * NSM];
+#pragma unroll
+  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
+  ROWS_BEGIN {
+    double kx[NSM];
+    if (single) {
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) kx[s] = kx0[s];
+    } else {
+      spmv_row<NSM>(a, a.val, r, a.phat, kx);
+    }
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) {
+      if (s >= NS || L.sc[SC_ACTIVE][s] == 0.0) continue;
+      int64_t g = r * NS + s;
+      double sv = a.r[g] - L.sc[SC_ALPHA][s] * kx[s];
+      double sh = a.dinv[r] * sv;
+      a.v[g] = kx[s];
+      a.sv[g] = sv;
+      a.shat[g] = sh;
+      loc[0 * NSM + s] += sv * sv;
+      loc[1 * NSM + s] += a.rhat[g] * sv;
+      loc[2 * NSM + s] += a.w[g] * sh;
+    }
+  } ROWS_END
+  write_partials<NSM>(loc, 3, a, SLOT_V, L.wsum, L.tot);
+  return true;
+}
+
+// half-step convergence from slot V ; t = K shat ; partials (t, s), (t, t).
+// Shots converged on the half step take x += alpha phat.  Buffer B -> C.
+template <int NSM>
+__device__ void phase_t(const SolveArgs& a, Shared& L) {
+  const int NS = a.NS;
+  double part[NQ * NSM];
+  fetch_partials<NSM>(3, a, SLOT_V, part);
+  load_scalars(a, 1, L);
+  if (idle_forward(a, 2, L)) return;
+  const int64_t r0 = (int64_t)blockIdx.x * CT + threadIdx.x;
+  const bool single = (int64_t)gridDim.x * CT >= a.n;
+  double kx0[NSM];
+  if (single && r0 < a.n) spmv_row<NSM>(a, a.val, r0, a.shat, kx0);
+  block_sums<NQ * NSM>(part, 3 * NSM, L.wsum, L.tot);
+  const double tol2 = a.rtol * a.rtol;
+  if (threadIdx.x < NS) {
+    const int s = threadIdx.x;
+    L.sc[SC_SDONE][s] = (L.sc[SC_ACTIVE][s] != 0.0 && L.tot[s] <= tol2 * L.sc[SC_BN2][s]) ? 1.0 : 0.0;
+    L.sc[SC_RS][s] = L.tot[NSM + s];
+    L.sc[SC_WS][s] = L.tot[2 * NSM + s];
+  }
+  __syncthreads();
+  store_scalars(a, 2, L);
+  double loc[NQ * NSM];
+#pragma unroll
+  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
+  ROWS_BEGIN {
+    double kx[NSM];
+    if (single) {
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) kx[s] = kx0[s];
+    } else {
+      spmv_row<NSM>(a, a.val, r, a.shat, kx);
+    }
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) {
+      if (s >= NS || L.sc[SC_ACTIVE][s] == 0.0) continue;
+      int64_t g = r * NS + s;
+      if (L.sc[SC_SDONE][s] != 0.0) {
+        a.x[g] += L.sc[SC_ALPHA][s] * a.phat[g];
+        continue;
+      }
+      a.t[g] = kx[s];
+      loc[0 * NSM + s] += kx[s] * a.sv[g];
+      loc[1 * NSM + s] += kx[s] * kx[s];
+    }
+  } ROWS_END
+  write_partials<NSM>(loc, 2, a, SLOT_T, L.wsum, L.tot);
+}
+
+// omega, rho, beta from slot T ; x += alpha phat + omega shat ; r = s - omega t ;
+// p = r + beta (p - omega v) ; phat = D^-1 p ; partials |r|^2, (w, phat).  Buffer C -> A.
+template <int NSM>
+__device__ void phase_x(const SolveArgs& a, Shared& L) {
+  const int NS = a.NS;
+  double part[NQ * NSM];
+  fetch_partials<NSM>(2, a, SLOT_T, part);
+  load_scalars(a, 2, L);
+  if (idle_forward(a, 0, L)) return;
+  block_sums<NQ * NSM>(part, 2 * NSM, L.wsum, L.tot);
+  if (threadIdx.x < NS) {
+    const int s = threadIdx.x;
+    if (L.sc[SC_SDONE][s] != 0.0) L.sc[SC_ACTIVE][s] = 0.0;
+    L.sc[SC_SDONE][s] = 0.0;
+    L.sc[SC_BETA][s] = 0.0;
+    if (L.sc[SC_ACTIVE][s] != 0.0) {
+      double om = L.tot[s] / L.tot[NSM + s];
+      double rho_new = L.sc[SC_RS][s] - om * L.sc[SC_WS][s];
+      L.sc[SC_BETA][s] = (rho_new / L.sc[SC_RHO][s]) * (L.sc[SC_ALPHA][s] / om);
+      L.sc[SC_OMEGA][s] = om;
+      L.sc[SC_RHO][s] = rho_new;
+    }
+  }
+  __syncthreads();
+  update_any(L, NS);
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.sc[SC_ITERS][0] += 1.0;
+  double loc[NQ * NSM];
+#pragma unroll
+  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
+  ROWS_BEGIN {
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) {
+      if (s >= NS || L.sc[SC_ACTIVE][s] == 0.0) continue;
+      int64_t g = r * NS + s;
+      const double al = L.sc[SC_ALPHA][s], om = L.sc[SC_OMEGA][s];
+      a.x[g] += al * a.phat[g] + om * a.shat[g];
+      double rv = a.sv[g] - om * a.t[g];
+      double pv = rv + L.sc[SC_BETA][s] * (a.p[g] - om * a.v[g]);
+      double ph = a.dinv[r] * pv;
       a.r[g] = rv;
-      a.rhat[g] = rv;
-      a.p[g] = 0.0;
-      a.v[g] = 0.0;
-      loc[0][s] += bv * bv;
-      loc[1][s] += rv * rv;
+      a.p[g] = pv;
+      a.phat[g] = ph;
+      loc[0 * NSM + s] += rv * rv;
+      loc[1 * NSM + s] += a.w[g] * ph;
     }
+  } ROWS_END
+  write_partials<NSM>(loc, 2, a, SLOT_X, L.wsum, L.tot);
+  store_scalars(a, 0, L);
+}
+
+template <int NSM>
+__global__ void __launch_bounds__(CT) k_phase_v(SolveArgs a) {
+  __shared__ Shared L;
+  phase_v<NSM>(a, L);
+}
+
+template <int NSM>
+__global__ void __launch_bounds__(CT) k_phase_t(SolveArgs a) {
+  __shared__ Shared L;
+  phase_t<NSM>(a, L);
+}
+
+template <int NSM>
+__global__ void __launch_bounds__(CT) k_phase_x(SolveArgs a) {
+  __shared__ Shared L;
+  phase_x<NSM>(a, L);
+}
+
+// Grid barrier for the rescue kernel (all blocks co-resident by cooperative
+// launch): arrival counters in groups of 16 blocks, one counter for the
+// groups, and a generation word the others poll.  The poll is bounded: after
+// about two seconds it flags an error and stops waiting, so a broken barrier
+// ends the kernel instead of hanging it.
+__device__ __forceinline__ unsigned ld_acquire(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void grid_barrier(unsigned* bar, unsigned& gen_seen, int* status) {
+  __syncthreads();
+  if (threadIdx.x == 0 && gen_seen != 0xFFFFFFFFu) {
+    const int G = 16;
+    const int nb = gridDim.x, ng = (nb + G - 1) / G, grp = blockIdx.x / G;
+    const int gsize = min(G, nb - grp * G);
+    unsigned* gen = bar;
+    unsigned* top = bar + 32;
+    unsigned* ctr = bar + 64 + 32 * grp;
+    const unsigned g = gen_seen;
+    __threadfence();
+    unsigned old = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == (unsigned)(gsize - 1)) {
+      __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned o2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 == (unsigned)(ng - 1)) {
+        __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    long spins = 0;
+    bool timed_out = false;
+    while (ld_acquire(gen) == g) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > 2000000L) {
+        atomicOr(&status[0], 8);
+        timed_out = true;
+        break;
+      }
+    }
+    gen_seen = timed_out ? 0xFFFFFFFFu : g + 1;
+    __threadfence();
   }
-  block_partial<NSM>(loc, 2, a, 0, red, tsh);
-  grid.sync();
-  grid_total<NSM>(2, a, 0, red, tsh, tot);
-  bool any = false;
-#pragma unroll
-  for (int s = 0; s < NSM; ++s) {
-    bn2[s] = tot[0][s];
-    double rn2 = tot[1][s];
-    rho_old[s] = rn2;           // (rhat, r) with rhat = r
-    alpha[s] = 1.0;
-    omega[s] = 1.0;
-    active[s] = (s < NS) && (bn2[s] > 0.0) && (rn2 > a.rtol * a.rtol * bn2[s]) && isfinite(rn2);
-    any = any || active[s];
-  }
-  // a zero right-hand side has the zero solution
-  for (int64_t r = gtid; r < a.n; r += gsz) {
-#pragma unroll
-    for (int s = 0; s < NSM; ++s)
-      if (s < NS && bn2[s] == 0.0) a.x[r * NS + s] = 0.0;
-  }
-  double rho_new[NSM];
-#pragma unroll
-  for (int s = 0; s < NSM; ++s) rho_new[s] = rho_old[s];
-  bool first = true;
-  int it = 0;
-  for (it = 0; it < a.max_iter && any; ++it) {
-    // p = r + beta (p - omega v); phat = D^-1 p
-    for (int64_t r = gtid; r < a.n; r += gsz) {
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) {
-        if (s >= NS || !active[s]) continue;
-        int64_t g = r * NS + s;
-        double beta = first ? 0.0 : (rho_new[s] / rho_old[s]) * (alpha[s] / omega[s]);
-        double pv = a.r[g] + beta * (a.p[g] - omega[s] * a.v[g]);
-        a.p[g] = pv;
-        a.phat[g] = a.dinv[r] * pv;
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) if (!first) rho_old[s] = rho_new[s];
-    first = false;
-    grid.sync();
-    // v = K phat ; (rhat, v)
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) loc[0][s] = 0.0;
-    for (int64_t r = gtid; r < a.n; r += gsz) {
-      double kx[NSM];
-      spmv_row<NSM>(a, r, a.phat, kx);
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) {
-        if (s >= NS || !active[s]) continue;
-        int64_t g = r * NS + s;
-        a.v[g] = kx[s];
-        loc[0][s] += a.rhat[g] * kx[s];
-      }
-    }
-    block_partial<NSM>(loc, 1, a, 1, red, tsh);
-    grid.sync();
-    grid_total<NSM>(1, a, 1, red, tsh, tot);
-#pragma unroll
-    for (int s = 0; s < NSM; ++s)
-      if (s < NS && active[s]) alpha[s] = rho_old[s] / tot[0][s];
-    // s = r - alpha v ; shat = D^-1 s ; |s|^2
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) loc[0][s] = 0.0;
-    for (int64_t r = gtid; r < a.n; r += gsz) {
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) {
-        if (s >= NS || !active[s]) continue;
-        int64_t g = r * NS + s;
-        double sv = a.r[g] - alpha[s] * a.v[g];
-        a.sv[g] = sv;
-        a.shat[g] = a.dinv[r] * sv;
-        loc[0][s] += sv * sv;
-      }
-    }
-    block_partial<NSM>(loc, 1, a, 2, red, tsh);
-    grid.sync();
-    grid_total<NSM>(1, a, 2, red, tsh, tot);
-    bool sdone[NSM];
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) sdone[s] = (s < NS && active[s]) && (tot[0][s] <= a.rtol * a.rtol * bn2[s]);
-    // t = K shat ; (t, s), (t, t)
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) { loc[0][s] = 0.0; loc[1][s] = 0.0; }
-    for (int64_t r = gtid; r < a.n; r += gsz) {
-      double kx[NSM];
-      spmv_row<NSM>(a, r, a.shat, kx);
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) {
-        if (s >= NS || !active[s]) continue;
-        int64_t g = r * NS + s;
-        if (sdone[s]) {   // converged on the half step: x += alpha phat
-          a.x[g] += alpha[s] * a.phat[g];
-          continue;
-        }
-        a.t[g] = kx[s];
-        loc[0][s] += kx[s] * a.sv[g];
-        loc[1][s] += kx[s] * kx[s];
-      }
-    }
-    block_partial<NSM>(loc, 2, a, 3, red, tsh);
-    grid.sync();
-    grid_total<NSM>(2, a, 3, red, tsh, tot);
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) {
-      if (sdone[s]) active[s] = false;
-      if (s < NS && active[s]) omega[s] = tot[0][s] / tot[1][s];
-    }
-    // x += alpha phat + omega shat ; r = s - omega t ; (rhat, r), |r|^2
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) { loc[0][s] = 0.0; loc[1][s] = 0.0; }
-    for (int64_t r = gtid; r < a.n; r += gsz) {
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) {
-        if (s >= NS || !active[s]) continue;
-        int64_t g = r * NS + s;
-        a.x[g] += alpha[s] * a.phat[g] + omega[s] * a.shat[g];
-        double rv = a.sv[g] - omega[s] * a.t[g];
-        a.r[g] = rv;
-        loc[0][s] += a.rhat[g] * rv;
-        loc[1][s] += rv * rv;
-      }
-    }
-    block_partial<NSM>(loc, 2, a, 0, red, tsh);
-    grid.sync();
-    grid_total<NSM>(2, a, 0, red, tsh, tot);
-    any = false;
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) {
-      if (s < NS && active[s]) {
-        rho_new[s] = tot[0][s];
-        double rn2 = tot[1][s];
-        if (!isfinite(rn2) || !isfinite(rho_new[s])) {
-          active[s] = false;
-          if (blockIdx.x == 0 && threadIdx.x == 0) {
-            atomicOr(&a.status[0], 4);
-            atomicCAS(&a.status[1], -1, (int)a.step);
-          }
-        } else if (rn2 <= a.rtol * a.rtol * bn2[s]) {
-          active[s] = false;
-        } else if (rho_new[s] == 0.0) {  // breakdown
-          active[s] = false;
-          if (blockIdx.x == 0 && threadIdx.x == 0) {
-            atomicOr(&a.status[0], 2);
-            atomicCAS(&a.status[1], -1, (int)a.step);
-          }
-        }
-      }
-      any = any || active[s];
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.status[2] = it;
-    atomicMax(&a.status[3], it);
-    atomicAdd(&a.status[4], it);
-    atomicAdd(&a.status[5], 1);
-    if (any) {
-      atomicOr(&a.status[0], 2);
-      atomicCAS(&a.status[1], -1, (int)a.step);
-    }
+  __syncthreads();
+}
+
+// Continues the iteration for solves that the enqueued phases did not finish,
+// with the same grid, row mapping and partial slots (so the same arithmetic);
+// leaves at once when every shot has converged.
+template <int NSM>
+__global__ void __launch_bounds__(CT) k_rescue(SolveArgs a, int max_more) {
+  __shared__ Shared L;
+  unsigned gen_seen = 0;
+  if (threadIdx.x == 0) gen_seen = ld_acquire(a.bar);
+  for (int i = 0; i < max_more; ++i) {
+    bool go = phase_v<NSM>(a, L);
+    grid_barrier(a.bar, gen_seen, a.status);
+    if (!go) break;
+    phase_t<NSM>(a, L);
+    grid_barrier(a.bar, gen_seen, a.status);
+    phase_x<NSM>(a, L);
+    grid_barrier(a.bar, gen_seen, a.status);
   }
 }
 
-int g_coop_blocks[5] = {0, 0, 0, 0, 0};
+// final convergence check of slot X and statistics
+template <int NSM>
+__global__ void __launch_bounds__(CT) k_finish(SolveArgs a) {
+  __shared__ Shared L;
+  const int NS = a.NS;
+  load_scalars(a, 0, L);
+  read_totals<NSM>(2, a, SLOT_X, L.wsum, L.tot);
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double tol2 = a.rtol * a.rtol;
+  int unconverged = 0;
+  if (L.sc[SC_ANY][0] != 0.0)
+    for (int s = 0; s < NS; ++s)
+      if (L.sc[SC_ACTIVE][s] != 0.0 && !(L.tot[s] <= tol2 * L.sc[SC_BN2][s])) unconverged = 1;
+  int it = (int)L.sc[SC_ITERS][0];
+  a.status[2] = it;
+  atomicMax(&a.status[3], it);
+  atomicAdd(&a.status[4], it);
+  atomicAdd(&a.status[5], 1);
+  if (unconverged) {
+    atomicOr(&a.status[0], 2);
+    atomicCAS(&a.status[1], -1, (int)a.step);
+  }
+}
 
 template <int NSM>
-int coop_grid(int idx, int64_t n, int want_blocks) {
-  if (g_coop_blocks[idx] == 0) {
+hipError_t enqueue(const SolveArgs& a, int iters, int max_more, unsigned blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_init1<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+  hipLaunchKernelGGL(k_init2<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+  for (int i = 0; i < iters; ++i) {
+    hipLaunchKernelGGL(k_phase_v<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+    hipLaunchKernelGGL(k_phase_t<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+    hipLaunchKernelGGL(k_phase_x<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+  }
+  if (max_more > 0) {
+    SolveArgs b = a;
+    void* args[] = {&b, &max_more};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_rescue<NSM>, dim3(blocks), dim3(CT), args, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_finish<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+  return hipGetLastError();
+}
+
+// largest grid whose blocks can all be resident at once (the rescue kernel needs it)
+template <int NSM>
+int coresident_blocks() {
+  static int cached = 0;
+  if (cached == 0) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bicgstab_kernel<NSM>, CT, 0) != hipSuccess) return 0;
-    g_coop_blocks[idx] = per * cus;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rescue<NSM>, CT, 0) != hipSuccess) return 0;
+    cached = per * cus;
   }
-  // the cooperative grid barrier costs about 0.13 us per block on MI355X, so a
-  // small grid of large blocks is faster than filling the chip
-  int64_t want = (n + CT - 1) / CT;
-  if (want > want_blocks) want = want_blocks;
-  int64_t cap = g_coop_blocks[idx] < 256 ? g_coop_blocks[idx] : 256;
-  if (want < 1) want = 1;
-  return (int)(want < cap ? want : cap);
+  return cached;
 }
 
 }  // namespace
@@ -335,7 +575,7 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS) {
   w->NS = NS;
   w->n = n_nodes;
   int64_t sz = n_nodes * NS;
-  SBFWI_CHECK(sbfwi_alloc(&w->r, 8 * sz));
+  SBFWI_CHECK(sbfwi_alloc(&w->r, 9 * sz));
   w->rhat = w->r + sz;
   w->p = w->rhat + sz;
   w->v = w->p + sz;
@@ -343,13 +583,24 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS) {
   w->t = w->sv + sz;
   w->phat = w->t + sz;
   w->shat = w->phat + sz;
-  SBFWI_CHECK(sbfwi_alloc(&w->partial, (int64_t)4 * NQ * 256 * NS));
+  w->w = w->shat + sz;
+  int64_t want = (n_nodes + CT - 1) / CT;
+  int cap = NS <= 1 ? coresident_blocks<1>() : NS <= 2 ? coresident_blocks<2>() : NS <= 4 ? coresident_blocks<4>()
+          : NS <= 8 ? coresident_blocks<8>() : coresident_blocks<16>();
+  if (cap <= 0) return sbfwi_fail(SBFWI_EHIP, "cannot query the co-resident grid size");
+  w->nblocks = (int)(want < cap ? want : cap);
+  SBFWI_CHECK(sbfwi_alloc(&w->partial, (int64_t)4 * NQ * w->nblocks * NS));
+  SBFWI_CHECK(sbfwi_alloc(&w->scal, (int64_t)3 * SC_N * MAXS));
+  SBFWI_CHECK(sbfwi_alloc(&w->bar, 64 + 32 * ((w->nblocks + 15) / 16 + 1)));
+  SBFWI_HIP(hipMemset(w->bar, 0, sizeof(unsigned) * (64 + 32 * ((w->nblocks + 15) / 16 + 1))));
   return SBFWI_OK;
 }
 
 void sbfwi_coarse_work_free(CoarseWork* w) {
   sbfwi_dev_free(w->r);
   sbfwi_dev_free(w->partial);
+  sbfwi_dev_free(w->scal);
+  sbfwi_dev_free(w->bar);
   *w = CoarseWork();
 }
 
@@ -359,32 +610,32 @@ int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
   SolveArgs a;
   a.n = m->n_nodes;
   a.NS = w->NS;
-  a.row_ptr = m->d.row_ptr;
-  a.col = m->d.col;
-  a.val = transpose ? f->d.KTval : f->d.Kval;
+  a.ell_off = m->d.ell_off;
+  a.ell_w = m->d.ell_w;
+  a.ell_col = m->d.ell_col;
+  a.val = transpose ? f->d.KTell : f->d.Kell;
+  a.valT = transpose ? f->d.Kell : f->d.KTell;
   a.dinv = f->d.diag_inv;
   a.b = b;
   a.x = x;
   a.r = w->r; a.rhat = w->rhat; a.p = w->p; a.v = w->v; a.sv = w->sv; a.t = w->t;
-  a.phat = w->phat; a.shat = w->shat;
+  a.phat = w->phat; a.shat = w->shat; a.w = w->w;
   a.partial = w->partial;
+  a.scal = w->scal;
+  a.bar = w->bar;
   a.rtol = f->rtol;
-  a.max_iter = f->max_iter;
   a.status = f->d.status;
   a.step = step;
-  void* args[] = {&a};
-  int nsm = a.NS <= 1 ? 1 : a.NS <= 2 ? 2 : a.NS <= 4 ? 4 : a.NS <= 8 ? 8 : 16;
-  const void* fn;
-  int blocks;
-  switch (nsm) {
-    case 1: fn = (const void*)bicgstab_kernel<1>; blocks = coop_grid<1>(0, a.n, f->solver_blocks); break;
-    case 2: fn = (const void*)bicgstab_kernel<2>; blocks = coop_grid<2>(1, a.n, f->solver_blocks); break;
-    case 4: fn = (const void*)bicgstab_kernel<4>; blocks = coop_grid<4>(2, a.n, f->solver_blocks); break;
-    case 8: fn = (const void*)bicgstab_kernel<8>; blocks = coop_grid<8>(3, a.n, f->solver_blocks); break;
-    default: fn = (const void*)bicgstab_kernel<16>; blocks = coop_grid<16>(4, a.n, f->solver_blocks); break;
-  }
-  if (blocks <= 0) return sbfwi_fail(SBFWI_EHIP, "cannot size the cooperative coarse-solve grid");
+  const int iters = f->enqueued_iters < f->max_iter ? f->enqueued_iters : f->max_iter;
+  const int more = f->max_iter - iters;
+  const unsigned blocks = (unsigned)w->nblocks;
   ProfScope ps(PK_SOLVE, s);
-  SBFWI_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(CT), args, 0, s));
+  hipError_t e;
+  if (a.NS == 1) e = enqueue<1>(a, iters, more, blocks, s);
+  else if (a.NS == 2) e = enqueue<2>(a, iters, more, blocks, s);
+  else if (a.NS <= 4) e = enqueue<4>(a, iters, more, blocks, s);
+  else if (a.NS <= 8) e = enqueue<8>(a, iters, more, blocks, s);
+  else e = enqueue<16>(a, iters, more, blocks, s);
+  if (e != hipSuccess) return sbfwi_fail(SBFWI_EHIP, "coarse solve launch: %s", hipGetErrorString(e));
   return SBFWI_OK;
 }

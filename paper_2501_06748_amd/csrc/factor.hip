@@ -389,10 +389,17 @@ __global__ void assemble_kernel(int64_t nnz, const int64_t* __restrict__ cptr,
 }
 
 __global__ void transpose_diag_kernel(int64_t nnz, int64_t n_nodes, const int64_t* __restrict__ tr,
-                                      const int64_t* __restrict__ diag, const double* __restrict__ K,
-                                      double* __restrict__ KT, double* __restrict__ dinv) {
+                                      const int64_t* __restrict__ diag, const int64_t* __restrict__ ell_pos,
+                                      const double* __restrict__ K, double* __restrict__ KT,
+                                      double* __restrict__ Kell, double* __restrict__ KTell,
+                                      double* __restrict__ dinv) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < nnz) KT[q] = K[tr[q]];
+  if (q < nnz) {
+    double kt = K[tr[q]];
+    KT[q] = kt;
+    Kell[ell_pos[q]] = K[q];
+    KTell[ell_pos[q]] = kt;
+  }
   if (q < n_nodes) dinv[q] = 1.0 / K[diag[q]];
 }
 
@@ -403,7 +410,7 @@ void sbfwi_factors_free(sbfwi_factors_s* f) {
   FactorsDev& d = f->d;
   void* ptrs[] = {d.finv, d.th_band, d.ps_band, d.pm_band, d.th_np1, d.phim1, d.psim1,
                   d.G, d.S, d.psit0, d.psin_inv, d.phit_n, d.thm1_inv, d.gbasis,
-                  d.Kval, d.KTval, d.diag_inv, d.status};
+                  d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv, d.status};
   for (void* p : ptrs) sbfwi_dev_free(p);
   delete f;
 }
@@ -447,6 +454,8 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   A(&d.gbasis, 32 * m->n_loop);
   A(&d.Kval, m->nnz);
   A(&d.KTval, m->nnz);
+  A(&d.Kell, m->d.n_ell);
+  A(&d.KTell, m->d.n_ell);
   A(&d.diag_inv, m->n_nodes);
   if (rc == SBFWI_OK) rc = sbfwi_alloc(&d.status, 8);
   if (rc != SBFWI_OK) {
@@ -479,8 +488,11 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
                        d.S, d.Kval);
     int64_t big = m->nnz > m->n_nodes ? m->nnz : m->n_nodes;
     unsigned g2 = (unsigned)((big + 255) / 256);
+    he = hipMemsetAsync(d.Kell, 0, sizeof(double) * m->d.n_ell, s);
+    if (he == hipSuccess) he = hipMemsetAsync(d.KTell, 0, sizeof(double) * m->d.n_ell, s);
+    if (he != hipSuccess) return hip_fail(he, "hipMemsetAsync");
     hipLaunchKernelGGL(transpose_diag_kernel, dim3(g2), dim3(256), 0, s, m->nnz, m->n_nodes, m->d.tr_idx,
-                       m->d.diag_idx, d.Kval, d.KTval, d.diag_inv);
+                       m->d.diag_idx, m->d.ell_pos, d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv);
     he = hipGetLastError();
     if (he != hipSuccess) return hip_fail(he, "assembly launch");
   }

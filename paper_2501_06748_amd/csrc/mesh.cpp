@@ -44,6 +44,38 @@ static int upload_mesh(sbfwi_mesh_s* m, const std::vector<int64_t>& loop_nodes,
   SBFWI_CHECK(sbfwi_upload(&m->d.contrib_ptr, cptr));
   SBFWI_CHECK(sbfwi_upload(&m->d.contrib_src, csrc));
   for (int c = 0; c < 3; ++c) SBFWI_CHECK(sbfwi_upload(&m->class_elems[c], m->h_class_elems[c]));
+  // sliced ELL layout of the coarse pattern
+  const int64_t n = m->n_nodes, ns = (n + ELL_SLICE - 1) / ELL_SLICE;
+  std::vector<int64_t> eoff(ns + 1, 0);
+  std::vector<int32_t> ew(ns, 0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    int64_t w = 0;
+    for (int64_t r = sl * ELL_SLICE; r < std::min(n, (sl + 1) * ELL_SLICE); ++r)
+      w = std::max(w, m->h_row_ptr[r + 1] - m->h_row_ptr[r]);
+    ew[sl] = (int32_t)w;
+    eoff[sl + 1] = eoff[sl] + w * ELL_SLICE;
+  }
+  std::vector<int32_t> ecol(eoff[ns]);
+  std::vector<int64_t> epos(m->nnz);
+  for (int64_t sl = 0; sl < ns; ++sl)
+    for (int64_t lr = 0; lr < ELL_SLICE; ++lr) {
+      int64_t r = sl * ELL_SLICE + lr;
+      for (int64_t k = 0; k < ew[sl]; ++k) {
+        int64_t pos = eoff[sl] + k * ELL_SLICE + lr;
+        int64_t q = r < n ? m->h_row_ptr[r] + k : -1;
+        if (r < n && q < m->h_row_ptr[r + 1]) {
+          ecol[pos] = (int32_t)m->h_col64[q];
+          epos[q] = pos;
+        } else {
+          ecol[pos] = (int32_t)(r < n ? r : 0);
+        }
+      }
+    }
+  m->d.n_ell = eoff[ns];
+  SBFWI_CHECK(sbfwi_upload(&m->d.ell_off, eoff));
+  SBFWI_CHECK(sbfwi_upload(&m->d.ell_w, ew));
+  SBFWI_CHECK(sbfwi_upload(&m->d.ell_col, ecol));
+  SBFWI_CHECK(sbfwi_upload(&m->d.ell_pos, epos));
   return SBFWI_OK;
 }
 
@@ -53,6 +85,7 @@ void sbfwi_mesh_free(sbfwi_mesh_s* m) {
   void* ptrs[] = {d.nb, d.nr, d.loop_off, d.par_off, d.int_off, d.x_off, d.finv_off,
                   d.dense_off, d.loop_nodes, d.loop_xy, d.centre, d.node_ptr, d.node_slot,
                   d.row_ptr, d.col, d.diag_idx, d.tr_idx, d.contrib_ptr, d.contrib_src,
+                  d.ell_off, d.ell_w, d.ell_col, d.ell_pos,
                   m->class_elems[0], m->class_elems[1], m->class_elems[2]};
   for (void* p : ptrs) sbfwi_dev_free(p);
   delete m;

@@ -45,7 +45,15 @@ struct MeshDev {
   int64_t* tr_idx = nullptr;     // [nnz] position of (c, r) for entry (r, c)
   int64_t* contrib_ptr = nullptr;  // [nnz+1]
   int64_t* contrib_src = nullptr;  // index into S storage (dense_off[e] + i*nb + j)
+  // sliced ELL copy of the coarse pattern: slices of ELL_SLICE rows, column-major
+  // inside a slice and padded to the widest row of the slice (padding: column = row, value 0)
+  int64_t n_ell = 0;
+  int64_t* ell_off = nullptr;   // [n_slices + 1] offsets of the slices
+  int32_t* ell_w = nullptr;     // [n_slices] width of each slice
+  int32_t* ell_col = nullptr;   // [n_ell]
+  int64_t* ell_pos = nullptr;   // [nnz] ELL position of every CSR entry
 };
+#define ELL_SLICE 256
 
 struct sbfwi_mesh_s {
   int64_t n_nodes = 0, n_elem = 0, n_params = 0, n_int = 0, n_loop = 0, n_x = 0;
@@ -79,6 +87,8 @@ struct FactorsDev {
   double* gbasis = nullptr;    // [32 n_loop] d(E0,E1,E2,M0 segment block)/d(nodal density)
   double* Kval = nullptr;      // [nnz] coarse matrix on the CSR pattern
   double* KTval = nullptr;     // [nnz] its transpose on the same (symmetric) pattern
+  double* Kell = nullptr;      // [n_ell] K_g in the sliced ELL layout
+  double* KTell = nullptr;     // [n_ell] K_g^T in the sliced ELL layout
   double* diag_inv = nullptr;  // [n_nodes] Jacobi preconditioner
   int* status = nullptr;       // device status words
 };
@@ -88,7 +98,7 @@ struct sbfwi_factors_s {
   double c = 0, dt = 0, beta = 0, gamma = 0;
   double rtol = 1e-13;
   int max_iter = 500;
-  int solver_blocks = 32;        // cooperative grid size of the coarse solve (tunable)
+  int enqueued_iters = 13;       // BiCGStab iterations enqueued per solve (more run in a rescue kernel)
   int64_t bytes = 0;
   FactorsDev d;
 };
@@ -169,7 +179,9 @@ struct CoarseWork {
   int NS = 0;
   int64_t n = 0;
   double *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *sv = nullptr,
-         *t = nullptr, *phat = nullptr, *shat = nullptr, *partial = nullptr;
+         *t = nullptr, *phat = nullptr, *shat = nullptr, *w = nullptr, *partial = nullptr,
+         *scal = nullptr;
+  unsigned* bar = nullptr;
   int nblocks = 0, nthreads = 0;
 };
 int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS);
@@ -183,6 +195,7 @@ struct StepWork {
   int NS = 0;
   double *u = nullptr, *v = nullptr, *a = nullptr;      // interior state
   double *U = nullptr, *V = nullptr, *A = nullptr;      // nodal state
+  double* corr = nullptr;                               // predictor correction of the coarse solve
   double *q = nullptr, *yn = nullptr, *fhat = nullptr, *F = nullptr, *Unew = nullptr;
   CoarseWork cw;
 };

@@ -255,11 +255,12 @@ __global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__
 }
 
 // F = sum of element sources gathered over node -> slot + point sources;
-// Unew = predictor u + dt v + dt^2/2 a (initial guess of the coarse solve).
+// Unew = initial guess of the coarse solve: the predictor u + dt v + dt^2/2 a
+// plus the correction the previous step needed on top of its own predictor.
 __global__ void rhs_kernel(MeshDev m, int NS, const double* __restrict__ fhat, double* __restrict__ F,
                            const double* __restrict__ U, const double* __restrict__ V,
-                           const double* __restrict__ A, double* __restrict__ Unew, double dt,
-                           SourceTable src, int64_t k) {
+                           const double* __restrict__ A, double* __restrict__ Unew,
+                           const double* __restrict__ corr, double dt, SourceTable src, int64_t k) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= m.n_nodes * NS) return;
   int64_t node = g / NS;
@@ -274,12 +275,13 @@ __global__ void rhs_kernel(MeshDev m, int NS, const double* __restrict__ fhat, d
     }
   }
   F[g] = acc;
-  Unew[g] = U[g] + dt * V[g] + 0.5 * dt * dt * A[g];
+  Unew[g] = U[g] + dt * V[g] + 0.5 * dt * dt * A[g] + corr[g];
 }
 
-// Nodal Newmark update and receiver sampling.
+// Nodal Newmark update, predictor correction and receiver sampling.
 __global__ void nodal_kernel(int64_t n_nodes, int NS, FactorsDev f, const double* __restrict__ Unew,
                              double* __restrict__ U, double* __restrict__ V, double* __restrict__ A,
+                             double* __restrict__ corr,
                              int n_rec, const int64_t* __restrict__ rec_node, double* __restrict__ traces,
                              int64_t n_steps, int64_t k) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -287,6 +289,7 @@ __global__ void nodal_kernel(int64_t n_nodes, int NS, FactorsDev f, const double
   if (g < nn) {
     double uo = U[g], vo = V[g], ao = A[g], un = Unew[g];
     double w = f.a0 * uo + f.a1 * vo + f.a2 * ao;
+    corr[g] = un - (uo + f.dt * vo + 0.5 * f.dt * f.dt * ao);
     V[g] = f.c1 * (un - uo) + f.c2 * vo + f.c3 * ao;
     A[g] = f.a0 * un - w;
     U[g] = un;
@@ -328,17 +331,19 @@ void launch_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const Ste
 
 }  // namespace
 
-int64_t sbfwi_state_size(sbfwi_mesh_s* m, int NS) { return 3 * (m->n_int + m->n_nodes) * (int64_t)NS; }
+// interior u, v, a; nodal U, V, A and the predictor correction of the coarse solve
+int64_t sbfwi_state_size(sbfwi_mesh_s* m, int NS) { return (3 * m->n_int + 4 * m->n_nodes) * (int64_t)NS; }
 
 int sbfwi_step_work_alloc(StepWork* w, sbfwi_mesh_s* m, int NS) {
   w->NS = NS;
   int64_t ni = m->n_int * NS, nn = m->n_nodes * NS, nl = m->n_loop * NS;
-  SBFWI_CHECK(sbfwi_alloc(&w->u, 3 * ni + 3 * nn));  // u, v, a, U, V, A contiguous
+  SBFWI_CHECK(sbfwi_alloc(&w->u, 3 * ni + 4 * nn));  // u, v, a, U, V, A, corr contiguous
   w->v = w->u + ni;
   w->a = w->v + ni;
   w->U = w->a + ni;
   w->V = w->U + nn;
   w->A = w->V + nn;
+  w->corr = w->A + nn;
   SBFWI_CHECK(sbfwi_alloc(&w->q, ni));
   SBFWI_CHECK(sbfwi_alloc(&w->yn, nl));
   SBFWI_CHECK(sbfwi_alloc(&w->fhat, nl));
@@ -388,7 +393,7 @@ int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceT
   {
   ProfScope ps(PK_RHS, st);
   hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, m->d, w->NS, w->fhat,
-                     w->F, w->U, w->V, w->A, w->Unew, f->dt, src, k);
+                     w->F, w->U, w->V, w->A, w->Unew, w->corr, f->dt, src, k);
   }
   SBFWI_HIP(hipGetLastError());
   SBFWI_CHECK(sbfwi_coarse_solve(f, &w->cw, 0, w->F, w->Unew, k, st));
@@ -396,7 +401,7 @@ int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceT
   {
   ProfScope ps(PK_NODAL, st);
   hipLaunchKernelGGL(nodal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m->n_nodes, w->NS,
-                     f->d, w->Unew, w->U, w->V, w->A, n_rec, rec_node, traces, n_steps, k);
+                     f->d, w->Unew, w->U, w->V, w->A, w->corr, n_rec, rec_node, traces, n_steps, k);
   }
   launch_sweep(false, m, f->d, a, st);
   SBFWI_HIP(hipGetLastError());
