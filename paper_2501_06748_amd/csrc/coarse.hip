@@ -8,8 +8,11 @@
 // Design (measured on MI355X): a device-wide barrier inside one persistent
 // kernel writes back and invalidates L2 on every arrival, which leaves the
 // following gathers latency-bound; ordinary kernel boundaries are cheaper.
-// So every phase of an iteration is its own full-grid kernel (one row per
-// thread, all shots of the run together).  A phase writes per-block partial
+// So every phase of an iteration is its own full-grid kernel covering all
+// shots of the run together.  A block takes one slice of ELL_SLICE rows at a
+// time with ELL_LPR lanes per row: the lanes of a row split its entries for
+// the product (so a row costs one round of loads, not a chain of them) and
+// then split its shots for the vector updates.  A phase writes per-block partial
 // sums; the next phase's blocks each reduce all of them in the same fixed
 // order, so every block derives identical scalars without atomics or
 // barriers, and results are bit-reproducible.  Scalars rotate through three
@@ -28,7 +31,9 @@
 
 namespace {
 
-constexpr int CT = 256;     // threads per block (one row per thread)
+constexpr int LPR = ELL_LPR;          // lanes per row
+constexpr int CT = ELL_SLICE * LPR;   // threads per block: one slice of rows at a time
+static_assert(CT == 1024 && (LPR & (LPR - 1)) == 0, "block shape");
 constexpr int MAXS = 16;    // shots of a run
 constexpr int NQ = 3;       // max quantities per reduction
 
@@ -36,6 +41,7 @@ enum { SC_BN2, SC_RHO, SC_ALPHA, SC_OMEGA, SC_RS, SC_WS, SC_BETA, SC_ACTIVE, SC_
 
 struct SolveArgs {
   int64_t n;
+  int64_t n_slices;
   int NS;
   const int64_t* ell_off;
   const int32_t* ell_w;
@@ -46,7 +52,7 @@ struct SolveArgs {
   const double* b;
   double* x;
   double *r, *rhat, *p, *v, *sv, *t, *phat, *shat, *w;
-  double* partial;     // [slot][NQ][nblocks][NS]
+  double* partial;     // [slot][nblocks][NQ][NS]
   double* scal;        // [3][SC_N][MAXS] rotating scalar buffers
   unsigned* bar;       // grid-barrier words of the rescue kernel
   double rtol;
@@ -56,28 +62,31 @@ struct SolveArgs {
 
 enum { SLOT_A = 0, SLOT_X = 1, SLOT_V = 2, SLOT_T = 3 };
 
-// y = K x for one row and all shots, from the sliced ELL layout: the k-th
-// entries of the rows of a slice are contiguous, so every value and column
-// load of a wavefront is coalesced; U entries are loaded before their x
-// gathers.  Padding entries have value 0 and a valid column.
+// y = K x for the row of this thread's lane group and all shots, from the
+// sliced ELL layout: chunk c of a slice holds entries k = c*LPR .. c*LPR+LPR-1
+// of every row, lane-contiguous, so thread t of the block loads word c * CT + t
+// (coalesced) and the LPR lanes of a row hold LPR different entries.  Chunks
+// are loaded U at a time before their x gathers; a butterfly over the row's
+// lanes then leaves the full sums in every lane (the same bits in each, as
+// IEEE addition is commutative).  Padding entries have value 0 and a valid
+// column.  Must be called by all threads of the block (uniform control flow).
 template <int NSM>
-__device__ __forceinline__ void spmv_row(const SolveArgs& a, const double* __restrict__ val, int64_t r,
-                                         const double* __restrict__ xin, double (&out)[NSM]) {
-  constexpr int U = NSM <= 2 ? 16 : (NSM <= 4 ? 16 : 4);
+__device__ __forceinline__ void spmv_slice(const SolveArgs& a, const double* __restrict__ val, int64_t sl,
+                                           const double* __restrict__ xin, double (&out)[NSM]) {
+  constexpr int U = NSM <= 4 ? 16 : (NSM <= 8 ? 8 : 4);
 #pragma unroll
   for (int s = 0; s < NSM; ++s) out[s] = 0.0;
-  const int64_t sl = r / ELL_SLICE, lr = r - sl * ELL_SLICE;
-  const int w = a.ell_w[sl];
-  const double* vp = val + a.ell_off[sl] + lr;
-  const int32_t* cp = a.ell_col + a.ell_off[sl] + lr;
-  for (int k = 0; k < w; k += U) {
+  const int nc = a.ell_w[sl];
+  const double* vp = val + a.ell_off[sl] + threadIdx.x;
+  const int32_t* cp = a.ell_col + a.ell_off[sl] + threadIdx.x;
+  for (int c0 = 0; c0 < nc; c0 += U) {
     double kv[U];
     int c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      bool ok = k + u < w;
-      kv[u] = ok ? vp[(int64_t)(k + u) * ELL_SLICE] : 0.0;
-      c[u] = ok ? cp[(int64_t)(k + u) * ELL_SLICE] : 0;
+      bool ok = c0 + u < nc;
+      kv[u] = ok ? vp[(int64_t)(c0 + u) * CT] : 0.0;
+      c[u] = ok ? cp[(int64_t)(c0 + u) * CT] : 0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -87,81 +96,94 @@ __device__ __forceinline__ void spmv_row(const SolveArgs& a, const double* __res
         if (s < a.NS) out[s] += kv[u] * xc[s];
     }
   }
+#pragma unroll
+  for (int m = 1; m < LPR; m <<= 1)
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) out[s] += __shfl_xor(out[s], m, 64);
 }
 
-// Block sums of nv values held by every thread, in a fixed order (wavefront
-// shuffle tree, then the waves in index order); results land in tot[0..nv).
-template <int NV>
-__device__ void block_sums(double (&v)[NV], int nv, double* wsum, double* tot) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    if (q >= nv) break;
-    double x = v[q];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) wsum[wave * NV + q] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < nv) {
-    double t = 0.0;
-    for (int w = 0; w < CT / 64; ++w) t += wsum[w * NV + threadIdx.x];
-    tot[threadIdx.x] = t;
-  }
-  __syncthreads();
-}
-
-template <int NSM>
-__device__ void write_partials(double (&loc)[NQ * NSM], int nq, const SolveArgs& a, int slot, double* wsum,
-                               double* tot) {
-  block_sums<NQ * NSM>(loc, nq * NSM, wsum, tot);
-  if (threadIdx.x < nq * NSM) {
-    int q = threadIdx.x / NSM, s = threadIdx.x % NSM;
-    if (s < a.NS) a.partial[(((int64_t)slot * NQ + q) * gridDim.x + blockIdx.x) * a.NS + s] = tot[threadIdx.x];
-  }
-}
-
-// Totals of a slot written by the previous phase (same grid size), identical in every block.
-template <int NSM>
-__device__ void read_totals(int nq, const SolveArgs& a, int slot, double* wsum, double* tots) {
-  const int nbk = gridDim.x;
-  double v[NQ * NSM];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) {
-      double acc = 0.0;
-      if (q < nq && s < a.NS)
-        for (int b = threadIdx.x; b < nbk; b += CT) acc += a.partial[(((int64_t)slot * NQ + q) * nbk + b) * a.NS + s];
-      v[q * NSM + s] = acc;
-    }
-  block_sums<NQ * NSM>(v, nq * NSM, wsum, tots);
-}
+constexpr int PG = 32;      // groups of the partial-slot reduction
 
 struct Shared {
   double wsum[(CT / 64) * NQ * MAXS];
-  double tot[NQ * MAXS];
+  double red[PG * NQ * MAXS];
+  double tot[NQ * MAXS];     // tot[q * MAXS + s]
   double sc[SC_N][MAXS];
 };
+
+// Partial sums owned by a lane: quantity q of shot s lives in loc[q][s / LPR]
+// of lane s % LPR (each lane of a row handles the shots s = j, j + LPR, ...).
+template <int NSM>
+struct Loc {
+  static constexpr int OWNS = (NSM + LPR - 1) / LPR;
+  double v[NQ][OWNS];
+  __device__ Loc() {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int i = 0; i < OWNS; ++i) v[q][i] = 0.0;
+  }
+  __device__ double& operator()(int q, int s) { return v[q][s / LPR]; }
+};
+
+// Block totals of lane-owned partial sums, stored as this block's entry of a
+// partial slot [slot][block][NQ * NS].  Fixed order: xor butterfly over the
+// lanes of a wavefront that own the same shots, then the waves in index order.
+template <int NSM>
+__device__ void write_partials(Loc<NSM>& loc, int nq, const SolveArgs& a, int slot, Shared& L) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, NS = a.NS;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int i = 0; i < Loc<NSM>::OWNS; ++i) {
+      double x = loc.v[q][i];
+#pragma unroll
+      for (int m = LPR; m < 64; m <<= 1) x += __shfl_xor(x, m, 64);
+      const int s = lane + i * LPR;
+      if (lane < LPR && q < nq && s < NS) L.wsum[(wave * NQ + q) * MAXS + s] = x;
+    }
+  __syncthreads();
+  if (threadIdx.x < nq * NS) {
+    const int q = threadIdx.x / NS, s = threadIdx.x - q * NS;
+    double t = 0.0;
+    for (int w = 0; w < CT / 64; ++w) t += L.wsum[(w * NQ + q) * MAXS + s];
+    a.partial[((int64_t)slot * gridDim.x + blockIdx.x) * (NQ * NS) + q * NS + s] = t;
+  }
+}
+
+// Sum over all blocks of a partial slot written by the previous phase (same
+// grid), identical in every block.  With nv = nq * NS values per block and
+// G = min(PG, CT / nv) groups, fetch_partials issues this thread's loads
+// (value v = t % nv of blocks g, g + G, ... for group g = t / nv < G) early, so
+// that they overlap the scalar loads; finish_partials adds the groups in index
+// order into L.tot[q * MAXS + s].
+__device__ __forceinline__ int partial_groups(int nv) { return min(PG, CT / nv); }
+
+__device__ __forceinline__ double fetch_partials(int nq, const SolveArgs& a, int slot) {
+  const int nv = nq * a.NS, G = partial_groups(nv), g = threadIdx.x / nv, v = threadIdx.x - g * nv;
+  double acc = 0.0;
+  if (g < G)
+    for (int b = g; b < (int)gridDim.x; b += G)
+      acc += a.partial[((int64_t)slot * gridDim.x + b) * (NQ * a.NS) + v];
+  return acc;
+}
+
+__device__ void finish_partials(double acc, int nq, const SolveArgs& a, Shared& L) {
+  const int nv = nq * a.NS, G = partial_groups(nv), g = threadIdx.x / nv, v = threadIdx.x - g * nv;
+  if (g < G) L.red[g * nv + v] = acc;
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double t = 0.0;
+    for (int k = 0; k < G; ++k) t += L.red[k * nv + threadIdx.x];
+    const int q = threadIdx.x / a.NS, s = threadIdx.x - q * a.NS;
+    L.tot[q * MAXS + s] = t;
+  }
+  __syncthreads();
+}
 
 __device__ void load_scalars(const SolveArgs& a, int buf, Shared& L) {
   for (int q = threadIdx.x; q < SC_N * MAXS; q += CT) (&L.sc[0][0])[q] = a.scal[buf * SC_N * MAXS + q];
   __syncthreads();
-}
-
-// Loads this thread's share of a partial slot into registers (issued early so
-// that it overlaps the scalar loads and the phase's independent vector loads).
-template <int NSM>
-__device__ void fetch_partials(int nq, const SolveArgs& a, int slot, double (&v)[NQ * NSM]) {
-  const int nbk = gridDim.x;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) {
-      double acc = 0.0;
-      if (q < nq && s < a.NS)
-        for (int b = threadIdx.x; b < nbk; b += CT) acc += a.partial[(((int64_t)slot * NQ + q) * nbk + b) * a.NS + s];
-      v[q * NSM + s] = acc;
-    }
 }
 
 __device__ void store_scalars(const SolveArgs& a, int buf, Shared& L) {
@@ -187,31 +209,39 @@ __device__ void update_any(Shared& L, int NS) {
   __syncthreads();
 }
 
-#define ROWS_BEGIN for (int64_t r = (int64_t)blockIdx.x * CT + threadIdx.x; r < a.n; r += (int64_t)gridDim.x * CT) {
-#define ROWS_END }
+// Slice loop of a block (uniform over the block): row r of lane group
+// threadIdx.x / LPR, lane j; OWN(s) selects the shots s = j, j + LPR, ... of
+// this lane (compile-time s, so per-shot registers stay registers).
+#define SLICES_BEGIN                                                              \
+  const int lane_j = threadIdx.x & (LPR - 1);                                     \
+  for (int64_t sl = blockIdx.x; sl < a.n_slices; sl += gridDim.x) {               \
+    const int64_t r = sl * ELL_SLICE + (threadIdx.x / LPR);                       \
+    const bool row_ok = r < a.n;
+#define SLICES_END }
+#define OWN(s) if ((s & (LPR - 1)) == lane_j && s < NS && row_ok)
 
 // r = b - K x ; rhat = r ; partials |b|^2, |r|^2
 template <int NSM>
 __global__ void __launch_bounds__(CT) k_init1(SolveArgs a) {
   __shared__ Shared L;
-  double loc[NQ * NSM];
-#pragma unroll
-  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
-  ROWS_BEGIN {
+  Loc<NSM> loc;
+  const int NS = a.NS;
+  SLICES_BEGIN {
     double kx[NSM];
-    spmv_row<NSM>(a, a.val, r, a.x, kx);
+    spmv_slice<NSM>(a, a.val, sl, a.x, kx);
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
-      if (s >= a.NS) continue;
-      int64_t g = r * a.NS + s;
-      double bv = a.b[g], rv = bv - kx[s];
-      a.r[g] = rv;
-      a.rhat[g] = rv;
-      loc[0 * NSM + s] += bv * bv;
-      loc[1 * NSM + s] += rv * rv;
+      OWN(s) {
+        int64_t g = r * NS + s;
+        double bv = a.b[g], rv = bv - kx[s];
+        a.r[g] = rv;
+        a.rhat[g] = rv;
+        loc(0, s) += bv * bv;
+        loc(1, s) += rv * rv;
+      }
     }
-  } ROWS_END
-  write_partials<NSM>(loc, 2, a, SLOT_A, L.wsum, L.tot);
+  } SLICES_END
+  write_partials<NSM>(loc, 2, a, SLOT_A, L);
 }
 
 // scalars from slot A; w = K^T rhat ; p = r ; phat = D^-1 p ; partials |r|^2, (w, phat)
@@ -219,11 +249,11 @@ template <int NSM>
 __global__ void __launch_bounds__(CT) k_init2(SolveArgs a) {
   __shared__ Shared L;
   const int NS = a.NS;
-  read_totals<NSM>(2, a, SLOT_A, L.wsum, L.tot);
+  finish_partials(fetch_partials(2, a, SLOT_A), 2, a, L);
   const double tol2 = a.rtol * a.rtol;
   if (threadIdx.x < MAXS) {
     const int s = threadIdx.x;
-    double bn2 = s < NS ? L.tot[s] : 0.0, rn2 = s < NS ? L.tot[NSM + s] : 0.0;
+    double bn2 = s < NS ? L.tot[s] : 0.0, rn2 = s < NS ? L.tot[MAXS + s] : 0.0;
     for (int k = 0; k < SC_N; ++k) L.sc[k][s] = 0.0;
     L.sc[SC_BN2][s] = bn2;
     L.sc[SC_RHO][s] = rn2;
@@ -233,27 +263,26 @@ __global__ void __launch_bounds__(CT) k_init2(SolveArgs a) {
   }
   __syncthreads();
   update_any(L, NS);
-  double loc[NQ * NSM];
-#pragma unroll
-  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
-  ROWS_BEGIN {
+  Loc<NSM> loc;
+  SLICES_BEGIN {
     double kx[NSM];
-    spmv_row<NSM>(a, a.valT, r, a.rhat, kx);
+    spmv_slice<NSM>(a, a.valT, sl, a.rhat, kx);
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
-      if (s >= NS) continue;
-      int64_t g = r * NS + s;
-      if (L.sc[SC_BN2][s] == 0.0) a.x[g] = 0.0;
-      double pv = a.r[g];
-      double ph = a.dinv[r] * pv;
-      a.w[g] = kx[s];
-      a.p[g] = pv;
-      a.phat[g] = ph;
-      loc[0 * NSM + s] += pv * pv;
-      loc[1 * NSM + s] += kx[s] * ph;
+      OWN(s) {
+        int64_t g = r * NS + s;
+        if (L.sc[SC_BN2][s] == 0.0) a.x[g] = 0.0;
+        double pv = a.r[g];
+        double ph = a.dinv[r] * pv;
+        a.w[g] = kx[s];
+        a.p[g] = pv;
+        a.phat[g] = ph;
+        loc(0, s) += pv * pv;
+        loc(1, s) += kx[s] * ph;
+      }
     }
-  } ROWS_END
-  write_partials<NSM>(loc, 2, a, SLOT_X, L.wsum, L.tot);
+  } SLICES_END
+  write_partials<NSM>(loc, 2, a, SLOT_X, L);
   store_scalars(a, 0, L);
 }
 
@@ -262,21 +291,19 @@ __global__ void __launch_bounds__(CT) k_init2(SolveArgs a) {
 template <int NSM>
 __device__ bool phase_v(const SolveArgs& a, Shared& L) {
   const int NS = a.NS;
-  double part[NQ * NSM];
-  fetch_partials<NSM>(2, a, SLOT_X, part);
+  const double part = fetch_partials(2, a, SLOT_X);
   load_scalars(a, 0, L);
   if (idle_forward(a, 1, L)) return false;
-  // with one row per thread, v = K phat (independent of this phase's scalars) starts first
-  const int64_t r0 = (int64_t)blockIdx.x * CT + threadIdx.x;
-  const bool single = (int64_t)gridDim.x * CT >= a.n;
+  // with one slice per block, v = K phat (independent of this phase's scalars) starts first
+  const bool single = (int64_t)gridDim.x >= a.n_slices;
   double kx0[NSM];
-  if (single && r0 < a.n) spmv_row<NSM>(a, a.val, r0, a.phat, kx0);
-  block_sums<NQ * NSM>(part, 2 * NSM, L.wsum, L.tot);
+  if (single) spmv_slice<NSM>(a, a.val, blockIdx.x, a.phat, kx0);
+  finish_partials(part, 2, a, L);
   const double tol2 = a.rtol * a.rtol;
   if (threadIdx.x < NS) {
     const int s = threadIdx.x;
     if (L.sc[SC_ACTIVE][s] != 0.0) {
-      double rn2 = L.tot[s], wp = L.tot[NSM + s], rho = L.sc[SC_RHO][s];
+      double rn2 = L.tot[s], wp = L.tot[MAXS + s], rho = L.sc[SC_RHO][s];
       if (!isfinite(rn2) || !isfinite(rho) || !isfinite(wp)) {
         L.sc[SC_ACTIVE][s] = 0.0;
         if (blockIdx.x == 0) {
@@ -300,32 +327,32 @@ __device__ bool phase_v(const SolveArgs& a, Shared& L) {
   update_any(L, NS);
   store_scalars(a, 1, L);
   if (L.sc[SC_ANY][0] == 0.0) return false;
-  double loc[NQ * NSM];
-#pragma unroll
-  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
-  ROWS_BEGIN {
+  Loc<NSM> loc;
+  SLICES_BEGIN {
     double kx[NSM];
     if (single) {
 #pragma unroll
       for (int s = 0; s < NSM; ++s) kx[s] = kx0[s];
     } else {
-      spmv_row<NSM>(a, a.val, r, a.phat, kx);
+      spmv_slice<NSM>(a, a.val, sl, a.phat, kx);
     }
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
-      if (s >= NS || L.sc[SC_ACTIVE][s] == 0.0) continue;
-      int64_t g = r * NS + s;
-      double sv = a.r[g] - L.sc[SC_ALPHA][s] * kx[s];
-      double sh = a.dinv[r] * sv;
-      a.v[g] = kx[s];
-      a.sv[g] = sv;
-      a.shat[g] = sh;
-      loc[0 * NSM + s] += sv * sv;
-      loc[1 * NSM + s] += a.rhat[g] * sv;
-      loc[2 * NSM + s] += a.w[g] * sh;
+      OWN(s) {
+        if (L.sc[SC_ACTIVE][s] == 0.0) continue;
+        int64_t g = r * NS + s;
+        double sv = a.r[g] - L.sc[SC_ALPHA][s] * kx[s];
+        double sh = a.dinv[r] * sv;
+        a.v[g] = kx[s];
+        a.sv[g] = sv;
+        a.shat[g] = sh;
+        loc(0, s) += sv * sv;
+        loc(1, s) += a.rhat[g] * sv;
+        loc(2, s) += a.w[g] * sh;
+      }
     }
-  } ROWS_END
-  write_partials<NSM>(loc, 3, a, SLOT_V, L.wsum, L.tot);
+  } SLICES_END
+  write_partials<NSM>(loc, 3, a, SLOT_V, L);
   return true;
 }
 
@@ -334,49 +361,47 @@ __device__ bool phase_v(const SolveArgs& a, Shared& L) {
 template <int NSM>
 __device__ void phase_t(const SolveArgs& a, Shared& L) {
   const int NS = a.NS;
-  double part[NQ * NSM];
-  fetch_partials<NSM>(3, a, SLOT_V, part);
+  const double part = fetch_partials(3, a, SLOT_V);
   load_scalars(a, 1, L);
   if (idle_forward(a, 2, L)) return;
-  const int64_t r0 = (int64_t)blockIdx.x * CT + threadIdx.x;
-  const bool single = (int64_t)gridDim.x * CT >= a.n;
+  const bool single = (int64_t)gridDim.x >= a.n_slices;
   double kx0[NSM];
-  if (single && r0 < a.n) spmv_row<NSM>(a, a.val, r0, a.shat, kx0);
-  block_sums<NQ * NSM>(part, 3 * NSM, L.wsum, L.tot);
+  if (single) spmv_slice<NSM>(a, a.val, blockIdx.x, a.shat, kx0);
+  finish_partials(part, 3, a, L);
   const double tol2 = a.rtol * a.rtol;
   if (threadIdx.x < NS) {
     const int s = threadIdx.x;
     L.sc[SC_SDONE][s] = (L.sc[SC_ACTIVE][s] != 0.0 && L.tot[s] <= tol2 * L.sc[SC_BN2][s]) ? 1.0 : 0.0;
-    L.sc[SC_RS][s] = L.tot[NSM + s];
-    L.sc[SC_WS][s] = L.tot[2 * NSM + s];
+    L.sc[SC_RS][s] = L.tot[MAXS + s];
+    L.sc[SC_WS][s] = L.tot[2 * MAXS + s];
   }
   __syncthreads();
   store_scalars(a, 2, L);
-  double loc[NQ * NSM];
-#pragma unroll
-  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
-  ROWS_BEGIN {
+  Loc<NSM> loc;
+  SLICES_BEGIN {
     double kx[NSM];
     if (single) {
 #pragma unroll
       for (int s = 0; s < NSM; ++s) kx[s] = kx0[s];
     } else {
-      spmv_row<NSM>(a, a.val, r, a.shat, kx);
+      spmv_slice<NSM>(a, a.val, sl, a.shat, kx);
     }
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
-      if (s >= NS || L.sc[SC_ACTIVE][s] == 0.0) continue;
-      int64_t g = r * NS + s;
-      if (L.sc[SC_SDONE][s] != 0.0) {
-        a.x[g] += L.sc[SC_ALPHA][s] * a.phat[g];
-        continue;
+      OWN(s) {
+        if (L.sc[SC_ACTIVE][s] == 0.0) continue;
+        int64_t g = r * NS + s;
+        if (L.sc[SC_SDONE][s] != 0.0) {
+          a.x[g] += L.sc[SC_ALPHA][s] * a.phat[g];
+          continue;
+        }
+        a.t[g] = kx[s];
+        loc(0, s) += kx[s] * a.sv[g];
+        loc(1, s) += kx[s] * kx[s];
       }
-      a.t[g] = kx[s];
-      loc[0 * NSM + s] += kx[s] * a.sv[g];
-      loc[1 * NSM + s] += kx[s] * kx[s];
     }
-  } ROWS_END
-  write_partials<NSM>(loc, 2, a, SLOT_T, L.wsum, L.tot);
+  } SLICES_END
+  write_partials<NSM>(loc, 2, a, SLOT_T, L);
 }
 
 // omega, rho, beta from slot T ; x += alpha phat + omega shat ; r = s - omega t ;
@@ -384,18 +409,17 @@ __device__ void phase_t(const SolveArgs& a, Shared& L) {
 template <int NSM>
 __device__ void phase_x(const SolveArgs& a, Shared& L) {
   const int NS = a.NS;
-  double part[NQ * NSM];
-  fetch_partials<NSM>(2, a, SLOT_T, part);
+  const double part = fetch_partials(2, a, SLOT_T);
   load_scalars(a, 2, L);
   if (idle_forward(a, 0, L)) return;
-  block_sums<NQ * NSM>(part, 2 * NSM, L.wsum, L.tot);
+  finish_partials(part, 2, a, L);
   if (threadIdx.x < NS) {
     const int s = threadIdx.x;
     if (L.sc[SC_SDONE][s] != 0.0) L.sc[SC_ACTIVE][s] = 0.0;
     L.sc[SC_SDONE][s] = 0.0;
     L.sc[SC_BETA][s] = 0.0;
     if (L.sc[SC_ACTIVE][s] != 0.0) {
-      double om = L.tot[s] / L.tot[NSM + s];
+      double om = L.tot[s] / L.tot[MAXS + s];
       double rho_new = L.sc[SC_RS][s] - om * L.sc[SC_WS][s];
       L.sc[SC_BETA][s] = (rho_new / L.sc[SC_RHO][s]) * (L.sc[SC_ALPHA][s] / om);
       L.sc[SC_OMEGA][s] = om;
@@ -405,27 +429,27 @@ __device__ void phase_x(const SolveArgs& a, Shared& L) {
   __syncthreads();
   update_any(L, NS);
   if (blockIdx.x == 0 && threadIdx.x == 0) L.sc[SC_ITERS][0] += 1.0;
-  double loc[NQ * NSM];
-#pragma unroll
-  for (int q = 0; q < NQ * NSM; ++q) loc[q] = 0.0;
-  ROWS_BEGIN {
+  Loc<NSM> loc;
+  SLICES_BEGIN {
 #pragma unroll
     for (int s = 0; s < NSM; ++s) {
-      if (s >= NS || L.sc[SC_ACTIVE][s] == 0.0) continue;
-      int64_t g = r * NS + s;
-      const double al = L.sc[SC_ALPHA][s], om = L.sc[SC_OMEGA][s];
-      a.x[g] += al * a.phat[g] + om * a.shat[g];
-      double rv = a.sv[g] - om * a.t[g];
-      double pv = rv + L.sc[SC_BETA][s] * (a.p[g] - om * a.v[g]);
-      double ph = a.dinv[r] * pv;
-      a.r[g] = rv;
-      a.p[g] = pv;
-      a.phat[g] = ph;
-      loc[0 * NSM + s] += rv * rv;
-      loc[1 * NSM + s] += a.w[g] * ph;
+      OWN(s) {
+        if (L.sc[SC_ACTIVE][s] == 0.0) continue;
+        int64_t g = r * NS + s;
+        const double al = L.sc[SC_ALPHA][s], om = L.sc[SC_OMEGA][s];
+        a.x[g] += al * a.phat[g] + om * a.shat[g];
+        double rv = a.sv[g] - om * a.t[g];
+        double pv = rv + L.sc[SC_BETA][s] * (a.p[g] - om * a.v[g]);
+        double ph = a.dinv[r] * pv;
+        a.r[g] = rv;
+        a.p[g] = pv;
+        a.phat[g] = ph;
+        loc(0, s) += rv * rv;
+        loc(1, s) += a.w[g] * ph;
+      }
     }
-  } ROWS_END
-  write_partials<NSM>(loc, 2, a, SLOT_X, L.wsum, L.tot);
+  } SLICES_END
+  write_partials<NSM>(loc, 2, a, SLOT_X, L);
   store_scalars(a, 0, L);
 }
 
@@ -501,9 +525,9 @@ __global__ void __launch_bounds__(CT) k_rescue(SolveArgs a, int max_more) {
   unsigned gen_seen = 0;
   if (threadIdx.x == 0) gen_seen = ld_acquire(a.bar);
   for (int i = 0; i < max_more; ++i) {
-    bool go = phase_v<NSM>(a, L);
+    // go is the same in every block (identical scalars), so all blocks leave together
+    if (!phase_v<NSM>(a, L)) break;
     grid_barrier(a.bar, gen_seen, a.status);
-    if (!go) break;
     phase_t<NSM>(a, L);
     grid_barrier(a.bar, gen_seen, a.status);
     phase_x<NSM>(a, L);
@@ -517,7 +541,7 @@ __global__ void __launch_bounds__(CT) k_finish(SolveArgs a) {
   __shared__ Shared L;
   const int NS = a.NS;
   load_scalars(a, 0, L);
-  read_totals<NSM>(2, a, SLOT_X, L.wsum, L.tot);
+  finish_partials(fetch_partials(2, a, SLOT_X), 2, a, L);
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   const double tol2 = a.rtol * a.rtol;
   int unconverged = 0;
@@ -584,12 +608,12 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS) {
   w->phat = w->t + sz;
   w->shat = w->phat + sz;
   w->w = w->shat + sz;
-  int64_t want = (n_nodes + CT - 1) / CT;
+  int64_t want = (n_nodes + ELL_SLICE - 1) / ELL_SLICE;
   int cap = NS <= 1 ? coresident_blocks<1>() : NS <= 2 ? coresident_blocks<2>() : NS <= 4 ? coresident_blocks<4>()
           : NS <= 8 ? coresident_blocks<8>() : coresident_blocks<16>();
   if (cap <= 0) return sbfwi_fail(SBFWI_EHIP, "cannot query the co-resident grid size");
   w->nblocks = (int)(want < cap ? want : cap);
-  SBFWI_CHECK(sbfwi_alloc(&w->partial, (int64_t)4 * NQ * w->nblocks * NS));
+  SBFWI_CHECK(sbfwi_alloc(&w->partial, (int64_t)4 * w->nblocks * NQ * NS));
   SBFWI_CHECK(sbfwi_alloc(&w->scal, (int64_t)3 * SC_N * MAXS));
   SBFWI_CHECK(sbfwi_alloc(&w->bar, 64 + 32 * ((w->nblocks + 15) / 16 + 1)));
   SBFWI_HIP(hipMemset(w->bar, 0, sizeof(unsigned) * (64 + 32 * ((w->nblocks + 15) / 16 + 1))));
@@ -609,6 +633,7 @@ int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
   sbfwi_mesh_s* m = f->m;
   SolveArgs a;
   a.n = m->n_nodes;
+  a.n_slices = (m->n_nodes + ELL_SLICE - 1) / ELL_SLICE;
   a.NS = w->NS;
   a.ell_off = m->d.ell_off;
   a.ell_w = m->d.ell_w;

@@ -44,7 +44,10 @@ static int upload_mesh(sbfwi_mesh_s* m, const std::vector<int64_t>& loop_nodes,
   SBFWI_CHECK(sbfwi_upload(&m->d.contrib_ptr, cptr));
   SBFWI_CHECK(sbfwi_upload(&m->d.contrib_src, csrc));
   for (int c = 0; c < 3; ++c) SBFWI_CHECK(sbfwi_upload(&m->class_elems[c], m->h_class_elems[c]));
-  // sliced ELL layout of the coarse pattern
+  // sliced ELL layout of the coarse pattern: slices of ELL_SLICE rows, each
+  // padded to its widest row rounded up to ELL_LPR entries; chunk c of a slice
+  // stores entries k = c*ELL_LPR .. c*ELL_LPR + ELL_LPR-1 of every row, row-major
+  // inside the chunk: position = off + (c * ELL_SLICE + row_in_slice) * ELL_LPR + k % ELL_LPR
   const int64_t n = m->n_nodes, ns = (n + ELL_SLICE - 1) / ELL_SLICE;
   std::vector<int64_t> eoff(ns + 1, 0);
   std::vector<int32_t> ew(ns, 0);
@@ -52,16 +55,17 @@ static int upload_mesh(sbfwi_mesh_s* m, const std::vector<int64_t>& loop_nodes,
     int64_t w = 0;
     for (int64_t r = sl * ELL_SLICE; r < std::min(n, (sl + 1) * ELL_SLICE); ++r)
       w = std::max(w, m->h_row_ptr[r + 1] - m->h_row_ptr[r]);
-    ew[sl] = (int32_t)w;
-    eoff[sl + 1] = eoff[sl] + w * ELL_SLICE;
+    const int64_t chunks = (w + ELL_LPR - 1) / ELL_LPR;
+    ew[sl] = (int32_t)chunks;
+    eoff[sl + 1] = eoff[sl] + chunks * ELL_SLICE * ELL_LPR;
   }
   std::vector<int32_t> ecol(eoff[ns]);
   std::vector<int64_t> epos(m->nnz);
   for (int64_t sl = 0; sl < ns; ++sl)
     for (int64_t lr = 0; lr < ELL_SLICE; ++lr) {
       int64_t r = sl * ELL_SLICE + lr;
-      for (int64_t k = 0; k < ew[sl]; ++k) {
-        int64_t pos = eoff[sl] + k * ELL_SLICE + lr;
+      for (int64_t k = 0; k < (int64_t)ew[sl] * ELL_LPR; ++k) {
+        int64_t pos = eoff[sl] + ((k / ELL_LPR) * ELL_SLICE + lr) * ELL_LPR + k % ELL_LPR;
         int64_t q = r < n ? m->h_row_ptr[r] + k : -1;
         if (r < n && q < m->h_row_ptr[r + 1]) {
           ecol[pos] = (int32_t)m->h_col64[q];

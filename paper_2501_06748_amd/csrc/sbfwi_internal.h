@@ -45,15 +45,17 @@ struct MeshDev {
   int64_t* tr_idx = nullptr;     // [nnz] position of (c, r) for entry (r, c)
   int64_t* contrib_ptr = nullptr;  // [nnz+1]
   int64_t* contrib_src = nullptr;  // index into S storage (dense_off[e] + i*nb + j)
-  // sliced ELL copy of the coarse pattern: slices of ELL_SLICE rows, column-major
-  // inside a slice and padded to the widest row of the slice (padding: column = row, value 0)
+  // sliced ELL copy of the coarse pattern: slices of ELL_SLICE rows, padded to
+  // the widest row of the slice in chunks of ELL_LPR entries (padding: column =
+  // row, value 0); chunk c holds entries c*ELL_LPR.. of every row, row-major
   int64_t n_ell = 0;
   int64_t* ell_off = nullptr;   // [n_slices + 1] offsets of the slices
-  int32_t* ell_w = nullptr;     // [n_slices] width of each slice
+  int32_t* ell_w = nullptr;     // [n_slices] chunks of ELL_LPR entries in each slice
   int32_t* ell_col = nullptr;   // [n_ell]
   int64_t* ell_pos = nullptr;   // [nnz] ELL position of every CSR entry
 };
 #define ELL_SLICE 256
+#define ELL_LPR 4
 
 struct sbfwi_mesh_s {
   int64_t n_nodes = 0, n_elem = 0, n_params = 0, n_int = 0, n_loop = 0, n_x = 0;
