@@ -204,13 +204,17 @@ int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
 /*
  * Live kernel timing.  sbfwi_profile(mask) brackets every launch of the kernels
  * whose bit is set with HIP events on the launch stream (bit ids: 0 condense,
- * 1 recover, 2 coarse solve, 3 source gather, 4 nodal update, 5 transposed
- * condense, 6 transposed recover, 7 adjoint gather, 8 adjoint nodal update,
- * 9 exact-gradient contraction, 10 paper-kernel correlation, 11 factorisation).
- * A sweep over elements of several n_b classes counts as one launch.
- * sbfwi_profile_read waits for the recorded events and writes, for each of
- * the 16 ids, host_out[2 id] = launches and host_out[2 id + 1] = total ms;
- * reset != 0 clears the totals.  One host thread only.
+ * 1 recover, 2 coarse solve (all its kernels), 3 source gather, 4 nodal
+ * update, 5 transposed condense, 6 transposed recover, 7 adjoint gather,
+ * 8 adjoint nodal update, 9 exact-gradient contraction, 10 paper-kernel
+ * correlation, 11 factorisation, 12 / 13 / 14 the three per-iteration kernels
+ * of the coarse solve (v = K p, t = K s, the x / r / p update), 15 its two
+ * start-up kernels).  A sweep over elements of several n_b classes counts as
+ * one launch.  Recorded pairs are accumulated as they complete (the oldest
+ * are waited for once many are in flight).  sbfwi_profile_read waits for the
+ * rest and writes, for each of the 20 ids, host_out[2 id] = launches and
+ * host_out[2 id + 1] = total ms; reset != 0 clears the totals.  One host
+ * thread only.
  */
 int sbfwi_profile(uint32_t kernel_mask);
 int sbfwi_profile_read(double* host_out, int reset);

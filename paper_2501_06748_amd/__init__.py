@@ -191,7 +191,8 @@ def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:
 
 
 PROFILE_KERNELS = ["condense", "recover", "coarse_solve", "source_gather", "nodal_update", "adj_condense",
-                   "adj_recover", "adj_gather", "adj_nodal_update", "grad_exact", "grad_paper", "factor"]
+                   "adj_recover", "adj_gather", "adj_nodal_update", "grad_exact", "grad_paper", "factor",
+                   "solve_v", "solve_t", "solve_x", "solve_init"]
 
 
 def sbfwi_profile(kernels):
@@ -201,7 +202,7 @@ def sbfwi_profile(kernels):
 
 
 def sbfwi_profile_read(reset=False) -> dict:
-    buf = np.zeros(32, dtype=np.float64)
+    buf = np.zeros(40, dtype=np.float64)
     check(lib().sbfwi_profile_read(buf.ctypes.data_as(C.c_void_p), int(bool(reset))))
     return {name: {"launches": int(buf[2 * i]), "ms": float(buf[2 * i + 1])}
             for i, name in enumerate(PROFILE_KERNELS) if buf[2 * i] > 0}

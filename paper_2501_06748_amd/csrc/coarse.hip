@@ -561,11 +561,21 @@ __global__ void __launch_bounds__(CT) k_finish(SolveArgs a) {
 
 template <int NSM>
 hipError_t enqueue(const SolveArgs& a, int iters, int max_more, unsigned blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_init1<NSM>, dim3(blocks), dim3(CT), 0, s, a);
-  hipLaunchKernelGGL(k_init2<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+  {
+    ProfScope ps(PK_SOLVE_INIT, s);
+    hipLaunchKernelGGL(k_init1<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+    hipLaunchKernelGGL(k_init2<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+  }
   for (int i = 0; i < iters; ++i) {
-    hipLaunchKernelGGL(k_phase_v<NSM>, dim3(blocks), dim3(CT), 0, s, a);
-    hipLaunchKernelGGL(k_phase_t<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+    {
+      ProfScope ps(PK_SOLVE_V, s);
+      hipLaunchKernelGGL(k_phase_v<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+    }
+    {
+      ProfScope ps(PK_SOLVE_T, s);
+      hipLaunchKernelGGL(k_phase_t<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+    }
+    ProfScope ps(PK_SOLVE_X, s);
     hipLaunchKernelGGL(k_phase_x<NSM>, dim3(blocks), dim3(CT), 0, s, a);
   }
   if (max_more > 0) {

@@ -24,6 +24,28 @@ struct Prof {
 
 Prof g_prof;
 
+// Accumulates the oldest recorded pairs (waiting for them) and returns their
+// events to the pool.
+int drain(size_t count) {
+  count = count < g_prof.pending.size() ? count : g_prof.pending.size();
+  for (size_t i = 0; i < count; ++i) {
+    auto& p = g_prof.pending[i];
+    SBFWI_HIP(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    SBFWI_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    g_prof.ms[p.id] += ms;
+    g_prof.calls[p.id] += 1;
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
+  }
+  g_prof.pending.erase(g_prof.pending.begin(), g_prof.pending.begin() + count);
+  return SBFWI_OK;
+}
+
+// pairs kept in flight before the oldest half is drained (bounds the event pool;
+// the newest half stays queued, so the device never runs dry)
+constexpr size_t kMaxPending = 8192;
+
 hipEvent_t take() {
   if (!g_prof.pool.empty()) {
     hipEvent_t e = g_prof.pool.back();
@@ -49,6 +71,7 @@ ProfScope::~ProfScope() {
   if (!b) return;
   if (hipEventRecord(b, s_) != hipSuccess) return;
   g_prof.pending.push_back({id_, (hipEvent_t)a_, b});
+  if (g_prof.pending.size() > kMaxPending) drain(kMaxPending / 2);
 }
 
 extern "C" int sbfwi_profile(uint32_t kernel_mask) {
@@ -58,16 +81,7 @@ extern "C" int sbfwi_profile(uint32_t kernel_mask) {
 
 extern "C" int sbfwi_profile_read(double* out, int reset) {
   if (!out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
-  for (auto& p : g_prof.pending) {
-    SBFWI_HIP(hipEventSynchronize(p.b));
-    float ms = 0.f;
-    SBFWI_HIP(hipEventElapsedTime(&ms, p.a, p.b));
-    g_prof.ms[p.id] += ms;
-    g_prof.calls[p.id] += 1;
-    g_prof.pool.push_back(p.a);
-    g_prof.pool.push_back(p.b);
-  }
-  g_prof.pending.clear();
+  SBFWI_CHECK(drain(g_prof.pending.size()));
   for (int k = 0; k < SBFWI_PROF_KERNELS; ++k) {
     out[2 * k] = (double)g_prof.calls[k];
     out[2 * k + 1] = g_prof.ms[k];

@@ -157,3 +157,41 @@ def test_exact_gradient_ragged_multishot():
     err = rel_l2(grad, gref)
     log(f"  gradient relative L2 = {err:.3e}")
     assert err <= 1e-8
+
+
+def test_full_size_sampled_parity():
+    """The benchmark's plate at full size (128 x 64 elements, n_b 16, N_r 32,
+    4 shots, the launch configuration bench.py times): factor data of 32
+    seeded elements and the whole nodal wavefield of the first 3 steps.  The
+    wavelets are seeded N(0, 1) samples so that the first steps carry signal."""
+    steps = 3
+    wl = W.config_paper(n_steps=steps, n_shots=4)
+    rng = np.random.default_rng(1000 * 1 + 7)
+    wl.wavelets = rng.standard_normal((wl.n_shots, steps))
+    wl.rec_nodes = np.arange(wl.mesh.n_nodes, dtype=np.int64)
+    rho = wl.models["random30"]
+    log(f"full-size sampled parity: {wl.mesh.n_elem} el, {wl.mesh.n_nodes} nodes, {steps} steps")
+    g = GpuModel(wl, rho)
+    tr, _ = g.forward(n_steps=steps)
+    tr = tr.cpu().numpy()
+    om = _oracle_model(wl, rho)
+    mesh = wl.mesh
+    nb = mesh.n_b().astype(np.int64)
+    S_gpu = g.sb.sbfwi_copy_factor_data(g.f, 0, int((nb ** 2).sum()))
+    nfinv = int(((mesh.n_r - 1).astype(np.int64) * nb ** 2).sum())
+    F_gpu = g.sb.sbfwi_copy_factor_data(g.f, 2, nfinv)
+    S_or = _per_element(mesh, om.groups, lambda gr, i: gr.f["S"][i])
+    F_or = _per_element(mesh, om.groups, lambda gr, i: np.linalg.inv(gr.f["phit"][i, :gr.n]))
+    soff = np.concatenate([[0], np.cumsum(nb ** 2)])
+    foff = np.concatenate([[0], np.cumsum((mesh.n_r - 1).astype(np.int64) * nb ** 2)])
+    worst = 0.0
+    for e in rng.choice(mesh.n_elem, size=32, replace=False):
+        worst = max(worst, rel_l2(S_gpu[soff[e]:soff[e + 1]], S_or[e].ravel()),
+                    rel_l2(F_gpu[foff[e]:foff[e + 1]], F_or[e].ravel()))
+    log(f"  sampled elements: worst relative L2 (S, phi~^-1) = {worst:.3e}")
+    assert worst <= 1e-11
+    ref = ostp.forward(om, wl.src_nodes, wl.wavelets, wl.rec_nodes, steps)
+    err = rel_l2(tr, ref)
+    log(f"  nodal wavefield relative L2 = {err:.3e}")
+    assert np.isfinite(tr).all()
+    assert err <= 1e-10
