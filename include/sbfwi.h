@@ -113,11 +113,34 @@ int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, double dt,
 /* Solver controls: relative residual tolerance (default 1e-13) and iteration cap (default 500). */
 int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
 
-/* Launch-shape controls (results do not depend on them beyond rounding order):
- *   param 0: BiCGStab iterations enqueued as separate kernels per coarse solve (1 .. 1000,
- *            default 13); iterations after convergence are no-ops, and a solve that needs
- *            more continues in one cooperative kernel up to the limit of sbfwi_set_solver. */
+/* Launch-shape controls; none of them changes any result bit:
+ *   param 0:  BiCGStab iterations enqueued as separate kernels per coarse solve (1 .. 1000,
+ *             default 13); iterations after convergence are no-ops, and a solve that needs
+ *             more continues in one cooperative kernel up to the limit of sbfwi_set_solver.
+ *   param 1:  1 = forward runs without full storage replay every time step from HIP graphs
+ *             captured at the first step (on a library stream of default priority, ordered
+ *             after the caller's stream); 0 = ordinary launches (default).
+ *   param 2:  reset the sweep launch plan to the defaults (value ignored).
+ *   param 10 + 3 k + c: shots per block (0 = default, 1, 2, 4, 8, 16) of sweep k (0 condense,
+ *             1 recover, 2 transposed condense, 3 transposed recover) for n_b class c
+ *             (n_b <= 8, <= 16, <= 24).
+ *   param 30 + k: > 0 = sweep k runs as one persistent launch over all classes with this
+ *             many shots per block; 0 = one launch per class. */
 int sbfwi_set_launch(sbfwi_factors f, int param, int value);
+
+/*
+ * Autotuner of the sweep launch plan for runs of n_shots shots on these factors:
+ * for every sweep kind and n_b class, each shots-per-block choice (1 .. 16, up to the
+ * shot count rounded up to a power of two) is timed on the factors with zero state,
+ * as is the single persistent launch over all classes; the fastest plan is kept for
+ * later runs (sbfwi_set_launch param 2 resets it).  Synchronous; allocates and frees
+ * its own work buffers.
+ *   host_out (may be NULL): 24 doubles, for k = 0 .. 3: [6k .. 6k+2] the chosen shots
+ *   per block of the three classes (0 = class empty), [6k+3] the persistent launch's
+ *   shots per block (0 = not chosen), [6k+4] ms of the best per-class launches,
+ *   [6k+5] ms of the best persistent launch.
+ */
+int sbfwi_autotune(sbfwi_factors f, int n_shots, double* host_out, hipStream_t s);
 
 /*
  * Copies factor data to host memory (for inspection and tests), synchronous.

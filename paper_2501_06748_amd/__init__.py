@@ -135,6 +135,28 @@ def sbfwi_set_launch(f: FactorsHandle, param: int, value: int):
     check(lib().sbfwi_set_launch(f, int(param), int(value)))
 
 
+def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
+    """Times the sweep launch shapes for runs of n_shots shots and keeps the fastest plan."""
+    out = np.zeros(24, dtype=np.float64)
+    check(lib().sbfwi_autotune(f, int(n_shots), out.ctypes.data_as(C.c_void_p), _stream(stream)))
+    kinds = ["condense", "recover", "adj_condense", "adj_recover"]
+    return {k: {"shots_per_block": [int(v) for v in out[6 * i:6 * i + 3]], "fused": int(out[6 * i + 3]),
+                "ms_per_class": float(out[6 * i + 4]), "ms_fused": float(out[6 * i + 5])}
+            for i, k in enumerate(kinds)}
+
+
+LAUNCH_ENQUEUED_ITERS, LAUNCH_GRAPHS, LAUNCH_RESET_PLAN = 0, 1, 2
+
+
+def launch_param_shots(sweep: int, cls: int) -> int:
+    """sbfwi_set_launch parameter of the shots per block of sweep (0..3) and n_b class (0..2)."""
+    return 10 + 3 * sweep + cls
+
+
+def launch_param_fused(sweep: int) -> int:
+    return 30 + sweep
+
+
 def sbfwi_copy_factor_data(f: FactorsHandle, which: int, count: int) -> np.ndarray:
     out = np.empty(count, dtype=np.float64)
     check(lib().sbfwi_copy_factor_data(f, int(which), out.ctypes.data_as(C.c_void_p)))

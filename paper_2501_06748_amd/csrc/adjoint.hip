@@ -88,11 +88,8 @@ __device__ __forceinline__ double denseT_mv(const double* F, const double* vec, 
 
 // U^T sweep: z_j, and the coupling psi~_{n-1}^T z_{n-1} to the coarse rows.
 template <int NBT, int S>
-__global__ void __launch_bounds__(WT) adj_condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                          FactorsDev f, AdjArgs a) {
-  __shared__ AdjLds<NBT, S> L;
-  const int e = elems[blockIdx.x];
-  const int s0 = blockIdx.y * S;
+__device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
+                                                  const AdjArgs& a, AdjLds<NBT, S>& L) {
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e];
@@ -146,11 +143,8 @@ __global__ void __launch_bounds__(WT) adj_condense_kernel(const int32_t* __restr
 
 // L^T sweep, adjoint Newmark chain at the interior levels, and P_n^T lambda_n.
 template <int NBT, int S>
-__global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                         FactorsDev f, AdjArgs a) {
-  __shared__ AdjLds<NBT, S> L;
-  const int e = elems[blockIdx.x];
-  const int s0 = blockIdx.y * S;
+__device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
+                                                 const AdjArgs& a, AdjLds<NBT, S>& L) {
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e], xo = m.x_off[e];
@@ -238,6 +232,45 @@ __global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restri
     double acc = 0.0;
     for (int c = 0; c < nb; ++c) acc += Tm[c * nb + i] * L.t[c * S + s];
     if (s < ns) a.lam[(xo + i) * a.NS + s0 + s] = -acc;
+  }
+}
+
+
+// One block per (element of an n_b class, group of S shots).
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) adj_condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                          FactorsDev f, AdjArgs a) {
+  __shared__ AdjLds<NBT, S> L;
+  adj_condense_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+}
+
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                         FactorsDev f, AdjArgs a) {
+  __shared__ AdjLds<NBT, S> L;
+  adj_recover_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+}
+
+// One persistent launch over all n_b classes (work items in order of
+// decreasing cost; LDS sized for the largest class).
+template <int S, bool CONDENSE>
+__global__ void __launch_bounds__(WT) adj_sweep_fused_kernel(const int32_t* __restrict__ order, int64_t n_work,
+                                                             int groups, MeshDev m, FactorsDev f, AdjArgs a) {
+  __shared__ AdjLds<24, S> L;
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int e = order[w / groups];
+    const int s0 = (int)(w % groups) * S;
+    const int nb = m.nb[e];
+    if (nb <= 8) {
+      auto& Ls = *reinterpret_cast<AdjLds<8, S>*>(&L);
+      if (CONDENSE) adj_condense_body<8, S>(e, s0, m, f, a, Ls); else adj_recover_body<8, S>(e, s0, m, f, a, Ls);
+    } else if (nb <= 16) {
+      auto& Ls = *reinterpret_cast<AdjLds<16, S>*>(&L);
+      if (CONDENSE) adj_condense_body<16, S>(e, s0, m, f, a, Ls); else adj_recover_body<16, S>(e, s0, m, f, a, Ls);
+    } else {
+      if (CONDENSE) adj_condense_body<24, S>(e, s0, m, f, a, L); else adj_recover_body<24, S>(e, s0, m, f, a, L);
+    }
+    __syncthreads();
   }
 }
 
@@ -453,21 +486,65 @@ void launch_adj(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, con
     hipLaunchKernelGGL((adj_recover_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
 }
 
-template <int S>
-void launch_adj_all(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
-  launch_adj<8, S>(condense, m, 0, f, a, st);
-  launch_adj<16, S>(condense, m, 1, f, a, st);
-  launch_adj<24, S>(condense, m, 2, f, a, st);
+template <int NBT>
+void launch_adj_s(bool condense, sbfwi_mesh_s* m, int cl, int S, const FactorsDev& f, const AdjArgs& a,
+                  hipStream_t st) {
+  switch (S) {
+    case 1: launch_adj<NBT, 1>(condense, m, cl, f, a, st); break;
+    case 2: launch_adj<NBT, 2>(condense, m, cl, f, a, st); break;
+    case 4: launch_adj<NBT, 4>(condense, m, cl, f, a, st); break;
+    case 8: launch_adj<NBT, 8>(condense, m, cl, f, a, st); break;
+    default: launch_adj<NBT, 16>(condense, m, cl, f, a, st); break;
+  }
 }
 
-void launch_adj_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+void launch_adj_cls(bool condense, sbfwi_mesh_s* m, int cl, int S, const FactorsDev& f, const AdjArgs& a,
+                    hipStream_t st) {
+  if (cl == 0) launch_adj_s<8>(condense, m, cl, S, f, a, st);
+  else if (cl == 1) launch_adj_s<16>(condense, m, cl, S, f, a, st);
+  else launch_adj_s<24>(condense, m, cl, S, f, a, st);
+}
+
+template <int S>
+void launch_adj_fused_s(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+  const int groups = (a.NS + S - 1) / S;
+  const int64_t n_work = m->n_elem * groups;
+  auto kern = condense ? adj_sweep_fused_kernel<S, true> : adj_sweep_fused_kernel<S, false>;
+  static int per_cu[2] = {0, 0};
+  int& pc = per_cu[condense ? 0 : 1];
+  if (pc == 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, WT, 0) != hipSuccess) pc = 1;
+  const int64_t cap = (int64_t)(pc > 0 ? pc : 1) * sbfwi_device_cus();
+  const unsigned blocks = (unsigned)(n_work < cap ? n_work : cap);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(WT), 0, st, m->d.elem_by_cost, n_work, groups, m->d, f, a);
+}
+
+void launch_adj_fused(bool condense, int S, sbfwi_mesh_s* m, const FactorsDev& f, const AdjArgs& a,
+                      hipStream_t st) {
+  switch (S) {
+    case 1: launch_adj_fused_s<1>(condense, m, f, a, st); break;
+    case 2: launch_adj_fused_s<2>(condense, m, f, a, st); break;
+    case 4: launch_adj_fused_s<4>(condense, m, f, a, st); break;
+    case 8: launch_adj_fused_s<8>(condense, m, f, a, st); break;
+    default: launch_adj_fused_s<16>(condense, m, f, a, st); break;
+  }
+}
+
+// Transposed condense or recover over every element with the plan's shape choices.
+void launch_adj_plan(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const SweepPlan& plan,
+                     const AdjArgs& a, hipStream_t st) {
+  const int kind = condense ? SW_ADJ_CONDENSE : SW_ADJ_RECOVER;
+  if (plan.fusedS[kind] > 0) {
+    launch_adj_fused(condense, plan.fusedS[kind], m, f, a, st);
+    return;
+  }
+  const int def = sbfwi_default_shots_per_block(a.NS);
+  for (int cl = 0; cl < 3; ++cl)
+    launch_adj_cls(condense, m, cl, plan.S[kind][cl] > 0 ? plan.S[kind][cl] : def, f, a, st);
+}
+
+void launch_adj_sweep(bool condense, sbfwi_factors_s* fac, const AdjArgs& a, hipStream_t st) {
   ProfScope ps(condense ? PK_ADJ_CONDENSE : PK_ADJ_RECOVER, st);
-  if (a.NS >= 4)
-    launch_adj_all<4>(condense, m, f, a, st);
-  else if (a.NS >= 2)
-    launch_adj_all<2>(condense, m, f, a, st);
-  else
-    launch_adj_all<1>(condense, m, f, a, st);
+  launch_adj_plan(condense, fac->m, fac->d, fac->plan, a, st);
 }
 
 template <int NBT, int S>
@@ -594,7 +671,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
       const double* Fs = ck->full_store ? (kind == 0 ? ck->fstore : ck->vstore) + (k - 1) * m->n_params * NS
                                         : fseg + (k - k0 - 1) * m->n_params * NS;
       if (mode == SBFWI_GRAD_EXACT) {
-        launch_adj_sweep(true, m, f->d, a, st);
+        launch_adj_sweep(true, f, a, st);
         {
         ProfScope ps(PK_ADJ_RHS, st);
         hipLaunchKernelGGL(adj_rhs_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a, w.rhs, ck->n_rec,
@@ -602,7 +679,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         }
         SBFWI_HIP(hipGetLastError());
         SBFWI_CHECK(sbfwi_coarse_solve(f, &w.cw, 1, w.rhs, w.lamB, k, st));
-        launch_adj_sweep(false, m, f->d, a, st);
+        launch_adj_sweep(false, f, a, st);
         {
           ProfScope ps(PK_ADJ_NODAL, st);
           hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
@@ -660,4 +737,100 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   if (flags[0] & 4) return sbfwi_fail(SBFWI_ENONFINITE, "non-finite coarse residual at step %d", flags[1]);
   if (flags[0] & 2) return sbfwi_fail(SBFWI_ENOCONV, "coarse solve did not converge at step %d", flags[1]);
   return SBFWI_OK;
+}
+
+namespace {
+
+template <typename Fn>
+int time_launch(Fn&& fn, int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  fn();
+  SBFWI_HIP(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) fn();
+  SBFWI_HIP(hipEventRecord(e1, st));
+  SBFWI_HIP(hipEventSynchronize(e1));
+  SBFWI_HIP(hipGetLastError());
+  float t = 0.f;
+  SBFWI_HIP(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / reps;
+  return SBFWI_OK;
+}
+
+int tune_adj(sbfwi_factors_s* f, const AdjArgs& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double* out) {
+  sbfwi_mesh_s* m = f->m;
+  const int cands[5] = {1, 2, 4, 8, 16};
+  int smax = 1;
+  while (smax < a.NS) smax *= 2;
+  for (int kind = SW_ADJ_CONDENSE; kind <= SW_ADJ_RECOVER; ++kind) {
+    const bool cond = kind == SW_ADJ_CONDENSE;
+    double sum_best = 0.0;
+    for (int cl = 0; cl < 3; ++cl) {
+      f->plan.S[kind][cl] = 0;
+      if (m->h_class_elems[cl].empty()) continue;
+      float best = 1e30f;
+      int bs = 0;
+      for (int S : cands) {
+        if (S > smax) break;
+        float t = 0.f;
+        SBFWI_CHECK(time_launch([&] { launch_adj_cls(cond, m, cl, S, f->d, a, st); }, 3, st, e0, e1, &t));
+        if (t < best) { best = t; bs = S; }
+      }
+      f->plan.S[kind][cl] = bs;
+      sum_best += best;
+    }
+    float bestf = 1e30f;
+    int bfs = 0;
+    for (int S : cands) {
+      if (S > smax) break;
+      float t = 0.f;
+      SBFWI_CHECK(time_launch([&] { launch_adj_fused(cond, S, m, f->d, a, st); }, 3, st, e0, e1, &t));
+      if (t < bestf) { bestf = t; bfs = S; }
+    }
+    f->plan.fusedS[kind] = bestf < 0.97 * sum_best ? bfs : 0;
+    if (out) {
+      double* o = out + 6 * kind;
+      for (int cl = 0; cl < 3; ++cl) o[cl] = f->plan.S[kind][cl];
+      o[3] = f->plan.fusedS[kind];
+      o[4] = sum_best;
+      o[5] = bestf;
+    }
+  }
+  return SBFWI_OK;
+}
+
+}  // namespace
+
+int sbfwi_tune_adj_sweeps(sbfwi_factors_s* f, int NS, hipStream_t st, double* out) {
+  sbfwi_mesh_s* m = f->m;
+  AdjWork w;
+  AdjArgs a;
+  a.NS = NS;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int64_t ni = m->n_int * NS, nn = m->n_nodes * NS;
+  int rc = sbfwi_alloc(&w.seeds, 3 * ni + 3 * nn);
+  if (rc == SBFWI_OK) rc = sbfwi_alloc(&w.z, ni);
+  if (rc == SBFWI_OK) rc = sbfwi_alloc(&w.gB, m->n_loop * NS);
+  if (rc == SBFWI_OK) rc = sbfwi_alloc(&w.pl, m->n_loop * NS);
+  if (rc == SBFWI_OK) rc = sbfwi_alloc(&w.lamB, nn);
+  if (rc == SBFWI_OK) rc = sbfwi_alloc(&w.lam, m->n_x * NS);
+  if (rc == SBFWI_OK) {
+    a.ub = w.seeds; a.vb = a.ub + ni; a.ab = a.vb + ni;
+    a.UB = a.ab + ni; a.VB = a.UB + nn; a.AB = a.VB + nn;
+    a.z = w.z; a.gB = w.gB; a.pl = w.pl; a.lamB = w.lamB; a.lam = w.lam;
+    // zero inputs: the timings do not depend on the values
+    bool ok = hipMemsetAsync(w.seeds, 0, sizeof(double) * (3 * ni + 3 * nn), st) == hipSuccess;
+    ok = ok && hipMemsetAsync(w.z, 0, sizeof(double) * ni, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(w.gB, 0, sizeof(double) * m->n_loop * NS, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(w.pl, 0, sizeof(double) * m->n_loop * NS, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(w.lamB, 0, sizeof(double) * nn, st) == hipSuccess;
+    ok = ok && hipMemsetAsync(w.lam, 0, sizeof(double) * m->n_x * NS, st) == hipSuccess;
+    if (!ok) rc = sbfwi_fail(SBFWI_EHIP, "memset failed");
+  }
+  if (rc == SBFWI_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = sbfwi_fail(SBFWI_EHIP, "event creation failed");
+  if (rc == SBFWI_OK) rc = tune_adj(f, a, st, e0, e1, out);
+  (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  adj_free(&w);
+  return rc;
 }

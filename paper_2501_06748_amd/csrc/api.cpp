@@ -72,16 +72,53 @@ extern "C" int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter) {
   return SBFWI_OK;
 }
 
+int sbfwi_device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 1;
+  }
+  return cus;
+}
+
+static bool valid_shots_per_block(int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16; }
+
 extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
   if (!f) return sbfwi_fail(SBFWI_EINVAL, "NULL factors");
-  switch (param) {
-    case 0:
-      if (value < 1 || value > 1000) return sbfwi_fail(SBFWI_EINVAL, "enqueued iterations must be in 1..1000");
-      f->enqueued_iters = value;
-      return SBFWI_OK;
-    default:
-      return sbfwi_fail(SBFWI_EINVAL, "unknown launch parameter %d", param);
+  if (param == 0) {
+    if (value < 1 || value > 1000) return sbfwi_fail(SBFWI_EINVAL, "enqueued iterations must be in 1..1000");
+    f->enqueued_iters = value;
+    return SBFWI_OK;
   }
+  if (param == 1) {
+    if (value != 0 && value != 1) return sbfwi_fail(SBFWI_EINVAL, "graph replay flag must be 0 or 1");
+    f->use_graphs = value;
+    return SBFWI_OK;
+  }
+  if (param == 2) {
+    f->plan = SweepPlan();
+    return SBFWI_OK;
+  }
+  if (param >= 10 && param < 10 + 3 * SW_N) {
+    if (!valid_shots_per_block(value)) return sbfwi_fail(SBFWI_EINVAL, "shots per block must be 0, 1, 2, 4, 8 or 16");
+    f->plan.S[(param - 10) / 3][(param - 10) % 3] = value;
+    return SBFWI_OK;
+  }
+  if (param >= 30 && param < 30 + SW_N) {
+    if (!valid_shots_per_block(value)) return sbfwi_fail(SBFWI_EINVAL, "shots per block must be 0, 1, 2, 4, 8 or 16");
+    f->plan.fusedS[param - 30] = value;
+    return SBFWI_OK;
+  }
+  return sbfwi_fail(SBFWI_EINVAL, "unknown launch parameter %d", param);
+}
+
+extern "C" int sbfwi_autotune(sbfwi_factors f, int n_shots, double* host_out, hipStream_t s) {
+  if (!f) return sbfwi_fail(SBFWI_EINVAL, "NULL factors");
+  if (n_shots <= 0 || n_shots > 16) return sbfwi_fail(SBFWI_EINVAL, "n_shots must be in 1..16");
+  SBFWI_CHECK(sbfwi_tune_step_sweeps(f, n_shots, s, host_out));
+  return sbfwi_tune_adj_sweeps(f, n_shots, s, host_out);
 }
 
 extern "C" int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* dst) {
@@ -195,10 +232,16 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
   src.node_stride = 1;
   src.amp = wavelet;
   src.amp_steps = n_steps;
+  const bool graphs = f->use_graphs && !(ck && ck->full_store);
+  if (graphs) SBFWI_CHECK(sbfwi_graph_step_reset(&w, 1, s));
   for (int64_t k = 1; k <= n_steps; ++k) {
     double *xs = nullptr, *fs = nullptr, *vs = nullptr;
     if (ck && !ck->full_store && (k - 1) % ck->interval == 0)
       SBFWI_CHECK(sbfwi_state_copy(m, &w, ck->states + ((k - 1) / ck->interval) * ssz, 1, s));
+    if (graphs) {
+      SBFWI_CHECK(sbfwi_forward_step_graph(f, &w, src, n_rec, rec_node, traces, n_steps, s));
+      continue;
+    }
     if (ck && ck->full_store) {
       xs = ck->xstore + (k - 1) * m->n_x * n_shots;
       fs = ck->fstore + (k - 1) * m->n_params * n_shots;
@@ -234,9 +277,19 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
   }
   sbfwi_ckpt_s* ck = n_ckpt != 0 ? new sbfwi_ckpt_s() : nullptr;
   StepWork w;
-  int rc = forward_run(f, n_shots, n_steps, src_node, wavelet, n_rec, rec_node, traces, n_ckpt, ck, s, w);
-  (void)hipStreamSynchronize(s);
+  // graph replay needs a stream that can be captured: the run goes to a
+  // library stream (default priority) ordered after the caller's work
+  hipStream_t rs = s;
+  hipStream_t own = nullptr;
+  if (f->use_graphs) {
+    SBFWI_HIP(hipStreamSynchronize(s));
+    SBFWI_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    rs = own;
+  }
+  int rc = forward_run(f, n_shots, n_steps, src_node, wavelet, n_rec, rec_node, traces, n_ckpt, ck, rs, w);
+  (void)hipStreamSynchronize(rs);
   sbfwi_step_work_free(&w);
+  if (own) (void)hipStreamDestroy(own);
   if (rc != SBFWI_OK) {
     ckpt_free(ck);
     return rc;

@@ -58,9 +58,12 @@ struct SolveArgs {
   double rtol;
   int* status;         // [0] flags (2 no convergence, 4 non-finite), [1] step, [2] last, [3] max, [4] total iterations, [5] solves
   int64_t step;
+  const int64_t* step_ptr;  // when set, the step number is read here (graph replays)
 };
 
 enum { SLOT_A = 0, SLOT_X = 1, SLOT_V = 2, SLOT_T = 3 };
+
+__device__ __forceinline__ int step_of(const SolveArgs& a) { return (int)(a.step_ptr ? *a.step_ptr : a.step); }
 
 // y = K x for the row of this thread's lane group and all shots, from the
 // sliced ELL layout: chunk c of a slice holds entries k = c*LPR .. c*LPR+LPR-1
@@ -308,7 +311,7 @@ __device__ bool phase_v(const SolveArgs& a, Shared& L) {
         L.sc[SC_ACTIVE][s] = 0.0;
         if (blockIdx.x == 0) {
           atomicOr(&a.status[0], 4);
-          atomicCAS(&a.status[1], -1, (int)a.step);
+          atomicCAS(&a.status[1], -1, step_of(a));
         }
       } else if (rn2 <= tol2 * L.sc[SC_BN2][s]) {
         L.sc[SC_ACTIVE][s] = 0.0;
@@ -316,7 +319,7 @@ __device__ bool phase_v(const SolveArgs& a, Shared& L) {
         L.sc[SC_ACTIVE][s] = 0.0;
         if (blockIdx.x == 0) {
           atomicOr(&a.status[0], 2);
-          atomicCAS(&a.status[1], -1, (int)a.step);
+          atomicCAS(&a.status[1], -1, step_of(a));
         }
       } else {
         L.sc[SC_ALPHA][s] = rho / wp;
@@ -555,36 +558,41 @@ __global__ void __launch_bounds__(CT) k_finish(SolveArgs a) {
   atomicAdd(&a.status[5], 1);
   if (unconverged) {
     atomicOr(&a.status[0], 2);
-    atomicCAS(&a.status[1], -1, (int)a.step);
+    atomicCAS(&a.status[1], -1, step_of(a));
   }
 }
 
+// parts: 1 = start-up and the enqueued iterations, 2 = the rescue kernel,
+// 4 = the final check (a captured graph holds parts 1 and 4; the cooperative
+// rescue launch runs between its replays)
 template <int NSM>
-hipError_t enqueue(const SolveArgs& a, int iters, int max_more, unsigned blocks, hipStream_t s) {
-  {
-    ProfScope ps(PK_SOLVE_INIT, s);
-    hipLaunchKernelGGL(k_init1<NSM>, dim3(blocks), dim3(CT), 0, s, a);
-    hipLaunchKernelGGL(k_init2<NSM>, dim3(blocks), dim3(CT), 0, s, a);
-  }
-  for (int i = 0; i < iters; ++i) {
+hipError_t enqueue(const SolveArgs& a, int iters, int max_more, unsigned blocks, int parts, hipStream_t s) {
+  if (parts & 1) {
     {
-      ProfScope ps(PK_SOLVE_V, s);
-      hipLaunchKernelGGL(k_phase_v<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+      ProfScope ps(PK_SOLVE_INIT, s);
+      hipLaunchKernelGGL(k_init1<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+      hipLaunchKernelGGL(k_init2<NSM>, dim3(blocks), dim3(CT), 0, s, a);
     }
-    {
-      ProfScope ps(PK_SOLVE_T, s);
-      hipLaunchKernelGGL(k_phase_t<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+    for (int i = 0; i < iters; ++i) {
+      {
+        ProfScope ps(PK_SOLVE_V, s);
+        hipLaunchKernelGGL(k_phase_v<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+      }
+      {
+        ProfScope ps(PK_SOLVE_T, s);
+        hipLaunchKernelGGL(k_phase_t<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+      }
+      ProfScope ps(PK_SOLVE_X, s);
+      hipLaunchKernelGGL(k_phase_x<NSM>, dim3(blocks), dim3(CT), 0, s, a);
     }
-    ProfScope ps(PK_SOLVE_X, s);
-    hipLaunchKernelGGL(k_phase_x<NSM>, dim3(blocks), dim3(CT), 0, s, a);
   }
-  if (max_more > 0) {
+  if ((parts & 2) && max_more > 0) {
     SolveArgs b = a;
     void* args[] = {&b, &max_more};
     hipError_t e = hipLaunchCooperativeKernel((const void*)k_rescue<NSM>, dim3(blocks), dim3(CT), args, 0, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_finish<NSM>, dim3(blocks), dim3(CT), 0, s, a);
+  if (parts & 4) hipLaunchKernelGGL(k_finish<NSM>, dim3(blocks), dim3(CT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -640,6 +648,11 @@ void sbfwi_coarse_work_free(CoarseWork* w) {
 
 int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b, double* x,
                        int64_t step, hipStream_t s) {
+  return sbfwi_coarse_solve_parts(f, w, transpose, b, x, step, nullptr, 7, s);
+}
+
+int sbfwi_coarse_solve_parts(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b, double* x,
+                             int64_t step, const int64_t* step_ptr, int parts, hipStream_t s) {
   sbfwi_mesh_s* m = f->m;
   SolveArgs a;
   a.n = m->n_nodes;
@@ -661,16 +674,17 @@ int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
   a.rtol = f->rtol;
   a.status = f->d.status;
   a.step = step;
+  a.step_ptr = step_ptr;
   const int iters = f->enqueued_iters < f->max_iter ? f->enqueued_iters : f->max_iter;
   const int more = f->max_iter - iters;
   const unsigned blocks = (unsigned)w->nblocks;
   ProfScope ps(PK_SOLVE, s);
   hipError_t e;
-  if (a.NS == 1) e = enqueue<1>(a, iters, more, blocks, s);
-  else if (a.NS == 2) e = enqueue<2>(a, iters, more, blocks, s);
-  else if (a.NS <= 4) e = enqueue<4>(a, iters, more, blocks, s);
-  else if (a.NS <= 8) e = enqueue<8>(a, iters, more, blocks, s);
-  else e = enqueue<16>(a, iters, more, blocks, s);
+  if (a.NS == 1) e = enqueue<1>(a, iters, more, blocks, parts, s);
+  else if (a.NS == 2) e = enqueue<2>(a, iters, more, blocks, parts, s);
+  else if (a.NS <= 4) e = enqueue<4>(a, iters, more, blocks, parts, s);
+  else if (a.NS <= 8) e = enqueue<8>(a, iters, more, blocks, parts, s);
+  else e = enqueue<16>(a, iters, more, blocks, parts, s);
   if (e != hipSuccess) return sbfwi_fail(SBFWI_EHIP, "coarse solve launch: %s", hipGetErrorString(e));
   return SBFWI_OK;
 }

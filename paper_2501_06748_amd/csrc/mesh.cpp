@@ -44,6 +44,7 @@ static int upload_mesh(sbfwi_mesh_s* m, const std::vector<int64_t>& loop_nodes,
   SBFWI_CHECK(sbfwi_upload(&m->d.contrib_ptr, cptr));
   SBFWI_CHECK(sbfwi_upload(&m->d.contrib_src, csrc));
   for (int c = 0; c < 3; ++c) SBFWI_CHECK(sbfwi_upload(&m->class_elems[c], m->h_class_elems[c]));
+  SBFWI_CHECK(sbfwi_upload(&m->d.elem_by_cost, m->h_elem_by_cost));
   // sliced ELL layout of the coarse pattern: slices of ELL_SLICE rows, each
   // padded to its widest row rounded up to ELL_LPR entries; chunk c of a slice
   // stores entries k = c*ELL_LPR .. c*ELL_LPR + ELL_LPR-1 of every row, row-major
@@ -89,7 +90,7 @@ void sbfwi_mesh_free(sbfwi_mesh_s* m) {
   void* ptrs[] = {d.nb, d.nr, d.loop_off, d.par_off, d.int_off, d.x_off, d.finv_off,
                   d.dense_off, d.loop_nodes, d.loop_xy, d.centre, d.node_ptr, d.node_slot,
                   d.row_ptr, d.col, d.diag_idx, d.tr_idx, d.contrib_ptr, d.contrib_src,
-                  d.ell_off, d.ell_w, d.ell_col, d.ell_pos,
+                  d.ell_off, d.ell_w, d.ell_col, d.ell_pos, d.elem_by_cost,
                   m->class_elems[0], m->class_elems[1], m->class_elems[2]};
   for (void* p : ptrs) sbfwi_dev_free(p);
   delete m;
@@ -269,10 +270,18 @@ extern "C" int sbfwi_build_mesh(const double* node_xy, int64_t n_nodes, const in
     for (int64_t t = 0; t < m->n_dense; ++t) csrc[fill[entry_of[t]]++] = t;
   }
   m->n_contrib = m->n_dense;
-  for (int64_t e = 0; e < n_elem; ++e) {
+  // elements by decreasing sweep cost N_r n_b^2 (ties by index): the blocks of
+  // a launch are dispatched roughly in index order, so long sweeps start first
+  std::vector<int32_t> by_cost(n_elem);
+  for (int64_t e = 0; e < n_elem; ++e) by_cost[e] = (int32_t)e;
+  std::stable_sort(by_cost.begin(), by_cost.end(), [&](int32_t x, int32_t y) {
+    return (int64_t)m->h_nr[x] * m->h_nb[x] * m->h_nb[x] > (int64_t)m->h_nr[y] * m->h_nb[y] * m->h_nb[y];
+  });
+  for (int32_t e : by_cost) {
     int c = m->h_nb[e] <= 8 ? 0 : (m->h_nb[e] <= 16 ? 1 : 2);
-    m->h_class_elems[c].push_back((int32_t)e);
+    m->h_class_elems[c].push_back(e);
   }
+  m->h_elem_by_cost = by_cost;
   m->d.n_nodes = n_nodes;
   m->d.n_elem = n_elem;
   m->d.n_loop = m->n_loop;

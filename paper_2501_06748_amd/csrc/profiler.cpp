@@ -59,8 +59,12 @@ hipEvent_t take() {
 
 }  // namespace
 
+static int g_suspended = 0;
+
+void sbfwi_prof_suspend(int on) { g_suspended = on; }
+
 ProfScope::ProfScope(int id, hipStream_t s) : id_(id), s_(s) {
-  if (!(g_prof.mask & (1u << id))) return;
+  if (g_suspended || !(g_prof.mask & (1u << id))) return;
   a_ = take();
   if (a_ && hipEventRecord((hipEvent_t)a_, s) != hipSuccess) a_ = nullptr;
 }

@@ -37,6 +37,7 @@ struct MeshDev {
   int64_t* loop_nodes = nullptr;
   double* loop_xy = nullptr;     // [n_loop][2]
   double* centre = nullptr;      // [n_elem][2]
+  int32_t* elem_by_cost = nullptr;  // [n_elem] elements by decreasing N_r n_b^2 (persistent sweeps)
   int64_t* node_ptr = nullptr;   // [n_nodes+1] -> node_slot
   int64_t* node_slot = nullptr;  // loop slots (loop_off[e] + i) that touch each node
   int64_t* row_ptr = nullptr;    // coarse CSR
@@ -66,6 +67,7 @@ struct sbfwi_mesh_s {
   std::vector<int64_t> h_loop_off, h_par_off, h_int_off, h_x_off, h_finv_off, h_dense_off;
   std::vector<int64_t> h_row_ptr, h_col64;
   std::vector<int32_t> h_class_elems[3];
+  std::vector<int32_t> h_elem_by_cost;
   MeshDev d;
   int32_t* class_elems[3] = {nullptr, nullptr, nullptr};   // elements with nb <= 8, 16, 24
 };
@@ -95,12 +97,26 @@ struct FactorsDev {
   int* status = nullptr;       // device status words
 };
 
+// Launch plan of the sweep kernels: shots per block (1, 2, 4, 8 or 16) for each
+// n_b class (n_b <= 8, <= 16, <= 24) of each sweep, or (fusedS > 0) one
+// persistent launch over all classes with fusedS shots per block.  Zero
+// entries take the default for the run's shot count.
+enum { SW_CONDENSE = 0, SW_RECOVER = 1, SW_ADJ_CONDENSE = 2, SW_ADJ_RECOVER = 3, SW_N = 4 };
+struct SweepPlan {
+  int S[SW_N][3] = {};
+  int fusedS[SW_N] = {};
+};
+inline int sbfwi_default_shots_per_block(int NS) { return NS >= 4 ? 4 : (NS >= 2 ? 2 : 1); }
+int sbfwi_device_cus();
+
 struct sbfwi_factors_s {
   sbfwi_mesh_s* m = nullptr;
   double c = 0, dt = 0, beta = 0, gamma = 0;
   double rtol = 1e-13;
   int max_iter = 500;
   int enqueued_iters = 13;       // BiCGStab iterations enqueued per solve (more run in a rescue kernel)
+  int use_graphs = 0;            // forward runs replay each time step from HIP graphs
+  SweepPlan plan;
   int64_t bytes = 0;
   FactorsDev d;
 };
@@ -129,6 +145,7 @@ enum {
 };
 // Brackets the launches made during its lifetime with events on stream s when
 // kernel id is enabled by sbfwi_profile.
+void sbfwi_prof_suspend(int on);   // no events are recorded while suspended (graph capture)
 struct ProfScope {
   ProfScope(int id, hipStream_t s);
   ~ProfScope();
@@ -192,6 +209,11 @@ void sbfwi_coarse_work_free(CoarseWork* w);
 // sides; x holds the initial guess on entry.  Records failures in f->status.
 int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b,
                        double* x, int64_t step, hipStream_t s);
+// The same in parts (bit 1: start-up and enqueued iterations, bit 2: the
+// cooperative rescue kernel, bit 4: final check); step_ptr (device, may be
+// NULL) overrides step when failures are recorded.
+int sbfwi_coarse_solve_parts(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b,
+                             double* x, int64_t step, const int64_t* step_ptr, int parts, hipStream_t s);
 
 struct StepWork {
   int NS = 0;
@@ -200,6 +222,9 @@ struct StepWork {
   double* corr = nullptr;                               // predictor correction of the coarse solve
   double *q = nullptr, *yn = nullptr, *fhat = nullptr, *F = nullptr, *Unew = nullptr;
   CoarseWork cw;
+  // graph replay of a time step: device step counter and the two captured halves
+  int64_t* kdev = nullptr;
+  hipGraphExec_t g_pre = nullptr, g_post = nullptr;
 };
 int sbfwi_step_work_alloc(StepWork* w, sbfwi_mesh_s* m, int NS);
 void sbfwi_step_work_free(StepWork* w);
@@ -224,7 +249,23 @@ int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceT
                        int n_rec, const int64_t* rec_node, double* traces, int64_t n_steps,
                        double* xs, double* fs, int field_kind, hipStream_t s, double* vs = nullptr);
 int sbfwi_state_copy(sbfwi_mesh_s* m, StepWork* w, double* dst, int to_store, hipStream_t s);
+// Graph replay of forward steps (no per-step stores): the first call captures
+// the step on stream s (which must not be the null stream) into two graphs
+// around the coarse solve's cooperative rescue launch; every call replays one
+// step, whose number is kept on the device (set by sbfwi_graph_step_reset).
+int sbfwi_graph_step_reset(StepWork* w, int64_t k, hipStream_t s);
+int sbfwi_forward_step_graph(sbfwi_factors_s* f, StepWork* w, const SourceTable& src, int n_rec,
+                             const int64_t* rec_node, double* traces, int64_t n_steps, hipStream_t s);
 int sbfwi_step_zero(sbfwi_mesh_s* m, StepWork* w, hipStream_t s);
+
+// Autotuning of the sweep launch plans (step.hip: condense / recover,
+// adjoint.hip: transposed condense / recover) for runs of NS shots: every
+// candidate is timed on the factors with zero state and the fastest kept in
+// f->plan.  out (host, may be NULL) receives per sweep kind: the chosen S of
+// the three classes, the fused S (0 = per-class launches), and the best time
+// in ms of the per-class and of the fused variants.
+int sbfwi_tune_step_sweeps(sbfwi_factors_s* f, int NS, hipStream_t s, double* out);
+int sbfwi_tune_adj_sweeps(sbfwi_factors_s* f, int NS, hipStream_t s, double* out);
 
 int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_src, int mode,
                        double* grad, hipStream_t s);

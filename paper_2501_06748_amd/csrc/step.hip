@@ -16,6 +16,8 @@
 //   u_j = q_j - phi~_j^-1 (psi~_j u_{j+1})   (j = n-1 .. 0),
 // the paper's u_j = phi~_j^-1 (p~_j - psi~_j u_{j+1}); then the Newmark update of
 // velocity and acceleration at every level (eq. Newmark).
+#include <functional>
+
 #include "sbfwi_internal.h"
 
 namespace {
@@ -76,11 +78,8 @@ __device__ __forceinline__ double dense_mv(const double* F, const double* vec, i
 }
 
 template <int NBT, int S>
-__global__ void __launch_bounds__(WT) condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                      FactorsDev f, StepArgs a) {
-  __shared__ StepLds<NBT, S> L;
-  const int e = elems[blockIdx.x];
-  const int s0 = blockIdx.y * S;
+__device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
+                                              const StepArgs& a, StepLds<NBT, S>& L) {
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e];
@@ -148,11 +147,8 @@ __global__ void __launch_bounds__(WT) condense_kernel(const int32_t* __restrict_
 }
 
 template <int NBT, int S>
-__global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                     FactorsDev f, StepArgs a) {
-  __shared__ StepLds<NBT, S> L;
-  const int e = elems[blockIdx.x];
-  const int s0 = blockIdx.y * S;
+__device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
+                                             const StepArgs& a, StepLds<NBT, S>& L) {
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e], xo = m.x_off[e];
@@ -254,13 +250,64 @@ __global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__
   }
 }
 
+// Device step counter of graph replays.
+__global__ void set_step_kernel(int64_t* kdev, int64_t k) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *kdev = k;
+}
+
+__global__ void advance_step_kernel(int64_t* kdev) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *kdev = *kdev + 1;
+}
+
+// One block per (element of an n_b class, group of S shots).
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                      FactorsDev f, StepArgs a) {
+  __shared__ StepLds<NBT, S> L;
+  condense_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+}
+
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                     FactorsDev f, StepArgs a) {
+  __shared__ StepLds<NBT, S> L;
+  recover_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+}
+
+// One persistent launch over all n_b classes: the blocks walk the work items
+// (element, group of S shots) in order of decreasing cost (N_r n_b^2), item
+// w = blockIdx.x + i gridDim.x; each item runs the body of its element's class
+// in a shared LDS buffer sized for the largest class.
+template <int S, bool CONDENSE>
+__global__ void __launch_bounds__(WT) sweep_fused_kernel(const int32_t* __restrict__ order, int64_t n_work,
+                                                         int groups, MeshDev m, FactorsDev f, StepArgs a) {
+  __shared__ StepLds<24, S> L;
+  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int e = order[w / groups];
+    const int s0 = (int)(w % groups) * S;
+    const int nb = m.nb[e];
+    if (nb <= 8) {
+      auto& Ls = *reinterpret_cast<StepLds<8, S>*>(&L);
+      if (CONDENSE) condense_body<8, S>(e, s0, m, f, a, Ls); else recover_body<8, S>(e, s0, m, f, a, Ls);
+    } else if (nb <= 16) {
+      auto& Ls = *reinterpret_cast<StepLds<16, S>*>(&L);
+      if (CONDENSE) condense_body<16, S>(e, s0, m, f, a, Ls); else recover_body<16, S>(e, s0, m, f, a, Ls);
+    } else {
+      if (CONDENSE) condense_body<24, S>(e, s0, m, f, a, L); else recover_body<24, S>(e, s0, m, f, a, L);
+    }
+    __syncthreads();
+  }
+}
+
 // F = sum of element sources gathered over node -> slot + point sources;
 // Unew = initial guess of the coarse solve: the predictor u + dt v + dt^2/2 a
 // plus the correction the previous step needed on top of its own predictor.
 __global__ void rhs_kernel(MeshDev m, int NS, const double* __restrict__ fhat, double* __restrict__ F,
                            const double* __restrict__ U, const double* __restrict__ V,
                            const double* __restrict__ A, double* __restrict__ Unew,
-                           const double* __restrict__ corr, double dt, SourceTable src, int64_t k) {
+                           const double* __restrict__ corr, double dt, SourceTable src, int64_t k,
+                           const int64_t* __restrict__ kdev) {
+  if (kdev) k = *kdev;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= m.n_nodes * NS) return;
   int64_t node = g / NS;
@@ -283,7 +330,8 @@ __global__ void nodal_kernel(int64_t n_nodes, int NS, FactorsDev f, const double
                              double* __restrict__ U, double* __restrict__ V, double* __restrict__ A,
                              double* __restrict__ corr,
                              int n_rec, const int64_t* __restrict__ rec_node, double* __restrict__ traces,
-                             int64_t n_steps, int64_t k) {
+                             int64_t n_steps, int64_t k, const int64_t* __restrict__ kdev) {
+  if (kdev) k = *kdev;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = n_nodes * NS;
   if (g < nn) {
@@ -312,21 +360,56 @@ void launch_cr(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, cons
     hipLaunchKernelGGL((recover_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
 }
 
-template <int S>
-void launch_all(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
-  launch_cr<8, S>(condense, m, 0, f, a, st);
-  launch_cr<16, S>(condense, m, 1, f, a, st);
-  launch_cr<24, S>(condense, m, 2, f, a, st);
+template <int NBT>
+void launch_cr_s(bool condense, sbfwi_mesh_s* m, int cl, int S, const FactorsDev& f, const StepArgs& a,
+                 hipStream_t st) {
+  switch (S) {
+    case 1: launch_cr<NBT, 1>(condense, m, cl, f, a, st); break;
+    case 2: launch_cr<NBT, 2>(condense, m, cl, f, a, st); break;
+    case 4: launch_cr<NBT, 4>(condense, m, cl, f, a, st); break;
+    case 8: launch_cr<NBT, 8>(condense, m, cl, f, a, st); break;
+    default: launch_cr<NBT, 16>(condense, m, cl, f, a, st); break;
+  }
 }
 
-void launch_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
+template <int S>
+void launch_fused(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
+  const int groups = (a.NS + S - 1) / S;
+  const int64_t n_work = m->n_elem * groups;
+  auto kern = condense ? sweep_fused_kernel<S, true> : sweep_fused_kernel<S, false>;
+  static int per_cu[2] = {0, 0};
+  int& pc = per_cu[condense ? 0 : 1];
+  if (pc == 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, WT, 0) != hipSuccess) pc = 1;
+  const int64_t cap = (int64_t)(pc > 0 ? pc : 1) * sbfwi_device_cus();
+  const unsigned blocks = (unsigned)(n_work < cap ? n_work : cap);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(WT), 0, st, m->d.elem_by_cost, n_work, groups, m->d, f, a);
+}
+
+// Condense or recover over every element, with the shots-per-block choice of
+// the plan for each n_b class (or its single persistent launch).
+void launch_step_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const SweepPlan& plan,
+                             const StepArgs& a, hipStream_t st) {
+  const int kind = condense ? SW_CONDENSE : SW_RECOVER;
+  const int fs = plan.fusedS[kind];
+  if (fs > 0) {
+    switch (fs) {
+      case 1: launch_fused<1>(condense, m, f, a, st); break;
+      case 2: launch_fused<2>(condense, m, f, a, st); break;
+      case 4: launch_fused<4>(condense, m, f, a, st); break;
+      case 8: launch_fused<8>(condense, m, f, a, st); break;
+      default: launch_fused<16>(condense, m, f, a, st); break;
+    }
+    return;
+  }
+  const int def = sbfwi_default_shots_per_block(a.NS);
+  launch_cr_s<8>(condense, m, 0, plan.S[kind][0] > 0 ? plan.S[kind][0] : def, f, a, st);
+  launch_cr_s<16>(condense, m, 1, plan.S[kind][1] > 0 ? plan.S[kind][1] : def, f, a, st);
+  launch_cr_s<24>(condense, m, 2, plan.S[kind][2] > 0 ? plan.S[kind][2] : def, f, a, st);
+}
+
+void launch_sweep(bool condense, sbfwi_factors_s* fac, const StepArgs& a, hipStream_t st) {
   ProfScope ps(condense ? PK_CONDENSE : PK_RECOVER, st);
-  if (a.NS >= 4)
-    launch_all<4>(condense, m, f, a, st);
-  else if (a.NS == 3 || a.NS == 2)
-    launch_all<2>(condense, m, f, a, st);
-  else
-    launch_all<1>(condense, m, f, a, st);
+  launch_step_sweep(condense, fac->m, fac->d, fac->plan, a, st);
 }
 
 }  // namespace
@@ -350,6 +433,7 @@ int sbfwi_step_work_alloc(StepWork* w, sbfwi_mesh_s* m, int NS) {
   SBFWI_CHECK(sbfwi_alloc(&w->F, nn));
   SBFWI_CHECK(sbfwi_alloc(&w->Unew, nn));
   SBFWI_CHECK(sbfwi_coarse_work_alloc(&w->cw, m->n_nodes, NS));
+  SBFWI_CHECK(sbfwi_alloc(&w->kdev, 1));
   return SBFWI_OK;
 }
 
@@ -361,6 +445,9 @@ void sbfwi_step_work_free(StepWork* w) {
   sbfwi_dev_free(w->F);
   sbfwi_dev_free(w->Unew);
   sbfwi_coarse_work_free(&w->cw);
+  sbfwi_dev_free(w->kdev);
+  if (w->g_pre) (void)hipGraphExecDestroy(w->g_pre);
+  if (w->g_post) (void)hipGraphExecDestroy(w->g_post);
   *w = StepWork();
 }
 
@@ -378,32 +465,203 @@ int sbfwi_state_copy(sbfwi_mesh_s* m, StepWork* w, double* dst, int to_store, hi
   return SBFWI_OK;
 }
 
-int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceTable& src, int n_rec,
-                       const int64_t* rec_node, double* traces, int64_t n_steps, double* xs, double* fs,
-                       int field_kind, hipStream_t st, double* vs) {
-  sbfwi_mesh_s* m = f->m;
+namespace {
+
+StepArgs step_args(StepWork* w, double* xs, double* fs, int field_kind, double* vs) {
   StepArgs a;
   a.NS = w->NS;
   a.u = w->u; a.v = w->v; a.a = w->a;
   a.U = w->U; a.V = w->V; a.A = w->A;
   a.q = w->q; a.yn = w->yn; a.fhat = w->fhat; a.Unew = w->Unew;
   a.xs = xs; a.fs = fs; a.field_kind = field_kind; a.vs = vs;
-  launch_sweep(true, m, f->d, a, st);
+  return a;
+}
+
+// condense, gather of the coarse right-hand side and initial guess
+int step_pre(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, const int64_t* kdev,
+             const SourceTable& src, hipStream_t st) {
+  sbfwi_mesh_s* m = f->m;
+  launch_sweep(true, f, a, st);
   int64_t nn = m->n_nodes * w->NS;
   {
-  ProfScope ps(PK_RHS, st);
-  hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, m->d, w->NS, w->fhat,
-                     w->F, w->U, w->V, w->A, w->Unew, w->corr, f->dt, src, k);
+    ProfScope ps(PK_RHS, st);
+    hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, m->d, w->NS, w->fhat,
+                       w->F, w->U, w->V, w->A, w->Unew, w->corr, f->dt, src, k, kdev);
   }
-  SBFWI_HIP(hipGetLastError());
-  SBFWI_CHECK(sbfwi_coarse_solve(f, &w->cw, 0, w->F, w->Unew, k, st));
-  int64_t tot = nn + (int64_t)n_rec * w->NS;
-  {
-  ProfScope ps(PK_NODAL, st);
-  hipLaunchKernelGGL(nodal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m->n_nodes, w->NS,
-                     f->d, w->Unew, w->U, w->V, w->A, w->corr, n_rec, rec_node, traces, n_steps, k);
-  }
-  launch_sweep(false, m, f->d, a, st);
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;
+}
+
+// nodal Newmark update, receivers, recover
+int step_post(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, const int64_t* kdev, int n_rec,
+              const int64_t* rec_node, double* traces, int64_t n_steps, hipStream_t st) {
+  sbfwi_mesh_s* m = f->m;
+  int64_t nn = m->n_nodes * w->NS;
+  int64_t tot = nn + (int64_t)n_rec * w->NS;
+  {
+    ProfScope ps(PK_NODAL, st);
+    hipLaunchKernelGGL(nodal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m->n_nodes, w->NS,
+                       f->d, w->Unew, w->U, w->V, w->A, w->corr, n_rec, rec_node, traces, n_steps, k, kdev);
+  }
+  launch_sweep(false, f, a, st);
+  SBFWI_HIP(hipGetLastError());
+  return SBFWI_OK;
+}
+
+int capture(hipStream_t st, hipGraphExec_t* out, const std::function<int()>& body) {
+  hipGraph_t g = nullptr;
+  SBFWI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  sbfwi_prof_suspend(1);
+  int rc = body();
+  sbfwi_prof_suspend(0);
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc != SBFWI_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return sbfwi_fail(SBFWI_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return sbfwi_fail(SBFWI_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+  return SBFWI_OK;
+}
+
+}  // namespace
+
+int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceTable& src, int n_rec,
+                       const int64_t* rec_node, double* traces, int64_t n_steps, double* xs, double* fs,
+                       int field_kind, hipStream_t st, double* vs) {
+  const StepArgs a = step_args(w, xs, fs, field_kind, vs);
+  SBFWI_CHECK(step_pre(f, w, a, k, nullptr, src, st));
+  SBFWI_CHECK(sbfwi_coarse_solve(f, &w->cw, 0, w->F, w->Unew, k, st));
+  return step_post(f, w, a, k, nullptr, n_rec, rec_node, traces, n_steps, st);
+}
+
+int sbfwi_graph_step_reset(StepWork* w, int64_t k, hipStream_t st) {
+  hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, w->kdev, k);
+  SBFWI_HIP(hipGetLastError());
+  return SBFWI_OK;
+}
+
+int sbfwi_forward_step_graph(sbfwi_factors_s* f, StepWork* w, const SourceTable& src, int n_rec,
+                             const int64_t* rec_node, double* traces, int64_t n_steps, hipStream_t st) {
+  const StepArgs a = step_args(w, nullptr, nullptr, 0, nullptr);
+  if (!w->g_pre) {
+    SBFWI_CHECK(capture(st, &w->g_pre, [&]() -> int {
+      SBFWI_CHECK(step_pre(f, w, a, 0, w->kdev, src, st));
+      return sbfwi_coarse_solve_parts(f, &w->cw, 0, w->F, w->Unew, 0, w->kdev, 1, st);
+    }));
+    SBFWI_CHECK(capture(st, &w->g_post, [&]() -> int {
+      SBFWI_CHECK(sbfwi_coarse_solve_parts(f, &w->cw, 0, w->F, w->Unew, 0, w->kdev, 4, st));
+      SBFWI_CHECK(step_post(f, w, a, 0, w->kdev, n_rec, rec_node, traces, n_steps, st));
+      hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, w->kdev);
+      SBFWI_HIP(hipGetLastError());
+      return SBFWI_OK;
+    }));
+  }
+  SBFWI_HIP(hipGraphLaunch(w->g_pre, st));
+  SBFWI_CHECK(sbfwi_coarse_solve_parts(f, &w->cw, 0, w->F, w->Unew, 0, w->kdev, 2, st));
+  SBFWI_HIP(hipGraphLaunch(w->g_post, st));
+  return SBFWI_OK;
+}
+
+namespace {
+
+// Average time in ms of reps launches (after one untimed launch) on stream st.
+template <typename Fn>
+int time_launch(Fn&& fn, int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  fn();
+  SBFWI_HIP(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) fn();
+  SBFWI_HIP(hipEventRecord(e1, st));
+  SBFWI_HIP(hipEventSynchronize(e1));
+  SBFWI_HIP(hipGetLastError());
+  float t = 0.f;
+  SBFWI_HIP(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / reps;
+  return SBFWI_OK;
+}
+
+void launch_cls(bool condense, sbfwi_mesh_s* m, int cl, int S, const FactorsDev& f, const StepArgs& a,
+                hipStream_t st) {
+  if (cl == 0) launch_cr_s<8>(condense, m, cl, S, f, a, st);
+  else if (cl == 1) launch_cr_s<16>(condense, m, cl, S, f, a, st);
+  else launch_cr_s<24>(condense, m, cl, S, f, a, st);
+}
+
+void launch_fused_s(bool condense, int S, sbfwi_mesh_s* m, const FactorsDev& f, const StepArgs& a,
+                    hipStream_t st) {
+  switch (S) {
+    case 1: launch_fused<1>(condense, m, f, a, st); break;
+    case 2: launch_fused<2>(condense, m, f, a, st); break;
+    case 4: launch_fused<4>(condense, m, f, a, st); break;
+    case 8: launch_fused<8>(condense, m, f, a, st); break;
+    default: launch_fused<16>(condense, m, f, a, st); break;
+  }
+}
+
+int tune_step(sbfwi_factors_s* f, StepWork& w, int NS, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double* out) {
+  sbfwi_mesh_s* m = f->m;
+  StepArgs a;
+  a.NS = NS;
+  a.u = w.u; a.v = w.v; a.a = w.a;
+  a.U = w.U; a.V = w.V; a.A = w.A;
+  a.q = w.q; a.yn = w.yn; a.fhat = w.fhat; a.Unew = w.Unew;
+  a.xs = nullptr; a.fs = nullptr; a.field_kind = 0; a.vs = nullptr;
+  const int cands[5] = {1, 2, 4, 8, 16};
+  int smax = 1;
+  while (smax < NS) smax *= 2;
+  for (int kind = SW_CONDENSE; kind <= SW_RECOVER; ++kind) {
+    const bool cond = kind == SW_CONDENSE;
+    double sum_best = 0.0;
+    for (int cl = 0; cl < 3; ++cl) {
+      f->plan.S[kind][cl] = 0;
+      if (m->h_class_elems[cl].empty()) continue;
+      float best = 1e30f;
+      int bs = 0;
+      for (int S : cands) {
+        if (S > smax) break;
+        float t = 0.f;
+        SBFWI_CHECK(time_launch([&] { launch_cls(cond, m, cl, S, f->d, a, st); }, 3, st, e0, e1, &t));
+        if (t < best) { best = t; bs = S; }
+      }
+      f->plan.S[kind][cl] = bs;
+      sum_best += best;
+    }
+    float bestf = 1e30f;
+    int bfs = 0;
+    for (int S : cands) {
+      if (S > smax) break;
+      float t = 0.f;
+      SBFWI_CHECK(time_launch([&] { launch_fused_s(cond, S, m, f->d, a, st); }, 3, st, e0, e1, &t));
+      if (t < bestf) { bestf = t; bfs = S; }
+    }
+    // the single persistent launch is kept only when clearly faster
+    f->plan.fusedS[kind] = bestf < 0.97 * sum_best ? bfs : 0;
+    if (out) {
+      double* o = out + 6 * kind;
+      for (int cl = 0; cl < 3; ++cl) o[cl] = f->plan.S[kind][cl];
+      o[3] = f->plan.fusedS[kind];
+      o[4] = sum_best;
+      o[5] = bestf;
+    }
+  }
+  return SBFWI_OK;
+}
+
+}  // namespace
+
+int sbfwi_tune_step_sweeps(sbfwi_factors_s* f, int NS, hipStream_t st, double* out) {
+  StepWork w;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = sbfwi_step_work_alloc(&w, f->m, NS);
+  if (rc == SBFWI_OK) rc = sbfwi_step_zero(f->m, &w, st);
+  if (rc == SBFWI_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = sbfwi_fail(SBFWI_EHIP, "event creation failed");
+  if (rc == SBFWI_OK) rc = tune_step(f, w, NS, st, e0, e1, out);
+  (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  sbfwi_step_work_free(&w);
+  return rc;
 }

@@ -17,11 +17,11 @@ from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, near
 from .models import (fine_point_positions, homogeneous, smoothed_voids,
                      smooth_random_field, seeded_ellipses, seeded_circle)
 from .signals import ricker, sine_burst
-from .configs import config_tiny, config_paper, config_small, config_quadtree_tiny, Workload
+from .configs import config_tiny, config_paper, config_small, config_quadtree_tiny, config_quadtree, Workload
 
 __all__ = [
     "Mesh", "uniform_rect_mesh", "quadtree_mesh", "top_edge_nodes", "nearest_top_node",
     "fine_point_positions", "homogeneous", "smoothed_voids", "smooth_random_field",
     "seeded_ellipses", "seeded_circle", "ricker", "sine_burst",
-    "config_tiny", "config_paper", "config_small", "config_quadtree_tiny", "Workload",
+    "config_tiny", "config_paper", "config_small", "config_quadtree_tiny", "config_quadtree", "Workload",
 ]

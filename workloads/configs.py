@@ -8,6 +8,11 @@
   edge.
 * ``config_small``  -- a reduced plate used by parity tests at sizes that
   span several tiles and a ragged tail.
+* ``config_quadtree`` -- the 0.1 x 0.05 m plate as a quadtree refined from
+  level 4 (3.125 mm cells) to level 8 around three seeded voids: about 6200
+  elements with hanging nodes (n_b 8 .. 14), N_r proportional to the cell
+  size (16 .. 64), 16 shots on the top edge, 32 receivers as in
+  ``config_paper``.
 
 Every model is sampled on the fine grid (one density per element, radial
 level and boundary node).  Seeds are 1000 * config_index + item_index.
@@ -126,3 +131,24 @@ def config_quadtree_tiny(n_steps: int = 40) -> Workload:
         "random30": smooth_random_field(pts, 3 * 1000 + 1, 2700.0, 0.3, wavelength=0.006),
     }
     return Workload("quadtree-tiny", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models)
+
+
+def config_quadtree(n_steps: int = 4000, n_shots: int = 16) -> Workload:
+    """Batching workload: ragged quadtree plate, many shots."""
+    lx, ly = 0.1, 0.05
+    voids = seeded_ellipses(2 * 1000 + 0, 3, (lx, ly), 0.002, 0.006, 0.004)
+    centres = [(v[0], v[1]) for v in voids]
+    mesh = quadtree_mesh(lx, ly, base_level=4, max_level=8, refine_centres=centres, refine_radius=0.01,
+                         n_b_max=24, n_r_max=64, n_r_min=16)
+    xs = [lx * (k + 0.5) / n_shots for k in range(n_shots)]
+    src = np.asarray([nearest_top_node(mesh, x) for x in xs], dtype=np.int64)
+    rec = np.asarray([nearest_top_node(mesh, lx * (k + 0.5) / 32) for k in range(32)], dtype=np.int64)
+    dt, f0 = 2e-8, 5e5
+    wav = np.repeat(ricker(n_steps, dt, f0)[None, :], n_shots, axis=0)
+    pts = fine_point_positions(mesh)
+    models = {
+        "homogeneous": homogeneous(mesh, 2700.0),
+        "voids_floor_half": smoothed_voids(pts, voids, 2700.0, 0.5, ly / 2 ** 8 / 16),
+        "random30": smooth_random_field(pts, 2 * 1000 + 1, 2700.0, 0.3),
+    }
+    return Workload("quadtree-l4-l8-3voids", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models)
