@@ -52,12 +52,17 @@ enum {
 
 enum { SBFWI_SCHEME_PAPER_FD = 0 };
 enum { SBFWI_GRAD_EXACT = 0, SBFWI_GRAD_PAPER_KERNEL = 1 };
+/* Flag OR-ed into the gradient mode: one gradient (and one misfit) per shot. */
+enum { SBFWI_GRAD_PER_SHOT = 16 };
 
 /* Message of the last failure on this thread ("" if none). */
 const char* sbfwi_last_error(void);
 
-/* Optional device allocator for handle internals (NULL, NULL restores hipMalloc/hipFree).
- * alloc(bytes, ctx) returns device memory or NULL; free(ptr, ctx) releases it. */
+/* Optional device allocator for handle internals and work buffers (NULL, NULL
+ * restores hipMalloc/hipFree).  alloc(bytes, ctx) returns device memory or NULL;
+ * free(ptr, ctx) releases it.  It is called on the thread that makes the library
+ * call.  Every block is released by the allocator that made it, also after the
+ * registration has changed.  Thread-safe. */
 int sbfwi_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx),
                         void (*free_fn)(void* ptr, void* ctx), void* ctx);
 
@@ -129,6 +134,18 @@ int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
 int sbfwi_set_launch(sbfwi_factors f, int param, int value);
 
 /*
+ * Device-memory footprint, in bytes, of a run on mesh m with n_shots shots,
+ * n_steps steps and n_ckpt as in sbfwi_forward (an upper bound of what the
+ * library allocates): host_out[0] the factors of one model, [1] the checkpoint
+ * store kept between sbfwi_forward and the end of sbfwi_adjoint, [2] the work
+ * buffers of the forward run, [3] the work buffers of the backward pass (0 if
+ * n_ckpt = 0; the residual of sbfwi_gradient counted with at most 64 receivers
+ * per shot).  A forward + gradient run needs [1] + max([2], [3]) on top of the
+ * factors.  For admission control by a caller that shares the device.
+ */
+int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int n_ckpt, int64_t* host_out);
+
+/*
  * Autotuner of the sweep launch plan for runs of n_shots shots on these factors:
  * for every sweep kind and n_b class, each shots-per-block choice (1 .. 16, up to the
  * shot count rounded up to a power of two) is timed on the factors with zero state,
@@ -196,7 +213,9 @@ int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps,
  *           velocities at every fine-grid point; the back-propagated field is
  *           the forward scheme driven by the time-reversed adj_src at the
  *           receivers; sign -1 so that it points along the exact gradient).
- *   grad    device [n_params], overwritten with the sum over shots.
+ *           With SBFWI_GRAD_PER_SHOT or-ed in, every shot gets its own gradient.
+ *   grad    device [n_params], overwritten with the sum over shots; with
+ *           SBFWI_GRAD_PER_SHOT: [n_shots][n_params], one gradient per shot.
  * Synchronises s at the end.
  */
 int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_src, int mode,
@@ -207,7 +226,8 @@ int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_src, int mod
  * into misfit[0] (device), and its gradient via sbfwi_adjoint with
  * adj_src = dt (traces - observed).
  *   observed, traces device [n_shots][n_rec][n_steps] (traces from the run that
- *   made ck).
+ *   made ck).  With SBFWI_GRAD_PER_SHOT in mode, misfit holds n_shots values
+ *   (one per shot) and grad [n_shots][n_params].
  */
 int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
                    const double* traces, int mode, double* misfit, double* grad,

@@ -24,6 +24,7 @@ from ._abi import SbfwiError, check, lib
 SCHEME_PAPER_FD = 0
 GRAD_EXACT = 0
 GRAD_PAPER_KERNEL = 1
+GRAD_PER_SHOT = 16
 
 
 def _stream(stream):
@@ -135,6 +136,13 @@ def sbfwi_set_launch(f: FactorsHandle, param: int, value: int):
     check(lib().sbfwi_set_launch(f, int(param), int(value)))
 
 
+def sbfwi_plan_bytes(m: MeshHandle, n_shots: int, n_steps: int, n_ckpt: int = -1) -> dict:
+    out = np.zeros(4, dtype=np.int64)
+    check(lib().sbfwi_plan_bytes(m, int(n_shots), int(n_steps), int(n_ckpt), out.ctypes.data_as(C.c_void_p)))
+    return {"factors": int(out[0]), "checkpoints": int(out[1]), "forward_work": int(out[2]),
+            "backward_work": int(out[3])}
+
+
 def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
     """Times the sweep launch shapes for runs of n_shots shots and keeps the fastest plan."""
     out = np.zeros(24, dtype=np.float64)
@@ -186,14 +194,29 @@ def sbfwi_forward(f: FactorsHandle, src_node, wavelet, rec_node, traces, n_ckpt=
     return CkptHandle(out.value, f) if n_ckpt != 0 else None
 
 
+def _check_grad_shapes(f, n_shots, mode, grad, misfit=None):
+    n_params = sbfwi_mesh_info(f.mesh)["n_params"]
+    per = n_shots if (int(mode) & GRAD_PER_SHOT) else 1
+    if grad.numel() != per * n_params:
+        raise ValueError(f"grad must hold {per} x {n_params} values")
+    if misfit is not None and misfit.numel() < per:
+        raise ValueError(f"misfit must hold {per} values")
+
+
 def sbfwi_adjoint(f: FactorsHandle, ck: CkptHandle, adj_src, mode, grad, stream=None):
+    """adj_src [S, R, N_t] f64 (device); grad [n_params] or, with GRAD_PER_SHOT, [S, n_params]."""
     import torch
+    _check_grad_shapes(f, int(adj_src.shape[0]), mode, grad)
     check(lib().sbfwi_adjoint(f, ck, _dptr(adj_src, torch.float64, "adj_src"), int(mode),
                               _dptr(grad, torch.float64, "grad"), _stream(stream)))
 
 
 def sbfwi_gradient(f: FactorsHandle, ck: CkptHandle, observed, traces, mode, misfit, grad, stream=None):
+    """observed, traces [S, R, N_t]; misfit [1] (or [S] with GRAD_PER_SHOT); grad as in sbfwi_adjoint."""
     import torch
+    if observed.shape != traces.shape:
+        raise ValueError("observed and traces must have the same shape")
+    _check_grad_shapes(f, int(traces.shape[0]), mode, grad, misfit)
     check(lib().sbfwi_gradient(f, ck, _dptr(observed, torch.float64, "observed"),
                                _dptr(traces, torch.float64, "traces"), int(mode),
                                _dptr(misfit, torch.float64, "misfit"), _dptr(grad, torch.float64, "grad"),
@@ -237,4 +260,5 @@ def sbfwi_factors_info(f: FactorsHandle) -> dict:
 
 
 __all__ = [n for n in dir() if n.startswith("sbfwi_")] + ["SbfwiError", "MeshHandle", "FactorsHandle",
-                                                          "CkptHandle", "GRAD_EXACT", "GRAD_PAPER_KERNEL"]
+                                                          "CkptHandle", "GRAD_EXACT", "GRAD_PAPER_KERNEL",
+                                                          "GRAD_PER_SHOT"]

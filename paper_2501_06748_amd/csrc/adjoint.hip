@@ -26,6 +26,8 @@
 // matrices with respect to the nodal densities of each level (eq. Es is
 // linear in the densities); every thread owns one fine-grid parameter and
 // sums over shots, so the accumulation is deterministic.
+#include <atomic>
+
 #include "sbfwi_internal.h"
 
 namespace {
@@ -325,7 +327,7 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
                                                         FactorsDev f, int NS, const double* __restrict__ X,
                                                         const double* __restrict__ lam,
                                                         const double* __restrict__ acc_a,
-                                                        double* __restrict__ grad, int s0) {
+                                                        double* __restrict__ grad, int s0, int64_t shot_stride) {
   __shared__ GradLds<NBT, S> L;
   const int e = elems[blockIdx.x];
   const int ns = min(S, NS - s0);
@@ -427,10 +429,17 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
       L.g[it] = s < ns ? acc : 0.0;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nb; k += WT) {
-      double t = 0.0;
-      for (int s = 0; s < S; ++s) t += L.g[k * S + s];
-      grad[po + (int64_t)lev * nb + k] += t;
+    if (shot_stride == 0) {   // summed over the shots of the run
+      for (int k = threadIdx.x; k < nb; k += WT) {
+        double t = 0.0;
+        for (int s = 0; s < S; ++s) t += L.g[k * S + s];
+        grad[po + (int64_t)lev * nb + k] += t;
+      }
+    } else {                  // one gradient per shot
+      for (int it = threadIdx.x; it < items; it += WT) {
+        const int k = it / S, s = it % S;
+        if (s < ns) grad[(s0 + s) * shot_stride + po + (int64_t)lev * nb + k] += L.g[it];
+      }
     }
     __syncthreads();
   }
@@ -439,7 +448,7 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
 // Paper kernel: g -= dt * sum_s v~ v at every fine-grid point.
 __global__ void grad_paper_kernel(MeshDev m, int NS, double dt, int64_t n_params, const int32_t* __restrict__ par_elem,
                                   const double* __restrict__ vint, const double* __restrict__ Vnod,
-                                  const double* __restrict__ vf, double* __restrict__ grad) {
+                                  const double* __restrict__ vf, double* __restrict__ grad, int per_shot) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_params) return;
   const int e = par_elem[p];
@@ -451,9 +460,12 @@ __global__ void grad_paper_kernel(MeshDev m, int NS, double dt, int64_t n_params
   for (int s = 0; s < NS; ++s) {
     double vl = lev < n ? vint[(m.int_off[e] + (int64_t)lev * nb + k) * NS + s]
                         : Vnod[m.loop_nodes[m.loop_off[e] + k] * NS + s];
-    g += vl * vf[p * NS + s];
+    if (per_shot)
+      grad[s * n_params + p] -= dt * (vl * vf[p * NS + s]);
+    else
+      g += vl * vf[p * NS + s];
   }
-  grad[p] -= dt * g;
+  if (!per_shot) grad[p] -= dt * g;
 }
 
 __global__ void misfit_kernel(const double* __restrict__ tr, const double* __restrict__ ob, int64_t count,
@@ -510,9 +522,12 @@ void launch_adj_fused_s(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, con
   const int groups = (a.NS + S - 1) / S;
   const int64_t n_work = m->n_elem * groups;
   auto kern = condense ? adj_sweep_fused_kernel<S, true> : adj_sweep_fused_kernel<S, false>;
-  static int per_cu[2] = {0, 0};
-  int& pc = per_cu[condense ? 0 : 1];
-  if (pc == 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, WT, 0) != hipSuccess) pc = 1;
+  static std::atomic<int> per_cu[2] = {0, 0};   // occupancy, queried once per kernel
+  int pc = per_cu[condense ? 0 : 1].load();
+  if (pc == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, WT, 0) != hipSuccess || pc <= 0) pc = 1;
+    per_cu[condense ? 0 : 1].store(pc);
+  }
   const int64_t cap = (int64_t)(pc > 0 ? pc : 1) * sbfwi_device_cus();
   const unsigned blocks = (unsigned)(n_work < cap ? n_work : cap);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(WT), 0, st, m->d.elem_by_cost, n_work, groups, m->d, f, a);
@@ -549,31 +564,32 @@ void launch_adj_sweep(bool condense, sbfwi_factors_s* fac, const AdjArgs& a, hip
 
 template <int NBT, int S>
 void launch_grad_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, int NS, const double* X, const double* lam,
-                     const double* acc, double* grad, hipStream_t st) {
+                     const double* acc, double* grad, int64_t stride, hipStream_t st) {
   int64_t cnt = (int64_t)m->h_class_elems[cl].size();
   if (cnt == 0) return;
   // shot groups run one after another on the stream, so every gradient entry
   // has a single writer at a time and the sum over shots is deterministic
   for (int s0 = 0; s0 < NS; s0 += S)
     hipLaunchKernelGGL((grad_exact_kernel<NBT, S>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl], m->d,
-                       f, NS, X, lam, acc, grad, s0);
+                       f, NS, X, lam, acc, grad, s0, stride);
 }
 
 template <int S>
 void launch_grad_all(sbfwi_mesh_s* m, const FactorsDev& f, int NS, const double* X, const double* lam,
-                     const double* acc, double* grad, hipStream_t st) {
-  launch_grad_cls<8, S>(m, 0, f, NS, X, lam, acc, grad, st);
-  launch_grad_cls<16, S>(m, 1, f, NS, X, lam, acc, grad, st);
-  launch_grad_cls<24, S>(m, 2, f, NS, X, lam, acc, grad, st);
+                     const double* acc, double* grad, int64_t stride, hipStream_t st) {
+  launch_grad_cls<8, S>(m, 0, f, NS, X, lam, acc, grad, stride, st);
+  launch_grad_cls<16, S>(m, 1, f, NS, X, lam, acc, grad, stride, st);
+  launch_grad_cls<24, S>(m, 2, f, NS, X, lam, acc, grad, stride, st);
 }
 
+// stride 0: gradient summed over shots; stride n_params: one gradient per shot
 void launch_grad(sbfwi_mesh_s* m, const FactorsDev& f, int NS, const double* X, const double* lam,
-                 const double* acc, double* grad, hipStream_t st) {
+                 const double* acc, double* grad, int64_t stride, hipStream_t st) {
   ProfScope ps(PK_GRAD_EXACT, st);
-  if (NS <= 1) launch_grad_all<1>(m, f, NS, X, lam, acc, grad, st);
-  else if (NS <= 2) launch_grad_all<2>(m, f, NS, X, lam, acc, grad, st);
-  else if (NS <= 4) launch_grad_all<4>(m, f, NS, X, lam, acc, grad, st);
-  else launch_grad_all<8>(m, f, NS, X, lam, acc, grad, st);
+  if (NS <= 1) launch_grad_all<1>(m, f, NS, X, lam, acc, grad, stride, st);
+  else if (NS <= 2) launch_grad_all<2>(m, f, NS, X, lam, acc, grad, stride, st);
+  else if (NS <= 4) launch_grad_all<4>(m, f, NS, X, lam, acc, grad, stride, st);
+  else launch_grad_all<8>(m, f, NS, X, lam, acc, grad, stride, st);
 }
 
 struct AdjWork {
@@ -617,7 +633,9 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
       for (int64_t p = m->h_par_off[e]; p < m->h_par_off[e + 1]; ++p) pe[p] = (int32_t)e;
     SBFWI_CHECK(sbfwi_upload(&w.par_elem, pe));
   }
-  SBFWI_HIP(hipMemsetAsync(grad, 0, sizeof(double) * m->n_params, st));
+  const int per_shot = (mode & SBFWI_GRAD_PER_SHOT) ? 1 : 0;
+  mode &= ~SBFWI_GRAD_PER_SHOT;
+  SBFWI_HIP(hipMemsetAsync(grad, 0, sizeof(double) * m->n_params * (per_shot ? NS : 1), st));
   SourceTable fsrc;
   fsrc.n_src = 1;
   fsrc.node = ck->src_node;
@@ -684,14 +702,14 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
           ProfScope ps(PK_ADJ_NODAL, st);
           hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
         }
-        launch_grad(m, f->d, NS, X, (const double*)w.lam, Fs, grad, st);
+        launch_grad(m, f->d, NS, X, (const double*)w.lam, Fs, grad, per_shot ? m->n_params : 0, st);
         SBFWI_HIP(hipGetLastError());
       } else {
         const int64_t kp = N + 1 - k;  // back-propagation step paired with forward step k
         SBFWI_CHECK(sbfwi_forward_step(f, &bw, kp, bsrc, 0, nullptr, nullptr, N, nullptr, nullptr, 0, st));
         ProfScope ps(PK_GRAD_PAPER, st);
         hipLaunchKernelGGL(grad_paper_kernel, dim3(gp), dim3(256), 0, st, m->d, NS, f->dt, m->n_params,
-                           w.par_elem, (const double*)bw.v, (const double*)bw.V, Fs, grad);
+                           w.par_elem, (const double*)bw.v, (const double*)bw.V, Fs, grad, per_shot);
         SBFWI_HIP(hipGetLastError());
       }
     }

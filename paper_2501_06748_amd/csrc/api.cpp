@@ -1,17 +1,29 @@
 // Exported C ABI: argument checks, handle lifetimes, the forward driver with
 // checkpointing, and error reporting.  Every computation runs in the HIP
 // kernels of factor.hip, step.hip, coarse.hip and adjoint.hip.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 #include "sbfwi_internal.h"
 
 static thread_local char g_err[1024] = "";
-static void* (*g_alloc)(size_t, void*) = nullptr;
-static void (*g_free)(void*, void*) = nullptr;
-static void* g_alloc_ctx = nullptr;
+
+// The registered allocator, and for every live allocation the deallocator of
+// the allocator that made it (so that switching allocators while handles are
+// alive frees each block where it came from).
+struct Allocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+static std::mutex g_alloc_mu;
+static Allocator g_allocator;
+static std::unordered_map<void*, Allocator> g_owner;
 
 int sbfwi_fail(int code, const char* fmt, ...) {
   va_list ap;
@@ -22,19 +34,38 @@ int sbfwi_fail(int code, const char* fmt, ...) {
 }
 
 void* sbfwi_dev_alloc(size_t bytes) {
-  if (g_alloc) return g_alloc(bytes, g_alloc_ctx);
+  Allocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_allocator;
+  }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  if (a.alloc) {
+    p = a.alloc(bytes, a.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
-    return nullptr;
+    p = nullptr;
+  }
+  if (p) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_owner[p] = a;
   }
   return p;
 }
 
 void sbfwi_dev_free(void* p) {
   if (!p) return;
-  if (g_free)
-    g_free(p, g_alloc_ctx);
+  Allocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_owner.find(p);
+    if (it != g_owner.end()) {
+      a = it->second;
+      g_owner.erase(it);
+    }
+  }
+  if (a.free)
+    a.free(p, a.ctx);
   else
     (void)hipFree(p);
 }
@@ -46,9 +77,10 @@ extern "C" const char* sbfwi_last_error(void) { return g_err; }
 extern "C" int sbfwi_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
   if ((alloc_fn == nullptr) != (free_fn == nullptr))
     return sbfwi_fail(SBFWI_EINVAL, "allocator and deallocator must be given together");
-  g_alloc = alloc_fn;
-  g_free = free_fn;
-  g_alloc_ctx = ctx;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_allocator.alloc = alloc_fn;
+  g_allocator.free = free_fn;
+  g_allocator.ctx = ctx;
   return SBFWI_OK;
 }
 
@@ -73,12 +105,14 @@ extern "C" int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter) {
 }
 
 int sbfwi_device_cus() {
-  static int cus = 0;
+  static std::atomic<int> cached{0};
+  int cus = cached.load();
   if (cus == 0) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 1;
+    cached.store(cus);
   }
   return cus;
 }
@@ -112,6 +146,42 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
     return SBFWI_OK;
   }
   return sbfwi_fail(SBFWI_EINVAL, "unknown launch parameter %d", param);
+}
+
+extern "C" int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int n_ckpt, int64_t* out) {
+  if (!m || !out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  if (n_shots <= 0 || n_shots > 16 || n_steps <= 0 || n_ckpt < -1)
+    return sbfwi_fail(SBFWI_EINVAL, "bad shot, step or checkpoint count");
+  const int64_t NS = n_shots;
+  const int64_t n_slices = (m->n_nodes + ELL_SLICE - 1) / ELL_SLICE;
+  // the allocations of factor.hip, step.hip, coarse.hip, adjoint.hip and api.cpp
+  const int64_t factors = 8 * (m->n_finv + 9 * m->n_params + 9 * m->n_loop + 6 * m->n_dense + 32 * m->n_loop +
+                               2 * m->nnz + 2 * m->d.n_ell + m->n_nodes) + 32;
+  const int64_t coarse = 8 * (9 * m->n_nodes * NS + 4 * n_slices * 3 * NS + 3 * 11 * 16) +
+                         4 * (64 + 32 * (n_slices / 16 + 2));
+  const int64_t state = 8 * sbfwi_state_size(m, (int)NS);
+  const int64_t fwd_work = state + 8 * NS * (m->n_int + 2 * m->n_loop + 2 * m->n_nodes) + coarse + 8;
+  int64_t ckpt = 8 * NS * n_steps + 16 * NS + 8 * 64;   // copies of sources, wavelets, receivers (bounded)
+  int64_t interval = 1;
+  if (n_ckpt >= n_steps) {
+    ckpt += 8 * n_steps * (m->n_x + 2 * m->n_params) * NS;
+  } else if (n_ckpt != 0) {
+    int64_t cnt = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)n_steps));
+    interval = (n_steps + cnt - 1) / cnt;
+    ckpt += ((n_steps + interval - 1) / interval) * state;
+  }
+  int64_t bwd = 0;
+  if (n_ckpt != 0) {
+    bwd = 8 * NS * (3 * m->n_int + 3 * m->n_nodes + m->n_int + 2 * m->n_loop + 2 * m->n_nodes + m->n_x) +
+          coarse + 4 * m->n_params;
+    if (n_ckpt < n_steps) bwd += fwd_work + 8 * interval * NS * (m->n_x + m->n_params);
+    bwd += 8 * NS * n_steps * 64;   // residual of sbfwi_gradient, receivers bounded by 64 per shot
+  }
+  out[0] = factors;
+  out[1] = ckpt;
+  out[2] = fwd_work;
+  out[3] = bwd;
+  return SBFWI_OK;
 }
 
 extern "C" int sbfwi_autotune(sbfwi_factors f, int n_shots, double* host_out, hipStream_t s) {
@@ -302,7 +372,8 @@ extern "C" int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_s
                              hipStream_t s) {
   if (!f || !ck || !adj_src || !grad) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   if (ck->f != f) return sbfwi_fail(SBFWI_EINVAL, "checkpoints belong to other factors");
-  if (mode != SBFWI_GRAD_EXACT && mode != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
+  const int base = mode & ~SBFWI_GRAD_PER_SHOT;
+  if (base != SBFWI_GRAD_EXACT && base != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
   return sbfwi_adjoint_impl(f, ck, adj_src, mode, grad, s);
 }
 
@@ -312,7 +383,14 @@ extern "C" int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* obse
   int64_t count = (int64_t)ck->n_shots * ck->n_rec * ck->n_steps;
   double* res = nullptr;
   SBFWI_CHECK(sbfwi_alloc(&res, count));
-  int rc = sbfwi_misfit_residual(traces, observed, count, f->dt, res, misfit, s);
+  int rc = SBFWI_OK;
+  if (mode & SBFWI_GRAD_PER_SHOT) {
+    const int64_t per = (int64_t)ck->n_rec * ck->n_steps;
+    for (int q = 0; q < ck->n_shots && rc == SBFWI_OK; ++q)
+      rc = sbfwi_misfit_residual(traces + q * per, observed + q * per, per, f->dt, res + q * per, misfit + q, s);
+  } else {
+    rc = sbfwi_misfit_residual(traces, observed, count, f->dt, res, misfit, s);
+  }
   if (rc == SBFWI_OK) rc = sbfwi_adjoint(f, ck, res, mode, grad, s);
   (void)hipStreamSynchronize(s);
   sbfwi_dev_free(res);

@@ -27,6 +27,8 @@
 // (rhat = r_0 fixed for the solve), (rhat, K phat) = (w, phat) and
 // (rhat, K shat) = (w, shat) are formed together with phat and shat, and
 // rho_{i+1} = (rhat, s) - omega (w, shat) = (rhat, r_{i+1}).
+#include <atomic>
+
 #include "sbfwi_internal.h"
 
 namespace {
@@ -599,15 +601,15 @@ hipError_t enqueue(const SolveArgs& a, int iters, int max_more, unsigned blocks,
 // largest grid whose blocks can all be resident at once (the rescue kernel needs it)
 template <int NSM>
 int coresident_blocks() {
-  static int cached = 0;
-  if (cached == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  static std::atomic<int> cached{0};   // queried once (host threads may race benignly)
+  int c = cached.load();
+  if (c == 0) {
+    int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rescue<NSM>, CT, 0) != hipSuccess) return 0;
-    cached = per * cus;
+    c = per * sbfwi_device_cus();
+    cached.store(c);
   }
-  return cached;
+  return c;
 }
 
 }  // namespace

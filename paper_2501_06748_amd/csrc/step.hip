@@ -16,6 +16,7 @@
 //   u_j = q_j - phi~_j^-1 (psi~_j u_{j+1})   (j = n-1 .. 0),
 // the paper's u_j = phi~_j^-1 (p~_j - psi~_j u_{j+1}); then the Newmark update of
 // velocity and acceleration at every level (eq. Newmark).
+#include <atomic>
 #include <functional>
 
 #include "sbfwi_internal.h"
@@ -377,9 +378,12 @@ void launch_fused(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const Ste
   const int groups = (a.NS + S - 1) / S;
   const int64_t n_work = m->n_elem * groups;
   auto kern = condense ? sweep_fused_kernel<S, true> : sweep_fused_kernel<S, false>;
-  static int per_cu[2] = {0, 0};
-  int& pc = per_cu[condense ? 0 : 1];
-  if (pc == 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, WT, 0) != hipSuccess) pc = 1;
+  static std::atomic<int> per_cu[2] = {0, 0};   // occupancy, queried once per kernel
+  int pc = per_cu[condense ? 0 : 1].load();
+  if (pc == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, WT, 0) != hipSuccess || pc <= 0) pc = 1;
+    per_cu[condense ? 0 : 1].store(pc);
+  }
   const int64_t cap = (int64_t)(pc > 0 ? pc : 1) * sbfwi_device_cus();
   const unsigned blocks = (unsigned)(n_work < cap ? n_work : cap);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(WT), 0, st, m->d.elem_by_cost, n_work, groups, m->d, f, a);
