@@ -23,7 +23,8 @@ from dataclasses import dataclass
 import torch
 from torch.autograd.function import once_differentiable
 
-from . import (GRAD_EXACT, sbfwi_adjoint, sbfwi_factor_elements, sbfwi_forward, sbfwi_mesh_info)
+from . import (GRAD_EXACT, sbfwi_adjoint, sbfwi_factor_elements, sbfwi_forward, sbfwi_mesh_info,
+               sbfwi_set_solver)
 
 
 @dataclass
@@ -32,7 +33,8 @@ class WaveProblem:
 
     mesh: handle from sbfwi_build_mesh; src [S] int64, wavelet [S, N_t] f64,
     rec [R] int64; n_ckpt as in sbfwi_forward (-1 = sqrt(T) checkpoints,
-    >= N_t = full storage); mode: GRAD_EXACT or GRAD_PAPER_KERNEL."""
+    >= N_t = full storage); mode: GRAD_EXACT or GRAD_PAPER_KERNEL; rtol: relative
+    residual of the coarse solves (the library default 1e-13 when None)."""
     mesh: object
     c: float
     dt: float
@@ -43,6 +45,7 @@ class WaveProblem:
     gamma: float = 0.5
     n_ckpt: int = -1
     mode: int = GRAD_EXACT
+    rtol: float = None
 
     @property
     def n_params(self) -> int:
@@ -57,6 +60,8 @@ class _Traces(torch.autograd.Function):
     def forward(ctx, rho, prob):
         rho_d = rho.detach().contiguous()
         f = sbfwi_factor_elements(prob.mesh, rho_d, prob.c, prob.dt, prob.beta, prob.gamma)
+        if prob.rtol is not None:
+            sbfwi_set_solver(f, prob.rtol, 500)
         traces = torch.zeros(prob.trace_shape(), dtype=torch.float64, device=rho.device)
         need = ctx.needs_input_grad[0]
         ck = sbfwi_forward(f, prob.src, prob.wavelet, prob.rec, traces, n_ckpt=prob.n_ckpt if need else 0)

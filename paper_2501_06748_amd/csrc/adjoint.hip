@@ -311,7 +311,10 @@ __global__ void adj_nodal_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a) {
 // live in rolling LDS windows; for every level m the band entries of the
 // sensitivities E-bar of E0, E1, E2 (and lambda_m a_m^T for M0) are formed per
 // item (i, s), then contracted with the per-segment density derivatives alpha
-// and summed over the shots of the group.
+// (staged in LDS once per element) and summed over the shots of the group.
+// The global loads of the next level's X, lambda and a are issued before the
+// current level is computed and land in the windows after it, so the level
+// recursion does not wait on memory.
 template <int NBT, int S>
 struct GradLds {
   double X[5][NBT * S];
@@ -320,6 +323,7 @@ struct GradLds {
   double E[3][3][NBT * S];   // [tau][sub, diag, super][item]
   double M[3][NBT * S];
   double g[NBT * S];
+  double gb[NBT * 32];       // alpha of the element's segments
 };
 
 template <int NBT, int S>
@@ -328,6 +332,7 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
                                                         const double* __restrict__ lam,
                                                         const double* __restrict__ acc_a,
                                                         double* __restrict__ grad, int s0, int64_t shot_stride) {
+  constexpr int IPT = (NBT * S + WT - 1) / WT;   // items per thread
   __shared__ GradLds<NBT, S> L;
   const int e = elems[blockIdx.x];
   const int ns = min(S, NS - s0);
@@ -337,16 +342,34 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
   const int items = nb * S;
   auto xs = [&](int l) { return (l + 2) % 5; };
   auto ls = [&](int r) { return (r + 1) % 3; };
-  auto load_x = [&](int l) {
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      L.X[xs(l)][it] = s < ns ? X[(xo + (int64_t)(l + 1) * nb + i) * NS + s0 + s] : 0.0;
+  // registers of the prefetched level
+  double px[IPT], pl[IPT], pa[IPT];
+  auto fetch_x = [&](int l) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = it / S, s = it % S;
+      px[u] = (it < items && s < ns) ? X[(xo + (int64_t)(l + 1) * nb + i) * NS + s0 + s] : 0.0;
     }
   };
-  auto load_l = [&](int r) {
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      L.L[ls(r)][it] = s < ns ? lam[(xo + (int64_t)(r + 1) * nb + i) * NS + s0 + s] : 0.0;
+  auto fetch_l = [&](int r) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = it / S, s = it % S;
+      pl[u] = (it < items && s < ns) ? lam[(xo + (int64_t)(r + 1) * nb + i) * NS + s0 + s] : 0.0;
+    }
+  };
+  auto fetch_a = [&](int lev) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = it / S, s = it % S;
+      pa[u] = (it < items && s < ns) ? acc_a[(po + (int64_t)lev * nb + i) * NS + s0 + s] : 0.0;
+    }
+  };
+  auto put = [&](double* dst, const double (&v)[IPT]) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT;
+      if (it < items) dst[it] = v[u];
     }
   };
   // FD weight of level mm in the radial derivative at row r (one-sided at the ends)
@@ -355,19 +378,24 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
     if (r == n) return mm == n - 1 ? -1.0 / h : (mm == n ? 1.0 / h : 0.0);
     return mm == r - 1 ? -0.5 / h : (mm == r + 1 ? 0.5 / h : 0.0);
   };
-  load_x(-1);
-  load_x(0);
-  load_x(1);
-  load_l(-1);
-  load_l(0);
+  // start: windows hold X(-1 .. 2), lambda(-1 .. 1), a(0); registers hold the next level
+  for (int q = threadIdx.x; q < nb * 32; q += WT) L.gb[q] = f.gbasis[32 * lo + q];
+  for (int l = -1; l <= 2 && l <= n + 1; ++l) {
+    fetch_x(l);
+    put(L.X[xs(l)], px);
+  }
+  for (int r = -1; r <= 1 && r <= n + 1; ++r) {
+    fetch_l(r);
+    put(L.L[ls(r)], pl);
+  }
+  fetch_a(0);
+  put(L.A, pa);
+  __syncthreads();
   for (int lev = 0; lev <= n; ++lev) {
-    if (lev + 2 <= n + 1) load_x(lev + 2);
-    if (lev + 1 <= n + 1) load_l(lev + 1);
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      L.A[it] = s < ns ? acc_a[(po + (int64_t)lev * nb + i) * NS + s0 + s] : 0.0;
-    }
-    __syncthreads();
+    const bool nx = lev + 3 <= n + 1, nl = lev + 2 <= n + 1, na = lev + 1 <= n;
+    if (nx) fetch_x(lev + 3);
+    if (nl) fetch_l(lev + 2);
+    if (na) fetch_a(lev + 1);
     const double xm = xi0 + h * lev;
     for (int it = threadIdx.x; it < items; it += WT) {
       int i = it / S, s = it % S;
@@ -408,11 +436,15 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
       }
     }
     __syncthreads();
+    // the windows' oldest slots are free now: the prefetched level moves in
+    if (nx) put(L.X[xs(lev + 3)], px);
+    if (nl) put(L.L[ls(lev + 2)], pl);
+    if (na) put(L.A, pa);
     for (int it = threadIdx.x; it < items; it += WT) {
       int k = it / S, s = it % S;
       int km = md(k - 1, nb), kp = md(k + 1, nb);
-      const double* gl = f.gbasis + 32 * (lo + km);   // segment (km, k): k is its end 1
-      const double* gr = f.gbasis + 32 * (lo + k);    // segment (k, kp): k is its end 0
+      const double* gl = L.gb + 32 * km;   // segment (km, k): k is its end 1
+      const double* gr = L.gb + 32 * k;    // segment (k, kp): k is its end 0
       auto D = [&](const double (*T)[NBT * S], int node, int t) { return T[t][node * S + s]; };
       double acc = 0.0;
       for (int tau = 0; tau < 3; ++tau) {
@@ -441,7 +473,6 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
         if (s < ns) grad[(s0 + s) * shot_stride + po + (int64_t)lev * nb + k] += L.g[it];
       }
     }
-    __syncthreads();
   }
 }
 

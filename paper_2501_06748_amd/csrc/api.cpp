@@ -72,6 +72,30 @@ void sbfwi_dev_free(void* p) {
 
 void sbfwi_factors_free(sbfwi_factors_s* f);
 
+// One non-blocking stream per host thread for the library's synchronous copies
+// (created on first use, kept until the process ends).
+static hipStream_t aux_stream() {
+  thread_local hipStream_t s = nullptr;
+  if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  return s;
+}
+
+int sbfwi_copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipStream_t s = aux_stream();
+  if (!s) return sbfwi_fail(SBFWI_EHIP, "cannot create the copy stream");
+  SBFWI_HIP(hipMemcpyAsync(dst, src, bytes, kind, s));
+  SBFWI_HIP(hipStreamSynchronize(s));
+  return SBFWI_OK;
+}
+
+int sbfwi_zero_sync(void* dst, size_t bytes) {
+  hipStream_t s = aux_stream();
+  if (!s) return sbfwi_fail(SBFWI_EHIP, "cannot create the copy stream");
+  SBFWI_HIP(hipMemsetAsync(dst, 0, bytes, s));
+  SBFWI_HIP(hipStreamSynchronize(s));
+  return SBFWI_OK;
+}
+
 extern "C" const char* sbfwi_last_error(void) { return g_err; }
 
 extern "C" int sbfwi_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
@@ -202,20 +226,20 @@ extern "C" int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* dst) {
     case 3: src = f->d.G; n = f->m->n_dense; break;
     default: return sbfwi_fail(SBFWI_EINVAL, "unknown factor data %d", which);
   }
-  SBFWI_HIP(hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
+  SBFWI_CHECK(sbfwi_copy_sync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
   return SBFWI_OK;
 }
 
 extern "C" int sbfwi_solver_stats(sbfwi_factors f, int64_t* out, int reset) {
   if (!f || !out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   int st[8];
-  SBFWI_HIP(hipMemcpy(st, f->d.status, sizeof(st), hipMemcpyDeviceToHost));
+  SBFWI_CHECK(sbfwi_copy_sync(st, f->d.status, sizeof(st), hipMemcpyDeviceToHost));
   out[0] = st[5];
   out[1] = st[4];
   out[2] = st[3];
   if (reset) {
     int z[3] = {0, 0, 0};
-    SBFWI_HIP(hipMemcpy(f->d.status + 3, z, sizeof(z), hipMemcpyHostToDevice));
+    SBFWI_CHECK(sbfwi_copy_sync(f->d.status + 3, z, sizeof(z), hipMemcpyHostToDevice));
   }
   return SBFWI_OK;
 }
@@ -336,12 +360,14 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
   // node ids are checked on the host (small arrays)
   {
     std::vector<int64_t> h(n_shots);
-    SBFWI_HIP(hipMemcpy(h.data(), src_node, n_shots * sizeof(int64_t), hipMemcpyDeviceToHost));
+    SBFWI_HIP(hipMemcpyAsync(h.data(), src_node, n_shots * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SBFWI_HIP(hipStreamSynchronize(s));
     for (int64_t v : h)
       if (v < 0 || v >= f->m->n_nodes) return sbfwi_fail(SBFWI_EINVAL, "source node %lld out of range", (long long)v);
     std::vector<int64_t> r(n_rec);
     if (n_rec > 0)
-      SBFWI_HIP(hipMemcpy(r.data(), rec_node, n_rec * sizeof(int64_t), hipMemcpyDeviceToHost));
+      SBFWI_HIP(hipMemcpyAsync(r.data(), rec_node, n_rec * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (n_rec > 0) SBFWI_HIP(hipStreamSynchronize(s));
     for (int64_t v : r)
       if (v < 0 || v >= f->m->n_nodes) return sbfwi_fail(SBFWI_EINVAL, "receiver node %lld out of range", (long long)v);
   }

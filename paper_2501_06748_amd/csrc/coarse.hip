@@ -636,7 +636,7 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS) {
   SBFWI_CHECK(sbfwi_alloc(&w->partial, (int64_t)4 * w->nblocks * NQ * NS));
   SBFWI_CHECK(sbfwi_alloc(&w->scal, (int64_t)3 * SC_N * MAXS));
   SBFWI_CHECK(sbfwi_alloc(&w->bar, 64 + 32 * ((w->nblocks + 15) / 16 + 1)));
-  SBFWI_HIP(hipMemset(w->bar, 0, sizeof(unsigned) * (64 + 32 * ((w->nblocks + 15) / 16 + 1))));
+  SBFWI_CHECK(sbfwi_zero_sync(w->bar, sizeof(unsigned) * (64 + 32 * ((w->nblocks + 15) / 16 + 1))));
   return SBFWI_OK;
 }
 

@@ -156,6 +156,10 @@ struct ProfScope {
 
 // ---- error handling / allocation (api.cpp) ----
 int sbfwi_fail(int code, const char* fmt, ...);
+// Synchronous copy on a per-thread library stream (never the legacy null
+// stream, so it is legal while other threads capture graphs).
+int sbfwi_copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+int sbfwi_zero_sync(void* dst, size_t bytes);
 void* sbfwi_dev_alloc(size_t bytes);
 void sbfwi_dev_free(void* p);
 
@@ -186,7 +190,7 @@ static inline int sbfwi_alloc(T** p, int64_t count) {
 template <typename T>
 static inline int sbfwi_upload(T** p, const std::vector<T>& v) {
   SBFWI_CHECK(sbfwi_alloc(p, (int64_t)v.size()));
-  if (!v.empty()) SBFWI_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!v.empty()) SBFWI_CHECK(sbfwi_copy_sync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return SBFWI_OK;
 }
 

@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import ctypes as C
 import queue
+import sys
 import threading
 import time
 from collections import OrderedDict
@@ -155,9 +156,13 @@ def use_torch_allocator(enable: bool = True):
         return
 
     def _alloc(nbytes, ctx):
+        # the block comes from the current stream's pool; waiting for that stream makes it idle,
+        # so the library may also use it on its own streams
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
-                                                      torch.cuda.current_stream())
+            st = torch.cuda.current_stream()
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), st)
+            st.synchronize()
+            return p
         except Exception:
             return None
 
@@ -381,7 +386,12 @@ def run_stream(server, requests, time_scale=1.0):
         if delay > 0:
             time.sleep(delay)
         server.submit(r)
-    res = server.wait(len(requests))
+    res = {}
+    step = max(1, len(requests) // 8)
+    for k in range(step, len(requests) + step, step):     # progress lines while waiting
+        res = server.wait(min(k, len(requests)))
+        print(f"[serving] {len(res)}/{len(requests)} requests done at {server.now():.1f} s", file=sys.stderr,
+              flush=True)
     server.stop()
     return res
 
