@@ -107,8 +107,14 @@ int sbfwi_mesh_info(sbfwi_mesh m, int64_t* host_out);
  *   c       wave speed; dt, beta, gamma the Newmark parameters (beta > 0).
  *   scheme  SBFWI_SCHEME_PAPER_FD (central differences in xi).
  *   coarse_solver 0 = BiCGStab with Jacobi preconditioning (K_g is not
- *           symmetric); other values are rejected.
- * Synchronises s.  SBFWI_ESINGULAR if a pivot block cannot be inverted.
+ *           symmetric), solved every step to the tolerance of sbfwi_set_solver;
+ *           1 = direct: K_g = L U factored here once, in a nested-dissection
+ *           order of the nodes (supernodes of the dissection tree, fronts
+ *           eliminated without pivoting), every step then solves with the
+ *           factors (K_g^T = U^T L^T for the adjoint); the factorisation runs
+ *           on the host and its factors are kept on the device.
+ * Synchronises s.  SBFWI_ESINGULAR if a pivot block (or, for coarse_solver 1,
+ * a pivot of K_g) is zero or not finite.
  * The factors keep a reference to m, which must outlive them.
  */
 int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, double dt,
@@ -235,6 +241,12 @@ int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
 
 /* Checkpoint store footprint in bytes (host_out[0]) and checkpoint interval (host_out[1]). */
 int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* host_out);
+
+/* Nested-dissection structure used by the direct coarse solver (host values):
+ * host_out[0] supernodes, [1] depth of the dissection tree (levels = depth + 1),
+ * [2] largest supernode, [3] sum of |J|^2, [4] sum of |J| |B_J|, [5] sum of |B_J|,
+ * [6] most supernodes on one level. */
+int sbfwi_direct_info(sbfwi_mesh m, int64_t* host_out);
 
 /* Coarse-solve statistics accumulated on these factors (synchronous):
  * host_out[0] = solves, [1] = total Krylov iterations, [2] = largest iteration count.

@@ -143,6 +143,13 @@ def sbfwi_plan_bytes(m: MeshHandle, n_shots: int, n_steps: int, n_ckpt: int = -1
             "backward_work": int(out[3])}
 
 
+def sbfwi_direct_info(m: MeshHandle) -> dict:
+    out = np.zeros(7, dtype=np.int64)
+    check(lib().sbfwi_direct_info(m, out.ctypes.data_as(C.c_void_p)))
+    keys = ["supernodes", "depth", "max_supernode", "sum_J2", "sum_JB", "sum_B", "max_per_level"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
 def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
     """Times the sweep launch shapes for runs of n_shots shots and keeps the fastest plan."""
     out = np.zeros(24, dtype=np.float64)

@@ -688,7 +688,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     SBFWI_CHECK(sbfwi_alloc(&w.lamB, nn));
     SBFWI_CHECK(sbfwi_alloc(&w.lam, m->n_x * NS));
     SBFWI_HIP(hipMemsetAsync(w.lamB, 0, sizeof(double) * nn, st));
-    SBFWI_CHECK(sbfwi_coarse_work_alloc(&w.cw, m->n_nodes, NS));
+    SBFWI_CHECK(sbfwi_coarse_work_alloc(&w.cw, m, NS));
     a.z = w.z; a.gB = w.gB; a.pl = w.pl; a.lamB = w.lamB; a.lam = w.lam;
   } else {
     SBFWI_CHECK(sbfwi_step_work_alloc(&bw, m, NS));

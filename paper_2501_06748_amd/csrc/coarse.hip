@@ -614,8 +614,9 @@ int coresident_blocks() {
 
 }  // namespace
 
-int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS) {
+int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS) {
   if (NS > MAXS) return sbfwi_fail(SBFWI_EINVAL, "at most %d shots per run", MAXS);
+  const int64_t n_nodes = m->n_nodes;
   w->NS = NS;
   w->n = n_nodes;
   int64_t sz = n_nodes * NS;
@@ -637,6 +638,12 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS) {
   SBFWI_CHECK(sbfwi_alloc(&w->scal, (int64_t)3 * SC_N * MAXS));
   SBFWI_CHECK(sbfwi_alloc(&w->bar, 64 + 32 * ((w->nblocks + 15) / 16 + 1)));
   SBFWI_CHECK(sbfwi_zero_sync(w->bar, sizeof(unsigned) * (64 + 32 * ((w->nblocks + 15) / 16 + 1))));
+  if (m->dsym) {   // direct solve: per-position scratch and the contribution buffer
+    SBFWI_CHECK(sbfwi_alloc(&w->dtb, 3 * sz));
+    w->dyb = w->dtb + sz;
+    w->dxp = w->dyb + sz;
+    SBFWI_CHECK(sbfwi_alloc(&w->dcb, m->dsym->b_ptr[m->dsym->nS] * NS));
+  }
   return SBFWI_OK;
 }
 
@@ -645,6 +652,8 @@ void sbfwi_coarse_work_free(CoarseWork* w) {
   sbfwi_dev_free(w->partial);
   sbfwi_dev_free(w->scal);
   sbfwi_dev_free(w->bar);
+  sbfwi_dev_free(w->dtb);
+  sbfwi_dev_free(w->dcb);
   *w = CoarseWork();
 }
 
@@ -655,6 +664,11 @@ int sbfwi_coarse_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
 
 int sbfwi_coarse_solve_parts(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b, double* x,
                              int64_t step, const int64_t* step_ptr, int parts, hipStream_t s) {
+  if (f->dnum) {   // direct factors: the whole solve is part 1 (plain launches, no cooperative kernel)
+    if (!(parts & 1)) return SBFWI_OK;
+    if (!w->dtb) return sbfwi_fail(SBFWI_EINVAL, "work buffers lack the direct-solve scratch");
+    return sbfwi_direct_solve(f, w, transpose, b, x, s);
+  }
   sbfwi_mesh_s* m = f->m;
   SolveArgs a;
   a.n = m->n_nodes;

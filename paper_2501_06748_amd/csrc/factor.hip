@@ -412,11 +412,12 @@ void sbfwi_factors_free(sbfwi_factors_s* f) {
                   d.G, d.S, d.psit0, d.psin_inv, d.phit_n, d.thm1_inv, d.gbasis,
                   d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv, d.status};
   for (void* p : ptrs) sbfwi_dev_free(p);
+  sbfwi_direct_num_free(f->dnum);
   delete f;
 }
 
 int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, double beta,
-                      double gamma, hipStream_t s, sbfwi_factors_s** out) {
+                      double gamma, int coarse_solver, hipStream_t s, sbfwi_factors_s** out) {
   sbfwi_factors_s* f = new sbfwi_factors_s();
   f->m = m;
   f->c = c;
@@ -504,6 +505,13 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   if (st[0] & 1) {
     sbfwi_factors_free(f);
     return sbfwi_fail(SBFWI_ESINGULAR, "a pivot block of the condensation sweep is singular");
+  }
+  if (coarse_solver == 1) {
+    rc = sbfwi_direct_factor(f, s);
+    if (rc != SBFWI_OK) {
+      sbfwi_factors_free(f);
+      return rc;
+    }
   }
   *out = f;
   return SBFWI_OK;

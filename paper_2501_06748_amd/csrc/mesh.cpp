@@ -93,6 +93,7 @@ void sbfwi_mesh_free(sbfwi_mesh_s* m) {
                   d.ell_off, d.ell_w, d.ell_col, d.ell_pos, d.elem_by_cost,
                   m->class_elems[0], m->class_elems[1], m->class_elems[2]};
   for (void* p : ptrs) sbfwi_dev_free(p);
+  sbfwi_direct_sym_free(m->dsym);
   delete m;
 }
 
@@ -288,6 +289,7 @@ extern "C" int sbfwi_build_mesh(const double* node_xy, int64_t n_nodes, const in
   m->d.nnz = m->nnz;
   m->d.xi0 = xi0;
   int rc = upload_mesh(m, loop_nodes, loop_xy, centre, node_ptr, node_slot, col, diag, tr, cnt, csrc);
+  if (rc == SBFWI_OK) rc = sbfwi_direct_symbolic(m, node_xy);
   if (rc != SBFWI_OK) {
     sbfwi_mesh_free(m);
     return rc;

@@ -58,6 +58,34 @@ struct MeshDev {
 #define ELL_SLICE 256
 #define ELL_LPR 4
 
+// Nested-dissection structure of the coarse system (direct.hip): device view.
+struct DirectDev {
+  int64_t* inv = nullptr;      // [n] node at each elimination position
+  int64_t* sn_ptr = nullptr;   // [nS+1] position range of each supernode (postorder)
+  int64_t* b_ptr = nullptr;    // [nS+1] range of each supernode's B set in bpos
+  int64_t* bpos = nullptr;     // positions coupled to a supernode after its subtree's elimination
+  int64_t* cl_ptr = nullptr;   // [n+1] per position: its contributions from descendants
+  int64_t* cl_idx = nullptr;   // index into the contribution buffer (= index into bpos)
+  int64_t* mm_off = nullptr;   // [nS+1] offsets of the |J| x |J| blocks
+  int64_t* mb_off = nullptr;   // [nS+1] offsets of the |J| x |B_J| blocks
+};
+struct DirectSym {
+  int nS = 0, depth = 0;
+  int64_t max_nj = 0;
+  std::vector<int64_t> pos, inv, sn_ptr, b_ptr, bpos, cl_ptr, cl_idx, mm_off, mb_off;
+  std::vector<int32_t> level, lvl_ptr, lvl_sn;
+  std::vector<std::vector<int32_t>> children;
+  DirectDev d;
+  int32_t* lvl_sn_dev = nullptr;
+};
+// Factors of K_g (index 0) and of K_g^T (index 1), column-major per supernode.
+struct DirectNum {
+  double* P[2] = {nullptr, nullptr};
+  double* C[2] = {nullptr, nullptr};
+  double* Q[2] = {nullptr, nullptr};
+  double* E[2] = {nullptr, nullptr};
+};
+
 struct sbfwi_mesh_s {
   int64_t n_nodes = 0, n_elem = 0, n_params = 0, n_int = 0, n_loop = 0, n_x = 0;
   int64_t nnz = 0, n_finv = 0, n_dense = 0, n_contrib = 0;
@@ -70,6 +98,7 @@ struct sbfwi_mesh_s {
   std::vector<int32_t> h_elem_by_cost;
   MeshDev d;
   int32_t* class_elems[3] = {nullptr, nullptr, nullptr};   // elements with nb <= 8, 16, 24
+  DirectSym* dsym = nullptr;
 };
 
 // Plain device view of a factored model (kernel argument).
@@ -117,6 +146,7 @@ struct sbfwi_factors_s {
   int enqueued_iters = 13;       // BiCGStab iterations enqueued per solve (more run in a rescue kernel)
   int use_graphs = 0;            // forward runs replay each time step from HIP graphs
   SweepPlan plan;
+  DirectNum* dnum = nullptr;     // direct factors of K_g (coarse solver 1), else BiCGStab
   int64_t bytes = 0;
   FactorsDev d;
 };
@@ -196,7 +226,7 @@ static inline int sbfwi_upload(T** p, const std::vector<T>& v) {
 
 // ---- stage entry points (factor.hip, step.hip, coarse.hip, adjoint.hip) ----
 int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, double beta,
-                      double gamma, hipStream_t s, sbfwi_factors_s** out);
+                      double gamma, int coarse_solver, hipStream_t s, sbfwi_factors_s** out);
 
 struct CoarseWork {
   int NS = 0;
@@ -206,8 +236,9 @@ struct CoarseWork {
          *scal = nullptr;
   unsigned* bar = nullptr;
   int nblocks = 0, nthreads = 0;
+  double *dtb = nullptr, *dyb = nullptr, *dxp = nullptr, *dcb = nullptr;   // direct solve
 };
-int sbfwi_coarse_work_alloc(CoarseWork* w, int64_t n_nodes, int NS);
+int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS);
 void sbfwi_coarse_work_free(CoarseWork* w);
 // Solves K x = b (transpose = 0) or K^T x = b (transpose = 1) for NS right-hand
 // sides; x holds the initial guess on entry.  Records failures in f->status.
@@ -268,6 +299,14 @@ int sbfwi_step_zero(sbfwi_mesh_s* m, StepWork* w, hipStream_t s);
 // f->plan.  out (host, may be NULL) receives per sweep kind: the chosen S of
 // the three classes, the fused S (0 = per-class launches), and the best time
 // in ms of the per-class and of the fused variants.
+// Direct coarse solver (direct.hip).
+int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* host_node_xy);
+void sbfwi_direct_sym_free(DirectSym* ds);
+int sbfwi_direct_factor(sbfwi_factors_s* f, hipStream_t s);
+void sbfwi_direct_num_free(DirectNum* dn);
+int sbfwi_direct_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b, double* x,
+                       hipStream_t s);
+
 int sbfwi_tune_step_sweeps(sbfwi_factors_s* f, int NS, hipStream_t s, double* out);
 int sbfwi_tune_adj_sweeps(sbfwi_factors_s* f, int NS, hipStream_t s, double* out);
 

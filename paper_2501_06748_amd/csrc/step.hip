@@ -436,7 +436,7 @@ int sbfwi_step_work_alloc(StepWork* w, sbfwi_mesh_s* m, int NS) {
   SBFWI_CHECK(sbfwi_alloc(&w->fhat, nl));
   SBFWI_CHECK(sbfwi_alloc(&w->F, nn));
   SBFWI_CHECK(sbfwi_alloc(&w->Unew, nn));
-  SBFWI_CHECK(sbfwi_coarse_work_alloc(&w->cw, m->n_nodes, NS));
+  SBFWI_CHECK(sbfwi_coarse_work_alloc(&w->cw, m, NS));
   SBFWI_CHECK(sbfwi_alloc(&w->kdev, 1));
   return SBFWI_OK;
 }
