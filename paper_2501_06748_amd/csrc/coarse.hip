@@ -638,11 +638,10 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS) {
   SBFWI_CHECK(sbfwi_alloc(&w->scal, (int64_t)3 * SC_N * MAXS));
   SBFWI_CHECK(sbfwi_alloc(&w->bar, 64 + 32 * ((w->nblocks + 15) / 16 + 1)));
   SBFWI_CHECK(sbfwi_zero_sync(w->bar, sizeof(unsigned) * (64 + 32 * ((w->nblocks + 15) / 16 + 1))));
-  if (m->dsym) {   // direct solve: per-position scratch and the contribution buffer
-    SBFWI_CHECK(sbfwi_alloc(&w->dtb, 3 * sz));
-    w->dyb = w->dtb + sz;
+  if (m->dsym) {   // direct solve: forward and backward results by elimination position
+    SBFWI_CHECK(sbfwi_alloc(&w->dyb, 3 * sz));
     w->dxp = w->dyb + sz;
-    SBFWI_CHECK(sbfwi_alloc(&w->dcb, m->dsym->b_ptr[m->dsym->nS] * NS));
+    w->dbp = w->dxp + sz;
   }
   return SBFWI_OK;
 }
@@ -652,8 +651,7 @@ void sbfwi_coarse_work_free(CoarseWork* w) {
   sbfwi_dev_free(w->partial);
   sbfwi_dev_free(w->scal);
   sbfwi_dev_free(w->bar);
-  sbfwi_dev_free(w->dtb);
-  sbfwi_dev_free(w->dcb);
+  sbfwi_dev_free(w->dyb);
   *w = CoarseWork();
 }
 
@@ -666,7 +664,7 @@ int sbfwi_coarse_solve_parts(sbfwi_factors_s* f, CoarseWork* w, int transpose, c
                              int64_t step, const int64_t* step_ptr, int parts, hipStream_t s) {
   if (f->dnum) {   // direct factors: the whole solve is part 1 (plain launches, no cooperative kernel)
     if (!(parts & 1)) return SBFWI_OK;
-    if (!w->dtb) return sbfwi_fail(SBFWI_EINVAL, "work buffers lack the direct-solve scratch");
+    if (!w->dyb) return sbfwi_fail(SBFWI_EINVAL, "work buffers lack the direct-solve scratch");
     return sbfwi_direct_solve(f, w, transpose, b, x, s);
   }
   sbfwi_mesh_s* m = f->m;

@@ -33,7 +33,10 @@
 // are bit-reproducible.
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <numeric>
+#include <mutex>
+#include <thread>
 
 #include "sbfwi_internal.h"
 
@@ -121,71 +124,116 @@ struct Dissect {
   }
 };
 
-__global__ void fwd_level_kernel(const int32_t* __restrict__ lvl_sn, DirectDev d, const double* __restrict__ P,
-                                 const double* __restrict__ Cm, int NS, const double* __restrict__ b,
-                                 double* __restrict__ tb, double* __restrict__ yb, double* __restrict__ cb,
-                                 int* __restrict__ status) {
-  const int J = lvl_sn[blockIdx.x];
-  const int64_t j0 = d.sn_ptr[J];
-  const int nj = (int)(d.sn_ptr[J + 1] - j0);
-  const int64_t b0 = d.b_ptr[J];
-  const int nb = (int)(d.b_ptr[J + 1] - b0);
-  const double* Pj = P + d.mm_off[J];
-  const double* Cj = Cm + d.mb_off[J];
-  for (int it = threadIdx.x; it < nj * NS; it += DT) {
-    const int i = it / NS, s = it - i * NS;
-    const int64_t p = j0 + i;
-    double t = b[d.inv[p] * NS + s];
-    for (int64_t q = d.cl_ptr[p]; q < d.cl_ptr[p + 1]; ++q) t -= cb[d.cl_idx[q] * NS + s];
-    tb[p * NS + s] = t;
+// out[(J, i)] = sum_k M_J[i][k] src_k over the row of (J, i): the first n_J
+// entries read the vector `own` at J's own positions (the permuted right-hand
+// side forward, y backward), the rest read `done` at the row's column list
+// (the contributors' positions forward, B_J backward), values solved at
+// earlier levels.  G lanes per row (G a power of two up to the block) split
+// the entries lane-strided in chunks of U loads issued before their use; a
+// fixed butterfly inside each wavefront, then (rows wider than a wavefront)
+// the wavefronts of the row in index order, sum them.
+template <int NSM, bool FWD>
+__global__ void __launch_bounds__(DT) direct_rows_kernel(DirectDev d, int64_t row0, int64_t nrows, int G,
+                                                         const double* __restrict__ vals, int NS,
+                                                         const double* __restrict__ own,
+                                                         const double* __restrict__ done,
+                                                         double* __restrict__ out_pos,
+                                                         double* __restrict__ out_node, int* __restrict__ status) {
+  constexpr int U = NSM <= 4 ? 8 : 4;
+  __shared__ double red[DT / 64][NSM];
+  const int64_t gt = (int64_t)blockIdx.x * DT + threadIdx.x;
+  const int64_t r = gt / G;
+  const int lane = (int)(gt - r * G);
+  const bool valid = r < nrows;
+  double acc[NSM];
+#pragma unroll
+  for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
+  int64_t j0 = 0;
+  int i = 0;
+  if (valid) {
+    const int J = d.row_sn[row0 + r];
+    i = d.row_i[row0 + r];
+    j0 = d.sn_ptr[J];
+    const int nj = (int)(d.sn_ptr[J + 1] - j0);
+    const int64_t len = FWD ? nj + d.ncols[J] : nj + (d.b_ptr[J + 1] - d.b_ptr[J]);
+    const double* v = vals + (FWD ? d.fm_off[J] : d.bm_off[J]) + (int64_t)i * len;
+    const int64_t* cols = (FWD ? d.col_idx + d.cf_off[J] : d.bpos + d.b_ptr[J]) - nj;
+    for (int64_t k0 = lane; k0 < len; k0 += (int64_t)G * U) {
+      double a[U];
+      const double* src[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + (int64_t)u * G;
+        const bool ok = k < len;
+        a[u] = ok ? v[k] : 0.0;
+        src[u] = !ok ? own + j0 * NS : (k < nj ? own + (j0 + k) * NS : done + cols[k] * NS);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int s = 0; s < NSM; ++s)
+          if (s < NS) acc[s] += a[u] * src[u][s];
+    }
   }
-  __syncthreads();
-  bool bad = false;
-  for (int it = threadIdx.x; it < nj * NS; it += DT) {
-    const int i = it / NS, s = it - i * NS;
-    double y = 0.0;
-    for (int k = 0; k < nj; ++k) y += Pj[(int64_t)k * nj + i] * tb[(j0 + k) * NS + s];
-    yb[(j0 + i) * NS + s] = y;
-    bad = bad || !isfinite(y);
+  const int gw = G < 64 ? G : 64;
+  for (int m = 1; m < gw; m <<= 1)
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) acc[s] += __shfl_xor(acc[s], m, 64);
+  if (G > 64) {   // rows wider than a wavefront: add the row's wavefronts in index order
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) red[wave][s] = acc[s];
+    __syncthreads();
+    if (lane == 0) {
+      const int w0 = wave, nw = G / 64;
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += red[w0 + q][s];
+        acc[s] = t;
+      }
+    }
   }
-  if (bad) atomicOr(&status[0], 4);
-  __syncthreads();
-  for (int it = threadIdx.x; it < nb * NS; it += DT) {
-    const int r = it / NS, s = it - r * NS;
-    double c = 0.0;
-    for (int k = 0; k < nj; ++k) c += Cj[(int64_t)k * nb + r] * yb[(j0 + k) * NS + s];
-    cb[(b0 + r) * NS + s] = c;
+  if (valid && lane == 0) {
+    bool bad = false;
+    for (int s = 0; s < NS; ++s) {
+      out_pos[(j0 + i) * NS + s] = acc[s];
+      if (!FWD) out_node[d.inv[j0 + i] * NS + s] = acc[s];
+      bad = bad || !isfinite(acc[s]);
+    }
+    if (bad) atomicOr(&status[0], 4);
   }
 }
 
-__global__ void bwd_level_kernel(const int32_t* __restrict__ lvl_sn, DirectDev d, const double* __restrict__ Q,
-                                 const double* __restrict__ E, int NS, const double* __restrict__ yb,
-                                 double* __restrict__ tb, double* __restrict__ xp, double* __restrict__ x) {
-  const int J = lvl_sn[blockIdx.x];
-  const int64_t j0 = d.sn_ptr[J];
-  const int nj = (int)(d.sn_ptr[J + 1] - j0);
-  const int64_t b0 = d.b_ptr[J];
-  const int nb = (int)(d.b_ptr[J + 1] - b0);
-  const double* Qj = Q + d.mm_off[J];
-  const double* Ej = E + d.mb_off[J];
-  for (int it = threadIdx.x; it < nj * NS; it += DT) {
-    const int i = it / NS, s = it - i * NS;
-    double t = yb[(j0 + i) * NS + s];
-    for (int r = 0; r < nb; ++r) t -= Ej[(int64_t)r * nj + i] * xp[d.bpos[b0 + r] * NS + s];
-    tb[(j0 + i) * NS + s] = t;
-  }
-  __syncthreads();
-  for (int it = threadIdx.x; it < nj * NS; it += DT) {
-    const int i = it / NS, s = it - i * NS;
-    double v = 0.0;
-    for (int k = 0; k < nj; ++k) v += Qj[(int64_t)k * nj + i] * tb[(j0 + k) * NS + s];
-    xp[(j0 + i) * NS + s] = v;
-    x[d.inv[j0 + i] * NS + s] = v;
-  }
+// right-hand side by elimination position
+__global__ void permute_kernel(int64_t n, int NS, const int64_t* __restrict__ inv, const double* __restrict__ b,
+                               double* __restrict__ bp) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * NS) return;
+  const int64_t p = g / NS;
+  bp[g] = b[inv[p] * NS + (g - p * NS)];
 }
 
 __global__ void count_solve_kernel(int* status) {
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);
+}
+
+// Runs fn(i) for i in [0, n) on up to `threads` host threads (dynamic assignment).
+template <typename Fn>
+void parallel_for(int64_t n, Fn&& fn) {
+  int threads = (int)std::min<int64_t>(n, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  if (threads <= 1) {
+    for (int64_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t)
+    pool.emplace_back([&] {
+      for (int64_t i = next++; i < n; i = next++) fn(i);
+    });
+  for (auto& th : pool) th.join();
 }
 
 }  // namespace
@@ -208,6 +256,9 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   ds->pos.assign(n, 0);
   for (int64_t p = 0; p < n; ++p) ds->pos[ds->inv[p]] = p;
   ds->children = dis.kids;
+  ds->snp.assign(n, 0);
+  for (int J = 0; J < nS; ++J)
+    for (int64_t p = ds->sn_ptr[J]; p < ds->sn_ptr[J + 1]; ++p) ds->snp[p] = J;
   ds->level.assign(nS, 0);
   for (int J = nS - 1; J >= 0; --J)   // parents come after their children
     for (int c : ds->children[J]) ds->level[c] = ds->level[J] + 1;
@@ -236,27 +287,44 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   }
   ds->bpos.resize(ds->b_ptr[nS]);
   for (int J = 0; J < nS; ++J) std::copy(B[J].begin(), B[J].end(), ds->bpos.begin() + ds->b_ptr[J]);
-  // contribution lists per position: (D, k) with B_D[k] = p, D ascending
-  std::vector<int64_t> cnt(n + 1, 0);
-  for (int64_t q = 0; q < ds->b_ptr[nS]; ++q) cnt[ds->bpos[q] + 1]++;
-  for (int64_t p = 0; p < n; ++p) cnt[p + 1] += cnt[p];
-  ds->cl_ptr = cnt;
-  ds->cl_idx.assign(cnt[n], 0);
-  {
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int D = 0; D < nS; ++D)
-      for (int64_t q = ds->b_ptr[D]; q < ds->b_ptr[D + 1]; ++q) ds->cl_idx[fill[ds->bpos[q]]++] = q;
+  // contributors of every supernode: the descendants D whose B_D meets J (D ascending)
+  ds->ctr.assign(nS, {});
+  for (int D = 0; D < nS; ++D) {
+    int last = -1;
+    for (int64_t q = ds->b_ptr[D]; q < ds->b_ptr[D + 1]; ++q) {
+      const int J = ds->sn_of(ds->bpos[q]);
+      if (J != last) ds->ctr[J].push_back(D);   // bpos is sorted, so each J appears in one run
+      last = J;
+    }
   }
-  // dense block offsets and level lists
-  ds->mm_off.assign(nS + 1, 0);
-  ds->mb_off.assign(nS + 1, 0);
+  for (auto& c : ds->ctr) {
+    std::sort(c.begin(), c.end());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
+  }
+  // forward rows of J read its own nodes, then the positions of its contributors;
+  // backward rows read J's positions, then B_J
+  ds->ncols.assign(nS, 0);
+  ds->cf_off.assign(nS + 1, 0);
+  ds->fm_off.assign(nS + 1, 0);
+  ds->bm_off.assign(nS + 1, 0);
   ds->max_nj = 0;
   for (int J = 0; J < nS; ++J) {
     const int64_t nj = ds->sn_ptr[J + 1] - ds->sn_ptr[J], nb = ds->b_ptr[J + 1] - ds->b_ptr[J];
-    ds->mm_off[J + 1] = ds->mm_off[J] + nj * nj;
-    ds->mb_off[J + 1] = ds->mb_off[J] + nj * nb;
+    int64_t nc = 0;
+    for (int D : ds->ctr[J]) nc += ds->sn_ptr[D + 1] - ds->sn_ptr[D];
+    ds->ncols[J] = nc;
+    ds->cf_off[J + 1] = ds->cf_off[J] + nc;
+    ds->fm_off[J + 1] = ds->fm_off[J] + nj * (nj + nc);
+    ds->bm_off[J + 1] = ds->bm_off[J] + nj * (nj + nb);
     ds->max_nj = std::max<int64_t>(ds->max_nj, nj);
   }
+  ds->col_idx.assign(ds->cf_off[nS], 0);
+  for (int J = 0; J < nS; ++J) {
+    int64_t o = ds->cf_off[J];
+    for (int D : ds->ctr[J])
+      for (int64_t p = ds->sn_ptr[D]; p < ds->sn_ptr[D + 1]; ++p) ds->col_idx[o++] = p;
+  }
+  // levels: supernodes, their rows, and lanes per row from the longest row of the level
   ds->lvl_ptr.assign(ds->depth + 2, 0);
   for (int J = 0; J < nS; ++J) ds->lvl_ptr[ds->level[J] + 1]++;
   for (int l = 0; l <= ds->depth; ++l) ds->lvl_ptr[l + 1] += ds->lvl_ptr[l];
@@ -265,23 +333,50 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
     std::vector<int32_t> fill(ds->lvl_ptr.begin(), ds->lvl_ptr.end() - 1);
     for (int J = 0; J < nS; ++J) ds->lvl_sn[fill[ds->level[J]]++] = J;
   }
+  ds->row_ptr.assign(ds->depth + 2, 0);
+  ds->g_fwd.assign(ds->depth + 1, 1);
+  ds->g_bwd.assign(ds->depth + 1, 1);
+  auto lanes = [](int64_t len) {
+    int g = 1;
+    while (g < DT && g * 16 < len) g *= 2;   // about 16 entries per lane, at most a block per row
+    return g;
+  };
+  for (int l = 0; l <= ds->depth; ++l) {
+    int64_t lf = 0, lb = 0;
+    for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) {
+      const int J = ds->lvl_sn[q];
+      const int64_t nj = ds->sn_ptr[J + 1] - ds->sn_ptr[J];
+      for (int64_t i = 0; i < nj; ++i) {
+        ds->row_sn.push_back(J);
+        ds->row_i.push_back((int32_t)i);
+      }
+      lf = std::max(lf, nj + ds->ncols[J]);
+      lb = std::max(lb, nj + ds->b_ptr[J + 1] - ds->b_ptr[J]);
+    }
+    ds->row_ptr[l + 1] = (int64_t)ds->row_sn.size();
+    ds->g_fwd[l] = lanes(lf);
+    ds->g_bwd[l] = lanes(lb);
+  }
   DirectDev& d = ds->d;
   SBFWI_CHECK(sbfwi_upload(&d.inv, ds->inv));
   SBFWI_CHECK(sbfwi_upload(&d.sn_ptr, ds->sn_ptr));
   SBFWI_CHECK(sbfwi_upload(&d.b_ptr, ds->b_ptr));
   SBFWI_CHECK(sbfwi_upload(&d.bpos, ds->bpos));
-  SBFWI_CHECK(sbfwi_upload(&d.cl_ptr, ds->cl_ptr));
-  SBFWI_CHECK(sbfwi_upload(&d.cl_idx, ds->cl_idx));
-  SBFWI_CHECK(sbfwi_upload(&d.mm_off, ds->mm_off));
-  SBFWI_CHECK(sbfwi_upload(&d.mb_off, ds->mb_off));
-  SBFWI_CHECK(sbfwi_upload(&ds->lvl_sn_dev, ds->lvl_sn));
+  SBFWI_CHECK(sbfwi_upload(&d.ncols, ds->ncols));
+  SBFWI_CHECK(sbfwi_upload(&d.cf_off, ds->cf_off));
+  SBFWI_CHECK(sbfwi_upload(&d.col_idx, ds->col_idx));
+  SBFWI_CHECK(sbfwi_upload(&d.fm_off, ds->fm_off));
+  SBFWI_CHECK(sbfwi_upload(&d.bm_off, ds->bm_off));
+  SBFWI_CHECK(sbfwi_upload(&d.row_sn, ds->row_sn));
+  SBFWI_CHECK(sbfwi_upload(&d.row_i, ds->row_i));
   return SBFWI_OK;
 }
 
 void sbfwi_direct_sym_free(DirectSym* ds) {
   if (!ds) return;
   DirectDev& d = ds->d;
-  void* ptrs[] = {d.inv, d.sn_ptr, d.b_ptr, d.bpos, d.cl_ptr, d.cl_idx, d.mm_off, d.mb_off, ds->lvl_sn_dev};
+  void* ptrs[] = {d.inv, d.sn_ptr, d.b_ptr, d.bpos, d.ncols, d.cf_off, d.col_idx, d.fm_off, d.bm_off,
+                  d.row_sn, d.row_i};
   for (void* p : ptrs) sbfwi_dev_free(p);
   delete ds;
 }
@@ -290,10 +385,10 @@ void sbfwi_direct_sym_free(DirectSym* ds) {
 
 namespace {
 
-// Unit-lower-triangular inverse of the strictly-lower part of A (n x n, row-major,
-// leading dimension lda) into column-major out; upper-triangular inverse likewise.
-void inv_unit_lower(const double* A, int64_t lda, int n, double* out) {
-  std::vector<double> X((size_t)n * n, 0.0);   // row-major
+// Unit-lower-triangular inverse of the strictly-lower part of the leading n x n
+// block of A (row-major, leading dimension lda) into row-major out (n x n).
+void inv_unit_lower(const double* A, int64_t lda, int n, double* X) {
+  std::fill(X, X + (size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
     X[(size_t)j * n + j] = 1.0;
     for (int i = j + 1; i < n; ++i) {
@@ -302,12 +397,11 @@ void inv_unit_lower(const double* A, int64_t lda, int n, double* out) {
       X[(size_t)i * n + j] = s;
     }
   }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) out[(size_t)j * n + i] = X[(size_t)i * n + j];
 }
 
-void inv_upper(const double* A, int64_t lda, int n, double* out) {
-  std::vector<double> X((size_t)n * n, 0.0);   // row-major
+// Inverse of the upper triangle (with diagonal) of the leading n x n block of A.
+void inv_upper(const double* A, int64_t lda, int n, double* X) {
+  std::fill(X, X + (size_t)n * n, 0.0);
   for (int j = n - 1; j >= 0; --j) {
     X[(size_t)j * n + j] = 1.0 / A[j * lda + j];
     for (int i = j - 1; i >= 0; --i) {
@@ -316,8 +410,98 @@ void inv_upper(const double* A, int64_t lda, int n, double* out) {
       X[(size_t)i * n + j] = s / A[i * lda + i];
     }
   }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) out[(size_t)j * n + i] = X[(size_t)i * n + j];
+}
+
+// Per-supernode results of the elimination (row-major): P = L11^-1, Q = U11^-1,
+// L21 (nb x nj), U12 (nj x nb).
+struct FrontOut {
+  std::vector<double> P, Q, L21, U12, upd;
+};
+
+int eliminate_front(const DirectSym* ds, sbfwi_mesh_s* m, const std::vector<double>& K,
+                    const std::vector<double>& KT, std::vector<FrontOut>& fo, int J, std::vector<int64_t>& loc) {
+  const int64_t j0 = ds->sn_ptr[J], j1 = ds->sn_ptr[J + 1];
+  const int nj = (int)(j1 - j0);
+  const int64_t b0 = ds->b_ptr[J];
+  const int nb = (int)(ds->b_ptr[J + 1] - b0);
+  const int64_t mf = nj + nb;
+  for (int64_t p = j0; p < j1; ++p) loc[p] = p - j0;
+  for (int r = 0; r < nb; ++r) loc[ds->bpos[b0 + r]] = nj + r;
+  int rc = SBFWI_OK;
+  std::vector<double> F((size_t)mf * mf, 0.0);   // row-major front: rows and columns J then B_J
+  for (int64_t p = j0; p < j1 && rc == SBFWI_OK; ++p) {
+    const int64_t v = ds->inv[p], lp = p - j0;
+    for (int64_t q = m->h_row_ptr[v]; q < m->h_row_ptr[v + 1]; ++q) {
+      const int64_t pc = ds->pos[m->h_col64[q]];
+      if (pc < j0) continue;                         // assembled in a descendant's front
+      const int64_t lc = loc[pc];
+      if (lc < 0) {
+        rc = sbfwi_fail(SBFWI_EINVAL, "dissection structure misses a coupling");
+        break;
+      }
+      F[(size_t)lp * mf + lc] += K[q];                // row in J
+      if (pc >= j1) F[(size_t)lc * mf + lp] += KT[q]; // row in B_J, column in J: K[c][v]
+    }
+  }
+  for (int c : ds->children[J]) {
+    const int64_t cb0 = ds->b_ptr[c];
+    const int cnb = (int)(ds->b_ptr[c + 1] - cb0);
+    const std::vector<double>& U = fo[c].upd;
+    for (int a = 0; a < cnb; ++a) {
+      const int64_t la = loc[ds->bpos[cb0 + a]];
+      for (int bb = 0; bb < cnb; ++bb) F[(size_t)la * mf + loc[ds->bpos[cb0 + bb]]] += U[(size_t)a * cnb + bb];
+    }
+    std::vector<double>().swap(fo[c].upd);
+  }
+  for (int64_t p = j0; p < j1; ++p) loc[p] = -1;
+  for (int r = 0; r < nb; ++r) loc[ds->bpos[b0 + r]] = -1;
+  if (rc != SBFWI_OK) return rc;
+  for (int k = 0; k < nj; ++k) {
+    const double piv = F[(size_t)k * mf + k];
+    if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv))
+      return sbfwi_fail(SBFWI_ESINGULAR, "coarse matrix: zero pivot in the direct factorisation");
+    const double* rk = &F[(size_t)k * mf];
+    for (int64_t i = k + 1; i < mf; ++i) {
+      double* ri = &F[(size_t)i * mf];
+      const double l = ri[k] / piv;
+      ri[k] = l;
+      if (l != 0.0)
+        for (int64_t j = k + 1; j < mf; ++j) ri[j] -= l * rk[j];
+    }
+  }
+  FrontOut& o = fo[J];
+  o.P.resize((size_t)nj * nj);
+  o.Q.resize((size_t)nj * nj);
+  inv_unit_lower(F.data(), mf, nj, o.P.data());
+  inv_upper(F.data(), mf, nj, o.Q.data());
+  o.L21.resize((size_t)nb * nj);
+  o.U12.resize((size_t)nj * nb);
+  for (int r = 0; r < nb; ++r)
+    for (int k = 0; k < nj; ++k) {
+      o.L21[(size_t)r * nj + k] = F[(size_t)(nj + r) * mf + k];
+      o.U12[(size_t)k * nb + r] = F[(size_t)k * mf + nj + r];
+    }
+  o.upd.resize((size_t)nb * nb);
+  for (int a = 0; a < nb; ++a)
+    for (int bb = 0; bb < nb; ++bb) o.upd[(size_t)a * nb + bb] = F[(size_t)(nj + a) * mf + nj + bb];
+  return SBFWI_OK;
+}
+
+// rows [r0, r1) of out = [A | -A R]: A (nj x nj), R (nj x nc), both row-major; out rows have nj + nc entries
+void fold_rows(const double* A, const double* R, int nj, int64_t nc, int r0, int r1, double* out) {
+  const int64_t len = nj + nc;
+  for (int i = r0; i < r1; ++i) {
+    double* o = out + (size_t)i * len;
+    for (int k = 0; k < nj; ++k) o[k] = A[(size_t)i * nj + k];
+    double* t = o + nj;
+    for (int64_t c = 0; c < nc; ++c) t[c] = 0.0;
+    for (int k = 0; k < nj; ++k) {
+      const double a = A[(size_t)i * nj + k];
+      if (a == 0.0) continue;
+      const double* rk = R + (size_t)k * nc;
+      for (int64_t c = 0; c < nc; ++c) t[c] -= a * rk[c];
+    }
+  }
 }
 
 }  // namespace
@@ -332,113 +516,128 @@ int sbfwi_direct_factor(sbfwi_factors_s* f, hipStream_t s) {
   SBFWI_HIP(hipMemcpyAsync(KT.data(), f->d.KTval, nnz * sizeof(double), hipMemcpyDeviceToHost, s));
   SBFWI_HIP(hipStreamSynchronize(s));
   const int nS = ds->nS;
-  const int64_t nmm = ds->mm_off[nS], nmb = ds->mb_off[nS];
-  std::vector<double> Pn(nmm), Qn(nmm), Pt(nmm), Qt(nmm), Cn(nmb), En(nmb), Ct(nmb), Et(nmb);
-  std::vector<std::vector<double>> upd(nS);
-  std::vector<int64_t> loc(n, -1);
+  std::vector<FrontOut> fo(nS);
+  // eliminate level by level from the leaves (the fronts of one level are independent)
+  for (int l = ds->depth; l >= 0; --l) {
+    const int q0 = ds->lvl_ptr[l], cnt = ds->lvl_ptr[l + 1] - q0;
+    std::atomic<int> rc{SBFWI_OK};
+    parallel_for(cnt, [&](int64_t q) {
+      thread_local std::vector<int64_t> loc;
+      if ((int64_t)loc.size() != n) loc.assign(n, -1);
+      int r = eliminate_front(ds, m, K, KT, fo, ds->lvl_sn[q0 + q], loc);
+      if (r != SBFWI_OK) rc = r;
+    });
+    if (rc != SBFWI_OK)   // the message was recorded on a worker thread
+      return sbfwi_fail(rc.load(), rc == SBFWI_ESINGULAR ? "coarse matrix: zero pivot in the direct factorisation"
+                                                         : "direct factorisation: dissection misses a coupling");
+  }
+  // folded row blocks: forward FM_J = [P_J | -P_J Lrow_J], backward BM_J = [Q_J | -Q_J U12_J]
+  // and for K^T: [Q_J^T | -Q_J^T Lrow'_J], [P_J^T | -P_J^T L21_J^T]
+  const int64_t nf = ds->fm_off[nS], nbm = ds->bm_off[nS];
+  std::vector<double> FM(nf), BM(nbm), FMt(nf), BMt(nbm);
+  struct Item {
+    int J, r0, r1;
+  };
+  std::vector<Item> items;
   for (int J = 0; J < nS; ++J) {
-    const int64_t j0 = ds->sn_ptr[J], j1 = ds->sn_ptr[J + 1];
-    const int nj = (int)(j1 - j0);
-    const int64_t b0 = ds->b_ptr[J];
-    const int nb = (int)(ds->b_ptr[J + 1] - b0);
-    const int64_t mf = nj + nb;
-    for (int64_t p = j0; p < j1; ++p) loc[p] = p - j0;
-    for (int r = 0; r < nb; ++r) loc[ds->bpos[b0 + r]] = nj + r;
-    std::vector<double> F((size_t)mf * mf, 0.0);   // row-major front
-    for (int64_t p = j0; p < j1; ++p) {
-      const int64_t v = ds->inv[p], lp = p - j0;
-      for (int64_t q = m->h_row_ptr[v]; q < m->h_row_ptr[v + 1]; ++q) {
-        const int64_t pc = ds->pos[m->h_col64[q]];
-        if (pc < j0) continue;                    // belongs to a descendant's front
-        const int64_t lc = loc[pc];
-        if (lc < 0) return sbfwi_fail(SBFWI_EINVAL, "dissection structure misses a coupling");
-        F[(size_t)lp * mf + lc] += K[q];          // row in J
-        if (pc >= j1) F[(size_t)lc * mf + lp] += KT[q];   // column in J, row in B_J: K[c][v]
+    const int nj = (int)(ds->sn_ptr[J + 1] - ds->sn_ptr[J]);
+    const int64_t work = (int64_t)nj * (nj + ds->ncols[J]);
+    const int chunk = work > (1 << 16) ? std::max(1, (int)((1 << 16) / std::max<int64_t>(1, nj + ds->ncols[J]))) : nj;
+    for (int r0 = 0; r0 < nj; r0 += chunk) items.push_back({J, r0, std::min(nj, r0 + chunk)});
+  }
+  // Lrow_J / Lrow'_J (nj x ncols): rows of the contributors' L21 (U12^T) that fall in J
+  std::vector<std::vector<double>> lrow(nS), lrowt(nS);
+  parallel_for(nS, [&](int64_t Jq) {
+    const int J = (int)Jq;
+    const int64_t j0 = ds->sn_ptr[J];
+    const int nj = (int)(ds->sn_ptr[J + 1] - j0);
+    const int64_t nc = ds->ncols[J];
+    lrow[J].assign((size_t)nj * nc, 0.0);
+    lrowt[J].assign((size_t)nj * nc, 0.0);
+    int64_t c0 = 0;
+    for (int D : ds->ctr[J]) {
+      const int nd = (int)(ds->sn_ptr[D + 1] - ds->sn_ptr[D]);
+      const int64_t db0 = ds->b_ptr[D];
+      const int dnb = (int)(ds->b_ptr[D + 1] - db0);
+      for (int k = 0; k < dnb; ++k) {
+        const int64_t p = ds->bpos[db0 + k];
+        if (p < j0 || p >= j0 + nj) continue;
+        const int i = (int)(p - j0);
+        for (int mm = 0; mm < nd; ++mm) {
+          lrow[J][(size_t)i * nc + c0 + mm] = fo[D].L21[(size_t)k * nd + mm];
+          lrowt[J][(size_t)i * nc + c0 + mm] = fo[D].U12[(size_t)mm * dnb + k];
+        }
       }
+      c0 += nd;
     }
-    for (int c : ds->children[J]) {
-      const int64_t cb0 = ds->b_ptr[c];
-      const int cnb = (int)(ds->b_ptr[c + 1] - cb0);
-      const std::vector<double>& U = upd[c];
-      for (int a = 0; a < cnb; ++a) {
-        const int64_t la = loc[ds->bpos[cb0 + a]];
-        for (int bb = 0; bb < cnb; ++bb) F[(size_t)la * mf + loc[ds->bpos[cb0 + bb]]] += U[(size_t)a * cnb + bb];
-      }
-      std::vector<double>().swap(upd[c]);
-    }
-    // eliminate the first nj pivots
-    for (int k = 0; k < nj; ++k) {
-      const double piv = F[(size_t)k * mf + k];
-      if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv))
-        return sbfwi_fail(SBFWI_ESINGULAR, "coarse matrix: zero pivot in the direct factorisation");
-      const double* rk = &F[(size_t)k * mf];
-      for (int64_t i = k + 1; i < mf; ++i) {
-        double* ri = &F[(size_t)i * mf];
-        const double l = ri[k] / piv;
-        ri[k] = l;
-        if (l != 0.0)
-          for (int64_t j = k + 1; j < mf; ++j) ri[j] -= l * rk[j];
-      }
-    }
-    double* pn = &Pn[ds->mm_off[J]];
-    double* qn = &Qn[ds->mm_off[J]];
-    inv_unit_lower(F.data(), mf, nj, pn);
-    inv_upper(F.data(), mf, nj, qn);
-    double* pt = &Pt[ds->mm_off[J]];
-    double* qt = &Qt[ds->mm_off[J]];
+  });
+  parallel_for((int64_t)items.size(), [&](int64_t q) {
+    const Item it = items[q];
+    const int J = it.J;
+    const int nj = (int)(ds->sn_ptr[J + 1] - ds->sn_ptr[J]);
+    const int nb = (int)(ds->b_ptr[J + 1] - ds->b_ptr[J]);
+    const int64_t nc = ds->ncols[J];
+    const FrontOut& o = fo[J];
+    std::vector<double> Pt((size_t)nj * nj), Qt((size_t)nj * nj), L21t((size_t)nj * nb);
     for (int i = 0; i < nj; ++i)
       for (int k = 0; k < nj; ++k) {
-        pt[(size_t)k * nj + i] = qn[(size_t)i * nj + k];   // (U11^-1)^T
-        qt[(size_t)k * nj + i] = pn[(size_t)i * nj + k];   // (L11^-1)^T
+        Pt[(size_t)i * nj + k] = o.Q[(size_t)k * nj + i];   // (U11^-1)^T
+        Qt[(size_t)i * nj + k] = o.P[(size_t)k * nj + i];   // (L11^-1)^T
       }
-    double* cn = &Cn[ds->mb_off[J]];
-    double* en = &En[ds->mb_off[J]];
-    double* ct = &Ct[ds->mb_off[J]];
-    double* et = &Et[ds->mb_off[J]];
     for (int r = 0; r < nb; ++r)
-      for (int k = 0; k < nj; ++k) {
-        const double l21 = F[(size_t)(nj + r) * mf + k];
-        const double u12 = F[(size_t)k * mf + nj + r];
-        cn[(size_t)k * nb + r] = l21;     // C = L21 (nb x nj)
-        en[(size_t)r * nj + k] = u12;     // E = U12 (nj x nb)
-        ct[(size_t)k * nb + r] = u12;     // C^T-solve = U12^T (nb x nj)
-        et[(size_t)r * nj + k] = l21;     // E^T-solve = L21^T (nj x nb)
-      }
-    if (nb > 0) {
-      std::vector<double>& U = upd[J];
-      U.resize((size_t)nb * nb);
-      for (int a = 0; a < nb; ++a)
-        for (int bb = 0; bb < nb; ++bb) U[(size_t)a * nb + bb] = F[(size_t)(nj + a) * mf + nj + bb];
-    }
-    for (int64_t p = j0; p < j1; ++p) loc[p] = -1;
-    for (int r = 0; r < nb; ++r) loc[ds->bpos[b0 + r]] = -1;
-  }
+      for (int k = 0; k < nj; ++k) L21t[(size_t)k * nb + r] = o.L21[(size_t)r * nj + k];
+    fold_rows(o.P.data(), lrow[J].data(), nj, nc, it.r0, it.r1, &FM[ds->fm_off[J]]);
+    fold_rows(Pt.data(), lrowt[J].data(), nj, nc, it.r0, it.r1, &FMt[ds->fm_off[J]]);
+    fold_rows(o.Q.data(), o.U12.data(), nj, nb, it.r0, it.r1, &BM[ds->bm_off[J]]);
+    fold_rows(Qt.data(), L21t.data(), nj, nb, it.r0, it.r1, &BMt[ds->bm_off[J]]);
+  });
   DirectNum* dn = new DirectNum();
   f->dnum = dn;
-  SBFWI_CHECK(sbfwi_upload(&dn->P[0], Pn));
-  SBFWI_CHECK(sbfwi_upload(&dn->C[0], Cn));
-  SBFWI_CHECK(sbfwi_upload(&dn->Q[0], Qn));
-  SBFWI_CHECK(sbfwi_upload(&dn->E[0], En));
-  SBFWI_CHECK(sbfwi_upload(&dn->P[1], Pt));
-  SBFWI_CHECK(sbfwi_upload(&dn->C[1], Ct));
-  SBFWI_CHECK(sbfwi_upload(&dn->Q[1], Qt));
-  SBFWI_CHECK(sbfwi_upload(&dn->E[1], Et));
-  f->bytes += 8 * 4 * (nmm + nmb);
+  SBFWI_CHECK(sbfwi_upload(&dn->FM[0], FM));
+  SBFWI_CHECK(sbfwi_upload(&dn->BM[0], BM));
+  SBFWI_CHECK(sbfwi_upload(&dn->FM[1], FMt));
+  SBFWI_CHECK(sbfwi_upload(&dn->BM[1], BMt));
+  f->bytes += 8 * 2 * (nf + nbm);
   return SBFWI_OK;
 }
 
 void sbfwi_direct_num_free(DirectNum* dn) {
   if (!dn) return;
   for (int t = 0; t < 2; ++t) {
-    sbfwi_dev_free(dn->P[t]);
-    sbfwi_dev_free(dn->C[t]);
-    sbfwi_dev_free(dn->Q[t]);
-    sbfwi_dev_free(dn->E[t]);
+    sbfwi_dev_free(dn->FM[t]);
+    sbfwi_dev_free(dn->BM[t]);
   }
   delete dn;
 }
 
 // ------------------------------------------------------------------ solve
+
+namespace {
+
+template <int NSM>
+void launch_rows(bool fwd, DirectSym* ds, int l, const double* vals, int NS, const double* vin,
+                 const double* vdone, double* out_pos, double* out_node, int* status, hipStream_t s) {
+  const int64_t r0 = ds->row_ptr[l], nr = ds->row_ptr[l + 1] - r0;
+  const int G = fwd ? ds->g_fwd[l] : ds->g_bwd[l];
+  const unsigned blocks = (unsigned)((nr * G + DT - 1) / DT);
+  if (fwd)
+    hipLaunchKernelGGL((direct_rows_kernel<NSM, true>), dim3(blocks), dim3(DT), 0, s, ds->d, r0, nr, G, vals, NS,
+                       vin, vdone, out_pos, out_node, status);
+  else
+    hipLaunchKernelGGL((direct_rows_kernel<NSM, false>), dim3(blocks), dim3(DT), 0, s, ds->d, r0, nr, G, vals, NS,
+                       vin, vdone, out_pos, out_node, status);
+}
+
+void launch_rows_ns(bool fwd, DirectSym* ds, int l, const double* vals, int NS, const double* vin,
+                    const double* vdone, double* out_pos, double* out_node, int* status, hipStream_t s) {
+  if (NS == 1) launch_rows<1>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
+  else if (NS == 2) launch_rows<2>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
+  else if (NS <= 4) launch_rows<4>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
+  else if (NS <= 8) launch_rows<8>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
+  else launch_rows<16>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
+}
+
+}  // namespace
 
 int sbfwi_direct_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b, double* x,
                        hipStream_t s) {
@@ -446,16 +645,15 @@ int sbfwi_direct_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
   DirectNum* dn = f->dnum;
   const int t = transpose ? 1 : 0;
   ProfScope ps(PK_SOLVE, s);
-  for (int l = ds->depth; l >= 0; --l) {
-    const int cnt = ds->lvl_ptr[l + 1] - ds->lvl_ptr[l];
-    hipLaunchKernelGGL(fwd_level_kernel, dim3(cnt), dim3(DT), 0, s, ds->lvl_sn_dev + ds->lvl_ptr[l], ds->d,
-                       dn->P[t], dn->C[t], w->NS, b, w->dtb, w->dyb, w->dcb, f->d.status);
-  }
-  for (int l = 0; l <= ds->depth; ++l) {
-    const int cnt = ds->lvl_ptr[l + 1] - ds->lvl_ptr[l];
-    hipLaunchKernelGGL(bwd_level_kernel, dim3(cnt), dim3(DT), 0, s, ds->lvl_sn_dev + ds->lvl_ptr[l], ds->d,
-                       dn->Q[t], dn->E[t], w->NS, w->dyb, w->dtb, w->dxp, x);
-  }
+  // forward, deepest level first: y (by position) from b (permuted to positions) and the contributors' y
+  const int64_t nn = f->m->n_nodes * w->NS;
+  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, f->m->n_nodes, w->NS,
+                     ds->d.inv, b, w->dbp);
+  for (int l = ds->depth; l >= 0; --l)
+    launch_rows_ns(true, ds, l, dn->FM[t], w->NS, w->dbp, w->dyb, w->dyb, nullptr, f->d.status, s);
+  // backward, root first: x (by position and by node) from y and the solved B sets
+  for (int l = 0; l <= ds->depth; ++l)
+    launch_rows_ns(false, ds, l, dn->BM[t], w->NS, w->dyb, w->dxp, w->dxp, x, f->d.status, s);
   hipLaunchKernelGGL(count_solve_kernel, dim3(1), dim3(64), 0, s, f->d.status);
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;
@@ -468,8 +666,8 @@ extern "C" int sbfwi_direct_info(sbfwi_mesh m, int64_t* out) {
   out[0] = ds->nS;
   out[1] = ds->depth;
   out[2] = ds->max_nj;
-  out[3] = ds->mm_off[ds->nS];
-  out[4] = ds->mb_off[ds->nS];
+  out[3] = ds->fm_off[ds->nS];
+  out[4] = ds->bm_off[ds->nS];
   out[5] = ds->b_ptr[ds->nS];
   int64_t mx = 0;
   for (int l = 0; l <= ds->depth; ++l) mx = std::max<int64_t>(mx, ds->lvl_ptr[l + 1] - ds->lvl_ptr[l]);

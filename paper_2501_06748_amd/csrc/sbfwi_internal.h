@@ -64,26 +64,27 @@ struct DirectDev {
   int64_t* sn_ptr = nullptr;   // [nS+1] position range of each supernode (postorder)
   int64_t* b_ptr = nullptr;    // [nS+1] range of each supernode's B set in bpos
   int64_t* bpos = nullptr;     // positions coupled to a supernode after its subtree's elimination
-  int64_t* cl_ptr = nullptr;   // [n+1] per position: its contributions from descendants
-  int64_t* cl_idx = nullptr;   // index into the contribution buffer (= index into bpos)
-  int64_t* mm_off = nullptr;   // [nS+1] offsets of the |J| x |J| blocks
-  int64_t* mb_off = nullptr;   // [nS+1] offsets of the |J| x |B_J| blocks
+  int64_t* ncols = nullptr;    // [nS] positions of the supernode's contributors
+  int64_t* cf_off = nullptr;   // [nS+1] their range in col_idx
+  int64_t* col_idx = nullptr;  // contributor positions, supernode after supernode
+  int64_t* fm_off = nullptr;   // [nS+1] forward row blocks: |J| x (|J| + ncols)
+  int64_t* bm_off = nullptr;   // [nS+1] backward row blocks: |J| x (|J| + |B_J|)
+  int32_t* row_sn = nullptr;   // rows level by level: supernode
+  int32_t* row_i = nullptr;    //                      row within it
 };
 struct DirectSym {
   int nS = 0, depth = 0;
   int64_t max_nj = 0;
-  std::vector<int64_t> pos, inv, sn_ptr, b_ptr, bpos, cl_ptr, cl_idx, mm_off, mb_off;
-  std::vector<int32_t> level, lvl_ptr, lvl_sn;
-  std::vector<std::vector<int32_t>> children;
+  std::vector<int64_t> pos, inv, sn_ptr, b_ptr, bpos, ncols, cf_off, col_idx, fm_off, bm_off, row_ptr;
+  std::vector<int32_t> level, lvl_ptr, lvl_sn, row_sn, row_i, g_fwd, g_bwd, snp;
+  std::vector<std::vector<int32_t>> children, ctr;
   DirectDev d;
-  int32_t* lvl_sn_dev = nullptr;
+  int sn_of(int64_t p) const { return snp[p]; }
 };
-// Factors of K_g (index 0) and of K_g^T (index 1), column-major per supernode.
+// Folded row blocks of K_g (index 0) and of K_g^T (index 1), row-major per supernode.
 struct DirectNum {
-  double* P[2] = {nullptr, nullptr};
-  double* C[2] = {nullptr, nullptr};
-  double* Q[2] = {nullptr, nullptr};
-  double* E[2] = {nullptr, nullptr};
+  double* FM[2] = {nullptr, nullptr};
+  double* BM[2] = {nullptr, nullptr};
 };
 
 struct sbfwi_mesh_s {
@@ -236,7 +237,7 @@ struct CoarseWork {
          *scal = nullptr;
   unsigned* bar = nullptr;
   int nblocks = 0, nthreads = 0;
-  double *dtb = nullptr, *dyb = nullptr, *dxp = nullptr, *dcb = nullptr;   // direct solve
+  double *dyb = nullptr, *dxp = nullptr, *dbp = nullptr;   // direct solve: y, x, b by elimination position
 };
 int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS);
 void sbfwi_coarse_work_free(CoarseWork* w);
