@@ -34,7 +34,8 @@ class WaveProblem:
     mesh: handle from sbfwi_build_mesh; src [S] int64, wavelet [S, N_t] f64,
     rec [R] int64; n_ckpt as in sbfwi_forward (-1 = sqrt(T) checkpoints,
     >= N_t = full storage); mode: GRAD_EXACT or GRAD_PAPER_KERNEL; rtol: relative
-    residual of the coarse solves (the library default 1e-13 when None)."""
+    residual of the iterative coarse solves (the library default 1e-13 when None);
+    coarse_solver: 1 = direct (factored once per model), 0 = BiCGStab."""
     mesh: object
     c: float
     dt: float
@@ -46,6 +47,7 @@ class WaveProblem:
     n_ckpt: int = -1
     mode: int = GRAD_EXACT
     rtol: float = None
+    coarse_solver: int = 1
 
     @property
     def n_params(self) -> int:
@@ -59,7 +61,8 @@ class _Traces(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho, prob):
         rho_d = rho.detach().contiguous()
-        f = sbfwi_factor_elements(prob.mesh, rho_d, prob.c, prob.dt, prob.beta, prob.gamma)
+        f = sbfwi_factor_elements(prob.mesh, rho_d, prob.c, prob.dt, prob.beta, prob.gamma,
+                                  coarse_solver=prob.coarse_solver)
         if prob.rtol is not None:
             sbfwi_set_solver(f, prob.rtol, 500)
         traces = torch.zeros(prob.trace_shape(), dtype=torch.float64, device=rho.device)

@@ -42,6 +42,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--nt", type=int, default=4000)
     ap.add_argument("--shots", type=int, default=16)
+    ap.add_argument("--coarse-solver", type=int, default=1)
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import workloads as W
@@ -63,7 +64,7 @@ def main(argv=None):
            "time_steps": N, "shots": S, "units": units}
 
     def factor(rho):
-        return sbfwi_factor_elements(mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma)
+        return sbfwi_factor_elements(mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma, coarse_solver=args.coarse_solver)
 
     ft = factor(rho_t)
     observed = torch.zeros((S, R, N), dtype=torch.float64, device=dev)

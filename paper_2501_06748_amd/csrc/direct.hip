@@ -44,6 +44,7 @@ namespace {
 
 constexpr int kLeaf = 24;     // nodes per leaf supernode
 constexpr int DT = 256;       // threads per block of the solve kernels
+constexpr int kSubtrees = 512;// subtrees solved one per block at the bottom of the tree
 
 // ------------------------------------------------------------------ ordering
 
@@ -133,31 +134,17 @@ struct Dissect {
 // fixed butterfly inside each wavefront, then (rows wider than a wavefront)
 // the wavefronts of the row in index order, sum them.
 template <int NSM, bool FWD>
-__global__ void __launch_bounds__(DT) direct_rows_kernel(DirectDev d, int64_t row0, int64_t nrows, int G,
-                                                         const double* __restrict__ vals, int NS,
-                                                         const double* __restrict__ own,
-                                                         const double* __restrict__ done,
-                                                         double* __restrict__ out_pos,
-                                                         double* __restrict__ out_node, int* __restrict__ status) {
+__device__ __forceinline__ void row_dot(const DirectDev& d, const RowMeta& rm, bool valid, int lane, int G,
+                                        const double* __restrict__ vals, int NS, const double* __restrict__ own,
+                                        const double* __restrict__ done, double (&acc)[NSM]) {
   constexpr int U = NSM <= 4 ? 8 : 4;
-  __shared__ double red[DT / 64][NSM];
-  const int64_t gt = (int64_t)blockIdx.x * DT + threadIdx.x;
-  const int64_t r = gt / G;
-  const int lane = (int)(gt - r * G);
-  const bool valid = r < nrows;
-  double acc[NSM];
 #pragma unroll
   for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
-  int64_t j0 = 0;
-  int i = 0;
   if (valid) {
-    const int J = d.row_sn[row0 + r];
-    i = d.row_i[row0 + r];
-    j0 = d.sn_ptr[J];
-    const int nj = (int)(d.sn_ptr[J + 1] - j0);
-    const int64_t len = FWD ? nj + d.ncols[J] : nj + (d.b_ptr[J + 1] - d.b_ptr[J]);
-    const double* v = vals + (FWD ? d.fm_off[J] : d.bm_off[J]) + (int64_t)i * len;
-    const int64_t* cols = (FWD ? d.col_idx + d.cf_off[J] : d.bpos + d.b_ptr[J]) - nj;
+    const int64_t j0 = rm.j0, len = rm.len;
+    const int nj = rm.nj;
+    const double* v = vals + rm.val_off;
+    const int64_t* cols = (FWD ? d.col_idx : d.bpos) + rm.col_off - nj;
     for (int64_t k0 = lane; k0 < len; k0 += (int64_t)G * U) {
       double a[U];
       const double* src[U];
@@ -179,6 +166,45 @@ __global__ void __launch_bounds__(DT) direct_rows_kernel(DirectDev d, int64_t ro
   for (int m = 1; m < gw; m <<= 1)
 #pragma unroll
     for (int s = 0; s < NSM; ++s) acc[s] += __shfl_xor(acc[s], m, 64);
+}
+
+template <int NSM, bool FWD>
+__device__ __forceinline__ void row_store(const RowMeta& rm, int NS, const double (&acc)[NSM],
+                                          double* __restrict__ out_pos, double* __restrict__ out_node,
+                                          int* __restrict__ status) {
+  bool bad = false;
+  for (int s = 0; s < NS; ++s) {
+    out_pos[rm.pos * NS + s] = acc[s];
+    if (!FWD) out_node[rm.node * NS + s] = acc[s];
+    bad = bad || !isfinite(acc[s]);
+  }
+  if (bad) atomicOr(&status[0], 4);
+}
+
+// out[(J, i)] = sum_k M_J[i][k] src_k over the row of (J, i): the first n_J
+// entries read the vector `own` at J's own positions (the permuted right-hand
+// side forward, y backward), the rest read `done` at the row's column list
+// (the contributors' positions forward, B_J backward), values solved at
+// earlier levels.  G lanes per row (G a power of two up to the block) split
+// the entries lane-strided in chunks of U loads issued before their use; a
+// fixed butterfly inside each wavefront, then (rows wider than a wavefront)
+// the wavefronts of the row in index order, sum them.  One launch per level.
+template <int NSM, bool FWD>
+__global__ void __launch_bounds__(DT) direct_rows_kernel(DirectDev d, int64_t row0, int64_t nrows, int G,
+                                                         const double* __restrict__ vals, int NS,
+                                                         const double* __restrict__ own,
+                                                         const double* __restrict__ done,
+                                                         double* __restrict__ out_pos,
+                                                         double* __restrict__ out_node, int* __restrict__ status) {
+  __shared__ double red[DT / 64][NSM];
+  const int64_t gt = (int64_t)blockIdx.x * DT + threadIdx.x;
+  const int64_t r = gt / G;
+  const int lane = (int)(gt - r * G);
+  const bool valid = r < nrows;
+  RowMeta rm{};
+  if (valid) rm = (FWD ? d.fwd_rows : d.bwd_rows)[row0 + r];   // one 48-byte load per row
+  double acc[NSM];
+  row_dot<NSM, FWD>(d, rm, valid, lane, G, vals, NS, own, done, acc);
   if (G > 64) {   // rows wider than a wavefront: add the row's wavefronts in index order
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
@@ -186,23 +212,46 @@ __global__ void __launch_bounds__(DT) direct_rows_kernel(DirectDev d, int64_t ro
       for (int s = 0; s < NSM; ++s) red[wave][s] = acc[s];
     __syncthreads();
     if (lane == 0) {
-      const int w0 = wave, nw = G / 64;
+      const int nw = G / 64;
 #pragma unroll
       for (int s = 0; s < NSM; ++s) {
         double t = 0.0;
-        for (int q = 0; q < nw; ++q) t += red[w0 + q][s];
+        for (int q = 0; q < nw; ++q) t += red[wave + q][s];
         acc[s] = t;
       }
     }
   }
-  if (valid && lane == 0) {
-    bool bad = false;
-    for (int s = 0; s < NS; ++s) {
-      out_pos[(j0 + i) * NS + s] = acc[s];
-      if (!FWD) out_node[d.inv[j0 + i] * NS + s] = acc[s];
-      bad = bad || !isfinite(acc[s]);
+  if (valid && lane == 0) row_store<NSM, FWD>(rm, NS, acc, out_pos, out_node, status);
+}
+
+// The bottom of the dissection tree: one block per subtree (rooted at the cut
+// level) walks its levels in order -- deepest first forward, cut level first
+// backward -- with a block barrier between levels instead of a launch; rows
+// of a level use SG lanes each.
+template <int NSM, bool FWD>
+__global__ void __launch_bounds__(DT) direct_subtree_kernel(DirectDev d, const int64_t* __restrict__ seg, int NL,
+                                                            const int64_t* __restrict__ sub_rows,
+                                                            const double* __restrict__ vals, int NS,
+                                                            const double* __restrict__ own,
+                                                            const double* __restrict__ done,
+                                                            double* __restrict__ out_pos,
+                                                            double* __restrict__ out_node, int* __restrict__ status) {
+  constexpr int SG = 16;
+  const int64_t* sg = seg + (int64_t)blockIdx.x * (NL + 1);
+  const int lane = threadIdx.x % SG;
+  for (int q = 0; q < NL; ++q) {
+    const int li = FWD ? q : NL - 1 - q;   // segment li holds the rows of the li-th deepest level
+    const int64_t a = sg[li], e = sg[li + 1];
+    for (int64_t base = a; base < e; base += DT / SG) {
+      const int64_t r = base + threadIdx.x / SG;
+      const bool valid = r < e;
+      RowMeta rm{};
+      if (valid) rm = (FWD ? d.fwd_rows : d.bwd_rows)[sub_rows[r]];
+      double acc[NSM];
+      row_dot<NSM, FWD>(d, rm, valid, lane, SG, vals, NS, own, done, acc);
+      if (valid && lane == 0) row_store<NSM, FWD>(rm, NS, acc, out_pos, out_node, status);
     }
-    if (bad) atomicOr(&status[0], 4);
+    __syncthreads();   // this level's results are read by the next level of the block
   }
 }
 
@@ -357,6 +406,67 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
     ds->g_fwd[l] = lanes(lf);
     ds->g_bwd[l] = lanes(lb);
   }
+  // cut level: the shallowest level with at least kSubtrees supernodes; the
+  // subtrees rooted there are solved by one block each
+  ds->cut = ds->depth + 1;
+  for (int l = 0; l <= ds->depth; ++l)
+    if (ds->lvl_ptr[l + 1] - ds->lvl_ptr[l] >= kSubtrees) {
+      ds->cut = l;
+      break;
+    }
+  ds->n_sub = 0;
+  ds->NL = ds->depth - ds->cut + 1;
+  if (ds->cut <= ds->depth) {
+    ds->n_sub = ds->lvl_ptr[ds->cut + 1] - ds->lvl_ptr[ds->cut];
+    // row range of every supernode in the level-ordered row arrays
+    std::vector<int64_t> first_row(nS, 0);
+    for (int l = 0; l <= ds->depth; ++l) {
+      int64_t r = ds->row_ptr[l];
+      for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) {
+        const int J = ds->lvl_sn[q];
+        first_row[J] = r;
+        r += ds->sn_ptr[J + 1] - ds->sn_ptr[J];
+      }
+    }
+    ds->seg.assign((size_t)ds->n_sub * (ds->NL + 1), 0);
+    for (int b = 0; b < ds->n_sub; ++b) {
+      const int R = ds->lvl_sn[ds->lvl_ptr[ds->cut] + b];
+      std::vector<std::vector<int32_t>> by_level(ds->NL);   // index = depth - level
+      std::vector<int32_t> stack{R};
+      while (!stack.empty()) {
+        const int J = stack.back();
+        stack.pop_back();
+        by_level[ds->depth - ds->level[J]].push_back(J);
+        for (int c : ds->children[J]) stack.push_back(c);
+      }
+      for (int li = 0; li < ds->NL; ++li) {
+        ds->seg[(size_t)b * (ds->NL + 1) + li] = (int64_t)ds->sub_rows.size();
+        std::sort(by_level[li].begin(), by_level[li].end());
+        for (int J : by_level[li])
+          for (int64_t i = 0; i < ds->sn_ptr[J + 1] - ds->sn_ptr[J]; ++i) ds->sub_rows.push_back(first_row[J] + i);
+      }
+      ds->seg[(size_t)b * (ds->NL + 1) + ds->NL] = (int64_t)ds->sub_rows.size();
+    }
+  }
+  const int64_t nrows = (int64_t)ds->row_sn.size();
+  std::vector<RowMeta> fr(nrows), br(nrows);
+  for (int64_t q = 0; q < nrows; ++q) {
+    const int J = ds->row_sn[q], i = ds->row_i[q];
+    const int64_t j0 = ds->sn_ptr[J], nj = ds->sn_ptr[J + 1] - j0, nb = ds->b_ptr[J + 1] - ds->b_ptr[J];
+    RowMeta a{};
+    a.j0 = j0;
+    a.pos = j0 + i;
+    a.node = ds->inv[j0 + i];
+    a.nj = (int32_t)nj;
+    a.len = (int32_t)(nj + ds->ncols[J]);
+    a.val_off = ds->fm_off[J] + (int64_t)i * a.len;
+    a.col_off = ds->cf_off[J];
+    fr[q] = a;
+    a.len = (int32_t)(nj + nb);
+    a.val_off = ds->bm_off[J] + (int64_t)i * a.len;
+    a.col_off = ds->b_ptr[J];
+    br[q] = a;
+  }
   DirectDev& d = ds->d;
   SBFWI_CHECK(sbfwi_upload(&d.inv, ds->inv));
   SBFWI_CHECK(sbfwi_upload(&d.sn_ptr, ds->sn_ptr));
@@ -367,8 +477,12 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   SBFWI_CHECK(sbfwi_upload(&d.col_idx, ds->col_idx));
   SBFWI_CHECK(sbfwi_upload(&d.fm_off, ds->fm_off));
   SBFWI_CHECK(sbfwi_upload(&d.bm_off, ds->bm_off));
-  SBFWI_CHECK(sbfwi_upload(&d.row_sn, ds->row_sn));
-  SBFWI_CHECK(sbfwi_upload(&d.row_i, ds->row_i));
+  SBFWI_CHECK(sbfwi_upload(&d.fwd_rows, fr));
+  SBFWI_CHECK(sbfwi_upload(&d.bwd_rows, br));
+  if (ds->n_sub > 0) {
+    SBFWI_CHECK(sbfwi_upload(&ds->seg_dev, ds->seg));
+    SBFWI_CHECK(sbfwi_upload(&ds->sub_rows_dev, ds->sub_rows));
+  }
   return SBFWI_OK;
 }
 
@@ -376,7 +490,7 @@ void sbfwi_direct_sym_free(DirectSym* ds) {
   if (!ds) return;
   DirectDev& d = ds->d;
   void* ptrs[] = {d.inv, d.sn_ptr, d.b_ptr, d.bpos, d.ncols, d.cf_off, d.col_idx, d.fm_off, d.bm_off,
-                  d.row_sn, d.row_i};
+                  d.fwd_rows, d.bwd_rows, ds->seg_dev, ds->sub_rows_dev};
   for (void* p : ptrs) sbfwi_dev_free(p);
   delete ds;
 }
@@ -617,6 +731,15 @@ namespace {
 template <int NSM>
 void launch_rows(bool fwd, DirectSym* ds, int l, const double* vals, int NS, const double* vin,
                  const double* vdone, double* out_pos, double* out_node, int* status, hipStream_t s) {
+  if (l < 0) {   // the subtree blocks below the cut level
+    if (fwd)
+      hipLaunchKernelGGL((direct_subtree_kernel<NSM, true>), dim3(ds->n_sub), dim3(DT), 0, s, ds->d, ds->seg_dev,
+                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status);
+    else
+      hipLaunchKernelGGL((direct_subtree_kernel<NSM, false>), dim3(ds->n_sub), dim3(DT), 0, s, ds->d, ds->seg_dev,
+                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status);
+    return;
+  }
   const int64_t r0 = ds->row_ptr[l], nr = ds->row_ptr[l + 1] - r0;
   const int G = fwd ? ds->g_fwd[l] : ds->g_bwd[l];
   const unsigned blocks = (unsigned)((nr * G + DT - 1) / DT);
@@ -649,11 +772,14 @@ int sbfwi_direct_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
   const int64_t nn = f->m->n_nodes * w->NS;
   hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, f->m->n_nodes, w->NS,
                      ds->d.inv, b, w->dbp);
-  for (int l = ds->depth; l >= 0; --l)
+  // (levels at and below the cut level in one launch of subtree blocks, marked by level -1)
+  if (ds->n_sub > 0) launch_rows_ns(true, ds, -1, dn->FM[t], w->NS, w->dbp, w->dyb, w->dyb, nullptr, f->d.status, s);
+  for (int l = std::min(ds->depth, ds->cut - 1); l >= 0; --l)
     launch_rows_ns(true, ds, l, dn->FM[t], w->NS, w->dbp, w->dyb, w->dyb, nullptr, f->d.status, s);
   // backward, root first: x (by position and by node) from y and the solved B sets
-  for (int l = 0; l <= ds->depth; ++l)
+  for (int l = 0; l <= std::min(ds->depth, ds->cut - 1); ++l)
     launch_rows_ns(false, ds, l, dn->BM[t], w->NS, w->dyb, w->dxp, w->dxp, x, f->d.status, s);
+  if (ds->n_sub > 0) launch_rows_ns(false, ds, -1, dn->BM[t], w->NS, w->dyb, w->dxp, w->dxp, x, f->d.status, s);
   hipLaunchKernelGGL(count_solve_kernel, dim3(1), dim3(64), 0, s, f->d.status);
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;

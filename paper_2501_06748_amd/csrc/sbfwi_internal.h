@@ -58,6 +58,11 @@ struct MeshDev {
 #define ELL_SLICE 256
 #define ELL_LPR 4
 
+// One row of the direct solve: where its values, columns and output live.
+struct alignas(16) RowMeta {
+  int64_t val_off, col_off, j0, pos, node;
+  int32_t nj, len;
+};
 // Nested-dissection structure of the coarse system (direct.hip): device view.
 struct DirectDev {
   int64_t* inv = nullptr;      // [n] node at each elimination position
@@ -69,8 +74,8 @@ struct DirectDev {
   int64_t* col_idx = nullptr;  // contributor positions, supernode after supernode
   int64_t* fm_off = nullptr;   // [nS+1] forward row blocks: |J| x (|J| + ncols)
   int64_t* bm_off = nullptr;   // [nS+1] backward row blocks: |J| x (|J| + |B_J|)
-  int32_t* row_sn = nullptr;   // rows level by level: supernode
-  int32_t* row_i = nullptr;    //                      row within it
+  RowMeta* fwd_rows = nullptr;   // rows level by level (forward solve)
+  RowMeta* bwd_rows = nullptr;   // rows level by level (backward solve)
 };
 struct DirectSym {
   int nS = 0, depth = 0;
@@ -78,6 +83,9 @@ struct DirectSym {
   std::vector<int64_t> pos, inv, sn_ptr, b_ptr, bpos, ncols, cf_off, col_idx, fm_off, bm_off, row_ptr;
   std::vector<int32_t> level, lvl_ptr, lvl_sn, row_sn, row_i, g_fwd, g_bwd, snp;
   std::vector<std::vector<int32_t>> children, ctr;
+  int cut = 0, n_sub = 0, NL = 0;            // subtree blocks: cut level, their count, levels per subtree
+  std::vector<int64_t> seg, sub_rows;        // per subtree: row segments by level (deepest first)
+  int64_t *seg_dev = nullptr, *sub_rows_dev = nullptr;
   DirectDev d;
   int sn_of(int64_t p) const { return snp[p]; }
 };

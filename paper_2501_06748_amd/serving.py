@@ -214,7 +214,9 @@ class ShotServer:
     """slots: concurrent batches; budget_bytes: device memory budget (default 80 % of free);
     batching / cache / graphs: continuous batching, factor cache, graph replay of forward steps."""
 
-    def __init__(self, slots=4, budget_bytes=None, batching=True, cache=True, graphs=True, keep_grad=True):
+    def __init__(self, slots=4, budget_bytes=None, batching=True, cache=True, graphs=True, keep_grad=True,
+                 coarse_solver=1):
+        self.coarse_solver = coarse_solver
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = int(0.8 * free)
@@ -287,7 +289,8 @@ class ShotServer:
     def _build_model(self, mk, stream):
         h = self._hosts[mk]
         r = torch.tensor(h.rho, dtype=torch.float64, device="cuda")
-        f = sbfwi_factor_elements(h.handle, r, h.recipe.c, h.recipe.dt, 0.25, 0.5, stream=stream)
+        f = sbfwi_factor_elements(h.handle, r, h.recipe.c, h.recipe.dt, 0.25, 0.5, coarse_solver=self.coarse_solver,
+                                  stream=stream)
         if self.graphs:
             sbfwi_set_launch(f, LAUNCH_GRAPHS, 1)
         return _Model(f, sbfwi_mesh_info(h.handle)["n_params"])
