@@ -21,16 +21,21 @@
 // in elimination order lies in J and from the children's update matrices;
 // its first |J| pivots are eliminated without pivoting (K_g is dominated by
 // the a0-weighted mass term), giving L11, U11, L21 = F21 U11^-1,
-// U12 = L11^-1 F12 and the update F22 - L21 U12 for J's parent.  The device
-// keeps, per supernode and column-major, P = L11^-1, C = L21, Q = U11^-1 and
-// E = U12 (and the transposed set for K_g^T).
+// U12 = L11^-1 F12 and the update F22 - L21 U12 for J's parent.
 //
-// Solve (device, per level of the dissection tree, one block per supernode):
-// forward, deepest level first: t_J = b_J - (sum of the contributions
-// L21^(D) y_D of J's descendants D to J's rows, added in a fixed order),
-// y_J = P_J t_J, then J's own contribution C_J y_J to its B_J rows;
-// backward, root first: x_J = Q_J (y_J - E_J x_{B_J}).  No atomics: results
-// are bit-reproducible.
+// The device keeps, per supernode, two folded row blocks: forward
+// FM_J = [P | -P Lrow_J] with P = L11^-1 and Lrow_J the rows of L that J's
+// rows hold in the columns of earlier supernodes (its contributors), so that
+// y_J = FM_J [b_J ; y_contributors]; backward BM_J = [Q | -Q U12] with
+// Q = U11^-1, so that x_J = BM_J [y_J ; x_{B_J}].  K_g^T = U^T L^T has its own
+// pair.  Every row of a block is one dot product of a dense row with values
+// gathered at a column list.
+//
+// Solve (device): per level of the dissection tree one launch over all rows
+// of that level's supernodes -- forward deepest level first, backward root
+// first -- with the levels below the cut (where the tree has kSubtrees
+// supernodes) solved by one block per subtree.  No atomics: results are
+// bit-reproducible.
 #include <algorithm>
 #include <cmath>
 #include <atomic>

@@ -20,7 +20,7 @@ from ._gpu import log, rel_l2
 pytestmark = pytest.mark.gpu
 
 
-def _problem(wl, n_steps, n_ckpt=-1, mode=0):
+def _problem(wl, n_steps, n_ckpt=-1, mode=0, coarse_solver=1):
     import paper_2501_06748_amd as sb
     from paper_2501_06748_amd.autograd import WaveProblem
     m = wl.mesh
@@ -31,7 +31,7 @@ def _problem(wl, n_steps, n_ckpt=-1, mode=0):
                        wavelet=torch.tensor(np.ascontiguousarray(wl.wavelets[:, :n_steps]), dtype=torch.float64,
                                             device=dev),
                        rec=torch.tensor(wl.rec_nodes, dtype=torch.int64, device=dev),
-                       beta=wl.beta, gamma=wl.gamma, n_ckpt=n_ckpt, mode=mode)
+                       beta=wl.beta, gamma=wl.gamma, n_ckpt=n_ckpt, mode=mode, coarse_solver=coarse_solver)
 
 
 def _objective(prob, observed):
@@ -55,16 +55,17 @@ def _data(prob, rho_true):
         return simulate(torch.tensor(rho_true, dtype=torch.float64, device="cuda"), prob)
 
 
-def test_backward_equals_library_gradient_and_oracle():
+@pytest.mark.parametrize("coarse_solver", [1, 0])
+def test_backward_equals_library_gradient_and_oracle(coarse_solver):
     import paper_2501_06748_amd as sb
     wl = W.config_tiny(n_steps=48)
-    prob = _problem(wl, 48)
+    prob = _problem(wl, 48, coarse_solver=coarse_solver)
     rho = torch.tensor(wl.models["random30"], dtype=torch.float64, device="cuda")
     obs = _data(prob, wl.models["void_floor_half"])
-    log("autograd backward vs sbfwi_gradient vs oracle (tiny, 48 steps)")
+    log(f"autograd backward vs sbfwi_gradient vs oracle (tiny, 48 steps, coarse solver {coarse_solver})")
     J = _objective(prob, obs)
     val, g = _value_and_grad(J, rho)
-    f = sb.sbfwi_factor_elements(prob.mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma)
+    f = sb.sbfwi_factor_elements(prob.mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma, coarse_solver=coarse_solver)
     tr = torch.zeros(prob.trace_shape(), dtype=torch.float64, device="cuda")
     ck = sb.sbfwi_forward(f, prob.src, prob.wavelet, prob.rec, tr, n_ckpt=-1)
     mis = torch.zeros(1, dtype=torch.float64, device="cuda")
