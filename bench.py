@@ -154,6 +154,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--coarse-solver", type=int, default=1,
                     help="0: BiCGStab every step; 1: nested-dissection LU factored once per model (default)")
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="1: forward steps replayed from HIP graphs (their launches are then not seen by the "
+                         "live kernel timing)")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="1: sweep launch plan autotuned once per mesh and shot count, before the timed region")
     ap.add_argument("--counter-probe", type=int, default=0, metavar="K",
                     help="run K gradient steps of the workload (--nt steps each) plus a 1 GiB device copy, "
                          "print nothing else and exit: the program profiled by hardware-counter runs")
@@ -184,10 +189,16 @@ def main():
     misfit = torch.zeros(1, dtype=torch.float64, device=dev)
     grad = torch.zeros(info["n_params"], dtype=torch.float64, device=dev)
 
+    plan = None
+
     def factor(rho):
         f = sb.sbfwi_factor_elements(mh, rho, wl.c, wl.dt, wl.beta, wl.gamma, coarse_solver=args.coarse_solver)
         if args.solver_iters:
             sb.sbfwi_set_launch(f, 0, args.solver_iters)
+        if args.graphs:
+            sb.sbfwi_set_launch(f, sb.LAUNCH_GRAPHS, 1)
+        if plan is not None:
+            sb.apply_plan(f, plan)
         return f
 
     if args.counter_probe:
@@ -205,9 +216,11 @@ def main():
         print("[bench] counter probe done", file=sys.stderr, flush=True)
         return
 
-    # observed data (outside the timed region)
+    # observed data and the launch plan (outside the timed region)
     ft = factor(rho_true)
     sb.sbfwi_forward(ft, src, wav, rec, observed)
+    if args.autotune:
+        plan = sb.sbfwi_autotune(ft, S)
     ft.close()
     torch.cuda.synchronize()
     print(f"[bench] observed data simulated ({wl.name}, {S} shots, {N} steps)", file=sys.stderr, flush=True)
@@ -286,6 +299,7 @@ def main():
                    "shots": S, "receivers": R, "dt": wl.dt, "checkpoints": "sqrt(T)", "gradient": "exact",
                    "coarse_solver": "nested-dissection LU, factored per model" if args.coarse_solver == 1
                    else "BiCGStab, rtol 1e-13",
+                   "graphs": bool(args.graphs), "launch_plan": "autotuned" if plan is not None else "default",
                    "units_per_step": units},
         "roofline": roof,
         "kernel_ms_per_step_warmup": breakdown,

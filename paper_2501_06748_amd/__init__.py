@@ -172,6 +172,16 @@ def launch_param_fused(sweep: int) -> int:
     return 30 + sweep
 
 
+def apply_plan(f: FactorsHandle, plan: dict) -> None:
+    """Sets the launch plan returned by sbfwi_autotune (for the same mesh and shot count) on
+    other factors, e.g. those of the next model of an inversion."""
+    kinds = ["condense", "recover", "adj_condense", "adj_recover"]
+    for i, k in enumerate(kinds):
+        for cl, v in enumerate(plan[k]["shots_per_block"]):
+            sbfwi_set_launch(f, launch_param_shots(i, cl), int(v))
+        sbfwi_set_launch(f, launch_param_fused(i), int(plan[k]["fused"]))
+
+
 def sbfwi_copy_factor_data(f: FactorsHandle, which: int, count: int) -> np.ndarray:
     out = np.empty(count, dtype=np.float64)
     check(lib().sbfwi_copy_factor_data(f, int(which), out.ctypes.data_as(C.c_void_p)))

@@ -306,71 +306,73 @@ __global__ void adj_nodal_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a) {
   a.AB[g] = f.c3 * vb + f.a2 * wb;
 }
 
-// Exact gradient for one step: one wavefront per (element, shot group).  The
-// forward unknowns X (levels m-2 .. m+2) and adjoint rows lambda (m-1 .. m+1)
-// live in rolling LDS windows; for every level m the band entries of the
-// sensitivities E-bar of E0, E1, E2 (and lambda_m a_m^T for M0) are formed per
-// item (i, s), then contracted with the per-segment density derivatives alpha
-// (staged in LDS once per element) and summed over the shots of the group.
-// The global loads of the next level's X, lambda and a are issued before the
-// current level is computed and land in the windows after it, so the level
-// recursion does not wait on memory.
-template <int NBT, int S>
-struct GradLds {
-  double X[5][NBT * S];
-  double L[3][NBT * S];
-  double A[NBT * S];
-  double E[3][3][NBT * S];   // [tau][sub, diag, super][item]
-  double M[3][NBT * S];
-  double g[NBT * S];
-  double gb[NBT * 32];       // alpha of the element's segments
-};
+// Lanes of one wavefront exchanging values through LDS: the LDS operations of
+// a wave complete in issue order, so only the compiler's code motion has to be
+// fenced (the block of these kernels is exactly one wavefront).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
+// Exact gradient for one step: one wavefront per (element, group of S shots),
+// one item (boundary node i, shot s) per lane.  At level m the band entries of
+// the sensitivities of E0, E1, E2 and M0 are short sums of products of
+// quantities of the two nodes involved:
+//   e0(i, j) = sum_a lam_i[a] Q_j[a]        e1(i, j) = sum_a R_i[a] lam_j[a] - lam_i[1] T_j
+//   e2(i, j) = -lam_i[1] X_j(m)             m0(i, j) = lam_i[1] acc_j(m)
+// with lam[a] the adjoint rows m-1, m, m+1 and Q, R, T the forward unknowns'
+// radial differences weighted by the FD stencil of every row that touches
+// level m (one-sided at the ends, plus the flux rows at xi0 and at the
+// boundary).  Each lane forms the 12 quantities of its node from register
+// windows of X (levels m-2 .. m+2), lam (rows m-1 .. m+1) and the
+// accelerations (level m), publishes them in LDS, evaluates the four band
+// entries of the segment (i, i+1) it owns and contracts them with that
+// segment's density derivatives alpha (registers): the end-0 part is node i's,
+// the end-1 part goes to node i+1 through LDS.  The next level's X, lam and
+// accelerations are loaded while the current level is computed; the results
+// of GCH levels collect in LDS and are added to the gradient together.
 template <int NBT, int S>
 __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restrict__ elems, MeshDev m,
                                                         FactorsDev f, int NS, const double* __restrict__ X,
                                                         const double* __restrict__ lam,
                                                         const double* __restrict__ acc_a,
                                                         double* __restrict__ grad, int s0, int64_t shot_stride) {
-  constexpr int IPT = (NBT * S + WT - 1) / WT;   // items per thread
-  __shared__ GradLds<NBT, S> L;
+  static_assert(NBT * S <= WT, "one (node, shot) item per lane");
+  constexpr int GCH = 16;
+  __shared__ double V[12][NBT * S];   // the level's per-node quantities, by item
+  __shared__ double C1[NBT * S];      // end-1 parts, by receiving item
+  __shared__ double Gb[GCH][NBT * S]; // gradient per level of the chunk and item
   const int e = elems[blockIdx.x];
   const int ns = min(S, NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1;
   const int64_t po = m.par_off[e], lo = m.loop_off[e], xo = m.x_off[e];
   const double h = (1.0 - m.xi0) / n, xi0 = m.xi0;
-  const int items = nb * S;
-  auto xs = [&](int l) { return (l + 2) % 5; };
-  auto ls = [&](int r) { return (r + 1) % 3; };
-  // registers of the prefetched level
-  double px[IPT], pl[IPT], pa[IPT];
-  auto fetch_x = [&](int l) {
+  const int it = threadIdx.x;
+  const bool own = it < nb * S;           // the lane holds an item (node i, shot s)
+  const int i = own ? it / S : 0, s = it % S;
+  const bool act = own && s < ns;         // ... of a shot of the run
+  const int itp = md(i + 1, nb) * S + s;  // item of node i + 1, end 1 of segment (i, i + 1)
+  const bool summed = shot_stride == 0;
+  double al[32];   // alpha of segment (i, i + 1): [tau * 8 + end * 4 + k], then M0 at 24 + end * 4 + k
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      const int it = threadIdx.x + u * WT, i = it / S, s = it % S;
-      px[u] = (it < items && s < ns) ? X[(xo + (int64_t)(l + 1) * nb + i) * NS + s0 + s] : 0.0;
-    }
+  for (int q = 0; q < 32; ++q) al[q] = own ? f.gbasis[32 * (lo + i) + q] : 0.0;
+  // loads are unconditional (a lane without a value reads word 0 and drops it), so
+  // that the waits for the prefetched level do not depend on branches
+  auto ldx = [&](int l) -> double {
+    const bool ok = act && l <= n + 1;
+    const double v = X[ok ? (xo + (int64_t)(l + 1) * nb + i) * NS + s0 + s : 0];
+    return ok ? v : 0.0;
   };
-  auto fetch_l = [&](int r) {
-#pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      const int it = threadIdx.x + u * WT, i = it / S, s = it % S;
-      pl[u] = (it < items && s < ns) ? lam[(xo + (int64_t)(r + 1) * nb + i) * NS + s0 + s] : 0.0;
-    }
+  auto ldl = [&](int r) -> double {
+    const bool ok = act && r <= n + 1;
+    const double v = lam[ok ? (xo + (int64_t)(r + 1) * nb + i) * NS + s0 + s : 0];
+    return ok ? v : 0.0;
   };
-  auto fetch_a = [&](int lev) {
-#pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      const int it = threadIdx.x + u * WT, i = it / S, s = it % S;
-      pa[u] = (it < items && s < ns) ? acc_a[(po + (int64_t)lev * nb + i) * NS + s0 + s] : 0.0;
-    }
-  };
-  auto put = [&](double* dst, const double (&v)[IPT]) {
-#pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-      const int it = threadIdx.x + u * WT;
-      if (it < items) dst[it] = v[u];
-    }
+  auto lda = [&](int l) -> double {
+    const bool ok = act && l <= n;
+    const double v = acc_a[ok ? (po + (int64_t)l * nb + i) * NS + s0 + s : 0];
+    return ok ? v : 0.0;
   };
   // FD weight of level mm in the radial derivative at row r (one-sided at the ends)
   auto dw = [&](int r, int mm) -> double {
@@ -378,101 +380,92 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
     if (r == n) return mm == n - 1 ? -1.0 / h : (mm == n ? 1.0 / h : 0.0);
     return mm == r - 1 ? -0.5 / h : (mm == r + 1 ? 0.5 / h : 0.0);
   };
-  // start: windows hold X(-1 .. 2), lambda(-1 .. 1), a(0); registers hold the next level
-  for (int q = threadIdx.x; q < nb * 32; q += WT) L.gb[q] = f.gbasis[32 * lo + q];
-  for (int l = -1; l <= 2 && l <= n + 1; ++l) {
-    fetch_x(l);
-    put(L.X[xs(l)], px);
-  }
-  for (int r = -1; r <= 1 && r <= n + 1; ++r) {
-    fetch_l(r);
-    put(L.L[ls(r)], pl);
-  }
-  fetch_a(0);
-  put(L.A, pa);
-  __syncthreads();
+  // windows at level 0 (X(-2) does not exist: its weights are zero)
+  double x0 = 0.0, x1 = ldx(-1), x2 = ldx(0), x3 = ldx(1), x4 = ldx(2);
+  double l0 = ldl(-1), l1 = ldl(0), l2 = ldl(1);
+  double aw = lda(0);
   for (int lev = 0; lev <= n; ++lev) {
-    const bool nx = lev + 3 <= n + 1, nl = lev + 2 <= n + 1, na = lev + 1 <= n;
-    if (nx) fetch_x(lev + 3);
-    if (nl) fetch_l(lev + 2);
-    if (na) fetch_a(lev + 1);
-    const double xm = xi0 + h * lev;
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      auto Xv = [&](int l, int node) { return L.X[xs(l)][node * S + s]; };
-      auto Lv = [&](int r, int node) { return L.L[ls(r)][node * S + s]; };
-      const int jn[3] = {md(i - 1, nb), i, md(i + 1, nb)};   // sub, diag, super columns
-      for (int t = 0; t < 3; ++t) {
-        const int j = jn[t];
-        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-        {  // row lev itself
-          double dj = Xv(lev + 1, j) - Xv(lev - 1, j);
-          double di = Xv(lev + 1, i) - Xv(lev - 1, i);
-          double lap = Xv(lev - 1, j) - 2.0 * Xv(lev, j) + Xv(lev + 1, j);
-          e0 += Lv(lev, i) * (xm * xm / (h * h) * lap + xm / (2.0 * h) * dj);
-          e1 += xm / (2.0 * h) * (di * Lv(lev, j) - Lv(lev, i) * dj);
-          e2 -= Lv(lev, i) * Xv(lev, j);
-        }
-        for (int r = lev - 1; r <= lev + 1; ++r) {  // rows whose radial derivative uses this level
-          if (r < 0 || r > n) continue;
-          double w = dw(r, lev);
-          if (w == 0.0) continue;
-          double xr = xi0 + h * r;
-          e0 += w * xr * xr / (2.0 * h) * Lv(r, i) * (Xv(r + 1, j) - Xv(r - 1, j));
-          e1 += w * xr * Xv(r, i) * Lv(r, j);
-        }
-        if (lev == 0) {  // flux row at xi0
-          e0 += xi0 / (2.0 * h) * Lv(-1, i) * (Xv(1, j) - Xv(-1, j));
-          e1 += Xv(0, i) * Lv(-1, j);
-        }
-        if (lev == n) {  // flux row at the boundary
-          e0 += (xi0 + h * n) / (2.0 * h) * Lv(n + 1, i) * (Xv(n + 1, j) - Xv(n - 1, j));
-          e1 += Xv(n, i) * Lv(n + 1, j);
-        }
-        L.E[0][t][it] = e0;
-        L.E[1][t][it] = e1;
-        L.E[2][t][it] = e2;
-        L.M[t][it] = Lv(lev, i) * L.A[j * S + s];
-      }
+    const double px = ldx(lev + 3), pl = ldl(lev + 2), pa = lda(lev + 1);
+    const double xm = xi0 + h * lev, hm = xm / (2.0 * h);
+    // weights of rows lev - 1, lev, lev + 1: c for the E0 terms, b for the E1 terms
+    double cw[3], bw[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int r = lev - 1 + a;
+      const double w = (r >= 0 && r <= n) ? dw(r, lev) : 0.0, xr = xi0 + h * r;
+      cw[a] = w * xr * xr / (2.0 * h);
+      bw[a] = w * xr;
     }
-    __syncthreads();
-    // the windows' oldest slots are free now: the prefetched level moves in
-    if (nx) put(L.X[xs(lev + 3)], px);
-    if (nl) put(L.L[ls(lev + 2)], pl);
-    if (na) put(L.A, pa);
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int k = it / S, s = it % S;
-      int km = md(k - 1, nb), kp = md(k + 1, nb);
-      const double* gl = L.gb + 32 * km;   // segment (km, k): k is its end 1
-      const double* gr = L.gb + 32 * k;    // segment (k, kp): k is its end 0
-      auto D = [&](const double (*T)[NBT * S], int node, int t) { return T[t][node * S + s]; };
-      double acc = 0.0;
-      for (int tau = 0; tau < 3; ++tau) {
-        const double (*T)[NBT * S] = L.E[tau];
-        const double* al = gl + tau * 8 + 4;
-        const double* ar = gr + tau * 8;
-        acc -= al[0] * D(T, km, 1) + al[1] * D(T, km, 2) + al[2] * D(T, k, 0) + al[3] * D(T, k, 1);
-        acc -= ar[0] * D(T, k, 1) + ar[1] * D(T, k, 2) + ar[2] * D(T, kp, 0) + ar[3] * D(T, kp, 1);
-      }
-      const double* ml = gl + 24 + 4;
-      const double* mr = gr + 24;
-      acc += xm * xm * (ml[0] * D(L.M, km, 1) + ml[1] * D(L.M, km, 2) + ml[2] * D(L.M, k, 0) + ml[3] * D(L.M, k, 1) +
-                        mr[0] * D(L.M, k, 1) + mr[1] * D(L.M, k, 2) + mr[2] * D(L.M, kp, 0) + mr[3] * D(L.M, kp, 1));
-      L.g[it] = s < ns ? acc : 0.0;
+    const double f0 = lev == 0 ? xi0 / (2.0 * h) : 0.0, g0 = lev == 0 ? 1.0 : 0.0;
+    const double fn = lev == n ? (xi0 + h * n) / (2.0 * h) : 0.0, gn = lev == n ? 1.0 : 0.0;
+    // this node's quantities
+    const double dm = x2 - x0, d0 = x3 - x1, dp = x4 - x2, T = hm * d0;
+    const double Lp[3] = {l0, l1, l2};
+    const double Qp[3] = {cw[0] * dm + f0 * d0, xm * xm / (h * h) * (x1 - 2.0 * x2 + x3) + T + cw[1] * d0,
+                          cw[2] * dp + fn * d0};
+    const double Rp[3] = {bw[0] * x1 + g0 * x2, T + bw[1] * x2, bw[2] * x3 + gn * x2};
+    if (own) {
+      V[0][it] = Lp[0]; V[1][it] = Lp[1]; V[2][it] = Lp[2];
+      V[3][it] = Qp[0]; V[4][it] = Qp[1]; V[5][it] = Qp[2];
+      V[6][it] = Rp[0]; V[7][it] = Rp[1]; V[8][it] = Rp[2];
+      V[9][it] = T; V[10][it] = x2; V[11][it] = aw;
     }
-    __syncthreads();
-    if (shot_stride == 0) {   // summed over the shots of the run
-      for (int k = threadIdx.x; k < nb; k += WT) {
-        double t = 0.0;
-        for (int s = 0; s < S; ++s) t += L.g[k * S + s];
-        grad[po + (int64_t)lev * nb + k] += t;
+    wave_lds_sync();
+    double end0 = 0.0;
+    if (own) {
+      double Lq[3], Qq[3], Rq[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        Lq[a] = V[a][itp];
+        Qq[a] = V[3 + a][itp];
+        Rq[a] = V[6 + a][itp];
       }
-    } else {                  // one gradient per shot
-      for (int it = threadIdx.x; it < items; it += WT) {
-        const int k = it / S, s = it % S;
-        if (s < ns) grad[(s0 + s) * shot_stride + po + (int64_t)lev * nb + k] += L.g[it];
+      const double Tq = V[9][itp], Xq = V[10][itp], Aq = V[11][itp];
+      // band entries (p, p), (p, q), (q, p), (q, q) of the segment, p = i, q = i + 1
+      const double E0[4] = {Lp[0] * Qp[0] + Lp[1] * Qp[1] + Lp[2] * Qp[2],
+                            Lp[0] * Qq[0] + Lp[1] * Qq[1] + Lp[2] * Qq[2],
+                            Lq[0] * Qp[0] + Lq[1] * Qp[1] + Lq[2] * Qp[2],
+                            Lq[0] * Qq[0] + Lq[1] * Qq[1] + Lq[2] * Qq[2]};
+      const double E1[4] = {Rp[0] * Lp[0] + Rp[1] * Lp[1] + Rp[2] * Lp[2] - Lp[1] * T,
+                            Rp[0] * Lq[0] + Rp[1] * Lq[1] + Rp[2] * Lq[2] - Lp[1] * Tq,
+                            Rq[0] * Lp[0] + Rq[1] * Lp[1] + Rq[2] * Lp[2] - Lq[1] * T,
+                            Rq[0] * Lq[0] + Rq[1] * Lq[1] + Rq[2] * Lq[2] - Lq[1] * Tq};
+      const double E2[4] = {-Lp[1] * x2, -Lp[1] * Xq, -Lq[1] * x2, -Lq[1] * Xq};
+      const double M0[4] = {Lp[1] * aw, Lp[1] * Aq, Lq[1] * aw, Lq[1] * Aq};
+      double s0e = 0.0, s1e = 0.0, s0m = 0.0, s1m = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s0e += al[k] * E0[k] + al[8 + k] * E1[k] + al[16 + k] * E2[k];
+        s1e += al[4 + k] * E0[k] + al[12 + k] * E1[k] + al[20 + k] * E2[k];
+        s0m += al[24 + k] * M0[k];
+        s1m += al[28 + k] * M0[k];
       }
+      end0 = xm * xm * s0m - s0e;
+      C1[itp] = xm * xm * s1m - s1e;
     }
+    wave_lds_sync();
+    if (own) Gb[lev % GCH][it] = end0 + C1[it];   // C1[it] from the lane of segment (i - 1, i)
+    if (lev % GCH == GCH - 1 || lev == n) {       // add the chunk's levels to the gradient
+      wave_lds_sync();
+      const int l0c = lev - lev % GCH, nl = lev - l0c + 1;
+      if (summed) {
+        for (int q = it; q < nl * nb; q += WT) {
+          const int l = q / nb, k = q % nb;
+          double t = 0.0;
+          for (int u = 0; u < ns; ++u) t += Gb[l][k * S + u];
+          grad[po + (int64_t)(l0c + l) * nb + k] += t;
+        }
+      } else {
+        for (int q = it; q < nl * nb * ns; q += WT) {
+          const int l = q / (nb * ns), r = q % (nb * ns), k = r / ns, u = r % ns;
+          grad[(int64_t)(s0 + u) * shot_stride + po + (int64_t)(l0c + l) * nb + k] += Gb[l][k * S + u];
+        }
+      }
+      wave_lds_sync();
+    }
+    x0 = x1; x1 = x2; x2 = x3; x3 = x4; x4 = px;
+    l0 = l1; l1 = l2; l2 = pl;
+    aw = pa;
   }
 }
 
@@ -608,9 +601,10 @@ void launch_grad_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, int NS, const
 template <int S>
 void launch_grad_all(sbfwi_mesh_s* m, const FactorsDev& f, int NS, const double* X, const double* lam,
                      const double* acc, double* grad, int64_t stride, hipStream_t st) {
+  // at most one item per lane: 8 shots per group for n_b <= 8, 4 for <= 16, 2 for <= 24
   launch_grad_cls<8, S>(m, 0, f, NS, X, lam, acc, grad, stride, st);
-  launch_grad_cls<16, S>(m, 1, f, NS, X, lam, acc, grad, stride, st);
-  launch_grad_cls<24, S>(m, 2, f, NS, X, lam, acc, grad, stride, st);
+  launch_grad_cls<16, (S < 4 ? S : 4)>(m, 1, f, NS, X, lam, acc, grad, stride, st);
+  launch_grad_cls<24, (S < 2 ? S : 2)>(m, 2, f, NS, X, lam, acc, grad, stride, st);
 }
 
 // stride 0: gradient summed over shots; stride n_params: one gradient per shot

@@ -639,9 +639,8 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS) {
   SBFWI_CHECK(sbfwi_alloc(&w->bar, 64 + 32 * ((w->nblocks + 15) / 16 + 1)));
   SBFWI_CHECK(sbfwi_zero_sync(w->bar, sizeof(unsigned) * (64 + 32 * ((w->nblocks + 15) / 16 + 1))));
   if (m->dsym) {   // direct solve: forward and backward results by elimination position
-    SBFWI_CHECK(sbfwi_alloc(&w->dyb, 3 * sz));
+    SBFWI_CHECK(sbfwi_alloc(&w->dyb, 2 * sz));
     w->dxp = w->dyb + sz;
-    w->dbp = w->dxp + sz;
   }
   return SBFWI_OK;
 }

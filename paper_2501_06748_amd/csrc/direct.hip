@@ -131,8 +131,8 @@ struct Dissect {
 };
 
 // out[(J, i)] = sum_k M_J[i][k] src_k over the row of (J, i): the first n_J
-// entries read the vector `own` at J's own positions (the permuted right-hand
-// side forward, y backward), the rest read `done` at the row's column list
+// entries read the vector `own` at J's own positions (the right-hand side by
+// node forward, y backward), the rest read `done` at the row's column list
 // (the contributors' positions forward, B_J backward), values solved at
 // earlier levels.  G lanes per row (G a power of two up to the block) split
 // the entries lane-strided in chunks of U loads issued before their use; a
@@ -158,7 +158,10 @@ __device__ __forceinline__ void row_dot(const DirectDev& d, const RowMeta& rm, b
         const int64_t k = k0 + (int64_t)u * G;
         const bool ok = k < len;
         a[u] = ok ? v[k] : 0.0;
-        src[u] = !ok ? own + j0 * NS : (k < nj ? own + (j0 + k) * NS : done + cols[k] * NS);
+        if (FWD)   // own = the right-hand side by node: position j0 + k holds node inv[j0 + k]
+          src[u] = !ok ? own : (k < nj ? own + d.inv[j0 + k] * NS : done + cols[k] * NS);
+        else
+          src[u] = !ok ? own + j0 * NS : (k < nj ? own + (j0 + k) * NS : done + cols[k] * NS);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -187,8 +190,8 @@ __device__ __forceinline__ void row_store(const RowMeta& rm, int NS, const doubl
 }
 
 // out[(J, i)] = sum_k M_J[i][k] src_k over the row of (J, i): the first n_J
-// entries read the vector `own` at J's own positions (the permuted right-hand
-// side forward, y backward), the rest read `done` at the row's column list
+// entries read the vector `own` at J's own positions (the right-hand side by
+// node forward, y backward), the rest read `done` at the row's column list
 // (the contributors' positions forward, B_J backward), values solved at
 // earlier levels.  G lanes per row (G a power of two up to the block) split
 // the entries lane-strided in chunks of U loads issued before their use; a
@@ -200,8 +203,10 @@ __global__ void __launch_bounds__(DT) direct_rows_kernel(DirectDev d, int64_t ro
                                                          const double* __restrict__ own,
                                                          const double* __restrict__ done,
                                                          double* __restrict__ out_pos,
-                                                         double* __restrict__ out_node, int* __restrict__ status) {
+                                                         double* __restrict__ out_node, int* __restrict__ status,
+                                                         int count) {
   __shared__ double red[DT / 64][NSM];
+  if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
   const int64_t gt = (int64_t)blockIdx.x * DT + threadIdx.x;
   const int64_t r = gt / G;
   const int lane = (int)(gt - r * G);
@@ -240,8 +245,10 @@ __global__ void __launch_bounds__(DT) direct_subtree_kernel(DirectDev d, const i
                                                             const double* __restrict__ own,
                                                             const double* __restrict__ done,
                                                             double* __restrict__ out_pos,
-                                                            double* __restrict__ out_node, int* __restrict__ status) {
+                                                            double* __restrict__ out_node, int* __restrict__ status,
+                                                            int count) {
   constexpr int SG = 16;
+  if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
   const int64_t* sg = seg + (int64_t)blockIdx.x * (NL + 1);
   const int lane = threadIdx.x % SG;
   for (int q = 0; q < NL; ++q) {
@@ -260,18 +267,6 @@ __global__ void __launch_bounds__(DT) direct_subtree_kernel(DirectDev d, const i
   }
 }
 
-// right-hand side by elimination position
-__global__ void permute_kernel(int64_t n, int NS, const int64_t* __restrict__ inv, const double* __restrict__ b,
-                               double* __restrict__ bp) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n * NS) return;
-  const int64_t p = g / NS;
-  bp[g] = b[inv[p] * NS + (g - p * NS)];
-}
-
-__global__ void count_solve_kernel(int* status) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);
-}
 
 // Runs fn(i) for i in [0, n) on up to `threads` host threads (dynamic assignment).
 template <typename Fn>
@@ -735,14 +730,14 @@ namespace {
 
 template <int NSM>
 void launch_rows(bool fwd, DirectSym* ds, int l, const double* vals, int NS, const double* vin,
-                 const double* vdone, double* out_pos, double* out_node, int* status, hipStream_t s) {
+                 const double* vdone, double* out_pos, double* out_node, int* status, int count, hipStream_t s) {
   if (l < 0) {   // the subtree blocks below the cut level
     if (fwd)
       hipLaunchKernelGGL((direct_subtree_kernel<NSM, true>), dim3(ds->n_sub), dim3(DT), 0, s, ds->d, ds->seg_dev,
-                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status);
+                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status, count);
     else
       hipLaunchKernelGGL((direct_subtree_kernel<NSM, false>), dim3(ds->n_sub), dim3(DT), 0, s, ds->d, ds->seg_dev,
-                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status);
+                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status, count);
     return;
   }
   const int64_t r0 = ds->row_ptr[l], nr = ds->row_ptr[l + 1] - r0;
@@ -750,19 +745,19 @@ void launch_rows(bool fwd, DirectSym* ds, int l, const double* vals, int NS, con
   const unsigned blocks = (unsigned)((nr * G + DT - 1) / DT);
   if (fwd)
     hipLaunchKernelGGL((direct_rows_kernel<NSM, true>), dim3(blocks), dim3(DT), 0, s, ds->d, r0, nr, G, vals, NS,
-                       vin, vdone, out_pos, out_node, status);
+                       vin, vdone, out_pos, out_node, status, count);
   else
     hipLaunchKernelGGL((direct_rows_kernel<NSM, false>), dim3(blocks), dim3(DT), 0, s, ds->d, r0, nr, G, vals, NS,
-                       vin, vdone, out_pos, out_node, status);
+                       vin, vdone, out_pos, out_node, status, count);
 }
 
 void launch_rows_ns(bool fwd, DirectSym* ds, int l, const double* vals, int NS, const double* vin,
-                    const double* vdone, double* out_pos, double* out_node, int* status, hipStream_t s) {
-  if (NS == 1) launch_rows<1>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
-  else if (NS == 2) launch_rows<2>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
-  else if (NS <= 4) launch_rows<4>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
-  else if (NS <= 8) launch_rows<8>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
-  else launch_rows<16>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, s);
+                    const double* vdone, double* out_pos, double* out_node, int* status, int count, hipStream_t s) {
+  if (NS == 1) launch_rows<1>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
+  else if (NS == 2) launch_rows<2>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
+  else if (NS <= 4) launch_rows<4>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
+  else if (NS <= 8) launch_rows<8>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
+  else launch_rows<16>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
 }
 
 }  // namespace
@@ -772,20 +767,19 @@ int sbfwi_direct_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
   DirectSym* ds = f->m->dsym;
   DirectNum* dn = f->dnum;
   const int t = transpose ? 1 : 0;
+  const int NS = w->NS;
+  int* st = f->d.status;
   ProfScope ps(PK_SOLVE, s);
-  // forward, deepest level first: y (by position) from b (permuted to positions) and the contributors' y
-  const int64_t nn = f->m->n_nodes * w->NS;
-  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, f->m->n_nodes, w->NS,
-                     ds->d.inv, b, w->dbp);
-  // (levels at and below the cut level in one launch of subtree blocks, marked by level -1)
-  if (ds->n_sub > 0) launch_rows_ns(true, ds, -1, dn->FM[t], w->NS, w->dbp, w->dyb, w->dyb, nullptr, f->d.status, s);
-  for (int l = std::min(ds->depth, ds->cut - 1); l >= 0; --l)
-    launch_rows_ns(true, ds, l, dn->FM[t], w->NS, w->dbp, w->dyb, w->dyb, nullptr, f->d.status, s);
-  // backward, root first: x (by position and by node) from y and the solved B sets
-  for (int l = 0; l <= std::min(ds->depth, ds->cut - 1); ++l)
-    launch_rows_ns(false, ds, l, dn->BM[t], w->NS, w->dyb, w->dxp, w->dxp, x, f->d.status, s);
-  if (ds->n_sub > 0) launch_rows_ns(false, ds, -1, dn->BM[t], w->NS, w->dyb, w->dxp, w->dxp, x, f->d.status, s);
-  hipLaunchKernelGGL(count_solve_kernel, dim3(1), dim3(64), 0, s, f->d.status);
+  const int top = std::min(ds->depth, ds->cut - 1);   // deepest level launched on its own
+  // forward, deepest level first: y (by position) from b (by node) and the contributors' y;
+  // the levels at and below the cut level run in one launch of subtree blocks (level -1)
+  if (ds->n_sub > 0) launch_rows_ns(true, ds, -1, dn->FM[t], NS, b, w->dyb, w->dyb, nullptr, st, 0, s);
+  for (int l = top; l >= 0; --l) launch_rows_ns(true, ds, l, dn->FM[t], NS, b, w->dyb, w->dyb, nullptr, st, 0, s);
+  // backward, root first: x (by position and by node) from y and the solved B sets; the
+  // last launch counts the solve
+  for (int l = 0; l <= top; ++l)
+    launch_rows_ns(false, ds, l, dn->BM[t], NS, w->dyb, w->dxp, w->dxp, x, st, ds->n_sub == 0 && l == top, s);
+  if (ds->n_sub > 0) launch_rows_ns(false, ds, -1, dn->BM[t], NS, w->dyb, w->dxp, w->dxp, x, st, 1, s);
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;
 }

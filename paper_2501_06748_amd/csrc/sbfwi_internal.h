@@ -245,7 +245,7 @@ struct CoarseWork {
          *scal = nullptr;
   unsigned* bar = nullptr;
   int nblocks = 0, nthreads = 0;
-  double *dyb = nullptr, *dxp = nullptr, *dbp = nullptr;   // direct solve: y, x, b by elimination position
+  double *dyb = nullptr, *dxp = nullptr;   // direct solve: y and x by elimination position
 };
 int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS);
 void sbfwi_coarse_work_free(CoarseWork* w);
