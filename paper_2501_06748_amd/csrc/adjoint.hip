@@ -52,12 +52,15 @@ struct AdjLds {
   double l1[NBT * S];
 };
 
+// loads are unconditional (lanes past the block reread word 0), so that the
+// waits for them do not depend on branches
 template <int NBT>
 __device__ __forceinline__ void prefetch(double (&reg)[(NBT * NBT + WT - 1) / WT], const double* src, int nbnb) {
 #pragma unroll
   for (int r = 0; r < (NBT * NBT + WT - 1) / WT; ++r) {
     int q = threadIdx.x + r * WT;
-    reg[r] = q < nbnb ? src[q] : 0.0;
+    const double v = src[q < nbnb ? q : 0];
+    reg[r] = q < nbnb ? v : 0.0;
   }
 }
 
@@ -88,58 +91,205 @@ __device__ __forceinline__ double denseT_mv(const double* F, const double* vec, 
   return acc;
 }
 
+// Target of the stores of lanes without an item, so that every lane stores
+// unconditionally and the waits for the prefetched level count exactly.
+__device__ double g_adj_sink[WT];
+
 // U^T sweep: z_j, and the coupling psi~_{n-1}^T z_{n-1} to the coarse rows.
+// The next level's F block, seeds and psi~ band entries are loaded at the top
+// of each level and consumed at its end; lanes without an item load word 0 of
+// their arrays and store to g_adj_sink.
 template <int NBT, int S>
 __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                                   const AdjArgs& a, AdjLds<NBT, S>& L) {
+  constexpr int IPT = (NBT * S + WT - 1) / WT;
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e];
   const double* Fe = f.finv + m.finv_off[e];
   const int items = nb * S;
+  int ii[IPT], si[IPT];
+  bool own[IPT], ok[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int it = threadIdx.x + u * WT;
+    own[u] = it < items;
+    ii[u] = own[u] ? it / S : 0;
+    si[u] = it % S;
+    ok[u] = own[u] && si[u] < ns;
+  }
   double reg[(NBT * NBT + WT - 1) / WT];
+  double cu[IPT], cv[IPT], ca[IPT], cb[3][IPT];
+  // seeds of level j and the entries of psi~_{j-1}^T's row i (psi_0's for j = 0: unused)
+  auto load_level = [&](int j, double (&uu)[IPT], double (&vv)[IPT], double (&aa)[IPT], double (&bd)[3][IPT]) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int i = ii[u];
+      const int64_t g = ok[u] ? (io + (int64_t)j * nb + i) * a.NS + s0 + si[u] : 0;
+      uu[u] = a.ub[g];
+      vv[u] = a.vb[g];
+      aa[u] = a.ab[g];
+      const double* bp = f.ps_band + 3 * (po + (int64_t)(j > 0 ? j - 1 : 0) * nb);
+      bd[0][u] = bp[2 * nb + md(i - 1, nb)];
+      bd[1][u] = bp[nb + i];
+      bd[2][u] = bp[md(i + 1, nb)];
+    }
+  };
   prefetch<NBT>(reg, Fe, nbnb);
   commit<NBT>(reg, L.F[0], nb);
+  load_level(0, cu, cv, ca, cb);
   int cur = 0;
   __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);   // nothing in flight at the loop entry
   for (int j = 0; j < n; ++j) {
-    if (j + 1 < n) prefetch<NBT>(reg, Fe + (int64_t)(j + 1) * nbnb, nbnb);
+    const int jn = j + 1 < n ? j + 1 : n - 1;   // the last level reloads its own data (unused)
+    prefetch<NBT>(reg, Fe + (int64_t)jn * nbnb, nbnb);
+    double nu[IPT], nv[IPT], na[IPT], nbd[3][IPT];
+    load_level(jn, nu, nv, na, nbd);
     // y = u~_j - psi~_{j-1}^T z_{j-1}
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      double y = 0.0;
-      if (s < ns) {
-        int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
-        y = a.ub[g] + f.c1 * a.vb[g] + f.a0 * a.ab[g];
-      }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      double y = ok[u] ? cu[u] + f.c1 * cv[u] + f.a0 * ca[u] : 0.0;
       if (j == 1) {
         const double* P0 = f.psit0 + m.dense_off[e];
         double acc = 0.0;
         for (int c = 0; c < nb; ++c) acc += P0[c * nb + i] * L.x[c * S + s];
         y -= acc;
       } else if (j > 1) {
-        y -= bandT_mv(f.ps_band + 3 * (po + (int64_t)(j - 1) * nb), L.x, nb, i, s, S);
+        y -= cb[0][u] * L.x[md(i - 1, nb) * S + s] + cb[1][u] * L.x[i * S + s] + cb[2][u] * L.x[md(i + 1, nb) * S + s];
       }
-      L.y[it] = y;
+      if (own[u]) L.y[it] = y;
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      double zv = denseT_mv<NBT>(L.F[cur], L.y, nb, i, s, S);
-      L.t[it] = zv;
-      if (s < ns) a.z[(io + (int64_t)j * nb + i) * a.NS + s0 + s] = zv;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      const double zv = denseT_mv<NBT>(L.F[cur], L.y, nb, i, s, S);
+      if (own[u]) L.t[it] = zv;
+      const int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
+      *(ok[u] ? a.z + g : g_adj_sink + threadIdx.x) = zv;
     }
-    if (j + 1 < n) commit<NBT>(reg, L.F[cur ^ 1], nb);
+    commit<NBT>(reg, L.F[cur ^ 1], nb);
     __syncthreads();
     for (int it = threadIdx.x; it < items; it += WT) L.x[it] = L.t[it];
     __syncthreads();
     cur ^= 1;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      cu[u] = nu[u];
+      cv[u] = nv[u];
+      ca[u] = na[u];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cb[k][u] = nbd[k][u];
+    }
   }
   // coupling to the coarse rows: psi_{n-1}^T z_{n-1} (n >= 2, so psi~_{n-1} = psi_{n-1})
   const double* psn1 = f.ps_band + 3 * (po + (int64_t)(n - 1) * nb);
   for (int it = threadIdx.x; it < items; it += WT) {
     int i = it / S, s = it % S;
     if (s < ns) a.gB[(lo + i) * a.NS + s0 + s] = bandT_mv(psn1, L.x, nb, i, s, S);
+  }
+}
+
+// Level loop of the L^T sweep (j = n-1 .. 0) with the adjoint Newmark chain;
+// the next level's F block, z, seeds and the theta / P band entries are loaded
+// at the top of each level and consumed at its end.
+template <int NBT, int S, bool LAM>
+__device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev& m, const FactorsDev& f,
+                                                   const AdjArgs& a, AdjLds<NBT, S>& L, double (&reg)[(NBT * NBT + WT - 1) / WT]) {
+  constexpr int IPT = (NBT * S + WT - 1) / WT;
+  const int ns = min(S, a.NS - s0);
+  const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
+  const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e], xo = m.x_off[e];
+  const double* Fe = f.finv + m.finv_off[e];
+  const int items = nb * S;
+  int ii[IPT], si[IPT];
+  bool own[IPT], ok[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int it = threadIdx.x + u * WT;
+    own[u] = it < items;
+    ii[u] = own[u] ? it / S : 0;
+    si[u] = it % S;
+    ok[u] = own[u] && si[u] < ns;
+  }
+  double cz[IPT], cv[IPT], ca[IPT], ct[3][IPT], cp[3][IPT];
+  // level j: z, v-bar and a-bar seeds, row i of theta_{j+1}^T and of P_j^T
+  auto load_level = [&](int j, double (&zz)[IPT], double (&vv)[IPT], double (&aa)[IPT], double (&tb)[3][IPT],
+                        double (&pb)[3][IPT]) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int i = ii[u], im = md(i - 1, nb), ip = md(i + 1, nb);
+      const int64_t g = ok[u] ? (io + (int64_t)j * nb + i) * a.NS + s0 + si[u] : 0;
+      zz[u] = a.z[g];
+      vv[u] = a.vb[g];
+      aa[u] = a.ab[g];
+      const double* tp = f.th_band + 3 * (po + (int64_t)(j + 1) * nb);
+      const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb);
+      tb[0][u] = tp[2 * nb + im];
+      tb[1][u] = tp[nb + i];
+      tb[2][u] = tp[ip];
+      pb[0][u] = pp[2 * nb + im];
+      pb[1][u] = pp[nb + i];
+      pb[2][u] = pp[ip];
+    }
+  };
+  load_level(n - 1, cz, cv, ca, ct, cp);
+  int cur = 1;
+  __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);   // nothing in flight at the loop entry
+  for (int j = n - 1; j >= 0; --j) {
+    const int jn = j > 0 ? j - 1 : 0;   // the last level reloads level 0 (unused)
+    prefetch<NBT>(reg, Fe + (int64_t)jn * nbnb, nbnb);
+    double nz[IPT], nv[IPT], na[IPT], nt[3][IPT], np[3][IPT];
+    load_level(jn, nz, nv, na, nt, np);
+    // t = theta_{j+1}^T lambda_{j+1} (+ theta_{n+1}^T lambda_{n+1} when j = n-1)
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      double tv = ct[0][u] * L.x[md(i - 1, nb) * S + s] + ct[1][u] * L.x[i * S + s] + ct[2][u] * L.x[md(i + 1, nb) * S + s];
+      if (j == n - 1) tv += bandT_mv(f.th_np1 + 3 * lo, L.l1, nb, i, s, S);
+      if (own[u]) L.t[it] = tv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      const double lv = ok[u] ? cz[u] - denseT_mv<NBT>(L.F[cur], L.t, nb, i, s, S) : 0.0;
+      if (own[u]) L.y[it] = lv;
+    }
+    commit<NBT>(reg, L.F[cur ^ 1], nb);   // the last level commits an unused block
+    __syncthreads();
+    // adjoint Newmark chain at level j: w-bar = P_j^T lambda_j - a-bar
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      const int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
+      const double vb = cv[u];
+      const double wb = (cp[0][u] * L.y[md(i - 1, nb) * S + s] + cp[1][u] * L.y[i * S + s] +
+                         cp[2][u] * L.y[md(i + 1, nb) * S + s]) - ca[u];
+      double* sink = g_adj_sink + threadIdx.x;
+      *(ok[u] ? a.ub + g : sink) = -f.c1 * vb + f.a0 * wb;
+      *(ok[u] ? a.vb + g : sink) = f.c2 * vb + f.a1 * wb;
+      *(ok[u] ? a.ab + g : sink) = f.c3 * vb + f.a2 * wb;
+      if (LAM) *(ok[u] ? a.lam + (xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s : sink) = own[u] ? L.y[it] : 0.0;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += WT) L.x[it] = L.y[it];
+    __syncthreads();
+    cur ^= 1;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      cz[u] = nz[u];
+      cv[u] = nv[u];
+      ca[u] = na[u];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ct[k][u] = nt[k][u];
+        cp[k][u] = np[k][u];
+      }
+    }
   }
 }
 
@@ -180,49 +330,9 @@ __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m
       }
     }
   }
-  int cur = 1;
   __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
-    if (j > 0) prefetch<NBT>(reg, Fe + (int64_t)(j - 1) * nbnb, nbnb);
-    // t = theta_{j+1}^T lambda_{j+1} (+ theta_{n+1}^T lambda_{n+1} when j = n-1)
-    const double* thj1 = f.th_band + 3 * (po + (int64_t)(j + 1) * nb);
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      double tv = bandT_mv(thj1, L.x, nb, i, s, S);
-      if (j == n - 1) tv += bandT_mv(f.th_np1 + 3 * lo, L.l1, nb, i, s, S);
-      L.t[it] = tv;
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      double lv = 0.0;
-      if (s < ns) {
-        int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
-        lv = a.z[g] - denseT_mv<NBT>(L.F[cur], L.t, nb, i, s, S);
-      }
-      L.y[it] = lv;
-    }
-    if (j > 0) commit<NBT>(reg, L.F[cur ^ 1], nb);
-    __syncthreads();
-    // adjoint Newmark chain at level j: w-bar = P_j^T lambda_j - a-bar
-    const double* pmj = f.pm_band + 3 * (po + (int64_t)j * nb);
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      if (s < ns) {
-        int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
-        double vb = a.vb[g];
-        double wb = bandT_mv(pmj, L.y, nb, i, s, S) - a.ab[g];
-        a.ub[g] = -f.c1 * vb + f.a0 * wb;
-        a.vb[g] = f.c2 * vb + f.a1 * wb;
-        a.ab[g] = f.c3 * vb + f.a2 * wb;
-        if (a.lam) a.lam[(xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s] = L.y[it];
-      }
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < items; it += WT) L.x[it] = L.y[it];
-    __syncthreads();
-    cur ^= 1;
-  }
+  if (a.lam) adj_recover_levels<NBT, S, true>(e, s0, m, f, a, L, reg);
+  else adj_recover_levels<NBT, S, false>(e, s0, m, f, a, L, reg);
   if (!a.lam) return;
   // lambda_{-1} = -theta_{-1}^-T theta_0^T lambda_0
   const double* th0 = f.th_band + 3 * po;

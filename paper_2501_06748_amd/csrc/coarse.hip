@@ -641,6 +641,7 @@ int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS) {
   if (m->dsym) {   // direct solve: forward and backward results by elimination position
     SBFWI_CHECK(sbfwi_alloc(&w->dyb, 2 * sz));
     w->dxp = w->dyb + sz;
+    SBFWI_CHECK(sbfwi_alloc(&w->dupd, std::max<int64_t>(1, m->dsym->b_ptr[m->dsym->nS]) * NS));
   }
   return SBFWI_OK;
 }
@@ -651,6 +652,7 @@ void sbfwi_coarse_work_free(CoarseWork* w) {
   sbfwi_dev_free(w->scal);
   sbfwi_dev_free(w->bar);
   sbfwi_dev_free(w->dyb);
+  sbfwi_dev_free(w->dupd);
   *w = CoarseWork();
 }
 

@@ -23,19 +23,19 @@
 // the a0-weighted mass term), giving L11, U11, L21 = F21 U11^-1,
 // U12 = L11^-1 F12 and the update F22 - L21 U12 for J's parent.
 //
-// The device keeps, per supernode, two folded row blocks: forward
-// FM_J = [P | -P Lrow_J] with P = L11^-1 and Lrow_J the rows of L that J's
-// rows hold in the columns of earlier supernodes (its contributors), so that
-// y_J = FM_J [b_J ; y_contributors]; backward BM_J = [Q | -Q U12] with
-// Q = U11^-1, so that x_J = BM_J [y_J ; x_{B_J}].  K_g^T = U^T L^T has its own
-// pair.  Every row of a block is one dot product of a dense row with values
-// gathered at a column list.
-//
-// Solve (device): per level of the dissection tree one launch over all rows
-// of that level's supernodes -- forward deepest level first, backward root
-// first -- with the levels below the cut (where the tree has kSubtrees
-// supernodes) solved by one block per subtree.  No atomics: results are
-// bit-reproducible.
+// Solve (device, multifrontal).  Forward, L y = b, leaves first: with the
+// children's update vectors u_c (over their B sets), the front vector of J is
+// t_J = b_J - sum_c u_c[J] and y_J = P_J t_J with P_J = L11^-1; J passes on
+// u_J = sum_c u_c[B_J] + C_J y_J with C_J = L21, so each supernode reads only
+// its children.  The device keeps FW_J = [P_J ; C_J P_J] ((|J| + |B_J|) x |J|)
+// and evaluates y_J and u_J - sum_c u_c[B_J] as FW_J t_J.  Backward, U x = y,
+// root first: x_J = Q_J y_J - Q_J U12 x_{B_J} with Q_J = U11^-1 from
+// BM_J = [Q_J | -Q_J U12] and the vector [y_J ; x_{B_J}].  K_g^T = U^T L^T
+// uses the same structure with (U11^-T, U12^T) forward and (L11^-T, L21^T)
+// backward.  One launch per level of the dissection tree above the cut level
+// (the shallowest with kSubtrees supernodes), one block per subtree below it;
+// every block assembles a supernode's vector in LDS once and then runs its
+// rows against it.  No atomics: results are bit-reproducible.
 #include <algorithm>
 #include <cmath>
 #include <atomic>
@@ -130,141 +130,115 @@ struct Dissect {
   }
 };
 
-// out[(J, i)] = sum_k M_J[i][k] src_k over the row of (J, i): the first n_J
-// entries read the vector `own` at J's own positions (the right-hand side by
-// node forward, y backward), the rest read `done` at the row's column list
-// (the contributors' positions forward, B_J backward), values solved at
-// earlier levels.  G lanes per row (G a power of two up to the block) split
-// the entries lane-strided in chunks of U loads issued before their use; a
-// fixed butterfly inside each wavefront, then (rows wider than a wavefront)
-// the wavefronts of the row in index order, sum them.
+// One block of a solve program.  For each of its steps: the slot records
+// assemble vectors in LDS (forward: the right-hand side at the supernode's
+// nodes minus the children's update entries listed for the slot; backward: y
+// at J's positions, then x at B_J), then G lanes per row dot each dense row
+// with its supernode's vector (lane-strided, chunks of U loads in flight, a
+// fixed butterfly to sum) and write it: forward to y by position (kind 0) or,
+// plus the children's update entries listed for the row, to the update vector
+// (kind 1); backward to x by position and by node.  Shots s0 .. s0 + NSM - 1
+// of NS are handled.  A block barrier separates the steps, whose later ones
+// read what earlier ones wrote.
 template <int NSM, bool FWD>
-__device__ __forceinline__ void row_dot(const DirectDev& d, const RowMeta& rm, bool valid, int lane, int G,
-                                        const double* __restrict__ vals, int NS, const double* __restrict__ own,
-                                        const double* __restrict__ done, double (&acc)[NSM]) {
-  constexpr int U = NSM <= 4 ? 8 : 4;
-#pragma unroll
-  for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
-  if (valid) {
-    const int64_t j0 = rm.j0, len = rm.len;
-    const int nj = rm.nj;
-    const double* v = vals + rm.val_off;
-    const int64_t* cols = (FWD ? d.col_idx : d.bpos) + rm.col_off - nj;
-    for (int64_t k0 = lane; k0 < len; k0 += (int64_t)G * U) {
-      double a[U];
-      const double* src[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t k = k0 + (int64_t)u * G;
-        const bool ok = k < len;
-        a[u] = ok ? v[k] : 0.0;
-        if (FWD)   // own = the right-hand side by node: position j0 + k holds node inv[j0 + k]
-          src[u] = !ok ? own : (k < nj ? own + d.inv[j0 + k] * NS : done + cols[k] * NS);
-        else
-          src[u] = !ok ? own + j0 * NS : (k < nj ? own + (j0 + k) * NS : done + cols[k] * NS);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int s = 0; s < NSM; ++s)
-          if (s < NS) acc[s] += a[u] * src[u][s];
-    }
-  }
-  const int gw = G < 64 ? G : 64;
-  for (int m = 1; m < gw; m <<= 1)
-#pragma unroll
-    for (int s = 0; s < NSM; ++s) acc[s] += __shfl_xor(acc[s], m, 64);
-}
-
-template <int NSM, bool FWD>
-__device__ __forceinline__ void row_store(const RowMeta& rm, int NS, const double (&acc)[NSM],
-                                          double* __restrict__ out_pos, double* __restrict__ out_node,
-                                          int* __restrict__ status) {
+__global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk0, int G,
+                                                         const int64_t* __restrict__ gl_idx,
+                                                         const double* __restrict__ vals, int NS, int s0,
+                                                         const double* __restrict__ in, double* __restrict__ upd,
+                                                         double* __restrict__ out, int* __restrict__ status,
+                                                         int count) {
+  extern __shared__ double vec[];   // [slot][NSM]
+  constexpr int U = 4;
+  const int64_t b = blk0 + blockIdx.x;
+  if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
+  const int ns = min(NSM, NS - s0);
+  const int lane = threadIdx.x % G;
   bool bad = false;
-  for (int s = 0; s < NS; ++s) {
-    out_pos[rm.pos * NS + s] = acc[s];
-    if (!FWD) out_node[rm.node * NS + s] = acc[s];
-    bad = bad || !isfinite(acc[s]);
+  for (int64_t st = p.blk[b]; st < p.blk[b + 1]; ++st) {
+    const DStep S = p.steps[st];
+    for (int64_t q = S.v0 + threadIdx.x; q < S.v1; q += DT) {
+      const DVRec v = p.vrec[q];
+      double acc[NSM];
+      const double* src = FWD ? in : (v.ngl ? upd : in);
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) acc[s] = s < ns ? src[v.src * NS + s0 + s] : 0.0;
+      if (FWD)
+        for (int g = 0; g < v.ngl; ++g) {
+          const int64_t e = gl_idx[v.gl + g];
+#pragma unroll
+          for (int s = 0; s < NSM; ++s)
+            if (s < ns) acc[s] -= upd[e * NS + s0 + s];
+        }
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) vec[v.slot * NSM + s] = acc[s];
+    }
+    __syncthreads();
+    for (int64_t base = S.r0; base < S.r1; base += DT / G) {
+      const int64_t r = base + threadIdx.x / G;
+      const bool valid = r < S.r1;
+      DRRec rr{};
+      if (valid) rr = p.rrec[r];
+      double acc[NSM];
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
+      const double* v = vals + rr.val;
+      for (int k0 = lane; k0 < rr.len; k0 += G * U) {
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * G;
+          a[u] = k < rr.len ? v[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * G;
+          if (k < rr.len) {
+            const double* x = vec + (int64_t)(rr.slot0 + k) * NSM;
+#pragma unroll
+            for (int s = 0; s < NSM; ++s) acc[s] += a[u] * x[s];
+          }
+        }
+      }
+      for (int m = 1; m < G; m <<= 1)
+#pragma unroll
+        for (int s = 0; s < NSM; ++s) acc[s] += __shfl_xor(acc[s], m, 64);
+      if (valid && lane == 0) {
+        if (FWD) {
+          if (rr.kind == 0) {
+#pragma unroll
+            for (int s = 0; s < NSM; ++s)
+              if (s < ns) out[rr.out * NS + s0 + s] = acc[s];
+          } else {
+            double pass[NSM];
+#pragma unroll
+            for (int s = 0; s < NSM; ++s) pass[s] = 0.0;
+            for (int g = 0; g < rr.ngl; ++g) {
+              const int64_t e = gl_idx[rr.aux + g];
+#pragma unroll
+              for (int s = 0; s < NSM; ++s)
+                if (s < ns) pass[s] += upd[e * NS + s0 + s];
+            }
+#pragma unroll
+            for (int s = 0; s < NSM; ++s) {
+              acc[s] += pass[s];
+              if (s < ns) upd[rr.out * NS + s0 + s] = acc[s];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < NSM; ++s)
+            if (s < ns) {
+              upd[rr.out * NS + s0 + s] = acc[s];
+              out[rr.aux * NS + s0 + s] = acc[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NSM; ++s) bad = bad || (s < ns && !isfinite(acc[s]));
+      }
+    }
+    __syncthreads();   // the next step reads this one's results and reuses the LDS vectors
   }
   if (bad) atomicOr(&status[0], 4);
-}
-
-// out[(J, i)] = sum_k M_J[i][k] src_k over the row of (J, i): the first n_J
-// entries read the vector `own` at J's own positions (the right-hand side by
-// node forward, y backward), the rest read `done` at the row's column list
-// (the contributors' positions forward, B_J backward), values solved at
-// earlier levels.  G lanes per row (G a power of two up to the block) split
-// the entries lane-strided in chunks of U loads issued before their use; a
-// fixed butterfly inside each wavefront, then (rows wider than a wavefront)
-// the wavefronts of the row in index order, sum them.  One launch per level.
-template <int NSM, bool FWD>
-__global__ void __launch_bounds__(DT) direct_rows_kernel(DirectDev d, int64_t row0, int64_t nrows, int G,
-                                                         const double* __restrict__ vals, int NS,
-                                                         const double* __restrict__ own,
-                                                         const double* __restrict__ done,
-                                                         double* __restrict__ out_pos,
-                                                         double* __restrict__ out_node, int* __restrict__ status,
-                                                         int count) {
-  __shared__ double red[DT / 64][NSM];
-  if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
-  const int64_t gt = (int64_t)blockIdx.x * DT + threadIdx.x;
-  const int64_t r = gt / G;
-  const int lane = (int)(gt - r * G);
-  const bool valid = r < nrows;
-  RowMeta rm{};
-  if (valid) rm = (FWD ? d.fwd_rows : d.bwd_rows)[row0 + r];   // one 48-byte load per row
-  double acc[NSM];
-  row_dot<NSM, FWD>(d, rm, valid, lane, G, vals, NS, own, done, acc);
-  if (G > 64) {   // rows wider than a wavefront: add the row's wavefronts in index order
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) red[wave][s] = acc[s];
-    __syncthreads();
-    if (lane == 0) {
-      const int nw = G / 64;
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) {
-        double t = 0.0;
-        for (int q = 0; q < nw; ++q) t += red[wave + q][s];
-        acc[s] = t;
-      }
-    }
-  }
-  if (valid && lane == 0) row_store<NSM, FWD>(rm, NS, acc, out_pos, out_node, status);
-}
-
-// The bottom of the dissection tree: one block per subtree (rooted at the cut
-// level) walks its levels in order -- deepest first forward, cut level first
-// backward -- with a block barrier between levels instead of a launch; rows
-// of a level use SG lanes each.
-template <int NSM, bool FWD>
-__global__ void __launch_bounds__(DT) direct_subtree_kernel(DirectDev d, const int64_t* __restrict__ seg, int NL,
-                                                            const int64_t* __restrict__ sub_rows,
-                                                            const double* __restrict__ vals, int NS,
-                                                            const double* __restrict__ own,
-                                                            const double* __restrict__ done,
-                                                            double* __restrict__ out_pos,
-                                                            double* __restrict__ out_node, int* __restrict__ status,
-                                                            int count) {
-  constexpr int SG = 16;
-  if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
-  const int64_t* sg = seg + (int64_t)blockIdx.x * (NL + 1);
-  const int lane = threadIdx.x % SG;
-  for (int q = 0; q < NL; ++q) {
-    const int li = FWD ? q : NL - 1 - q;   // segment li holds the rows of the li-th deepest level
-    const int64_t a = sg[li], e = sg[li + 1];
-    for (int64_t base = a; base < e; base += DT / SG) {
-      const int64_t r = base + threadIdx.x / SG;
-      const bool valid = r < e;
-      RowMeta rm{};
-      if (valid) rm = (FWD ? d.fwd_rows : d.bwd_rows)[sub_rows[r]];
-      double acc[NSM];
-      row_dot<NSM, FWD>(d, rm, valid, lane, SG, vals, NS, own, done, acc);
-      if (valid && lane == 0) row_store<NSM, FWD>(rm, NS, acc, out_pos, out_node, status);
-    }
-    __syncthreads();   // this level's results are read by the next level of the block
-  }
 }
 
 
@@ -336,44 +310,46 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   }
   ds->bpos.resize(ds->b_ptr[nS]);
   for (int J = 0; J < nS; ++J) std::copy(B[J].begin(), B[J].end(), ds->bpos.begin() + ds->b_ptr[J]);
-  // contributors of every supernode: the descendants D whose B_D meets J (D ascending)
-  ds->ctr.assign(nS, {});
-  for (int D = 0; D < nS; ++D) {
-    int last = -1;
-    for (int64_t q = ds->b_ptr[D]; q < ds->b_ptr[D + 1]; ++q) {
-      const int J = ds->sn_of(ds->bpos[q]);
-      if (J != last) ds->ctr[J].push_back(D);   // bpos is sorted, so each J appears in one run
-      last = J;
-    }
-  }
-  for (auto& c : ds->ctr) {
-    std::sort(c.begin(), c.end());
-    c.erase(std::unique(c.begin(), c.end()), c.end());
-  }
-  // forward rows of J read its own nodes, then the positions of its contributors;
-  // backward rows read J's positions, then B_J
-  ds->ncols.assign(nS, 0);
-  ds->cf_off.assign(nS + 1, 0);
-  ds->fm_off.assign(nS + 1, 0);
+  // row blocks: forward FW_J (|J| + |B_J|) x |J|, backward BM_J |J| x (|J| + |B_J|)
+  ds->fw_off.assign(nS + 1, 0);
   ds->bm_off.assign(nS + 1, 0);
-  ds->max_nj = 0;
+  std::vector<int64_t> fr_off(nS + 1, 0);   // front rows (J then B_J) of every supernode
   for (int J = 0; J < nS; ++J) {
     const int64_t nj = ds->sn_ptr[J + 1] - ds->sn_ptr[J], nb = ds->b_ptr[J + 1] - ds->b_ptr[J];
-    int64_t nc = 0;
-    for (int D : ds->ctr[J]) nc += ds->sn_ptr[D + 1] - ds->sn_ptr[D];
-    ds->ncols[J] = nc;
-    ds->cf_off[J + 1] = ds->cf_off[J] + nc;
-    ds->fm_off[J + 1] = ds->fm_off[J] + nj * (nj + nc);
+    ds->fw_off[J + 1] = ds->fw_off[J] + (nj + nb) * nj;
     ds->bm_off[J + 1] = ds->bm_off[J] + nj * (nj + nb);
+    fr_off[J + 1] = fr_off[J] + nj + nb;
     ds->max_nj = std::max<int64_t>(ds->max_nj, nj);
+    ds->sum_j2 += nj * nj;
+    ds->sum_jb += nj * nb;
   }
-  ds->col_idx.assign(ds->cf_off[nS], 0);
-  for (int J = 0; J < nS; ++J) {
-    int64_t o = ds->cf_off[J];
-    for (int D : ds->ctr[J])
-      for (int64_t p = ds->sn_ptr[D]; p < ds->sn_ptr[D + 1]; ++p) ds->col_idx[o++] = p;
+  // the children's update entries that land in each front row of J (B_c lies in J and B_J),
+  // listed child by child
+  std::vector<int64_t> gl_ptr(fr_off[nS] + 1, 0), gl;
+  auto front_row = [&](int J, int64_t p) -> int64_t {   // front row of position p in J, or -1
+    const int64_t j0 = ds->sn_ptr[J], j1 = ds->sn_ptr[J + 1];
+    if (p >= j0 && p < j1) return p - j0;
+    const auto b0 = ds->bpos.begin() + ds->b_ptr[J], b1 = ds->bpos.begin() + ds->b_ptr[J + 1];
+    const auto it = std::lower_bound(b0, b1, p);
+    return (it != b1 && *it == p) ? (j1 - j0) + (it - b0) : -1;
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int64_t> fill;
+    if (pass == 1) {
+      for (int64_t r = 0; r < fr_off[nS]; ++r) gl_ptr[r + 1] += gl_ptr[r];
+      gl.assign(gl_ptr[fr_off[nS]], 0);
+      fill.assign(gl_ptr.begin(), gl_ptr.end() - 1);
+    }
+    for (int J = 0; J < nS; ++J)
+      for (int c : ds->children[J])
+        for (int64_t k = ds->b_ptr[c]; k < ds->b_ptr[c + 1]; ++k) {
+          const int64_t fr = front_row(J, ds->bpos[k]);
+          if (fr < 0) return sbfwi_fail(SBFWI_EINVAL, "nested dissection: a child's coupling leaves its parent's front");
+          if (pass == 0) gl_ptr[fr_off[J] + fr + 1]++;
+          else gl[fill[fr_off[J] + fr]++] = k;
+        }
   }
-  // levels: supernodes, their rows, and lanes per row from the longest row of the level
+  // levels
   ds->lvl_ptr.assign(ds->depth + 2, 0);
   for (int J = 0; J < nS; ++J) ds->lvl_ptr[ds->level[J] + 1]++;
   for (int l = 0; l <= ds->depth; ++l) ds->lvl_ptr[l + 1] += ds->lvl_ptr[l];
@@ -381,30 +357,6 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   {
     std::vector<int32_t> fill(ds->lvl_ptr.begin(), ds->lvl_ptr.end() - 1);
     for (int J = 0; J < nS; ++J) ds->lvl_sn[fill[ds->level[J]]++] = J;
-  }
-  ds->row_ptr.assign(ds->depth + 2, 0);
-  ds->g_fwd.assign(ds->depth + 1, 1);
-  ds->g_bwd.assign(ds->depth + 1, 1);
-  auto lanes = [](int64_t len) {
-    int g = 1;
-    while (g < DT && g * 16 < len) g *= 2;   // about 16 entries per lane, at most a block per row
-    return g;
-  };
-  for (int l = 0; l <= ds->depth; ++l) {
-    int64_t lf = 0, lb = 0;
-    for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) {
-      const int J = ds->lvl_sn[q];
-      const int64_t nj = ds->sn_ptr[J + 1] - ds->sn_ptr[J];
-      for (int64_t i = 0; i < nj; ++i) {
-        ds->row_sn.push_back(J);
-        ds->row_i.push_back((int32_t)i);
-      }
-      lf = std::max(lf, nj + ds->ncols[J]);
-      lb = std::max(lb, nj + ds->b_ptr[J + 1] - ds->b_ptr[J]);
-    }
-    ds->row_ptr[l + 1] = (int64_t)ds->row_sn.size();
-    ds->g_fwd[l] = lanes(lf);
-    ds->g_bwd[l] = lanes(lb);
   }
   // cut level: the shallowest level with at least kSubtrees supernodes; the
   // subtrees rooted there are solved by one block each
@@ -414,84 +366,198 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
       ds->cut = l;
       break;
     }
-  ds->n_sub = 0;
-  ds->NL = ds->depth - ds->cut + 1;
-  if (ds->cut <= ds->depth) {
-    ds->n_sub = ds->lvl_ptr[ds->cut + 1] - ds->lvl_ptr[ds->cut];
-    // row range of every supernode in the level-ordered row arrays
-    std::vector<int64_t> first_row(nS, 0);
-    for (int l = 0; l <= ds->depth; ++l) {
-      int64_t r = ds->row_ptr[l];
-      for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) {
-        const int J = ds->lvl_sn[q];
-        first_row[J] = r;
-        r += ds->sn_ptr[J + 1] - ds->sn_ptr[J];
+  ds->n_sub = ds->cut <= ds->depth ? ds->lvl_ptr[ds->cut + 1] - ds->lvl_ptr[ds->cut] : 0;
+  const int top = std::min(ds->depth, ds->cut - 1);   // deepest level with a launch of its own
+  // programs (t = 0 forward, 1 backward)
+  struct Prog {
+    std::vector<DVRec> v;
+    std::vector<DRRec> r;
+    std::vector<DStep> st;
+    std::vector<int64_t> blk{0};
+  } P[2];
+  auto lanes = [](int64_t len) {   // about 8 entries per lane, at most a wavefront per row
+    int g = 1;
+    while (g < 64 && g * 8 < len) g *= 2;
+    return g;
+  };
+  auto nrows = [&](int t, int J) {
+    const int64_t nj = ds->sn_ptr[J + 1] - ds->sn_ptr[J];
+    return t == 0 ? nj + ds->b_ptr[J + 1] - ds->b_ptr[J] : nj;
+  };
+  auto row_len = [&](int t, int J) {
+    const int64_t nj = ds->sn_ptr[J + 1] - ds->sn_ptr[J];
+    return t == 0 ? nj : nj + ds->b_ptr[J + 1] - ds->b_ptr[J];
+  };
+  auto emit_slots = [&](int t, int J, int base) -> int {   // J's vector at LDS slots base ..
+    const int64_t j0 = ds->sn_ptr[J], nj = ds->sn_ptr[J + 1] - j0, b0 = ds->b_ptr[J];
+    const int64_t nb = ds->b_ptr[J + 1] - b0;
+    for (int64_t i = 0; i < nj; ++i) {
+      DVRec v{};
+      v.slot = base + (int32_t)i;
+      if (t == 0) {
+        v.src = ds->inv[j0 + i];
+        v.gl = gl_ptr[fr_off[J] + i];
+        v.ngl = (int32_t)(gl_ptr[fr_off[J] + i + 1] - v.gl);
+      } else {
+        v.src = j0 + i;
+      }
+      P[t].v.push_back(v);
+    }
+    if (t == 1)
+      for (int64_t r = 0; r < nb; ++r) {
+        DVRec v{};
+        v.src = ds->bpos[b0 + r];
+        v.ngl = 1;
+        v.slot = base + (int32_t)(nj + r);
+        P[t].v.push_back(v);
+      }
+    return (int)(t == 0 ? nj : nj + nb);
+  };
+  auto emit_rows = [&](int t, int J, int base, int64_t r0, int64_t r1) {
+    const int64_t j0 = ds->sn_ptr[J], nj = ds->sn_ptr[J + 1] - j0, nb = ds->b_ptr[J + 1] - ds->b_ptr[J];
+    for (int64_t r = r0; r < r1; ++r) {
+      DRRec w{};
+      w.slot0 = base;
+      if (t == 0) {
+        w.val = ds->fw_off[J] + r * nj;
+        w.len = (int32_t)nj;
+        if (r < nj) {
+          w.out = j0 + r;
+        } else {
+          w.kind = 1;
+          w.out = ds->b_ptr[J] + (r - nj);
+          w.aux = gl_ptr[fr_off[J] + r];
+          w.ngl = (int32_t)(gl_ptr[fr_off[J] + r + 1] - w.aux);
+        }
+      } else {
+        w.val = ds->bm_off[J] + r * (nj + nb);
+        w.len = (int32_t)(nj + nb);
+        w.out = j0 + r;
+        w.aux = ds->inv[j0 + r];
+      }
+      P[t].r.push_back(w);
+    }
+  };
+  auto level_launch = [&](int t, int l) {   // one block per (supernode, slice of its rows)
+    DLaunch L;
+    L.blk0 = (int64_t)P[t].blk.size() - 1;
+    int64_t len = 1;
+    for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) len = std::max(len, row_len(t, ds->lvl_sn[q]));
+    L.G = lanes(len);
+    const int64_t per = (int64_t)(DT / L.G) * 4;
+    for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) {
+      const int J = ds->lvl_sn[q];
+      const int64_t v0 = (int64_t)P[t].v.size();
+      L.slots = std::max(L.slots, emit_slots(t, J, 0));
+      const int64_t v1 = (int64_t)P[t].v.size(), nr = nrows(t, J);
+      for (int64_t a = 0; a < nr; a += per) {
+        const int64_t r0 = (int64_t)P[t].r.size();
+        emit_rows(t, J, 0, a, std::min(nr, a + per));
+        P[t].st.push_back({v0, v1, r0, (int64_t)P[t].r.size()});
+        P[t].blk.push_back((int64_t)P[t].st.size());
       }
     }
-    ds->seg.assign((size_t)ds->n_sub * (ds->NL + 1), 0);
+    L.nblk = (int64_t)P[t].blk.size() - 1 - L.blk0;
+    ds->launches[t].push_back(L);
+  };
+  auto subtree_launch = [&](int t) {   // one block per subtree rooted at the cut level
+    DLaunch L;
+    L.blk0 = (int64_t)P[t].blk.size() - 1;
+    const int NL = ds->depth - ds->cut + 1;
+    int64_t len = 1;
     for (int b = 0; b < ds->n_sub; ++b) {
-      const int R = ds->lvl_sn[ds->lvl_ptr[ds->cut] + b];
-      std::vector<std::vector<int32_t>> by_level(ds->NL);   // index = depth - level
-      std::vector<int32_t> stack{R};
+      std::vector<std::vector<int32_t>> by_level(NL);   // index = depth - level
+      std::vector<int32_t> stack{ds->lvl_sn[ds->lvl_ptr[ds->cut] + b]};
       while (!stack.empty()) {
         const int J = stack.back();
         stack.pop_back();
         by_level[ds->depth - ds->level[J]].push_back(J);
         for (int c : ds->children[J]) stack.push_back(c);
       }
-      for (int li = 0; li < ds->NL; ++li) {
-        ds->seg[(size_t)b * (ds->NL + 1) + li] = (int64_t)ds->sub_rows.size();
+      for (int q = 0; q < NL; ++q) {
+        const int li = t == 0 ? q : NL - 1 - q;   // forward deepest first, backward cut level first
+        if (by_level[li].empty()) continue;
         std::sort(by_level[li].begin(), by_level[li].end());
-        for (int J : by_level[li])
-          for (int64_t i = 0; i < ds->sn_ptr[J + 1] - ds->sn_ptr[J]; ++i) ds->sub_rows.push_back(first_row[J] + i);
+        const int64_t v0 = (int64_t)P[t].v.size();
+        std::vector<int> base;
+        int slots = 0;
+        for (int J : by_level[li]) {
+          base.push_back(slots);
+          slots += emit_slots(t, J, slots);
+        }
+        const int64_t v1 = (int64_t)P[t].v.size(), r0 = (int64_t)P[t].r.size();
+        for (size_t k = 0; k < by_level[li].size(); ++k) {
+          const int J = by_level[li][k];
+          emit_rows(t, J, base[k], 0, nrows(t, J));
+          len = std::max(len, row_len(t, J));
+        }
+        P[t].st.push_back({v0, v1, r0, (int64_t)P[t].r.size()});
+        L.slots = std::max(L.slots, slots);
       }
-      ds->seg[(size_t)b * (ds->NL + 1) + ds->NL] = (int64_t)ds->sub_rows.size();
+      P[t].blk.push_back((int64_t)P[t].st.size());
     }
+    L.G = lanes(len);
+    L.nblk = ds->n_sub;
+    ds->launches[t].push_back(L);
+  };
+  if (ds->n_sub > 0) subtree_launch(0);
+  for (int l = top; l >= 0; --l) level_launch(0, l);
+  for (int l = 0; l <= top; ++l) level_launch(1, l);
+  if (ds->n_sub > 0) subtree_launch(1);
+  for (int t = 0; t < 2; ++t)
+    for (const DLaunch& L : ds->launches[t]) ds->max_slots = std::max(ds->max_slots, L.slots);
+  // every record stays inside the arrays and LDS vectors it addresses
+  const int64_t n_upd = ds->b_ptr[nS], n_gl = (int64_t)gl.size();
+  for (int t = 0; t < 2; ++t) {
+    const int64_t vals = t == 0 ? ds->fw_off[nS] : ds->bm_off[nS];
+    bool ok = true;
+    int64_t blocks = 0;
+    for (const DLaunch& L : ds->launches[t]) {
+      ok = ok && L.blk0 == blocks && L.nblk >= 0 && L.blk0 + L.nblk < (int64_t)P[t].blk.size();
+      blocks += L.nblk;
+      for (int64_t b = L.blk0; ok && b < L.blk0 + L.nblk; ++b)
+        for (int64_t q = P[t].blk[b]; ok && q < P[t].blk[b + 1]; ++q) {
+          const DStep& S = P[t].st[q];
+          ok = S.v0 <= S.v1 && S.v1 <= (int64_t)P[t].v.size() && S.r0 <= S.r1 && S.r1 <= (int64_t)P[t].r.size();
+          for (int64_t i = S.v0; ok && i < S.v1; ++i) {
+            const DVRec& v = P[t].v[i];
+            ok = v.src >= 0 && v.src < n && v.slot >= 0 && v.slot < L.slots &&
+                 (t == 1 ? (v.ngl == 0 || v.ngl == 1) : (v.ngl >= 0 && v.gl >= 0 && v.gl + v.ngl <= n_gl));
+          }
+          for (int64_t i = S.r0; ok && i < S.r1; ++i) {
+            const DRRec& w = P[t].r[i];
+            ok = w.len >= 0 && w.val >= 0 && w.val + w.len <= vals && w.slot0 >= 0 && w.slot0 + w.len <= L.slots;
+            if (t == 1) ok = ok && w.out >= 0 && w.out < n && w.aux >= 0 && w.aux < n;
+            else if (w.kind == 0) ok = ok && w.out >= 0 && w.out < n;
+            else ok = ok && w.out >= 0 && w.out < n_upd && w.ngl >= 0 && w.aux >= 0 && w.aux + w.ngl <= n_gl;
+          }
+        }
+    }
+    if (!ok || blocks + 1 != (int64_t)P[t].blk.size())
+      return sbfwi_fail(SBFWI_EINVAL, "direct solve program out of bounds (internal error)");
   }
-  const int64_t nrows = (int64_t)ds->row_sn.size();
-  std::vector<RowMeta> fr(nrows), br(nrows);
-  for (int64_t q = 0; q < nrows; ++q) {
-    const int J = ds->row_sn[q], i = ds->row_i[q];
-    const int64_t j0 = ds->sn_ptr[J], nj = ds->sn_ptr[J + 1] - j0, nb = ds->b_ptr[J + 1] - ds->b_ptr[J];
-    RowMeta a{};
-    a.j0 = j0;
-    a.pos = j0 + i;
-    a.node = ds->inv[j0 + i];
-    a.nj = (int32_t)nj;
-    a.len = (int32_t)(nj + ds->ncols[J]);
-    a.val_off = ds->fm_off[J] + (int64_t)i * a.len;
-    a.col_off = ds->cf_off[J];
-    fr[q] = a;
-    a.len = (int32_t)(nj + nb);
-    a.val_off = ds->bm_off[J] + (int64_t)i * a.len;
-    a.col_off = ds->b_ptr[J];
-    br[q] = a;
+  for (int64_t e : gl)
+    if (e < 0 || e >= n_upd) return sbfwi_fail(SBFWI_EINVAL, "direct solve program out of bounds (internal error)");
+  for (int t = 0; t < 2; ++t) {
+    SBFWI_CHECK(sbfwi_upload(&ds->prog[t].vrec, P[t].v));
+    SBFWI_CHECK(sbfwi_upload(&ds->prog[t].rrec, P[t].r));
+    SBFWI_CHECK(sbfwi_upload(&ds->prog[t].steps, P[t].st));
+    SBFWI_CHECK(sbfwi_upload(&ds->prog[t].blk, P[t].blk));
   }
-  DirectDev& d = ds->d;
-  SBFWI_CHECK(sbfwi_upload(&d.inv, ds->inv));
-  SBFWI_CHECK(sbfwi_upload(&d.sn_ptr, ds->sn_ptr));
-  SBFWI_CHECK(sbfwi_upload(&d.b_ptr, ds->b_ptr));
-  SBFWI_CHECK(sbfwi_upload(&d.bpos, ds->bpos));
-  SBFWI_CHECK(sbfwi_upload(&d.ncols, ds->ncols));
-  SBFWI_CHECK(sbfwi_upload(&d.cf_off, ds->cf_off));
-  SBFWI_CHECK(sbfwi_upload(&d.col_idx, ds->col_idx));
-  SBFWI_CHECK(sbfwi_upload(&d.fm_off, ds->fm_off));
-  SBFWI_CHECK(sbfwi_upload(&d.bm_off, ds->bm_off));
-  SBFWI_CHECK(sbfwi_upload(&d.fwd_rows, fr));
-  SBFWI_CHECK(sbfwi_upload(&d.bwd_rows, br));
-  if (ds->n_sub > 0) {
-    SBFWI_CHECK(sbfwi_upload(&ds->seg_dev, ds->seg));
-    SBFWI_CHECK(sbfwi_upload(&ds->sub_rows_dev, ds->sub_rows));
-  }
+  if (gl.empty()) gl.push_back(0);
+  SBFWI_CHECK(sbfwi_upload(&ds->gl_idx, gl));
   return SBFWI_OK;
 }
 
 void sbfwi_direct_sym_free(DirectSym* ds) {
   if (!ds) return;
-  DirectDev& d = ds->d;
-  void* ptrs[] = {d.inv, d.sn_ptr, d.b_ptr, d.bpos, d.ncols, d.cf_off, d.col_idx, d.fm_off, d.bm_off,
-                  d.fwd_rows, d.bwd_rows, ds->seg_dev, ds->sub_rows_dev};
-  for (void* p : ptrs) sbfwi_dev_free(p);
+  for (int t = 0; t < 2; ++t) {
+    sbfwi_dev_free(ds->prog[t].vrec);
+    sbfwi_dev_free(ds->prog[t].rrec);
+    sbfwi_dev_free(ds->prog[t].steps);
+    sbfwi_dev_free(ds->prog[t].blk);
+  }
+  sbfwi_dev_free(ds->gl_idx);
   delete ds;
 }
 
@@ -645,52 +711,14 @@ int sbfwi_direct_factor(sbfwi_factors_s* f, hipStream_t s) {
       return sbfwi_fail(rc.load(), rc == SBFWI_ESINGULAR ? "coarse matrix: zero pivot in the direct factorisation"
                                                          : "direct factorisation: dissection misses a coupling");
   }
-  // folded row blocks: forward FM_J = [P_J | -P_J Lrow_J], backward BM_J = [Q_J | -Q_J U12_J]
-  // and for K^T: [Q_J^T | -Q_J^T Lrow'_J], [P_J^T | -P_J^T L21_J^T]
-  const int64_t nf = ds->fm_off[nS], nbm = ds->bm_off[nS];
-  std::vector<double> FM(nf), BM(nbm), FMt(nf), BMt(nbm);
-  struct Item {
-    int J, r0, r1;
-  };
-  std::vector<Item> items;
-  for (int J = 0; J < nS; ++J) {
-    const int nj = (int)(ds->sn_ptr[J + 1] - ds->sn_ptr[J]);
-    const int64_t work = (int64_t)nj * (nj + ds->ncols[J]);
-    const int chunk = work > (1 << 16) ? std::max(1, (int)((1 << 16) / std::max<int64_t>(1, nj + ds->ncols[J]))) : nj;
-    for (int r0 = 0; r0 < nj; r0 += chunk) items.push_back({J, r0, std::min(nj, r0 + chunk)});
-  }
-  // Lrow_J / Lrow'_J (nj x ncols): rows of the contributors' L21 (U12^T) that fall in J
-  std::vector<std::vector<double>> lrow(nS), lrowt(nS);
+  // row blocks: forward FW_J = [P_J ; L21_J P_J], backward BM_J = [Q_J | -Q_J U12_J];
+  // for K^T: [Q_J^T ; U12_J^T Q_J^T] and [P_J^T | -P_J^T L21_J^T]
+  const int64_t nfw = ds->fw_off[nS], nbm = ds->bm_off[nS];
+  std::vector<double> FW(nfw), BM(nbm), FWt(nfw), BMt(nbm);
   parallel_for(nS, [&](int64_t Jq) {
     const int J = (int)Jq;
-    const int64_t j0 = ds->sn_ptr[J];
-    const int nj = (int)(ds->sn_ptr[J + 1] - j0);
-    const int64_t nc = ds->ncols[J];
-    lrow[J].assign((size_t)nj * nc, 0.0);
-    lrowt[J].assign((size_t)nj * nc, 0.0);
-    int64_t c0 = 0;
-    for (int D : ds->ctr[J]) {
-      const int nd = (int)(ds->sn_ptr[D + 1] - ds->sn_ptr[D]);
-      const int64_t db0 = ds->b_ptr[D];
-      const int dnb = (int)(ds->b_ptr[D + 1] - db0);
-      for (int k = 0; k < dnb; ++k) {
-        const int64_t p = ds->bpos[db0 + k];
-        if (p < j0 || p >= j0 + nj) continue;
-        const int i = (int)(p - j0);
-        for (int mm = 0; mm < nd; ++mm) {
-          lrow[J][(size_t)i * nc + c0 + mm] = fo[D].L21[(size_t)k * nd + mm];
-          lrowt[J][(size_t)i * nc + c0 + mm] = fo[D].U12[(size_t)mm * dnb + k];
-        }
-      }
-      c0 += nd;
-    }
-  });
-  parallel_for((int64_t)items.size(), [&](int64_t q) {
-    const Item it = items[q];
-    const int J = it.J;
     const int nj = (int)(ds->sn_ptr[J + 1] - ds->sn_ptr[J]);
     const int nb = (int)(ds->b_ptr[J + 1] - ds->b_ptr[J]);
-    const int64_t nc = ds->ncols[J];
     const FrontOut& o = fo[J];
     std::vector<double> Pt((size_t)nj * nj), Qt((size_t)nj * nj), L21t((size_t)nj * nb);
     for (int i = 0; i < nj; ++i)
@@ -700,25 +728,41 @@ int sbfwi_direct_factor(sbfwi_factors_s* f, hipStream_t s) {
       }
     for (int r = 0; r < nb; ++r)
       for (int k = 0; k < nj; ++k) L21t[(size_t)k * nb + r] = o.L21[(size_t)r * nj + k];
-    fold_rows(o.P.data(), lrow[J].data(), nj, nc, it.r0, it.r1, &FM[ds->fm_off[J]]);
-    fold_rows(Pt.data(), lrowt[J].data(), nj, nc, it.r0, it.r1, &FMt[ds->fm_off[J]]);
-    fold_rows(o.Q.data(), o.U12.data(), nj, nb, it.r0, it.r1, &BM[ds->bm_off[J]]);
-    fold_rows(Qt.data(), L21t.data(), nj, nb, it.r0, it.r1, &BMt[ds->bm_off[J]]);
+    double* fw = &FW[ds->fw_off[J]];
+    double* fwt = &FWt[ds->fw_off[J]];
+    std::copy(o.P.begin(), o.P.end(), fw);
+    std::copy(Pt.begin(), Pt.end(), fwt);
+    for (int r = 0; r < nb; ++r) {   // C P with C = L21 (K_g) or U12^T (K_g^T)
+      double* a = fw + (size_t)(nj + r) * nj;
+      double* at = fwt + (size_t)(nj + r) * nj;
+      for (int k = 0; k < nj; ++k) a[k] = at[k] = 0.0;
+      for (int mm = 0; mm < nj; ++mm) {
+        const double c = o.L21[(size_t)r * nj + mm], ct = o.U12[(size_t)mm * nb + r];
+        const double* pr = &o.P[(size_t)mm * nj];
+        const double* ptr = &Pt[(size_t)mm * nj];
+        if (c != 0.0)
+          for (int k = 0; k < nj; ++k) a[k] += c * pr[k];
+        if (ct != 0.0)
+          for (int k = 0; k < nj; ++k) at[k] += ct * ptr[k];
+      }
+    }
+    fold_rows(o.Q.data(), o.U12.data(), nj, nb, 0, nj, &BM[ds->bm_off[J]]);
+    fold_rows(Qt.data(), L21t.data(), nj, nb, 0, nj, &BMt[ds->bm_off[J]]);
   });
   DirectNum* dn = new DirectNum();
   f->dnum = dn;
-  SBFWI_CHECK(sbfwi_upload(&dn->FM[0], FM));
+  SBFWI_CHECK(sbfwi_upload(&dn->FW[0], FW));
   SBFWI_CHECK(sbfwi_upload(&dn->BM[0], BM));
-  SBFWI_CHECK(sbfwi_upload(&dn->FM[1], FMt));
+  SBFWI_CHECK(sbfwi_upload(&dn->FW[1], FWt));
   SBFWI_CHECK(sbfwi_upload(&dn->BM[1], BMt));
-  f->bytes += 8 * 2 * (nf + nbm);
+  f->bytes += 8 * 2 * (nfw + nbm);
   return SBFWI_OK;
 }
 
 void sbfwi_direct_num_free(DirectNum* dn) {
   if (!dn) return;
   for (int t = 0; t < 2; ++t) {
-    sbfwi_dev_free(dn->FM[t]);
+    sbfwi_dev_free(dn->FW[t]);
     sbfwi_dev_free(dn->BM[t]);
   }
   delete dn;
@@ -729,57 +773,58 @@ void sbfwi_direct_num_free(DirectNum* dn) {
 namespace {
 
 template <int NSM>
-void launch_rows(bool fwd, DirectSym* ds, int l, const double* vals, int NS, const double* vin,
-                 const double* vdone, double* out_pos, double* out_node, int* status, int count, hipStream_t s) {
-  if (l < 0) {   // the subtree blocks below the cut level
-    if (fwd)
-      hipLaunchKernelGGL((direct_subtree_kernel<NSM, true>), dim3(ds->n_sub), dim3(DT), 0, s, ds->d, ds->seg_dev,
-                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status, count);
-    else
-      hipLaunchKernelGGL((direct_subtree_kernel<NSM, false>), dim3(ds->n_sub), dim3(DT), 0, s, ds->d, ds->seg_dev,
-                         ds->NL, ds->sub_rows_dev, vals, NS, vin, vdone, out_pos, out_node, status, count);
-    return;
-  }
-  const int64_t r0 = ds->row_ptr[l], nr = ds->row_ptr[l + 1] - r0;
-  const int G = fwd ? ds->g_fwd[l] : ds->g_bwd[l];
-  const unsigned blocks = (unsigned)((nr * G + DT - 1) / DT);
-  if (fwd)
-    hipLaunchKernelGGL((direct_rows_kernel<NSM, true>), dim3(blocks), dim3(DT), 0, s, ds->d, r0, nr, G, vals, NS,
-                       vin, vdone, out_pos, out_node, status, count);
+void launch_prog(int t, const DirectSym* ds, const DLaunch& L, const double* vals, int NS, int s0,
+                 const double* in, double* upd, double* out, int* status, int count, hipStream_t s) {
+  const size_t lds = (size_t)L.slots * NSM * sizeof(double);
+  if (t == 0)
+    hipLaunchKernelGGL((direct_prog_kernel<NSM, true>), dim3((unsigned)L.nblk), dim3(DT), lds, s, ds->prog[0],
+                       L.blk0, L.G, ds->gl_idx, vals, NS, s0, in, upd, out, status, count);
   else
-    hipLaunchKernelGGL((direct_rows_kernel<NSM, false>), dim3(blocks), dim3(DT), 0, s, ds->d, r0, nr, G, vals, NS,
-                       vin, vdone, out_pos, out_node, status, count);
+    hipLaunchKernelGGL((direct_prog_kernel<NSM, false>), dim3((unsigned)L.nblk), dim3(DT), lds, s, ds->prog[1],
+                       L.blk0, L.G, ds->gl_idx, vals, NS, s0, in, upd, out, status, count);
 }
 
-void launch_rows_ns(bool fwd, DirectSym* ds, int l, const double* vals, int NS, const double* vin,
-                    const double* vdone, double* out_pos, double* out_node, int* status, int count, hipStream_t s) {
-  if (NS == 1) launch_rows<1>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
-  else if (NS == 2) launch_rows<2>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
-  else if (NS <= 4) launch_rows<4>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
-  else if (NS <= 8) launch_rows<8>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
-  else launch_rows<16>(fwd, ds, l, vals, NS, vin, vdone, out_pos, out_node, status, count, s);
+// Runs one direction's program for shots s0 .. s0 + nsm - 1 (nsm a power of two).
+void run_prog(int t, const DirectSym* ds, int nsm, const double* vals, int NS, int s0, const double* in,
+              double* upd, double* out, int* status, bool count_last, hipStream_t s) {
+  const size_t nl = ds->launches[t].size();
+  for (size_t k = 0; k < nl; ++k) {
+    const DLaunch& L = ds->launches[t][k];
+    const int count = count_last && k + 1 == nl;
+    if (L.nblk == 0) continue;
+    switch (nsm) {
+      case 1: launch_prog<1>(t, ds, L, vals, NS, s0, in, upd, out, status, count, s); break;
+      case 2: launch_prog<2>(t, ds, L, vals, NS, s0, in, upd, out, status, count, s); break;
+      case 4: launch_prog<4>(t, ds, L, vals, NS, s0, in, upd, out, status, count, s); break;
+      case 8: launch_prog<8>(t, ds, L, vals, NS, s0, in, upd, out, status, count, s); break;
+      default: launch_prog<16>(t, ds, L, vals, NS, s0, in, upd, out, status, count, s); break;
+    }
+  }
 }
 
 }  // namespace
 
 int sbfwi_direct_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const double* b, double* x,
                        hipStream_t s) {
-  DirectSym* ds = f->m->dsym;
-  DirectNum* dn = f->dnum;
+  const DirectSym* ds = f->m->dsym;
+  const DirectNum* dn = f->dnum;
   const int t = transpose ? 1 : 0;
   const int NS = w->NS;
-  int* st = f->d.status;
   ProfScope ps(PK_SOLVE, s);
-  const int top = std::min(ds->depth, ds->cut - 1);   // deepest level launched on its own
-  // forward, deepest level first: y (by position) from b (by node) and the contributors' y;
-  // the levels at and below the cut level run in one launch of subtree blocks (level -1)
-  if (ds->n_sub > 0) launch_rows_ns(true, ds, -1, dn->FM[t], NS, b, w->dyb, w->dyb, nullptr, st, 0, s);
-  for (int l = top; l >= 0; --l) launch_rows_ns(true, ds, l, dn->FM[t], NS, b, w->dyb, w->dyb, nullptr, st, 0, s);
-  // backward, root first: x (by position and by node) from y and the solved B sets; the
-  // last launch counts the solve
-  for (int l = 0; l <= top; ++l)
-    launch_rows_ns(false, ds, l, dn->BM[t], NS, w->dyb, w->dxp, w->dxp, x, st, ds->n_sub == 0 && l == top, s);
-  if (ds->n_sub > 0) launch_rows_ns(false, ds, -1, dn->BM[t], NS, w->dyb, w->dxp, w->dxp, x, st, 1, s);
+  // shots per pass: the shot count rounded up to a power of two, at most 16, and
+  // small enough that the largest block vector fits in 64 KiB of LDS
+  int nsm = 1;
+  while (nsm < NS && nsm < 16) nsm *= 2;
+  while (nsm > 1 && (size_t)ds->max_slots * nsm * sizeof(double) > 65536) nsm /= 2;
+  if ((size_t)ds->max_slots * sizeof(double) > 65536)
+    return sbfwi_fail(SBFWI_EINVAL, "direct solve: a supernode front is too large for LDS");
+  for (int s0 = 0; s0 < NS; s0 += nsm) {
+    const bool last = s0 + nsm >= NS;
+    // forward, leaves first: y (by position) and the update vectors from b (by node)
+    run_prog(0, ds, nsm, dn->FW[t], NS, s0, b, w->dupd, w->dyb, f->d.status, false, s);
+    // backward, root first: x (by position and by node) from y
+    run_prog(1, ds, nsm, dn->BM[t], NS, s0, w->dyb, w->dxp, x, f->d.status, last, s);
+  }
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;
 }
@@ -791,8 +836,8 @@ extern "C" int sbfwi_direct_info(sbfwi_mesh m, int64_t* out) {
   out[0] = ds->nS;
   out[1] = ds->depth;
   out[2] = ds->max_nj;
-  out[3] = ds->fm_off[ds->nS];
-  out[4] = ds->bm_off[ds->nS];
+  out[3] = ds->sum_j2;
+  out[4] = ds->sum_jb;
   out[5] = ds->b_ptr[ds->nS];
   int64_t mx = 0;
   for (int l = 0; l <= ds->depth; ++l) mx = std::max<int64_t>(mx, ds->lvl_ptr[l + 1] - ds->lvl_ptr[l]);

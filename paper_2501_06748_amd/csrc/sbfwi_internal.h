@@ -58,40 +58,55 @@ struct MeshDev {
 #define ELL_SLICE 256
 #define ELL_LPR 4
 
-// One row of the direct solve: where its values, columns and output live.
-struct alignas(16) RowMeta {
-  int64_t val_off, col_off, j0, pos, node;
-  int32_t nj, len;
+// Direct solve programs (direct.hip).  A block of the solve kernel runs a list
+// of steps; a step first assembles vectors in LDS (one DVRec per LDS slot, one
+// value per shot), then evaluates dense rows against them (one DRRec per row).
+struct alignas(16) DVRec {
+  int64_t src;     // forward: node of the right-hand side; backward: position of y (own) or x (B set)
+  int64_t gl;      // forward: start of the slot's list of children's update entries
+  int32_t ngl;     // forward: length of that list; backward: 0 = read y, 1 = read x
+  int32_t slot;    // LDS slot
 };
-// Nested-dissection structure of the coarse system (direct.hip): device view.
-struct DirectDev {
-  int64_t* inv = nullptr;      // [n] node at each elimination position
-  int64_t* sn_ptr = nullptr;   // [nS+1] position range of each supernode (postorder)
-  int64_t* b_ptr = nullptr;    // [nS+1] range of each supernode's B set in bpos
-  int64_t* bpos = nullptr;     // positions coupled to a supernode after its subtree's elimination
-  int64_t* ncols = nullptr;    // [nS] positions of the supernode's contributors
-  int64_t* cf_off = nullptr;   // [nS+1] their range in col_idx
-  int64_t* col_idx = nullptr;  // contributor positions, supernode after supernode
-  int64_t* fm_off = nullptr;   // [nS+1] forward row blocks: |J| x (|J| + ncols)
-  int64_t* bm_off = nullptr;   // [nS+1] backward row blocks: |J| x (|J| + |B_J|)
-  RowMeta* fwd_rows = nullptr;   // rows level by level (forward solve)
-  RowMeta* bwd_rows = nullptr;   // rows level by level (backward solve)
+struct alignas(16) DRRec {
+  int64_t val;     // offset of the row's values
+  int64_t out;     // forward: position of y (kind 0) or update entry (kind 1); backward: position of x
+  int64_t aux;     // forward kind 1: start of the row's list of children's update entries; backward: node
+  int32_t len;     // columns (LDS slots slot0 .. slot0 + len - 1)
+  int32_t slot0;
+  int32_t ngl;     // forward kind 1: length of that list
+  int32_t kind;    // forward: 0 = row of y, 1 = row of the update vector
 };
+struct DStep {
+  int64_t v0, v1, r0, r1;   // slot records [v0, v1), row records [r0, r1)
+};
+struct DProgDev {
+  DVRec* vrec = nullptr;
+  DRRec* rrec = nullptr;
+  DStep* steps = nullptr;
+  int64_t* blk = nullptr;    // steps of block b: [blk[b], blk[b+1])
+};
+struct DLaunch {
+  int64_t blk0 = 0, nblk = 0;   // blocks of the launch in the program's block list
+  int G = 1, slots = 0;         // lanes per row, LDS slots per block
+};
+// Nested-dissection structure of the coarse system and the solve programs.
 struct DirectSym {
   int nS = 0, depth = 0;
-  int64_t max_nj = 0;
-  std::vector<int64_t> pos, inv, sn_ptr, b_ptr, bpos, ncols, cf_off, col_idx, fm_off, bm_off, row_ptr;
-  std::vector<int32_t> level, lvl_ptr, lvl_sn, row_sn, row_i, g_fwd, g_bwd, snp;
-  std::vector<std::vector<int32_t>> children, ctr;
-  int cut = 0, n_sub = 0, NL = 0;            // subtree blocks: cut level, their count, levels per subtree
-  std::vector<int64_t> seg, sub_rows;        // per subtree: row segments by level (deepest first)
-  int64_t *seg_dev = nullptr, *sub_rows_dev = nullptr;
-  DirectDev d;
+  int64_t max_nj = 0, sum_j2 = 0, sum_jb = 0;
+  std::vector<int64_t> pos, inv, sn_ptr, b_ptr, bpos, fw_off, bm_off;
+  std::vector<int32_t> level, lvl_ptr, lvl_sn, snp;
+  std::vector<std::vector<int32_t>> children;
+  int cut = 0, n_sub = 0;             // subtree blocks: cut level and their count
+  int max_slots = 0;                  // largest LDS vector of any block (slots)
+  std::vector<DLaunch> launches[2];   // forward, backward programs in launch order
+  DProgDev prog[2];
+  int64_t* gl_idx = nullptr;          // children's update entries gathered by the forward slots and rows
   int sn_of(int64_t p) const { return snp[p]; }
 };
-// Folded row blocks of K_g (index 0) and of K_g^T (index 1), row-major per supernode.
+// Row blocks of K_g (index 0) and of K_g^T (index 1), row-major per supernode:
+// forward FW_J = [P_J ; C_J P_J], backward BM_J = [Q_J | -Q_J U12_J] (see direct.hip).
 struct DirectNum {
-  double* FM[2] = {nullptr, nullptr};
+  double* FW[2] = {nullptr, nullptr};
   double* BM[2] = {nullptr, nullptr};
 };
 
@@ -246,6 +261,7 @@ struct CoarseWork {
   unsigned* bar = nullptr;
   int nblocks = 0, nthreads = 0;
   double *dyb = nullptr, *dxp = nullptr;   // direct solve: y and x by elimination position
+  double* dupd = nullptr;                  // direct solve: the supernodes' update vectors
 };
 int sbfwi_coarse_work_alloc(CoarseWork* w, sbfwi_mesh_s* m, int NS);
 void sbfwi_coarse_work_free(CoarseWork* w);

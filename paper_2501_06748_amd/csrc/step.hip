@@ -47,12 +47,15 @@ struct StepLds {
 
 constexpr int WT = 64;
 
+// loads are unconditional (lanes past the block reread word 0), so that the
+// waits for them do not depend on branches
 template <int NBT>
 __device__ __forceinline__ void prefetch(double (&reg)[(NBT * NBT + WT - 1) / WT], const double* src, int nbnb) {
 #pragma unroll
   for (int r = 0; r < (NBT * NBT + WT - 1) / WT; ++r) {
     int q = threadIdx.x + r * WT;
-    reg[r] = q < nbnb ? src[q] : 0.0;
+    const double v = src[q < nbnb ? q : 0];
+    reg[r] = q < nbnb ? v : 0.0;
   }
 }
 
@@ -78,59 +81,116 @@ __device__ __forceinline__ double dense_mv(const double* F, const double* vec, i
   return acc;
 }
 
+// Target of the stores of lanes without an item, so that every lane stores
+// unconditionally and the waits for the prefetched level count exactly.
+__device__ double g_sink[WT];
+
 template <int NBT, int S>
 __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                               const StepArgs& a, StepLds<NBT, S>& L) {
+  // Levels j = 0 .. n-1 stream: the next level's F block, state (u, v, a; on the
+  // boundary level the nodal state) and bands P, theta are loaded at the top of
+  // each level and consumed at its end; lanes without an item load word 0 of
+  // their arrays and store to g_sink.
+  constexpr int IPT = (NBT * S + WT - 1) / WT;
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e];
   const double* Fe = f.finv + m.finv_off[e];
   const int items = nb * S;
+  int ii[IPT], si[IPT];
+  bool own[IPT], ok[IPT];
+  int64_t lnode[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int it = threadIdx.x + u * WT;
+    own[u] = it < items;
+    ii[u] = own[u] ? it / S : 0;
+    si[u] = it % S;
+    ok[u] = own[u] && si[u] < ns;
+    lnode[u] = m.loop_nodes[lo + ii[u]];
+  }
   double reg[(NBT * NBT + WT - 1) / WT];
+  double cu[IPT], cv[IPT], ca[IPT], cp[3][IPT], ct[3][IPT];
+  auto load_level = [&](int j, double (&uu)[IPT], double (&vv)[IPT], double (&aa)[IPT], double (&pb)[3][IPT],
+                        double (&tb)[3][IPT]) {
+    const bool nodal = j == n;
+    const double* su = nodal ? a.U : a.u;
+    const double* sv = nodal ? a.V : a.v;
+    const double* sa = nodal ? a.A : a.a;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int64_t row = nodal ? lnode[u] : io + (int64_t)j * nb + ii[u];
+      const int64_t g = ok[u] ? row * a.NS + s0 + si[u] : 0;
+      uu[u] = su[g];
+      vv[u] = sv[g];
+      aa[u] = sa[g];
+      const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb) + ii[u];   // node 0 for lanes without an item
+      const double* tp = f.th_band + 3 * (po + (int64_t)j * nb) + ii[u];
+      pb[0][u] = pp[0];
+      pb[1][u] = pp[nb];
+      pb[2][u] = pp[2 * nb];
+      tb[0][u] = tp[0];
+      tb[1][u] = tp[nb];
+      tb[2][u] = tp[2 * nb];
+    }
+  };
+  // y_j = P_j w_j - theta_j q_{j-1} into L.y (L.x holds q_{j-1})
+  auto level_rhs = [&](int j) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT;
+      if (own[u]) L.w[it] = ok[u] ? f.a0 * cu[u] + f.a1 * cv[u] + f.a2 * ca[u] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      const int im = md(i - 1, nb) * S + s, ic = i * S + s, ip = md(i + 1, nb) * S + s;
+      double y = cp[0][u] * L.w[im] + cp[1][u] * L.w[ic] + cp[2][u] * L.w[ip];
+      if (j > 0) y -= ct[0][u] * L.x[im] + ct[1][u] * L.x[ic] + ct[2][u] * L.x[ip];
+      if (own[u]) L.y[it] = y;
+    }
+    __syncthreads();
+  };
   prefetch<NBT>(reg, Fe, nbnb);
   commit<NBT>(reg, L.F[0], nb);
+  load_level(0, cu, cv, ca, cp, ct);
   int cur = 0;
-  for (int j = 0; j <= n; ++j) {
-    // w_j = a0 u + a1 v + a2 a (interior level, or the nodal state on the boundary level)
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      double w = 0.0;
-      if (s < ns) {
-        if (j < n) {
-          int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
-          w = f.a0 * a.u[g] + f.a1 * a.v[g] + f.a2 * a.a[g];
-        } else {
-          int64_t g = m.loop_nodes[lo + i] * a.NS + s0 + s;
-          w = f.a0 * a.U[g] + f.a1 * a.V[g] + f.a2 * a.A[g];
-        }
-      }
-      L.w[it] = w;
+  __syncthreads();
+  __builtin_amdgcn_s_waitcnt(0);   // nothing in flight at the loop entry
+  for (int j = 0; j < n; ++j) {
+    const int jf = j + 1 < n ? j + 1 : n - 1;   // the last interior level reloads its own block (unused)
+    prefetch<NBT>(reg, Fe + (int64_t)jf * nbnb, nbnb);
+    double nu[IPT], nv[IPT], na[IPT], np[3][IPT], nt[3][IPT];
+    load_level(j + 1, nu, nv, na, np, nt);
+    level_rhs(j);
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      const double qv = dense_mv<NBT>(L.F[cur], L.y, nb, i, s, S);
+      if (own[u]) L.t[it] = qv;
+      const int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
+      *(ok[u] ? a.q + g : g_sink + threadIdx.x) = qv;
     }
-    if (j + 1 < n) prefetch<NBT>(reg, Fe + (int64_t)(j + 1) * nbnb, nbnb);
+    commit<NBT>(reg, L.F[cur ^ 1], nb);
     __syncthreads();
-    const double* pm = f.pm_band + 3 * (po + (int64_t)j * nb);
-    const double* th = f.th_band + 3 * (po + (int64_t)j * nb);
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      double y = band_mv(pm, L.w, nb, i, s, S);
-      if (j > 0) y -= band_mv(th, L.x, nb, i, s, S);   // L.x holds q_{j-1}
-      L.y[it] = y;
-    }
+    for (int it = threadIdx.x; it < items; it += WT) L.x[it] = L.t[it];  // q_j
     __syncthreads();
-    if (j < n) {
-      for (int it = threadIdx.x; it < items; it += WT) {
-        int i = it / S, s = it % S;
-        double qv = dense_mv<NBT>(L.F[cur], L.y, nb, i, s, S);
-        L.t[it] = qv;
-        if (s < ns) a.q[(io + (int64_t)j * nb + i) * a.NS + s0 + s] = qv;
+    cur ^= 1;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      cu[u] = nu[u];
+      cv[u] = nv[u];
+      ca[u] = na[u];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        cp[k][u] = np[k][u];
+        ct[k][u] = nt[k][u];
       }
-      if (j + 1 < n) commit<NBT>(reg, L.F[cur ^ 1], nb);
-      __syncthreads();
-      for (int it = threadIdx.x; it < items; it += WT) L.x[it] = L.t[it];  // q_j
-      __syncthreads();
-      cur ^= 1;
     }
   }
+  level_rhs(n);   // boundary level: y_n
   // y_n -> global; f_hat = -theta_{n+1} q_{n-1} - G y_n
   const double* Ge = f.G + m.dense_off[e];
   prefetch<NBT>(reg, Ge, nbnb);
@@ -143,6 +203,119 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
     if (s < ns) {
       a.yn[(lo + i) * a.NS + s0 + s] = L.y[it];
       a.fhat[(lo + i) * a.NS + s0 + s] = fh;
+    }
+  }
+}
+
+// Level loop of the recovery sweep (j = n-1 .. 0).  The next level's F block,
+// state (q, u, v, a) and psi~ band are loaded at the top of each level and
+// consumed at its end, so the sweep streams without waiting on the level
+// recursion; the loads of lanes without an item read word 0 and the stores
+// of such lanes go to g_sink.
+template <int NBT, int S, bool STORE>
+__device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, const FactorsDev& f,
+                                               const StepArgs& a, StepLds<NBT, S>& L) {
+  constexpr int IPT = (NBT * S + WT - 1) / WT;
+  const int ns = min(S, a.NS - s0);
+  const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
+  const int64_t io = m.int_off[e], po = m.par_off[e], xo = m.x_off[e];
+  const double* Fe = f.finv + m.finv_off[e];
+  const int items = nb * S;
+  int ii[IPT], si[IPT];
+  bool own[IPT], ok[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    const int it = threadIdx.x + u * WT;
+    own[u] = it < items;
+    ii[u] = own[u] ? it / S : 0;
+    si[u] = it % S;
+    ok[u] = own[u] && si[u] < ns;
+  }
+  double reg[(NBT * NBT + WT - 1) / WT];
+  double cq[IPT], cu[IPT], cv[IPT], ca[IPT], cb[3][IPT];
+  auto load_level = [&](int j, double (&q)[IPT], double (&uu)[IPT], double (&vv)[IPT], double (&aa)[IPT],
+                        double (&bd)[3][IPT]) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int64_t g = ok[u] ? (io + (int64_t)j * nb + ii[u]) * a.NS + s0 + si[u] : 0;
+      q[u] = a.q[g];
+      uu[u] = a.u[g];
+      vv[u] = a.v[g];
+      aa[u] = a.a[g];
+      const double* bp = f.ps_band + 3 * (po + (int64_t)j * nb) + ii[u];   // node 0 for lanes without an item
+      bd[0][u] = bp[0];
+      bd[1][u] = bp[nb];
+      bd[2][u] = bp[2 * nb];
+    }
+  };
+  load_level(n - 1, cq, cu, cv, ca, cb);
+  int cur = 0;
+  __syncthreads();
+  // nothing in flight at the loop entry: the compiler then counts the waits
+  // inside the loop from the loop's own loads and stores alone
+  __builtin_amdgcn_s_waitcnt(0);
+  for (int j = n - 1; j >= 0; --j) {
+    const int jn = j > 0 ? j - 1 : 0;   // the last level reloads level 0 (unused)
+    prefetch<NBT>(reg, Fe + (int64_t)jn * nbnb, nbnb);
+    double nq[IPT], nu[IPT], nv[IPT], na[IPT], nbd[3][IPT];
+    load_level(jn, nq, nu, nv, na, nbd);
+    // t = psi~_j u_{j+1}
+    if (j > 0) {
+#pragma unroll
+      for (int u = 0; u < IPT; ++u) {
+        const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+        if (own[u])
+          L.t[it] = cb[0][u] * L.x[md(i - 1, nb) * S + s] + cb[1][u] * L.x[i * S + s] +
+                    cb[2][u] * L.x[md(i + 1, nb) * S + s];
+      }
+    } else {
+      const double* P0 = f.psit0 + m.dense_off[e];
+      for (int it = threadIdx.x; it < items; it += WT) {
+        int i = it / S, s = it % S;
+        double acc = 0.0;
+        for (int c = 0; c < nb; ++c) acc += P0[i * nb + c] * L.x[c * S + s];
+        L.t[it] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
+      const int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
+      const double uj = ok[u] ? cq[u] - dense_mv<NBT>(L.F[cur], L.t, nb, i, s, S) : 0.0;
+      const double uo = cu[u], vo = cv[u], ao = ca[u];
+      const double w = f.a0 * uo + f.a1 * vo + f.a2 * ao;
+      const double vn = f.c1 * (uj - uo) + f.c2 * vo + f.c3 * ao;
+      const double an = f.a0 * uj - w;
+      double* sink = g_sink + threadIdx.x;
+      *(ok[u] ? a.u + g : sink) = uj;
+      *(ok[u] ? a.v + g : sink) = vn;
+      *(ok[u] ? a.a + g : sink) = an;
+      if (STORE) {
+        const int64_t gp = (po + (int64_t)j * nb + i) * a.NS + s0 + s;
+        *(ok[u] ? a.xs + (xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s : sink) = uj;
+        *(ok[u] ? a.fs + gp : sink) = a.field_kind == 0 ? an : vn;
+        *(ok[u] && a.vs ? a.vs + gp : sink) = vn;
+      }
+      if (own[u]) L.y[it] = uj;
+    }
+    commit<NBT>(reg, L.F[cur ^ 1], nb);   // the last level commits an unused block
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += WT) {
+      if (j == 1) L.u1[it] = L.y[it];
+      L.x[it] = L.y[it];
+    }
+    __syncthreads();
+    cur ^= 1;
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      cq[u] = nq[u];
+      cu[u] = nu[u];
+      cv[u] = nv[u];
+      ca[u] = na[u];
+      cb[0][u] = nbd[0][u];
+      cb[1][u] = nbd[1][u];
+      cb[2][u] = nbd[2][u];
     }
   }
 }
@@ -172,54 +345,9 @@ __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, co
       if (a.vs) a.vs[(po + (int64_t)n * nb + i) * a.NS + s0 + s] = a.V[m.loop_nodes[lo + i] * a.NS + s0 + s];
     }
   }
-  int cur = 0;
   __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
-    if (j > 0) prefetch<NBT>(reg, Fe + (int64_t)(j - 1) * nbnb, nbnb);
-    // t = psi~_j u_{j+1}
-    if (j > 0) {
-      const double* ps = f.ps_band + 3 * (po + (int64_t)j * nb);
-      for (int it = threadIdx.x; it < items; it += WT) L.t[it] = band_mv(ps, L.x, nb, it / S, it % S, S);
-    } else {
-      const double* P0 = f.psit0 + m.dense_off[e];
-      for (int it = threadIdx.x; it < items; it += WT) {
-        int i = it / S, s = it % S;
-        double acc = 0.0;
-        for (int c = 0; c < nb; ++c) acc += P0[i * nb + c] * L.x[c * S + s];
-        L.t[it] = acc;
-      }
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < items; it += WT) {
-      int i = it / S, s = it % S;
-      double uj = 0.0;
-      if (s < ns) {
-        int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
-        uj = a.q[g] - dense_mv<NBT>(L.F[cur], L.t, nb, i, s, S);
-        double uo = a.u[g], vo = a.v[g], ao = a.a[g];
-        double w = f.a0 * uo + f.a1 * vo + f.a2 * ao;
-        double vn = f.c1 * (uj - uo) + f.c2 * vo + f.c3 * ao;
-        double an = f.a0 * uj - w;
-        a.u[g] = uj;
-        a.v[g] = vn;
-        a.a[g] = an;
-        if (a.xs) {
-          a.xs[(xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s] = uj;
-          a.fs[(po + (int64_t)j * nb + i) * a.NS + s0 + s] = a.field_kind == 0 ? an : vn;
-          if (a.vs) a.vs[(po + (int64_t)j * nb + i) * a.NS + s0 + s] = vn;
-        }
-      }
-      L.y[it] = uj;
-    }
-    if (j > 0) commit<NBT>(reg, L.F[cur ^ 1], nb);
-    __syncthreads();
-    for (int it = threadIdx.x; it < items; it += WT) {
-      if (j == 1) L.u1[it] = L.y[it];
-      L.x[it] = L.y[it];
-    }
-    __syncthreads();
-    cur ^= 1;
-  }
+  if (a.xs) recover_levels<NBT, S, true>(e, s0, m, f, a, L);
+  else recover_levels<NBT, S, false>(e, s0, m, f, a, L);
   if (!a.xs) return;
   // ghosts: u_{-1} = theta_{-1}^-1 (-(phi_{-1} u_0 + psi_{-1} u_1)),
   //         u_{n+1} = psi_n^-1 (y_n - phi~_n u_n)
