@@ -132,43 +132,78 @@ struct Dissect {
 
 // One block of a solve program.  For each of its steps: the slot records
 // assemble vectors in LDS (forward: the right-hand side at the supernode's
-// nodes minus the children's update entries listed for the slot; backward: y
-// at J's positions, then x at B_J), then G lanes per row dot each dense row
-// with its supernode's vector (lane-strided, chunks of U loads in flight, a
-// fixed butterfly to sum) and write it: forward to y by position (kind 0) or,
-// plus the children's update entries listed for the row, to the update vector
-// (kind 1); backward to x by position and by node.  Shots s0 .. s0 + NSM - 1
+// nodes minus the children's update entries of the slot; backward: y at J's
+// positions, then x at B_J), then G lanes per row dot each dense row with its
+// supernode's vector (lane-strided, chunks of U values in flight, a fixed
+// butterfly to sum) and write it: forward to y by position (kind 0) or, plus
+// the children's update entries of the row, to the update vector (kind 1);
+// backward to x by position and by node.  A thread's first row record, its
+// first chunk of values and its pass-through entries are loaded before the
+// vector is assembled, so that their latency overlaps.  Shots s0 .. s0 + NSM - 1
 // of NS are handled.  A block barrier separates the steps, whose later ones
 // read what earlier ones wrote.
 template <int NSM, bool FWD>
-__global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk0, int G,
-                                                         const int64_t* __restrict__ gl_idx,
+__global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk0, int64_t st0, int G,
                                                          const double* __restrict__ vals, int NS, int s0,
                                                          const double* __restrict__ in, double* __restrict__ upd,
                                                          double* __restrict__ out, int* __restrict__ status,
                                                          int count) {
   extern __shared__ double vec[];   // [slot][NSM]
   constexpr int U = 4;
-  const int64_t b = blk0 + blockIdx.x;
   if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
   const int ns = min(NSM, NS - s0);
   const int lane = threadIdx.x % G;
+  int64_t sa, sb;
+  if (st0 >= 0) {
+    sa = st0 + blockIdx.x;
+    sb = sa + 1;
+  } else {
+    sa = p.blk[blk0 + blockIdx.x];
+    sb = p.blk[blk0 + blockIdx.x + 1];
+  }
   bool bad = false;
-  for (int64_t st = p.blk[b]; st < p.blk[b + 1]; ++st) {
+  for (int64_t st = sa; st < sb; ++st) {
     const DStep S = p.steps[st];
+    DRRec rr{};
+    double a[U], pass[NSM];
+    auto load_row = [&](int64_t r) {
+      rr = r < S.r1 ? p.rrec[r] : DRRec{};
+      const double* v = vals + rr.val;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = lane + u * G;
+        a[u] = k < rr.len ? v[k] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) pass[s] = 0.0;
+      if (FWD && lane == 0) {
+        if (rr.ngl > 0)
+#pragma unroll
+          for (int s = 0; s < NSM; ++s)
+            if (s < ns) pass[s] += upd[rr.g0 * NS + s0 + s];
+        if (rr.ngl > 1)
+#pragma unroll
+          for (int s = 0; s < NSM; ++s)
+            if (s < ns) pass[s] += upd[rr.g1 * NS + s0 + s];
+      }
+    };
+    load_row(S.r0 + threadIdx.x / G);
     for (int64_t q = S.v0 + threadIdx.x; q < S.v1; q += DT) {
       const DVRec v = p.vrec[q];
       double acc[NSM];
       const double* src = FWD ? in : (v.ngl ? upd : in);
 #pragma unroll
       for (int s = 0; s < NSM; ++s) acc[s] = s < ns ? src[v.src * NS + s0 + s] : 0.0;
-      if (FWD)
-        for (int g = 0; g < v.ngl; ++g) {
-          const int64_t e = gl_idx[v.gl + g];
+      if (FWD) {
+        if (v.ngl > 0)
 #pragma unroll
           for (int s = 0; s < NSM; ++s)
-            if (s < ns) acc[s] -= upd[e * NS + s0 + s];
-        }
+            if (s < ns) acc[s] -= upd[v.g0 * NS + s0 + s];
+        if (v.ngl > 1)
+#pragma unroll
+          for (int s = 0; s < NSM; ++s)
+            if (s < ns) acc[s] -= upd[v.g1 * NS + s0 + s];
+      }
 #pragma unroll
       for (int s = 0; s < NSM; ++s) vec[v.slot * NSM + s] = acc[s];
     }
@@ -176,18 +211,26 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
     for (int64_t base = S.r0; base < S.r1; base += DT / G) {
       const int64_t r = base + threadIdx.x / G;
       const bool valid = r < S.r1;
-      DRRec rr{};
-      if (valid) rr = p.rrec[r];
+      if (base != S.r0) load_row(r);
       double acc[NSM];
 #pragma unroll
       for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = lane + u * G;
+        if (k < rr.len) {
+          const double* x = vec + (int64_t)(rr.slot0 + k) * NSM;
+#pragma unroll
+          for (int s = 0; s < NSM; ++s) acc[s] += a[u] * x[s];
+        }
+      }
       const double* v = vals + rr.val;
-      for (int k0 = lane; k0 < rr.len; k0 += G * U) {
-        double a[U];
+      for (int k0 = lane + G * U; k0 < rr.len; k0 += G * U) {
+        double b[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int k = k0 + u * G;
-          a[u] = k < rr.len ? v[k] : 0.0;
+          b[u] = k < rr.len ? v[k] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -195,7 +238,7 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
           if (k < rr.len) {
             const double* x = vec + (int64_t)(rr.slot0 + k) * NSM;
 #pragma unroll
-            for (int s = 0; s < NSM; ++s) acc[s] += a[u] * x[s];
+            for (int s = 0; s < NSM; ++s) acc[s] += b[u] * x[s];
           }
         }
       }
@@ -209,15 +252,6 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
             for (int s = 0; s < NSM; ++s)
               if (s < ns) out[rr.out * NS + s0 + s] = acc[s];
           } else {
-            double pass[NSM];
-#pragma unroll
-            for (int s = 0; s < NSM; ++s) pass[s] = 0.0;
-            for (int g = 0; g < rr.ngl; ++g) {
-              const int64_t e = gl_idx[rr.aux + g];
-#pragma unroll
-              for (int s = 0; s < NSM; ++s)
-                if (s < ns) pass[s] += upd[e * NS + s0 + s];
-            }
 #pragma unroll
             for (int s = 0; s < NSM; ++s) {
               acc[s] += pass[s];
@@ -229,7 +263,7 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
           for (int s = 0; s < NSM; ++s)
             if (s < ns) {
               upd[rr.out * NS + s0 + s] = acc[s];
-              out[rr.aux * NS + s0 + s] = acc[s];
+              out[rr.g0 * NS + s0 + s] = acc[s];
             }
         }
 #pragma unroll
@@ -396,8 +430,10 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
       v.slot = base + (int32_t)i;
       if (t == 0) {
         v.src = ds->inv[j0 + i];
-        v.gl = gl_ptr[fr_off[J] + i];
-        v.ngl = (int32_t)(gl_ptr[fr_off[J] + i + 1] - v.gl);
+        const int64_t g = gl_ptr[fr_off[J] + i];
+        v.ngl = (int32_t)(gl_ptr[fr_off[J] + i + 1] - g);
+        v.g0 = v.ngl > 0 ? gl[g] : 0;
+        v.g1 = v.ngl > 1 ? gl[g + 1] : 0;
       } else {
         v.src = j0 + i;
       }
@@ -426,14 +462,16 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
         } else {
           w.kind = 1;
           w.out = ds->b_ptr[J] + (r - nj);
-          w.aux = gl_ptr[fr_off[J] + r];
-          w.ngl = (int32_t)(gl_ptr[fr_off[J] + r + 1] - w.aux);
+          const int64_t g = gl_ptr[fr_off[J] + r];
+          w.ngl = (int32_t)(gl_ptr[fr_off[J] + r + 1] - g);
+          w.g0 = w.ngl > 0 ? gl[g] : 0;
+          w.g1 = w.ngl > 1 ? gl[g + 1] : 0;
         }
       } else {
         w.val = ds->bm_off[J] + r * (nj + nb);
         w.len = (int32_t)(nj + nb);
         w.out = j0 + r;
-        w.aux = ds->inv[j0 + r];
+        w.g0 = ds->inv[j0 + r];
       }
       P[t].r.push_back(w);
     }
@@ -444,7 +482,8 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
     int64_t len = 1;
     for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) len = std::max(len, row_len(t, ds->lvl_sn[q]));
     L.G = lanes(len);
-    const int64_t per = (int64_t)(DT / L.G) * 4;
+    L.st0 = (int64_t)P[t].st.size();
+    const int64_t per = DT / L.G;   // one pass of rows per block
     for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) {
       const int J = ds->lvl_sn[q];
       const int64_t v0 = (int64_t)P[t].v.size();
@@ -507,13 +546,15 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   for (int t = 0; t < 2; ++t)
     for (const DLaunch& L : ds->launches[t]) ds->max_slots = std::max(ds->max_slots, L.slots);
   // every record stays inside the arrays and LDS vectors it addresses
-  const int64_t n_upd = ds->b_ptr[nS], n_gl = (int64_t)gl.size();
+  const int64_t n_upd = ds->b_ptr[nS];
   for (int t = 0; t < 2; ++t) {
     const int64_t vals = t == 0 ? ds->fw_off[nS] : ds->bm_off[nS];
     bool ok = true;
     int64_t blocks = 0;
     for (const DLaunch& L : ds->launches[t]) {
       ok = ok && L.blk0 == blocks && L.nblk >= 0 && L.blk0 + L.nblk < (int64_t)P[t].blk.size();
+      for (int64_t b = L.blk0; ok && L.st0 >= 0 && b < L.blk0 + L.nblk; ++b)   // single-step blocks
+        ok = P[t].blk[b] == L.st0 + (b - L.blk0) && P[t].blk[b + 1] == P[t].blk[b] + 1;
       blocks += L.nblk;
       for (int64_t b = L.blk0; ok && b < L.blk0 + L.nblk; ++b)
         for (int64_t q = P[t].blk[b]; ok && q < P[t].blk[b + 1]; ++q) {
@@ -522,30 +563,30 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
           for (int64_t i = S.v0; ok && i < S.v1; ++i) {
             const DVRec& v = P[t].v[i];
             ok = v.src >= 0 && v.src < n && v.slot >= 0 && v.slot < L.slots &&
-                 (t == 1 ? (v.ngl == 0 || v.ngl == 1) : (v.ngl >= 0 && v.gl >= 0 && v.gl + v.ngl <= n_gl));
+                 (t == 1 ? (v.ngl == 0 || v.ngl == 1)
+                         : (v.ngl >= 0 && v.ngl <= 2 && (v.ngl < 1 || (v.g0 >= 0 && v.g0 < n_upd)) &&
+                            (v.ngl < 2 || (v.g1 >= 0 && v.g1 < n_upd))));
           }
           for (int64_t i = S.r0; ok && i < S.r1; ++i) {
             const DRRec& w = P[t].r[i];
             ok = w.len >= 0 && w.val >= 0 && w.val + w.len <= vals && w.slot0 >= 0 && w.slot0 + w.len <= L.slots;
-            if (t == 1) ok = ok && w.out >= 0 && w.out < n && w.aux >= 0 && w.aux < n;
+            if (t == 1) ok = ok && w.out >= 0 && w.out < n && w.g0 >= 0 && w.g0 < n;
             else if (w.kind == 0) ok = ok && w.out >= 0 && w.out < n;
-            else ok = ok && w.out >= 0 && w.out < n_upd && w.ngl >= 0 && w.aux >= 0 && w.aux + w.ngl <= n_gl;
+            else
+              ok = ok && w.out >= 0 && w.out < n_upd && w.ngl >= 0 && w.ngl <= 2 &&
+                   (w.ngl < 1 || (w.g0 >= 0 && w.g0 < n_upd)) && (w.ngl < 2 || (w.g1 >= 0 && w.g1 < n_upd));
           }
         }
     }
     if (!ok || blocks + 1 != (int64_t)P[t].blk.size())
       return sbfwi_fail(SBFWI_EINVAL, "direct solve program out of bounds (internal error)");
   }
-  for (int64_t e : gl)
-    if (e < 0 || e >= n_upd) return sbfwi_fail(SBFWI_EINVAL, "direct solve program out of bounds (internal error)");
   for (int t = 0; t < 2; ++t) {
     SBFWI_CHECK(sbfwi_upload(&ds->prog[t].vrec, P[t].v));
     SBFWI_CHECK(sbfwi_upload(&ds->prog[t].rrec, P[t].r));
     SBFWI_CHECK(sbfwi_upload(&ds->prog[t].steps, P[t].st));
     SBFWI_CHECK(sbfwi_upload(&ds->prog[t].blk, P[t].blk));
   }
-  if (gl.empty()) gl.push_back(0);
-  SBFWI_CHECK(sbfwi_upload(&ds->gl_idx, gl));
   return SBFWI_OK;
 }
 
@@ -557,7 +598,6 @@ void sbfwi_direct_sym_free(DirectSym* ds) {
     sbfwi_dev_free(ds->prog[t].steps);
     sbfwi_dev_free(ds->prog[t].blk);
   }
-  sbfwi_dev_free(ds->gl_idx);
   delete ds;
 }
 
@@ -778,10 +818,10 @@ void launch_prog(int t, const DirectSym* ds, const DLaunch& L, const double* val
   const size_t lds = (size_t)L.slots * NSM * sizeof(double);
   if (t == 0)
     hipLaunchKernelGGL((direct_prog_kernel<NSM, true>), dim3((unsigned)L.nblk), dim3(DT), lds, s, ds->prog[0],
-                       L.blk0, L.G, ds->gl_idx, vals, NS, s0, in, upd, out, status, count);
+                       L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
   else
     hipLaunchKernelGGL((direct_prog_kernel<NSM, false>), dim3((unsigned)L.nblk), dim3(DT), lds, s, ds->prog[1],
-                       L.blk0, L.G, ds->gl_idx, vals, NS, s0, in, upd, out, status, count);
+                       L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
 }
 
 // Runs one direction's program for shots s0 .. s0 + nsm - 1 (nsm a power of two).

@@ -63,17 +63,18 @@ struct MeshDev {
 // value per shot), then evaluates dense rows against them (one DRRec per row).
 struct alignas(16) DVRec {
   int64_t src;     // forward: node of the right-hand side; backward: position of y (own) or x (B set)
-  int64_t gl;      // forward: start of the slot's list of children's update entries
-  int32_t ngl;     // forward: length of that list; backward: 0 = read y, 1 = read x
+  int64_t g0, g1;  // forward: the children's update entries to subtract (ngl of them)
+  int32_t ngl;     // forward: 0, 1 or 2; backward: 0 = read y, 1 = read x
   int32_t slot;    // LDS slot
 };
 struct alignas(16) DRRec {
   int64_t val;     // offset of the row's values
   int64_t out;     // forward: position of y (kind 0) or update entry (kind 1); backward: position of x
-  int64_t aux;     // forward kind 1: start of the row's list of children's update entries; backward: node
+  int64_t g0;      // forward kind 1: first child update entry passed through; backward: node
+  int64_t g1;      // forward kind 1: second one
   int32_t len;     // columns (LDS slots slot0 .. slot0 + len - 1)
   int32_t slot0;
-  int32_t ngl;     // forward kind 1: length of that list
+  int32_t ngl;     // forward kind 1: entries passed through (0, 1 or 2)
   int32_t kind;    // forward: 0 = row of y, 1 = row of the update vector
 };
 struct DStep {
@@ -87,6 +88,7 @@ struct DProgDev {
 };
 struct DLaunch {
   int64_t blk0 = 0, nblk = 0;   // blocks of the launch in the program's block list
+  int64_t st0 = -1;             // >= 0: block b of the launch runs the single step st0 + b
   int G = 1, slots = 0;         // lanes per row, LDS slots per block
 };
 // Nested-dissection structure of the coarse system and the solve programs.
@@ -100,7 +102,6 @@ struct DirectSym {
   int max_slots = 0;                  // largest LDS vector of any block (slots)
   std::vector<DLaunch> launches[2];   // forward, backward programs in launch order
   DProgDev prog[2];
-  int64_t* gl_idx = nullptr;          // children's update entries gathered by the forward slots and rows
   int sn_of(int64_t p) const { return snp[p]; }
 };
 // Row blocks of K_g (index 0) and of K_g^T (index 1), row-major per supernode:

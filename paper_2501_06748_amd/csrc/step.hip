@@ -21,6 +21,10 @@
 
 #include "sbfwi_internal.h"
 
+// Multiply-adds fuse within an expression only: every launch shape (items per
+// lane, shots per block) then rounds each (element, shot) the same way.
+#pragma clang fp contract(on)
+
 namespace {
 
 __device__ __forceinline__ int md(int i, int nb) { return i < 0 ? i + nb : (i >= nb ? i - nb : i); }
