@@ -248,6 +248,15 @@ int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* host_out);
  * [6] most supernodes on one level. */
 int sbfwi_direct_info(sbfwi_mesh m, int64_t* host_out);
 
+/* Launches of the direct solve's forward (dir 0) or backward (dir 1) program,
+ * in launch order: host_out[8 k + 0 .. 7] = blocks, lanes per row, LDS vector
+ * slots per block, steps, row records, slot records, most rows in one step,
+ * and 1 for the launch of subtree blocks (0 for a level of the dissection
+ * tree).  *n_launches receives the number of launches; at most cap are
+ * written.  EINVAL: NULL arguments, dir not 0 or 1, or a mesh without the
+ * dissection order. */
+int sbfwi_direct_launches(sbfwi_mesh m, int dir, int64_t* host_out, int cap, int* n_launches);
+
 /* Coarse-solve statistics accumulated on these factors (synchronous):
  * host_out[0] = solves, [1] = total Krylov iterations, [2] = largest iteration count.
  * reset != 0 clears them afterwards. */

@@ -150,6 +150,16 @@ def sbfwi_direct_info(m: MeshHandle) -> dict:
     return {k: int(v) for k, v in zip(keys, out)}
 
 
+def sbfwi_direct_launches(m: MeshHandle, direction: int) -> list:
+    """Launches of the direct solve's forward (0) or backward (1) program, in order."""
+    cap = 256
+    out = np.zeros(8 * cap, dtype=np.int64)
+    n = C.c_int(0)
+    check(lib().sbfwi_direct_launches(m, int(direction), out.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
+    keys = ["blocks", "lanes", "slots", "steps", "rows", "slot_records", "max_step_rows", "subtrees"]
+    return [dict(zip(keys, (int(v) for v in out[8 * k:8 * k + 8]))) for k in range(min(n.value, cap))]
+
+
 def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
     """Times the sweep launch shapes for runs of n_shots shots and keeps the fastest plan."""
     out = np.zeros(24, dtype=np.float64)

@@ -34,6 +34,7 @@ SIGNATURES = {
     "sbfwi_autotune": (i32, [vp, i32, vp, vp]),
     "sbfwi_plan_bytes": (i32, [vp, i32, i64, i32, vp]),
     "sbfwi_direct_info": (i32, [vp, vp]),
+    "sbfwi_direct_launches": (i32, [vp, i32, vp, i32, vp]),
     "sbfwi_copy_factor_data": (i32, [vp, i32, vp]),
     "sbfwi_coarse_pattern": (i32, [vp, vp, vp]),
     "sbfwi_forward": (i32, [vp, i32, i64, vp, vp, i32, vp, vp, i32, C.POINTER(vp), vp]),

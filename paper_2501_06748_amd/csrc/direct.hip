@@ -139,8 +139,8 @@ struct Dissect {
 // the children's update entries of the row, to the update vector (kind 1);
 // backward to x by position and by node.  A thread's first row record, its
 // first chunk of values and its pass-through entries are loaded before the
-// vector is assembled, so that their latency overlaps.  Shots s0 .. s0 + NSM - 1
-// of NS are handled.  A block barrier separates the steps, whose later ones
+// vector is assembled, and each later pass's while the previous one
+// computes.  Shots s0 .. s0 + NSM - 1 of NS are handled.  A block barrier separates the steps, whose later ones
 // read what earlier ones wrote.
 template <int NSM, bool FWD>
 __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk0, int64_t st0, int G,
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
                                                          double* __restrict__ out, int* __restrict__ status,
                                                          int count) {
   extern __shared__ double vec[];   // [slot][NSM]
-  constexpr int U = 4;
+  constexpr int U = 8;   // values per lane in flight: a whole row when it has at most 8 G entries
   if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
   const int ns = min(NSM, NS - s0);
   const int lane = threadIdx.x % G;
@@ -164,30 +164,30 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
   bool bad = false;
   for (int64_t st = sa; st < sb; ++st) {
     const DStep S = p.steps[st];
-    DRRec rr{};
-    double a[U], pass[NSM];
-    auto load_row = [&](int64_t r) {
-      rr = r < S.r1 ? p.rrec[r] : DRRec{};
-      const double* v = vals + rr.val;
+    DRRec rr{}, nrr{};
+    double a[U], pass[NSM], na[U], npass[NSM];
+    auto load_row = [&](int64_t r, DRRec& w, double (&x)[U], double (&ps)[NSM]) {
+      w = r < S.r1 ? p.rrec[r] : DRRec{};
+      const double* v = vals + w.val;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = lane + u * G;
-        a[u] = k < rr.len ? v[k] : 0.0;
+        x[u] = k < w.len ? v[k] : 0.0;
       }
 #pragma unroll
-      for (int s = 0; s < NSM; ++s) pass[s] = 0.0;
+      for (int s = 0; s < NSM; ++s) ps[s] = 0.0;
       if (FWD && lane == 0) {
-        if (rr.ngl > 0)
+        if (w.ngl > 0)
 #pragma unroll
           for (int s = 0; s < NSM; ++s)
-            if (s < ns) pass[s] += upd[rr.g0 * NS + s0 + s];
-        if (rr.ngl > 1)
+            if (s < ns) ps[s] += upd[w.g0 * NS + s0 + s];
+        if (w.ngl > 1)
 #pragma unroll
           for (int s = 0; s < NSM; ++s)
-            if (s < ns) pass[s] += upd[rr.g1 * NS + s0 + s];
+            if (s < ns) ps[s] += upd[w.g1 * NS + s0 + s];
       }
     };
-    load_row(S.r0 + threadIdx.x / G);
+    load_row(S.r0 + threadIdx.x / G, rr, a, pass);
     for (int64_t q = S.v0 + threadIdx.x; q < S.v1; q += DT) {
       const DVRec v = p.vrec[q];
       double acc[NSM];
@@ -211,7 +211,8 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
     for (int64_t base = S.r0; base < S.r1; base += DT / G) {
       const int64_t r = base + threadIdx.x / G;
       const bool valid = r < S.r1;
-      if (base != S.r0) load_row(r);
+      // the next pass's row is loaded while this one is computed
+      if (base + DT / G < S.r1) load_row(r + DT / G, nrr, na, npass);
       double acc[NSM];
 #pragma unroll
       for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
@@ -269,6 +270,11 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
 #pragma unroll
         for (int s = 0; s < NSM; ++s) bad = bad || (s < ns && !isfinite(acc[s]));
       }
+      rr = nrr;
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] = na[u];
+#pragma unroll
+      for (int s = 0; s < NSM; ++s) pass[s] = npass[s];
     }
     __syncthreads();   // the next step reads this one's results and reuses the LDS vectors
   }
@@ -544,7 +550,17 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   for (int l = 0; l <= top; ++l) level_launch(1, l);
   if (ds->n_sub > 0) subtree_launch(1);
   for (int t = 0; t < 2; ++t)
-    for (const DLaunch& L : ds->launches[t]) ds->max_slots = std::max(ds->max_slots, L.slots);
+    for (DLaunch& L : ds->launches[t]) {
+      ds->max_slots = std::max(ds->max_slots, L.slots);
+      for (int64_t b = L.blk0; b < L.blk0 + L.nblk; ++b)
+        for (int64_t q = P[t].blk[b]; q < P[t].blk[b + 1]; ++q) {
+          const DStep& S = P[t].st[q];
+          L.steps++;
+          L.rows += S.r1 - S.r0;
+          L.vrecs += S.v1 - S.v0;
+          L.max_step_rows = std::max(L.max_step_rows, S.r1 - S.r0);
+        }
+    }
   // every record stays inside the arrays and LDS vectors it addresses
   const int64_t n_upd = ds->b_ptr[nS];
   for (int t = 0; t < 2; ++t) {
@@ -866,6 +882,21 @@ int sbfwi_direct_solve(sbfwi_factors_s* f, CoarseWork* w, int transpose, const d
     run_prog(1, ds, nsm, dn->BM[t], NS, s0, w->dyb, w->dxp, x, f->d.status, last, s);
   }
   SBFWI_HIP(hipGetLastError());
+  return SBFWI_OK;
+}
+
+extern "C" int sbfwi_direct_launches(sbfwi_mesh m, int dir, int64_t* out, int cap, int* n_launches) {
+  if (!m || !out || !n_launches) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  if (dir != 0 && dir != 1) return sbfwi_fail(SBFWI_EINVAL, "dir must be 0 (forward) or 1 (backward)");
+  const DirectSym* ds = m->dsym;
+  if (!ds) return sbfwi_fail(SBFWI_EINVAL, "mesh has no dissection order");
+  const auto& Ls = ds->launches[dir];
+  *n_launches = (int)Ls.size();
+  for (int k = 0; k < (int)Ls.size() && k < cap; ++k) {
+    const DLaunch& L = Ls[k];
+    const int64_t v[8] = {L.nblk, L.G, L.slots, L.steps, L.rows, L.vrecs, L.max_step_rows, L.st0 >= 0 ? 0 : 1};
+    for (int q = 0; q < 8; ++q) out[8 * k + q] = v[q];
+  }
   return SBFWI_OK;
 }
 

@@ -90,6 +90,7 @@ struct DLaunch {
   int64_t blk0 = 0, nblk = 0;   // blocks of the launch in the program's block list
   int64_t st0 = -1;             // >= 0: block b of the launch runs the single step st0 + b
   int G = 1, slots = 0;         // lanes per row, LDS slots per block
+  int64_t steps = 0, rows = 0, vrecs = 0, max_step_rows = 0;   // totals (introspection)
 };
 // Nested-dissection structure of the coarse system and the solve programs.
 struct DirectSym {
