@@ -755,8 +755,15 @@ int sbfwi_misfit_residual(const double* traces, const double* observed, int64_t 
   return SBFWI_OK;
 }
 
+// The backward pass.  Checkpoint segments are recomputed (forward steps that
+// store the unknowns with ghosts and the level field of every step) and then
+// stepped back by the adjoint.  With a recompute stream sr, the recompute of
+// segment s - 1 runs on sr into the other of two segment stores while the
+// adjoint steps of segment s run on st (events ev[0..1]: segment in store b
+// recomputed; ev[2..3]: the adjoint is done with store b).
 static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_src, int mode, double* grad,
-                       hipStream_t st, AdjWork& w, StepWork& fw, StepWork& bw, double* xseg, double* fseg) {
+                       hipStream_t st, AdjWork& w, StepWork& fw, StepWork& bw, double* const xseg[2],
+                       double* const fseg[2], hipStream_t sr, const hipEvent_t* ev) {
   sbfwi_mesh_s* m = f->m;
   const int NS = ck->n_shots;
   const int64_t N = ck->n_steps, C = ck->interval;
@@ -809,20 +816,41 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   const int64_t nseg = (N + C - 1) / C;
   const unsigned gp = (unsigned)((m->n_params + 255) / 256);
   const unsigned gn = (unsigned)((nn + 255) / 256);
+  auto recompute = [&](int64_t seg, int b, hipStream_t s) -> int {
+    const int64_t k0 = seg * C, k1 = std::min(k0 + C, N);
+    SBFWI_CHECK(sbfwi_state_copy(m, &fw, ck->states + seg * sbfwi_state_size(m, NS), 0, s));
+    for (int64_t k = k0 + 1; k <= k1; ++k) {
+      double* xs = xseg[b] + (k - k0 - 1) * m->n_x * NS;
+      double* fs = fseg[b] + (k - k0 - 1) * m->n_params * NS;
+      SBFWI_CHECK(sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, s));
+    }
+    return SBFWI_OK;
+  };
+  const bool ov = sr != nullptr && !ck->full_store;
+  if (ov) {   // the recompute stream starts after everything enqueued on st so far
+    SBFWI_HIP(hipEventRecord(ev[4], st));
+    SBFWI_HIP(hipStreamWaitEvent(sr, ev[4], 0));
+    SBFWI_CHECK(recompute(nseg - 1, (int)((nseg - 1) % 2), sr));
+    SBFWI_HIP(hipEventRecord(ev[(nseg - 1) % 2], sr));
+  }
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t k0 = seg * C, k1 = std::min(k0 + C, N);
-    if (!ck->full_store) {
-      SBFWI_CHECK(sbfwi_state_copy(m, &fw, ck->states + seg * sbfwi_state_size(m, NS), 0, st));
-      for (int64_t k = k0 + 1; k <= k1; ++k) {
-        double* xs = xseg + (k - k0 - 1) * m->n_x * NS;
-        double* fs = fseg + (k - k0 - 1) * m->n_params * NS;
-        SBFWI_CHECK(sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, st));
+    const int b = ov ? (int)(seg % 2) : 0;
+    if (ov) {
+      if (seg >= 1) {   // segment seg - 1 into the other store, once the adjoint of seg + 1 is done with it
+        const int nb = (int)((seg - 1) % 2);
+        if (seg + 1 <= nseg - 1) SBFWI_HIP(hipStreamWaitEvent(sr, ev[2 + nb], 0));
+        SBFWI_CHECK(recompute(seg - 1, nb, sr));
+        SBFWI_HIP(hipEventRecord(ev[nb], sr));
       }
+      SBFWI_HIP(hipStreamWaitEvent(st, ev[b], 0));
+    } else if (!ck->full_store) {
+      SBFWI_CHECK(recompute(seg, 0, st));
     }
     for (int64_t k = k1; k > k0; --k) {
-      const double* X = ck->full_store ? ck->xstore + (k - 1) * m->n_x * NS : xseg + (k - k0 - 1) * m->n_x * NS;
+      const double* X = ck->full_store ? ck->xstore + (k - 1) * m->n_x * NS : xseg[b] + (k - k0 - 1) * m->n_x * NS;
       const double* Fs = ck->full_store ? (kind == 0 ? ck->fstore : ck->vstore) + (k - 1) * m->n_params * NS
-                                        : fseg + (k - k0 - 1) * m->n_params * NS;
+                                        : fseg[b] + (k - k0 - 1) * m->n_params * NS;
       if (mode == SBFWI_GRAD_EXACT) {
         launch_adj_sweep(true, f, a, st);
         {
@@ -848,6 +876,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         SBFWI_HIP(hipGetLastError());
       }
     }
+    if (ov) SBFWI_HIP(hipEventRecord(ev[2 + b], st));
   }
   return SBFWI_OK;
 }
@@ -858,20 +887,34 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   const int NS = ck->n_shots;
   AdjWork w;
   StepWork fw, bw;
-  double* xseg = nullptr;
-  double* fseg = nullptr;
+  double* xseg[2] = {nullptr, nullptr};
+  double* fseg[2] = {nullptr, nullptr};
+  hipStream_t sr = nullptr;
+  hipEvent_t ev[5] = {};
   int rc = SBFWI_OK;
   if (!ck->full_store) {
     rc = sbfwi_step_work_alloc(&fw, m, NS);
-    if (rc == SBFWI_OK) rc = sbfwi_alloc(&xseg, ck->interval * m->n_x * NS);
-    if (rc == SBFWI_OK) rc = sbfwi_alloc(&fseg, ck->interval * m->n_params * NS);
+    if (rc == SBFWI_OK) rc = sbfwi_alloc(&xseg[0], ck->interval * m->n_x * NS);
+    if (rc == SBFWI_OK) rc = sbfwi_alloc(&fseg[0], ck->interval * m->n_params * NS);
+    // overlap of recompute and adjoint (direct coarse solver only: no cooperative launches);
+    // skipped if the second segment store does not fit
+    if (rc == SBFWI_OK && f->overlap_adjoint && f->dnum && ck->interval < ck->n_steps) {
+      if (sbfwi_alloc(&xseg[1], ck->interval * m->n_x * NS) == SBFWI_OK &&
+          sbfwi_alloc(&fseg[1], ck->interval * m->n_params * NS) == SBFWI_OK) {
+        bool ok = hipStreamCreateWithFlags(&sr, hipStreamNonBlocking) == hipSuccess;
+        for (int q = 0; q < 5 && ok; ++q) ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
+        if (!ok) rc = sbfwi_fail(SBFWI_EHIP, "adjoint: cannot create the recompute stream");
+      } else {
+        (void)hipGetLastError();   // the second store did not fit: one segment after the other
+      }
+    }
   }
   if (rc == SBFWI_OK) {
     int flags0[4] = {0, -1, 0, 0};
     hipError_t he = hipMemcpyAsync(f->d.status, flags0, 2 * sizeof(int), hipMemcpyHostToDevice, st);
     if (he != hipSuccess) rc = sbfwi_fail(SBFWI_EHIP, "status reset: %s", hipGetErrorString(he));
   }
-  if (rc == SBFWI_OK) rc = adjoint_run(f, ck, adj_src, mode, grad, st, w, fw, bw, xseg, fseg);
+  if (rc == SBFWI_OK) rc = adjoint_run(f, ck, adj_src, mode, grad, st, w, fw, bw, xseg, fseg, sr, ev);
   int flags[4] = {0, -1, 0, 0};
   if (rc == SBFWI_OK) {
     hipError_t he = hipMemcpyAsync(flags, f->d.status, sizeof(flags), hipMemcpyDeviceToHost, st);
@@ -880,11 +923,17 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   } else {
     (void)hipStreamSynchronize(st);
   }
+  if (sr) (void)hipStreamSynchronize(sr);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (sr) (void)hipStreamDestroy(sr);
   adj_free(&w);
   if (!ck->full_store) sbfwi_step_work_free(&fw);
   if (bw.u) sbfwi_step_work_free(&bw);
-  sbfwi_dev_free(xseg);
-  sbfwi_dev_free(fseg);
+  for (int b = 0; b < 2; ++b) {
+    sbfwi_dev_free(xseg[b]);
+    sbfwi_dev_free(fseg[b]);
+  }
   if (rc != SBFWI_OK) return rc;
   if (flags[0] & 8) return sbfwi_fail(SBFWI_EHIP, "adjoint: coarse-solve grid barrier timed out");
   if (flags[0] & 4) return sbfwi_fail(SBFWI_ENONFINITE, "non-finite coarse residual at step %d", flags[1]);

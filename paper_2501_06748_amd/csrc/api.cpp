@@ -160,6 +160,11 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
     f->plan = SweepPlan();
     return SBFWI_OK;
   }
+  if (param == 3) {
+    if (value != 0 && value != 1) return sbfwi_fail(SBFWI_EINVAL, "overlap flag must be 0 or 1");
+    f->overlap_adjoint = value;
+    return SBFWI_OK;
+  }
   if (param >= 10 && param < 10 + 3 * SW_N) {
     if (!valid_shots_per_block(value)) return sbfwi_fail(SBFWI_EINVAL, "shots per block must be 0, 1, 2, 4, 8 or 16");
     f->plan.S[(param - 10) / 3][(param - 10) % 3] = value;
@@ -199,7 +204,9 @@ extern "C" int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int 
   if (n_ckpt != 0) {
     bwd = 8 * NS * (3 * m->n_int + 3 * m->n_nodes + m->n_int + 2 * m->n_loop + 2 * m->n_nodes + m->n_x) +
           coarse + 4 * m->n_params;
-    if (n_ckpt < n_steps) bwd += fwd_work + 8 * interval * NS * (m->n_x + m->n_params);
+    // the segment recompute: its work buffers and two segment stores (the second one
+    // when the recompute of the next segment overlaps the adjoint of the current one)
+    if (n_ckpt < n_steps) bwd += fwd_work + 2 * 8 * interval * NS * (m->n_x + m->n_params);
     bwd += 8 * NS * n_steps * 64;   // residual of sbfwi_gradient, receivers bounded by 64 per shot
   }
   out[0] = factors;

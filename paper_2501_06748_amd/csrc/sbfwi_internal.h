@@ -171,6 +171,7 @@ struct sbfwi_factors_s {
   int max_iter = 500;
   int enqueued_iters = 13;       // BiCGStab iterations enqueued per solve (more run in a rescue kernel)
   int use_graphs = 0;            // forward runs replay each time step from HIP graphs
+  int overlap_adjoint = 1;       // recompute the next checkpoint segment while the adjoint runs the current one
   SweepPlan plan;
   DirectNum* dnum = nullptr;     // direct factors of K_g (coarse solver 1), else BiCGStab
   int64_t bytes = 0;
