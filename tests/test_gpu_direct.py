@@ -66,3 +66,22 @@ def test_direct_full_size_matches_iterative(shots):
     err = rel_l2(td, ti)
     log(f"full size, {shots} shots: direct vs BiCGStab nodal wavefield relative L2 = {err:.3e}")
     assert err <= 1e-11
+
+
+@pytest.mark.parametrize("n_ckpt", [-1, 3])
+def test_overlapped_recompute_is_bit_identical(n_ckpt):
+    """The backward pass with the segment recompute overlapped on a second stream
+    (default) gives the same bits as one segment after the other, and the oracle's
+    gradient; several segments, odd and even counts."""
+    wl = W.config_small(nx=4, ny=2, segs=2, n_r=7, n_steps=40, n_shots=3)
+    rho = wl.models["random30"]
+    obs = ostp.forward(_om(wl, rho * 0.95), wl.src_nodes, wl.wavelets, wl.rec_nodes, 40)
+    g = GpuModel(wl, rho, coarse_solver=1)
+    _, mis1, grad1, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt)
+    g.sb.sbfwi_set_launch(g.f, 3, 0)
+    _, mis0, grad0, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt)
+    gref, Jref = oadj.exact_gradient(_om(wl, rho), wl.src_nodes, wl.wavelets, wl.rec_nodes, obs, 40)
+    err = rel_l2(grad1, gref)
+    log(f"overlapped recompute (n_ckpt {n_ckpt}): bit-identical {np.array_equal(grad1, grad0)}, vs oracle {err:.3e}")
+    assert np.array_equal(grad1, grad0) and mis1 == mis0
+    assert err <= 1e-8
