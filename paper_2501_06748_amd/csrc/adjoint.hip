@@ -760,10 +760,14 @@ int sbfwi_misfit_residual(const double* traces, const double* observed, int64_t 
 // stepped back by the adjoint.  With a recompute stream sr, the recompute of
 // segment s - 1 runs on sr into the other of two segment stores while the
 // adjoint steps of segment s run on st (events ev[0..1]: segment in store b
-// recomputed; ev[2..3]: the adjoint is done with store b).
+// recomputed; ev[2..3]: the adjoint and its gradient contractions are done
+// with store b).  With a gradient stream sg (exact mode), the contraction of
+// step k runs on sg while the adjoint computes step k - 1; the adjoint rows
+// alternate between two buffers lam[0..1] (events ev[5..6]: rows of buffer q
+// written; ev[7..8]: the contraction is done reading them).
 static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_src, int mode, double* grad,
                        hipStream_t st, AdjWork& w, StepWork& fw, StepWork& bw, double* const xseg[2],
-                       double* const fseg[2], hipStream_t sr, const hipEvent_t* ev) {
+                       double* const fseg[2], hipStream_t sr, hipStream_t sg, const hipEvent_t* ev) {
   sbfwi_mesh_s* m = f->m;
   const int NS = ck->n_shots;
   const int64_t N = ck->n_steps, C = ck->interval;
@@ -797,7 +801,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     SBFWI_CHECK(sbfwi_alloc(&w.pl, m->n_loop * NS));
     SBFWI_CHECK(sbfwi_alloc(&w.rhs, nn));
     SBFWI_CHECK(sbfwi_alloc(&w.lamB, nn));
-    SBFWI_CHECK(sbfwi_alloc(&w.lam, m->n_x * NS));
+    SBFWI_CHECK(sbfwi_alloc(&w.lam, (sg ? 2 : 1) * m->n_x * NS));
     SBFWI_HIP(hipMemsetAsync(w.lamB, 0, sizeof(double) * nn, st));
     SBFWI_CHECK(sbfwi_coarse_work_alloc(&w.cw, m, NS));
     a.z = w.z; a.gB = w.gB; a.pl = w.pl; a.lamB = w.lamB; a.lam = w.lam;
@@ -827,9 +831,14 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     return SBFWI_OK;
   };
   const bool ov = sr != nullptr && !ck->full_store;
-  if (ov) {   // the recompute stream starts after everything enqueued on st so far
+  const bool gs = sg != nullptr && mode == SBFWI_GRAD_EXACT;
+  int64_t n_grad = 0;   // contractions launched on sg
+  if (ov || gs) {   // the side streams start after everything enqueued on st so far
     SBFWI_HIP(hipEventRecord(ev[4], st));
-    SBFWI_HIP(hipStreamWaitEvent(sr, ev[4], 0));
+    if (ov) SBFWI_HIP(hipStreamWaitEvent(sr, ev[4], 0));
+    if (gs) SBFWI_HIP(hipStreamWaitEvent(sg, ev[4], 0));
+  }
+  if (ov) {
     SBFWI_CHECK(recompute(nseg - 1, (int)((nseg - 1) % 2), sr));
     SBFWI_HIP(hipEventRecord(ev[(nseg - 1) % 2], sr));
   }
@@ -852,6 +861,11 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
       const double* Fs = ck->full_store ? (kind == 0 ? ck->fstore : ck->vstore) + (k - 1) * m->n_params * NS
                                         : fseg[b] + (k - k0 - 1) * m->n_params * NS;
       if (mode == SBFWI_GRAD_EXACT) {
+        const int q = (int)(k % 2);
+        if (gs) {   // rows buffer q: the contraction of step k + 2 must be done reading it
+          if (n_grad >= 2) SBFWI_HIP(hipStreamWaitEvent(st, ev[7 + q], 0));
+          a.lam = w.lam + (int64_t)q * m->n_x * NS;
+        }
         launch_adj_sweep(true, f, a, st);
         {
         ProfScope ps(PK_ADJ_RHS, st);
@@ -865,7 +879,15 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
           ProfScope ps(PK_ADJ_NODAL, st);
           hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
         }
-        launch_grad(m, f->d, NS, X, (const double*)w.lam, Fs, grad, per_shot ? m->n_params : 0, st);
+        if (gs) {
+          SBFWI_HIP(hipEventRecord(ev[5 + q], st));
+          SBFWI_HIP(hipStreamWaitEvent(sg, ev[5 + q], 0));
+          launch_grad(m, f->d, NS, X, (const double*)a.lam, Fs, grad, per_shot ? m->n_params : 0, sg);
+          SBFWI_HIP(hipEventRecord(ev[7 + q], sg));
+          ++n_grad;
+        } else {
+          launch_grad(m, f->d, NS, X, (const double*)w.lam, Fs, grad, per_shot ? m->n_params : 0, st);
+        }
         SBFWI_HIP(hipGetLastError());
       } else {
         const int64_t kp = N + 1 - k;  // back-propagation step paired with forward step k
@@ -876,6 +898,8 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         SBFWI_HIP(hipGetLastError());
       }
     }
+    // the segment's contractions read its store too: st waits for the last one
+    if (gs && n_grad > 0) SBFWI_HIP(hipStreamWaitEvent(st, ev[7 + (int)((k0 + 1) % 2)], 0));
     if (ov) SBFWI_HIP(hipEventRecord(ev[2 + b], st));
   }
   return SBFWI_OK;
@@ -889,8 +913,8 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   StepWork fw, bw;
   double* xseg[2] = {nullptr, nullptr};
   double* fseg[2] = {nullptr, nullptr};
-  hipStream_t sr = nullptr;
-  hipEvent_t ev[5] = {};
+  hipStream_t sr = nullptr, sg = nullptr;
+  hipEvent_t ev[9] = {};
   int rc = SBFWI_OK;
   if (!ck->full_store) {
     rc = sbfwi_step_work_alloc(&fw, m, NS);
@@ -901,9 +925,10 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     if (rc == SBFWI_OK && f->overlap_adjoint && f->dnum && ck->interval < ck->n_steps) {
       if (sbfwi_alloc(&xseg[1], ck->interval * m->n_x * NS) == SBFWI_OK &&
           sbfwi_alloc(&fseg[1], ck->interval * m->n_params * NS) == SBFWI_OK) {
-        bool ok = hipStreamCreateWithFlags(&sr, hipStreamNonBlocking) == hipSuccess;
-        for (int q = 0; q < 5 && ok; ++q) ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
-        if (!ok) rc = sbfwi_fail(SBFWI_EHIP, "adjoint: cannot create the recompute stream");
+        bool ok = hipStreamCreateWithFlags(&sr, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&sg, hipStreamNonBlocking) == hipSuccess;
+        for (int q = 0; q < 9 && ok; ++q) ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
+        if (!ok) rc = sbfwi_fail(SBFWI_EHIP, "adjoint: cannot create the side streams");
       } else {
         (void)hipGetLastError();   // the second store did not fit: one segment after the other
       }
@@ -914,7 +939,7 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     hipError_t he = hipMemcpyAsync(f->d.status, flags0, 2 * sizeof(int), hipMemcpyHostToDevice, st);
     if (he != hipSuccess) rc = sbfwi_fail(SBFWI_EHIP, "status reset: %s", hipGetErrorString(he));
   }
-  if (rc == SBFWI_OK) rc = adjoint_run(f, ck, adj_src, mode, grad, st, w, fw, bw, xseg, fseg, sr, ev);
+  if (rc == SBFWI_OK) rc = adjoint_run(f, ck, adj_src, mode, grad, st, w, fw, bw, xseg, fseg, sr, sg, ev);
   int flags[4] = {0, -1, 0, 0};
   if (rc == SBFWI_OK) {
     hipError_t he = hipMemcpyAsync(flags, f->d.status, sizeof(flags), hipMemcpyDeviceToHost, st);
@@ -924,9 +949,11 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     (void)hipStreamSynchronize(st);
   }
   if (sr) (void)hipStreamSynchronize(sr);
+  if (sg) (void)hipStreamSynchronize(sg);
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
   if (sr) (void)hipStreamDestroy(sr);
+  if (sg) (void)hipStreamDestroy(sg);
   adj_free(&w);
   if (!ck->full_store) sbfwi_step_work_free(&fw);
   if (bw.u) sbfwi_step_work_free(&bw);
