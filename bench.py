@@ -50,10 +50,11 @@ def kernel_bytes(mesh, NS, nnz):
         # reads phi~^-1 (n blocks), G, bands P (n+1), theta (n+1); state u,v,a (n levels) and the
         # nodal state on the loop; writes q (n levels), y_n and f_hat on the loop
         "condense": blk + band(n + 1) + band(n + 2) + NS * (3 * n * nb + 3 * nb + n * nb + 2 * nb),
-        # reads phi~^-1, psi~_0, bands psi (n-1); q, u, v, a, u_n; writes u, v, a (a launch of the
-        # forward run; the checkpoint recompute also stores the unknowns with ghosts and the
-        # accelerations for the adjoint)
-        "recover": blk + band(n - 1) + NS * (n * nb + 3 * n * nb + nb + 3 * n * nb),
+        # reads phi~^-1, psi~_0, bands psi (n-1); q, u, v, a, u_n; writes u, v, a; in the
+        # checkpoint recompute (half of the launches of a gradient evaluation) it also stores the
+        # unknowns with ghosts (n+3 levels) and the accelerations (n+1 levels) for the adjoint
+        "recover": blk + band(n - 1) + NS * (n * nb + 3 * n * nb + nb + 3 * n * nb)
+                   + NS * ((n + 3) + (n + 1)) * nb // 2,
         # reads phi~^-1, psi~_0, bands psi; seeds (3 n); writes z (n) and the coupling (1)
         "adj_condense": blk + band(n - 1) + NS * (3 * n * nb + n * nb + nb),
         # reads G, phi~^-1, theta (n+2), P (n+1), theta_-1^-1; lambda_B, z, seeds (2 n);
@@ -224,13 +225,9 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] observed data simulated ({wl.name}, {S} shots, {N} steps)", file=sys.stderr, flush=True)
 
-    def step(prof_fwd=None, prof_bwd=None):
+    def step():
         f = factor(rho0)
-        if prof_fwd is not None:
-            sb.sbfwi_profile(prof_fwd)
         ck = sb.sbfwi_forward(f, src, wav, rec, traces, n_ckpt=-1)
-        if prof_bwd is not None:
-            sb.sbfwi_profile(prof_bwd)
         sb.sbfwi_gradient(f, ck, observed, traces, sb.GRAD_EXACT, misfit, grad)
         stats = sb.sbfwi_solver_stats(f)
         ck.close()
@@ -252,17 +249,14 @@ def main():
     # launch; rocprofv3 kernel statistics of this command rank them by kernel time).
     long_k = [k for k in warm if k != "factor" and warm[k]["ms"] / max(warm[k]["launches"], 1) > 0.05]
     dominant = max(long_k, key=lambda k: warm[k]["ms"]) if long_k else "recover"
-    # timed region: events around the dominant kernel only, in the phase that launches it
-    # alone on the device (the backward pass overlaps the segment recompute with the
-    # adjoint steps on two streams, so its launches share the device)
-    in_fwd = dominant in ("condense", "recover", "source_gather", "nodal_update")
-    prof_fwd, prof_bwd = ([dominant], 0) if in_fwd else (0, [dominant])
-    sb.sbfwi_profile(0)
+    # timed region: events around every launch of the dominant kernel only (in the backward
+    # pass its launches share the device with the overlapped adjoint steps, as in the run)
+    sb.sbfwi_profile([dominant])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
     for _ in range(args.steps):
-        stats = step(prof_fwd, prof_bwd)
+        stats = step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     live = sb.sbfwi_profile_read(reset=True)
@@ -283,8 +277,7 @@ def main():
         achieved = moved / max(d_ms / 1e3, 1e-12) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant, wl.name),
-                "kernel": dominant, "phase": "forward run" if in_fwd else "backward pass",
-                "avg_launch_us": avg_s * 1e6, "launches": d_launches,
+                "kernel": dominant, "avg_launch_us": avg_s * 1e6, "launches": d_launches,
                 "active_launches": active, "algorithmic_bytes_per_active_launch": kb[dominant]}
     else:
         roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,

@@ -50,6 +50,8 @@ namespace {
 constexpr int kLeaf = 24;     // nodes per leaf supernode
 constexpr int DT = 256;       // threads per block of the solve kernels
 constexpr int kSubtrees = 512;// subtrees solved one per block at the bottom of the tree
+constexpr int kLevelU = 8;    // row values per lane in flight, level launches
+constexpr int kSubtreeU = 16; // and subtree launches
 
 // ------------------------------------------------------------------ ordering
 
@@ -134,7 +136,9 @@ struct Dissect {
 // assemble vectors in LDS (forward: the right-hand side at the supernode's
 // nodes minus the children's update entries of the slot; backward: y at J's
 // positions, then x at B_J), then G lanes per row dot each dense row with its
-// supernode's vector (lane-strided, chunks of U values in flight, a fixed
+// supernode's vector (lane-strided, chunks of U values per lane in flight: a
+// whole row when it has at most U G entries; U = 8 for the level launches,
+// 16 for the subtree launches, whose steps hold many short rows; a fixed
 // butterfly to sum) and write it: forward to y by position (kind 0) or, plus
 // the children's update entries of the row, to the update vector (kind 1);
 // backward to x by position and by node.  A thread's first row record, its
@@ -142,14 +146,13 @@ struct Dissect {
 // vector is assembled, and each later pass's while the previous one
 // computes.  Shots s0 .. s0 + NSM - 1 of NS are handled.  A block barrier separates the steps, whose later ones
 // read what earlier ones wrote.
-template <int NSM, bool FWD>
+template <int NSM, bool FWD, int U>
 __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk0, int64_t st0, int G,
                                                          const double* __restrict__ vals, int NS, int s0,
                                                          const double* __restrict__ in, double* __restrict__ upd,
                                                          double* __restrict__ out, int* __restrict__ status,
                                                          int count) {
   extern __shared__ double vec[];   // [slot][NSM]
-  constexpr int U = 8;   // values per lane in flight: a whole row when it has at most 8 G entries
   if (count && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&status[5], 1);   // solves done
   const int ns = min(NSM, NS - s0);
   const int lane = threadIdx.x % G;
@@ -211,8 +214,13 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
     for (int64_t base = S.r0; base < S.r1; base += DT / G) {
       const int64_t r = base + threadIdx.x / G;
       const bool valid = r < S.r1;
-      // the next pass's row is loaded while this one is computed
-      if (base + DT / G < S.r1) load_row(r + DT / G, nrr, na, npass);
+      // the next pass's row is loaded while this one is computed (short chunks only: the
+      // subtree launches' wide chunks would not leave room for a second set of registers)
+      if constexpr (U <= 8) {
+        if (base + DT / G < S.r1) load_row(r + DT / G, nrr, na, npass);
+      } else {
+        if (base != S.r0) load_row(r, rr, a, pass);
+      }
       double acc[NSM];
 #pragma unroll
       for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
@@ -270,11 +278,13 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
 #pragma unroll
         for (int s = 0; s < NSM; ++s) bad = bad || (s < ns && !isfinite(acc[s]));
       }
-      rr = nrr;
+      if constexpr (U <= 8) {
+        rr = nrr;
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[u] = na[u];
+        for (int u = 0; u < U; ++u) a[u] = na[u];
 #pragma unroll
-      for (int s = 0; s < NSM; ++s) pass[s] = npass[s];
+        for (int s = 0; s < NSM; ++s) pass[s] = npass[s];
+      }
     }
     __syncthreads();   // the next step reads this one's results and reuses the LDS vectors
   }
@@ -415,9 +425,9 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
     std::vector<DStep> st;
     std::vector<int64_t> blk{0};
   } P[2];
-  auto lanes = [](int64_t len) {   // about 8 entries per lane, at most a wavefront per row
+  auto lanes = [](int64_t len, int per_lane) {   // per_lane entries per lane, at most a wavefront per row
     int g = 1;
-    while (g < 64 && g * 8 < len) g *= 2;
+    while (g < 64 && g * per_lane < len) g *= 2;
     return g;
   };
   auto nrows = [&](int t, int J) {
@@ -487,7 +497,7 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
     L.blk0 = (int64_t)P[t].blk.size() - 1;
     int64_t len = 1;
     for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) len = std::max(len, row_len(t, ds->lvl_sn[q]));
-    L.G = lanes(len);
+    L.G = lanes(len, kLevelU);
     L.st0 = (int64_t)P[t].st.size();
     const int64_t per = DT / L.G;   // one pass of rows per block
     for (int q = ds->lvl_ptr[l]; q < ds->lvl_ptr[l + 1]; ++q) {
@@ -541,7 +551,7 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
       }
       P[t].blk.push_back((int64_t)P[t].st.size());
     }
-    L.G = lanes(len);
+    L.G = lanes(len, kSubtreeU);
     L.nblk = ds->n_sub;
     ds->launches[t].push_back(L);
   };
@@ -832,12 +842,19 @@ template <int NSM>
 void launch_prog(int t, const DirectSym* ds, const DLaunch& L, const double* vals, int NS, int s0,
                  const double* in, double* upd, double* out, int* status, int count, hipStream_t s) {
   const size_t lds = (size_t)L.slots * NSM * sizeof(double);
-  if (t == 0)
-    hipLaunchKernelGGL((direct_prog_kernel<NSM, true>), dim3((unsigned)L.nblk), dim3(DT), lds, s, ds->prog[0],
-                       L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
+  const bool sub = L.st0 < 0;
+  if (t == 0 && !sub)
+    hipLaunchKernelGGL((direct_prog_kernel<NSM, true, kLevelU>), dim3((unsigned)L.nblk), dim3(DT), lds, s,
+                       ds->prog[0], L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
+  else if (t == 0)
+    hipLaunchKernelGGL((direct_prog_kernel<NSM, true, kSubtreeU>), dim3((unsigned)L.nblk), dim3(DT), lds, s,
+                       ds->prog[0], L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
+  else if (!sub)
+    hipLaunchKernelGGL((direct_prog_kernel<NSM, false, kLevelU>), dim3((unsigned)L.nblk), dim3(DT), lds, s,
+                       ds->prog[1], L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
   else
-    hipLaunchKernelGGL((direct_prog_kernel<NSM, false>), dim3((unsigned)L.nblk), dim3(DT), lds, s, ds->prog[1],
-                       L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
+    hipLaunchKernelGGL((direct_prog_kernel<NSM, false, kSubtreeU>), dim3((unsigned)L.nblk), dim3(DT), lds, s,
+                       ds->prog[1], L.blk0, L.st0, L.G, vals, NS, s0, in, upd, out, status, count);
 }
 
 // Runs one direction's program for shots s0 .. s0 + nsm - 1 (nsm a power of two).
