@@ -278,7 +278,8 @@ int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
  * 8 adjoint nodal update, 9 exact-gradient contraction, 10 paper-kernel
  * correlation, 11 factorisation, 12 / 13 / 14 the three per-iteration kernels
  * of the coarse solve (v = K p, t = K s, the x / r / p update), 15 its two
- * start-up kernels).  A sweep over elements of several n_b classes counts as
+ * start-up kernels, 16 the recover sweep of the checkpoint recompute, which
+ * also stores the adjoint's inputs; id 1 counts the other recover sweeps).  A sweep over elements of several n_b classes counts as
  * one launch.  Recorded pairs are accumulated as they complete (the oldest
  * are waited for once many are in flight).  sbfwi_profile_read waits for the
  * rest and writes, for each of the 20 ids, host_out[2 id] = launches and

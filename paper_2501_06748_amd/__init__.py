@@ -119,7 +119,9 @@ def sbfwi_mesh_info(m: MeshHandle) -> dict:
 
 
 def sbfwi_factor_elements(m: MeshHandle, rho, c, dt, beta=0.25, gamma=0.5, scheme=SCHEME_PAPER_FD,
-                          coarse_solver=0, stream=None) -> FactorsHandle:
+                          coarse_solver=1, stream=None) -> FactorsHandle:
+    """Factors of one model: rho [n_params] f64 (device).  coarse_solver 1 (default): the
+    direct nested-dissection LU of K_g, factored here once; 0: BiCGStab every step."""
     import torch
     out = C.c_void_p()
     check(lib().sbfwi_factor_elements(m, _dptr(rho, torch.float64, "rho"), float(c), float(dt), float(beta),
@@ -264,7 +266,7 @@ def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:
 
 PROFILE_KERNELS = ["condense", "recover", "coarse_solve", "source_gather", "nodal_update", "adj_condense",
                    "adj_recover", "adj_gather", "adj_nodal_update", "grad_exact", "grad_paper", "factor",
-                   "solve_v", "solve_t", "solve_x", "solve_init"]
+                   "solve_v", "solve_t", "solve_x", "solve_init", "recover_store"]
 
 
 def sbfwi_profile(kernels):

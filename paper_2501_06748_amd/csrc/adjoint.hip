@@ -913,7 +913,7 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   StepWork fw, bw;
   double* xseg[2] = {nullptr, nullptr};
   double* fseg[2] = {nullptr, nullptr};
-  hipStream_t sr = nullptr, sg = nullptr;
+  hipStream_t sr = nullptr, sg = nullptr;   // recompute and contraction streams
   hipEvent_t ev[9] = {};
   int rc = SBFWI_OK;
   if (!ck->full_store) {

@@ -165,6 +165,7 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
     f->overlap_adjoint = value;
     return SBFWI_OK;
   }
+
   if (param >= 10 && param < 10 + 3 * SW_N) {
     if (!valid_shots_per_block(value)) return sbfwi_fail(SBFWI_EINVAL, "shots per block must be 0, 1, 2, 4, 8 or 16");
     f->plan.S[(param - 10) / 3][(param - 10) % 3] = value;

@@ -324,7 +324,9 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
   }
 }
 
-template <int NBT, int S>
+// STORE: the checkpoint recompute's launches, which also store the unknowns
+// with ghosts and the level field for the adjoint (a.xs, a.fs, a.vs).
+template <int NBT, int S, bool STORE>
 __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                              const StepArgs& a, StepLds<NBT, S>& L) {
   const int ns = min(S, a.NS - s0);
@@ -341,7 +343,7 @@ __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, co
     if (s < ns) un = a.Unew[m.loop_nodes[lo + i] * a.NS + s0 + s];
     L.x[it] = un;
     L.w[it] = un;  // keep u_n for the ghost
-    if (a.xs && s < ns) {
+    if (STORE && s < ns) {
       a.xs[(xo + (int64_t)(n + 1) * nb + i) * a.NS + s0 + s] = un;
       double fv = a.field_kind == 0 ? a.A[m.loop_nodes[lo + i] * a.NS + s0 + s]
                                     : a.V[m.loop_nodes[lo + i] * a.NS + s0 + s];
@@ -350,9 +352,8 @@ __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, co
     }
   }
   __syncthreads();
-  if (a.xs) recover_levels<NBT, S, true>(e, s0, m, f, a, L);
-  else recover_levels<NBT, S, false>(e, s0, m, f, a, L);
-  if (!a.xs) return;
+  recover_levels<NBT, S, STORE>(e, s0, m, f, a, L);
+  if (!STORE) return;
   // ghosts: u_{-1} = theta_{-1}^-1 (-(phi_{-1} u_0 + psi_{-1} u_1)),
   //         u_{n+1} = psi_n^-1 (y_n - phi~_n u_n)
   const int64_t dofs = m.dense_off[e];
@@ -400,18 +401,18 @@ __global__ void __launch_bounds__(WT) condense_kernel(const int32_t* __restrict_
   condense_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
 }
 
-template <int NBT, int S>
+template <int NBT, int S, bool STORE>
 __global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
                                                      FactorsDev f, StepArgs a) {
   __shared__ StepLds<NBT, S> L;
-  recover_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+  recover_body<NBT, S, STORE>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
 }
 
 // One persistent launch over all n_b classes: the blocks walk the work items
 // (element, group of S shots) in order of decreasing cost (N_r n_b^2), item
 // w = blockIdx.x + i gridDim.x; each item runs the body of its element's class
 // in a shared LDS buffer sized for the largest class.
-template <int S, bool CONDENSE>
+template <int S, bool CONDENSE, bool STORE>
 __global__ void __launch_bounds__(WT) sweep_fused_kernel(const int32_t* __restrict__ order, int64_t n_work,
                                                          int groups, MeshDev m, FactorsDev f, StepArgs a) {
   __shared__ StepLds<24, S> L;
@@ -421,12 +422,12 @@ __global__ void __launch_bounds__(WT) sweep_fused_kernel(const int32_t* __restri
     const int nb = m.nb[e];
     if (nb <= 8) {
       auto& Ls = *reinterpret_cast<StepLds<8, S>*>(&L);
-      if (CONDENSE) condense_body<8, S>(e, s0, m, f, a, Ls); else recover_body<8, S>(e, s0, m, f, a, Ls);
+      if (CONDENSE) condense_body<8, S>(e, s0, m, f, a, Ls); else recover_body<8, S, STORE>(e, s0, m, f, a, Ls);
     } else if (nb <= 16) {
       auto& Ls = *reinterpret_cast<StepLds<16, S>*>(&L);
-      if (CONDENSE) condense_body<16, S>(e, s0, m, f, a, Ls); else recover_body<16, S>(e, s0, m, f, a, Ls);
+      if (CONDENSE) condense_body<16, S>(e, s0, m, f, a, Ls); else recover_body<16, S, STORE>(e, s0, m, f, a, Ls);
     } else {
-      if (CONDENSE) condense_body<24, S>(e, s0, m, f, a, L); else recover_body<24, S>(e, s0, m, f, a, L);
+      if (CONDENSE) condense_body<24, S>(e, s0, m, f, a, L); else recover_body<24, S, STORE>(e, s0, m, f, a, L);
     }
     __syncthreads();
   }
@@ -489,8 +490,10 @@ void launch_cr(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, cons
   dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
   if (condense)
     hipLaunchKernelGGL((condense_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+  else if (a.xs)
+    hipLaunchKernelGGL((recover_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
   else
-    hipLaunchKernelGGL((recover_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((recover_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
 }
 
 template <int NBT>
@@ -509,12 +512,14 @@ template <int S>
 void launch_fused(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
   const int groups = (a.NS + S - 1) / S;
   const int64_t n_work = m->n_elem * groups;
-  auto kern = condense ? sweep_fused_kernel<S, true> : sweep_fused_kernel<S, false>;
-  static std::atomic<int> per_cu[2] = {0, 0};   // occupancy, queried once per kernel
-  int pc = per_cu[condense ? 0 : 1].load();
+  const int which = condense ? 0 : (a.xs ? 2 : 1);
+  auto kern = which == 0 ? sweep_fused_kernel<S, true, false>
+                         : which == 1 ? sweep_fused_kernel<S, false, false> : sweep_fused_kernel<S, false, true>;
+  static std::atomic<int> per_cu[3] = {0, 0, 0};   // occupancy, queried once per kernel
+  int pc = per_cu[which].load();
   if (pc == 0) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, WT, 0) != hipSuccess || pc <= 0) pc = 1;
-    per_cu[condense ? 0 : 1].store(pc);
+    per_cu[which].store(pc);
   }
   const int64_t cap = (int64_t)(pc > 0 ? pc : 1) * sbfwi_device_cus();
   const unsigned blocks = (unsigned)(n_work < cap ? n_work : cap);
@@ -544,7 +549,7 @@ void launch_step_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, cons
 }
 
 void launch_sweep(bool condense, sbfwi_factors_s* fac, const StepArgs& a, hipStream_t st) {
-  ProfScope ps(condense ? PK_CONDENSE : PK_RECOVER, st);
+  ProfScope ps(condense ? PK_CONDENSE : (a.xs ? PK_RECOVER_STORE : PK_RECOVER), st);
   launch_step_sweep(condense, fac->m, fac->d, fac->plan, a, st);
 }
 
