@@ -137,6 +137,10 @@ int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
  *             priority) while the adjoint steps of the current segment run, into a second
  *             segment store (default; skipped when that store cannot be allocated);
  *             0 = one segment after the other.
+ *   param 4:  1 = forward runs with checkpoints (not full storage) also keep every step's
+ *             coarse solution (n_nodes x shots x steps doubles, skipped when it does not fit)
+ *             and the checkpoint recompute then skips its coarse solves (default);
+ *             0 = the recompute solves again.
  *   param 10 + 3 k + c: shots per block (0 = default, 1, 2, 4, 8, 16) of sweep k (0 condense,
  *             1 recover, 2 transposed condense, 3 transposed recover) for n_b class c
  *             (n_b <= 8, <= 16, <= 24).
@@ -151,7 +155,8 @@ int sbfwi_set_launch(sbfwi_factors f, int param, int value);
  * store kept between sbfwi_forward and the end of sbfwi_adjoint, [2] the work
  * buffers of the forward run, [3] the work buffers of the backward pass (0 if
  * n_ckpt = 0; the residual of sbfwi_gradient counted with at most 64 receivers
- * per shot, and two checkpoint-segment stores, see sbfwi_set_launch param 3).  A forward + gradient run needs [1] + max([2], [3]) on top of the
+ * per shot, and two checkpoint-segment stores, see sbfwi_set_launch param 3);
+ * [1] includes the kept coarse solutions (param 4).  A forward + gradient run needs [1] + max([2], [3]) on top of the
  * factors.  For admission control by a caller that shares the device.
  */
 int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int n_ckpt, int64_t* host_out);

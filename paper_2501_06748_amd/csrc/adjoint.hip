@@ -826,7 +826,8 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     for (int64_t k = k0 + 1; k <= k1; ++k) {
       double* xs = xseg[b] + (k - k0 - 1) * m->n_x * NS;
       double* fs = fseg[b] + (k - k0 - 1) * m->n_params * NS;
-      SBFWI_CHECK(sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, s));
+      const double* us = ck->ustore ? ck->ustore + (k - 1) * m->n_nodes * NS : nullptr;
+      SBFWI_CHECK(sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, s, nullptr, us));
     }
     return SBFWI_OK;
   };

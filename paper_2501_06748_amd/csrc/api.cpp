@@ -165,6 +165,11 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
     f->overlap_adjoint = value;
     return SBFWI_OK;
   }
+  if (param == 4) {
+    if (value != 0 && value != 1) return sbfwi_fail(SBFWI_EINVAL, "solution store flag must be 0 or 1");
+    f->keep_solutions = value;
+    return SBFWI_OK;
+  }
 
   if (param >= 10 && param < 10 + 3 * SW_N) {
     if (!valid_shots_per_block(value)) return sbfwi_fail(SBFWI_EINVAL, "shots per block must be 0, 1, 2, 4, 8 or 16");
@@ -200,6 +205,7 @@ extern "C" int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int 
     int64_t cnt = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)n_steps));
     interval = (n_steps + cnt - 1) / cnt;
     ckpt += ((n_steps + interval - 1) / interval) * state;
+    ckpt += 8 * n_steps * m->n_nodes * NS;   // the coarse solutions kept for the recompute
   }
   int64_t bwd = 0;
   if (n_ckpt != 0) {
@@ -270,6 +276,7 @@ static void ckpt_free(sbfwi_ckpt_s* ck) {
   sbfwi_dev_free(ck->xstore);
   sbfwi_dev_free(ck->fstore);
   sbfwi_dev_free(ck->vstore);
+  sbfwi_dev_free(ck->ustore);
   delete ck;
 }
 
@@ -327,8 +334,16 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
       ck->n_saved = (n_steps + ck->interval - 1) / ck->interval;
       SBFWI_CHECK(sbfwi_alloc(&ck->states, ck->n_saved * ssz));
       ck->bytes = 8 * ck->n_saved * ssz;
+      // every step's coarse solution, for a recompute without coarse solves (skipped if it does not fit)
+      if (f->keep_solutions && n_steps > ck->interval) {
+        if (sbfwi_alloc(&ck->ustore, n_steps * m->n_nodes * n_shots) == SBFWI_OK)
+          ck->bytes += 8 * n_steps * m->n_nodes * n_shots;
+        else
+          (void)hipGetLastError();
+      }
     }
   }
+  w.ustore = ck ? ck->ustore : nullptr;
   SourceTable src;
   src.n_src = 1;
   src.node = src_node;

@@ -172,6 +172,7 @@ struct sbfwi_factors_s {
   int enqueued_iters = 13;       // BiCGStab iterations enqueued per solve (more run in a rescue kernel)
   int use_graphs = 0;            // forward runs replay each time step from HIP graphs
   int overlap_adjoint = 1;       // recompute the next checkpoint segment while the adjoint runs the current one
+  int keep_solutions = 1;        // forward runs with checkpoints keep every step's coarse solution
   SweepPlan plan;
   DirectNum* dnum = nullptr;     // direct factors of K_g (coarse solver 1), else BiCGStab
   int64_t bytes = 0;
@@ -191,6 +192,7 @@ struct sbfwi_ckpt_s {
   double* xstore = nullptr;      // full storage: [n_steps][n_x*NS]
   double* fstore = nullptr;      // full storage: [n_steps][n_params*NS] accelerations a^k
   double* vstore = nullptr;      // full storage: [n_steps][n_params*NS] velocities v^k
+  double* ustore = nullptr;      // optional: [n_steps][n_nodes*NS] coarse solutions (the recompute skips its solves)
 };
 
 // ---- live kernel timing (profiler.cpp) ----
@@ -285,6 +287,7 @@ struct StepWork {
   double *U = nullptr, *V = nullptr, *A = nullptr;      // nodal state
   double* corr = nullptr;                               // predictor correction of the coarse solve
   double *q = nullptr, *yn = nullptr, *fhat = nullptr, *F = nullptr, *Unew = nullptr;
+  double* ustore = nullptr;   // optional: every step's coarse solution, [n_steps][n_nodes*NS]
   CoarseWork cw;
   // graph replay of a time step: device step counter and the two captured halves
   int64_t* kdev = nullptr;
@@ -309,9 +312,12 @@ struct SourceTable {
 // One forward step k: condense, assemble, coarse solve, nodal update, recover.
 // Optional stores (nullptr = skip): unknowns with ghosts (xs) and a level field
 // (fs: a^k when field_kind = 0, v^k when field_kind = 1); receiver traces.
+// usol (optional): the step's coarse solution, kept by an earlier run of the
+// same step; the gather and the coarse solve are then skipped.
 int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceTable& src,
                        int n_rec, const int64_t* rec_node, double* traces, int64_t n_steps,
-                       double* xs, double* fs, int field_kind, hipStream_t s, double* vs = nullptr);
+                       double* xs, double* fs, int field_kind, hipStream_t s, double* vs = nullptr,
+                       const double* usol = nullptr);
 int sbfwi_state_copy(sbfwi_mesh_s* m, StepWork* w, double* dst, int to_store, hipStream_t s);
 // Graph replay of forward steps (no per-step stores): the first call captures
 // the step on stream s (which must not be the null stream) into two graphs

@@ -464,12 +464,14 @@ __global__ void nodal_kernel(int64_t n_nodes, int NS, FactorsDev f, const double
                              double* __restrict__ U, double* __restrict__ V, double* __restrict__ A,
                              double* __restrict__ corr,
                              int n_rec, const int64_t* __restrict__ rec_node, double* __restrict__ traces,
-                             int64_t n_steps, int64_t k, const int64_t* __restrict__ kdev) {
+                             int64_t n_steps, int64_t k, const int64_t* __restrict__ kdev,
+                             double* __restrict__ ustore) {
   if (kdev) k = *kdev;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = n_nodes * NS;
   if (g < nn) {
     double uo = U[g], vo = V[g], ao = A[g], un = Unew[g];
+    if (ustore) ustore[(k - 1) * nn + g] = un;
     double w = f.a0 * uo + f.a1 * vo + f.a2 * ao;
     corr[g] = un - (uo + f.dt * vo + 0.5 * f.dt * f.dt * ao);
     V[g] = f.c1 * (un - uo) + f.c2 * vo + f.c3 * ao;
@@ -633,7 +635,7 @@ int step_pre(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, cons
   return SBFWI_OK;
 }
 
-// nodal Newmark update, receivers, recover
+// nodal Newmark update, receivers, recover (a.Unew: the step's coarse solution)
 int step_post(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, const int64_t* kdev, int n_rec,
               const int64_t* rec_node, double* traces, int64_t n_steps, hipStream_t st) {
   sbfwi_mesh_s* m = f->m;
@@ -642,7 +644,8 @@ int step_post(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, con
   {
     ProfScope ps(PK_NODAL, st);
     hipLaunchKernelGGL(nodal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m->n_nodes, w->NS,
-                       f->d, w->Unew, w->U, w->V, w->A, w->corr, n_rec, rec_node, traces, n_steps, k, kdev);
+                       f->d, a.Unew, w->U, w->V, w->A, w->corr, n_rec, rec_node, traces, n_steps, k, kdev,
+                       w->ustore);
   }
   launch_sweep(false, f, a, st);
   SBFWI_HIP(hipGetLastError());
@@ -671,8 +674,13 @@ int capture(hipStream_t st, hipGraphExec_t* out, const std::function<int()>& bod
 
 int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceTable& src, int n_rec,
                        const int64_t* rec_node, double* traces, int64_t n_steps, double* xs, double* fs,
-                       int field_kind, hipStream_t st, double* vs) {
-  const StepArgs a = step_args(w, xs, fs, field_kind, vs);
+                       int field_kind, hipStream_t st, double* vs, const double* usol) {
+  StepArgs a = step_args(w, xs, fs, field_kind, vs);
+  if (usol) {   // the coarse solution is known: condense (for q and y_n), then nodal update and recover
+    a.Unew = const_cast<double*>(usol);   // read only by the nodal update and the recover sweep
+    launch_sweep(true, f, a, st);
+    return step_post(f, w, a, k, nullptr, n_rec, rec_node, traces, n_steps, st);
+  }
   SBFWI_CHECK(step_pre(f, w, a, k, nullptr, src, st));
   SBFWI_CHECK(sbfwi_coarse_solve(f, &w->cw, 0, w->F, w->Unew, k, st));
   return step_post(f, w, a, k, nullptr, n_rec, rec_node, traces, n_steps, st);

@@ -70,18 +70,23 @@ def test_direct_full_size_matches_iterative(shots):
 
 @pytest.mark.parametrize("n_ckpt", [-1, 3])
 def test_overlapped_recompute_is_bit_identical(n_ckpt):
-    """The backward pass with the segment recompute overlapped on a second stream
-    (default) gives the same bits as one segment after the other, and the oracle's
-    gradient; several segments, odd and even counts."""
+    """The backward pass with the segment recompute overlapped on a second stream and
+    fed with the forward run's kept coarse solutions (the defaults) gives the same bits
+    as one segment after the other with coarse solves, and the oracle's gradient;
+    several segments, odd and even counts."""
     wl = W.config_small(nx=4, ny=2, segs=2, n_r=7, n_steps=40, n_shots=3)
     rho = wl.models["random30"]
     obs = ostp.forward(_om(wl, rho * 0.95), wl.src_nodes, wl.wavelets, wl.rec_nodes, 40)
     g = GpuModel(wl, rho, coarse_solver=1)
     _, mis1, grad1, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt)
-    g.sb.sbfwi_set_launch(g.f, 3, 0)
-    _, mis0, grad0, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt)
+    for overlap, keep in ((0, 1), (1, 0), (0, 0)):
+        g.sb.sbfwi_set_launch(g.f, 3, overlap)
+        g.sb.sbfwi_set_launch(g.f, 4, keep)
+        _, mis0, grad0, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt)
+        log(f"n_ckpt {n_ckpt}, overlap {overlap}, kept solutions {keep}: bit-identical "
+            f"{np.array_equal(grad1, grad0)}")
+        assert np.array_equal(grad1, grad0) and mis1 == mis0
     gref, Jref = oadj.exact_gradient(_om(wl, rho), wl.src_nodes, wl.wavelets, wl.rec_nodes, obs, 40)
     err = rel_l2(grad1, gref)
-    log(f"overlapped recompute (n_ckpt {n_ckpt}): bit-identical {np.array_equal(grad1, grad0)}, vs oracle {err:.3e}")
-    assert np.array_equal(grad1, grad0) and mis1 == mis0
+    log(f"overlapped recompute with kept solutions (n_ckpt {n_ckpt}): vs oracle {err:.3e}")
     assert err <= 1e-8
