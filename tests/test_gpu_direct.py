@@ -90,3 +90,24 @@ def test_overlapped_recompute_is_bit_identical(n_ckpt):
     err = rel_l2(grad1, gref)
     log(f"overlapped recompute with kept solutions (n_ckpt {n_ckpt}): vs oracle {err:.3e}")
     assert err <= 1e-8
+
+
+def test_solve_program_structure():
+    """The solve programs cover every row once: the forward program evaluates
+    |J| + |B_J| rows per supernode (y and the update vector), the backward one |J|;
+    one launch per dissection level above the cut plus one for the subtrees."""
+    import paper_2501_06748_amd as sb
+    wl = W.config_paper(n_steps=2)
+    m = wl.mesh
+    mh = sb.sbfwi_build_mesh(m.node_xy, m.elem_ptr, m.elem_nodes, m.n_r, xi0=wl.xi0)
+    info = sb.sbfwi_direct_info(mh)
+    fwd, bwd = sb.sbfwi_direct_launches(mh, 0), sb.sbfwi_direct_launches(mh, 1)
+    n = int(m.n_nodes)
+    log(f"dissection: {info}; {len(fwd)} forward and {len(bwd)} backward launches")
+    assert sum(L["rows"] for L in fwd) == n + info["sum_B"]
+    assert sum(L["rows"] for L in bwd) == n
+    assert sum(L["slot_records"] for L in fwd) == n            # one slot per own node
+    assert sum(L["slot_records"] for L in bwd) == n + info["sum_B"]
+    assert len(fwd) == len(bwd) and fwd[0]["subtrees"] == 1 and bwd[-1]["subtrees"] == 1
+    assert all(L["subtrees"] == 0 for L in fwd[1:]) and fwd[-1]["blocks"] >= 1
+    assert all(1 <= L["lanes"] <= 64 and L["slots"] >= 1 for L in fwd + bwd)
