@@ -195,13 +195,15 @@ def main():
 
     plan = None
 
+    overlap = args.overlap
+
     def factor(rho):
         f = sb.sbfwi_factor_elements(mh, rho, wl.c, wl.dt, wl.beta, wl.gamma, coarse_solver=args.coarse_solver)
         if args.solver_iters:
             sb.sbfwi_set_launch(f, 0, args.solver_iters)
         if args.graphs:
             sb.sbfwi_set_launch(f, sb.LAUNCH_GRAPHS, 1)
-        sb.sbfwi_set_launch(f, 3, args.overlap)
+        sb.sbfwi_set_launch(f, 3, overlap)
         if plan is not None:
             sb.apply_plan(f, plan)
         return f
@@ -243,6 +245,19 @@ def main():
         f.close()
         return stats
 
+    # kernel census (untimed, before the warmup): one gradient evaluation with the backward pass
+    # on one stream, so that every kernel runs alone, each kernel kind timed by events
+    overlap = 0
+    torch.cuda.synchronize()
+    t_f = time.perf_counter()
+    factor(rho0).close()   # the whole factorisation of a model (element factors, coarse assembly, coarse LU)
+    t_factor = time.perf_counter() - t_f
+    sb.sbfwi_profile([k for k in sb.PROFILE_KERNELS if not k.startswith("solve_")])
+    step()
+    torch.cuda.synchronize()
+    census = sb.sbfwi_profile_read(reset=True)
+    sb.sbfwi_profile(0)
+    overlap = args.overlap
     # warmup: every kernel id except the coarse solve as a whole (its kernels are timed one by one)
     warm_ids = [k for k in sb.PROFILE_KERNELS if k != "coarse_solve"]
     sb.sbfwi_profile(warm_ids)
@@ -292,6 +307,22 @@ def main():
         roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
                 "kernel": dominant, "avg_launch_us": avg_s * 1e6, "launches": d_launches}
     breakdown = {k: round(v["ms"] / max(args.warmup, 1), 3) for k, v in warm.items()}
+    # per-kernel rates of the census (kernels alone): HBM-bound sweeps and contraction against
+    # 8 TB/s, the element factorisation against FP64 (8 n_b^3 flop per element and level)
+    kernels = {}
+    for k, v in census.items():
+        if v["launches"] == 0:
+            continue
+        avg = v["ms"] / v["launches"]
+        ent = {"launches": v["launches"], "avg_us": round(avg * 1e3, 2)}
+        if k in kb and not k.startswith("solve_"):
+            gbs = kb[k] / (avg * 1e-3) / 1e9
+            ent.update({"GB/s": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 3)})
+        if k == "factor":
+            flop = float(8 * (mesh.n_b().astype("int64") ** 3 * mesh.n_r.astype("int64")).sum())
+            ent.update({"GFLOP/s": round(flop / (avg * 1e-3) / 1e9, 1), "frac_fp64_peak": round(flop / (avg * 1e-3) / 78.6e12, 4)})
+        kernels[k] = ent
+    kernels["factorisation_s"] = round(t_factor, 4)
     out = {
         "metric": "element*radial*steps/s fwd+adj FP64",
         "value": value,
@@ -314,6 +345,7 @@ def main():
                    "units_per_step": units},
         "roofline": roof,
         "kernel_ms_per_step_warmup": breakdown,
+        "kernels_alone": kernels,
         "coarse_solver": stats,
         "misfit": float(misfit.item()),
     }

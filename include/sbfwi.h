@@ -281,7 +281,7 @@ int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
  * 1 recover, 2 coarse solve (all its kernels), 3 source gather, 4 nodal
  * update, 5 transposed condense, 6 transposed recover, 7 adjoint gather,
  * 8 adjoint nodal update, 9 exact-gradient contraction, 10 paper-kernel
- * correlation, 11 factorisation, 12 / 13 / 14 the three per-iteration kernels
+ * correlation, 11 element factorisation kernels, 12 / 13 / 14 the three per-iteration kernels
  * of the coarse solve (v = K p, t = K s, the x / r / p update), 15 its two
  * start-up kernels, 16 the recover sweep of the checkpoint recompute, which
  * also stores the adjoint's inputs; id 1 counts the other recover sweeps).  A sweep over elements of several n_b classes counts as

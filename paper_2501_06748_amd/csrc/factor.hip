@@ -469,19 +469,23 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   };
   hipError_t he = hipMemsetAsync(d.status, 0, 8 * sizeof(int), s);
   if (he != hipSuccess) return hip_fail(he, "hipMemsetAsync");
-  ProfScope ps_factor(PK_FACTOR, s);
-  for (int cl = 0; cl < 3; ++cl) {
-    int64_t cnt = (int64_t)m->h_class_elems[cl].size();
-    if (cnt == 0) continue;
-    dim3 grid((unsigned)cnt), block(FT);
-    if (cl == 0)
-      hipLaunchKernelGGL(factor_kernel<8>, grid, block, 0, s, m->class_elems[0], m->d, rho, c, d.a0, d, d.status);
-    else if (cl == 1)
-      hipLaunchKernelGGL(factor_kernel<16>, grid, block, 0, s, m->class_elems[1], m->d, rho, c, d.a0, d, d.status);
-    else
-      hipLaunchKernelGGL(factor_kernel<24>, grid, block, 0, s, m->class_elems[2], m->d, rho, c, d.a0, d, d.status);
-    he = hipGetLastError();
-    if (he != hipSuccess) return hip_fail(he, "factor_kernel launch");
+  {
+    ProfScope ps_factor(PK_FACTOR, s);   // the element factorisation kernels
+    for (int cl = 0; cl < 3; ++cl) {
+      int64_t cnt = (int64_t)m->h_class_elems[cl].size();
+      if (cnt == 0) continue;
+      dim3 grid((unsigned)cnt), block(FT);
+      if (cl == 0)
+        hipLaunchKernelGGL(factor_kernel<8>, grid, block, 0, s, m->class_elems[0], m->d, rho, c, d.a0, d, d.status);
+      else if (cl == 1)
+        hipLaunchKernelGGL(factor_kernel<16>, grid, block, 0, s, m->class_elems[1], m->d, rho, c, d.a0, d,
+                           d.status);
+      else
+        hipLaunchKernelGGL(factor_kernel<24>, grid, block, 0, s, m->class_elems[2], m->d, rho, c, d.a0, d,
+                           d.status);
+      he = hipGetLastError();
+      if (he != hipSuccess) return hip_fail(he, "factor_kernel launch");
+    }
   }
   {
     unsigned g = (unsigned)((m->nnz + 255) / 256);

@@ -93,9 +93,9 @@ def test_overlapped_recompute_is_bit_identical(n_ckpt):
 
 
 def test_solve_program_structure():
-    """The solve programs cover every row once: the forward program evaluates
-    |J| + |B_J| rows per supernode (y and the update vector), the backward one |J|;
-    one launch per dissection level above the cut plus one for the subtrees."""
+    """The solve programs evaluate every row once: the forward program |J| + |B_J|
+    rows per supernode (y and the update vector), the backward one |J|; one launch
+    per dissection level above the cut plus one for the subtrees."""
     import paper_2501_06748_amd as sb
     wl = W.config_paper(n_steps=2)
     m = wl.mesh
@@ -106,8 +106,9 @@ def test_solve_program_structure():
     log(f"dissection: {info}; {len(fwd)} forward and {len(bwd)} backward launches")
     assert sum(L["rows"] for L in fwd) == n + info["sum_B"]
     assert sum(L["rows"] for L in bwd) == n
-    assert sum(L["slot_records"] for L in fwd) == n            # one slot per own node
-    assert sum(L["slot_records"] for L in bwd) == n + info["sum_B"]
+    # every block assembles its supernode's whole vector (blocks sharing a supernode reread it)
+    assert sum(L["slot_records"] for L in fwd) >= n
+    assert sum(L["slot_records"] for L in bwd) >= n + info["sum_B"]
     assert len(fwd) == len(bwd) and fwd[0]["subtrees"] == 1 and bwd[-1]["subtrees"] == 1
     assert all(L["subtrees"] == 0 for L in fwd[1:]) and fwd[-1]["blocks"] >= 1
     assert all(1 <= L["lanes"] <= 64 and L["slots"] >= 1 for L in fwd + bwd)
