@@ -25,6 +25,11 @@ Modules
               Lyapunov) for radially constant density.
 ``stability`` step-map spectrum of the coupled discrete system (gate for
               models on which the radial finite-difference scheme is stable).
+``radial_galerkin`` linear radial elements for one element's dynamic
+              stiffness (an independent limit of the finite differences).
+``fem``       bilinear finite elements with lumped mass and central
+              differences: the generator of observed data from a finer,
+              conventional model (no inverse crime).
 
 Every function cites the passage of the paper it follows.  Parity-unpinned
 functions say so in their docstrings.

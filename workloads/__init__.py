@@ -14,14 +14,16 @@ rho0 = 2700 kg/m^3) with seeded voids and smooth fields are used instead.
 """
 
 from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, nearest_top_node
-from .models import (fine_point_positions, homogeneous, smoothed_voids,
+from .models import (fine_point_positions, homogeneous, smoothed_voids, sharp_voids,
                      smooth_random_field, seeded_ellipses, seeded_circle)
+from .fem_grid import FemGrid, fem_grid, fem_nodes, fem_density
 from .signals import ricker, sine_burst
 from .configs import config_tiny, config_paper, config_small, config_quadtree_tiny, config_quadtree, Workload
 
 __all__ = [
     "Mesh", "uniform_rect_mesh", "quadtree_mesh", "top_edge_nodes", "nearest_top_node",
-    "fine_point_positions", "homogeneous", "smoothed_voids", "smooth_random_field",
+    "fine_point_positions", "homogeneous", "smoothed_voids", "sharp_voids", "smooth_random_field",
+    "FemGrid", "fem_grid", "fem_nodes", "fem_density",
     "seeded_ellipses", "seeded_circle", "ricker", "sine_burst",
     "config_tiny", "config_paper", "config_small", "config_quadtree_tiny", "config_quadtree", "Workload",
 ]

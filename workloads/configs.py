@@ -15,7 +15,11 @@
   ``config_paper``.
 
 Every model is sampled on the fine grid (one density per element, radial
-level and boundary node).  Seeds are 1000 * config_index + item_index.
+level and boundary node).  ``fields`` holds the continuous models, so the
+same model can also be sampled at the element centres of the finite element
+data grid (``fem_cells`` cells per direction, a multiple of the boundary
+segments per element edge, so that every scaled-boundary node is a grid
+node).  Models whose name ends in ``_data`` are for observed data only.  Seeds are 1000 * config_index + item_index.
 """
 
 from __future__ import annotations
@@ -26,7 +30,7 @@ import numpy as np
 
 from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, nearest_top_node
 from .models import (fine_point_positions, homogeneous, smoothed_voids, smooth_random_field,
-                     seeded_circle, seeded_ellipses)
+                     seeded_circle, seeded_ellipses, sharp_voids)
 from .signals import ricker
 
 
@@ -42,6 +46,8 @@ class Workload:
     wavelets: np.ndarray           # [n_shots, n_steps] float64
     rec_nodes: np.ndarray          # [n_rec] int64
     models: dict = field(default_factory=dict)   # name -> rho [n_params]
+    fields: dict = field(default_factory=dict)   # name -> callable(points [P, 2]) -> rho [P]
+    fem_cells: tuple | None = None                # (nx, ny) of the finite element data grid
     beta: float = 0.25
     gamma: float = 0.5
     xi0: float = 1e-3
@@ -67,13 +73,16 @@ def config_tiny(n_steps: int = 200) -> Workload:
     pts = fine_point_positions(mesh)
     le = lx / 8
     void = seeded_circle(0 * 1000 + 0, [0.004, 0.004], [0.016, 0.016], 0.002)
-    models = {
-        "homogeneous": homogeneous(mesh, 2700.0),
-        "void_floor_half": smoothed_voids(pts, void, 2700.0, 0.5, le / 16),
-        "random30": smooth_random_field(pts, 0 * 1000 + 1, 2700.0, 0.3),
-        "void_data": smoothed_voids(pts, void, 2700.0, 1e-5, le / 16),
+    fields = {
+        "homogeneous": lambda p: np.full(p.shape[0], 2700.0),
+        "void_floor_half": lambda p: smoothed_voids(p, void, 2700.0, 0.5, le / 16),
+        "random30": lambda p: smooth_random_field(p, 0 * 1000 + 1, 2700.0, 0.3),
+        "void_data": lambda p: smoothed_voids(p, void, 2700.0, 1e-5, le / 16),
+        "void_sharp_data": lambda p: sharp_voids(p, void, 2700.0, 1e-5),
     }
-    return Workload("tiny-8x8-nb8-nr16", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models)
+    models = {k: fields[k](pts) for k in ("homogeneous", "void_floor_half", "random30", "void_data")}
+    return Workload("tiny-8x8-nb8-nr16", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models,
+                    fields=fields, fem_cells=(32, 32))
 
 
 def config_paper(n_steps: int = 4000, n_shots: int = 4) -> Workload:
@@ -87,12 +96,15 @@ def config_paper(n_steps: int = 4000, n_shots: int = 4) -> Workload:
     pts = fine_point_positions(mesh)
     le = lx / 128
     ell = seeded_ellipses(1 * 1000 + 0, 2, (lx, ly), 0.002, 0.006, 2 * le)
-    models = {
-        "homogeneous": homogeneous(mesh, 2700.0),
-        "voids_floor_half": smoothed_voids(pts, ell, 2700.0, 0.5, le / 32),
-        "random30": smooth_random_field(pts, 1 * 1000 + 1, 2700.0, 0.3),
+    fields = {
+        "homogeneous": lambda p: np.full(p.shape[0], 2700.0),
+        "voids_floor_half": lambda p: smoothed_voids(p, ell, 2700.0, 0.5, le / 32),
+        "random30": lambda p: smooth_random_field(p, 1 * 1000 + 1, 2700.0, 0.3),
+        "voids_data": lambda p: sharp_voids(p, ell, 2700.0, 1e-5),
     }
-    return Workload("paper-128x64-nb16-nr32", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models)
+    models = {k: fields[k](pts) for k in ("homogeneous", "voids_floor_half", "random30")}
+    return Workload("paper-128x64-nb16-nr32", mesh, 3000.0, 2700.0, dt, n_steps, src, wav, rec, models,
+                    fields=fields, fem_cells=(512, 256))
 
 
 def config_small(nx: int = 12, ny: int = 6, segs: int = 3, n_r: int = 12, n_steps: int = 60,
@@ -107,12 +119,13 @@ def config_small(nx: int = 12, ny: int = 6, segs: int = 3, n_r: int = 12, n_step
     f0 = 5e5
     wav = np.stack([ricker(n_steps, dt, f0, t0=(1.5 + 0.1 * s) / f0) for s in range(n_shots)])
     pts = fine_point_positions(mesh)
-    models = {
-        "homogeneous": homogeneous(mesh, 2700.0),
-        "random30": smooth_random_field(pts, 2 * 1000 + 1, 2700.0, 0.3, wavelength=lx / 3),
+    fields = {
+        "homogeneous": lambda p: np.full(p.shape[0], 2700.0),
+        "random30": lambda p: smooth_random_field(p, 2 * 1000 + 1, 2700.0, 0.3, wavelength=lx / 3),
     }
+    models = {k: f(pts) for k, f in fields.items()}
     return Workload(f"small-{nx}x{ny}-nb{4*segs}-nr{n_r}", mesh, 3000.0, 2700.0, dt, n_steps,
-                    src, wav, rec, models)
+                    src, wav, rec, models, fields=fields, fem_cells=(nx * 2 * segs, ny * 2 * segs))
 
 
 def config_quadtree_tiny(n_steps: int = 40) -> Workload:

@@ -85,6 +85,17 @@ def smoothed_voids(points: np.ndarray, voids, rho0: float, floor: float, width: 
     return rho0 * scale
 
 
+def sharp_voids(points: np.ndarray, voids, rho0: float, floor: float) -> np.ndarray:
+    """rho0 * floor inside any ellipse (cx, cy, a, b, angle), rho0 outside."""
+    inside = np.zeros(points.shape[0], dtype=bool)
+    for (cx, cy, a, b, ang) in voids:
+        dx, dy = points[:, 0] - cx, points[:, 1] - cy
+        ca, sa = np.cos(ang), np.sin(ang)
+        xp, yp = ca * dx + sa * dy, -sa * dx + ca * dy
+        inside |= (xp / a) ** 2 + (yp / b) ** 2 < 1.0
+    return np.where(inside, rho0 * floor, rho0)
+
+
 def smooth_random_field(points: np.ndarray, seed: int, rho0: float, amplitude: float = 0.3,
                         wavelength: float = 5e-3, n_modes: int = 12) -> np.ndarray:
     """rho0 * (1 + amplitude * g), g a sum of seeded plane waves scaled to [-1, 1]."""
