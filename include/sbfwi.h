@@ -284,7 +284,8 @@ int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
  * correlation, 11 element factorisation kernels, 12 / 13 / 14 the three per-iteration kernels
  * of the coarse solve (v = K p, t = K s, the x / r / p update), 15 its two
  * start-up kernels, 16 the recover sweep of the checkpoint recompute, which
- * also stores the adjoint's inputs; id 1 counts the other recover sweeps).  A sweep over elements of several n_b classes counts as
+ * also stores the adjoint's inputs; id 1 counts the other recover sweeps), 17 the
+ * time step of sbfwi_fem_forward.  A sweep over elements of several n_b classes counts as
  * one launch.  Recorded pairs are accumulated as they complete (the oldest
  * are waited for once many are in flight).  sbfwi_profile_read waits for the
  * rest and writes, for each of the 20 ids, host_out[2 id] = launches and
@@ -293,6 +294,33 @@ int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
  */
 int sbfwi_profile(uint32_t kernel_mask);
 int sbfwi_profile_read(double* host_out, int reset);
+
+/*
+ * sbfwi_fem_forward -- observed data from a conventional finite element model
+ * (Section "Numerical examples": the paper's data come from a finer bilinear
+ * finite element model, so that the inversion does not commit the inverse
+ * crime).  The scalar wave equation rho u_tt = div(rho c^2 grad u) + f of the
+ * governing equations, on nx x ny bilinear rectangles covering [0, lx] x [0, ly]
+ * with a free boundary, one density per element, lumped (row-sum) mass and
+ * explicit central differences M (u_{k+1} - 2 u_k + u_{k-1}) / dt^2 + K u_k = f_k,
+ * u_0 = u_1 = 0.  Time convention as in sbfwi_forward: the point force at
+ * t_k = k dt is wavelet[q * n_steps + k - 1] at node src_node[q], and
+ * traces[(q * n_rec + r) * n_steps + k - 1] = u(t_k) at node rec_node[r],
+ * k = 1 .. n_steps.
+ *   Grid nodes: node (i, j) at (i lx / nx, j ly / ny) has id j (nx + 1) + i.
+ *   rho_elem  device [ny][nx]: density of element (ie, je) at je nx + ie,
+ *             positive and finite (SBFWI_EINVAL otherwise).
+ *   src_node  device int64 [n_shots] (1 <= n_shots <= 64); rec_node device
+ *             int64 [n_rec]; ids in [0, (nx + 1)(ny + 1)), checked on the host.
+ *   wavelet   device [n_shots][n_steps]; traces device [n_shots][n_rec][n_steps].
+ * SBFWI_EINVAL if dt exceeds 1 / (c sqrt(1/hx^2 + 1/hy^2)) (the scheme's
+ * stability bound from the row sums of M^-1 K).  Work buffers (two wavefields
+ * of n_shots (nx + 1)(ny + 1) doubles and the coefficients) are allocated and
+ * freed by the call.  Synchronises s.
+ */
+int sbfwi_fem_forward(int nx, int ny, double lx, double ly, const double* rho_elem, double c, double dt,
+                      int n_shots, int64_t n_steps, const int64_t* src_node, const double* wavelet,
+                      int n_rec, const int64_t* rec_node, double* traces, hipStream_t s);
 
 void sbfwi_destroy_mesh(sbfwi_mesh m);
 void sbfwi_destroy_factors(sbfwi_factors f);

@@ -223,6 +223,23 @@ def sbfwi_forward(f: FactorsHandle, src_node, wavelet, rec_node, traces, n_ckpt=
     return CkptHandle(out.value, f) if n_ckpt != 0 else None
 
 
+def sbfwi_fem_forward(nx, ny, lx, ly, rho_elem, c, dt, src_node, wavelet, rec_node, traces, stream=None):
+    """Finite element data: rho_elem [ny * nx] f64, src_node [S] int64, wavelet [S, N_t] f64,
+    rec_node [R] int64, traces [S, R, N_t] f64 (device); grid node (i, j) is j (nx + 1) + i."""
+    import torch
+    n_shots, n_steps = int(wavelet.shape[0]), int(wavelet.shape[1])
+    n_rec = int(rec_node.shape[0])
+    if traces.shape != (n_shots, n_rec, n_steps) or src_node.shape != (n_shots,):
+        raise ValueError("shape mismatch between src_node, wavelet, rec_node and traces")
+    if rho_elem.numel() != int(nx) * int(ny):
+        raise ValueError("rho_elem must hold nx * ny densities")
+    check(lib().sbfwi_fem_forward(int(nx), int(ny), float(lx), float(ly), _dptr(rho_elem, torch.float64, "rho_elem"),
+                                  float(c), float(dt), n_shots, n_steps, _dptr(src_node, torch.int64, "src_node"),
+                                  _dptr(wavelet, torch.float64, "wavelet"), n_rec,
+                                  _dptr(rec_node, torch.int64, "rec_node"), _dptr(traces, torch.float64, "traces"),
+                                  _stream(stream)))
+
+
 def _check_grad_shapes(f, n_shots, mode, grad, misfit=None):
     n_params = sbfwi_mesh_info(f.mesh)["n_params"]
     per = n_shots if (int(mode) & GRAD_PER_SHOT) else 1
@@ -266,7 +283,7 @@ def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:
 
 PROFILE_KERNELS = ["condense", "recover", "coarse_solve", "source_gather", "nodal_update", "adj_condense",
                    "adj_recover", "adj_gather", "adj_nodal_update", "grad_exact", "grad_paper", "factor",
-                   "solve_v", "solve_t", "solve_x", "solve_init", "recover_store"]
+                   "solve_v", "solve_t", "solve_x", "solve_init", "recover_store", "fem_step"]
 
 
 def sbfwi_profile(kernels):

@@ -43,6 +43,7 @@ SIGNATURES = {
     "sbfwi_ckpt_info": (i32, [vp, vp]),
     "sbfwi_factors_info": (i32, [vp, vp]),
     "sbfwi_solver_stats": (i32, [vp, vp, i32]),
+    "sbfwi_fem_forward": (i32, [i32, i32, dbl, dbl, vp, dbl, dbl, i32, i64, vp, vp, i32, vp, vp, vp]),
     "sbfwi_profile": (i32, [C.c_uint32]),
     "sbfwi_profile_read": (i32, [vp, i32]),
     "sbfwi_destroy_mesh": (None, [vp]),

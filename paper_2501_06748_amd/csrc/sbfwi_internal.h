@@ -201,7 +201,7 @@ enum {
   PK_CONDENSE = 0, PK_RECOVER = 1, PK_SOLVE = 2, PK_RHS = 3, PK_NODAL = 4, PK_ADJ_CONDENSE = 5,
   PK_ADJ_RECOVER = 6, PK_ADJ_RHS = 7, PK_ADJ_NODAL = 8, PK_GRAD_EXACT = 9, PK_GRAD_PAPER = 10,
   PK_FACTOR = 11, PK_SOLVE_V = 12, PK_SOLVE_T = 13, PK_SOLVE_X = 14, PK_SOLVE_INIT = 15,
-  PK_RECOVER_STORE = 16
+  PK_RECOVER_STORE = 16, PK_FEM_STEP = 17
 };
 // Brackets the launches made during its lifetime with events on stream s when
 // kernel id is enabled by sbfwi_profile.

@@ -58,3 +58,21 @@ class GpuModel:
         self.sb.sbfwi_gradient(self.f, ck, obs, tr, mode, mis, grad)
         torch.cuda.synchronize()
         return tr.cpu().numpy(), float(mis.item()), grad.cpu().numpy(), ck
+
+
+def fem_gpu(grid, rho_elem, c, dt, src, wavelets, rec, n_steps=None):
+    """Finite element data on cuda:0 through the C ABI; returns traces [S, R, N] (numpy)."""
+    import torch
+    import paper_2501_06748_amd as sb
+    wav = np.ascontiguousarray(np.asarray(wavelets, dtype=np.float64))
+    if n_steps is not None:
+        wav = np.ascontiguousarray(wav[:, :n_steps])
+    S, N = wav.shape
+    d = "cuda"
+    tr = torch.full((S, len(rec), N), np.nan, dtype=torch.float64, device=d)
+    sb.sbfwi_fem_forward(grid.nx, grid.ny, grid.lx, grid.ly,
+                         torch.tensor(np.asarray(rho_elem, dtype=np.float64), device=d), c, dt,
+                         torch.tensor(np.asarray(src, dtype=np.int64), device=d), torch.tensor(wav, device=d),
+                         torch.tensor(np.asarray(rec, dtype=np.int64), device=d), tr)
+    torch.cuda.synchronize()
+    return tr.cpu().numpy()
