@@ -15,7 +15,9 @@ Modules
 ``element``   geometry, coefficient matrices E0, E1, E2, M0 (eq. Es), their
               radial finite differences, the three-point block rows and the
               ghost/boundary rows (eq. system), and the paper's condensation
-              sweep that yields the dynamic stiffness S and effective source.
+              sweep that yields the dynamic stiffness S and effective source;
+              also the rows of the radial Galerkin scheme (linear elements in
+              xi, lumped radial mass) in the same block layout.
 ``stepper``   coarse assembly, exact sparse LU coarse solve, the per-step
               condense / solve / recover / Newmark loop, receivers, misfit.
 ``adjoint``   exact discrete adjoint gradient of the misfit (transposed
@@ -25,8 +27,10 @@ Modules
               Lyapunov) for radially constant density.
 ``stability`` step-map spectrum of the coupled discrete system (gate for
               models on which the radial finite-difference scheme is stable).
-``radial_galerkin`` linear radial elements for one element's dynamic
-              stiffness (an independent limit of the finite differences).
+``radial_galerkin`` linear radial elements for one element, assembled
+              densely: its stiffness, mass and condensed dynamic stiffness (an
+              independent limit of the finite differences and the reference
+              of the Galerkin rows).
 ``fem``       bilinear finite elements with lumped mass and central
               differences: the generator of observed data from a finer,
               conventional model (no inverse crime).

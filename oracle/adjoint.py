@@ -38,7 +38,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .element import block_rows, coefficient_matrices, element_system, row_columns
+from .element import SCHEMES, coefficient_matrices, element_system, row_columns
 from .stepper import Model, forward
 
 
@@ -65,7 +65,9 @@ class _ElementBlocks:
 
 def _basis_rows(g, m, k):
     """d(theta, phi, psi, P)/d rho_{m,k}: the rows built from E-matrices of a unit
-    density at level m, node k (all rows are linear in the densities)."""
+    density at level m, node k, less the rows of zero densities (the rows are
+    affine in the densities: the radial Galerkin layout has constant identity
+    blocks)."""
     E_, nr, nb = len(g.elem_ids), g.n_r, g.n_b
     unit = np.zeros((E_, 1, nb))
     unit[:, 0, k] = 1.0
@@ -75,7 +77,9 @@ def _basis_rows(g, m, k):
         Z = np.zeros((E_, nr, nb, nb))
         Z[:, m] = B[:, 0]
         lev.append(Z)
-    return block_rows(*lev, g.xi, g.h, g.a0)
+    rows = SCHEMES[g.scheme]
+    zero = np.zeros((E_, nr, nb, nb))
+    return tuple(a - b for a, b in zip(rows(*lev, g.xi, g.h, g.a0), rows(zero, zero, zero, zero, g.xi, g.h, g.a0)))
 
 
 def exact_gradient(model: Model, src_nodes, wavelets, rec_nodes, observed, n_steps,
@@ -167,6 +171,7 @@ class _Sub:
         self.elem_ids = g.elem_ids[sel]
         self.xy, self.centre = g.xy[sel], g.centre[sel]
         self.n_r, self.n_b, self.xi, self.h, self.c, self.a0 = g.n_r, g.n_b, g.xi, g.h, g.c, g.a0
+        self.scheme = g.scheme
 
 
 def paper_kernel_gradient(model: Model, src_nodes, wavelets, rec_nodes, observed, n_steps,

@@ -169,6 +169,83 @@ def block_rows(E0, E1, E2, M0, xi, h, a0):
     return theta, phi, psi, P
 
 
+def galerkin_rows(E0, E1, E2, M0, xi, h, a0, n_quad: int = 4):
+    """Block rows of the radial Galerkin scheme, in the layout of ``block_rows``.
+
+    Linear finite elements between consecutive levels replace the central
+    differences (a deviation from the paper's eq. FD, which is not symmetric
+    and loses stability at large density contrast).  From the semi-weak
+    radial equation integrated by parts in xi with the internal flux
+    q = xi E0 u' + E1^T u (natural conditions q(xi0) = 0 and q(1) = f), the
+    stiffness block of levels (r, l) collects, over the intervals
+    [xi_j, xi_j+1] that contain both,
+        int [ xi N_r' N_l' E0 + N_r' N_l E1^T + N_r N_l' E1 + N_r N_l E2 / xi ] dxi,
+    with every E interpolated linearly between its two levels and n_quad-point
+    Gauss-Legendre quadrature per interval.  The radial mass is lumped:
+    M_r = sum over its intervals of int xi N_r M0 dxi.  Newmark turns
+    K u + M a = f into (K + a0 M) u = f + M w.
+
+    Layout (rows r = -1 .. n + 1 at index r + 1, as in ``block_rows``):
+      rows 0 .. n-1: the negated Galerkin rows (theta = -K_{r,r-1},
+        phi = -(K_rr + a0 M_r), psi = -K_{r,r+1}, P = -M_r);
+      row n: the identity on the unused level n + 1 with P_n = M_n, so that
+        u_{n+1} = M_n w_n;
+      row n + 1: the boundary row (K_{n,n-1}, K_nn + a0 M_n, -I) with the
+        nodal force on its right-hand side, so that it reads
+        K_{n,n-1} u_{n-1} + (K_nn + a0 M_n) u_n = f + M_n w_n;
+      row -1: the identity on the unused level -1 (u_{-1} = 0).
+    The elimination of ``condense`` then yields G = -I and the Schur
+    complement of the interior levels as S.
+    """
+    E_, nr, nb, _ = E0.shape
+    n = nr - 1
+    dt_ = E0.dtype
+    Kd = np.zeros((E_, nr, nb, nb), dt_)
+    Kl = np.zeros_like(Kd)    # block (r, r - 1)
+    Ku = np.zeros_like(Kd)    # block (r, r + 1)
+    Ml = np.zeros_like(Kd)
+    gp, gw = np.polynomial.legendre.leggauss(n_quad)
+    for j in range(n):
+        a, b = xi[j], xi[j + 1]
+        for t, w in zip(gp, gw):
+            x = (a + b) / 2 + (b - a) / 2 * t
+            ww = w * (b - a) / 2
+            Nf = ((b - x) / (b - a), (x - a) / (b - a))
+            dN = (-1.0 / (b - a), 1.0 / (b - a))
+            e0, e1, e2, m0 = [Nf[0] * E[:, j] + Nf[1] * E[:, j + 1] for E in (E0, E1, E2, M0)]
+            for p in range(2):
+                for q in range(2):
+                    blk = ww * (x * dN[p] * dN[q] * e0 + dN[p] * Nf[q] * T(e1) + Nf[p] * dN[q] * e1
+                                + Nf[p] * Nf[q] * e2 / x)
+                    if p == q:
+                        Kd[:, j + p] += blk
+                    elif q < p:
+                        Kl[:, j + p] += blk
+                    else:
+                        Ku[:, j + p] += blk
+                Ml[:, j + p] += ww * x * Nf[p] * m0
+    eye = np.broadcast_to(np.eye(nb, dtype=dt_), (E_, nb, nb))
+    shape = (E_, n + 3, nb, nb)
+    theta = np.zeros(shape, dt_)
+    phi = np.zeros(shape, dt_)
+    psi = np.zeros(shape, dt_)
+    P = np.zeros((E_, n + 1, nb, nb), dt_)
+    theta[:, 1:n + 1] = -Kl[:, :n]
+    phi[:, 1:n + 1] = -(Kd[:, :n] + a0 * Ml[:, :n])
+    psi[:, 1:n + 1] = -Ku[:, :n]
+    P[:, :n] = -Ml[:, :n]
+    psi[:, n + 1] = eye
+    P[:, n] = Ml[:, n]
+    theta[:, n + 2] = Kl[:, n]
+    phi[:, n + 2] = Kd[:, n] + a0 * Ml[:, n]
+    psi[:, n + 2] = -eye
+    theta[:, 0] = eye
+    return theta, phi, psi, P
+
+
+SCHEMES = {"paper_fd": block_rows, "radial_galerkin": galerkin_rows}
+
+
 def row_columns(r: int, n: int):
     """Levels of the three unknowns that row r couples (eq. system)."""
     if r == -1:
@@ -225,7 +302,7 @@ def condense(theta, phi, psi):
 class ElementGroup:
     """All oracle data of a group of elements with one (n_b, N_r)."""
 
-    def __init__(self, elem_ids, loops, xy, rho, c, xi0, a0, centre=None, n_gauss=2):
+    def __init__(self, elem_ids, loops, xy, rho, c, xi0, a0, centre=None, n_gauss=2, scheme="paper_fd"):
         self.elem_ids = np.asarray(elem_ids, dtype=np.int64)
         self.loops = np.asarray(loops, dtype=np.int64)          # [E, n_b]
         self.xy = xy
@@ -234,9 +311,9 @@ class ElementGroup:
         self.n = self.n_r - 1
         self.n_b = rho.shape[2]
         self.xi, self.h = radial_levels(self.n_r, xi0)
-        self.c, self.a0 = c, a0
+        self.c, self.a0, self.scheme = c, a0, scheme
         self.E0, self.E1, self.E2, self.M0 = coefficient_matrices(xy, self.centre, rho, c, n_gauss)
-        self.theta, self.phi, self.psi, self.P = block_rows(
+        self.theta, self.phi, self.psi, self.P = SCHEMES[scheme](
             self.E0, self.E1, self.E2, self.M0, self.xi, self.h, a0)
         self.f = condense(self.theta, self.phi, self.psi)
 
@@ -253,7 +330,7 @@ def group_elements(mesh):
     return [(np.asarray(v, dtype=np.int64), k[0], k[1]) for k, v in sorted(keys.items())]
 
 
-def build_groups(mesh, rho_flat, c, xi0, a0, n_gauss=2):
+def build_groups(mesh, rho_flat, c, xi0, a0, n_gauss=2, scheme="paper_fd"):
     """ElementGroup per (n_b, N_r) from the fine-grid density (level-major per element)."""
     offs = mesh.param_offsets()
     groups = []
@@ -261,5 +338,5 @@ def build_groups(mesh, rho_flat, c, xi0, a0, n_gauss=2):
         loops = np.stack([mesh.loop(e) for e in ids])
         xy = mesh.node_xy[loops]
         rho = np.stack([rho_flat[offs[e]:offs[e + 1]].reshape(n_r, n_b) for e in ids])
-        groups.append(ElementGroup(ids, loops, xy, rho, c, xi0, a0, n_gauss=n_gauss))
+        groups.append(ElementGroup(ids, loops, xy, rho, c, xi0, a0, n_gauss=n_gauss, scheme=scheme))
     return groups

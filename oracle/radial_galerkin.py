@@ -23,11 +23,15 @@ from __future__ import annotations
 import numpy as np
 
 
-def galerkin_stiffness(E0, E1, E2, M0, xi, a0, n_quad=4):
-    """Condensed boundary stiffness for level matrices E*[N_r, n_b, n_b] on levels xi."""
+def galerkin_matrices(E0, E1, E2, M0, xi, n_quad=4, lumped=False):
+    """Assembled stiffness K and mass M over all levels, dense [N_r n_b]^2, for
+    level matrices E*[N_r, n_b, n_b]; ``lumped`` sums each mass row over the
+    levels (one n_b x n_b block per level)."""
     n_r, nb = E0.shape[0], E0.shape[1]
     N = n_r * nb
-    K = np.zeros((N, N), np.result_type(E0, np.float64))
+    dt_ = np.result_type(E0, np.float64)
+    K = np.zeros((N, N), dt_)
+    M = np.zeros((N, N), dt_)
     gp, gw = np.polynomial.legendre.leggauss(n_quad)
     for j in range(n_r - 1):
         a, b = xi[j], xi[j + 1]
@@ -40,9 +44,19 @@ def galerkin_stiffness(E0, E1, E2, M0, xi, a0, n_quad=4):
             for p in range(2):
                 for q in range(2):
                     blk = ww * (x * dN[p] * dN[q] * e0 + dN[p] * Nf[q] * e1.T
-                                + Nf[p] * dN[q] * e1 + Nf[p] * Nf[q] * e2 / x
-                                + a0 * x * Nf[p] * Nf[q] * m0)
+                                + Nf[p] * dN[q] * e1 + Nf[p] * Nf[q] * e2 / x)
                     K[(j + p) * nb:(j + p + 1) * nb, (j + q) * nb:(j + q + 1) * nb] += blk
+                    mq = j + p if lumped else j + q
+                    M[(j + p) * nb:(j + p + 1) * nb, mq * nb:(mq + 1) * nb] += ww * x * Nf[p] * Nf[q] * m0
+    return K, M
+
+
+def galerkin_stiffness(E0, E1, E2, M0, xi, a0, n_quad=4, lumped=False):
+    """Condensed boundary stiffness for level matrices E*[N_r, n_b, n_b] on levels xi."""
+    n_r, nb = E0.shape[0], E0.shape[1]
+    N = n_r * nb
+    K, M = galerkin_matrices(E0, E1, E2, M0, xi, n_quad, lumped)
+    K = K + a0 * M
     I = np.arange(0, (n_r - 1) * nb)
     B = np.arange((n_r - 1) * nb, N)
     return K[np.ix_(B, B)] - K[np.ix_(B, I)] @ np.linalg.solve(K[np.ix_(I, I)], K[np.ix_(I, B)])

@@ -81,11 +81,11 @@ def coarse_matrix(groups, n_nodes):
 class Model:
     """Factored model: element groups, coarse matrix and its LU (once per rho, dt)."""
 
-    def __init__(self, mesh, rho_flat, c, dt, beta=0.25, gamma=0.5, xi0=1e-3, n_gauss=2):
+    def __init__(self, mesh, rho_flat, c, dt, beta=0.25, gamma=0.5, xi0=1e-3, n_gauss=2, scheme="paper_fd"):
         self.mesh = mesh
         self.nm = Newmark(dt, beta, gamma)
-        self.c, self.xi0 = c, xi0
-        self.groups = build_groups(mesh, rho_flat, c, xi0, self.nm.a0, n_gauss)
+        self.c, self.xi0, self.scheme = c, xi0, scheme
+        self.groups = build_groups(mesh, rho_flat, c, xi0, self.nm.a0, n_gauss, scheme)
         self.K = coarse_matrix(self.groups, mesh.n_nodes)
         self.lu = spla.splu(self.K)
 
