@@ -50,7 +50,7 @@ enum {
   SBFWI_EHIP = -7         /* a HIP runtime call failed                                        */
 };
 
-enum { SBFWI_SCHEME_PAPER_FD = 0 };
+enum { SBFWI_SCHEME_PAPER_FD = 0, SBFWI_SCHEME_RADIAL_GALERKIN = 1 };
 enum { SBFWI_GRAD_EXACT = 0, SBFWI_GRAD_PAPER_KERNEL = 1 };
 /* Flag OR-ed into the gradient mode: one gradient (and one misfit) per shot. */
 enum { SBFWI_GRAD_PER_SHOT = 16 };
@@ -105,7 +105,18 @@ int sbfwi_mesh_info(sbfwi_mesh m, int64_t* host_out);
  * assembles the coarse matrix K_g = sum_e L_e^T S_e L_e on the fixed pattern.
  *   rho     device [n_params] fine-grid density (layout above), > 0.
  *   c       wave speed; dt, beta, gamma the Newmark parameters (beta > 0).
- *   scheme  SBFWI_SCHEME_PAPER_FD (central differences in xi).
+ *   scheme  SBFWI_SCHEME_PAPER_FD: the paper's central differences in xi
+ *           (eq. FD; not symmetric, and unstable at strong radial density
+ *           contrast); SBFWI_SCHEME_RADIAL_GALERKIN: linear finite elements
+ *           between the levels on the semi-weak radial equation (integrated
+ *           by parts with the internal flux, natural conditions at xi0 and
+ *           xi = 1), E interpolated linearly between levels, 4-point
+ *           Gauss-Legendre quadrature per interval, radial mass lumped; the
+ *           element system is symmetric and average-acceleration Newmark
+ *           conserves its energy (a deviation from the paper, for models
+ *           such as voids at a 1e-5 density floor).  Both schemes share the
+ *           layout of the factors and every per-step call; the exact gradient
+ *           differentiates the scheme that was factored.
  *   coarse_solver 0 = BiCGStab with Jacobi preconditioning (K_g is not
  *           symmetric), solved every step to the tolerance of sbfwi_set_solver;
  *           1 = direct: K_g = L U factored here once, in a nested-dissection

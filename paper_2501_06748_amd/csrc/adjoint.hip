@@ -579,6 +579,154 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
   }
 }
 
+// Exact gradient of the radial Galerkin scheme for one step, in the lane and
+// LDS organisation of grad_exact_kernel.  The level matrices E_m enter the
+// Galerkin blocks of the two intervals around level m (as the interpolation
+// end 1 of interval m - 1 and end 0 of interval m), so the band entries of
+// the sensitivities at level m are
+//   e0(i, j) = sum_a L_a[i] Q_a[j]      e1(i, j) = sum_a (L_a[i] Zb_a[j] + Za_a[i] L_a[j])
+//   e2(i, j) = sum_a L_a[i] Y_a[j]      m0(i, j) = sum_a L_a[i] A_a[j]
+// over the Galerkin rows r = m - 1 + a (a = 0, 1, 2): L_a is the adjoint of
+// row r with the sign that makes the gradient -lambda^T dR/drho (rows of the
+// interior levels are stored negated; the boundary row is row n + 1 of the
+// layout), Q, Za, Zb, Y the unknowns of levels m - 1 .. m + 1 weighted by the
+// quadrature weights of E0, E1^T, E1 and E2 in block (r, l), and A the
+// accelerations weighted by the lumped-mass weights.  (For the boundary row
+// the mass term uses the boundary level's acceleration with the boundary
+// row's adjoint, which equals the identity row's adjoint of the unused level
+// n + 1.)
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                     FactorsDev f, int NS, const double* __restrict__ X,
+                                                     const double* __restrict__ lam,
+                                                     const double* __restrict__ acc_a,
+                                                     double* __restrict__ grad, int s0, int64_t shot_stride) {
+  static_assert(NBT * S <= WT, "one (node, shot) item per lane");
+  constexpr int GCH = 16;
+  __shared__ double V[18][NBT * S];   // the level's per-node quantities, by item
+  __shared__ double C1[NBT * S];      // end-1 parts, by receiving item
+  __shared__ double Gb[GCH][NBT * S]; // gradient per level of the chunk and item
+  const int e = elems[blockIdx.x];
+  const int ns = min(S, NS - s0);
+  const int nb = m.nb[e], n = m.nr[e] - 1;
+  const int64_t po = m.par_off[e], lo = m.loop_off[e], xo = m.x_off[e];
+  const double* W = f.rgw + f.rgw_off[n + 1];
+  const int it = threadIdx.x;
+  const bool own = it < nb * S;
+  const int i = own ? it / S : 0, s = it % S;
+  const bool act = own && s < ns;
+  const int itp = md(i + 1, nb) * S + s;
+  const bool summed = shot_stride == 0;
+  double al[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) al[q] = own ? f.gbasis[32 * (lo + i) + q] : 0.0;
+  auto ldx = [&](int l) -> double {   // unknowns of level l (0 .. n)
+    const bool ok = act && l >= 0 && l <= n;
+    const double v = X[ok ? (xo + (int64_t)(l + 1) * nb + i) * NS + s0 + s : 0];
+    return ok ? v : 0.0;
+  };
+  auto ldl = [&](int r) -> double {   // signed adjoint of Galerkin row r (0 .. n)
+    const bool ok = act && r >= 0 && r <= n;
+    const int fr = r < n ? r : n + 1;
+    const double v = lam[ok ? (xo + (int64_t)(fr + 1) * nb + i) * NS + s0 + s : 0];
+    return ok ? (r < n ? v : -v) : 0.0;
+  };
+  auto lda = [&](int l) -> double {
+    const bool ok = act && l >= 0 && l <= n;
+    const double v = acc_a[ok ? (po + (int64_t)l * nb + i) * NS + s0 + s : 0];
+    return ok ? v : 0.0;
+  };
+  double xa = 0.0, xb = ldx(0), xc = ldx(1);       // levels m - 1, m, m + 1
+  double la = 0.0, lb = ldl(0), lc = ldl(1);       // rows m - 1, m, m + 1
+  double aa = 0.0, ab = lda(0), ac = lda(1);
+  for (int lev = 0; lev <= n; ++lev) {
+    const double px = ldx(lev + 2), pl = ldl(lev + 2), pa = lda(lev + 2);
+    // weights of interval lev - 1 (level lev at its end 1) and interval lev (end 0)
+    const double* wl = W + (int64_t)(lev >= 1 ? lev - 1 : 0) * kRgW;
+    const double* wr = W + (int64_t)(lev < n ? lev : n - 1) * kRgW;
+    const bool hl = lev >= 1, hr = lev < n;
+    auto wL = [&](int o) { return hl ? wl[o] : 0.0; };
+    auto wR = [&](int o) { return hr ? wr[o] : 0.0; };
+    double Qk[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = 8 * k;
+      Qk[k][0] = wL(b + 0 + 0 + 1) * xa + wL(b + 0 + 2 + 1) * xb;
+      Qk[k][1] = wL(b + 4 + 0 + 1) * xa + wL(b + 4 + 2 + 1) * xb + wR(b + 0 + 0 + 0) * xb + wR(b + 0 + 2 + 0) * xc;
+      Qk[k][2] = wR(b + 4 + 0 + 0) * xb + wR(b + 4 + 2 + 0) * xc;
+    }
+    const double Ap[3] = {wL(32 + 0 + 1) * aa, (wL(32 + 2 + 1) + wR(32 + 0 + 0)) * ab, wR(32 + 2 + 0) * ac};
+    const double Lp[3] = {la, lb, lc};
+    if (own) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        V[a][it] = Lp[a];
+        V[3 + a][it] = Qk[0][a];
+        V[6 + a][it] = Qk[1][a];
+        V[9 + a][it] = Qk[2][a];
+        V[12 + a][it] = Qk[3][a];
+        V[15 + a][it] = Ap[a];
+      }
+    }
+    wave_lds_sync();
+    double end0 = 0.0;
+    if (own) {
+      double Lq[3], Qq[3], Zaq[3], Zbq[3], Yq[3], Aq[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        Lq[a] = V[a][itp];
+        Qq[a] = V[3 + a][itp];
+        Zaq[a] = V[6 + a][itp];
+        Zbq[a] = V[9 + a][itp];
+        Yq[a] = V[12 + a][itp];
+        Aq[a] = V[15 + a][itp];
+      }
+      double E0[4] = {0, 0, 0, 0}, E1[4] = {0, 0, 0, 0}, E2[4] = {0, 0, 0, 0}, M0[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        E0[0] += Lp[a] * Qk[0][a]; E0[1] += Lp[a] * Qq[a]; E0[2] += Lq[a] * Qk[0][a]; E0[3] += Lq[a] * Qq[a];
+        E1[0] += Lp[a] * Qk[2][a] + Qk[1][a] * Lp[a];
+        E1[1] += Lp[a] * Zbq[a] + Qk[1][a] * Lq[a];
+        E1[2] += Lq[a] * Qk[2][a] + Zaq[a] * Lp[a];
+        E1[3] += Lq[a] * Zbq[a] + Zaq[a] * Lq[a];
+        E2[0] += Lp[a] * Qk[3][a]; E2[1] += Lp[a] * Yq[a]; E2[2] += Lq[a] * Qk[3][a]; E2[3] += Lq[a] * Yq[a];
+        M0[0] += Lp[a] * Ap[a]; M0[1] += Lp[a] * Aq[a]; M0[2] += Lq[a] * Ap[a]; M0[3] += Lq[a] * Aq[a];
+      }
+      double s0e = 0.0, s1e = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s0e += al[k] * E0[k] + al[8 + k] * E1[k] + al[16 + k] * E2[k] + al[24 + k] * M0[k];
+        s1e += al[4 + k] * E0[k] + al[12 + k] * E1[k] + al[20 + k] * E2[k] + al[28 + k] * M0[k];
+      }
+      end0 = s0e;
+      C1[itp] = s1e;
+    }
+    wave_lds_sync();
+    if (own) Gb[lev % GCH][it] = end0 + C1[it];
+    if (lev % GCH == GCH - 1 || lev == n) {
+      wave_lds_sync();
+      const int l0c = lev - lev % GCH, nl = lev - l0c + 1;
+      if (summed) {
+        for (int q = it; q < nl * nb; q += WT) {
+          const int l = q / nb, k = q % nb;
+          double t = 0.0;
+          for (int u = 0; u < ns; ++u) t += Gb[l][k * S + u];
+          grad[po + (int64_t)(l0c + l) * nb + k] += t;
+        }
+      } else {
+        for (int q = it; q < nl * nb * ns; q += WT) {
+          const int l = q / (nb * ns), r = q % (nb * ns), k = r / ns, u = r % ns;
+          grad[(int64_t)(s0 + u) * shot_stride + po + (int64_t)(l0c + l) * nb + k] += Gb[l][k * S + u];
+        }
+      }
+      wave_lds_sync();
+    }
+    xa = xb; xb = xc; xc = px;
+    la = lb; lb = lc; lc = pl;
+    aa = ab; ab = ac; ac = pa;
+  }
+}
+
 // Paper kernel: g -= dt * sum_s v~ v at every fine-grid point.
 __global__ void grad_paper_kernel(MeshDev m, int NS, double dt, int64_t n_params, const int32_t* __restrict__ par_elem,
                                   const double* __restrict__ vint, const double* __restrict__ Vnod,
@@ -703,9 +851,14 @@ void launch_grad_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, int NS, const
   if (cnt == 0) return;
   // shot groups run one after another on the stream, so every gradient entry
   // has a single writer at a time and the sum over shots is deterministic
-  for (int s0 = 0; s0 < NS; s0 += S)
-    hipLaunchKernelGGL((grad_exact_kernel<NBT, S>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl], m->d,
-                       f, NS, X, lam, acc, grad, s0, stride);
+  for (int s0 = 0; s0 < NS; s0 += S) {
+    if (f.scheme == SBFWI_SCHEME_RADIAL_GALERKIN)
+      hipLaunchKernelGGL((grad_rg_kernel<NBT, S>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl], m->d,
+                         f, NS, X, lam, acc, grad, s0, stride);
+    else
+      hipLaunchKernelGGL((grad_exact_kernel<NBT, S>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl],
+                         m->d, f, NS, X, lam, acc, grad, s0, stride);
+  }
 }
 
 template <int S>

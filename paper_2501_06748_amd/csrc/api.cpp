@@ -116,10 +116,11 @@ extern "C" int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, 
   if (!m || !rho) return sbfwi_fail(SBFWI_EINVAL, "NULL mesh or density");
   if (!(c > 0) || !(dt > 0) || !(beta > 0) || !(gamma > 0))
     return sbfwi_fail(SBFWI_EINVAL, "c, dt, beta and gamma must be positive");
-  if (scheme != SBFWI_SCHEME_PAPER_FD) return sbfwi_fail(SBFWI_EINVAL, "unknown radial scheme %d", scheme);
+  if (scheme != SBFWI_SCHEME_PAPER_FD && scheme != SBFWI_SCHEME_RADIAL_GALERKIN)
+    return sbfwi_fail(SBFWI_EINVAL, "unknown radial scheme %d", scheme);
   if (coarse_solver != 0 && coarse_solver != 1)
     return sbfwi_fail(SBFWI_EINVAL, "unknown coarse solver %d", coarse_solver);
-  return sbfwi_factor_impl(m, rho, c, dt, beta, gamma, coarse_solver, s, out);
+  return sbfwi_factor_impl(m, rho, c, dt, beta, gamma, scheme, coarse_solver, s, out);
 }
 
 extern "C" int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter) {

@@ -14,7 +14,13 @@
 // The radial rows follow the central-difference discretisation of the
 // Newmark-discretised radial equation (eq. ODE_Newmark, eq. FD) with
 // one-sided differences of E0, E1 at the end levels and the two ghost rows of
-// the flux boundary conditions (eq. system).  The elimination is the paper's
+// the flux boundary conditions (eq. system).  The radial Galerkin scheme
+// (scheme 1) replaces them by linear elements in xi with the radial mass
+// lumped, written in the same row layout: the negated Galerkin rows of the
+// interior levels, an identity row for the unused level n + 1 that carries
+// the boundary level's mass source (u_{n+1} = M_n w_n), the boundary row
+// (K_{n,n-1}, K_nn + a0 M_n, -I) and an identity row for the unused level -1;
+// the elimination below then gives G = -I and the Galerkin Schur complement.  The elimination is the paper's
 // block Gauss sweep, organised so that only phi~_j^-1 is stored per level:
 // rho_j = theta_j phi~_{j-1}^-1 is applied as theta_j (phi~_{j-1}^-1 .), which
 // halves the factor storage and lets the same stored block serve the forward
@@ -30,6 +36,8 @@ struct ElemCtx {
   double xi0, h, c2, a0;
   const double* rho;  // element's [N_r][nb] densities (global)
   const double* alpha;  // LDS [4][nb][2][4]
+  int scheme;           // 0 central differences, 1 radial Galerkin
+  const double* rgw;    // Galerkin: weights of the element's intervals [n][kRgW]
 };
 
 __device__ __forceinline__ int md(int i, int nb) { return (i % nb + nb) % nb; }
@@ -69,8 +77,46 @@ __device__ double d_band(const ElemCtx& c, int tau, int j, int t, int i, bool tr
   return (E(j + 1) - E(j - 1)) / (2.0 * c.h);
 }
 
+// Galerkin rows.  Stiffness block (local row p, column q) of interval j and
+// the lumped mass of its local level p, band entry t of row i.
+__device__ double rg_k(const ElemCtx& c, int j, int p, int q, int t, int i) {
+  const double* w = c.rgw + (int64_t)j * kRgW;
+  const int o = 4 * p + 2 * q;
+  double v = 0.0;
+  for (int e = 0; e < 2; ++e) {
+    const int lev = j + e;
+    v += w[o + e] * e_band(c, 0, lev, t, i) + w[8 + o + e] * e_band_T(c, 1, lev, t, i) +
+         w[16 + o + e] * e_band(c, 1, lev, t, i) + w[24 + o + e] * e_band(c, 2, lev, t, i);
+  }
+  return v;
+}
+__device__ double rg_m(const ElemCtx& c, int j, int p, int t, int i) {
+  const double* w = c.rgw + (int64_t)j * kRgW;
+  return w[32 + 2 * p] * e_band(c, 3, j, t, i) + w[33 + 2 * p] * e_band(c, 3, j + 1, t, i);
+}
+
+__device__ double row_band_rg(const ElemCtx& c, int which, int r, int t, int i) {
+  const int n = c.n;
+  const double id = t == 1 ? 1.0 : 0.0;
+  if (r == -1) return which == 0 ? id : 0.0;
+  if (r == n) return which == 2 ? id : (which == 3 ? rg_m(c, n - 1, 1, t, i) : 0.0);
+  if (r == n + 1) {
+    if (which == 0) return rg_k(c, n - 1, 1, 0, t, i);
+    if (which == 1) return rg_k(c, n - 1, 1, 1, t, i) + c.a0 * rg_m(c, n - 1, 1, t, i);
+    return which == 2 ? -id : 0.0;
+  }
+  // interior level r: intervals r - 1 (local level 1) and r (local level 0)
+  if (which == 0) return r >= 1 ? -rg_k(c, r - 1, 1, 0, t, i) : 0.0;
+  if (which == 2) return -rg_k(c, r, 0, 1, t, i);
+  const double m = (r >= 1 ? rg_m(c, r - 1, 1, t, i) : 0.0) + rg_m(c, r, 0, t, i);
+  if (which == 3) return -m;
+  const double k = (r >= 1 ? rg_k(c, r - 1, 1, 1, t, i) : 0.0) + rg_k(c, r, 0, 0, t, i);
+  return -(k + c.a0 * m);
+}
+
 // Band entries of the rows: which = 0 theta, 1 phi, 2 psi, 3 P, for row r = -1 .. n+1.
 __device__ double row_band(const ElemCtx& c, int which, int r, int t, int i) {
+  if (c.scheme == SBFWI_SCHEME_RADIAL_GALERKIN) return row_band_rg(c, which, r, t, i);
   const double h = c.h;
   if (r == -1 || r == c.n + 1) {
     int lev = (r == -1) ? 0 : c.n;
@@ -272,6 +318,8 @@ __global__ void __launch_bounds__(FT) factor_kernel(
   ec.a0 = a0;
   ec.rho = rho + mm.par_off[e];
   ec.alpha = L.alpha;
+  ec.scheme = ff.scheme;
+  ec.rgw = ff.scheme == SBFWI_SCHEME_RADIAL_GALERKIN ? ff.rgw + ff.rgw_off[nr] : nullptr;
   const int64_t po = mm.par_off[e];
   // persistent bands: theta_j, psi_j, P_j for j = 0..n; theta_{n+1}, phi_{-1}, psi_{-1}
   for (int q = threadIdx.x; q < 3 * nb * nr; q += FT) {
@@ -410,14 +458,53 @@ void sbfwi_factors_free(sbfwi_factors_s* f) {
   FactorsDev& d = f->d;
   void* ptrs[] = {d.finv, d.th_band, d.ps_band, d.pm_band, d.th_np1, d.phim1, d.psim1,
                   d.G, d.S, d.psit0, d.psin_inv, d.phit_n, d.thm1_inv, d.gbasis,
-                  d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv, d.status};
+                  d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv, d.status, d.rgw};
+  sbfwi_dev_free(d.rgw_off);
   for (void* p : ptrs) sbfwi_dev_free(p);
   sbfwi_direct_num_free(f->dnum);
   delete f;
 }
 
+void sbfwi_rg_weights(double xi0, const std::vector<int>& level_counts, std::vector<double>& w,
+                      std::vector<int>& off) {
+  // Gauss-Legendre nodes and weights on [-1, 1], 4 points
+  const double gx[4] = {-0.86113631159405257522, -0.33998104358485626480, 0.33998104358485626480,
+                        0.86113631159405257522};
+  const double gw[4] = {0.34785484513745385737, 0.65214515486254614263, 0.65214515486254614263,
+                        0.34785484513745385737};
+  off.assign(129, -1);
+  w.clear();
+  for (int nr : level_counts) {
+    if (nr < 2 || nr > 128 || off[nr] >= 0) continue;
+    off[nr] = (int)w.size();
+    const int n = nr - 1;
+    const double h = (1.0 - xi0) / n;
+    for (int j = 0; j < n; ++j) {
+      const double a = xi0 + h * j, b = a + h;
+      double iv[kRgW] = {};
+      for (int g = 0; g < 4; ++g) {
+        const double x = 0.5 * (a + b) + 0.5 * (b - a) * gx[g], ww = 0.5 * (b - a) * gw[g];
+        const double N[2] = {(b - x) / (b - a), (x - a) / (b - a)};
+        const double dN[2] = {-1.0 / (b - a), 1.0 / (b - a)};
+        for (int p = 0; p < 2; ++p) {
+          for (int q = 0; q < 2; ++q)
+            for (int e = 0; e < 2; ++e) {
+              const int o = 4 * p + 2 * q + e;
+              iv[o] += ww * x * dN[p] * dN[q] * N[e];
+              iv[8 + o] += ww * dN[p] * N[q] * N[e];
+              iv[16 + o] += ww * N[p] * dN[q] * N[e];
+              iv[24 + o] += ww * N[p] * N[q] * N[e] / x;
+            }
+          for (int e = 0; e < 2; ++e) iv[32 + 2 * p + e] += ww * x * N[p] * N[e];
+        }
+      }
+      w.insert(w.end(), iv, iv + kRgW);
+    }
+  }
+}
+
 int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, double beta,
-                      double gamma, int coarse_solver, hipStream_t s, sbfwi_factors_s** out) {
+                      double gamma, int scheme, int coarse_solver, hipStream_t s, sbfwi_factors_s** out) {
   sbfwi_factors_s* f = new sbfwi_factors_s();
   f->m = m;
   f->c = c;
@@ -432,6 +519,8 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   d.c2 = 1.0 - gamma / beta;
   d.c3 = dt * (1.0 - gamma / (2.0 * beta));
   d.dt = dt;
+  d.scheme = scheme;
+  f->scheme = scheme;
   int rc = SBFWI_OK;
   auto A = [&](double** p, int64_t n) {
     if (rc == SBFWI_OK) {
@@ -459,6 +548,14 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   A(&d.KTell, m->d.n_ell);
   A(&d.diag_inv, m->n_nodes);
   if (rc == SBFWI_OK) rc = sbfwi_alloc(&d.status, 8);
+  if (rc == SBFWI_OK && scheme == SBFWI_SCHEME_RADIAL_GALERKIN) {
+    std::vector<double> w;
+    std::vector<int> off;
+    sbfwi_rg_weights(m->xi0, m->h_nr, w, off);
+    rc = sbfwi_upload(&d.rgw, w);
+    if (rc == SBFWI_OK) rc = sbfwi_upload(&d.rgw_off, off);
+    f->bytes += (int64_t)w.size() * 8 + (int64_t)off.size() * 4;
+  }
   if (rc != SBFWI_OK) {
     sbfwi_factors_free(f);
     return rc;

@@ -150,7 +150,24 @@ struct FactorsDev {
   double* KTell = nullptr;     // [n_ell] K_g^T in the sliced ELL layout
   double* diag_inv = nullptr;  // [n_nodes] Jacobi preconditioner
   int* status = nullptr;       // device status words
+  // radial Galerkin scheme: quadrature weights of every interval, by level count
+  int scheme = 0;
+  double* rgw = nullptr;       // [sum over level counts of (N_r - 1) * kRgW] weights
+  int* rgw_off = nullptr;      // [129] offset of the table of N_r levels (in doubles)
 };
+
+// Weights of one radial interval [xi_j, xi_j + h] in the Galerkin scheme, for
+// local levels p, q in {0, 1} (row, column) and interpolation end e in {0, 1}:
+//   [0 + 4p + 2q + e]  int xi N_p' N_q' N_e          (E0)
+//   [8 + 4p + 2q + e]  int N_p' N_q N_e              (E1^T)
+//   [16 + 4p + 2q + e] int N_p N_q' N_e              (E1)
+//   [24 + 4p + 2q + e] int N_p N_q N_e / xi          (E2)
+//   [32 + 2p + e]      int xi N_p N_e                (lumped M0)
+constexpr int kRgW = 36;
+// Gauss-Legendre quadrature (4 points per interval) of the weights above for
+// every level count present in the mesh; rgw_off[N_r] = -1 for absent counts.
+void sbfwi_rg_weights(double xi0, const std::vector<int>& level_counts, std::vector<double>& w,
+                      std::vector<int>& off);
 
 // Launch plan of the sweep kernels: shots per block (1, 2, 4, 8 or 16) for each
 // n_b class (n_b <= 8, <= 16, <= 24) of each sweep, or (fusedS > 0) one
@@ -173,6 +190,7 @@ struct sbfwi_factors_s {
   int use_graphs = 0;            // forward runs replay each time step from HIP graphs
   int overlap_adjoint = 1;       // recompute the next checkpoint segment while the adjoint runs the current one
   int keep_solutions = 1;        // forward runs with checkpoints keep every step's coarse solution
+  int scheme = 0;                // radial scheme (SBFWI_SCHEME_*)
   SweepPlan plan;
   DirectNum* dnum = nullptr;     // direct factors of K_g (coarse solver 1), else BiCGStab
   int64_t bytes = 0;
@@ -256,7 +274,7 @@ static inline int sbfwi_upload(T** p, const std::vector<T>& v) {
 
 // ---- stage entry points (factor.hip, step.hip, coarse.hip, adjoint.hip) ----
 int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, double beta,
-                      double gamma, int coarse_solver, hipStream_t s, sbfwi_factors_s** out);
+                      double gamma, int scheme, int coarse_solver, hipStream_t s, sbfwi_factors_s** out);
 
 struct CoarseWork {
   int NS = 0;

@@ -21,7 +21,7 @@ def rel_l2(a, b):
 class GpuModel:
     """Mesh + factors of a workload model on cuda:0."""
 
-    def __init__(self, wl, rho, dt=None, coarse_solver=0):
+    def __init__(self, wl, rho, dt=None, coarse_solver=0, scheme=0):
         import torch
         import paper_2501_06748_amd as sb
         self.sb, self.torch, self.wl = sb, torch, wl
@@ -29,7 +29,7 @@ class GpuModel:
         self.dt = wl.dt if dt is None else dt
         self.mesh = sb.sbfwi_build_mesh(m.node_xy, m.elem_ptr, m.elem_nodes, m.n_r, xi0=wl.xi0)
         self.rho = torch.tensor(np.asarray(rho), dtype=torch.float64, device="cuda")
-        self.f = sb.sbfwi_factor_elements(self.mesh, self.rho, wl.c, self.dt, wl.beta, wl.gamma,
+        self.f = sb.sbfwi_factor_elements(self.mesh, self.rho, wl.c, self.dt, wl.beta, wl.gamma, scheme=scheme,
                                           coarse_solver=coarse_solver)
         self.info = sb.sbfwi_mesh_info(self.mesh)
 

@@ -72,13 +72,13 @@ def test_backward_equals_library_gradient_and_oracle(coarse_solver):
     g_lib = torch.zeros_like(rho)
     sb.sbfwi_gradient(f, ck, obs, tr, sb.GRAD_EXACT, mis, g_lib)
     torch.cuda.synchronize()
-    assert val == pytest.approx(float(mis.item()), rel=1e-12)
+    assert val == pytest.approx(float(mis.item()), rel=1e-12, abs=0)
     assert rel_l2(g.cpu().numpy(), g_lib.cpu().numpy()) <= 1e-12
     om = ostp.Model(wl.mesh, wl.models["random30"], wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0)
     gref, Jref = oadj.exact_gradient(om, wl.src_nodes, wl.wavelets[:, :48], wl.rec_nodes, obs.cpu().numpy(), 48)
     err = rel_l2(g.cpu().numpy(), gref)
     log(f"  misfit {val:.6e} vs oracle {Jref:.6e}; gradient relative L2 vs oracle {err:.3e}")
-    assert val == pytest.approx(Jref, rel=1e-10)
+    assert val == pytest.approx(Jref, rel=1e-10, abs=0)
     assert err <= 1e-8
 
 

@@ -46,7 +46,7 @@ def test_direct_gradient_parity_and_multishot(shots):
     gref, Jref = oadj.exact_gradient(om, wl.src_nodes, wl.wavelets, wl.rec_nodes, obs, 24)
     err = rel_l2(grad, gref)
     log(f"direct exact gradient parity ({shots} shots): {err:.3e}")
-    assert mis == pytest.approx(Jref, rel=1e-10)
+    assert mis == pytest.approx(Jref, rel=1e-10, abs=0)
     assert err <= 1e-8
 
 

@@ -116,7 +116,7 @@ def test_exact_gradient_parity(ckpt):
     gref, Jref = oadj.exact_gradient(om, wl.src_nodes, wl.wavelets[:, :steps], wl.rec_nodes, obs, steps)
     err = rel_l2(grad, gref)
     log(f"  misfit {mis:.6e} vs {Jref:.6e}; gradient relative L2 = {err:.3e}")
-    assert mis == pytest.approx(Jref, rel=1e-10)
+    assert mis == pytest.approx(Jref, rel=1e-10, abs=0)
     assert err <= 1e-8
 
 
