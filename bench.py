@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--coarse-solver", type=int, default=1,
                     help="0: BiCGStab every step; 1: nested-dissection LU factored once per model (default)")
+    ap.add_argument("--scheme", type=int, default=0,
+                    help="radial scheme: 0 the paper's finite differences (default), 1 radial Galerkin")
     ap.add_argument("--graphs", type=int, default=0,
                     help="1: forward steps replayed from HIP graphs (their launches are then not seen by the "
                          "live kernel timing)")
@@ -218,7 +220,8 @@ def main():
         sb.sbfwi_fem_forward(fg.nx, fg.ny, fg.lx, fg.ly, f_rho, wl.c, wl.dt, f_src, wav, f_rec, observed)
 
     def factor(rho):
-        f = sb.sbfwi_factor_elements(mh, rho, wl.c, wl.dt, wl.beta, wl.gamma, coarse_solver=args.coarse_solver)
+        f = sb.sbfwi_factor_elements(mh, rho, wl.c, wl.dt, wl.beta, wl.gamma, scheme=args.scheme,
+                                     coarse_solver=args.coarse_solver)
         if args.solver_iters:
             sb.sbfwi_set_launch(f, 0, args.solver_iters)
         if args.graphs:
@@ -383,6 +386,7 @@ def main():
                    else "BiCGStab, rtol 1e-13",
                    "graphs": bool(args.graphs), "launch_plan": "autotuned" if plan is not None else "default",
                    "overlapped_backward": bool(args.overlap),
+                   "scheme": "radial Galerkin" if args.scheme == 1 else "paper finite differences",
                    "units_per_step": units},
         "roofline": roof,
         "kernel_ms_per_step_warmup": breakdown,

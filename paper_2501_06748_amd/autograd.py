@@ -35,7 +35,8 @@ class WaveProblem:
     rec [R] int64; n_ckpt as in sbfwi_forward (-1 = sqrt(T) checkpoints,
     >= N_t = full storage); mode: GRAD_EXACT or GRAD_PAPER_KERNEL; rtol: relative
     residual of the iterative coarse solves (the library default 1e-13 when None);
-    coarse_solver: 1 = direct (factored once per model), 0 = BiCGStab."""
+    coarse_solver: 1 = direct (factored once per model), 0 = BiCGStab;
+    scheme: SCHEME_PAPER_FD (0) or SCHEME_RADIAL_GALERKIN (1)."""
     mesh: object
     c: float
     dt: float
@@ -48,6 +49,7 @@ class WaveProblem:
     mode: int = GRAD_EXACT
     rtol: float = None
     coarse_solver: int = 1
+    scheme: int = 0
 
     @property
     def n_params(self) -> int:
@@ -62,7 +64,7 @@ class _Traces(torch.autograd.Function):
     def forward(ctx, rho, prob):
         rho_d = rho.detach().contiguous()
         f = sbfwi_factor_elements(prob.mesh, rho_d, prob.c, prob.dt, prob.beta, prob.gamma,
-                                  coarse_solver=prob.coarse_solver)
+                                  scheme=prob.scheme, coarse_solver=prob.coarse_solver)
         if prob.rtol is not None:
             sbfwi_set_solver(f, prob.rtol, 500)
         traces = torch.zeros(prob.trace_shape(), dtype=torch.float64, device=rho.device)

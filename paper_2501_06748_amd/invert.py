@@ -62,6 +62,7 @@ def main(argv=None):
     ap.add_argument("--check-rtol", type=float, default=1e-15)
     ap.add_argument("--coarse-solver", type=int, default=1)
     ap.add_argument("--data", choices=["fem", "sbfem"], default="fem")
+    ap.add_argument("--scheme", type=int, default=0, help="0: the paper's radial finite differences; 1: radial Galerkin")
     args = ap.parse_args(argv)
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -78,13 +79,15 @@ def main(argv=None):
                            wavelet=torch.tensor(np.ascontiguousarray(wl.wavelets[:, :nt]), dtype=torch.float64,
                                                 device=dev),
                            rec=torch.tensor(wl.rec_nodes, dtype=torch.int64, device=dev),
-                           beta=wl.beta, gamma=wl.gamma, n_ckpt=n_ckpt, coarse_solver=args.coarse_solver)
+                           beta=wl.beta, gamma=wl.gamma, n_ckpt=n_ckpt, coarse_solver=args.coarse_solver,
+                           scheme=args.scheme)
 
     prob = problem(args.nt)
     rho0 = float(wl.rho0)
     rho_h = torch.full((m.n_params,), rho0, dtype=torch.float64, device=dev)
     out = {"workload": wl.name, "time_steps": args.nt, "shots": args.shots, "n_params": int(m.n_params),
-           "coarse_solver": "direct" if args.coarse_solver == 1 else "bicgstab"}
+           "coarse_solver": "direct" if args.coarse_solver == 1 else "bicgstab",
+           "scheme": "radial Galerkin" if args.scheme == 1 else "paper finite differences"}
 
     t0 = time.perf_counter()
     if args.data == "fem":
