@@ -13,17 +13,19 @@ meshes are not available, so plates of the same scale (centimetres, 500 kHz,
 rho0 = 2700 kg/m^3) with seeded voids and smooth fields are used instead.
 """
 
-from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, nearest_top_node
+from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, nearest_top_node, cvt_mesh, edge_nodes
 from .models import (fine_point_positions, homogeneous, smoothed_voids, sharp_voids,
                      smooth_random_field, seeded_ellipses, seeded_circle)
 from .fem_grid import FemGrid, fem_grid, fem_nodes, fem_density
 from .signals import ricker, sine_burst
-from .configs import config_tiny, config_paper, config_small, config_quadtree_tiny, config_quadtree, Workload
+from .configs import (config_tiny, config_paper, config_small, config_quadtree_tiny, config_quadtree, config_cvt,
+                      Workload)
 
 __all__ = [
-    "Mesh", "uniform_rect_mesh", "quadtree_mesh", "top_edge_nodes", "nearest_top_node",
+    "Mesh", "uniform_rect_mesh", "quadtree_mesh", "top_edge_nodes", "nearest_top_node", "cvt_mesh", "edge_nodes",
     "fine_point_positions", "homogeneous", "smoothed_voids", "sharp_voids", "smooth_random_field",
     "FemGrid", "fem_grid", "fem_nodes", "fem_density",
     "seeded_ellipses", "seeded_circle", "ricker", "sine_burst",
-    "config_tiny", "config_paper", "config_small", "config_quadtree_tiny", "config_quadtree", "Workload",
+    "config_tiny", "config_paper", "config_small", "config_quadtree_tiny", "config_quadtree", "config_cvt",
+    "Workload",
 ]

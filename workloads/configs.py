@@ -8,6 +8,13 @@
   edge.
 * ``config_small``  -- a reduced plate used by parity tests at sizes that
   span several tiles and a ragged tail.
+* ``config_cvt``    -- the workload shape of the paper's timing tables:
+  centroidal Voronoi polygons (1000 .. 8000 cells) with 5 or 7 radial
+  intervals, c = 6000 m/s, dt = 0.2 us, 200 steps, two 2-cycle 500 kHz sine
+  bursts 30 mm apart at the middle of the top edge, receivers at a 1 mm pitch
+  along all four edges (nearest boundary nodes); the plate is 0.1 x 0.05 m
+  (the paper's specimen drawing is not available) with a central circular
+  hole of 5 mm radius in its models.
 * ``config_quadtree`` -- the 0.1 x 0.05 m plate as a quadtree refined from
   level 4 (3.125 mm cells) to level 8 around three seeded voids: about 6200
   elements with hanging nodes (n_b 8 .. 14), N_r proportional to the cell
@@ -28,10 +35,10 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, nearest_top_node
+from .meshes import Mesh, uniform_rect_mesh, quadtree_mesh, top_edge_nodes, nearest_top_node, cvt_mesh, edge_nodes
 from .models import (fine_point_positions, homogeneous, smoothed_voids, smooth_random_field,
                      seeded_circle, seeded_ellipses, sharp_voids)
-from .signals import ricker
+from .signals import ricker, sine_burst
 
 
 @dataclass
@@ -126,6 +133,37 @@ def config_small(nx: int = 12, ny: int = 6, segs: int = 3, n_r: int = 12, n_step
     models = {k: f(pts) for k, f in fields.items()}
     return Workload(f"small-{nx}x{ny}-nb{4*segs}-nr{n_r}", mesh, 3000.0, 2700.0, dt, n_steps,
                     src, wav, rec, models, fields=fields, fem_cells=(nx * 2 * segs, ny * 2 * segs))
+
+
+def config_cvt(n_cells: int = 8000, intervals: int = 7, n_steps: int = 200, lloyd_iters: int = 30,
+               mesh: Mesh | None = None) -> Workload:
+    """Polygon (CVT) plate in the shape of the paper's timing tables (``mesh``: reuse
+    the cells of an earlier call, with ``intervals + 1`` levels)."""
+    lx, ly = 0.1, 0.05
+    if mesh is None:
+        mesh = cvt_mesh(lx, ly, n_cells, intervals + 1, seed=4 * 1000 + n_cells, lloyd_iters=lloyd_iters)
+    else:
+        mesh = Mesh(mesh.node_xy, mesh.elem_ptr, mesh.elem_nodes, np.full(mesh.n_elem, intervals + 1, dtype=np.int32),
+                    mesh.extent, dict(mesh.meta))
+    src = np.asarray([nearest_top_node(mesh, 0.035), nearest_top_node(mesh, 0.065)], dtype=np.int64)
+    dt, f0 = 2e-7, 5e5
+    wav = np.repeat(sine_burst(n_steps, dt, f0, 2, 1e12)[None, :], 2, axis=0)
+    bnd = edge_nodes(mesh)
+    bxy = mesh.node_xy[bnd]
+    marks = [(x, y) for x in np.arange(0.0005, lx, 0.001) for y in (0.0, ly)] + \
+            [(x, y) for y in np.arange(0.0005, ly, 0.001) for x in (0.0, lx)]
+    rec = np.unique([bnd[np.argmin(np.hypot(bxy[:, 0] - x, bxy[:, 1] - y))] for (x, y) in marks]).astype(np.int64)
+    pts = fine_point_positions(mesh)
+    hole = [(lx / 2, ly / 2, 0.005, 0.005, 0.0)]
+    h = np.sqrt(lx * ly / n_cells)
+    fields = {
+        "homogeneous": lambda p: np.full(p.shape[0], 2700.0),
+        "hole_floor_half": lambda p: smoothed_voids(p, hole, 2700.0, 0.5, h / 4),
+        "hole_data": lambda p: sharp_voids(p, hole, 2700.0, 1e-5),
+    }
+    models = {k: fields[k](pts) for k in fields}
+    return Workload(f"cvt-{n_cells}-{intervals}i", mesh, 6000.0, 2700.0, dt, n_steps, src, wav, rec, models,
+                    fields=fields, f0=f0)
 
 
 def config_quadtree_tiny(n_steps: int = 40) -> Workload:

@@ -200,3 +200,112 @@ def top_edge_nodes(mesh: Mesh) -> np.ndarray:
 def nearest_top_node(mesh: Mesh, x: float) -> int:
     top = top_edge_nodes(mesh)
     return int(top[np.argmin(np.abs(mesh.node_xy[top, 0] - x))])
+
+
+def _bounded_voronoi(pts: np.ndarray, lx: float, ly: float):
+    """Voronoi cells of ``pts`` clipped to [0,lx]x[0,ly] (by mirroring the
+    generators across the four edges): (vertices, list of vertex-index loops)."""
+    from scipy.spatial import Voronoi
+    mir = [pts, np.c_[-pts[:, 0], pts[:, 1]], np.c_[2 * lx - pts[:, 0], pts[:, 1]],
+           np.c_[pts[:, 0], -pts[:, 1]], np.c_[pts[:, 0], 2 * ly - pts[:, 1]]]
+    vor = Voronoi(np.concatenate(mir))
+    loops = []
+    for i in range(pts.shape[0]):
+        reg = vor.regions[vor.point_region[i]]
+        if -1 in reg or len(reg) < 3:
+            raise RuntimeError("unbounded Voronoi cell")
+        loops.append(list(reg))
+    return vor.vertices, loops
+
+
+def cvt_mesh(lx: float, ly: float, n_cells: int, n_r: int, seed: int, lloyd_iters: int = 40,
+             merge_frac: float = 0.1) -> Mesh:
+    """Centroidal Voronoi tessellation of [0,lx]x[0,ly] with ``n_cells`` polygons.
+
+    Seeded uniform generators are moved ``lloyd_iters`` times to the centroids
+    of their (boundary-clipped) Voronoi cells.  Vertices closer than
+    ``merge_frac`` times the mean cell size are merged (short edges make
+    ill-conditioned segments), vertices on the plate's edges are snapped onto
+    them, and every loop is ordered counter-clockwise; each cell edge is one
+    straight segment, so n_b is the cell's vertex count.
+    """
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform([0.0, 0.0], [lx, ly], size=(n_cells, 2))
+    for _ in range(lloyd_iters):
+        verts, loops = _bounded_voronoi(pts, lx, ly)
+        for i, lp in enumerate(loops):
+            xy = verts[lp]
+            ctr = xy.mean(axis=0)
+            order = np.argsort(np.arctan2(xy[:, 1] - ctr[1], xy[:, 0] - ctr[0]))
+            xy = xy[order]
+            x, y = xy[:, 0], xy[:, 1]
+            xn, yn = np.roll(x, -1), np.roll(y, -1)
+            cr = x * yn - xn * y
+            a = cr.sum() / 2.0
+            pts[i] = [((x + xn) * cr).sum() / (6 * a), ((y + yn) * cr).sum() / (6 * a)]
+    verts, loops = _bounded_voronoi(pts, lx, ly)
+    used = sorted({v for lp in loops for v in lp})
+    V = verts[used].copy()
+    remap = {v: k for k, v in enumerate(used)}
+    loops = [[remap[v] for v in lp] for lp in loops]
+    tol = 1e-9 * max(lx, ly)
+    for d, L in ((0, lx), (1, ly)):
+        V[np.abs(V[:, d]) <= tol, d] = 0.0
+        V[np.abs(V[:, d] - L) <= tol, d] = L
+    # merge close vertices (union-find), preferring vertices on the plate's edges
+    h = np.sqrt(lx * ly / n_cells)
+    parent = list(range(V.shape[0]))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    on_edge = lambda k: V[k, 0] in (0.0, lx) or V[k, 1] in (0.0, ly)
+    corner = lambda k: V[k, 0] in (0.0, lx) and V[k, 1] in (0.0, ly)
+    for lp in loops:
+        for a, b in zip(lp, lp[1:] + lp[:1]):
+            if np.hypot(*(V[a] - V[b])) < merge_frac * h:
+                ra, rb = find(a), find(b)
+                if ra == rb:
+                    continue
+                if corner(rb) or (on_edge(rb) and not corner(ra) and not on_edge(ra)):
+                    ra, rb = rb, ra
+                if corner(rb) and corner(ra):
+                    continue
+                if on_edge(ra) and on_edge(rb) and not (V[ra, 0] == V[rb, 0] or V[ra, 1] == V[rb, 1]):
+                    continue
+                parent[rb] = ra
+    root = [find(k) for k in range(V.shape[0])]
+    keep = sorted(set(root))
+    newid = {r: k for k, r in enumerate(keep)}
+    node_xy = V[keep]
+    out = []
+    for lp in loops:
+        ids = []
+        for v in lp:
+            k = newid[root[v]]
+            if not ids or ids[-1] != k:
+                ids.append(k)
+        while len(ids) > 1 and ids[0] == ids[-1]:
+            ids.pop()
+        xy = node_xy[ids]
+        ctr = xy.mean(axis=0)
+        order = np.argsort(np.arctan2(xy[:, 1] - ctr[1], xy[:, 0] - ctr[0]))
+        out.append([ids[o] for o in order])
+    elem_ptr = np.zeros(len(out) + 1, dtype=np.int64)
+    elem_ptr[1:] = np.cumsum([len(l) for l in out])
+    elem_nodes = np.asarray([n for l in out for n in l], dtype=np.int64)
+    return Mesh(node_xy=node_xy, elem_ptr=elem_ptr, elem_nodes=elem_nodes,
+                n_r=np.full(len(out), n_r, dtype=np.int32), extent=(lx, ly),
+                meta={"kind": "cvt", "n_cells": n_cells, "seed": seed})
+
+
+def edge_nodes(mesh: Mesh) -> np.ndarray:
+    """Global ids of the nodes on the plate's outer boundary."""
+    lx, ly = mesh.extent
+    x, y = mesh.node_xy[:, 0], mesh.node_xy[:, 1]
+    tol = 1e-12 * max(lx, ly)
+    on = (np.abs(x) <= tol) | (np.abs(x - lx) <= tol) | (np.abs(y) <= tol) | (np.abs(y - ly) <= tol)
+    return np.nonzero(on)[0].astype(np.int64)
