@@ -24,7 +24,8 @@ Modules
               solves of the uncondensed block system by block elimination)
               and the paper's truncated zero-lag kernel.
 ``lfe``       conventional SBFEM by low-frequency expansion (Riccati +
-              Lyapunov) for radially constant density.
+              Lyapunov) for radially constant density, and the time-domain
+              path over element K, M from the radial condensation.
 ``stability`` step-map spectrum of the coupled discrete system (gate for
               models on which the radial finite-difference scheme is stable).
 ``radial_galerkin`` linear radial elements for one element, assembled

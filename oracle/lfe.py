@@ -36,3 +36,90 @@ def lfe_stiffness(E0, E1, E2):
 def lfe_mass(K, E0, E1, M0):
     A = (K - E1) @ np.linalg.inv(E0) + np.eye(K.shape[0])
     return sla.solve_continuous_lyapunov(A, M0)
+
+
+# ---------------------------------------------------------------------------
+# The conventional (low-frequency expansion) time-domain path.
+#
+# For density that does not vary along xi (the boundary values of every
+# element, as in eq. simplified) each element contributes a stiffness K_e and
+# a mass M_e on its boundary nodes only; the global system K U + M U'' = F is
+# stepped with the same Newmark scheme (eq. Newmark).  The K_e, M_e used here
+# are those of linear radial elements condensed onto the boundary level:
+# K_e the static Schur complement, M_e the radial mass seen through the
+# static modes.  They converge to the Riccati and Lyapunov solutions above as
+# the radial levels refine (O(h^2)); the tests pin that convergence.
+# ---------------------------------------------------------------------------
+
+from . import radial_galerkin as _rg
+from .element import coefficient_matrices as _coeffs, polygon_centroid as _centroid, radial_levels as _levels
+
+
+def condensed_matrices(E0, E1, E2, M0, xi, n_quad=4):
+    """K and M of one element with radially constant E0, E1, E2, M0 [n_b, n_b]
+    on the radial levels xi."""
+    n_r, nb = len(xi), E0.shape[0]
+    Er = [np.broadcast_to(E, (n_r,) + E.shape) for E in (E0, E1, E2, M0)]
+    K, M = _rg.galerkin_matrices(*Er, xi, n_quad, lumped=True)
+    I = np.arange(0, (n_r - 1) * nb)
+    B = np.arange((n_r - 1) * nb, n_r * nb)
+    X = np.linalg.solve(K[np.ix_(I, I)], K[np.ix_(I, B)])
+    Kc = K[np.ix_(B, B)] - K[np.ix_(B, I)] @ X
+    Phi = np.concatenate([-X, np.eye(nb)], axis=0)
+    Mc = Phi.T @ M @ Phi
+    return Kc, Mc
+
+
+class LfeModel:
+    """Assembled K, M of the low-frequency expansion path and the LU of K + a0 M.
+
+    rho_flat is the fine-grid density; only each element's boundary level
+    (level N_r - 1) is used.  The element's N_r sets the radial resolution of
+    the condensation."""
+
+    def __init__(self, mesh, rho_flat, c, dt, beta=0.25, gamma=0.5, xi0=1e-3):
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        from .stepper import Newmark
+        self.mesh, self.nm = mesh, Newmark(dt, beta, gamma)
+        offs = mesh.param_offsets()
+        rows, cols, kv, mv = [], [], [], []
+        self.Ke, self.Me = [], []
+        for e in range(mesh.n_elem):
+            lp = mesh.loop(e)
+            nb, nr = len(lp), int(mesh.n_r[e])
+            xy = mesh.node_xy[lp][None]
+            rb = np.asarray(rho_flat[offs[e]:offs[e + 1]]).reshape(nr, nb)[nr - 1][None, None]
+            E0, E1, E2, M0 = [E[0, 0] for E in _coeffs(xy, _centroid(xy), rb, c)]
+            xi, _ = _levels(nr, xi0)
+            Ke, Me = condensed_matrices(E0, E1, E2, M0, xi)
+            self.Ke.append(Ke)
+            self.Me.append(Me)
+            rows.append(np.repeat(lp, nb))
+            cols.append(np.tile(lp, nb))
+            kv.append(Ke.ravel())
+            mv.append(Me.ravel())
+        shape = (mesh.n_nodes, mesh.n_nodes)
+        r, cc = np.concatenate(rows), np.concatenate(cols)
+        self.K = sp.coo_matrix((np.concatenate(kv), (r, cc)), shape=shape).tocsc()
+        self.M = sp.coo_matrix((np.concatenate(mv), (r, cc)), shape=shape).tocsc()
+        self.lu = spla.splu((self.K + self.nm.a0 * self.M).tocsc())
+
+
+def lfe_forward(model: LfeModel, src_nodes, wavelets, rec_nodes, n_steps):
+    """Traces [n_shots, n_rec, n_steps] of the Newmark loop on K U + M U'' = F
+    (force sample k - 1 at step k, zero initial state)."""
+    nm, n = model.nm, model.mesh.n_nodes
+    out = np.zeros((len(src_nodes), len(rec_nodes), n_steps))
+    for s in range(len(src_nodes)):
+        U, V, A = np.zeros(n), np.zeros(n), np.zeros(n)
+        for k in range(1, n_steps + 1):
+            W = nm.a0 * U + nm.a1 * V + nm.a2 * A
+            F = model.M @ W
+            F[src_nodes[s]] += wavelets[s][k - 1]
+            Un = model.lu.solve(F)
+            V = nm.c1 * (Un - U) + nm.c2 * V + nm.c3 * A
+            A = nm.a0 * Un - W
+            U = Un
+            out[s, :, k - 1] = U[rec_nodes]
+    return out

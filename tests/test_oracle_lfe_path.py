@@ -1,0 +1,87 @@
+"""Pins of the low-frequency expansion time-domain path (``oracle.lfe``).
+
+* the element K, M from the radial condensation converge to the Riccati and
+  Lyapunov solutions (the textbook eigenvalue method and SciPy's Lyapunov
+  solver) at second order as the radial levels refine, on a square and on a
+  Voronoi polygon;
+* K is symmetric with the constants in its null space; M is symmetric
+  positive definite and carries the element's mass between xi0 and the
+  boundary, 1^T M 1 = (1 - xi0^2) / 2 * 1^T M0 1;
+* the assembled Newmark loop conserves 1/2 V^T M V + 1/2 U^T K U to rounding
+  once the source has stopped.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import element as el
+from oracle import lfe
+
+
+def _elem(kind):
+    if kind == "square":
+        m = W.uniform_rect_mesh(0.004, 0.004, 1, 1, segs=2, n_r=3)
+    else:
+        m = W.cvt_mesh(0.01, 0.01, 9, 3, seed=2, lloyd_iters=20)
+    lp = m.loop(4 if kind != "square" else 0)
+    xy = m.node_xy[lp][None]
+    rho = np.full((1, 1, len(lp)), 2700.0)
+    rho[0, 0, 1] = 1800.0
+    E = [x[0, 0] for x in el.coefficient_matrices(xy, el.polygon_centroid(xy), rho, 3000.0)]
+    return xy[0], E
+
+
+@pytest.mark.parametrize("kind", ["square", "polygon"])
+def test_condensed_matrices_converge_to_riccati_and_lyapunov(kind):
+    xy, (E0, E1, E2, M0) = _elem(kind)
+    K_ref, _ = lfe.lfe_stiffness(E0, E1, E2)
+    M_ref = lfe.lfe_mass(K_ref, E0, E1, M0)
+    ek, em = [], []
+    for nr in (9, 17, 33):
+        xi, _ = el.radial_levels(nr, 1e-3)
+        K, M = lfe.condensed_matrices(E0, E1, E2, M0, xi)
+        ek.append(np.abs(K - K_ref).max() / np.abs(K_ref).max())
+        em.append(np.abs(M - M_ref).max() / np.abs(M_ref).max())
+    assert ek[2] < 1e-3 and em[2] < 1e-3, (ek, em)
+    assert ek[1] < 0.4 * ek[0] and ek[2] < 0.4 * ek[1], ek
+    assert em[1] < 0.4 * em[0] and em[2] < 0.4 * em[1], em
+
+
+def test_condensed_matrices_invariants():
+    xy, (E0, E1, E2, M0) = _elem("polygon")
+    xi, _ = el.radial_levels(12, 1e-3)
+    K, M = lfe.condensed_matrices(E0, E1, E2, M0, xi)
+    assert np.abs(K - K.T).max() <= 1e-12 * np.abs(K).max()
+    assert np.abs(K @ np.ones(len(K))).max() <= 1e-10 * np.abs(K).max()
+    assert np.abs(M - M.T).max() <= 1e-12 * np.abs(M).max()
+    assert np.linalg.eigvalsh(M).min() > 0
+    # 1^T M 1 = integral of rho over the element between xi0 and 1: (1 - xi0^2) / 2 * 1^T M0 1
+    np.testing.assert_allclose(M.sum(), 0.5 * (1.0 - 1e-3 ** 2) * M0.sum(), rtol=1e-12)
+
+
+def test_lfe_loop_conserves_energy():
+    mesh = W.cvt_mesh(0.01, 0.01, 12, 10, seed=4, lloyd_iters=20)
+    pts = W.fine_point_positions(mesh)
+    rho = W.smooth_random_field(pts, 9, 2700.0, 0.3, wavelength=0.006)
+    dt = 1e-7
+    model = lfe.LfeModel(mesh, rho, 3000.0, dt)
+    nm = model.nm
+    src = W.nearest_top_node(mesh, 0.005)
+    wav = W.ricker(30, dt, 5e5, t0=1e-6)
+    n = mesh.n_nodes
+    U, V, A = np.zeros(n), np.zeros(n), np.zeros(n)
+    energies = []
+    for k in range(1, 231):
+        Wv = nm.a0 * U + nm.a1 * V + nm.a2 * A
+        F = model.M @ Wv
+        if k <= 30:
+            F[src] += wav[k - 1]
+        Un = model.lu.solve(F)
+        V = nm.c1 * (Un - U) + nm.c2 * V + nm.c3 * A
+        A = nm.a0 * Un - Wv
+        U = Un
+        if k > 30:
+            energies.append(0.5 * V @ (model.M @ V) + 0.5 * U @ (model.K @ U))
+    energies = np.asarray(energies)
+    assert energies[0] > 0 and np.abs(energies - energies[0]).max() <= 1e-11 * energies[0]
