@@ -50,7 +50,7 @@ enum {
   SBFWI_EHIP = -7         /* a HIP runtime call failed                                        */
 };
 
-enum { SBFWI_SCHEME_PAPER_FD = 0, SBFWI_SCHEME_RADIAL_GALERKIN = 1 };
+enum { SBFWI_SCHEME_PAPER_FD = 0, SBFWI_SCHEME_RADIAL_GALERKIN = 1, SBFWI_SCHEME_LFE = 2 };
 enum { SBFWI_GRAD_EXACT = 0, SBFWI_GRAD_PAPER_KERNEL = 1 };
 /* Flag OR-ed into the gradient mode: one gradient (and one misfit) per shot. */
 enum { SBFWI_GRAD_PER_SHOT = 16 };
@@ -117,6 +117,16 @@ int sbfwi_mesh_info(sbfwi_mesh m, int64_t* host_out);
  *           such as voids at a 1e-5 density floor).  Both schemes share the
  *           layout of the factors and every per-step call; the exact gradient
  *           differentiates the scheme that was factored.
+ *           SBFWI_SCHEME_LFE: the conventional path of the paper's benchmark
+ *           (Section "Low-frequency expansion", eq. simplified and eq. S):
+ *           radially constant density (each element's boundary-level values,
+ *           the other levels are ignored), element stiffness K_e and mass M_e
+ *           on the boundary nodes only, computed as the static condensation
+ *           of the element's N_r Galerkin levels (K_e) and the radial mass
+ *           seen through its static modes (M_e), which converge at second
+ *           order to the Riccati and Lyapunov solutions of the expansion;
+ *           the coarse matrix is K_g + a0 M_g.  Forward runs only (no
+ *           checkpoints, no adjoint).
  *   coarse_solver 0 = BiCGStab with Jacobi preconditioning (K_g is not
  *           symmetric), solved every step to the tolerance of sbfwi_set_solver;
  *           1 = direct: K_g = L U factored here once, in a nested-dissection
@@ -193,7 +203,11 @@ int sbfwi_autotune(sbfwi_factors f, int n_shots, double* host_out, hipStream_t s
  *   which = 1: values of K_g on the CSR pattern of sbfwi_coarse_pattern (nnz doubles);
  *   which = 2: the stored pivot inverses phi~_j^-1, j = 0 .. N_r-2, of every element,
  *              row-major (sum_e (N_r - 1) n_b^2 doubles);
- *   which = 3: G_e = psi_{n+1} psi_n^-1 of every element (sum_e n_b^2 doubles).
+ *   which = 3: G_e = psi_{n+1} psi_n^-1 of every element (sum_e n_b^2 doubles);
+ *   which = 4: (SBFWI_SCHEME_LFE) M_e of every element (sum_e n_b^2 doubles; which = 0
+ *              then holds K_e);
+ *   which = 5: (SBFWI_SCHEME_LFE) values of M_g on the CSR pattern (nnz doubles; which = 1
+ *              then holds K_g + a0 M_g).
  * host_dst must hold the documented count.
  */
 int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* host_dst);
@@ -216,6 +230,8 @@ int sbfwi_coarse_pattern(sbfwi_mesh m, int64_t* host_row_ptr, int64_t* host_col)
  *            n_ckpt >= n_steps stores every step (full storage).
  *   ckpt_out receives the checkpoint handle (needed by sbfwi_adjoint /
  *            sbfwi_gradient), or NULL.
+ * With factors of SBFWI_SCHEME_LFE the step is nodal only (F = M_g w + f,
+ * (K_g + a0 M_g) U = F, Newmark update) and n_ckpt must be 0.
  * Synchronises s at the end.  SBFWI_ENOCONV if the coarse solve fails,
  * SBFWI_ENONFINITE / SBFWI_EUNSTABLE if the wavefield blows up.
  */

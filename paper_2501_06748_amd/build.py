@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbfwi.so")
 SOURCES = ["api.cpp", "mesh.cpp", "profiler.cpp", "factor.hip", "step.hip", "coarse.hip", "adjoint.hip",
-           "direct.hip", "fem.hip"]
+           "direct.hip", "fem.hip", "lfe.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -116,7 +116,7 @@ extern "C" int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, 
   if (!m || !rho) return sbfwi_fail(SBFWI_EINVAL, "NULL mesh or density");
   if (!(c > 0) || !(dt > 0) || !(beta > 0) || !(gamma > 0))
     return sbfwi_fail(SBFWI_EINVAL, "c, dt, beta and gamma must be positive");
-  if (scheme != SBFWI_SCHEME_PAPER_FD && scheme != SBFWI_SCHEME_RADIAL_GALERKIN)
+  if (scheme != SBFWI_SCHEME_PAPER_FD && scheme != SBFWI_SCHEME_RADIAL_GALERKIN && scheme != SBFWI_SCHEME_LFE)
     return sbfwi_fail(SBFWI_EINVAL, "unknown radial scheme %d", scheme);
   if (coarse_solver != 0 && coarse_solver != 1)
     return sbfwi_fail(SBFWI_EINVAL, "unknown coarse solver %d", coarse_solver);
@@ -240,6 +240,12 @@ extern "C" int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* dst) {
     case 1: src = f->d.Kval; n = f->m->nnz; break;
     case 2: src = f->d.finv; n = f->m->n_finv; break;
     case 3: src = f->d.G; n = f->m->n_dense; break;
+    case 4:
+    case 5:
+      if (f->scheme != SBFWI_SCHEME_LFE) return sbfwi_fail(SBFWI_EINVAL, "factor data %d exists for scheme 2 only", which);
+      src = which == 4 ? f->d.Me : f->d.Mval;
+      n = which == 4 ? f->m->n_dense : f->m->nnz;
+      break;
     default: return sbfwi_fail(SBFWI_EINVAL, "unknown factor data %d", which);
   }
   SBFWI_CHECK(sbfwi_copy_sync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
@@ -382,6 +388,8 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
   if (n_rec < 0 || (n_rec > 0 && (!rec_node || !traces))) return sbfwi_fail(SBFWI_EINVAL, "bad receivers");
   if (n_ckpt != 0 && !ckpt_out) return sbfwi_fail(SBFWI_EINVAL, "checkpoints requested but ckpt_out is NULL");
   if (n_ckpt < -1) return sbfwi_fail(SBFWI_EINVAL, "n_ckpt must be >= -1");
+  if (f->scheme == SBFWI_SCHEME_LFE && n_ckpt != 0)
+    return sbfwi_fail(SBFWI_EINVAL, "the low-frequency expansion path has no adjoint: n_ckpt must be 0");
   // node ids are checked on the host (small arrays)
   {
     std::vector<int64_t> h(n_shots);
@@ -396,6 +404,8 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
     for (int64_t v : r)
       if (v < 0 || v >= f->m->n_nodes) return sbfwi_fail(SBFWI_EINVAL, "receiver node %lld out of range", (long long)v);
   }
+  if (f->scheme == SBFWI_SCHEME_LFE)
+    return sbfwi_lfe_forward(f, n_shots, n_steps, src_node, wavelet, n_rec, rec_node, traces, s);
   sbfwi_ckpt_s* ck = n_ckpt != 0 ? new sbfwi_ckpt_s() : nullptr;
   StepWork w;
   // graph replay needs a stream that can be captured: the run goes to a

@@ -36,8 +36,9 @@ struct ElemCtx {
   double xi0, h, c2, a0;
   const double* rho;  // element's [N_r][nb] densities (global)
   const double* alpha;  // LDS [4][nb][2][4]
-  int scheme;           // 0 central differences, 1 radial Galerkin
-  const double* rgw;    // Galerkin: weights of the element's intervals [n][kRgW]
+  int scheme;           // 0 central differences, 1 radial Galerkin, 2 low-frequency expansion
+  const double* rgw;    // Galerkin rows: weights of the element's intervals [n][kRgW]
+  int lfe;              // radially constant coefficients: every level takes the boundary level's densities
 };
 
 __device__ __forceinline__ int md(int i, int nb) { return (i % nb + nb) % nb; }
@@ -45,7 +46,7 @@ __device__ __forceinline__ int md(int i, int nb) { return (i % nb + nb) % nb; }
 // Band entry t (0 sub, 1 diag, 2 super) of row i of E^tau at level lev.
 __device__ double e_band(const ElemCtx& c, int tau, int lev, int t, int i) {
   const int nb = c.nb;
-  const double* r = c.rho + (int64_t)lev * nb;
+  const double* r = c.rho + (int64_t)(c.lfe ? c.n : lev) * nb;
   const double* al = c.alpha + tau * nb * 8;
   auto A = [&](int seg, int end, int ab) { return al[seg * 8 + end * 4 + ab]; };
   if (t == 1) {
@@ -116,7 +117,7 @@ __device__ double row_band_rg(const ElemCtx& c, int which, int r, int t, int i) 
 
 // Band entries of the rows: which = 0 theta, 1 phi, 2 psi, 3 P, for row r = -1 .. n+1.
 __device__ double row_band(const ElemCtx& c, int which, int r, int t, int i) {
-  if (c.scheme == SBFWI_SCHEME_RADIAL_GALERKIN) return row_band_rg(c, which, r, t, i);
+  if (c.scheme != SBFWI_SCHEME_PAPER_FD) return row_band_rg(c, which, r, t, i);
   const double h = c.h;
   if (r == -1 || r == c.n + 1) {
     int lev = (r == -1) ? 0 : c.n;
@@ -315,11 +316,12 @@ __global__ void __launch_bounds__(FT) factor_kernel(
   ec.xi0 = mm.xi0;
   ec.h = (1.0 - mm.xi0) / n;
   ec.c2 = c * c;
-  ec.a0 = a0;
+  ec.lfe = ff.scheme == SBFWI_SCHEME_LFE;
+  ec.a0 = ec.lfe ? 0.0 : a0;   // the expansion's K is the static condensation
   ec.rho = rho + mm.par_off[e];
   ec.alpha = L.alpha;
   ec.scheme = ff.scheme;
-  ec.rgw = ff.scheme == SBFWI_SCHEME_RADIAL_GALERKIN ? ff.rgw + ff.rgw_off[nr] : nullptr;
+  ec.rgw = ff.scheme != SBFWI_SCHEME_PAPER_FD ? ff.rgw + ff.rgw_off[nr] : nullptr;
   const int64_t po = mm.par_off[e];
   // persistent bands: theta_j, psi_j, P_j for j = 0..n; theta_{n+1}, phi_{-1}, psi_{-1}
   for (int q = threadIdx.x; q < 3 * nb * nr; q += FT) {
@@ -423,6 +425,45 @@ __global__ void __launch_bounds__(FT) factor_kernel(
     int i = q / nb, jj = q % nb;
     ff.S[dofs + q] = L.Ph1[i * NBT + jj] - L.A[i * NBT + jj];
   }
+  if (ec.lfe) {
+    // M = sum_i Phi_i^T M_i Phi_i over the static modes Phi_n = I,
+    // Phi_i = -phi~_i^-1 psi_i Phi_{i+1}; M_i = -P_i inside, M_n = P_n
+    __syncthreads();
+    load_rows<NBT>(ec, L, 0, 3, n);
+    __syncthreads();
+    band_to_dense<NBT>(L.band[0], L.Ph1, nb);     // Ph1 = M accumulator
+    for (int q = threadIdx.x; q < nb * nb; q += FT) {
+      int i = q / nb, jj = q % nb;
+      L.Ph[i * NBT + jj] = i == jj ? 1.0 : 0.0;   // Ph = Phi
+    }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; --j) {
+      load_rows<NBT>(ec, L, 1, 2, j);             // psi_j
+      load_rows<NBT>(ec, L, 2, 3, j);             // P_j
+      for (int q = threadIdx.x; q < nb * nb; q += FT)
+        L.Fp[(q / nb) * NBT + (q % nb)] = ff.finv[fo + (int64_t)j * nb * nb + q];
+      __syncthreads();
+      band_dense<NBT>(L.band[1], L.Ph, L.Z, nb);  // Z = psi_j Phi_{j+1}
+      __syncthreads();
+      dense_dense<NBT>(L.Fp, L.Z, L.A, nb);       // A = phi~_j^-1 Z = -Phi_j
+      __syncthreads();
+      for (int q = threadIdx.x; q < nb * nb; q += FT) {
+        int i = q / nb, jj = q % nb;
+        L.Ph[i * NBT + jj] = -L.A[i * NBT + jj];
+      }
+      __syncthreads();
+      band_dense<NBT>(L.band[2], L.Ph, L.B, nb);  // B = P_j Phi_j = -M_j Phi_j
+      __syncthreads();
+      for (int q = threadIdx.x; q < nb * nb; q += FT) {
+        int i = q / nb, jj = q % nb;
+        double v = 0.0;
+        for (int k = 0; k < nb; ++k) v += L.Ph[k * NBT + i] * L.B[k * NBT + jj];
+        L.Ph1[i * NBT + jj] -= v;
+      }
+      __syncthreads();
+    }
+    store_dense<NBT>(L.Ph1, ff.Me + dofs, nb);
+  }
   if (threadIdx.x == 0 && L.bad) atomicOr(status, 1);
 }
 
@@ -434,6 +475,22 @@ __global__ void assemble_kernel(int64_t nnz, const int64_t* __restrict__ cptr,
   double v = 0.0;
   for (int64_t t = cptr[q]; t < cptr[q + 1]; ++t) v += S[csrc[t]];
   K[q] = v;
+}
+
+// Low-frequency expansion: K_g + a0 M_g (the Newmark system matrix) and M_g.
+__global__ void assemble_lfe_kernel(int64_t nnz, const int64_t* __restrict__ cptr,
+                                    const int64_t* __restrict__ csrc, const double* __restrict__ S,
+                                    const double* __restrict__ Me, double a0, double* __restrict__ K,
+                                    double* __restrict__ M) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  double k = 0.0, m = 0.0;
+  for (int64_t t = cptr[q]; t < cptr[q + 1]; ++t) {
+    k += S[csrc[t]];
+    m += Me[csrc[t]];
+  }
+  K[q] = k + a0 * m;
+  M[q] = m;
 }
 
 __global__ void transpose_diag_kernel(int64_t nnz, int64_t n_nodes, const int64_t* __restrict__ tr,
@@ -458,7 +515,7 @@ void sbfwi_factors_free(sbfwi_factors_s* f) {
   FactorsDev& d = f->d;
   void* ptrs[] = {d.finv, d.th_band, d.ps_band, d.pm_band, d.th_np1, d.phim1, d.psim1,
                   d.G, d.S, d.psit0, d.psin_inv, d.phit_n, d.thm1_inv, d.gbasis,
-                  d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv, d.status, d.rgw};
+                  d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv, d.status, d.rgw, d.Me, d.Mval};
   sbfwi_dev_free(d.rgw_off);
   for (void* p : ptrs) sbfwi_dev_free(p);
   sbfwi_direct_num_free(f->dnum);
@@ -548,7 +605,11 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   A(&d.KTell, m->d.n_ell);
   A(&d.diag_inv, m->n_nodes);
   if (rc == SBFWI_OK) rc = sbfwi_alloc(&d.status, 8);
-  if (rc == SBFWI_OK && scheme == SBFWI_SCHEME_RADIAL_GALERKIN) {
+  if (scheme == SBFWI_SCHEME_LFE) {
+    A(&d.Me, m->n_dense);
+    A(&d.Mval, m->nnz);
+  }
+  if (rc == SBFWI_OK && scheme != SBFWI_SCHEME_PAPER_FD) {
     std::vector<double> w;
     std::vector<int> off;
     sbfwi_rg_weights(m->xi0, m->h_nr, w, off);
@@ -586,8 +647,12 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   }
   {
     unsigned g = (unsigned)((m->nnz + 255) / 256);
-    hipLaunchKernelGGL(assemble_kernel, dim3(g), dim3(256), 0, s, m->nnz, m->d.contrib_ptr, m->d.contrib_src,
-                       d.S, d.Kval);
+    if (scheme == SBFWI_SCHEME_LFE)
+      hipLaunchKernelGGL(assemble_lfe_kernel, dim3(g), dim3(256), 0, s, m->nnz, m->d.contrib_ptr,
+                         m->d.contrib_src, d.S, d.Me, d.a0, d.Kval, d.Mval);
+    else
+      hipLaunchKernelGGL(assemble_kernel, dim3(g), dim3(256), 0, s, m->nnz, m->d.contrib_ptr, m->d.contrib_src,
+                         d.S, d.Kval);
     int64_t big = m->nnz > m->n_nodes ? m->nnz : m->n_nodes;
     unsigned g2 = (unsigned)((big + 255) / 256);
     he = hipMemsetAsync(d.Kell, 0, sizeof(double) * m->d.n_ell, s);

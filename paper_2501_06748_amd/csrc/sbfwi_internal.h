@@ -154,7 +154,15 @@ struct FactorsDev {
   int scheme = 0;
   double* rgw = nullptr;       // [sum over level counts of (N_r - 1) * kRgW] weights
   int* rgw_off = nullptr;      // [129] offset of the table of N_r levels (in doubles)
+  // low-frequency expansion: element masses and the assembled global mass
+  double* Me = nullptr;        // [n_dense] M_e (S holds K_e)
+  double* Mval = nullptr;      // [nnz] M_g on the CSR pattern (Kval holds K_g + a0 M_g)
 };
+
+// Forward run of the low-frequency expansion path (lfe.hip); synchronises s.
+struct sbfwi_factors_s;
+int sbfwi_lfe_forward(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const int64_t* src_node,
+                      const double* wavelet, int n_rec, const int64_t* rec_node, double* traces, hipStream_t s);
 
 // Weights of one radial interval [xi_j, xi_j + h] in the Galerkin scheme, for
 // local levels p, q in {0, 1} (row, column) and interpolation end e in {0, 1}:

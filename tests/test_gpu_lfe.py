@@ -1,0 +1,89 @@
+"""Low-frequency expansion path (scheme 2) on the GPU against the oracle.
+
+Bars: element K_e, M_e and the assembled K_g + a0 M_g, M_g to 1e-11 relative;
+traces to relative L2 <= 1e-10.  Cases: the tiny plate (direct and iterative
+coarse solvers), a small Voronoi plate, and on the 8000-cell Voronoi plate
+with 33 radial levels sampled cells one by one and a finite 200-step run.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import element as oel
+from oracle import lfe as olfe
+
+from ._gpu import GpuModel, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+LFE = 2
+
+
+def _cvt_small(n_steps, n_r=12):
+    m = W.cvt_mesh(0.02, 0.01, 60, n_r, seed=5, lloyd_iters=30)
+    wl = W.Workload("cvt-small", m, 6000.0, 2700.0, 2e-7, n_steps,
+                    np.asarray([W.nearest_top_node(m, 0.007), W.nearest_top_node(m, 0.013)], dtype=np.int64),
+                    np.repeat(W.sine_burst(n_steps, 2e-7, 5e5, 2, 1e12)[None], 2, axis=0),
+                    W.edge_nodes(m)[::2].copy(), f0=5e5)
+    pts = W.fine_point_positions(m)
+    wl.models = {"random30": W.smooth_random_field(pts, 4 * 1000 + 7, 2700.0, 0.3, wavelength=0.006)}
+    return wl
+
+
+def _per_elem(g, which, mesh):
+    nb = mesh.n_b().astype(np.int64)
+    return g.sb.sbfwi_copy_factor_data(g.f, which, int((nb ** 2).sum()))
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "cvt"])
+def test_lfe_factor_and_forward_parity(cfg):
+    wl = W.config_tiny(200) if cfg == "tiny" else _cvt_small(120)
+    rho = wl.models["random30"]
+    log(f"lfe parity {cfg}: {wl.mesh.n_elem} elements, {wl.n_steps} steps")
+    om = olfe.LfeModel(wl.mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0)
+    ref = olfe.lfe_forward(om, wl.src_nodes, wl.wavelets, wl.rec_nodes, wl.n_steps)
+    for solver in (1, 0):
+        g = GpuModel(wl, rho, coarse_solver=solver, scheme=LFE)
+        Ke = _per_elem(g, 0, wl.mesh)
+        Me = _per_elem(g, 4, wl.mesh)
+        assert rel_l2(Ke, np.concatenate([k.ravel() for k in om.Ke])) <= 1e-11
+        assert rel_l2(Me, np.concatenate([k.ravel() for k in om.Me])) <= 1e-11
+        rp, col = g.sb.sbfwi_coarse_pattern(g.mesh)
+        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+        Keff = om.K + om.nm.a0 * om.M
+        assert rel_l2(g.sb.sbfwi_copy_factor_data(g.f, 1, len(col)), np.asarray(Keff[rows, col]).ravel()) <= 1e-11
+        assert rel_l2(g.sb.sbfwi_copy_factor_data(g.f, 5, len(col)), np.asarray(om.M[rows, col]).ravel()) <= 1e-11
+        tr, _ = g.forward()
+        err = rel_l2(tr.cpu().numpy(), ref)
+        log(f"  coarse solver {solver}: traces relative L2 {err:.3e}")
+        assert err <= 1e-10
+    with pytest.raises(g.sb.SbfwiError, match="no adjoint"):
+        g.forward(n_steps=5, n_ckpt=-1)
+
+
+def test_lfe_full_size_8000_cells():
+    base = W.config_cvt(8000, 7)
+    wl = W.config_cvt(8000, 32, mesh=base.mesh)
+    mesh = wl.mesh
+    rho = wl.models["hole_floor_half"]
+    log(f"lfe full size: {mesh.n_elem} cells, 33 radial levels")
+    g = GpuModel(wl, rho, coarse_solver=1, scheme=LFE)
+    Ke, Me = _per_elem(g, 0, mesh), _per_elem(g, 4, mesh)
+    nb = mesh.n_b().astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(nb ** 2)])
+    offs = mesh.param_offsets()
+    worst = 0.0
+    for e in np.random.default_rng(9).choice(mesh.n_elem, 12, replace=False):
+        lp = mesh.loop(e)
+        xy = mesh.node_xy[lp][None]
+        nr = int(mesh.n_r[e])
+        rb = rho[offs[e]:offs[e + 1]].reshape(nr, len(lp))[nr - 1][None, None]
+        E = [x[0, 0] for x in oel.coefficient_matrices(xy, oel.polygon_centroid(xy), rb, wl.c)]
+        K, M = olfe.condensed_matrices(*E, oel.radial_levels(nr, wl.xi0)[0])
+        worst = max(worst, rel_l2(Ke[off[e]:off[e + 1]], K.ravel()), rel_l2(Me[off[e]:off[e + 1]], M.ravel()))
+    log(f"  sampled cells: worst K_e, M_e relative L2 {worst:.3e}")
+    assert worst <= 1e-11
+    tr, _ = g.forward()
+    tr = tr.cpu().numpy()
+    assert np.isfinite(tr).all() and np.abs(tr).max() > 0
