@@ -388,8 +388,7 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
   if (n_rec < 0 || (n_rec > 0 && (!rec_node || !traces))) return sbfwi_fail(SBFWI_EINVAL, "bad receivers");
   if (n_ckpt != 0 && !ckpt_out) return sbfwi_fail(SBFWI_EINVAL, "checkpoints requested but ckpt_out is NULL");
   if (n_ckpt < -1) return sbfwi_fail(SBFWI_EINVAL, "n_ckpt must be >= -1");
-  if (f->scheme == SBFWI_SCHEME_LFE && n_ckpt != 0)
-    return sbfwi_fail(SBFWI_EINVAL, "the low-frequency expansion path has no adjoint: n_ckpt must be 0");
+
   // node ids are checked on the host (small arrays)
   {
     std::vector<int64_t> h(n_shots);
@@ -404,8 +403,38 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
     for (int64_t v : r)
       if (v < 0 || v >= f->m->n_nodes) return sbfwi_fail(SBFWI_EINVAL, "receiver node %lld out of range", (long long)v);
   }
-  if (f->scheme == SBFWI_SCHEME_LFE)
-    return sbfwi_lfe_forward(f, n_shots, n_steps, src_node, wavelet, n_rec, rec_node, traces, s);
+  if (f->scheme == SBFWI_SCHEME_LFE) {
+    // any n_ckpt != 0 keeps every step's nodal velocity (the paper-kernel gradient needs them all)
+    sbfwi_ckpt_s* ck = nullptr;
+    double* vstore = nullptr;
+    if (n_ckpt != 0) {
+      ck = new sbfwi_ckpt_s();
+      ck->f = f;
+      ck->n_shots = n_shots;
+      ck->n_rec = n_rec;
+      ck->n_steps = n_steps;
+      ck->interval = 1;
+      ck->full_store = true;
+      int rc = sbfwi_alloc(&ck->rec_node, n_rec > 0 ? n_rec : 1);
+      if (rc == SBFWI_OK) rc = sbfwi_alloc(&ck->vstore, n_steps * f->m->n_nodes * n_shots);
+      if (rc == SBFWI_OK && n_rec > 0 &&
+          hipMemcpyAsync(ck->rec_node, rec_node, n_rec * sizeof(int64_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = sbfwi_fail(SBFWI_EHIP, "hipMemcpyAsync failed");
+      if (rc != SBFWI_OK) {
+        ckpt_free(ck);
+        return rc;
+      }
+      ck->bytes = 8 * n_steps * f->m->n_nodes * n_shots;
+      vstore = ck->vstore;
+    }
+    int rc = sbfwi_lfe_forward(f, n_shots, n_steps, src_node, wavelet, n_rec, rec_node, traces, vstore, s);
+    if (rc != SBFWI_OK) {
+      ckpt_free(ck);
+      return rc;
+    }
+    if (ckpt_out) *ckpt_out = ck;
+    return SBFWI_OK;
+  }
   sbfwi_ckpt_s* ck = n_ckpt != 0 ? new sbfwi_ckpt_s() : nullptr;
   StepWork w;
   // graph replay needs a stream that can be captured: the run goes to a
@@ -435,6 +464,13 @@ extern "C" int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_s
   if (ck->f != f) return sbfwi_fail(SBFWI_EINVAL, "checkpoints belong to other factors");
   const int base = mode & ~SBFWI_GRAD_PER_SHOT;
   if (base != SBFWI_GRAD_EXACT && base != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
+  if (f->scheme == SBFWI_SCHEME_LFE) {
+    if (base != SBFWI_GRAD_PAPER_KERNEL)
+      return sbfwi_fail(SBFWI_EINVAL, "scheme 2 provides the paper-kernel gradient only");
+    SBFWI_CHECK(sbfwi_zero_sync(grad, sizeof(double) * f->m->n_params *
+                                          ((mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1)));
+    return sbfwi_lfe_adjoint(f, ck, adj_src, (mode & SBFWI_GRAD_PER_SHOT) != 0, grad, s);
+  }
   return sbfwi_adjoint_impl(f, ck, adj_src, mode, grad, s);
 }
 

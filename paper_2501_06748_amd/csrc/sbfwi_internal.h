@@ -159,10 +159,16 @@ struct FactorsDev {
   double* Mval = nullptr;      // [nnz] M_g on the CSR pattern (Kval holds K_g + a0 M_g)
 };
 
-// Forward run of the low-frequency expansion path (lfe.hip); synchronises s.
+// Low-frequency expansion path (lfe.hip): forward run (vstore, optional, keeps
+// every step's nodal velocity) and the paper-kernel gradient from the kept
+// velocities; both synchronise s.
 struct sbfwi_factors_s;
+struct sbfwi_ckpt_s;
 int sbfwi_lfe_forward(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const int64_t* src_node,
-                      const double* wavelet, int n_rec, const int64_t* rec_node, double* traces, hipStream_t s);
+                      const double* wavelet, int n_rec, const int64_t* rec_node, double* traces, double* vstore,
+                      hipStream_t s);
+int sbfwi_lfe_adjoint(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_src, int per_shot, double* grad,
+                      hipStream_t s);
 
 // Weights of one radial interval [xi_j, xi_j + h] in the Galerkin scheme, for
 // local levels p, q in {0, 1} (row, column) and interpolation end e in {0, 1}:

@@ -85,3 +85,33 @@ def test_lfe_loop_conserves_energy():
             energies.append(0.5 * V @ (model.M @ V) + 0.5 * U @ (model.K @ U))
     energies = np.asarray(energies)
     assert energies[0] > 0 and np.abs(energies - energies[0]).max() <= 1e-11 * energies[0]
+
+
+def test_lfe_paper_kernel_agrees_in_sign_with_finite_differences():
+    """The truncated kernel is an approximation (parity unpinned beyond this):
+    it must be a direction of increasing misfit and agree in sign with the
+    finite-difference derivative along the direction to the data model."""
+    wl = W.config_tiny(120)
+    m = wl.mesh
+    rho = wl.models["random30"]
+    rho0 = wl.models["homogeneous"]
+
+    def run(r):
+        return lfe.lfe_forward(lfe.LfeModel(m, r, wl.c, wl.dt), wl.src_nodes, wl.wavelets, wl.rec_nodes, 120)
+
+    obs = run(rho0)
+    g, _ = lfe.lfe_paper_kernel_gradient(lfe.LfeModel(m, rho, wl.c, wl.dt), wl.src_nodes, wl.wavelets,
+                                         wl.rec_nodes, obs, 120)
+    J = lambda r: 0.5 * wl.dt * np.sum((run(r) - obs) ** 2)
+    offs = m.param_offsets()
+    bnd = np.zeros(m.n_params, dtype=bool)
+    for e in range(m.n_elem):
+        bnd[offs[e] + (m.n_r[e] - 1) * m.n_b()[e]:offs[e + 1]] = True
+    assert np.all(g[~bnd] == 0.0) and np.abs(g[bnd]).max() > 0
+    h = 1e-4
+    d = np.where(bnd, rho0 - rho, 0.0)
+    fd_d = (J(rho + h * d) - J(rho - h * d)) / (2 * h)
+    assert fd_d < 0 and g @ d < 0
+    step = 1e-3 * np.abs(rho).max() / np.abs(g).max()
+    fd_g = (J(rho + step * g) - J(rho - step * g)) / (2 * step)
+    assert fd_g > 0
