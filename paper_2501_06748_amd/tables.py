@@ -32,7 +32,8 @@ import time
 import numpy as np
 import torch
 
-from . import GRAD_EXACT, GRAD_PAPER_KERNEL, sbfwi_build_mesh, sbfwi_factor_elements, sbfwi_forward, sbfwi_gradient
+from . import (GRAD_EXACT, GRAD_PAPER_KERNEL, LAUNCH_GRAPHS, sbfwi_build_mesh, sbfwi_factor_elements, sbfwi_forward,
+               sbfwi_gradient, sbfwi_set_launch)
 
 # seconds per epoch in the paper's timing table of the hole specimen (12 CPU threads)
 PAPER_CPU_S = {(1000, 5): 0.95, (1000, 7): 1.32, (2000, 5): 2.39, (2000, 7): 3.21,
@@ -51,6 +52,7 @@ def main(argv=None):
     ap.add_argument("--intervals", type=int, nargs="+", default=[5, 7])
     ap.add_argument("--schemes", type=int, nargs="+", default=[0, 1, 2])
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--graphs", type=int, default=0, help="1: forward steps replayed from HIP graphs")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import workloads as W
@@ -90,6 +92,8 @@ def main(argv=None):
                 def epoch():
                     f = sbfwi_factor_elements(mesh, rho_h, wl.c, wl.dt, wl.beta, wl.gamma, scheme=scheme,
                                               coarse_solver=1)
+                    if args.graphs:
+                        sbfwi_set_launch(f, LAUNCH_GRAPHS, 1)
                     ck = sbfwi_forward(f, src, wav, rec, tr, n_ckpt=-1)
                     sbfwi_gradient(f, ck, obs, tr, mode, mis, grad)
                     ck.close()
@@ -110,7 +114,7 @@ def main(argv=None):
                        "n_b_max": int(m.n_b().max()), "nodes": int(m.n_nodes), "receivers": R,
                        "seconds_per_epoch": sec, "units_per_s": None if scheme == 2 else units / sec,
                        "finite": bool(torch.isfinite(grad).all().item()),
-                       "gradient": "paper kernel" if scheme == 2 else "exact",
+                       "gradient": "paper kernel" if scheme == 2 else "exact", "graphs": bool(args.graphs),
                        "paper_cpu_seconds_per_epoch": PAPER_CPU_S.get(key)}
                 rows.append(row)
                 _log(f"[tables] {n_cells} cells, {row['intervals']} intervals, {name}: {sec * 1e3:.1f} ms per epoch, "
