@@ -257,6 +257,9 @@ int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps,
  *           the forward scheme driven by the time-reversed adj_src at the
  *           receivers; sign -1 so that it points along the exact gradient).
  *           With SBFWI_GRAD_PER_SHOT or-ed in, every shot gets its own gradient.
+ *           Factors of SBFWI_SCHEME_LFE accept SBFWI_GRAD_PAPER_KERNEL only
+ *           (SBFWI_EINVAL otherwise): the kernel at the nodal points, written
+ *           to every element's boundary-level entries (interior levels 0).
  *   grad    device [n_params], overwritten with the sum over shots; with
  *           SBFWI_GRAD_PER_SHOT: [n_shots][n_params], one gradient per shot.
  * Synchronises s at the end.
