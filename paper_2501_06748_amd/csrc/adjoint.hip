@@ -425,6 +425,30 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Adds the gradient of levels l0c .. lev (collected in Gb by item) to grad.
+// Every entry receives one addition per launch (launches are ordered on the
+// stream), so the hardware's floating-point add at the memory side gives the
+// same result as a read-modify-write, without the lane waiting for the read.
+template <int NBT, int S, int GCH>
+__device__ __forceinline__ void flush_chunk(const double (&Gb)[GCH][NBT * S], int l0c, int lev, int nb, int ns,
+                                            int it, int s0, int64_t po, int64_t shot_stride,
+                                            double* __restrict__ grad) {
+  const int nl = lev - l0c + 1;
+  if (shot_stride == 0) {
+    for (int q = it; q < nl * nb; q += WT) {
+      const int l = q / nb, k = q % nb;
+      double t = 0.0;
+      for (int u = 0; u < ns; ++u) t += Gb[l][k * S + u];
+      unsafeAtomicAdd(grad + po + (int64_t)(l0c + l) * nb + k, t);
+    }
+  } else {
+    for (int q = it; q < nl * nb * ns; q += WT) {
+      const int l = q / (nb * ns), r = q % (nb * ns), k = r / ns, u = r % ns;
+      unsafeAtomicAdd(grad + (int64_t)(s0 + u) * shot_stride + po + (int64_t)(l0c + l) * nb + k, Gb[l][k * S + u]);
+    }
+  }
+}
+
 // Exact gradient for one step: one wavefront per (element, group of S shots),
 // one item (boundary node i, shot s) per lane.  At level m the band entries of
 // the sensitivities of E0, E1, E2 and M0 are short sums of products of
@@ -436,12 +460,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // level m (one-sided at the ends, plus the flux rows at xi0 and at the
 // boundary).  Each lane forms the 12 quantities of its node from register
 // windows of X (levels m-2 .. m+2), lam (rows m-1 .. m+1) and the
-// accelerations (level m), publishes them in LDS, evaluates the four band
-// entries of the segment (i, i+1) it owns and contracts them with that
-// segment's density derivatives alpha (registers): the end-0 part is node i's,
-// the end-1 part goes to node i+1 through LDS.  The next level's X, lam and
-// accelerations are loaded while the current level is computed; the results
-// of GCH levels collect in LDS and are added to the gradient together.
+// accelerations (level m), takes those of node i+1 from that node's lane by
+// cross-lane permutes, evaluates the four band entries of the segment
+// (i, i+1) it owns and contracts them with that segment's density derivatives
+// alpha (registers): the end-0 part is node i's, the end-1 part is passed to
+// node i+1's lane the same way.  The next level's X, lam and accelerations are
+// loaded while the current level is computed; the results of GCH levels
+// collect in LDS and are added to the gradient together.
 template <int NBT, int S>
 __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restrict__ elems, MeshDev m,
                                                         FactorsDev f, int NS, const double* __restrict__ X,
@@ -450,8 +475,6 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
                                                         double* __restrict__ grad, int s0, int64_t shot_stride) {
   static_assert(NBT * S <= WT, "one (node, shot) item per lane");
   constexpr int GCH = 16;
-  __shared__ double V[12][NBT * S];   // the level's per-node quantities, by item
-  __shared__ double C1[NBT * S];      // end-1 parts, by receiving item
   __shared__ double Gb[GCH][NBT * S]; // gradient per level of the chunk and item
   const int e = elems[blockIdx.x];
   const int ns = min(S, NS - s0);
@@ -463,6 +486,7 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
   const int i = own ? it / S : 0, s = it % S;
   const bool act = own && s < ns;         // ... of a shot of the run
   const int itp = md(i + 1, nb) * S + s;  // item of node i + 1, end 1 of segment (i, i + 1)
+  const int itm = md(i - 1, nb) * S + s;  // item of node i - 1, whose segment ends at node i
   const bool summed = shot_stride == 0;
   double al[32];   // alpha of segment (i, i + 1): [tau * 8 + end * 4 + k], then M0 at 24 + end * 4 + k
 #pragma unroll
@@ -514,23 +538,16 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
     const double Qp[3] = {cw[0] * dm + f0 * d0, xm * xm / (h * h) * (x1 - 2.0 * x2 + x3) + T + cw[1] * d0,
                           cw[2] * dp + fn * d0};
     const double Rp[3] = {bw[0] * x1 + g0 * x2, T + bw[1] * x2, bw[2] * x3 + gn * x2};
-    if (own) {
-      V[0][it] = Lp[0]; V[1][it] = Lp[1]; V[2][it] = Lp[2];
-      V[3][it] = Qp[0]; V[4][it] = Qp[1]; V[5][it] = Qp[2];
-      V[6][it] = Rp[0]; V[7][it] = Rp[1]; V[8][it] = Rp[2];
-      V[9][it] = T; V[10][it] = x2; V[11][it] = aw;
-    }
-    wave_lds_sync();
-    double end0 = 0.0;
-    if (own) {
-      double Lq[3], Qq[3], Rq[3];
+    // node i + 1's quantities from its lane (every lane takes part in the exchange)
+    double Lq[3], Qq[3], Rq[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        Lq[a] = V[a][itp];
-        Qq[a] = V[3 + a][itp];
-        Rq[a] = V[6 + a][itp];
-      }
-      const double Tq = V[9][itp], Xq = V[10][itp], Aq = V[11][itp];
+    for (int a = 0; a < 3; ++a) {
+      Lq[a] = __shfl(Lp[a], itp, WT);
+      Qq[a] = __shfl(Qp[a], itp, WT);
+      Rq[a] = __shfl(Rp[a], itp, WT);
+    }
+    const double Tq = __shfl(T, itp, WT), Xq = __shfl(x2, itp, WT), Aq = __shfl(aw, itp, WT);
+    {
       // band entries (p, p), (p, q), (q, p), (q, q) of the segment, p = i, q = i + 1
       const double E0[4] = {Lp[0] * Qp[0] + Lp[1] * Qp[1] + Lp[2] * Qp[2],
                             Lp[0] * Qq[0] + Lp[1] * Qq[1] + Lp[2] * Qq[2],
@@ -550,27 +567,14 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
         s0m += al[24 + k] * M0[k];
         s1m += al[28 + k] * M0[k];
       }
-      end0 = xm * xm * s0m - s0e;
-      C1[itp] = xm * xm * s1m - s1e;
+      const double end0 = xm * xm * s0m - s0e, end1 = xm * xm * s1m - s1e;
+      // the end-1 part of segment (i - 1, i) comes from that segment's lane
+      const double c1 = __shfl(end1, itm, WT);
+      if (own) Gb[lev % GCH][it] = end0 + c1;
     }
-    wave_lds_sync();
-    if (own) Gb[lev % GCH][it] = end0 + C1[it];   // C1[it] from the lane of segment (i - 1, i)
     if (lev % GCH == GCH - 1 || lev == n) {       // add the chunk's levels to the gradient
       wave_lds_sync();
-      const int l0c = lev - lev % GCH, nl = lev - l0c + 1;
-      if (summed) {
-        for (int q = it; q < nl * nb; q += WT) {
-          const int l = q / nb, k = q % nb;
-          double t = 0.0;
-          for (int u = 0; u < ns; ++u) t += Gb[l][k * S + u];
-          grad[po + (int64_t)(l0c + l) * nb + k] += t;
-        }
-      } else {
-        for (int q = it; q < nl * nb * ns; q += WT) {
-          const int l = q / (nb * ns), r = q % (nb * ns), k = r / ns, u = r % ns;
-          grad[(int64_t)(s0 + u) * shot_stride + po + (int64_t)(l0c + l) * nb + k] += Gb[l][k * S + u];
-        }
-      }
+      flush_chunk<NBT, S, GCH>(Gb, lev - lev % GCH, lev, nb, ns, it, s0, po, shot_stride, grad);
       wave_lds_sync();
     }
     x0 = x1; x1 = x2; x2 = x3; x3 = x4; x4 = px;
@@ -579,8 +583,8 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
   }
 }
 
-// Exact gradient of the radial Galerkin scheme for one step, in the lane and
-// LDS organisation of grad_exact_kernel.  The level matrices E_m enter the
+// Exact gradient of the radial Galerkin scheme for one step, in the lane
+// organisation of grad_exact_kernel.  The level matrices E_m enter the
 // Galerkin blocks of the two intervals around level m (as the interpolation
 // end 1 of interval m - 1 and end 0 of interval m), so the band entries of
 // the sensitivities at level m are
@@ -603,8 +607,6 @@ __global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__
                                                      double* __restrict__ grad, int s0, int64_t shot_stride) {
   static_assert(NBT * S <= WT, "one (node, shot) item per lane");
   constexpr int GCH = 16;
-  __shared__ double V[18][NBT * S];   // the level's per-node quantities, by item
-  __shared__ double C1[NBT * S];      // end-1 parts, by receiving item
   __shared__ double Gb[GCH][NBT * S]; // gradient per level of the chunk and item
   const int e = elems[blockIdx.x];
   const int ns = min(S, NS - s0);
@@ -615,7 +617,8 @@ __global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__
   const bool own = it < nb * S;
   const int i = own ? it / S : 0, s = it % S;
   const bool act = own && s < ns;
-  const int itp = md(i + 1, nb) * S + s;
+  const int itp = md(i + 1, nb) * S + s;  // item of node i + 1
+  const int itm = md(i - 1, nb) * S + s;  // item of node i - 1
   const bool summed = shot_stride == 0;
   double al[32];
 #pragma unroll
@@ -657,30 +660,18 @@ __global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__
     }
     const double Ap[3] = {wL(32 + 0 + 1) * aa, (wL(32 + 2 + 1) + wR(32 + 0 + 0)) * ab, wR(32 + 2 + 0) * ac};
     const double Lp[3] = {la, lb, lc};
-    if (own) {
+    // node i + 1's quantities from its lane (every lane takes part in the exchange)
+    double Lq[3], Qq[3], Zaq[3], Zbq[3], Yq[3], Aq[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        V[a][it] = Lp[a];
-        V[3 + a][it] = Qk[0][a];
-        V[6 + a][it] = Qk[1][a];
-        V[9 + a][it] = Qk[2][a];
-        V[12 + a][it] = Qk[3][a];
-        V[15 + a][it] = Ap[a];
-      }
+    for (int a = 0; a < 3; ++a) {
+      Lq[a] = __shfl(Lp[a], itp, WT);
+      Qq[a] = __shfl(Qk[0][a], itp, WT);
+      Zaq[a] = __shfl(Qk[1][a], itp, WT);
+      Zbq[a] = __shfl(Qk[2][a], itp, WT);
+      Yq[a] = __shfl(Qk[3][a], itp, WT);
+      Aq[a] = __shfl(Ap[a], itp, WT);
     }
-    wave_lds_sync();
-    double end0 = 0.0;
-    if (own) {
-      double Lq[3], Qq[3], Zaq[3], Zbq[3], Yq[3], Aq[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        Lq[a] = V[a][itp];
-        Qq[a] = V[3 + a][itp];
-        Zaq[a] = V[6 + a][itp];
-        Zbq[a] = V[9 + a][itp];
-        Yq[a] = V[12 + a][itp];
-        Aq[a] = V[15 + a][itp];
-      }
+    {
       double E0[4] = {0, 0, 0, 0}, E1[4] = {0, 0, 0, 0}, E2[4] = {0, 0, 0, 0}, M0[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -698,27 +689,13 @@ __global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__
         s0e += al[k] * E0[k] + al[8 + k] * E1[k] + al[16 + k] * E2[k] + al[24 + k] * M0[k];
         s1e += al[4 + k] * E0[k] + al[12 + k] * E1[k] + al[20 + k] * E2[k] + al[28 + k] * M0[k];
       }
-      end0 = s0e;
-      C1[itp] = s1e;
+      // the end-1 part of segment (i - 1, i) comes from that segment's lane
+      const double c1 = __shfl(s1e, itm, WT);
+      if (own) Gb[lev % GCH][it] = s0e + c1;
     }
-    wave_lds_sync();
-    if (own) Gb[lev % GCH][it] = end0 + C1[it];
     if (lev % GCH == GCH - 1 || lev == n) {
       wave_lds_sync();
-      const int l0c = lev - lev % GCH, nl = lev - l0c + 1;
-      if (summed) {
-        for (int q = it; q < nl * nb; q += WT) {
-          const int l = q / nb, k = q % nb;
-          double t = 0.0;
-          for (int u = 0; u < ns; ++u) t += Gb[l][k * S + u];
-          grad[po + (int64_t)(l0c + l) * nb + k] += t;
-        }
-      } else {
-        for (int q = it; q < nl * nb * ns; q += WT) {
-          const int l = q / (nb * ns), r = q % (nb * ns), k = r / ns, u = r % ns;
-          grad[(int64_t)(s0 + u) * shot_stride + po + (int64_t)(l0c + l) * nb + k] += Gb[l][k * S + u];
-        }
-      }
+      flush_chunk<NBT, S, GCH>(Gb, lev - lev % GCH, lev, nb, ns, it, s0, po, shot_stride, grad);
       wave_lds_sync();
     }
     xa = xb; xb = xc; xc = px;

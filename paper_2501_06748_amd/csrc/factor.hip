@@ -116,8 +116,9 @@ __device__ double row_band_rg(const ElemCtx& c, int which, int r, int t, int i) 
 }
 
 // Band entries of the rows: which = 0 theta, 1 phi, 2 psi, 3 P, for row r = -1 .. n+1.
+template <int SCH>
 __device__ double row_band(const ElemCtx& c, int which, int r, int t, int i) {
-  if (c.scheme != SBFWI_SCHEME_PAPER_FD) return row_band_rg(c, which, r, t, i);
+  if constexpr (SCH != SBFWI_SCHEME_PAPER_FD) return row_band_rg(c, which, r, t, i);
   const double h = c.h;
   if (r == -1 || r == c.n + 1) {
     int lev = (r == -1) ? 0 : c.n;
@@ -256,12 +257,14 @@ __device__ void store_dense(const double* D, double* dst, int nb) {
   for (int q = threadIdx.x; q < nb * nb; q += FT) dst[q] = D[(q / nb) * NBT + (q % nb)];
 }
 
-template <int NBT>
+template <int NBT, int SCH>
 __device__ void load_rows(const ElemCtx& c, Lds<NBT>& L, int slot, int which, int r) {
-  for (int q = threadIdx.x; q < 3 * c.nb; q += FT) L.band[slot][q] = row_band(c, which, r, q / c.nb, q % c.nb);
+  for (int q = threadIdx.x; q < 3 * c.nb; q += FT) L.band[slot][q] = row_band<SCH>(c, which, r, q / c.nb, q % c.nb);
 }
 
-template <int NBT>
+// SCH: the radial scheme, fixed at compile time so that each instance keeps
+// only its own row builder.
+template <int NBT, int SCH>
 __global__ void __launch_bounds__(FT) factor_kernel(
     const int32_t* __restrict__ elems, const MeshDev mm, const double* __restrict__ rho,
     double c, double a0, FactorsDev ff, int* status) {
@@ -316,46 +319,46 @@ __global__ void __launch_bounds__(FT) factor_kernel(
   ec.xi0 = mm.xi0;
   ec.h = (1.0 - mm.xi0) / n;
   ec.c2 = c * c;
-  ec.lfe = ff.scheme == SBFWI_SCHEME_LFE;
+  ec.lfe = SCH == SBFWI_SCHEME_LFE;
   ec.a0 = ec.lfe ? 0.0 : a0;   // the expansion's K is the static condensation
   ec.rho = rho + mm.par_off[e];
   ec.alpha = L.alpha;
-  ec.scheme = ff.scheme;
-  ec.rgw = ff.scheme != SBFWI_SCHEME_PAPER_FD ? ff.rgw + ff.rgw_off[nr] : nullptr;
+  ec.scheme = SCH;
+  ec.rgw = SCH != SBFWI_SCHEME_PAPER_FD ? ff.rgw + ff.rgw_off[nr] : nullptr;
   const int64_t po = mm.par_off[e];
   // persistent bands: theta_j, psi_j, P_j for j = 0..n; theta_{n+1}, phi_{-1}, psi_{-1}
   for (int q = threadIdx.x; q < 3 * nb * nr; q += FT) {
     int j = q / (3 * nb), rem = q % (3 * nb), t = rem / nb, i = rem % nb;
-    ff.th_band[3 * po + j * 3 * nb + rem] = row_band(ec, 0, j, t, i);
-    ff.ps_band[3 * po + j * 3 * nb + rem] = row_band(ec, 2, j, t, i);
-    ff.pm_band[3 * po + j * 3 * nb + rem] = row_band(ec, 3, j, t, i);
+    ff.th_band[3 * po + j * 3 * nb + rem] = row_band<SCH>(ec, 0, j, t, i);
+    ff.ps_band[3 * po + j * 3 * nb + rem] = row_band<SCH>(ec, 2, j, t, i);
+    ff.pm_band[3 * po + j * 3 * nb + rem] = row_band<SCH>(ec, 3, j, t, i);
   }
   for (int q = threadIdx.x; q < 3 * nb; q += FT) {
-    ff.th_np1[3 * lo + q] = row_band(ec, 0, n + 1, q / nb, q % nb);
-    ff.phim1[3 * lo + q] = row_band(ec, 1, -1, q / nb, q % nb);
-    ff.psim1[3 * lo + q] = row_band(ec, 2, -1, q / nb, q % nb);
+    ff.th_np1[3 * lo + q] = row_band<SCH>(ec, 0, n + 1, q / nb, q % nb);
+    ff.phim1[3 * lo + q] = row_band<SCH>(ec, 1, -1, q / nb, q % nb);
+    ff.psim1[3 * lo + q] = row_band<SCH>(ec, 2, -1, q / nb, q % nb);
   }
   const int64_t dofs = mm.dense_off[e];
   const int64_t fo = mm.finv_off[e];
   // theta_{-1}^-1
-  load_rows<NBT>(ec, L, 0, 0, -1);
+  load_rows<NBT, SCH>(ec, L, 0, 0, -1);
   __syncthreads();
   band_to_dense<NBT>(L.band[0], L.A, nb);
   __syncthreads();
   invert<NBT>(L, L.A, L.B, nb);                 // B = theta_{-1}^-1
   store_dense<NBT>(L.B, ff.thm1_inv + dofs, nb);
   // rho_0 = theta_0 theta_{-1}^-1 ; phi~_0 = phi_0 - rho_0 phi_{-1} ; psi~_0 = psi_0 - rho_0 psi_{-1}
-  load_rows<NBT>(ec, L, 0, 0, 0);   // theta_0
-  load_rows<NBT>(ec, L, 1, 1, -1);  // phi_{-1}
-  load_rows<NBT>(ec, L, 2, 2, -1);  // psi_{-1}
+  load_rows<NBT, SCH>(ec, L, 0, 0, 0);   // theta_0
+  load_rows<NBT, SCH>(ec, L, 1, 1, -1);  // phi_{-1}
+  load_rows<NBT, SCH>(ec, L, 2, 2, -1);  // psi_{-1}
   __syncthreads();
   band_dense<NBT>(L.band[0], L.B, L.Z, nb);     // Z = rho_0
   __syncthreads();
   dense_band<NBT>(L.Z, L.band[1], L.A, nb);     // A = rho_0 phi_{-1}
   dense_band<NBT>(L.Z, L.band[2], L.B, nb);     // B = rho_0 psi_{-1}
   __syncthreads();
-  load_rows<NBT>(ec, L, 0, 1, 0);   // phi_0
-  load_rows<NBT>(ec, L, 1, 2, 0);   // psi_0
+  load_rows<NBT, SCH>(ec, L, 0, 1, 0);   // phi_0
+  load_rows<NBT, SCH>(ec, L, 1, 2, 0);   // psi_0
   __syncthreads();
   band_to_dense<NBT>(L.band[0], L.Ph, nb);
   band_to_dense<NBT>(L.band[1], L.Pp, nb);
@@ -375,12 +378,12 @@ __global__ void __launch_bounds__(FT) factor_kernel(
     if (j == 1) {
       dense_dense<NBT>(L.Fp, L.Pp, L.Z, nb);
     } else {
-      load_rows<NBT>(ec, L, 2, 2, j - 1);
+      load_rows<NBT, SCH>(ec, L, 2, 2, j - 1);
       __syncthreads();
       dense_band<NBT>(L.Fp, L.band[2], L.Z, nb);
     }
-    load_rows<NBT>(ec, L, 0, 0, j);   // theta_j
-    load_rows<NBT>(ec, L, 1, 1, j);   // phi_j
+    load_rows<NBT, SCH>(ec, L, 0, 0, j);   // theta_j
+    load_rows<NBT, SCH>(ec, L, 1, 1, j);   // phi_j
     __syncthreads();
     band_dense<NBT>(L.band[0], L.Z, L.A, nb);   // A = theta_j Z
     band_to_dense<NBT>(L.band[1], L.Ph, nb);
@@ -391,8 +394,8 @@ __global__ void __launch_bounds__(FT) factor_kernel(
     }
     __syncthreads();
     if (j == n) {
-      load_rows<NBT>(ec, L, 0, 0, n + 1);
-      load_rows<NBT>(ec, L, 1, 1, n + 1);
+      load_rows<NBT, SCH>(ec, L, 0, 0, n + 1);
+      load_rows<NBT, SCH>(ec, L, 1, 1, n + 1);
       __syncthreads();
       band_dense<NBT>(L.band[0], L.Z, L.A, nb);
       band_to_dense<NBT>(L.band[1], L.Ph1, nb);
@@ -409,8 +412,8 @@ __global__ void __launch_bounds__(FT) factor_kernel(
   }
   store_dense<NBT>(L.Ph, ff.phit_n + dofs, nb);
   // G = psi_{n+1} psi_n^-1 ; S = phi~_{n+1} - G phi~_n
-  load_rows<NBT>(ec, L, 0, 2, n);       // psi_n
-  load_rows<NBT>(ec, L, 1, 2, n + 1);   // psi_{n+1}
+  load_rows<NBT, SCH>(ec, L, 0, 2, n);       // psi_n
+  load_rows<NBT, SCH>(ec, L, 1, 2, n + 1);   // psi_{n+1}
   __syncthreads();
   band_to_dense<NBT>(L.band[0], L.A, nb);
   __syncthreads();
@@ -429,7 +432,7 @@ __global__ void __launch_bounds__(FT) factor_kernel(
     // M = sum_i Phi_i^T M_i Phi_i over the static modes Phi_n = I,
     // Phi_i = -phi~_i^-1 psi_i Phi_{i+1}; M_i = -P_i inside, M_n = P_n
     __syncthreads();
-    load_rows<NBT>(ec, L, 0, 3, n);
+    load_rows<NBT, SCH>(ec, L, 0, 3, n);
     __syncthreads();
     band_to_dense<NBT>(L.band[0], L.Ph1, nb);     // Ph1 = M accumulator
     for (int q = threadIdx.x; q < nb * nb; q += FT) {
@@ -438,8 +441,8 @@ __global__ void __launch_bounds__(FT) factor_kernel(
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
-      load_rows<NBT>(ec, L, 1, 2, j);             // psi_j
-      load_rows<NBT>(ec, L, 2, 3, j);             // P_j
+      load_rows<NBT, SCH>(ec, L, 1, 2, j);             // psi_j
+      load_rows<NBT, SCH>(ec, L, 2, 3, j);             // P_j
       for (int q = threadIdx.x; q < nb * nb; q += FT)
         L.Fp[(q / nb) * NBT + (q % nb)] = ff.finv[fo + (int64_t)j * nb * nb + q];
       __syncthreads();
@@ -560,6 +563,26 @@ void sbfwi_rg_weights(double xi0, const std::vector<int>& level_counts, std::vec
   }
 }
 
+template <int NBT>
+static void launch_factor_nb(int scheme, dim3 grid, dim3 block, hipStream_t s, const int32_t* elems, const MeshDev& md,
+                             const double* rho, double c, const FactorsDev& d) {
+  if (scheme == SBFWI_SCHEME_RADIAL_GALERKIN)
+    hipLaunchKernelGGL((factor_kernel<NBT, SBFWI_SCHEME_RADIAL_GALERKIN>), grid, block, 0, s, elems, md, rho, c, d.a0,
+                       d, d.status);
+  else if (scheme == SBFWI_SCHEME_LFE)
+    hipLaunchKernelGGL((factor_kernel<NBT, SBFWI_SCHEME_LFE>), grid, block, 0, s, elems, md, rho, c, d.a0, d, d.status);
+  else
+    hipLaunchKernelGGL((factor_kernel<NBT, SBFWI_SCHEME_PAPER_FD>), grid, block, 0, s, elems, md, rho, c, d.a0, d,
+                       d.status);
+}
+
+static void launch_factor(int cl, int scheme, dim3 grid, dim3 block, hipStream_t s, sbfwi_mesh_s* m,
+                          const double* rho, double c, const FactorsDev& d) {
+  if (cl == 0) launch_factor_nb<8>(scheme, grid, block, s, m->class_elems[0], m->d, rho, c, d);
+  else if (cl == 1) launch_factor_nb<16>(scheme, grid, block, s, m->class_elems[1], m->d, rho, c, d);
+  else launch_factor_nb<24>(scheme, grid, block, s, m->class_elems[2], m->d, rho, c, d);
+}
+
 int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, double beta,
                       double gamma, int scheme, int coarse_solver, hipStream_t s, sbfwi_factors_s** out) {
   sbfwi_factors_s* f = new sbfwi_factors_s();
@@ -633,14 +656,7 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
       int64_t cnt = (int64_t)m->h_class_elems[cl].size();
       if (cnt == 0) continue;
       dim3 grid((unsigned)cnt), block(FT);
-      if (cl == 0)
-        hipLaunchKernelGGL(factor_kernel<8>, grid, block, 0, s, m->class_elems[0], m->d, rho, c, d.a0, d, d.status);
-      else if (cl == 1)
-        hipLaunchKernelGGL(factor_kernel<16>, grid, block, 0, s, m->class_elems[1], m->d, rho, c, d.a0, d,
-                           d.status);
-      else
-        hipLaunchKernelGGL(factor_kernel<24>, grid, block, 0, s, m->class_elems[2], m->d, rho, c, d.a0, d,
-                           d.status);
+      launch_factor(cl, scheme, grid, block, s, m, rho, c, d);
       he = hipGetLastError();
       if (he != hipSuccess) return hip_fail(he, "factor_kernel launch");
     }
