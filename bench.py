@@ -312,11 +312,11 @@ def main():
     print(f"[bench] warmup done: {json.dumps({k: round(v['ms'], 1) for k, v in warm.items()})}", file=sys.stderr,
           flush=True)
     # The dominant kernel: the sweep of the forward stepper (condense, or recover counting its
-    # checkpoint-recompute variant) with the largest warmup total.  Its forward-run launches
-    # run alone on the device and are timed live (the backward pass overlaps the segment
-    # recompute, the adjoint steps and the gradient contraction on three streams, so its
-    # launches share the device); rocprofv3 lists them as the kernel instance without stores.
-    tot = lambda k: warm.get(k, {}).get("ms", 0.0)
+    # checkpoint-recompute variant) with the largest total time in the census, where every
+    # kernel runs alone (in the overlapped backward pass the event times of launches that
+    # share the device are inflated).  Its forward-run launches run alone on the device and
+    # are timed live; rocprofv3 lists them as the kernel instance without stores.
+    tot = lambda k: census.get(k, {}).get("ms", 0.0)
     dominant = "recover" if tot("recover") + tot("recover_store") >= tot("condense") else "condense"
     # timed region: events around the dominant kernel's forward-run launches only
     torch.cuda.synchronize()

@@ -950,15 +950,21 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   const int64_t nseg = (N + C - 1) / C;
   const unsigned gp = (unsigned)((m->n_params + 255) / 256);
   const unsigned gn = (unsigned)((nn + 255) / 256);
+  // recompute of segment seg into store b: its start (state copy) and its step k
+  auto recompute_begin = [&](int64_t seg, hipStream_t s) -> int {
+    return sbfwi_state_copy(m, &fw, ck->states + seg * sbfwi_state_size(m, NS), 0, s);
+  };
+  auto recompute_step = [&](int64_t seg, int b, int64_t k, hipStream_t s) -> int {
+    const int64_t k0 = seg * C;
+    double* xs = xseg[b] + (k - k0 - 1) * m->n_x * NS;
+    double* fs = fseg[b] + (k - k0 - 1) * m->n_params * NS;
+    const double* us = ck->ustore ? ck->ustore + (k - 1) * m->n_nodes * NS : nullptr;
+    return sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, s, nullptr, us);
+  };
   auto recompute = [&](int64_t seg, int b, hipStream_t s) -> int {
     const int64_t k0 = seg * C, k1 = std::min(k0 + C, N);
-    SBFWI_CHECK(sbfwi_state_copy(m, &fw, ck->states + seg * sbfwi_state_size(m, NS), 0, s));
-    for (int64_t k = k0 + 1; k <= k1; ++k) {
-      double* xs = xseg[b] + (k - k0 - 1) * m->n_x * NS;
-      double* fs = fseg[b] + (k - k0 - 1) * m->n_params * NS;
-      const double* us = ck->ustore ? ck->ustore + (k - 1) * m->n_nodes * NS : nullptr;
-      SBFWI_CHECK(sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, s, nullptr, us));
-    }
+    SBFWI_CHECK(recompute_begin(seg, s));
+    for (int64_t k = k0 + 1; k <= k1; ++k) SBFWI_CHECK(recompute_step(seg, b, k, s));
     return SBFWI_OK;
   };
   const bool ov = sr != nullptr && !ck->full_store;
@@ -976,18 +982,31 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t k0 = seg * C, k1 = std::min(k0 + C, N);
     const int b = ov ? (int)(seg % 2) : 0;
+    // recompute of segment seg - 1 (into the other store), paced by this segment's
+    // adjoint steps: its step j waits until the adjoint's step j has been reached,
+    // so that every adjoint step (and its latency-bound coarse solve) runs beside
+    // one recompute step instead of the recompute running ahead and the adjoint
+    // then running alone
+    const int nb = (int)((seg + 1) % 2);
+    int64_t kr = 0, kr1 = 0;   // next and last step of the paced recompute
     if (ov) {
-      if (seg >= 1) {   // segment seg - 1 into the other store, once the adjoint of seg + 1 is done with it
-        const int nb = (int)((seg - 1) % 2);
+      if (seg >= 1) {   // once the adjoint of seg + 1 is done with that store
         if (seg + 1 <= nseg - 1) SBFWI_HIP(hipStreamWaitEvent(sr, ev[2 + nb], 0));
-        SBFWI_CHECK(recompute(seg - 1, nb, sr));
-        SBFWI_HIP(hipEventRecord(ev[nb], sr));
+        SBFWI_CHECK(recompute_begin(seg - 1, sr));
+        kr = (seg - 1) * C + 1;
+        kr1 = seg * C;
       }
       SBFWI_HIP(hipStreamWaitEvent(st, ev[b], 0));
     } else if (!ck->full_store) {
       SBFWI_CHECK(recompute(seg, 0, st));
     }
     for (int64_t k = k1; k > k0; --k) {
+      if (kr && kr <= kr1) {
+        SBFWI_HIP(hipEventRecord(ev[9], st));
+        SBFWI_HIP(hipStreamWaitEvent(sr, ev[9], 0));
+        SBFWI_CHECK(recompute_step(seg - 1, nb, kr, sr));
+        ++kr;
+      }
       const double* X = ck->full_store ? ck->xstore + (k - 1) * m->n_x * NS : xseg[b] + (k - k0 - 1) * m->n_x * NS;
       const double* Fs = ck->full_store ? (kind == 0 ? ck->fstore : ck->vstore) + (k - 1) * m->n_params * NS
                                         : fseg[b] + (k - k0 - 1) * m->n_params * NS;
@@ -1029,6 +1048,10 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         SBFWI_HIP(hipGetLastError());
       }
     }
+    if (kr) {   // the rest of the paced recompute (a last segment shorter than the others)
+      for (; kr <= kr1; ++kr) SBFWI_CHECK(recompute_step(seg - 1, nb, kr, sr));
+      SBFWI_HIP(hipEventRecord(ev[nb], sr));
+    }
     // the segment's contractions read its store too: st waits for the last one
     if (gs && n_grad > 0) SBFWI_HIP(hipStreamWaitEvent(st, ev[7 + (int)((k0 + 1) % 2)], 0));
     if (ov) SBFWI_HIP(hipEventRecord(ev[2 + b], st));
@@ -1045,7 +1068,7 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   double* xseg[2] = {nullptr, nullptr};
   double* fseg[2] = {nullptr, nullptr};
   hipStream_t sr = nullptr, sg = nullptr;   // recompute and contraction streams
-  hipEvent_t ev[9] = {};
+  hipEvent_t ev[10] = {};
   int rc = SBFWI_OK;
   if (!ck->full_store) {
     rc = sbfwi_step_work_alloc(&fw, m, NS);
@@ -1058,7 +1081,7 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
           sbfwi_alloc(&fseg[1], ck->interval * m->n_params * NS) == SBFWI_OK) {
         bool ok = hipStreamCreateWithFlags(&sr, hipStreamNonBlocking) == hipSuccess &&
                   hipStreamCreateWithFlags(&sg, hipStreamNonBlocking) == hipSuccess;
-        for (int q = 0; q < 9 && ok; ++q) ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
+        for (int q = 0; q < 10 && ok; ++q) ok = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) == hipSuccess;
         if (!ok) rc = sbfwi_fail(SBFWI_EHIP, "adjoint: cannot create the side streams");
       } else {
         (void)hipGetLastError();   // the second store did not fit: one segment after the other
