@@ -39,9 +39,15 @@ struct StepArgs {
   double* vs;             // optional second level-field store (v^k) when fs holds a^k
 };
 
+// Row stride of the dense blocks in LDS: one word of padding per row, so
+// that the lanes of a wave, which read one row each in dense_mv, fall on
+// different banks (an unpadded stride of NBT words puts every row on the same
+// banks).
+__host__ __device__ constexpr int fstride(int nbt) { return nbt + 1; }
+
 template <int NBT, int S>
 struct StepLds {
-  double F[2][NBT * NBT];
+  double F[2][NBT * fstride(NBT)];
   double w[NBT * S];
   double y[NBT * S];
   double x[NBT * S];
@@ -68,7 +74,7 @@ __device__ __forceinline__ void commit(const double (&reg)[(NBT * NBT + WT - 1) 
 #pragma unroll
   for (int r = 0; r < (NBT * NBT + WT - 1) / WT; ++r) {
     int q = threadIdx.x + r * WT;
-    if (q < nb * nb) dst[(q / nb) * NBT + (q % nb)] = reg[r];
+    if (q < nb * nb) dst[(q / nb) * fstride(NBT) + (q % nb)] = reg[r];
   }
 }
 
@@ -81,7 +87,7 @@ __device__ __forceinline__ double band_mv(const double* band, const double* vec,
 template <int NBT>
 __device__ __forceinline__ double dense_mv(const double* F, const double* vec, int nb, int i, int s, int S) {
   double acc = 0.0;
-  for (int c = 0; c < nb; ++c) acc += F[i * NBT + c] * vec[c * S + s];
+  for (int c = 0; c < nb; ++c) acc += F[i * fstride(NBT) + c] * vec[c * S + s];
   return acc;
 }
 
