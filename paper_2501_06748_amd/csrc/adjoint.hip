@@ -481,6 +481,9 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
   const int nb = m.nb[e], n = m.nr[e] - 1;
   const int64_t po = m.par_off[e], lo = m.loop_off[e], xo = m.x_off[e];
   const double h = (1.0 - m.xi0) / n, xi0 = m.xi0;
+  // 1/h and 1/(2h) once per element: the per-level coefficients below then
+  // take multiplications only (an FP64 division is about ten instructions)
+  const double ih = 1.0 / h, i2h = 0.5 * ih;
   const int it = threadIdx.x;
   const bool own = it < nb * S;           // the lane holds an item (node i, shot s)
   const int i = own ? it / S : 0, s = it % S;
@@ -510,9 +513,9 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
   };
   // FD weight of level mm in the radial derivative at row r (one-sided at the ends)
   auto dw = [&](int r, int mm) -> double {
-    if (r == 0) return mm == 0 ? -1.0 / h : (mm == 1 ? 1.0 / h : 0.0);
-    if (r == n) return mm == n - 1 ? -1.0 / h : (mm == n ? 1.0 / h : 0.0);
-    return mm == r - 1 ? -0.5 / h : (mm == r + 1 ? 0.5 / h : 0.0);
+    if (r == 0) return mm == 0 ? -ih : (mm == 1 ? ih : 0.0);
+    if (r == n) return mm == n - 1 ? -ih : (mm == n ? ih : 0.0);
+    return mm == r - 1 ? -i2h : (mm == r + 1 ? i2h : 0.0);
   };
   // windows at level 0 (X(-2) does not exist: its weights are zero)
   double x0 = 0.0, x1 = ldx(-1), x2 = ldx(0), x3 = ldx(1), x4 = ldx(2);
@@ -520,22 +523,22 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
   double aw = lda(0);
   for (int lev = 0; lev <= n; ++lev) {
     const double px = ldx(lev + 3), pl = ldl(lev + 2), pa = lda(lev + 1);
-    const double xm = xi0 + h * lev, hm = xm / (2.0 * h);
+    const double xm = xi0 + h * lev, hm = xm * i2h;
     // weights of rows lev - 1, lev, lev + 1: c for the E0 terms, b for the E1 terms
     double cw[3], bw[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int r = lev - 1 + a;
       const double w = (r >= 0 && r <= n) ? dw(r, lev) : 0.0, xr = xi0 + h * r;
-      cw[a] = w * xr * xr / (2.0 * h);
+      cw[a] = w * xr * xr * i2h;
       bw[a] = w * xr;
     }
-    const double f0 = lev == 0 ? xi0 / (2.0 * h) : 0.0, g0 = lev == 0 ? 1.0 : 0.0;
-    const double fn = lev == n ? (xi0 + h * n) / (2.0 * h) : 0.0, gn = lev == n ? 1.0 : 0.0;
+    const double f0 = lev == 0 ? xi0 * i2h : 0.0, g0 = lev == 0 ? 1.0 : 0.0;
+    const double fn = lev == n ? (xi0 + h * n) * i2h : 0.0, gn = lev == n ? 1.0 : 0.0;
     // this node's quantities
     const double dm = x2 - x0, d0 = x3 - x1, dp = x4 - x2, T = hm * d0;
     const double Lp[3] = {l0, l1, l2};
-    const double Qp[3] = {cw[0] * dm + f0 * d0, xm * xm / (h * h) * (x1 - 2.0 * x2 + x3) + T + cw[1] * d0,
+    const double Qp[3] = {cw[0] * dm + f0 * d0, xm * xm * (ih * ih) * (x1 - 2.0 * x2 + x3) + T + cw[1] * d0,
                           cw[2] * dp + fn * d0};
     const double Rp[3] = {bw[0] * x1 + g0 * x2, T + bw[1] * x2, bw[2] * x3 + gn * x2};
     // node i + 1's quantities from its lane (every lane takes part in the exchange)
