@@ -262,7 +262,8 @@ int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps,
  *           to every element's boundary-level entries (interior levels 0).
  *   grad    device [n_params], overwritten with the sum over shots; with
  *           SBFWI_GRAD_PER_SHOT: [n_shots][n_params], one gradient per shot.
- * Synchronises s at the end.
+ * A run without receivers has no adjoint sources: adj_src may then be NULL and
+ * grad is set to zero.  Synchronises s at the end.
  */
 int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_src, int mode,
                   double* grad, hipStream_t s);
@@ -273,7 +274,9 @@ int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_src, int mod
  * adj_src = dt (traces - observed).
  *   observed, traces device [n_shots][n_rec][n_steps] (traces from the run that
  *   made ck).  With SBFWI_GRAD_PER_SHOT in mode, misfit holds n_shots values
- *   (one per shot) and grad [n_shots][n_params].
+ *   (one per shot) and grad [n_shots][n_params].  A run without receivers
+ *   (n_rec = 0) has no data: observed and traces may then be NULL, and misfit
+ *   and grad are set to zero (synchronously).
  */
 int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
                    const double* traces, int mode, double* misfit, double* grad,

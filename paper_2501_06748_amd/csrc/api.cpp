@@ -460,13 +460,17 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
 
 extern "C" int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_src, int mode, double* grad,
                              hipStream_t s) {
-  if (!f || !ck || !adj_src || !grad) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  if (!f || !ck || !grad || (!adj_src && ck->n_rec > 0)) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   if (ck->f != f) return sbfwi_fail(SBFWI_EINVAL, "checkpoints belong to other factors");
   const int base = mode & ~SBFWI_GRAD_PER_SHOT;
   if (base != SBFWI_GRAD_EXACT && base != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
+  if (f->scheme == SBFWI_SCHEME_LFE && base != SBFWI_GRAD_PAPER_KERNEL)
+    return sbfwi_fail(SBFWI_EINVAL, "scheme 2 provides the paper-kernel gradient only");
+  if (ck->n_rec == 0) {   // no receivers, no adjoint sources: the adjoint state and the gradient vanish
+    (void)hipStreamSynchronize(s);
+    return sbfwi_zero_sync(grad, sizeof(double) * f->m->n_params * ((mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1));
+  }
   if (f->scheme == SBFWI_SCHEME_LFE) {
-    if (base != SBFWI_GRAD_PAPER_KERNEL)
-      return sbfwi_fail(SBFWI_EINVAL, "scheme 2 provides the paper-kernel gradient only");
     SBFWI_CHECK(sbfwi_zero_sync(grad, sizeof(double) * f->m->n_params *
                                           ((mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1)));
     return sbfwi_lfe_adjoint(f, ck, adj_src, (mode & SBFWI_GRAD_PER_SHOT) != 0, grad, s);
@@ -476,8 +480,20 @@ extern "C" int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_s
 
 extern "C" int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed, const double* traces,
                               int mode, double* misfit, double* grad, hipStream_t s) {
-  if (!f || !ck || !observed || !traces || !misfit || !grad) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  if (!f || !ck || !misfit || !grad || ((!observed || !traces) && ck->n_rec > 0))
+    return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   int64_t count = (int64_t)ck->n_shots * ck->n_rec * ck->n_steps;
+  if (ck->n_rec == 0) {   // no data: the misfit and its gradient are zero
+    if (ck->f != f) return sbfwi_fail(SBFWI_EINVAL, "checkpoints belong to other factors");
+    const int base = mode & ~SBFWI_GRAD_PER_SHOT;
+    if (base != SBFWI_GRAD_EXACT && base != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
+    if (f->scheme == SBFWI_SCHEME_LFE && base != SBFWI_GRAD_PAPER_KERNEL)
+      return sbfwi_fail(SBFWI_EINVAL, "scheme 2 provides the paper-kernel gradient only");
+    const int nm = (mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1;
+    (void)hipStreamSynchronize(s);
+    SBFWI_CHECK(sbfwi_zero_sync(misfit, sizeof(double) * nm));
+    return sbfwi_zero_sync(grad, sizeof(double) * f->m->n_params * nm);
+  }
   double* res = nullptr;
   SBFWI_CHECK(sbfwi_alloc(&res, count));
   int rc = SBFWI_OK;
