@@ -483,16 +483,9 @@ extern "C" int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* obse
   if (!f || !ck || !misfit || !grad || ((!observed || !traces) && ck->n_rec > 0))
     return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   int64_t count = (int64_t)ck->n_shots * ck->n_rec * ck->n_steps;
-  if (ck->n_rec == 0) {   // no data: the misfit and its gradient are zero
-    if (ck->f != f) return sbfwi_fail(SBFWI_EINVAL, "checkpoints belong to other factors");
-    const int base = mode & ~SBFWI_GRAD_PER_SHOT;
-    if (base != SBFWI_GRAD_EXACT && base != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
-    if (f->scheme == SBFWI_SCHEME_LFE && base != SBFWI_GRAD_PAPER_KERNEL)
-      return sbfwi_fail(SBFWI_EINVAL, "scheme 2 provides the paper-kernel gradient only");
-    const int nm = (mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1;
-    (void)hipStreamSynchronize(s);
-    SBFWI_CHECK(sbfwi_zero_sync(misfit, sizeof(double) * nm));
-    return sbfwi_zero_sync(grad, sizeof(double) * f->m->n_params * nm);
+  if (ck->n_rec == 0) {   // no data: the misfit is zero, and so is its gradient (checked and set by sbfwi_adjoint)
+    SBFWI_CHECK(sbfwi_adjoint(f, ck, nullptr, mode, grad, s));
+    return sbfwi_zero_sync(misfit, sizeof(double) * ((mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1));
   }
   double* res = nullptr;
   SBFWI_CHECK(sbfwi_alloc(&res, count));
