@@ -121,6 +121,9 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
     lnode[u] = m.loop_nodes[lo + ii[u]];
   }
   double reg[(NBT * NBT + WT - 1) / WT];
+  // n_b <= 21: a level's three band rows of P (and of theta) fit the 64 lanes,
+  // one load each, and every item takes its entries by cross-lane shuffles
+  constexpr bool kBandShfl = 3 * NBT <= WT;
   double cu[IPT], cv[IPT], ca[IPT], cp[3][IPT], ct[3][IPT];
   auto load_level = [&](int j, double (&uu)[IPT], double (&vv)[IPT], double (&aa)[IPT], double (&pb)[3][IPT],
                         double (&tb)[3][IPT]) {
@@ -135,14 +138,21 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
       uu[u] = su[g];
       vv[u] = sv[g];
       aa[u] = sa[g];
-      const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb) + ii[u];   // node 0 for lanes without an item
-      const double* tp = f.th_band + 3 * (po + (int64_t)j * nb) + ii[u];
-      pb[0][u] = pp[0];
-      pb[1][u] = pp[nb];
-      pb[2][u] = pp[2 * nb];
-      tb[0][u] = tp[0];
-      tb[1][u] = tp[nb];
-      tb[2][u] = tp[2 * nb];
+      if constexpr (!kBandShfl) {
+        const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb) + ii[u];   // node 0 for lanes without an item
+        const double* tp = f.th_band + 3 * (po + (int64_t)j * nb) + ii[u];
+        pb[0][u] = pp[0];
+        pb[1][u] = pp[nb];
+        pb[2][u] = pp[2 * nb];
+        tb[0][u] = tp[0];
+        tb[1][u] = tp[nb];
+        tb[2][u] = tp[2 * nb];
+      }
+    }
+    if constexpr (kBandShfl) {   // word l of the level's three band rows in lane l (lanes past them: word 0)
+      const int l = (int)threadIdx.x < 3 * nb ? (int)threadIdx.x : 0;
+      pb[0][0] = f.pm_band[3 * (po + (int64_t)j * nb) + l];
+      tb[0][0] = f.th_band[3 * (po + (int64_t)j * nb) + l];
     }
   };
   // y_j = P_j w_j - theta_j q_{j-1} into L.y (L.x holds q_{j-1})
@@ -157,8 +167,20 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
     for (int u = 0; u < IPT; ++u) {
       const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
       const int im = md(i - 1, nb) * S + s, ic = i * S + s, ip = md(i + 1, nb) * S + s;
-      double y = cp[0][u] * L.w[im] + cp[1][u] * L.w[ic] + cp[2][u] * L.w[ip];
-      if (j > 0) y -= ct[0][u] * L.x[im] + ct[1][u] * L.x[ic] + ct[2][u] * L.x[ip];
+      double p0, p1, p2, t0, t1, t2;
+      if constexpr (kBandShfl) {   // band row entries of node i from the lanes that loaded them
+        p0 = __shfl(cp[0][0], i, WT);
+        p1 = __shfl(cp[0][0], nb + i, WT);
+        p2 = __shfl(cp[0][0], 2 * nb + i, WT);
+        t0 = __shfl(ct[0][0], i, WT);
+        t1 = __shfl(ct[0][0], nb + i, WT);
+        t2 = __shfl(ct[0][0], 2 * nb + i, WT);
+      } else {
+        p0 = cp[0][u]; p1 = cp[1][u]; p2 = cp[2][u];
+        t0 = ct[0][u]; t1 = ct[1][u]; t2 = ct[2][u];
+      }
+      double y = p0 * L.w[im] + p1 * L.w[ic] + p2 * L.w[ip];
+      if (j > 0) y -= t0 * L.x[im] + t1 * L.x[ic] + t2 * L.x[ip];
       if (own[u]) L.y[it] = y;
     }
     __syncthreads();
