@@ -67,12 +67,49 @@ def kernel_bytes(mesh, NS, nnz):
         # reads unknowns and adjoint rows (n+3 levels each), accelerations (n+1), alpha; grad RMW
         "grad_exact": 32 * nb + 2 * (n + 1) * nb + NS * (2 * (n + 3) * nb + (n + 1) * nb),
     }
+    # joint sweeps: the condense of the next step takes its state from the recover sweep in LDS
+    out["joint"] = out["recover"] + out["condense"] - NS * 3 * n * nb
+    out["joint_store"] = out["recover_store"] + out["condense"] - NS * 3 * n * nb
     res = {k: int(8 * v.sum()) for k, v in out.items()}
     nn = int(mesh.n_nodes)
     res["solve_v"] = 12 * nnz + 8 * nn + 8 * NS * nn * 7      # K, D^-1; phat, r, rhat, w in; v, s, shat out
     res["solve_t"] = 12 * nnz + 8 * NS * nn * 3               # K; shat, s in; t out
     res["solve_x"] = 8 * nn + 8 * NS * nn * 11                # D^-1; x, phat, p r/w, shat, s, t, v, w in; r out
     return res
+
+
+def method_bytes(mesh, NS):
+    """Algorithmic HBM bytes per launch of the HBM-bound sweeps from the method's
+    per-unit byte model (a unit = one element, radial level and shot of one time
+    step; 8-byte words): every pass over an element streams two dense n_b x n_b
+    blocks per level, shared by the S = NS shots of the launch, plus the level
+    state of each shot -- forward 16 n_b^2/S + 48 n_b (u, v, a read and
+    written), checkpoint recompute 16 n_b^2/S + 64 n_b (plus the stores the
+    adjoint needs), adjoint and gradient 16 n_b^2/S + 80 n_b (adjoint state read
+    and written, forward unknowns read, gradient).  A sweep over half a step (a
+    condense or a recover on its own, each adjoint sweep) takes one block and
+    half the state; the joint sweep (recover of a step with the condense of the
+    next) the whole step; the gradient contraction the rest of the adjoint's
+    80 n_b: 32 n_b.  Returns bytes per launch and per unit of the whole
+    evaluation (fwd + recompute + adjoint + gradient = 48 n_b^2/S + 192 n_b)."""
+    nb = mesh.n_b().astype("float64")
+    units = mesh.n_r.astype("float64") * NS            # units of one launch, per element
+    blk = nb * nb / NS
+    per_unit = {"joint": 16 * blk + 48 * nb, "joint_store": 16 * blk + 64 * nb,
+                "condense": 8 * blk + 24 * nb, "recover": 8 * blk + 24 * nb,
+                "recover_store": 8 * blk + 32 * nb,
+                "adj_condense": 8 * blk + 24 * nb, "adj_recover": 8 * blk + 24 * nb,
+                "grad_exact": 32 * nb}
+    per_launch = {k: float((units * v).sum()) for k, v in per_unit.items()}
+    evaluation_per_step = float((units * (48 * blk + 192 * nb)).sum())
+    return per_launch, evaluation_per_step
+
+
+# kernel instances as rocprofv3 names them (uniform 16-node elements, 4 shots per block)
+ROCPROF_NAME = {"joint": "joint_kernel<16, 4, false>", "joint_store": "joint_kernel<16, 4, true>",
+                "condense": "condense_kernel<16, 4>", "recover": "recover_kernel<16, 4, false>",
+                "recover_store": "recover_kernel<16, 4, true>", "adj_condense": "adj_condense_kernel<16, 4>",
+                "adj_recover": "adj_recover_kernel<16, 4>", "grad_exact": "grad_exact_kernel<16, 4>"}
 
 
 def fem_bytes(nx, ny, S, R):
@@ -97,6 +134,8 @@ KERNEL_SOURCES = {"solve_v": ["paper_2501_06748_amd/csrc/coarse.hip"],
                   "condense": ["paper_2501_06748_amd/csrc/step.hip"],
                   "recover": ["paper_2501_06748_amd/csrc/step.hip"],
                   "recover_store": ["paper_2501_06748_amd/csrc/step.hip"],
+                  "joint": ["paper_2501_06748_amd/csrc/step.hip"],
+                  "joint_store": ["paper_2501_06748_amd/csrc/step.hip"],
                   "adj_condense": ["paper_2501_06748_amd/csrc/adjoint.hip"],
                   "adj_recover": ["paper_2501_06748_amd/csrc/adjoint.hip"],
                   "grad_exact": ["paper_2501_06748_amd/csrc/adjoint.hip"],
@@ -244,6 +283,8 @@ def main():
         ya = torch.empty_like(xa)
         ya.copy_(xa)
         torch.cuda.synchronize()
+        mh.close()
+        sb.sbfwi_finalize()
         print("[bench] counter probe done", file=sys.stderr, flush=True)
         return
 
@@ -311,19 +352,19 @@ def main():
     warm = sb.sbfwi_profile_read(reset=True)
     print(f"[bench] warmup done: {json.dumps({k: round(v['ms'], 1) for k, v in warm.items()})}", file=sys.stderr,
           flush=True)
-    # The dominant kernel: the sweep of the forward stepper (condense, or recover counting its
-    # checkpoint-recompute variant) with the largest total time in the census, where every
-    # kernel runs alone (in the overlapped backward pass the event times of launches that
-    # share the device are inflated).  Its forward-run launches run alone on the device and
-    # are timed live; rocprofv3 lists them as the kernel instance without stores.
+    # The dominant kernel: the HBM-bound sweep kind (one kernel instance on this mesh) with the
+    # largest total time in the census.  Its launches are timed live by events over the timed
+    # region; in the overlapped backward pass launches share the device, and their durations
+    # (live and under rocprofv3 alike) include that sharing.
+    sweep_kinds = list(ROCPROF_NAME)
     tot = lambda k: census.get(k, {}).get("ms", 0.0)
-    dominant = "recover" if tot("recover") + tot("recover_store") >= tot("condense") else "condense"
-    # timed region: events around the dominant kernel's forward-run launches only
+    dominant = max(sweep_kinds, key=tot)
+    # timed region: events around the dominant kernel's launches only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
     for _ in range(args.steps):
-        stats = step([dominant], 0)
+        stats = step([dominant], [dominant])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     live = sb.sbfwi_profile_read(reset=True)
@@ -333,23 +374,42 @@ def main():
     units = int(mesh.n_r.astype(np.int64).sum()) * N * S
     value = units * args.steps / el
     kb = kernel_bytes(mesh, S, info["nnz"])
+    mb, eval_bytes_per_step = method_bytes(mesh, S)
     d_launches = live.get(dominant, {}).get("launches", 0)
     d_ms = live.get(dominant, {}).get("ms", 0.0)
     avg_s = d_ms / 1e3 / max(d_launches, 1)
-    if dominant in kb:
-        # coarse-solve kernels: enqueued launches after convergence only forward scalars, so the
-        # algorithmic bytes are those of the active launches (one per BiCGStab iteration)
-        active = stats["iterations"] if dominant.startswith("solve_") else d_launches
-        moved = kb[dominant] * active
-        achieved = moved / max(d_ms / 1e3, 1e-12) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant, wl.name),
-                "kernel": dominant, "timed_launches": "forward run", "avg_launch_us": avg_s * 1e6,
-                "launches": d_launches,
-                "active_launches": active, "algorithmic_bytes_per_active_launch": kb[dominant]}
-    else:
-        roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
-                "kernel": dominant, "avg_launch_us": avg_s * 1e6, "launches": d_launches}
+    achieved = mb[dominant] / max(avg_s, 1e-12) / 1e9
+    alone = census.get(dominant, {"launches": 0, "ms": 0.0})
+    alone_s = alone["ms"] / 1e3 / max(alone["launches"], 1)
+    # every sweep kind alone (census), against the method's bytes and against the builder's
+    # own every-input-and-output model (which also counts the q round trip and the band rows)
+    sweeps = {}
+    for k in sweep_kinds:
+        c = census.get(k)
+        if not c or c["launches"] == 0:
+            continue
+        a_s = c["ms"] / 1e3 / c["launches"]
+        sweeps[k] = {"launches": c["launches"], "avg_us_alone": round(a_s * 1e6, 2),
+                     "method_bytes_per_launch": int(mb[k]),
+                     "frac": round(mb[k] / a_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "model_bytes_per_launch": kb.get(k),
+                     "frac_model": round(kb[k] / a_s / 1e9 / HBM_PEAK_GBS, 4) if k in kb else None}
+    eval_bytes = eval_bytes_per_step * N
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant, wl.name),
+            "kernel": dominant, "rocprof_kernel": ROCPROF_NAME[dominant],
+            "timed_launches": "every launch of the kernel in the timed region",
+            "avg_launch_us": avg_s * 1e6, "launches": d_launches,
+            "algorithmic_bytes_per_launch": int(mb[dominant]),
+            "bytes_model": "16 n_b^2/S + 48 n_b (forward), + 64 n_b (recompute), + 80 n_b (adjoint + "
+                           "gradient) bytes per element*level*shot; half-step sweeps take one block and half "
+                           "the state",
+            "alone": {"avg_launch_us": round(alone_s * 1e6, 2),
+                      "frac": round(mb[dominant] / max(alone_s, 1e-12) / 1e9 / HBM_PEAK_GBS, 4)},
+            "sweeps_alone": sweeps,
+            "evaluation": {"algorithmic_bytes": eval_bytes, "GB/s": eval_bytes * args.steps / el / 1e9,
+                           "frac": eval_bytes * args.steps / el / 1e9 / HBM_PEAK_GBS,
+                           "bytes_per_unit": eval_bytes_per_step / (units / N)}}
     breakdown = {k: round(v["ms"] / max(args.warmup, 1), 3) for k, v in warm.items()}
     # per-kernel rates of the census (kernels alone): HBM-bound sweeps and contraction against
     # 8 TB/s, the element factorisation against FP64 (8 n_b^3 flop per element and level)
@@ -395,6 +455,8 @@ def main():
         "coarse_solver": stats,
         "misfit": float(misfit.item()),
     }
+    mh.close()
+    sb.sbfwi_finalize()   # no library stream or event outlives the run
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N)
     print(json.dumps(out))

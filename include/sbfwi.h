@@ -162,6 +162,11 @@ int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
  *             coarse solution (n_nodes x shots x steps doubles, skipped when it does not fit)
  *             and the checkpoint recompute then skips its coarse solves (default);
  *             0 = the recompute solves again.
+ *   param 5:  1 = the recover sweep of a time step and the condense sweep of the next one
+ *             run as one joint sweep per element (the new w of every level kept in LDS), so
+ *             that the state is read once per step (default; classes whose LDS would exceed
+ *             48 KB, and plans with a persistent sweep launch, run the two sweeps in turn);
+ *             0 = two separate sweeps.
  *   param 10 + 3 k + c: shots per block (0 = default, 1, 2, 4, 8, 16) of sweep k (0 condense,
  *             1 recover, 2 transposed condense, 3 transposed recover) for n_b class c
  *             (n_b <= 8, <= 16, <= 24).
@@ -232,8 +237,18 @@ int sbfwi_coarse_pattern(sbfwi_mesh m, int64_t* host_row_ptr, int64_t* host_col)
  *            sbfwi_gradient), or NULL.
  * With factors of SBFWI_SCHEME_LFE the step is nodal only (F = M_g w + f,
  * (K_g + a0 M_g) U = F, Newmark update) and n_ckpt must be 0.
- * Synchronises s at the end.  SBFWI_ENOCONV if the coarse solve fails,
- * SBFWI_ENONFINITE / SBFWI_EUNSTABLE if the wavefield blows up.
+ * Growth detector (schemes 0 and 1): every step checks each new nodal
+ * displacement of shot q against the envelope 10 * 4 k r F_k(q), r the largest
+ * 1 / |K_g,ii| and F_k(q) the sum of |wavelet| of shot q over steps 1 .. k.  For a
+ * stable system (symmetric K, M) the Newmark response to a point force obeys
+ * |u^k| <= k dt (M^-1)_max sum dt |f|, and 4 r approximates dt^2 (M^-1)_max, so
+ * stable runs stay below 0.15 of the envelope; the radial finite differences at
+ * strong density contrast grow exponentially (the step map has eigenvalues outside
+ * the unit circle) and cross it.  The run still completes every step (every kernel
+ * exits normally); the call then returns SBFWI_EUNSTABLE (finite values beyond the
+ * envelope) or SBFWI_ENONFINITE (a non-finite value), with the first such step in
+ * sbfwi_last_error, and the traces and checkpoints are meaningless.
+ * Synchronises s at the end.  SBFWI_ENOCONV if the coarse solve fails.
  */
 int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps,
                   const int64_t* src_node, const double* wavelet,
@@ -282,7 +297,11 @@ int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
                    const double* traces, int mode, double* misfit, double* grad,
                    hipStream_t s);
 
-/* Checkpoint store footprint in bytes (host_out[0]) and checkpoint interval (host_out[1]). */
+/* Checkpointed run (host values): host_out[0] footprint in bytes, [1] checkpoint interval,
+ * [2] shots, [3] receivers, [4] steps of the run -- the leading sizes of the adj_src,
+ * observed and traces arrays that sbfwi_adjoint and sbfwi_gradient read, and of the
+ * per-shot gradients they write (the ABI takes no sizes for those arrays: a caller
+ * passing shorter arrays makes the library read and write past them). */
 int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* host_out);
 
 /* Nested-dissection structure used by the direct coarse solver (host values):
@@ -318,7 +337,9 @@ int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
  * of the coarse solve (v = K p, t = K s, the x / r / p update), 15 its two
  * start-up kernels, 16 the recover sweep of the checkpoint recompute, which
  * also stores the adjoint's inputs; id 1 counts the other recover sweeps), 17 the
- * time step of sbfwi_fem_forward.  A sweep over elements of several n_b classes counts as
+ * time step of sbfwi_fem_forward, 18 the joint sweep (recover of a step and condense
+ * of the next, sbfwi_set_launch param 5), 19 its checkpoint-recompute variant with
+ * the stores; ids 0, 1 and 16 then count only the sweeps that run alone.  A sweep over elements of several n_b classes counts as
  * one launch.  Recorded pairs are accumulated as they complete (the oldest
  * are waited for once many are in flight).  sbfwi_profile_read waits for the
  * rest and writes, for each of the 20 ids, host_out[2 id] = launches and
@@ -354,6 +375,18 @@ int sbfwi_profile_read(double* host_out, int reset);
 int sbfwi_fem_forward(int nx, int ny, double lx, double ly, const double* rho_elem, double c, double dt,
                       int n_shots, int64_t n_steps, const int64_t* src_node, const double* wavelet,
                       int n_rec, const int64_t* rec_node, double* traces, hipStream_t s);
+
+/*
+ * sbfwi_finalize -- releases the runtime objects the library owns outside the
+ * handles: the per-thread streams of its synchronous copies and the events of
+ * the live kernel timing (pending timings are discarded, timing is switched
+ * off).  Waits for the device first.  Handles stay valid; later calls create
+ * what they need again.  Call it after the last handle is destroyed and before
+ * the process tears down the HIP runtime, so that no library-owned stream or
+ * event outlives the caller's own teardown.  Not to be called while another
+ * thread is inside the library.
+ */
+int sbfwi_finalize(void);
 
 void sbfwi_destroy_mesh(sbfwi_mesh m);
 void sbfwi_destroy_factors(sbfwi_factors f);

@@ -24,12 +24,21 @@ kernel is the time integral of (d_t lambda d_t u - c^2 grad lambda . grad u)
 (Section "Adjoint method"); the implementation notes drop the second term
 and evaluate the first at the nodal points from forward and back-propagated
 wavefields, the back-propagated field being the forward solver driven by
-the time-reversed residuals at the receivers.  Reading (index convention,
-chosen here because the paper gives only the continuous form): the
-back-propagated run is the forward stepper with source r^{N_t + 1 - k'} at
-reversed step k' (r = dt (u - d)), and g = sign * dt * sum_k' v~^{k'} v^{N_t + 1 - k'}
-at every (element, level, node).  Its sign is fixed by correlation with the
-exact gradient (parity unpinned beyond that).
+the time-reversed residuals at the receivers.  Readings (the paper gives
+only the continuous form):
+
+* source: the residual itself, r = u - d, as a nodal point load (the paper's
+  adjoint source is the residual d - u of the misfit's functional derivative;
+  with the stepper's sign convention M u'' + K u = f the back-propagated
+  system takes u - d);
+* time: the kernel's time integral by the rectangle rule of the misfit
+  (weight dt at t_k, k = 1 .. N_t); reversed step k' of the back-propagated run
+  applies r^{N_t + 1 - k'} and is paired with forward step N_t + 1 - k', the
+  pairing of the exact discrete adjoint, whose state at step k is driven by
+  the residuals of steps k .. N_t;
+* sign: the reversal turns d_t lambda into -d_t lambda~, so
+  g = -dt * sum_k' v~^{k'} v^{N_t + 1 - k'} at every (element, level, node);
+* no area weight: the paper evaluates the kernel at the nodal points.
 """
 
 from __future__ import annotations
@@ -176,12 +185,13 @@ class _Sub:
 
 def paper_kernel_gradient(model: Model, src_nodes, wavelets, rec_nodes, observed, n_steps,
                           sign: float = -1.0):
-    """Truncated zero-lag kernel at the nodal points (parity unpinned beyond its
-    correlation with the exact gradient)."""
+    """Truncated zero-lag kernel at the nodal points: -dt sum_k' v~^{k'} v^{N_t+1-k'},
+    v~ the velocities of the forward stepper driven by the time-reversed residuals
+    u - d at the receivers (readings in the module docstring)."""
     nm = model.nm
     mesh = model.mesh
     traces, trajs = forward(model, src_nodes, wavelets, rec_nodes, n_steps, keep=True)
-    res = nm.dt * (traces - observed)
+    res = traces - observed
     grad = np.zeros(mesh.n_params)
     offs = mesh.param_offsets()
     for s in range(len(src_nodes)):

@@ -44,11 +44,13 @@ def lfe_mass(K, E0, E1, M0):
 # For density that does not vary along xi (the boundary values of every
 # element, as in eq. simplified) each element contributes a stiffness K_e and
 # a mass M_e on its boundary nodes only; the global system K U + M U'' = F is
-# stepped with the same Newmark scheme (eq. Newmark).  The K_e, M_e used here
-# are those of linear radial elements condensed onto the boundary level:
-# K_e the static Schur complement, M_e the radial mass seen through the
-# static modes.  They converge to the Riccati and Lyapunov solutions above as
-# the radial levels refine (O(h^2)); the tests pin that convergence.
+# stepped with the same Newmark scheme (eq. Newmark).  By default K_e and M_e
+# are the paper's: the Riccati solution (lfe_stiffness) and the Lyapunov
+# solution (lfe_mass) above.  The alternative ``method="condensed"`` takes
+# those of linear radial elements condensed onto the boundary level: K_e the
+# static Schur complement, M_e the radial mass seen through the static modes;
+# they converge to the Riccati and Lyapunov solutions as the radial levels
+# refine (O(h^2)); the tests pin that convergence.
 # ---------------------------------------------------------------------------
 
 from . import radial_galerkin as _rg
@@ -74,10 +76,11 @@ class LfeModel:
     """Assembled K, M of the low-frequency expansion path and the LU of K + a0 M.
 
     rho_flat is the fine-grid density; only each element's boundary level
-    (level N_r - 1) is used.  The element's N_r sets the radial resolution of
-    the condensation."""
+    (level N_r - 1) is used.  method "riccati": K_e, M_e of eq. S (Riccati and
+    Lyapunov equations); "condensed": the radial condensation on the element's
+    N_r levels."""
 
-    def __init__(self, mesh, rho_flat, c, dt, beta=0.25, gamma=0.5, xi0=1e-3):
+    def __init__(self, mesh, rho_flat, c, dt, beta=0.25, gamma=0.5, xi0=1e-3, method="riccati"):
         import scipy.sparse as sp
         import scipy.sparse.linalg as spla
         from .stepper import Newmark
@@ -91,8 +94,12 @@ class LfeModel:
             xy = mesh.node_xy[lp][None]
             rb = np.asarray(rho_flat[offs[e]:offs[e + 1]]).reshape(nr, nb)[nr - 1][None, None]
             E0, E1, E2, M0 = [E[0, 0] for E in _coeffs(xy, _centroid(xy), rb, c)]
-            xi, _ = _levels(nr, xi0)
-            Ke, Me = condensed_matrices(E0, E1, E2, M0, xi)
+            if method == "riccati":
+                Ke, _ = lfe_stiffness(E0, E1, E2)
+                Me = lfe_mass(Ke, E0, E1, M0)
+            else:
+                xi, _ = _levels(nr, xi0)
+                Ke, Me = condensed_matrices(E0, E1, E2, M0, xi)
             self.Ke.append(Ke)
             self.Me.append(Me)
             rows.append(np.repeat(lp, nb))
@@ -146,13 +153,13 @@ def _lfe_velocities(model: LfeModel, nodes, amps, n_steps):
 def lfe_paper_kernel_gradient(model: LfeModel, src_nodes, wavelets, rec_nodes, observed, n_steps,
                               sign: float = -1.0):
     """The paper's truncated kernel on the expansion path: sign * dt * sum_k'
-    v~^{k'} v^{N_t + 1 - k'} at every node, the back-propagated run v~ driven
-    by the time-reversed residuals dt (u - d) at the receivers; every element's
-    boundary-level density at a node takes that node's value (parity unpinned
-    beyond its agreement in sign with finite differences of the misfit)."""
+    v~^{k'} v^{N_t + 1 - k'} at every node (sign -1), the back-propagated run v~
+    driven by the time-reversed residuals u - d at the receivers (the readings
+    of ``adjoint.paper_kernel_gradient``); every element's boundary-level
+    density at a node takes that node's value."""
     nm, mesh = model.nm, model.mesh
     traces = lfe_forward(model, src_nodes, wavelets, rec_nodes, n_steps)
-    res = nm.dt * (traces - observed)
+    res = traces - observed
     kern = np.zeros(mesh.n_nodes)
     for s in range(len(src_nodes)):
         v_f = _lfe_velocities(model, np.asarray([src_nodes[s]]), np.asarray(wavelets)[s:s + 1], n_steps)

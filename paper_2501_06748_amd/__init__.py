@@ -15,7 +15,9 @@ Higher layers in this package:
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -52,11 +54,17 @@ def _hptr(a, dtype):
     return a, a.ctypes.data_as(C.c_void_p)
 
 
+_live_handles = weakref.WeakSet()   # open handles, closed by sbfwi_finalize
+
+
 class _Handle:
     _destroy = None
+    _order = 0     # closing order at finalize: checkpoints, then factors, then meshes
 
     def __init__(self, ptr):
         self.ptr = ptr
+        if ptr:
+            _live_handles.add(self)
 
     def close(self):
         if self.ptr:
@@ -78,10 +86,12 @@ class _Handle:
 
 class MeshHandle(_Handle):
     _destroy = "sbfwi_destroy_mesh"
+    _order = 2
 
 
 class FactorsHandle(_Handle):
     _destroy = "sbfwi_destroy_factors"
+    _order = 1
 
     def __init__(self, ptr, mesh):
         super().__init__(ptr)
@@ -91,13 +101,35 @@ class FactorsHandle(_Handle):
 class CkptHandle(_Handle):
     _destroy = "sbfwi_destroy_ckpt"
 
-    def __init__(self, ptr, factors):
+    def __init__(self, ptr, factors, n_shots=0, n_rec=0, n_steps=0, n_params=0):
         super().__init__(ptr)
         self.factors = factors
+        # sizes of the run, checked against every array passed with this handle
+        self.n_shots, self.n_rec, self.n_steps, self.n_params = n_shots, n_rec, n_steps, n_params
 
 
 def sbfwi_last_error() -> str:
     return lib().sbfwi_last_error().decode()
+
+
+def sbfwi_finalize():
+    """Closes every open handle (checkpoints, factors, meshes) and releases the
+    library's own streams and events (sbfwi_finalize of the C ABI).  Registered
+    to run at interpreter exit; safe to call more than once."""
+    from . import _abi
+    if _abi._lib is None:
+        return
+    for h in sorted(list(_live_handles), key=lambda h: h._order):
+        h.close()
+    check(lib().sbfwi_finalize())
+
+
+@atexit.register
+def _finalize_at_exit():
+    try:
+        sbfwi_finalize()
+    except Exception:
+        pass
 
 
 def sbfwi_build_mesh(node_xy, elem_ptr, elem_nodes, n_r, centre_xy=None, xi0=1e-3) -> MeshHandle:
@@ -175,6 +207,7 @@ def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
 
 
 LAUNCH_ENQUEUED_ITERS, LAUNCH_GRAPHS, LAUNCH_RESET_PLAN = 0, 1, 2
+LAUNCH_OVERLAP_BACKWARD, LAUNCH_KEEP_SOLUTIONS, LAUNCH_JOINT_SWEEPS = 3, 4, 5
 
 
 def launch_param_shots(sweep: int, cls: int) -> int:
@@ -222,7 +255,9 @@ def sbfwi_forward(f: FactorsHandle, src_node, wavelet, rec_node, traces, n_ckpt=
                               _dptr(wavelet, torch.float64, "wavelet"), n_rec,
                               _dptr(rec_node, torch.int64, "rec_node"), _dptr(traces, torch.float64, "traces"),
                               int(n_ckpt), C.byref(out) if n_ckpt != 0 else None, _stream(stream)))
-    return CkptHandle(out.value, f) if n_ckpt != 0 else None
+    if n_ckpt == 0:
+        return None
+    return CkptHandle(out.value, f, n_shots, n_rec, n_steps, sbfwi_mesh_info(f.mesh)["n_params"])
 
 
 def sbfwi_fem_forward(nx, ny, lx, ly, rho_elem, c, dt, src_node, wavelet, rec_node, traces, stream=None):
@@ -242,11 +277,17 @@ def sbfwi_fem_forward(nx, ny, lx, ly, rho_elem, c, dt, src_node, wavelet, rec_no
                                   _stream(stream)))
 
 
-def _check_grad_shapes(f, n_shots, mode, grad, misfit=None):
-    n_params = sbfwi_mesh_info(f.mesh)["n_params"]
-    per = n_shots if (int(mode) & GRAD_PER_SHOT) else 1
-    if grad.numel() != per * n_params:
-        raise ValueError(f"grad must hold {per} x {n_params} values")
+def _check_run_shapes(ck, mode, grad, misfit=None, **series):
+    """Every array passed with a checkpoint handle must have the sizes of its run:
+    the library reads and writes them by the run's shot, receiver and step counts."""
+    run = (ck.n_shots, ck.n_rec, ck.n_steps)
+    for name, t in series.items():
+        if tuple(t.shape) != run:
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, the checkpointed run is "
+                             f"[shots, receivers, steps] = {list(run)}")
+    per = ck.n_shots if (int(mode) & GRAD_PER_SHOT) else 1
+    if grad.numel() != per * ck.n_params:
+        raise ValueError(f"grad must hold {per} x {ck.n_params} values")
     if misfit is not None and misfit.numel() < per:
         raise ValueError(f"misfit must hold {per} values")
 
@@ -254,7 +295,7 @@ def _check_grad_shapes(f, n_shots, mode, grad, misfit=None):
 def sbfwi_adjoint(f: FactorsHandle, ck: CkptHandle, adj_src, mode, grad, stream=None):
     """adj_src [S, R, N_t] f64 (device); grad [n_params] or, with GRAD_PER_SHOT, [S, n_params]."""
     import torch
-    _check_grad_shapes(f, int(adj_src.shape[0]), mode, grad)
+    _check_run_shapes(ck, mode, grad, adj_src=adj_src)
     check(lib().sbfwi_adjoint(f, ck, _dptr(adj_src, torch.float64, "adj_src"), int(mode),
                               _dptr(grad, torch.float64, "grad"), _stream(stream)))
 
@@ -262,9 +303,7 @@ def sbfwi_adjoint(f: FactorsHandle, ck: CkptHandle, adj_src, mode, grad, stream=
 def sbfwi_gradient(f: FactorsHandle, ck: CkptHandle, observed, traces, mode, misfit, grad, stream=None):
     """observed, traces [S, R, N_t]; misfit [1] (or [S] with GRAD_PER_SHOT); grad as in sbfwi_adjoint."""
     import torch
-    if observed.shape != traces.shape:
-        raise ValueError("observed and traces must have the same shape")
-    _check_grad_shapes(f, int(traces.shape[0]), mode, grad, misfit)
+    _check_run_shapes(ck, mode, grad, misfit, observed=observed, traces=traces)
     check(lib().sbfwi_gradient(f, ck, _dptr(observed, torch.float64, "observed"),
                                _dptr(traces, torch.float64, "traces"), int(mode),
                                _dptr(misfit, torch.float64, "misfit"), _dptr(grad, torch.float64, "grad"),
@@ -272,9 +311,10 @@ def sbfwi_gradient(f: FactorsHandle, ck: CkptHandle, observed, traces, mode, mis
 
 
 def sbfwi_ckpt_info(ck: CkptHandle) -> dict:
-    buf = np.zeros(2, dtype=np.int64)
+    buf = np.zeros(5, dtype=np.int64)
     check(lib().sbfwi_ckpt_info(ck, buf.ctypes.data_as(C.c_void_p)))
-    return {"bytes": int(buf[0]), "interval": int(buf[1])}
+    return {"bytes": int(buf[0]), "interval": int(buf[1]), "n_shots": int(buf[2]), "n_rec": int(buf[3]),
+            "n_steps": int(buf[4])}
 
 
 def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:
@@ -285,7 +325,8 @@ def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:
 
 PROFILE_KERNELS = ["condense", "recover", "coarse_solve", "source_gather", "nodal_update", "adj_condense",
                    "adj_recover", "adj_gather", "adj_nodal_update", "grad_exact", "grad_paper", "factor",
-                   "solve_v", "solve_t", "solve_x", "solve_init", "recover_store", "fem_step"]
+                   "solve_v", "solve_t", "solve_x", "solve_init", "recover_store", "fem_step", "joint",
+                   "joint_store"]
 
 
 def sbfwi_profile(kernels):

@@ -46,6 +46,7 @@ SIGNATURES = {
     "sbfwi_fem_forward": (i32, [i32, i32, dbl, dbl, vp, dbl, dbl, i32, i64, vp, vp, i32, vp, vp, vp]),
     "sbfwi_profile": (i32, [C.c_uint32]),
     "sbfwi_profile_read": (i32, [vp, i32]),
+    "sbfwi_finalize": (i32, []),
     "sbfwi_destroy_mesh": (None, [vp]),
     "sbfwi_destroy_factors": (None, [vp]),
     "sbfwi_destroy_ckpt": (None, [vp]),

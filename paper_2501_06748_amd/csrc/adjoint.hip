@@ -707,8 +707,10 @@ __global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__
   }
 }
 
-// Paper kernel: g -= dt * sum_s v~ v at every fine-grid point.
-__global__ void grad_paper_kernel(MeshDev m, int NS, double dt, int64_t n_params, const int32_t* __restrict__ par_elem,
+// Paper kernel: g -= w * sum_s v~ v at every fine-grid point.  The back-propagated
+// run is driven by adj_src = dt (u - d), dt times the paper's residual source, so
+// the rectangle rule's dt of the kernel's time integral is already in v~ (w = 1).
+__global__ void grad_paper_kernel(MeshDev m, int NS, double w, int64_t n_params, const int32_t* __restrict__ par_elem,
                                   const double* __restrict__ vint, const double* __restrict__ Vnod,
                                   const double* __restrict__ vf, double* __restrict__ grad, int per_shot) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -723,11 +725,11 @@ __global__ void grad_paper_kernel(MeshDev m, int NS, double dt, int64_t n_params
     double vl = lev < n ? vint[(m.int_off[e] + (int64_t)lev * nb + k) * NS + s]
                         : Vnod[m.loop_nodes[m.loop_off[e] + k] * NS + s];
     if (per_shot)
-      grad[s * n_params + p] -= dt * (vl * vf[p * NS + s]);
+      grad[s * n_params + p] -= w * (vl * vf[p * NS + s]);
     else
       g += vl * vf[p * NS + s];
   }
-  if (!per_shot) grad[p] -= dt * g;
+  if (!per_shot) grad[p] -= w * g;
 }
 
 __global__ void misfit_kernel(const double* __restrict__ tr, const double* __restrict__ ob, int64_t count,
@@ -962,7 +964,8 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     double* xs = xseg[b] + (k - k0 - 1) * m->n_x * NS;
     double* fs = fseg[b] + (k - k0 - 1) * m->n_params * NS;
     const double* us = ck->ustore ? ck->ustore + (k - 1) * m->n_nodes * NS : nullptr;
-    return sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, s, nullptr, us);
+    return sbfwi_forward_step(f, &fw, k, fsrc, 0, nullptr, nullptr, N, xs, fs, kind, s, nullptr, us,
+                              k < std::min(k0 + C, N));
   };
   auto recompute = [&](int64_t seg, int b, hipStream_t s) -> int {
     const int64_t k0 = seg * C, k1 = std::min(k0 + C, N);
@@ -1044,9 +1047,10 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         SBFWI_HIP(hipGetLastError());
       } else {
         const int64_t kp = N + 1 - k;  // back-propagation step paired with forward step k
-        SBFWI_CHECK(sbfwi_forward_step(f, &bw, kp, bsrc, 0, nullptr, nullptr, N, nullptr, nullptr, 0, st));
+        SBFWI_CHECK(sbfwi_forward_step(f, &bw, kp, bsrc, 0, nullptr, nullptr, N, nullptr, nullptr, 0, st, nullptr,
+                                       nullptr, kp < N));
         ProfScope ps(PK_GRAD_PAPER, st);
-        hipLaunchKernelGGL(grad_paper_kernel, dim3(gp), dim3(256), 0, st, m->d, NS, f->dt, m->n_params,
+        hipLaunchKernelGGL(grad_paper_kernel, dim3(gp), dim3(256), 0, st, m->d, NS, 1.0, m->n_params,
                            w.par_elem, (const double*)bw.v, (const double*)bw.V, Fs, grad, per_shot);
         SBFWI_HIP(hipGetLastError());
       }

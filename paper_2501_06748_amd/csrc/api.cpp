@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "sbfwi_internal.h"
 
@@ -72,12 +73,37 @@ void sbfwi_dev_free(void* p) {
 
 void sbfwi_factors_free(sbfwi_factors_s* f);
 
-// One non-blocking stream per host thread for the library's synchronous copies
-// (created on first use, kept until the process ends).
+// One non-blocking stream per host thread for the library's synchronous copies,
+// created on first use and registered so that sbfwi_finalize can destroy them
+// all; a thread's cached stream is recreated after a finalize (generation count).
+static std::mutex g_aux_mu;
+static std::vector<hipStream_t> g_aux_streams;
+static std::atomic<int> g_aux_gen{0};
+
 static hipStream_t aux_stream() {
   thread_local hipStream_t s = nullptr;
-  if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  thread_local int gen = -1;
+  const int cur = g_aux_gen.load();
+  if (s && gen == cur) return s;
+  s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return s = nullptr;
+  gen = cur;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  g_aux_streams.push_back(s);
   return s;
+}
+
+int sbfwi_prof_release();
+
+extern "C" int sbfwi_finalize(void) {
+  SBFWI_HIP(hipDeviceSynchronize());
+  int rc = sbfwi_prof_release();
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  g_aux_gen.fetch_add(1);
+  for (hipStream_t st : g_aux_streams)
+    if (hipStreamDestroy(st) != hipSuccess && rc == SBFWI_OK) rc = sbfwi_fail(SBFWI_EHIP, "hipStreamDestroy failed");
+  g_aux_streams.clear();
+  return rc;
 }
 
 int sbfwi_copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
@@ -171,6 +197,11 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
     f->keep_solutions = value;
     return SBFWI_OK;
   }
+  if (param == 5) {
+    if (value != 0 && value != 1) return sbfwi_fail(SBFWI_EINVAL, "joint sweep flag must be 0 or 1");
+    f->joint_sweeps = value;
+    return SBFWI_OK;
+  }
 
   if (param >= 10 && param < 10 + 3 * SW_N) {
     if (!valid_shots_per_block(value)) return sbfwi_fail(SBFWI_EINVAL, "shots per block must be 0, 1, 2, 4, 8 or 16");
@@ -197,7 +228,8 @@ extern "C" int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int 
   const int64_t coarse = 8 * (9 * m->n_nodes * NS + 4 * n_slices * 3 * NS + 3 * 11 * 16) +
                          4 * (64 + 32 * (n_slices / 16 + 2));
   const int64_t state = 8 * sbfwi_state_size(m, (int)NS);
-  const int64_t fwd_work = state + 8 * NS * (m->n_int + 2 * m->n_loop + 2 * m->n_nodes) + coarse + 8;
+  const int64_t fwd_work = state + 8 * NS * (m->n_int + 2 * m->n_loop + 2 * m->n_nodes) + coarse + 8 +
+                           8 * NS * n_steps;   // the growth envelope
   int64_t ckpt = 8 * NS * n_steps + 16 * NS + 8 * 64;   // copies of sources, wavelets, receivers (bounded)
   int64_t interval = 1;
   if (n_ckpt >= n_steps) {
@@ -293,6 +325,9 @@ extern "C" int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* out) {
   if (!ck || !out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   out[0] = ck->bytes;
   out[1] = ck->interval;
+  out[2] = ck->n_shots;
+  out[3] = ck->n_rec;
+  out[4] = ck->n_steps;
   return SBFWI_OK;
 }
 
@@ -301,6 +336,11 @@ static int read_status(sbfwi_factors_s* f, hipStream_t s, const char* what) {
   SBFWI_HIP(hipMemcpyAsync(flags, f->d.status, sizeof(flags), hipMemcpyDeviceToHost, s));
   SBFWI_HIP(hipStreamSynchronize(s));
   if (flags[0] & 8) return sbfwi_fail(SBFWI_EHIP, "%s: coarse-solve grid barrier timed out", what);
+  if (flags[0] & 32)
+    return sbfwi_fail(SBFWI_ENONFINITE, "%s: non-finite nodal displacement at step %d", what, flags[1]);
+  if (flags[0] & 16)
+    return sbfwi_fail(SBFWI_EUNSTABLE, "%s: nodal displacement beyond the growth envelope at step %d", what,
+                      flags[1]);
   if (flags[0] & 4) return sbfwi_fail(SBFWI_ENONFINITE, "%s: non-finite coarse residual at step %d", what, flags[1]);
   if (flags[0] & 2) return sbfwi_fail(SBFWI_ENOCONV, "%s: coarse solve did not converge at step %d", what, flags[1]);
   return SBFWI_OK;
@@ -312,6 +352,21 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
   sbfwi_mesh_s* m = f->m;
   SBFWI_CHECK(sbfwi_step_work_alloc(&w, m, n_shots));
   SBFWI_CHECK(sbfwi_step_zero(m, &w, s));
+  {
+    // growth envelope of the nodal displacement: kEnvelopeSafety * 4 k r F_k per shot and step
+    // (the wavelet was made ready on s by the caller; s was synchronised by the node checks)
+    std::vector<double> wav((size_t)n_shots * n_steps), env((size_t)n_shots * n_steps);
+    SBFWI_HIP(hipMemcpyAsync(wav.data(), wavelet, wav.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    SBFWI_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < n_shots; ++q) {
+      double F = 0.0;
+      for (int64_t k = 1; k <= n_steps; ++k) {
+        F += std::fabs(wav[(size_t)q * n_steps + k - 1]);
+        env[(size_t)(k - 1) * n_shots + q] = kEnvelopeSafety * 4.0 * (double)k * f->env_r * F;
+      }
+    }
+    SBFWI_CHECK(sbfwi_upload(&w.env, env));
+  }
   int flags0[4] = {0, -1, 0, 0};
   SBFWI_HIP(hipMemcpyAsync(f->d.status, flags0, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   const int64_t ssz = sbfwi_state_size(m, n_shots);
@@ -372,7 +427,8 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
       fs = ck->fstore + (k - 1) * m->n_params * n_shots;
       vs = ck->vstore + (k - 1) * m->n_params * n_shots;
     }
-    SBFWI_CHECK(sbfwi_forward_step(f, &w, k, src, n_rec, rec_node, traces, n_steps, xs, fs, 0, s, vs));
+    SBFWI_CHECK(sbfwi_forward_step(f, &w, k, src, n_rec, rec_node, traces, n_steps, xs, fs, 0, s, vs, nullptr,
+                                   k < n_steps));
   }
   return read_status(f, s, "forward");
 }

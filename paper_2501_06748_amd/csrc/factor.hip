@@ -688,6 +688,15 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
     sbfwi_factors_free(f);
     return sbfwi_fail(SBFWI_ESINGULAR, "a pivot block of the condensation sweep is singular");
   }
+  {   // response scale of the growth envelope: the largest 1 / |K_g,ii|
+    std::vector<double> di(m->n_nodes);
+    rc = sbfwi_copy_sync(di.data(), d.diag_inv, sizeof(double) * m->n_nodes, hipMemcpyDeviceToHost);
+    if (rc != SBFWI_OK) {
+      sbfwi_factors_free(f);
+      return rc;
+    }
+    for (double v : di) f->env_r = std::max(f->env_r, std::fabs(v));
+  }
   if (coarse_solver == 1) {
     rc = sbfwi_direct_factor(f, s);
     if (rc != SBFWI_OK) {

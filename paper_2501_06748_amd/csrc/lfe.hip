@@ -171,7 +171,7 @@ int sbfwi_lfe_adjoint(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_sr
   if (rc == SBFWI_OK) {
     const int64_t stride = per_shot ? m->n_params : 0;
     hipLaunchKernelGGL(lfe_scatter_kernel, dim3((unsigned)((m->n_elem + 7) / 8)), dim3(32, 8), 0, s, m->d, NS,
-                       corr, -f->dt, grad, stride);
+                       corr, -1.0, grad, stride);   // adj_src = dt (u - d): the rectangle rule's dt is in corr
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = sbfwi_fail(SBFWI_EHIP, "gradient scatter: %s", hipGetErrorString(e));

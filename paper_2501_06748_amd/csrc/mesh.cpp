@@ -281,6 +281,7 @@ extern "C" int sbfwi_build_mesh(const double* node_xy, int64_t n_nodes, const in
   for (int32_t e : by_cost) {
     int c = m->h_nb[e] <= 8 ? 0 : (m->h_nb[e] <= 16 ? 1 : 2);
     m->h_class_elems[c].push_back(e);
+    m->class_nmax[c] = std::max(m->class_nmax[c], m->h_nr[e] - 1);
   }
   m->h_elem_by_cost = by_cost;
   m->d.n_nodes = n_nodes;

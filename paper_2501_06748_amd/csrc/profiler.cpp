@@ -83,6 +83,22 @@ extern "C" int sbfwi_profile(uint32_t kernel_mask) {
   return SBFWI_OK;
 }
 
+// Destroys every event of the pool and of the pending pairs (their times are
+// discarded) and switches timing off.
+int sbfwi_prof_release() {
+  int rc = SBFWI_OK;
+  g_prof.mask = 0;
+  for (auto& p : g_prof.pending) {
+    g_prof.pool.push_back(p.a);
+    g_prof.pool.push_back(p.b);
+  }
+  g_prof.pending.clear();
+  for (hipEvent_t e : g_prof.pool)
+    if (hipEventDestroy(e) != hipSuccess) rc = sbfwi_fail(SBFWI_EHIP, "hipEventDestroy failed");
+  g_prof.pool.clear();
+  return rc;
+}
+
 extern "C" int sbfwi_profile_read(double* out, int reset) {
   if (!out) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
   SBFWI_CHECK(drain(g_prof.pending.size()));

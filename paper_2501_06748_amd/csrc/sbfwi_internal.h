@@ -121,6 +121,7 @@ struct sbfwi_mesh_s {
   std::vector<int64_t> h_loop_off, h_par_off, h_int_off, h_x_off, h_finv_off, h_dense_off;
   std::vector<int64_t> h_row_ptr, h_col64;
   std::vector<int32_t> h_class_elems[3];
+  int class_nmax[3] = {0, 0, 0};   // most interior levels of an element of each class
   std::vector<int32_t> h_elem_by_cost;
   MeshDev d;
   int32_t* class_elems[3] = {nullptr, nullptr, nullptr};   // elements with nb <= 8, 16, 24
@@ -204,9 +205,11 @@ struct sbfwi_factors_s {
   int use_graphs = 0;            // forward runs replay each time step from HIP graphs
   int overlap_adjoint = 1;       // recompute the next checkpoint segment while the adjoint runs the current one
   int keep_solutions = 1;        // forward runs with checkpoints keep every step's coarse solution
+  int joint_sweeps = 1;          // recover of step k and condense of step k + 1 in one sweep
   int scheme = 0;                // radial scheme (SBFWI_SCHEME_*)
   SweepPlan plan;
   DirectNum* dnum = nullptr;     // direct factors of K_g (coarse solver 1), else BiCGStab
+  double env_r = 0;              // largest 1 / |K_g,ii|: response scale of the growth envelope
   int64_t bytes = 0;
   FactorsDev d;
 };
@@ -227,13 +230,18 @@ struct sbfwi_ckpt_s {
   double* ustore = nullptr;      // optional: [n_steps][n_nodes*NS] coarse solutions (the recompute skips its solves)
 };
 
+// Growth envelope of a forward run (api.cpp): the nodal displacement of shot s at
+// step k may not exceed kEnvelopeSafety * 4 k r F_k(s), r = env_r of the factors and
+// F_k(s) the sum of |point forces| of shot s up to step k.
+constexpr double kEnvelopeSafety = 10.0;
+
 // ---- live kernel timing (profiler.cpp) ----
 #define SBFWI_PROF_KERNELS 20
 enum {
   PK_CONDENSE = 0, PK_RECOVER = 1, PK_SOLVE = 2, PK_RHS = 3, PK_NODAL = 4, PK_ADJ_CONDENSE = 5,
   PK_ADJ_RECOVER = 6, PK_ADJ_RHS = 7, PK_ADJ_NODAL = 8, PK_GRAD_EXACT = 9, PK_GRAD_PAPER = 10,
   PK_FACTOR = 11, PK_SOLVE_V = 12, PK_SOLVE_T = 13, PK_SOLVE_X = 14, PK_SOLVE_INIT = 15,
-  PK_RECOVER_STORE = 16, PK_FEM_STEP = 17
+  PK_RECOVER_STORE = 16, PK_FEM_STEP = 17, PK_JOINT = 18, PK_JOINT_STORE = 19
 };
 // Brackets the launches made during its lifetime with events on stream s when
 // kernel id is enabled by sbfwi_profile.
@@ -320,7 +328,11 @@ struct StepWork {
   double* corr = nullptr;                               // predictor correction of the coarse solve
   double *q = nullptr, *yn = nullptr, *fhat = nullptr, *F = nullptr, *Unew = nullptr;
   double* ustore = nullptr;   // optional: every step's coarse solution, [n_steps][n_nodes*NS]
+  double* env = nullptr;      // optional: growth envelope of the nodal displacement, [n_steps][NS] (owned)
   CoarseWork cw;
+  // the swept sources (q, y_n, f_hat) of the next step are already computed (by a
+  // joint sweep); reset whenever the state is replaced
+  bool condensed = false;
   // graph replay of a time step: device step counter and the two captured halves
   int64_t* kdev = nullptr;
   hipGraphExec_t g_pre = nullptr, g_post = nullptr;
@@ -341,7 +353,9 @@ struct SourceTable {
   int reversed = 0;
 };
 
-// One forward step k: condense, assemble, coarse solve, nodal update, recover.
+// One forward step k: condense (unless a joint sweep of step k - 1 did it), assemble,
+// coarse solve, nodal update, recover; with next = true (step k + 1 follows on
+// the same work buffers) the recover sweep also condenses step k + 1.
 // Optional stores (nullptr = skip): unknowns with ghosts (xs) and a level field
 // (fs: a^k when field_kind = 0, v^k when field_kind = 1); receiver traces.
 // usol (optional): the step's coarse solution, kept by an earlier run of the
@@ -349,7 +363,7 @@ struct SourceTable {
 int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceTable& src,
                        int n_rec, const int64_t* rec_node, double* traces, int64_t n_steps,
                        double* xs, double* fs, int field_kind, hipStream_t s, double* vs = nullptr,
-                       const double* usol = nullptr);
+                       const double* usol = nullptr, bool next = false);
 int sbfwi_state_copy(sbfwi_mesh_s* m, StepWork* w, double* dst, int to_store, hipStream_t s);
 // Graph replay of forward steps (no per-step stores): the first call captures
 // the step on stream s (which must not be the null stream) into two graphs

@@ -95,9 +95,19 @@ __device__ __forceinline__ double dense_mv(const double* F, const double* vec, i
 // unconditionally and the waits for the prefetched level count exactly.
 __device__ double g_sink[WT];
 
-template <int NBT, int S>
+// Newmark combination w = a0 u + a1 v + a2 a (eq. ODE_Newmark), written with
+// explicit multiply-adds so that every sweep that forms it rounds it alike.
+__device__ __forceinline__ double newmark_w(const FactorsDev& f, double u, double v, double a) {
+  return fma(f.a2, a, fma(f.a1, v, f.a0 * u));
+}
+
+// JOINT: the interior levels' w comes from wkeep (LDS, level-major, written by
+// the recover sweep of the previous step in the same block) instead of the
+// state in HBM; the boundary level always takes the nodal state.
+template <int NBT, int S, bool JOINT = false>
 __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
-                                              const StepArgs& a, StepLds<NBT, S>& L) {
+                                              const StepArgs& a, StepLds<NBT, S>& L,
+                                              const double* wkeep = nullptr) {
   // Levels j = 0 .. n-1 stream: the next level's F block, state (u, v, a; on the
   // boundary level the nodal state) and bands P, theta are loaded at the top of
   // each level and consumed at its end; lanes without an item load word 0 of
@@ -135,9 +145,13 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
     for (int u = 0; u < IPT; ++u) {
       const int64_t row = nodal ? lnode[u] : io + (int64_t)j * nb + ii[u];
       const int64_t g = ok[u] ? row * a.NS + s0 + si[u] : 0;
-      uu[u] = su[g];
-      vv[u] = sv[g];
-      aa[u] = sa[g];
+      if (JOINT && !nodal) {   // interior w from wkeep: no state loads
+        uu[u] = vv[u] = aa[u] = 0.0;
+      } else {
+        uu[u] = su[g];
+        vv[u] = sv[g];
+        aa[u] = sa[g];
+      }
       if constexpr (!kBandShfl) {
         const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb) + ii[u];   // node 0 for lanes without an item
         const double* tp = f.th_band + 3 * (po + (int64_t)j * nb) + ii[u];
@@ -160,7 +174,8 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int it = threadIdx.x + u * WT;
-      if (own[u]) L.w[it] = ok[u] ? f.a0 * cu[u] + f.a1 * cv[u] + f.a2 * ca[u] : 0.0;
+      if (own[u])
+        L.w[it] = JOINT && j < n ? wkeep[j * items + it] : (ok[u] ? newmark_w(f, cu[u], cv[u], ca[u]) : 0.0);
     }
     __syncthreads();
 #pragma unroll
@@ -244,9 +259,11 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
 // consumed at its end, so the sweep streams without waiting on the level
 // recursion; the loads of lanes without an item read word 0 and the stores
 // of such lanes go to g_sink.
+// wkeep (LDS, may be NULL): receives the new w of every interior level,
+// wkeep[j * items + it], for the condense of the next step in the same block.
 template <int NBT, int S, bool STORE>
 __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, const FactorsDev& f,
-                                               const StepArgs& a, StepLds<NBT, S>& L) {
+                                               const StepArgs& a, StepLds<NBT, S>& L, double* wkeep) {
   constexpr int IPT = (NBT * S + WT - 1) / WT;
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
@@ -316,9 +333,10 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
       const int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
       const double uj = ok[u] ? cq[u] - dense_mv<NBT>(L.F[cur], L.t, nb, i, s, S) : 0.0;
       const double uo = cu[u], vo = cv[u], ao = ca[u];
-      const double w = f.a0 * uo + f.a1 * vo + f.a2 * ao;
+      const double w = newmark_w(f, uo, vo, ao);
       const double vn = f.c1 * (uj - uo) + f.c2 * vo + f.c3 * ao;
       const double an = f.a0 * uj - w;
+      if (wkeep && own[u]) wkeep[j * items + it] = ok[u] ? newmark_w(f, uj, vn, an) : 0.0;
       double* sink = g_sink + threadIdx.x;
       *(ok[u] ? a.u + g : sink) = uj;
       *(ok[u] ? a.v + g : sink) = vn;
@@ -356,7 +374,8 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
 // with ghosts and the level field for the adjoint (a.xs, a.fs, a.vs).
 template <int NBT, int S, bool STORE>
 __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
-                                             const StepArgs& a, StepLds<NBT, S>& L) {
+                                             const StepArgs& a, StepLds<NBT, S>& L,
+                                             double* wkeep = nullptr) {
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e], xo = m.x_off[e];
@@ -380,7 +399,7 @@ __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, co
     }
   }
   __syncthreads();
-  recover_levels<NBT, S, STORE>(e, s0, m, f, a, L);
+  recover_levels<NBT, S, STORE>(e, s0, m, f, a, L, wkeep);
   if (!STORE) return;
   // ghosts: u_{-1} = theta_{-1}^-1 (-(phi_{-1} u_0 + psi_{-1} u_1)),
   //         u_{n+1} = psi_n^-1 (y_n - phi~_n u_n)
@@ -436,6 +455,24 @@ __global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__
   recover_body<NBT, S, STORE>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
 }
 
+// Joint sweep of one (element, group of S shots): the recover sweep of step k
+// (down the levels), which keeps every level's new w in LDS, then the condense
+// sweep of step k + 1 (up the levels) from that w and the nodal state already
+// updated by step k.  Every value is computed by the same expressions as in the
+// two separate sweeps, so the results are bit-identical; the state u, v, a is
+// read and written once per step instead of read twice, and one launch is saved.
+template <int NBT, int S, bool STORE>
+__global__ void __launch_bounds__(WT) joint_kernel(const int32_t* __restrict__ elems, MeshDev m, FactorsDev f,
+                                                   StepArgs a) {
+  __shared__ StepLds<NBT, S> L;
+  extern __shared__ double wkeep[];   // [interior levels][n_b * S] of the element
+  const int e = elems[blockIdx.x];
+  const int s0 = blockIdx.y * S;
+  recover_body<NBT, S, STORE>(e, s0, m, f, a, L, wkeep);
+  __syncthreads();
+  condense_body<NBT, S, true>(e, s0, m, f, a, L, wkeep);
+}
+
 // One persistent launch over all n_b classes: the blocks walk the work items
 // (element, group of S shots) in order of decreasing cost (N_r n_b^2), item
 // w = blockIdx.x + i gridDim.x; each item runs the body of its element's class
@@ -487,20 +524,29 @@ __global__ void rhs_kernel(MeshDev m, int NS, const double* __restrict__ fhat, d
   Unew[g] = U[g] + dt * V[g] + 0.5 * dt * dt * A[g] + corr[g];
 }
 
-// Nodal Newmark update, predictor correction and receiver sampling.
+// Nodal Newmark update, predictor correction and receiver sampling.  With env
+// (growth envelope of the run, [n_steps][NS]) every new nodal displacement is
+// checked against the bound of its step and shot: a non-finite value sets status
+// bit 32, a finite one beyond the bound bit 16, and the first such step is kept
+// in status[1].
 __global__ void nodal_kernel(int64_t n_nodes, int NS, FactorsDev f, const double* __restrict__ Unew,
                              double* __restrict__ U, double* __restrict__ V, double* __restrict__ A,
                              double* __restrict__ corr,
                              int n_rec, const int64_t* __restrict__ rec_node, double* __restrict__ traces,
                              int64_t n_steps, int64_t k, const int64_t* __restrict__ kdev,
-                             double* __restrict__ ustore) {
+                             double* __restrict__ ustore, const double* __restrict__ env,
+                             int* __restrict__ status) {
   if (kdev) k = *kdev;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nn = n_nodes * NS;
   if (g < nn) {
     double uo = U[g], vo = V[g], ao = A[g], un = Unew[g];
+    if (env && !(fabs(un) <= env[(k - 1) * NS + g % NS])) {
+      atomicOr(&status[0], isfinite(un) ? 16 : 32);
+      atomicCAS(&status[1], -1, (int)k);
+    }
     if (ustore) ustore[(k - 1) * nn + g] = un;
-    double w = f.a0 * uo + f.a1 * vo + f.a2 * ao;
+    double w = newmark_w(f, uo, vo, ao);
     corr[g] = un - (uo + f.dt * vo + 0.5 * f.dt * f.dt * ao);
     V[g] = f.c1 * (un - uo) + f.c2 * vo + f.c3 * ao;
     A[g] = f.a0 * un - w;
@@ -583,6 +629,69 @@ void launch_sweep(bool condense, sbfwi_factors_s* fac, const StepArgs& a, hipStr
   launch_step_sweep(condense, fac->m, fac->d, fac->plan, a, st);
 }
 
+// LDS of a joint-sweep block (the static sweep buffers and the kept w of the
+// class's deepest element) is held within this bound; larger classes run the
+// two sweeps one after the other.
+constexpr size_t kJointLdsMax = 48 * 1024;
+
+template <int NBT, int S>
+bool launch_joint_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
+  const int64_t cnt = (int64_t)m->h_class_elems[cl].size();
+  if (cnt == 0) return true;
+  const size_t dyn = (size_t)m->class_nmax[cl] * NBT * S * sizeof(double);
+  if (sizeof(StepLds<NBT, S>) + dyn > kJointLdsMax) return false;
+  dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  if (a.xs)
+    hipLaunchKernelGGL((joint_kernel<NBT, S, true>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+  else
+    hipLaunchKernelGGL((joint_kernel<NBT, S, false>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+  return true;
+}
+
+template <int NBT>
+bool launch_joint_s(sbfwi_mesh_s* m, int cl, int S, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
+  switch (S) {
+    case 1: return launch_joint_cls<NBT, 1>(m, cl, f, a, st);
+    case 2: return launch_joint_cls<NBT, 2>(m, cl, f, a, st);
+    case 4: return launch_joint_cls<NBT, 4>(m, cl, f, a, st);
+    case 8: return launch_joint_cls<NBT, 8>(m, cl, f, a, st);
+    default: return launch_joint_cls<NBT, 16>(m, cl, f, a, st);
+  }
+}
+
+// Recover of step k and condense of step k + 1: one joint launch per n_b class
+// with the recover sweep's shots per block, or, where its LDS would not fit or
+// the plan runs a sweep as one persistent launch, the two sweeps in turn.
+void launch_joint(sbfwi_factors_s* fac, const StepArgs& a, hipStream_t st) {
+  sbfwi_mesh_s* m = fac->m;
+  const SweepPlan& plan = fac->plan;
+  if (plan.fusedS[SW_RECOVER] > 0 || plan.fusedS[SW_CONDENSE] > 0) {
+    launch_sweep(false, fac, a, st);
+    launch_sweep(true, fac, a, st);
+    return;
+  }
+  ProfScope ps(a.xs ? PK_JOINT_STORE : PK_JOINT, st);
+  const int def = sbfwi_default_shots_per_block(a.NS);
+  for (int cl = 0; cl < 3; ++cl) {
+    const int S = plan.S[SW_RECOVER][cl] > 0 ? plan.S[SW_RECOVER][cl] : def;
+    const bool ok = cl == 0 ? launch_joint_s<8>(m, cl, S, fac->d, a, st)
+                            : cl == 1 ? launch_joint_s<16>(m, cl, S, fac->d, a, st)
+                                      : launch_joint_s<24>(m, cl, S, fac->d, a, st);
+    if (ok) continue;
+    const int Sc = plan.S[SW_CONDENSE][cl] > 0 ? plan.S[SW_CONDENSE][cl] : def;
+    if (cl == 0) {
+      launch_cr_s<8>(false, m, cl, S, fac->d, a, st);
+      launch_cr_s<8>(true, m, cl, Sc, fac->d, a, st);
+    } else if (cl == 1) {
+      launch_cr_s<16>(false, m, cl, S, fac->d, a, st);
+      launch_cr_s<16>(true, m, cl, Sc, fac->d, a, st);
+    } else {
+      launch_cr_s<24>(false, m, cl, S, fac->d, a, st);
+      launch_cr_s<24>(true, m, cl, Sc, fac->d, a, st);
+    }
+  }
+}
+
 }  // namespace
 
 // interior u, v, a; nodal U, V, A and the predictor correction of the coarse solve
@@ -617,6 +726,7 @@ void sbfwi_step_work_free(StepWork* w) {
   sbfwi_dev_free(w->Unew);
   sbfwi_coarse_work_free(&w->cw);
   sbfwi_dev_free(w->kdev);
+  sbfwi_dev_free(w->env);
   if (w->g_pre) (void)hipGraphExecDestroy(w->g_pre);
   if (w->g_post) (void)hipGraphExecDestroy(w->g_post);
   *w = StepWork();
@@ -624,15 +734,18 @@ void sbfwi_step_work_free(StepWork* w) {
 
 int sbfwi_step_zero(sbfwi_mesh_s* m, StepWork* w, hipStream_t s) {
   SBFWI_HIP(hipMemsetAsync(w->u, 0, sizeof(double) * sbfwi_state_size(m, w->NS), s));
+  w->condensed = false;
   return SBFWI_OK;
 }
 
 int sbfwi_state_copy(sbfwi_mesh_s* m, StepWork* w, double* dst, int to_store, hipStream_t s) {
   size_t bytes = sizeof(double) * sbfwi_state_size(m, w->NS);
-  if (to_store)
+  if (to_store) {
     SBFWI_HIP(hipMemcpyAsync(dst, w->u, bytes, hipMemcpyDeviceToDevice, s));
-  else
+  } else {
     SBFWI_HIP(hipMemcpyAsync(w->u, dst, bytes, hipMemcpyDeviceToDevice, s));
+    w->condensed = false;   // a new state: its sources are not swept yet
+  }
   return SBFWI_OK;
 }
 
@@ -648,11 +761,10 @@ StepArgs step_args(StepWork* w, double* xs, double* fs, int field_kind, double* 
   return a;
 }
 
-// condense, gather of the coarse right-hand side and initial guess
-int step_pre(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, const int64_t* kdev,
+// gather of the coarse right-hand side and initial guess
+int step_rhs(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, const int64_t* kdev,
              const SourceTable& src, hipStream_t st) {
   sbfwi_mesh_s* m = f->m;
-  launch_sweep(true, f, a, st);
   int64_t nn = m->n_nodes * w->NS;
   {
     ProfScope ps(PK_RHS, st);
@@ -663,9 +775,9 @@ int step_pre(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, cons
   return SBFWI_OK;
 }
 
-// nodal Newmark update, receivers, recover (a.Unew: the step's coarse solution)
-int step_post(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, const int64_t* kdev, int n_rec,
-              const int64_t* rec_node, double* traces, int64_t n_steps, hipStream_t st) {
+// nodal Newmark update and receivers (a.Unew: the step's coarse solution)
+int step_nodal(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, const int64_t* kdev, int n_rec,
+               const int64_t* rec_node, double* traces, int64_t n_steps, hipStream_t st) {
   sbfwi_mesh_s* m = f->m;
   int64_t nn = m->n_nodes * w->NS;
   int64_t tot = nn + (int64_t)n_rec * w->NS;
@@ -673,9 +785,22 @@ int step_post(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, con
     ProfScope ps(PK_NODAL, st);
     hipLaunchKernelGGL(nodal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m->n_nodes, w->NS,
                        f->d, a.Unew, w->U, w->V, w->A, w->corr, n_rec, rec_node, traces, n_steps, k, kdev,
-                       w->ustore);
+                       w->ustore, w->env, f->d.status);
   }
-  launch_sweep(false, f, a, st);
+  SBFWI_HIP(hipGetLastError());
+  return SBFWI_OK;
+}
+
+// the recover sweep of the step, joined with the condense of the next one when
+// it follows and joint sweeps are on; returns whether the next step is condensed
+int step_sweeps(sbfwi_factors_s* f, const StepArgs& a, bool next, hipStream_t st, bool* condensed) {
+  if (next && f->joint_sweeps) {
+    launch_joint(f, a, st);
+    *condensed = true;
+  } else {
+    launch_sweep(false, f, a, st);
+    *condensed = false;
+  }
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;
 }
@@ -702,16 +827,17 @@ int capture(hipStream_t st, hipGraphExec_t* out, const std::function<int()>& bod
 
 int sbfwi_forward_step(sbfwi_factors_s* f, StepWork* w, int64_t k, const SourceTable& src, int n_rec,
                        const int64_t* rec_node, double* traces, int64_t n_steps, double* xs, double* fs,
-                       int field_kind, hipStream_t st, double* vs, const double* usol) {
+                       int field_kind, hipStream_t st, double* vs, const double* usol, bool next) {
   StepArgs a = step_args(w, xs, fs, field_kind, vs);
-  if (usol) {   // the coarse solution is known: condense (for q and y_n), then nodal update and recover
+  if (!w->condensed) launch_sweep(true, f, a, st);
+  if (usol) {   // the coarse solution is known: no gather, no coarse solve
     a.Unew = const_cast<double*>(usol);   // read only by the nodal update and the recover sweep
-    launch_sweep(true, f, a, st);
-    return step_post(f, w, a, k, nullptr, n_rec, rec_node, traces, n_steps, st);
+  } else {
+    SBFWI_CHECK(step_rhs(f, w, a, k, nullptr, src, st));
+    SBFWI_CHECK(sbfwi_coarse_solve(f, &w->cw, 0, w->F, w->Unew, k, st));
   }
-  SBFWI_CHECK(step_pre(f, w, a, k, nullptr, src, st));
-  SBFWI_CHECK(sbfwi_coarse_solve(f, &w->cw, 0, w->F, w->Unew, k, st));
-  return step_post(f, w, a, k, nullptr, n_rec, rec_node, traces, n_steps, st);
+  SBFWI_CHECK(step_nodal(f, w, a, k, nullptr, n_rec, rec_node, traces, n_steps, st));
+  return step_sweeps(f, a, next, st, &w->condensed);
 }
 
 int sbfwi_graph_step_reset(StepWork* w, int64_t k, hipStream_t st) {
@@ -723,14 +849,21 @@ int sbfwi_graph_step_reset(StepWork* w, int64_t k, hipStream_t st) {
 int sbfwi_forward_step_graph(sbfwi_factors_s* f, StepWork* w, const SourceTable& src, int n_rec,
                              const int64_t* rec_node, double* traces, int64_t n_steps, hipStream_t st) {
   const StepArgs a = step_args(w, nullptr, nullptr, 0, nullptr);
+  // with joint sweeps each replayed step ends by condensing the next one (the last
+  // step's is unused), so only the first step needs a condense of its own
+  const bool joint = f->joint_sweeps != 0;
   if (!w->g_pre) {
+    if (joint && !w->condensed) launch_sweep(true, f, a, st);
     SBFWI_CHECK(capture(st, &w->g_pre, [&]() -> int {
-      SBFWI_CHECK(step_pre(f, w, a, 0, w->kdev, src, st));
+      if (!joint) launch_sweep(true, f, a, st);
+      SBFWI_CHECK(step_rhs(f, w, a, 0, w->kdev, src, st));
       return sbfwi_coarse_solve_parts(f, &w->cw, 0, w->F, w->Unew, 0, w->kdev, 1, st);
     }));
     SBFWI_CHECK(capture(st, &w->g_post, [&]() -> int {
       SBFWI_CHECK(sbfwi_coarse_solve_parts(f, &w->cw, 0, w->F, w->Unew, 0, w->kdev, 4, st));
-      SBFWI_CHECK(step_post(f, w, a, 0, w->kdev, n_rec, rec_node, traces, n_steps, st));
+      SBFWI_CHECK(step_nodal(f, w, a, 0, w->kdev, n_rec, rec_node, traces, n_steps, st));
+      bool cd = false;
+      SBFWI_CHECK(step_sweeps(f, a, joint, st, &cd));
       hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, w->kdev);
       SBFWI_HIP(hipGetLastError());
       return SBFWI_OK;
@@ -739,6 +872,7 @@ int sbfwi_forward_step_graph(sbfwi_factors_s* f, StepWork* w, const SourceTable&
   SBFWI_HIP(hipGraphLaunch(w->g_pre, st));
   SBFWI_CHECK(sbfwi_coarse_solve_parts(f, &w->cw, 0, w->F, w->Unew, 0, w->kdev, 2, st));
   SBFWI_HIP(hipGraphLaunch(w->g_post, st));
+  w->condensed = joint;
   return SBFWI_OK;
 }
 

@@ -19,9 +19,10 @@ def rel_l2(a, b):
 
 
 class GpuModel:
-    """Mesh + factors of a workload model on cuda:0."""
+    """Mesh + factors of a workload model on cuda:0 (by default with the library's
+    default coarse solver, the direct one)."""
 
-    def __init__(self, wl, rho, dt=None, coarse_solver=0, scheme=0):
+    def __init__(self, wl, rho, dt=None, coarse_solver=1, scheme=0):
         import torch
         import paper_2501_06748_amd as sb
         self.sb, self.torch, self.wl = sb, torch, wl

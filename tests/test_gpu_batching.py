@@ -57,8 +57,14 @@ def test_sweep_plans_bit_identical(name):
     variants = [("S=%d" % S, [(sb_.launch_param_shots(k, c), S) for k in range(4) for c in range(3)])
                 for S in (1, 2, 4, 8, 16)]
     variants += [("fused S=%d" % S, [(sb_.launch_param_fused(k), S) for k in range(4)]) for S in (1, 4, 16)]
+    # the recover and condense sweeps of consecutive steps run one after the other
+    # instead of as one joint sweep (the default), also with other plans
+    variants += [("separate sweeps", [(sb_.LAUNCH_JOINT_SWEEPS, 0)]),
+                 ("separate sweeps S=2", [(sb_.LAUNCH_JOINT_SWEEPS, 0)] +
+                  [(sb_.launch_param_shots(k, c), 2) for k in range(4) for c in range(3)])]
     for label, params in variants:
         sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_RESET_PLAN, 0)
+        sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_JOINT_SWEEPS, 1)
         for p, v in params:
             sb_.sbfwi_set_launch(g.f, p, v)
         tr, mis, gr, _ = g.gradient(obs, n_steps=steps)
@@ -66,6 +72,7 @@ def test_sweep_plans_bit_identical(name):
         log(f"  {label}: bit-identical {same}")
         assert same
     sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_RESET_PLAN, 0)
+    sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_JOINT_SWEEPS, 1)
 
 
 def test_autotuned_plan_and_graph_replay_bit_identical():
@@ -83,13 +90,16 @@ def test_autotuned_plan_and_graph_replay_bit_identical():
     tr1, mis1, g1, _ = g.gradient(obs, n_steps=steps)
     assert np.array_equal(tr1, tr0) and np.array_equal(g1, g0) and mis1 == mis0
     sb.sbfwi_set_launch(g.f, sb.LAUNCH_GRAPHS, 1)
-    for rep in range(2):   # every step replays the captured graphs; the run itself is repeated
-        trg, ck = g.forward(n_steps=steps, n_ckpt=0)
-        assert np.array_equal(trg.cpu().numpy(), tr0), f"graph replay run {rep} differs"
-        trg2, misg, gg, _ = g.gradient(obs, n_steps=steps)
-        assert np.array_equal(trg2, tr0) and np.array_equal(gg, g0) and misg == mis0
-    log("graph replay: forward traces and gradients bit-identical over two runs")
+    for joint in (1, 0):   # graphs of joint sweeps (default) and of separate ones
+        sb.sbfwi_set_launch(g.f, sb.LAUNCH_JOINT_SWEEPS, joint)
+        for rep in range(2):   # every step replays the captured graphs; the run itself is repeated
+            trg, ck = g.forward(n_steps=steps, n_ckpt=0)
+            assert np.array_equal(trg.cpu().numpy(), tr0), f"graph replay run {rep} differs (joint {joint})"
+            trg2, misg, gg, _ = g.gradient(obs, n_steps=steps)
+            assert np.array_equal(trg2, tr0) and np.array_equal(gg, g0) and misg == mis0
+    log("graph replay: forward traces and gradients bit-identical over two runs, joint and separate sweeps")
     sb.sbfwi_set_launch(g.f, sb.LAUNCH_GRAPHS, 0)
+    sb.sbfwi_set_launch(g.f, sb.LAUNCH_JOINT_SWEEPS, 1)
 
 
 def test_batched_shots_equal_per_shot_and_oracle():

@@ -42,7 +42,7 @@ def test_lfe_factor_and_forward_parity(cfg):
     wl = W.config_tiny(200) if cfg == "tiny" else _cvt_small(120)
     rho = wl.models["random30"]
     log(f"lfe parity {cfg}: {wl.mesh.n_elem} elements, {wl.n_steps} steps")
-    om = olfe.LfeModel(wl.mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0)
+    om = olfe.LfeModel(wl.mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0, method="condensed")
     ref = olfe.lfe_forward(om, wl.src_nodes, wl.wavelets, wl.rec_nodes, wl.n_steps)
     for solver in (1, 0):
         g = GpuModel(wl, rho, coarse_solver=solver, scheme=LFE)
@@ -92,12 +92,12 @@ def test_lfe_full_size_8000_cells():
 def test_lfe_paper_kernel_gradient_parity(cfg):
     wl = W.config_tiny(120) if cfg == "tiny" else _cvt_small(100)
     rho = wl.models["random30"]
-    om0 = olfe.LfeModel(wl.mesh, rho * 0.9, wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0)
+    om0 = olfe.LfeModel(wl.mesh, rho * 0.9, wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0, method="condensed")
     obs = olfe.lfe_forward(om0, wl.src_nodes, wl.wavelets, wl.rec_nodes, wl.n_steps)
     log(f"lfe paper-kernel gradient parity {cfg}")
     g = GpuModel(wl, rho, coarse_solver=1, scheme=LFE)
     tr, mis, grad, _ = g.gradient(obs, n_ckpt=-1, mode=1)
-    om = olfe.LfeModel(wl.mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0)
+    om = olfe.LfeModel(wl.mesh, rho, wl.c, wl.dt, wl.beta, wl.gamma, wl.xi0, method="condensed")
     gref, tref = olfe.lfe_paper_kernel_gradient(om, wl.src_nodes, wl.wavelets, wl.rec_nodes, obs, wl.n_steps)
     err = rel_l2(grad, gref)
     log(f"  traces {rel_l2(tr, tref):.3e}, gradient relative L2 {err:.3e}")

@@ -67,13 +67,15 @@ def test_factor_parity(cfg):
     assert rel_l2(Kv, K_or) <= 1e-11
 
 
-@pytest.mark.parametrize("cfg,model,steps", [("tiny", "homogeneous", 200), ("tiny", "random30", 120),
-                                             ("small", "random30", 60), ("quadtree", "random30", 40)])
-def test_forward_parity(cfg, model, steps):
+@pytest.mark.parametrize("cfg,model,steps,solver", [("tiny", "homogeneous", 200, 1), ("tiny", "random30", 120, 1),
+                                                    ("small", "random30", 60, 1), ("quadtree", "random30", 40, 1),
+                                                    ("tiny", "random30", 120, 0), ("quadtree", "random30", 40, 0)])
+def test_forward_parity(cfg, model, steps, solver):
     wl = {"tiny": W.config_tiny, "small": W.config_small, "quadtree": W.config_quadtree_tiny}[cfg]()
     rho = wl.models[model]
-    log(f"forward parity {cfg}/{model}: {wl.mesh.n_elem} el, {wl.n_shots} shots, {steps} steps")
-    g = GpuModel(wl, rho)
+    log(f"forward parity {cfg}/{model}: {wl.mesh.n_elem} el, {wl.n_shots} shots, {steps} steps, "
+        f"coarse solver {solver}")
+    g = GpuModel(wl, rho, coarse_solver=solver)
     tr, _ = g.forward(n_steps=steps)
     tr = tr.cpu().numpy()
     om = _oracle_model(wl, rho)
@@ -103,14 +105,14 @@ def _observed(wl, steps):
     return ostp.forward(om, wl.src_nodes, wl.wavelets[:, :steps], wl.rec_nodes, steps)
 
 
-@pytest.mark.parametrize("ckpt", [-1, 7])
-def test_exact_gradient_parity(ckpt):
+@pytest.mark.parametrize("ckpt,solver", [(-1, 1), (7, 1), (-1, 0)])
+def test_exact_gradient_parity(ckpt, solver):
     wl = W.config_tiny(n_steps=48)
     steps = 48
     rho = wl.models["random30"]
     obs = _observed(wl, steps)
-    log(f"exact gradient parity tiny, {steps} steps, n_ckpt={ckpt}")
-    g = GpuModel(wl, rho)
+    log(f"exact gradient parity tiny, {steps} steps, n_ckpt={ckpt}, coarse solver {solver}")
+    g = GpuModel(wl, rho, coarse_solver=solver)
     tr, mis, grad, _ = g.gradient(obs, n_steps=steps, n_ckpt=ckpt, mode=0)
     om = _oracle_model(wl, rho)
     gref, Jref = oadj.exact_gradient(om, wl.src_nodes, wl.wavelets[:, :steps], wl.rec_nodes, obs, steps)

@@ -7,8 +7,12 @@
 * dot-product test <F dm, dd> = <dm, F^T dd>, F the linearised
   density-to-trace map (F dm by complex step, F^T dd from the adjoint);
 * a ragged mesh (several (n_b, N_r) groups);
-* the paper's truncated kernel correlates positively with the exact
-  gradient at sign -1 (the reading of the back-propagation convention).
+* the paper's truncated kernel: recomputed from forward and back-propagated
+  velocities of the dense uncondensed system (no condensation, no coarse
+  assembly), -dt sum_k' v~^{k'} v^{N_t+1-k'} with the residual u - d as the
+  back-propagated source, element by element; a one-step shift of the
+  reversed index or a dt-weighted source must not pass that comparison; and
+  it correlates positively with the exact gradient (the sign reading).
 """
 
 import numpy as np
@@ -17,6 +21,8 @@ import pytest
 import workloads as W
 from oracle import adjoint as adj
 from oracle import stepper as stp
+
+from ._dense import DenseSystem
 
 
 def _case(mesh=None, nt=14, seed=5):
@@ -106,3 +112,36 @@ def test_paper_kernel_correlates_with_exact_gradient():
     gp, _ = adj.paper_kernel_gradient(m, cfg.src_nodes, cfg.wavelets, cfg.rec_nodes, obs,
                                       cfg.n_steps, sign=-1.0)
     assert np.corrcoef(g, gp)[0, 1] > 0.5
+
+
+def _dense_paper_kernel(dense, src, wav, rec, obs, nt, dt, shift=0, source_weight=1.0):
+    fwd = dense.run(src, wav, nt)
+    traces = np.stack([f["U"][rec] for f in fwd], axis=-1)          # [n_rec, nt]
+    res = source_weight * (traces - obs[0])
+    # reversed step k' applies r^{N_t + 1 - k'} = res[:, nt - k']
+    bwd = dense.run(rec, res[:, ::-1], nt)
+    g = np.zeros_like(fwd[0]["v_fine"])
+    for kp in range(1, nt + 1):
+        kf = nt + 1 - kp - shift                                    # forward step paired with k'
+        if 1 <= kf <= nt:
+            g -= dt * bwd[kp - 1]["v_fine"] * fwd[kf - 1]["v_fine"]
+    return g, traces
+
+
+def test_paper_kernel_equals_dense_recomputation():
+    mesh, rho, dt, nt, src, rec, wav, m, tr, obs = _case(seed=21)
+    gp, tr_o = adj.paper_kernel_gradient(m, src, wav, rec, obs, nt)
+    dense = DenseSystem(m)
+    g, tr_d = _dense_paper_kernel(dense, src, wav, rec, obs, nt, dt)
+    assert np.abs(tr_d - tr_o[0]).max() <= 1e-9 * np.abs(tr_d).max()
+    scale = np.abs(g).max()
+    assert scale > 0
+    assert np.abs(gp - g).max() <= 1e-8 * scale
+    # planted mistakes: the reversed index shifted by one step either way, and a
+    # back-propagated source weighted by dt, each differ from the oracle far
+    # beyond the tolerance above
+    for sh in (1, -1):
+        gs, _ = _dense_paper_kernel(dense, src, wav, rec, obs, nt, dt, shift=sh)
+        assert np.abs(gp - gs).max() > 1e-2 * scale
+    gw, _ = _dense_paper_kernel(dense, src, wav, rec, obs, nt, dt, source_weight=dt)
+    assert np.abs(gp - gw).max() > 0.5 * scale

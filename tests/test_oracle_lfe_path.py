@@ -8,7 +8,13 @@
   positive definite and carries the element's mass between xi0 and the
   boundary, 1^T M 1 = (1 - xi0^2) / 2 * 1^T M0 1;
 * the assembled Newmark loop conserves 1/2 V^T M V + 1/2 U^T K U to rounding
-  once the source has stopped.
+  once the source has stopped;
+* the paper's truncated kernel on this path equals its recomputation from
+  nodal velocities obtained by modal superposition (generalised symmetric
+  eigenvectors of K and M, every mode advanced by the trapezoidal rule, which
+  is average-acceleration Newmark for zero initial state and load), with the
+  residual u - d as the back-propagated source; a one-step shift of the
+  reversed index must not pass.
 """
 
 import numpy as np
@@ -115,3 +121,71 @@ def test_lfe_paper_kernel_agrees_in_sign_with_finite_differences():
     step = 1e-3 * np.abs(rho).max() / np.abs(g).max()
     fd_g = (J(rho + step * g) - J(rho - step * g)) / (2 * step)
     assert fd_g > 0
+
+
+def _modal_velocities(K, M, dt, nodes, amps, nt):
+    """Nodal velocities of M u'' + K u = f, f^k = amps[:, k - 1] at nodes, zero
+    initial state, by modal superposition and the trapezoidal rule per mode."""
+    import scipy.linalg as sla
+    w2, Phi = sla.eigh(K, M)
+    n = K.shape[0]
+    eta, deta = np.zeros(n), np.zeros(n)
+    g_old = np.zeros(n)
+    out = []
+    h = 0.5 * dt
+    det = 1.0 + h * h * w2
+    for k in range(1, nt + 1):
+        f = np.zeros(n)
+        np.add.at(f, nodes, amps[:, k - 1])
+        g = Phi.T @ f
+        # (I - h A) x' = (I + h A) x + h (b + b'),  A = [[0, 1], [-w2, 0]], b = [0, g]
+        r0 = eta + h * deta
+        r1 = deta - h * w2 * eta + h * (g_old + g)
+        eta, deta = (r0 + h * r1) / det, (r1 - h * w2 * r0) / det
+        g_old = g
+        out.append(Phi @ deta)
+    return out
+
+
+def test_lfe_paper_kernel_equals_modal_recomputation():
+    wl = W.config_tiny(40)
+    m = wl.mesh
+    model = lfe.LfeModel(m, wl.models["random30"], wl.c, wl.dt)
+    obs = lfe.lfe_forward(lfe.LfeModel(m, wl.models["homogeneous"], wl.c, wl.dt), wl.src_nodes, wl.wavelets,
+                          wl.rec_nodes, 40)
+    g, tr = lfe.lfe_paper_kernel_gradient(model, wl.src_nodes, wl.wavelets, wl.rec_nodes, obs, 40)
+    K, M = model.K.toarray(), model.M.toarray()
+    K, M = 0.5 * (K + K.T), 0.5 * (M + M.T)
+    nt, dt = 40, wl.dt
+    vf = _modal_velocities(K, M, dt, wl.src_nodes, wl.wavelets[:, :nt], nt)
+    tr_m = np.zeros_like(tr[0])
+    # displacements for the residual: integrate the same modal run (u from the trapezoidal rule)
+    u = np.zeros(m.n_nodes)
+    v_old = np.zeros(m.n_nodes)
+    for k in range(nt):
+        u = u + 0.5 * dt * (v_old + vf[k])
+        v_old = vf[k]
+        tr_m[:, k] = u[wl.rec_nodes]
+    assert np.abs(tr_m - tr[0]).max() <= 1e-8 * np.abs(tr[0]).max()
+    res = tr_m - obs[0]
+    vb = _modal_velocities(K, M, dt, wl.rec_nodes, res[:, ::-1], nt)
+
+    def kernel(shift):
+        kern = np.zeros(m.n_nodes)
+        for kp in range(1, nt + 1):
+            kf = nt + 1 - kp - shift
+            if 1 <= kf <= nt:
+                kern -= dt * vb[kp - 1] * vf[kf - 1]
+        out = np.zeros(m.n_params)
+        offs = m.param_offsets()
+        for e in range(m.n_elem):
+            lp = m.loop(e)
+            nb, nr = len(lp), int(m.n_r[e])
+            out[offs[e] + (nr - 1) * nb:offs[e + 1]] = kern[lp]
+        return out
+
+    ref = kernel(0)
+    scale = np.abs(ref).max()
+    assert scale > 0 and np.abs(g - ref).max() <= 1e-7 * scale
+    for sh in (1, -1):
+        assert np.abs(g - kernel(sh)).max() > 1e-2 * scale

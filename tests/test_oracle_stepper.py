@@ -15,9 +15,10 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import element as el
 from oracle import stepper as stp
 from oracle import stability as stab
+
+from ._dense import DenseSystem
 
 
 def _tiny(n_r=6, nx=2, seed=5):
@@ -35,43 +36,9 @@ def test_condensed_step_equals_dense_uncondensed_solve():
     wav = W.ricker(nt, dt, 5e5, t0=2e-7)[None]
     m = stp.Model(mesh, rho, 3000.0, dt)
     _, trajs = stp.forward(m, src, wav, rec, nt, keep=True)
-    g = m.groups[0]
-    n, nb, E = g.n, g.n_b, len(g.elem_ids)
-    Ae = el.element_system(g.theta, g.phi, g.psi)
-    # global unknowns: per element levels -1..n-1, n+1 (internal), then the nodes
-    blocks = list(range(0, n + 1)) + [n + 2]
-    ic = np.concatenate([np.arange(b * nb, (b + 1) * nb) for b in blocks])
-    bc = np.arange((n + 1) * nb, (n + 2) * nb)
-    ir = np.arange(0, (n + 2) * nb)
-    br = np.arange((n + 2) * nb, (n + 3) * nb)
-    NI = ic.size
-    N = E * NI + mesh.n_nodes
-    A = np.zeros((N, N))
-    for e in range(E):
-        sl = slice(e * NI, (e + 1) * NI)
-        nodes = E * NI + g.loops[e]
-        A[sl, sl] = Ae[e][np.ix_(ir, ic)]
-        A[sl, nodes] += Ae[e][np.ix_(ir, bc)]
-        A[np.ix_(nodes, np.arange(e * NI, (e + 1) * NI))] += Ae[e][np.ix_(br, ic)]
-        A[np.ix_(nodes, nodes)] += Ae[e][np.ix_(br, bc)]
-    nm = m.nm
-    U = V = Acc = np.zeros(mesh.n_nodes)
-    u = v = a = np.zeros((E, n, nb))
+    dense = DenseSystem(m).run(src, wav, nt)
     for k in range(1, nt + 1):
-        Wn = nm.a0 * U + nm.a1 * V + nm.a2 * Acc
-        wi = nm.a0 * u + nm.a1 * v + nm.a2 * a
-        p = np.einsum("ejab,ejb->eja", g.P, np.concatenate([wi, Wn[g.loops][:, None]], 1))
-        b = np.zeros(N)
-        for e in range(E):
-            b[e * NI + nb:e * NI + (n + 2) * nb] = p[e].ravel()
-        b[E * NI + src[0]] += wav[0, k - 1]
-        X = np.linalg.solve(A, b)
-        Un = X[E * NI:]
-        loc = X[:E * NI].reshape(E, n + 2, nb)
-        un = loc[:, 1:n + 1]
-        U, V, Acc = Un, nm.c1 * (Un - U) + nm.c2 * V + nm.c3 * Acc, nm.a0 * Un - Wn
-        u, v, a = un, nm.c1 * (un - u) + nm.c2 * v + nm.c3 * a, nm.a0 * un - wi
-        Xd = np.concatenate([loc[:, :n + 1], U[g.loops][:, None], loc[:, n + 1:]], axis=1)
+        Xd = dense[k - 1]["X"]
         Xc = trajs[0][k - 1]["full"][0]["X"]
         assert np.abs(Xd - Xc).max() <= 1e-9 * np.abs(Xd).max()
 
