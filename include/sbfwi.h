@@ -50,7 +50,8 @@ enum {
   SBFWI_EHIP = -7         /* a HIP runtime call failed                                        */
 };
 
-enum { SBFWI_SCHEME_PAPER_FD = 0, SBFWI_SCHEME_RADIAL_GALERKIN = 1, SBFWI_SCHEME_LFE = 2 };
+enum { SBFWI_SCHEME_PAPER_FD = 0, SBFWI_SCHEME_RADIAL_GALERKIN = 1, SBFWI_SCHEME_LFE = 2,
+       SBFWI_SCHEME_LFE_CONDENSED = 3 };
 enum { SBFWI_GRAD_EXACT = 0, SBFWI_GRAD_PAPER_KERNEL = 1 };
 /* Flag OR-ed into the gradient mode: one gradient (and one misfit) per shot. */
 enum { SBFWI_GRAD_PER_SHOT = 16 };
@@ -121,12 +122,19 @@ int sbfwi_mesh_info(sbfwi_mesh m, int64_t* host_out);
  *           (Section "Low-frequency expansion", eq. simplified and eq. S):
  *           radially constant density (each element's boundary-level values,
  *           the other levels are ignored), element stiffness K_e and mass M_e
- *           on the boundary nodes only, computed as the static condensation
- *           of the element's N_r Galerkin levels (K_e) and the radial mass
- *           seen through its static modes (M_e), which converge at second
- *           order to the Riccati and Lyapunov solutions of the expansion;
- *           the coarse matrix is K_g + a0 M_g.  Forward runs only (no
- *           checkpoints, no adjoint).
+ *           on the boundary nodes only: K_e solves the algebraic Riccati
+ *           equation (K - E1) E0^-1 (K - E1^T) = E2 (the invariant subspace of
+ *           the static radial matrix for the modes bounded at the centre,
+ *           obtained on the device by the scaled Newton iteration of the
+ *           matrix sign function) and M_e the Lyapunov equation of the
+ *           expansion (Newton iteration); the coarse matrix is K_g + a0 M_g;
+ *           the time loop is nodal only.  SBFWI_ENOCONV if an iteration does
+ *           not settle within 60 steps.
+ *           SBFWI_SCHEME_LFE_CONDENSED: the same path with K_e the static
+ *           condensation of the element's N_r radial Galerkin levels and M_e
+ *           the radial mass seen through its static modes, which converge at
+ *           second order in the radial spacing to the Riccati and Lyapunov
+ *           solutions.
  *   coarse_solver 0 = BiCGStab with Jacobi preconditioning (K_g is not
  *           symmetric), solved every step to the tolerance of sbfwi_set_solver;
  *           1 = direct: K_g = L U factored here once, in a nested-dissection
@@ -209,9 +217,9 @@ int sbfwi_autotune(sbfwi_factors f, int n_shots, double* host_out, hipStream_t s
  *   which = 2: the stored pivot inverses phi~_j^-1, j = 0 .. N_r-2, of every element,
  *              row-major (sum_e (N_r - 1) n_b^2 doubles);
  *   which = 3: G_e = psi_{n+1} psi_n^-1 of every element (sum_e n_b^2 doubles);
- *   which = 4: (SBFWI_SCHEME_LFE) M_e of every element (sum_e n_b^2 doubles; which = 0
+ *   which = 4: (expansion schemes) M_e of every element (sum_e n_b^2 doubles; which = 0
  *              then holds K_e);
- *   which = 5: (SBFWI_SCHEME_LFE) values of M_g on the CSR pattern (nnz doubles; which = 1
+ *   which = 5: (expansion schemes) values of M_g on the CSR pattern (nnz doubles; which = 1
  *              then holds K_g + a0 M_g).
  * host_dst must hold the documented count.
  */
@@ -235,7 +243,7 @@ int sbfwi_coarse_pattern(sbfwi_mesh m, int64_t* host_row_ptr, int64_t* host_col)
  *            n_ckpt >= n_steps stores every step (full storage).
  *   ckpt_out receives the checkpoint handle (needed by sbfwi_adjoint /
  *            sbfwi_gradient), or NULL.
- * With factors of SBFWI_SCHEME_LFE the step is nodal only (F = M_g w + f,
+ * With factors of SBFWI_SCHEME_LFE (or _LFE_CONDENSED) the step is nodal only (F = M_g w + f,
  * (K_g + a0 M_g) U = F, Newmark update) and n_ckpt must be 0.
  * Growth detector (schemes 0 and 1): every step checks each new nodal
  * displacement of shot q against the envelope 10 * 4 k r F_k(q), r the largest
@@ -272,7 +280,7 @@ int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps,
  *           the forward scheme driven by the time-reversed adj_src at the
  *           receivers; sign -1 so that it points along the exact gradient).
  *           With SBFWI_GRAD_PER_SHOT or-ed in, every shot gets its own gradient.
- *           Factors of SBFWI_SCHEME_LFE accept SBFWI_GRAD_PAPER_KERNEL only
+ *           Factors of the expansion schemes accept SBFWI_GRAD_PAPER_KERNEL only
  *           (SBFWI_EINVAL otherwise): the kernel at the nodal points, written
  *           to every element's boundary-level entries (interior levels 0).
  *   grad    device [n_params], overwritten with the sum over shots; with

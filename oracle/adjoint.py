@@ -63,13 +63,22 @@ def _partition(n, n_b):
 
 
 class _ElementBlocks:
-    def __init__(self, g):
+    """Per element: the coupling blocks of eq. system between the internal and
+    boundary unknowns and a sparse LU of its internal block (built for a few
+    hundred elements at a time, so that large meshes fit in memory)."""
+
+    def __init__(self, g, chunk=256):
         n, nb = g.n, g.n_b
         self.ic, self.bc, self.ir, self.br = _partition(n, nb)
-        A = element_system(g.theta, g.phi, g.psi)
-        self.AIB = A[:, self.ir][:, :, self.bc]
-        self.ABI = A[:, self.br][:, :, self.ic]
-        self.lu = [spla.splu(sp.csc_matrix(A[e][np.ix_(self.ir, self.ic)])) for e in range(A.shape[0])]
+        aib, abi, self.lu = [], [], []
+        for c0 in range(0, len(g.elem_ids), chunk):
+            sl = slice(c0, c0 + chunk)
+            A = element_system(g.theta[sl], g.phi[sl], g.psi[sl])
+            aib.append(A[:, self.ir][:, :, self.bc])
+            abi.append(A[:, self.br][:, :, self.ic])
+            self.lu += [spla.splu(sp.csc_matrix(A[e][np.ix_(self.ir, self.ic)])) for e in range(A.shape[0])]
+        self.AIB = np.concatenate(aib)
+        self.ABI = np.concatenate(abi)
 
 
 def _basis_rows(g, m, k):

@@ -26,6 +26,7 @@ from ._abi import SbfwiError, check, lib
 SCHEME_PAPER_FD = 0
 SCHEME_RADIAL_GALERKIN = 1
 SCHEME_LFE = 2
+SCHEME_LFE_CONDENSED = 3
 GRAD_EXACT = 0
 GRAD_PAPER_KERNEL = 1
 GRAD_PER_SHOT = 16

@@ -142,7 +142,7 @@ extern "C" int sbfwi_factor_elements(sbfwi_mesh m, const double* rho, double c, 
   if (!m || !rho) return sbfwi_fail(SBFWI_EINVAL, "NULL mesh or density");
   if (!(c > 0) || !(dt > 0) || !(beta > 0) || !(gamma > 0))
     return sbfwi_fail(SBFWI_EINVAL, "c, dt, beta and gamma must be positive");
-  if (scheme != SBFWI_SCHEME_PAPER_FD && scheme != SBFWI_SCHEME_RADIAL_GALERKIN && scheme != SBFWI_SCHEME_LFE)
+  if (scheme != SBFWI_SCHEME_PAPER_FD && scheme != SBFWI_SCHEME_RADIAL_GALERKIN && !sbfwi_is_lfe(scheme))
     return sbfwi_fail(SBFWI_EINVAL, "unknown radial scheme %d", scheme);
   if (coarse_solver != 0 && coarse_solver != 1)
     return sbfwi_fail(SBFWI_EINVAL, "unknown coarse solver %d", coarse_solver);
@@ -274,7 +274,8 @@ extern "C" int sbfwi_copy_factor_data(sbfwi_factors f, int which, double* dst) {
     case 3: src = f->d.G; n = f->m->n_dense; break;
     case 4:
     case 5:
-      if (f->scheme != SBFWI_SCHEME_LFE) return sbfwi_fail(SBFWI_EINVAL, "factor data %d exists for scheme 2 only", which);
+      if (!sbfwi_is_lfe(f->scheme))
+        return sbfwi_fail(SBFWI_EINVAL, "factor data %d exists for the expansion schemes only", which);
       src = which == 4 ? f->d.Me : f->d.Mval;
       n = which == 4 ? f->m->n_dense : f->m->nnz;
       break;
@@ -459,7 +460,7 @@ extern "C" int sbfwi_forward(sbfwi_factors f, int n_shots, int64_t n_steps, cons
     for (int64_t v : r)
       if (v < 0 || v >= f->m->n_nodes) return sbfwi_fail(SBFWI_EINVAL, "receiver node %lld out of range", (long long)v);
   }
-  if (f->scheme == SBFWI_SCHEME_LFE) {
+  if (sbfwi_is_lfe(f->scheme)) {
     // any n_ckpt != 0 keeps every step's nodal velocity (the paper-kernel gradient needs them all)
     sbfwi_ckpt_s* ck = nullptr;
     double* vstore = nullptr;
@@ -520,13 +521,13 @@ extern "C" int sbfwi_adjoint(sbfwi_factors f, sbfwi_ckpt ck, const double* adj_s
   if (ck->f != f) return sbfwi_fail(SBFWI_EINVAL, "checkpoints belong to other factors");
   const int base = mode & ~SBFWI_GRAD_PER_SHOT;
   if (base != SBFWI_GRAD_EXACT && base != SBFWI_GRAD_PAPER_KERNEL) return sbfwi_fail(SBFWI_EINVAL, "unknown mode");
-  if (f->scheme == SBFWI_SCHEME_LFE && base != SBFWI_GRAD_PAPER_KERNEL)
-    return sbfwi_fail(SBFWI_EINVAL, "scheme 2 provides the paper-kernel gradient only");
+  if (sbfwi_is_lfe(f->scheme) && base != SBFWI_GRAD_PAPER_KERNEL)
+    return sbfwi_fail(SBFWI_EINVAL, "the expansion schemes provide the paper-kernel gradient only");
   if (ck->n_rec == 0) {   // no receivers, no adjoint sources: the adjoint state and the gradient vanish
     (void)hipStreamSynchronize(s);
     return sbfwi_zero_sync(grad, sizeof(double) * f->m->n_params * ((mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1));
   }
-  if (f->scheme == SBFWI_SCHEME_LFE) {
+  if (sbfwi_is_lfe(f->scheme)) {
     SBFWI_CHECK(sbfwi_zero_sync(grad, sizeof(double) * f->m->n_params *
                                           ((mode & SBFWI_GRAD_PER_SHOT) ? ck->n_shots : 1)));
     return sbfwi_lfe_adjoint(f, ck, adj_src, (mode & SBFWI_GRAD_PER_SHOT) != 0, grad, s);

@@ -262,20 +262,14 @@ __device__ void load_rows(const ElemCtx& c, Lds<NBT>& L, int slot, int which, in
   for (int q = threadIdx.x; q < 3 * c.nb; q += FT) L.band[slot][q] = row_band<SCH>(c, which, r, q / c.nb, q % c.nb);
 }
 
-// SCH: the radial scheme, fixed at compile time so that each instance keeps
-// only its own row builder.
-template <int NBT, int SCH>
-__global__ void __launch_bounds__(FT) factor_kernel(
-    const int32_t* __restrict__ elems, const MeshDev mm, const double* __restrict__ rho,
-    double c, double a0, FactorsDev ff, int* status) {
-  __shared__ Lds<NBT> L;
-  const int e = elems[blockIdx.x];
+// Per-segment geometric weights alpha[tau][seg][end][ab] of eq. Es for the
+// element's nb segments, into alpha (LDS) and, if given, the gradient's copy
+// gbasis: two-point Gauss-Legendre (exact for the cubic integrands) of
+// c^2 det J_b (b1.b1 N N, b2.b1 dN N, b2.b2 dN dN) and det J_b N N, times the
+// end-node shape function.
+__device__ void segment_weights(const MeshDev& mm, int e, double c, double* alpha, double* gbasis) {
   const int nb = mm.nb[e];
-  const int nr = mm.nr[e];
-  const int n = nr - 1;
   const int64_t lo = mm.loop_off[e];
-  if (threadIdx.x == 0) L.bad = 0;
-  // per-segment geometric weights alpha[tau][seg][end][ab]
   const double cx = mm.centre[2 * e], cy = mm.centre[2 * e + 1];
   for (int s = threadIdx.x; s < nb; s += FT) {
     int s1 = md(s + 1, nb);
@@ -308,10 +302,27 @@ __global__ void __launch_bounds__(FT) factor_kernel(
     }
     for (int tau = 0; tau < 4; ++tau)
       for (int q = 0; q < 8; ++q) {
-        L.alpha[tau * nb * 8 + s * 8 + q] = acc[tau * 8 + q];
-        ff.gbasis[32 * (lo + s) + tau * 8 + q] = acc[tau * 8 + q];
+        alpha[tau * nb * 8 + s * 8 + q] = acc[tau * 8 + q];
+        if (gbasis) gbasis[32 * (lo + s) + tau * 8 + q] = acc[tau * 8 + q];
       }
   }
+}
+
+// SCH: the radial scheme, fixed at compile time so that each instance keeps
+// only its own row builder.
+template <int NBT, int SCH>
+__global__ void __launch_bounds__(FT) factor_kernel(
+    const int32_t* __restrict__ elems, const MeshDev mm, const double* __restrict__ rho,
+    double c, double a0, FactorsDev ff, int* status) {
+  __shared__ Lds<NBT> L;
+  const int e = elems[blockIdx.x];
+  const int nb = mm.nb[e];
+  const int nr = mm.nr[e];
+  const int n = nr - 1;
+  const int64_t lo = mm.loop_off[e];
+  if (threadIdx.x == 0) L.bad = 0;
+  // per-segment geometric weights alpha[tau][seg][end][ab]
+  segment_weights(mm, e, c, L.alpha, ff.gbasis);
   __syncthreads();
   ElemCtx ec;
   ec.nb = nb;
@@ -319,8 +330,8 @@ __global__ void __launch_bounds__(FT) factor_kernel(
   ec.xi0 = mm.xi0;
   ec.h = (1.0 - mm.xi0) / n;
   ec.c2 = c * c;
-  ec.lfe = SCH == SBFWI_SCHEME_LFE;
-  ec.a0 = ec.lfe ? 0.0 : a0;   // the expansion's K is the static condensation
+  ec.lfe = SCH == SBFWI_SCHEME_LFE_CONDENSED;
+  ec.a0 = ec.lfe ? 0.0 : a0;   // the condensed expansion's K is the static condensation
   ec.rho = rho + mm.par_off[e];
   ec.alpha = L.alpha;
   ec.scheme = SCH;
@@ -496,6 +507,318 @@ __global__ void assemble_lfe_kernel(int64_t nnz, const int64_t* __restrict__ cpt
   M[q] = m;
 }
 
+// ---------------------------------------------------------------------------
+// Low-frequency expansion (scheme 2, Section "Low-frequency expansion", eq. S):
+// per element, with the boundary level's densities at every level, K solves
+// the algebraic Riccati equation (K - E1) E0^-1 (K - E1^T) = E2 and M the
+// Lyapunov equation A M + M A^T = M0, A = (K - E1) E0^-1 + I.
+//
+// K: the graph {[u; K u]} is the invariant subspace of the static radial
+// matrix Z = [[-E0^-1 E1^T, E0^-1], [E2 - E1 E0^-1 E1^T, E1 E0^-1]] that
+// belongs to its eigenvalues with positive real part (the modes bounded at the
+// scaling centre) together with the constant mode [1; 0] (eigenvalue 0, whose
+// partner completes a Jordan pair).  The linear fields are modes of eigenvalue
+// 1, so the other positive eigenvalues are >= 1 and the shift Z - I/2 separates
+// them from 0 and the negative ones.  Its matrix sign function, by the
+// determinant-scaled Newton iteration X <- (mu X + (mu X)^-1) / 2, gives the
+// spectral projector P = (I + sign(Z - I/2)) / 2 onto the positive modes;
+// every column of P lies in the graph, [P11 P12] -> [P21 P22], and K 1 = 0, so
+// K = (P21 P11^T + P22 P12^T) (P11 P11^T + P12 P12^T + s 1 1^T)^-1 (any s > 0;
+// s = trace(P11 P11^T + P12 P12^T) / nb keeps the scales alike).
+// M: the eigenvalues of A are 1 + (those of the modes) >= 1, so sign(A) = I
+// and the Newton iteration on [[A, C], [0, -A^T]] -- A <- (mu A + (mu A)^-1)/2,
+// C <- (mu C + A^-1 C A^-T / mu)/2 from C = M0 -- converges to C = 2 M.
+// ---------------------------------------------------------------------------
+
+template <int NBT>
+struct RicLds {
+  double alpha[4 * NBT * 8];
+  double E0i[NBT * NBT];        // E0^-1 (compact, leading dimension nb)
+  double E1[NBT * NBT];
+  double M0[NBT * NBT];
+  double R0[4 * NBT * NBT];     // sign iterate S (2nb x 2nb), later K, A, C, T
+  double R1[4 * NBT * NBT];     // its inverse, later the nb x nb work blocks
+  double fac[2 * NBT];
+  double red[2 * FT];
+  int perm[2 * NBT];
+  int piv;
+  int bad;
+  double logdet;
+};
+
+// In-place Gauss-Jordan inversion with partial pivoting of the N x N matrix X
+// (leading dimension N) in LDS; *logdet receives log |det X|, *bad is set on a
+// zero or non-finite pivot.
+template <int NBT>
+__device__ void gj_invert(RicLds<NBT>& L, double* X, int N) {
+  if (threadIdx.x == 0) L.logdet = 0.0;
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    if (threadIdx.x == 0) {
+      int p = k;
+      double best = fabs(X[k * N + k]);
+      for (int r = k + 1; r < N; ++r) {
+        const double v = fabs(X[r * N + k]);
+        if (v > best) { best = v; p = r; }
+      }
+      L.piv = p;
+      L.perm[k] = p;
+      if (!(best > 1e-300) || !isfinite(best)) L.bad = 1;
+      L.logdet += log(best > 1e-300 ? best : 1e-300);
+    }
+    __syncthreads();
+    const int p = L.piv;
+    if (p != k)
+      for (int j = threadIdx.x; j < N; j += FT) {
+        const double t = X[k * N + j];
+        X[k * N + j] = X[p * N + j];
+        X[p * N + j] = t;
+      }
+    __syncthreads();
+    const double pv = X[k * N + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += FT) X[k * N + j] = (j == k ? 1.0 : X[k * N + j]) / pv;
+    for (int i = threadIdx.x; i < N; i += FT) L.fac[i] = i == k ? 0.0 : X[i * N + k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += FT)
+      if (i != k) X[i * N + k] = 0.0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < N * N; q += FT) {
+      const int i = q / N, j = q % N;
+      if (i != k) X[q] -= L.fac[i] * X[k * N + j];
+    }
+    __syncthreads();
+  }
+  for (int k = N - 1; k >= 0; --k) {   // undo the row interchanges on the columns of the inverse
+    const int p = L.perm[k];
+    if (p != k)
+      for (int i = threadIdx.x; i < N; i += FT) {
+        const double t = X[i * N + k];
+        X[i * N + k] = X[i * N + p];
+        X[i * N + p] = t;
+      }
+    __syncthreads();
+  }
+}
+
+// Largest |x| over the block's partial values (thread t holds a[t], b[t]).
+template <int NBT>
+__device__ void block_max2(RicLds<NBT>& L, double a, double b, double* ra, double* rb) {
+  L.red[threadIdx.x] = a;
+  L.red[FT + threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0, y = 0.0;
+    for (int t = 0; t < FT; ++t) {
+      x = fmax(x, L.red[t]);
+      y = fmax(y, L.red[FT + t]);
+    }
+    L.red[0] = x;
+    L.red[FT] = y;
+  }
+  __syncthreads();
+  *ra = L.red[0];
+  *rb = L.red[FT];
+  __syncthreads();
+}
+
+constexpr int kSignMaxIter = 60;
+
+// One scaled Newton step of the sign iteration on the N x N iterate X (its
+// inverse computed in Xi); returns the largest change and the largest entry.
+template <int NBT>
+__device__ void sign_step(RicLds<NBT>& L, double* X, double* Xi, int N, bool scale, double* change, double* norm) {
+  for (int q = threadIdx.x; q < N * N; q += FT) Xi[q] = X[q];
+  __syncthreads();
+  gj_invert<NBT>(L, Xi, N);
+  const double mu = scale ? exp(-L.logdet / N) : 1.0;
+  double ch = 0.0, nm = 0.0;
+  for (int q = threadIdx.x; q < N * N; q += FT) {
+    const double v = 0.5 * (mu * X[q] + Xi[q] / mu);
+    ch = fmax(ch, fabs(v - X[q]));
+    nm = fmax(nm, fabs(v));
+    X[q] = v;
+  }
+  block_max2<NBT>(L, ch, nm, change, norm);
+}
+
+template <int NBT>
+__global__ void __launch_bounds__(FT) lfe_riccati_kernel(const int32_t* __restrict__ elems, const MeshDev mm,
+                                                         const double* __restrict__ rho, double c, FactorsDev ff,
+                                                         int* status) {
+  __shared__ RicLds<NBT> L;
+  const int e = elems[blockIdx.x];
+  const int nb = mm.nb[e];
+  const int n = mm.nr[e] - 1;
+  const int nn = nb * nb;
+  if (threadIdx.x == 0) L.bad = 0;
+  segment_weights(mm, e, c, L.alpha, nullptr);
+  __syncthreads();
+  ElemCtx ec;
+  ec.nb = nb;
+  ec.n = n;
+  ec.xi0 = mm.xi0;
+  ec.h = (1.0 - mm.xi0) / n;
+  ec.c2 = c * c;
+  ec.lfe = 1;   // radially constant: the boundary level's densities
+  ec.a0 = 0.0;
+  ec.rho = rho + mm.par_off[e];
+  ec.alpha = L.alpha;
+  ec.scheme = SBFWI_SCHEME_LFE;
+  ec.rgw = nullptr;
+  // dense E0 (into R1, then inverted in place), E1, E2 (R1 + nn), M0
+  auto dense_e = [&](int tau, double* dst) {
+    for (int q = threadIdx.x; q < nn; q += FT) {
+      const int i = q / nb, j = q % nb;
+      double v = j == i ? e_band(ec, tau, n, 1, i) : 0.0;
+      if (j == md(i + 1, nb)) v += e_band(ec, tau, n, 2, i);
+      if (j == md(i - 1, nb)) v += e_band(ec, tau, n, 0, i);
+      dst[q] = v;
+    }
+  };
+  double* E2 = L.R1 + nn;
+  dense_e(0, L.R1);
+  dense_e(1, L.E1);
+  dense_e(2, E2);
+  dense_e(3, L.M0);
+  __syncthreads();
+  gj_invert<NBT>(L, L.R1, nb);
+  for (int q = threadIdx.x; q < nn; q += FT) L.E0i[q] = L.R1[q];
+  __syncthreads();
+  // S = Z - I/2 (2nb x 2nb); blocks: Z11 = -E0^-1 E1^T, Z12 = E0^-1,
+  // Z21 = E2 - E1 E0^-1 E1^T = E2 + E1 Z11, Z22 = E1 E0^-1
+  const int N = 2 * nb;
+  double* S = L.R0;
+  for (int q = threadIdx.x; q < nn; q += FT) {
+    const int i = q / nb, j = q % nb;
+    double z11 = 0.0, z22 = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      z11 -= L.E0i[i * nb + k] * L.E1[j * nb + k];
+      z22 += L.E1[i * nb + k] * L.E0i[k * nb + j];
+    }
+    S[i * N + j] = z11 - (i == j ? 0.5 : 0.0);
+    S[i * N + nb + j] = L.E0i[q];
+    S[(nb + i) * N + nb + j] = z22 - (i == j ? 0.5 : 0.0);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nn; q += FT) {
+    const int i = q / nb, j = q % nb;
+    double v = E2[q];
+    for (int k = 0; k < nb; ++k) v += L.E1[i * nb + k] * S[k * N + j];   // S11 = Z11 - I/2
+    S[(nb + i) * N + j] = v + 0.5 * L.E1[i * nb + j];                      // E1 (S11 + I/2) = E1 Z11
+  }
+  __syncthreads();
+  // sign(Z - I/2): scaled until the iterate settles, then plain Newton steps;
+  // one more step after the change first falls below the tolerance
+  bool done = false;
+  int it = 0, extra = 0;
+  bool scale = true;
+  for (; it < kSignMaxIter && !done; ++it) {
+    double ch, nm;
+    sign_step<NBT>(L, S, L.R1, N, scale, &ch, &nm);
+    if (ch <= 1e-2 * nm) scale = false;
+    if (ch <= 1e-14 * nm) done = ++extra > 1;
+  }
+  if (!done && threadIdx.x == 0) atomicOr(status, 2);
+  // P = (I + S) / 2; A = P11 P11^T + P12 P12^T + s 1 1^T (R1), Rm = P21 P11^T + P22 P12^T (R1 + nn)
+  for (int q = threadIdx.x; q < N * N; q += FT) S[q] = 0.5 * (S[q] + ((q / N) == (q % N) ? 1.0 : 0.0));
+  __syncthreads();
+  double* A = L.R1;
+  double* Rm = L.R1 + nn;
+  double tr = 0.0;
+  for (int q = threadIdx.x; q < nn; q += FT) {
+    const int i = q / nb, j = q % nb;
+    double a = 0.0, r = 0.0;
+    for (int k = 0; k < N; ++k) {
+      a += S[i * N + k] * S[j * N + k];
+      r += S[(nb + i) * N + k] * S[j * N + k];
+    }
+    A[q] = a;
+    Rm[q] = r;
+    if (i == j) tr += a;
+  }
+  double trace, unused;
+  {
+    L.red[threadIdx.x] = tr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < FT; ++k) t += L.red[k];
+      L.red[0] = t;
+    }
+    __syncthreads();
+    trace = L.red[0];
+    unused = 0.0;
+    __syncthreads();
+  }
+  (void)unused;
+  for (int q = threadIdx.x; q < nn; q += FT) A[q] += trace / nb;
+  __syncthreads();
+  gj_invert<NBT>(L, A, nb);
+  // K = Rm A^-1 (R0 slot 0); Al = (K - E1) E0^-1 + I (slot 1); C = M0 (slot 2)
+  double* K = L.R0;
+  double* Al = L.R0 + nn;
+  double* C = L.R0 + 2 * nn;
+  double* T = L.R0 + 3 * nn;
+  for (int q = threadIdx.x; q < nn; q += FT) {
+    const int i = q / nb, j = q % nb;
+    double v = 0.0;
+    for (int k = 0; k < nb; ++k) v += Rm[i * nb + k] * A[k * nb + j];
+    T[q] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nn; q += FT) K[q] = T[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < nn; q += FT) {
+    const int i = q / nb, j = q % nb;
+    double v = i == j ? 1.0 : 0.0;
+    for (int k = 0; k < nb; ++k) v += (K[i * nb + k] - L.E1[i * nb + k]) * L.E0i[k * nb + j];
+    Al[q] = v;
+    C[q] = L.M0[q];
+  }
+  __syncthreads();
+  // Lyapunov by the Newton iteration on [[Al, C], [0, -Al^T]]
+  double* X = L.R1;
+  done = false;
+  extra = 0;
+  scale = true;
+  for (it = 0; it < kSignMaxIter && !done; ++it) {
+    for (int q = threadIdx.x; q < nn; q += FT) X[q] = Al[q];
+    __syncthreads();
+    gj_invert<NBT>(L, X, nb);
+    const double mu = scale ? exp(-L.logdet / nb) : 1.0;
+    for (int q = threadIdx.x; q < nn; q += FT) {   // T = X C
+      const int i = q / nb, j = q % nb;
+      double v = 0.0;
+      for (int k = 0; k < nb; ++k) v += X[i * nb + k] * C[k * nb + j];
+      T[q] = v;
+    }
+    __syncthreads();
+    double ch = 0.0, nm = 0.0;
+    for (int q = threadIdx.x; q < nn; q += FT) {
+      const int i = q / nb, j = q % nb;
+      double v = 0.0;
+      for (int k = 0; k < nb; ++k) v += T[i * nb + k] * X[j * nb + k];   // X C X^T
+      C[q] = 0.5 * (mu * C[q] + v / mu);
+      const double a = 0.5 * (mu * Al[q] + X[q] / mu);
+      ch = fmax(ch, fabs(a - Al[q]));
+      nm = fmax(nm, fabs(a));
+      Al[q] = a;
+    }
+    double chg, nrm;
+    block_max2<NBT>(L, ch, nm, &chg, &nrm);
+    if (chg <= 1e-2 * nrm) scale = false;
+    if (chg <= 1e-14 * nrm) done = ++extra > 1;
+  }
+  if (!done && threadIdx.x == 0) atomicOr(status, 2);
+  const int64_t dofs = mm.dense_off[e];
+  for (int q = threadIdx.x; q < nn; q += FT) {
+    ff.S[dofs + q] = K[q];
+    ff.Me[dofs + q] = 0.5 * C[q];
+  }
+  if (threadIdx.x == 0 && L.bad) atomicOr(status, 1);
+}
+
 __global__ void transpose_diag_kernel(int64_t nnz, int64_t n_nodes, const int64_t* __restrict__ tr,
                                       const int64_t* __restrict__ diag, const int64_t* __restrict__ ell_pos,
                                       const double* __restrict__ K, double* __restrict__ KT,
@@ -570,7 +893,10 @@ static void launch_factor_nb(int scheme, dim3 grid, dim3 block, hipStream_t s, c
     hipLaunchKernelGGL((factor_kernel<NBT, SBFWI_SCHEME_RADIAL_GALERKIN>), grid, block, 0, s, elems, md, rho, c, d.a0,
                        d, d.status);
   else if (scheme == SBFWI_SCHEME_LFE)
-    hipLaunchKernelGGL((factor_kernel<NBT, SBFWI_SCHEME_LFE>), grid, block, 0, s, elems, md, rho, c, d.a0, d, d.status);
+    hipLaunchKernelGGL((lfe_riccati_kernel<NBT>), grid, block, 0, s, elems, md, rho, c, d, d.status);
+  else if (scheme == SBFWI_SCHEME_LFE_CONDENSED)
+    hipLaunchKernelGGL((factor_kernel<NBT, SBFWI_SCHEME_LFE_CONDENSED>), grid, block, 0, s, elems, md, rho, c, d.a0,
+                       d, d.status);
   else
     hipLaunchKernelGGL((factor_kernel<NBT, SBFWI_SCHEME_PAPER_FD>), grid, block, 0, s, elems, md, rho, c, d.a0, d,
                        d.status);
@@ -628,7 +954,7 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   A(&d.KTell, m->d.n_ell);
   A(&d.diag_inv, m->n_nodes);
   if (rc == SBFWI_OK) rc = sbfwi_alloc(&d.status, 8);
-  if (scheme == SBFWI_SCHEME_LFE) {
+  if (sbfwi_is_lfe(scheme)) {
     A(&d.Me, m->n_dense);
     A(&d.Mval, m->nnz);
   }
@@ -663,7 +989,7 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   }
   {
     unsigned g = (unsigned)((m->nnz + 255) / 256);
-    if (scheme == SBFWI_SCHEME_LFE)
+    if (sbfwi_is_lfe(scheme))
       hipLaunchKernelGGL(assemble_lfe_kernel, dim3(g), dim3(256), 0, s, m->nnz, m->d.contrib_ptr,
                          m->d.contrib_src, d.S, d.Me, d.a0, d.Kval, d.Mval);
     else
@@ -687,6 +1013,10 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   if (st[0] & 1) {
     sbfwi_factors_free(f);
     return sbfwi_fail(SBFWI_ESINGULAR, "a pivot block of the condensation sweep is singular");
+  }
+  if (st[0] & 2) {
+    sbfwi_factors_free(f);
+    return sbfwi_fail(SBFWI_ENOCONV, "the expansion's sign or Lyapunov iteration did not settle");
   }
   {   // response scale of the growth envelope: the largest 1 / |K_g,ii|
     std::vector<double> di(m->n_nodes);

@@ -22,6 +22,11 @@
 
 #define SBFWI_MAX_NB 24
 
+// The low-frequency expansion schemes (nodal time loop, K_e and M_e per element).
+inline bool sbfwi_is_lfe(int scheme) {
+  return scheme == SBFWI_SCHEME_LFE || scheme == SBFWI_SCHEME_LFE_CONDENSED;
+}
+
 // Plain device view of a mesh (kernel argument).
 struct MeshDev {
   int64_t n_nodes = 0, n_elem = 0, n_loop = 0, nnz = 0;
