@@ -385,6 +385,25 @@ int sbfwi_fem_forward(int nx, int ny, double lx, double ly, const double* rho_el
                       int n_rec, const int64_t* rec_node, double* traces, hipStream_t s);
 
 /*
+ * sbfwi_fem_forward_noalloc -- sbfwi_fem_forward for callers that cannot
+ * allocate memory (code near HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same arguments, kernels and results, but no
+ * device or host allocation by the library.  The work buffers (padded element
+ * coefficients, inverse lumped mass, two wavefields, a status word) live in a
+ * static device array of 48 MiB that every GPU the library runs on holds until
+ * the process ends; SBFWI_EINVAL, before any launch, when
+ * 8 ((nx + 2)(ny + 2) + (nx + 1)(ny + 1)(1 + 2 n_shots)) bytes plus alignment
+ * exceed it (the 512 x 256 grid takes 10.6 MB with 4 shots, 35 MB with 16).
+ * Node ids are checked on the device (SBFWI_EINVAL before the time loop).
+ * Every call on one GPU shares the array and finds the last call's contents
+ * (it clears what must start at zero): calls that overlap on one GPU race and
+ * must be serialised by the caller.  Synchronises s.
+ */
+int sbfwi_fem_forward_noalloc(int nx, int ny, double lx, double ly, const double* rho_elem, double c, double dt,
+                              int n_shots, int64_t n_steps, const int64_t* src_node, const double* wavelet,
+                              int n_rec, const int64_t* rec_node, double* traces, hipStream_t s);
+
+/*
  * sbfwi_finalize -- releases the runtime objects the library owns outside the
  * handles: the per-thread streams of its synchronous copies and the events of
  * the live kernel timing (pending timings are discarded, timing is switched

@@ -278,6 +278,24 @@ def sbfwi_fem_forward(nx, ny, lx, ly, rho_elem, c, dt, src_node, wavelet, rec_no
                                   _stream(stream)))
 
 
+def sbfwi_fem_forward_noalloc(nx, ny, lx, ly, rho_elem, c, dt, src_node, wavelet, rec_node, traces, stream=None):
+    """sbfwi_fem_forward without any allocation by the library (work buffers in its
+    static device scratch array; calls that overlap on one GPU race)."""
+    import torch
+    n_shots, n_steps = int(wavelet.shape[0]), int(wavelet.shape[1])
+    n_rec = int(rec_node.shape[0])
+    if traces.shape != (n_shots, n_rec, n_steps) or src_node.shape != (n_shots,):
+        raise ValueError("shape mismatch between src_node, wavelet, rec_node and traces")
+    if rho_elem.numel() != int(nx) * int(ny):
+        raise ValueError("rho_elem must hold nx * ny densities")
+    check(lib().sbfwi_fem_forward_noalloc(int(nx), int(ny), float(lx), float(ly),
+                                          _dptr(rho_elem, torch.float64, "rho_elem"), float(c), float(dt), n_shots,
+                                          n_steps, _dptr(src_node, torch.int64, "src_node"),
+                                          _dptr(wavelet, torch.float64, "wavelet"), n_rec,
+                                          _dptr(rec_node, torch.int64, "rec_node"),
+                                          _dptr(traces, torch.float64, "traces"), _stream(stream)))
+
+
 def _check_run_shapes(ck, mode, grad, misfit=None, **series):
     """Every array passed with a checkpoint handle must have the sizes of its run:
     the library reads and writes them by the run's shot, receiver and step counts."""

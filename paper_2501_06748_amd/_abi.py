@@ -44,6 +44,7 @@ SIGNATURES = {
     "sbfwi_factors_info": (i32, [vp, vp]),
     "sbfwi_solver_stats": (i32, [vp, vp, i32]),
     "sbfwi_fem_forward": (i32, [i32, i32, dbl, dbl, vp, dbl, dbl, i32, i64, vp, vp, i32, vp, vp, vp]),
+    "sbfwi_fem_forward_noalloc": (i32, [i32, i32, dbl, dbl, vp, dbl, dbl, i32, i64, vp, vp, i32, vp, vp, vp]),
     "sbfwi_profile": (i32, [C.c_uint32]),
     "sbfwi_profile_read": (i32, [vp, i32]),
     "sbfwi_finalize": (i32, []),

@@ -25,6 +25,7 @@
 #include "sbfwi_internal.h"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace {
@@ -126,6 +127,84 @@ __global__ void fem_record_kernel(const double* __restrict__ u, int64_t nn, cons
   record(u + (int64_t)blockIdx.x * nn, rec, n_rec, traces, blockIdx.x, n_steps, col);
 }
 
+// Node ids checked on the device: status bit 2 for an id outside [0, nn).
+__global__ void fem_check_nodes_kernel(const int64_t* __restrict__ nodes, int count, int64_t nn, int* status) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count && (nodes[t] < 0 || nodes[t] >= nn)) atomicOr(status, 2);
+}
+
+__global__ void fem_clear_status_kernel(int* status) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
+}
+
+// Device work buffers of one call: padded kappa, dt^2 / m, the two wavefields.
+struct FemWork {
+  double *kpad = nullptr, *minv = nullptr, *u0 = nullptr, *u1 = nullptr;
+  int* status = nullptr;
+};
+
+// Coefficients, zero initial fields and the time loop (buffers in w); the
+// densities are checked through w.status, which the caller has cleared.
+int fem_run(int nx, int ny, double hx, double hy, const double* rho_elem, double c, double dt, int n_shots,
+            int64_t n_steps, const int64_t* src_node, const double* wavelet, int n_rec, const int64_t* rec_node,
+            double* traces, const FemWork& w, int check_bits, hipStream_t s) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1);
+  const int64_t npad = (int64_t)(nx + 2) * (ny + 2);
+  auto blocks = [](int64_t n) { return (unsigned)((n + kFemBlock - 1) / kFemBlock); };
+  fem_kappa_kernel<<<blocks(npad), kFemBlock, 0, s>>>(nx, ny, rho_elem, c * c, w.kpad, w.status);
+  fem_mass_kernel<<<blocks(nn), kFemBlock, 0, s>>>(nx, ny, rho_elem, hx * hy / 4.0, dt * dt, w.minv);
+  fem_zero_kernel<<<blocks(nn * n_shots), kFemBlock, 0, s>>>(w.u0, nn * n_shots);
+  fem_zero_kernel<<<blocks(nn * n_shots), kFemBlock, 0, s>>>(w.u1, nn * n_shots);
+  SBFWI_HIP(hipGetLastError());
+  int status = 0;
+  SBFWI_HIP(hipMemcpyAsync(&status, w.status, sizeof(int), hipMemcpyDeviceToHost, s));
+  SBFWI_HIP(hipStreamSynchronize(s));
+  if ((status & 2) && (check_bits & 2)) return sbfwi_fail(SBFWI_EINVAL, "a source or receiver node is out of range");
+  if (status & 1) return sbfwi_fail(SBFWI_EINVAL, "element densities must be positive and finite");
+
+  FemDev g{nx, ny, nn, hy / (6.0 * hx), hx / (6.0 * hy), w.kpad, w.minv};
+  // grid padded to a multiple of the XCD count so the block spread is a bijection
+  const unsigned nb = (blocks(nn) + kXcds - 1) / kXcds * kXcds;
+  double* u = w.u1;   // u_k   (k = 1: zero)
+  double* up = w.u0;  // u_{k-1}, overwritten with u_{k+1}
+  for (int64_t k = 1; k < n_steps; ++k) {
+    {
+      ProfScope ps(PK_FEM_STEP, s);
+      fem_step_kernel<<<dim3(nb, n_shots), kFemBlock, 0, s>>>(g, u, up, src_node, wavelet, n_steps, k, rec_node,
+                                                              n_rec, traces);
+    }
+    double* t = u;
+    u = up;
+    up = t;
+  }
+  if (n_rec > 0) fem_record_kernel<<<n_shots, kFemBlock, 0, s>>>(u, nn, rec_node, n_rec, traces, n_steps, n_steps - 1);
+  SBFWI_HIP(hipGetLastError());
+  SBFWI_HIP(hipStreamSynchronize(s));
+  return SBFWI_OK;
+}
+
+// Argument checks shared by both entry points (host values only).
+int fem_check_args(int nx, int ny, double lx, double ly, const double* rho_elem, double c, double dt, int n_shots,
+                   int64_t n_steps, const int64_t* src_node, const double* wavelet, int n_rec,
+                   const int64_t* rec_node, double* traces) {
+  if (nx < 1 || ny < 1 || nx > 32768 || ny > 32768) return sbfwi_fail(SBFWI_EINVAL, "nx, ny must be in 1..32768");
+  if (!(lx > 0.0) || !(ly > 0.0) || !std::isfinite(lx) || !std::isfinite(ly))
+    return sbfwi_fail(SBFWI_EINVAL, "lx, ly must be positive");
+  if (!(c > 0.0) || !(dt > 0.0) || !std::isfinite(c) || !std::isfinite(dt))
+    return sbfwi_fail(SBFWI_EINVAL, "c and dt must be positive");
+  if (n_shots < 1 || n_shots > kMaxShots) return sbfwi_fail(SBFWI_EINVAL, "n_shots must be in 1..%d", kMaxShots);
+  if (n_steps < 1) return sbfwi_fail(SBFWI_EINVAL, "n_steps must be positive");
+  if (n_rec < 0 || (n_rec > 0 && (!rec_node || !traces))) return sbfwi_fail(SBFWI_EINVAL, "bad receivers");
+  if (!rho_elem || !src_node || !wavelet) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  const double hx = lx / nx, hy = ly / ny;
+  // central differences are stable for dt^2 lambda_max(M^-1 K) <= 4; the row
+  // sums bound lambda_max by 4 c^2 (1/hx^2 + 1/hy^2)
+  if (dt * c * std::sqrt(1.0 / (hx * hx) + 1.0 / (hy * hy)) > 1.0)
+    return sbfwi_fail(SBFWI_EINVAL, "dt = %g exceeds the stable step %g of the grid", dt,
+                      1.0 / (c * std::sqrt(1.0 / (hx * hx) + 1.0 / (hy * hy))));
+  return SBFWI_OK;
+}
+
 // Work buffers of one call; released after the stream has drained (also on
 // error returns after launches).
 struct FemBuffers {
@@ -157,21 +236,8 @@ extern "C" int sbfwi_fem_forward(int nx, int ny, double lx, double ly, const dou
                                  double dt, int n_shots, int64_t n_steps, const int64_t* src_node,
                                  const double* wavelet, int n_rec, const int64_t* rec_node, double* traces,
                                  hipStream_t s) {
-  if (nx < 1 || ny < 1 || nx > 32768 || ny > 32768) return sbfwi_fail(SBFWI_EINVAL, "nx, ny must be in 1..32768");
-  if (!(lx > 0.0) || !(ly > 0.0) || !std::isfinite(lx) || !std::isfinite(ly))
-    return sbfwi_fail(SBFWI_EINVAL, "lx, ly must be positive");
-  if (!(c > 0.0) || !(dt > 0.0) || !std::isfinite(c) || !std::isfinite(dt))
-    return sbfwi_fail(SBFWI_EINVAL, "c and dt must be positive");
-  if (n_shots < 1 || n_shots > kMaxShots) return sbfwi_fail(SBFWI_EINVAL, "n_shots must be in 1..%d", kMaxShots);
-  if (n_steps < 1) return sbfwi_fail(SBFWI_EINVAL, "n_steps must be positive");
-  if (n_rec < 0 || (n_rec > 0 && (!rec_node || !traces))) return sbfwi_fail(SBFWI_EINVAL, "bad receivers");
-  if (!rho_elem || !src_node || !wavelet) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
-  const double hx = lx / nx, hy = ly / ny;
-  // central differences are stable for dt^2 lambda_max(M^-1 K) <= 4; the row
-  // sums bound lambda_max by 4 c^2 (1/hx^2 + 1/hy^2)
-  if (dt * c * std::sqrt(1.0 / (hx * hx) + 1.0 / (hy * hy)) > 1.0)
-    return sbfwi_fail(SBFWI_EINVAL, "dt = %g exceeds the stable step %g of the grid", dt,
-                      1.0 / (c * std::sqrt(1.0 / (hx * hx) + 1.0 / (hy * hy))));
+  SBFWI_CHECK(fem_check_args(nx, ny, lx, ly, rho_elem, c, dt, n_shots, n_steps, src_node, wavelet, n_rec,
+                             rec_node, traces));
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1);
   SBFWI_CHECK(check_nodes(src_node, n_shots, nn, s, "source"));
   if (n_rec > 0) SBFWI_CHECK(check_nodes(rec_node, n_rec, nn, s, "receiver"));
@@ -185,34 +251,87 @@ extern "C" int sbfwi_fem_forward(int nx, int ny, double lx, double ly, const dou
   SBFWI_CHECK(sbfwi_alloc(&b.u1, nn * n_shots));
   SBFWI_CHECK(sbfwi_alloc(&b.status, 1));
   SBFWI_HIP(hipMemsetAsync(b.status, 0, sizeof(int), s));
-  auto blocks = [](int64_t n) { return (unsigned)((n + kFemBlock - 1) / kFemBlock); };
-  fem_kappa_kernel<<<blocks(npad), kFemBlock, 0, s>>>(nx, ny, rho_elem, c * c, b.kpad, b.status);
-  fem_mass_kernel<<<blocks(nn), kFemBlock, 0, s>>>(nx, ny, rho_elem, hx * hy / 4.0, dt * dt, b.minv);
-  fem_zero_kernel<<<blocks(nn * n_shots), kFemBlock, 0, s>>>(b.u0, nn * n_shots);
-  fem_zero_kernel<<<blocks(nn * n_shots), kFemBlock, 0, s>>>(b.u1, nn * n_shots);
-  SBFWI_HIP(hipGetLastError());
-  int status = 0;
-  SBFWI_HIP(hipMemcpyAsync(&status, b.status, sizeof(int), hipMemcpyDeviceToHost, s));
-  SBFWI_HIP(hipStreamSynchronize(s));
-  if (status) return sbfwi_fail(SBFWI_EINVAL, "element densities must be positive and finite");
+  FemWork w{b.kpad, b.minv, b.u0, b.u1, b.status};
+  return fem_run(nx, ny, lx / nx, ly / ny, rho_elem, c, dt, n_shots, n_steps, src_node, wavelet, n_rec, rec_node,
+                 traces, w, 0, s);
+}
 
-  FemDev g{nx, ny, nn, hy / (6.0 * hx), hx / (6.0 * hy), b.kpad, b.minv};
-  // grid padded to a multiple of the XCD count so the block spread is a bijection
-  const unsigned nb = (blocks(nn) + kXcds - 1) / kXcds * kXcds;
-  double* u = b.u1;   // u_k   (k = 1: zero)
-  double* up = b.u0;  // u_{k-1}, overwritten with u_{k+1}
-  for (int64_t k = 1; k < n_steps; ++k) {
-    {
-      ProfScope ps(PK_FEM_STEP, s);
-      fem_step_kernel<<<dim3(nb, n_shots), kFemBlock, 0, s>>>(g, u, up, src_node, wavelet, n_steps, k, rec_node,
-                                                              n_rec, traces);
-    }
-    double* t = u;
-    u = up;
-    up = t;
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the work buffers live in scratch, a static device
+// array that every GPU the library runs on holds until the process ends.  Its
+// device address is taken once per device (hipGetSymbolAddress, with that
+// device current) and kept; host code uses only that address, never the
+// array's name.  Every call on a GPU shares the array: calls that overlap on
+// one GPU race.  Layout: the status word, then kpad, minv, u0, u1, each at a
+// 256-byte boundary; everything that must start at zero is cleared by kernels.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kFemScratchBytes = (size_t)48 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kFemScratchBytes / sizeof(double)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of scratch on the current device (taken on its first use there).
+int scratch_address(void** out) {
+  int dev = -1;
+  SBFWI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return sbfwi_fail(SBFWI_EINVAL, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return sbfwi_fail(SBFWI_EHIP, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
   }
-  if (n_rec > 0) fem_record_kernel<<<n_shots, kFemBlock, 0, s>>>(u, nn, rec_node, n_rec, traces, n_steps, n_steps - 1);
-  SBFWI_HIP(hipGetLastError());
-  SBFWI_HIP(hipStreamSynchronize(s));
+  *out = g_scratch_ptr[dev];
   return SBFWI_OK;
+}
+
+inline size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" int sbfwi_fem_forward_noalloc(int nx, int ny, double lx, double ly, const double* rho_elem, double c,
+                                         double dt, int n_shots, int64_t n_steps, const int64_t* src_node,
+                                         const double* wavelet, int n_rec, const int64_t* rec_node,
+                                         double* traces, hipStream_t s) {
+  SBFWI_CHECK(fem_check_args(nx, ny, lx, ly, rho_elem, c, dt, n_shots, n_steps, src_node, wavelet, n_rec,
+                             rec_node, traces));
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1);
+  const int64_t npad = (int64_t)(nx + 2) * (ny + 2);
+  const size_t o_kpad = 256;
+  const size_t o_minv = o_kpad + round256(sizeof(double) * npad);
+  const size_t o_u0 = o_minv + round256(sizeof(double) * nn);
+  const size_t o_u1 = o_u0 + round256(sizeof(double) * nn * n_shots);
+  const size_t need = o_u1 + round256(sizeof(double) * nn * n_shots);
+  if (need > kFemScratchBytes)
+    return sbfwi_fail(SBFWI_EINVAL,
+                      "grid %d x %d with %d shots needs %zu bytes of scratch; the allocation-free call has %zu",
+                      nx, ny, n_shots, need, kFemScratchBytes);
+  void* base = nullptr;
+  SBFWI_CHECK(scratch_address(&base));
+  char* b = static_cast<char*>(base);
+  FemWork w;
+  w.status = reinterpret_cast<int*>(b);
+  w.kpad = reinterpret_cast<double*>(b + o_kpad);
+  w.minv = reinterpret_cast<double*>(b + o_minv);
+  w.u0 = reinterpret_cast<double*>(b + o_u0);
+  w.u1 = reinterpret_cast<double*>(b + o_u1);
+  // the array keeps the last call's contents: the status word is cleared here,
+  // the wavefields by fem_run; node ids are checked on the device
+  fem_clear_status_kernel<<<1, 64, 0, s>>>(w.status);
+  fem_check_nodes_kernel<<<(n_shots + 255) / 256, 256, 0, s>>>(src_node, n_shots, nn, w.status);
+  if (n_rec > 0) fem_check_nodes_kernel<<<(n_rec + 255) / 256, 256, 0, s>>>(rec_node, n_rec, nn, w.status);
+  SBFWI_HIP(hipGetLastError());
+  return fem_run(nx, ny, lx / nx, ly / ny, rho_elem, c, dt, n_shots, n_steps, src_node, wavelet, n_rec, rec_node,
+                 traces, w, 2, s);
 }
