@@ -63,7 +63,10 @@ def main(argv=None):
     ap.add_argument("--coarse-solver", type=int, default=1)
     ap.add_argument("--data", choices=["fem", "sbfem"], default="fem")
     ap.add_argument("--scheme", type=int, default=0, help="0: the paper's radial finite differences; 1: radial Galerkin")
+    ap.add_argument("--phases", default="checks,lbfgs",
+                    help="checks (finite differences, dot product, full storage) and/or lbfgs")
     args = ap.parse_args(argv)
+    phases = {p.strip() for p in args.phases.split(",") if p.strip()}
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import workloads as W
@@ -144,6 +147,18 @@ def main(argv=None):
     else:
         chk, gc = prob, g0
 
+    if "checks" in phases:
+        _checks(args, wl, out, rho_h, rho0, gc, chk, value, value_grad, problem, obs)
+
+    if "lbfgs" in phases:
+        _lbfgs(args, out, rho_h, rho0, J0, value_grad, truth)
+    print(json.dumps(out))
+
+
+def _checks(args, wl, out, rho_h, rho0, gc, chk, value, value_grad, problem, obs):
+    """Finite differences on seeded parameters and along a smooth direction, the
+    dot-product test and the sqrt(T) checkpoints against full storage."""
+    dev = rho_h.device
     rng = np.random.default_rng(3 * 1000 + 1)
     gn = gc.cpu().numpy()
     cand = np.flatnonzero(np.abs(gn) >= 1e-2 * np.abs(gn).max())
@@ -184,6 +199,10 @@ def main(argv=None):
     out["full_storage"] = {"steps": nf, "rel_l2": float(torch.linalg.norm(g_ck - g_full) / torch.linalg.norm(g_full))}
     _log(f"[invert] sqrt(T) vs full storage over {nf} steps: {out['full_storage']['rel_l2']:.2e}")
 
+
+def _lbfgs(args, out, rho_h, rho0, J0, value_grad, truth):
+    """L-BFGS iterations on the density scaling field within [1e-6, 2]."""
+
     def fg(mv):
         v, g = value_grad(rho0 * mv)
         return v / J0, g * (rho0 / J0)
@@ -200,7 +219,6 @@ def main(argv=None):
                     "seconds": time.perf_counter() - t0,
                     "scaling_min": float(res.x.min()), "scaling_max": float(res.x.max()),
                     "image_correlation": float(np.corrcoef(res.x.cpu().numpy(), truth)[0, 1])}
-    print(json.dumps(out))
 
 
 if __name__ == "__main__":

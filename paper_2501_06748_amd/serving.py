@@ -411,7 +411,9 @@ def summarize(results, requests):
 
 def main(argv=None):
     """Serving measurement: plain serial capacity, then the server at 0.5x and
-    0.9x of it (Poisson arrivals) and saturated; prints progress and one JSON line."""
+    0.9x of it (Poisson arrivals) and saturated; prints progress and one JSON line.
+    --phases selects the parts (plain, 0.5, 0.9, saturated); without the plain
+    phase --capacity gives the plain path's shots/s that sets the arrival rates."""
     import argparse
     import json
     import os
@@ -420,6 +422,8 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--scale", default="reduced")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--phases", default="plain,0.5,0.9,saturated")
+    ap.add_argument("--capacity", type=float, default=0.0, help="plain-path shots/s (when plain is not run)")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from workloads.serving import serving_requests
@@ -427,25 +431,34 @@ def main(argv=None):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    phases = [p.strip() for p in args.phases.split(",") if p.strip()]
     base = serving_requests(args.requests, scale=args.scale, rate=1.0)
     out = {"requests": args.requests, "scale": args.scale, "slots": args.slots}
-    # plain path: one request at a time, no batching, no cache, ordinary launches
-    srv = ShotServer(slots=1, batching=False, cache=False, graphs=False, keep_grad=False)
-    res = run_stream(srv, [_at(r, 0.0) for r in base])
-    plain = summarize(res, base)
-    out["plain_serial"] = plain
-    cap = plain["shots_per_s"]
-    log(f"[serving] plain serial: {plain}")
+    cap = args.capacity
+    if "plain" in phases:
+        # plain path: one request at a time, no batching, no cache, ordinary launches
+        srv = ShotServer(slots=1, batching=False, cache=False, graphs=False, keep_grad=False)
+        res = run_stream(srv, [_at(r, 0.0) for r in base])
+        plain = summarize(res, base)
+        out["plain_serial"] = plain
+        cap = plain["shots_per_s"]
+        log(f"[serving] plain serial: {plain}")
     for frac in (0.5, 0.9):
+        if str(frac) not in phases:
+            continue
+        if not cap > 0:
+            raise SystemExit("the load phases need the plain capacity (--capacity or the plain phase)")
         reqs = serving_requests(args.requests, scale=args.scale, rate=frac * cap)
         srv = ShotServer(slots=args.slots, keep_grad=False)
         res = run_stream(srv, reqs)
         out[f"server_at_{frac}x_plain"] = dict(summarize(res, reqs), arrival_rate=frac * cap)
         log(f"[serving] server at {frac} x plain capacity: {out[f'server_at_{frac}x_plain']}")
-    srv = ShotServer(slots=args.slots, keep_grad=False)
-    res = run_stream(srv, [_at(r, 0.0) for r in base])
-    out["server_saturated"] = summarize(res, base)
-    log(f"[serving] saturated: {out['server_saturated']}")
+    if "saturated" in phases:
+        srv = ShotServer(slots=args.slots, keep_grad=False)
+        res = run_stream(srv, [_at(r, 0.0) for r in base])
+        out["server_saturated"] = summarize(res, base)
+        log(f"[serving] saturated: {out['server_saturated']}")
+    out["plain_capacity_shots_per_s"] = cap
     print(json.dumps(out))
 
 

@@ -56,3 +56,37 @@ def test_results_same_alone_and_in_the_mix():
         assert np.isfinite(m.grad).all()
     log(f"worst relative difference alone vs mix over {len(reqs)} requests: {worst:.2e}")
     assert worst <= 1e-12
+
+
+def test_served_results_match_the_oracle():
+    """Two small requests served side by side (two slots, batching, factor cache,
+    graph replay) against the oracle: traces to relative L2 <= 1e-10, misfit to
+    1e-10, per-shot exact gradient to relative L2 <= 1e-8."""
+    from oracle import adjoint as oadj
+    from oracle import stepper as ostp
+    from paper_2501_06748_amd.serving import ShotServer
+    steps = 40
+    reqs = [r for r in serving_requests(40, seed=4 * 1000 + 5, rate=1000.0) if r.model.key in ("u29", "u21")][:2]
+    assert len({r.model.key for r in reqs}) == 2
+    for r in reqs:
+        r.model.n_steps = steps
+        r.n_steps = steps
+    srv = ShotServer(slots=2, batching=True, cache=True, graphs=True)
+    srv.start()
+    for r in reqs:
+        srv.submit(r)
+    res = srv.wait(len(reqs), timeout=240)
+    srv.stop()
+    for r in reqs:
+        got = res[r.rid]
+        assert not got.error, got.error
+        mesh, rho = r.model.build()
+        src, wav, rec, obs = r.inputs(mesh)
+        om = ostp.Model(mesh, rho, r.model.c, r.model.dt)
+        gref, Jref = oadj.exact_gradient(om, np.asarray([src]), wav[None], rec, obs[None], steps)
+        tref = ostp.forward(om, np.asarray([src]), wav[None], rec, steps)[0]
+        et, eg = rel_l2(got.traces, tref), rel_l2(got.grad, gref)
+        log(f"served request {r.rid} ({r.model.key}, {mesh.n_elem} elements): traces {et:.2e}, "
+            f"misfit {got.misfit:.6e} vs {Jref:.6e}, gradient {eg:.2e}")
+        assert et <= 1e-10 and eg <= 1e-8
+        assert got.misfit == pytest.approx(Jref, rel=1e-10, abs=0)
