@@ -70,6 +70,7 @@ def kernel_bytes(mesh, NS, nnz):
     # joint sweeps: the condense of the next step takes its state from the recover sweep in LDS
     out["joint"] = out["recover"] + out["condense"] - NS * 3 * n * nb
     out["joint_store"] = out["recover_store"] + out["condense"] - NS * 3 * n * nb
+    out["adj_joint"] = out["adj_recover"] + out["adj_condense"] - NS * 3 * n * nb
     res = {k: int(8 * v.sum()) for k, v in out.items()}
     nn = int(mesh.n_nodes)
     res["solve_v"] = 12 * nnz + 8 * nn + 8 * NS * nn * 7      # K, D^-1; phat, r, rhat, w in; v, s, shat out
@@ -89,13 +90,14 @@ def method_bytes(mesh, NS):
     and written, forward unknowns read, gradient).  A sweep over half a step (a
     condense or a recover on its own, each adjoint sweep) takes one block and
     half the state; the joint sweep (recover of a step with the condense of the
-    next) the whole step; the gradient contraction the rest of the adjoint's
-    80 n_b: 32 n_b.  Returns bytes per launch and per unit of the whole
+    next) the whole step, and so does the joint transposed sweep (two blocks and
+    the adjoint state's 48 n_b); the gradient contraction the rest of the
+    adjoint's 80 n_b: 32 n_b.  Returns bytes per launch and per unit of the whole
     evaluation (fwd + recompute + adjoint + gradient = 48 n_b^2/S + 192 n_b)."""
     nb = mesh.n_b().astype("float64")
     units = mesh.n_r.astype("float64") * NS            # units of one launch, per element
     blk = nb * nb / NS
-    per_unit = {"joint": 16 * blk + 48 * nb, "joint_store": 16 * blk + 64 * nb,
+    per_unit = {"joint": 16 * blk + 48 * nb, "joint_store": 16 * blk + 64 * nb, "adj_joint": 16 * blk + 48 * nb,
                 "condense": 8 * blk + 24 * nb, "recover": 8 * blk + 24 * nb,
                 "recover_store": 8 * blk + 32 * nb,
                 "adj_condense": 8 * blk + 24 * nb, "adj_recover": 8 * blk + 24 * nb,
@@ -108,7 +110,8 @@ def method_bytes(mesh, NS):
 # kernel instances as rocprofv3 names them (uniform 16-node elements, 4 shots per block)
 ROCPROF_NAME = {"joint": "joint_kernel<16, 4, false>", "joint_store": "joint_kernel<16, 4, true>",
                 "condense": "condense_kernel<16, 4>", "recover": "recover_kernel<16, 4, false>",
-                "recover_store": "recover_kernel<16, 4, true>", "adj_condense": "adj_condense_kernel<16, 4>",
+                "recover_store": "recover_kernel<16, 4, true>", "adj_joint": "adj_joint_kernel<16, 4>",
+                "adj_condense": "adj_condense_kernel<16, 4>",
                 "adj_recover": "adj_recover_kernel<16, 4>", "grad_exact": "grad_exact_kernel<16, 4>"}
 
 
@@ -138,6 +141,7 @@ KERNEL_SOURCES = {"solve_v": ["paper_2501_06748_amd/csrc/coarse.hip"],
                   "joint_store": ["paper_2501_06748_amd/csrc/step.hip"],
                   "adj_condense": ["paper_2501_06748_amd/csrc/adjoint.hip"],
                   "adj_recover": ["paper_2501_06748_amd/csrc/adjoint.hip"],
+                  "adj_joint": ["paper_2501_06748_amd/csrc/adjoint.hip"],
                   "grad_exact": ["paper_2501_06748_amd/csrc/adjoint.hip"],
                   "coarse_solve": ["paper_2501_06748_amd/csrc/coarse.hip"],
                   "fem_step": ["paper_2501_06748_amd/csrc/fem.hip"]}

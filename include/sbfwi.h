@@ -172,9 +172,15 @@ int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
  *             0 = the recompute solves again.
  *   param 5:  1 = the recover sweep of a time step and the condense sweep of the next one
  *             run as one joint sweep per element (the new w of every level kept in LDS), so
- *             that the state is read once per step (default; classes whose LDS would exceed
- *             48 KB, and plans with a persistent sweep launch, run the two sweeps in turn);
- *             0 = two separate sweeps.
+ *             that the state is read once per step, and likewise the transposed recover of
+ *             an adjoint step with the transposed condense of the earlier one (default;
+ *             classes whose LDS would exceed 48 KB, and plans with a persistent sweep
+ *             launch, run the two sweeps in turn); 0 = separate sweeps.
+ *   param 6:  (direct coarse solver) the solve programs of the mesh of f -- shared by every
+ *             factors handle on that mesh -- are rebuilt with the subtree launches (one block
+ *             per subtree, walking its levels) rooted at the shallowest level of the dissection
+ *             tree with at least value supernodes (default 512; a value above every level's
+ *             count gives one launch per level).  Waits for the device to be idle first.
  *   param 10 + 3 k + c: shots per block (0 = default, 1, 2, 4, 8, 16) of sweep k (0 condense,
  *             1 recover, 2 transposed condense, 3 transposed recover) for n_b class c
  *             (n_b <= 8, <= 16, <= 24).
@@ -305,6 +311,16 @@ int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
                    const double* traces, int mode, double* misfit, double* grad,
                    hipStream_t s);
 
+/*
+ * sbfwi_misfit -- the waveform misfit of eq. misfit with the rectangle rule,
+ * misfit[0] = 1/2 dt sum_i (traces[i] - observed[i])^2 over count samples (one
+ * deterministic reduction), and, if residual is not NULL, its derivative with
+ * respect to every trace sample, residual[i] = dt (traces[i] - observed[i]) (the
+ * adjoint source of sbfwi_adjoint).  All arrays device memory; asynchronous on s.
+ */
+int sbfwi_misfit(const double* observed, const double* traces, int64_t count, double dt, double* residual,
+                 double* misfit, hipStream_t s);
+
 /* Checkpointed run (host values): host_out[0] footprint in bytes, [1] checkpoint interval,
  * [2] shots, [3] receivers, [4] steps of the run -- the leading sizes of the adj_src,
  * observed and traces arrays that sbfwi_adjoint and sbfwi_gradient read, and of the
@@ -347,10 +363,12 @@ int sbfwi_factors_info(sbfwi_factors f, int64_t* host_out);
  * also stores the adjoint's inputs; id 1 counts the other recover sweeps), 17 the
  * time step of sbfwi_fem_forward, 18 the joint sweep (recover of a step and condense
  * of the next, sbfwi_set_launch param 5), 19 its checkpoint-recompute variant with
- * the stores; ids 0, 1 and 16 then count only the sweeps that run alone.  A sweep over elements of several n_b classes counts as
+ * the stores, 20 the joint transposed sweep (transposed recover of an adjoint step and
+ * transposed condense of the earlier one); ids 0, 1, 5, 6 and 16 then count only the
+ * sweeps that run alone.  A sweep over elements of several n_b classes counts as
  * one launch.  Recorded pairs are accumulated as they complete (the oldest
  * are waited for once many are in flight).  sbfwi_profile_read waits for the
- * rest and writes, for each of the 20 ids, host_out[2 id] = launches and
+ * rest and writes, for each of the 21 ids, host_out[2 id] = launches and
  * host_out[2 id + 1] = total ms; reset != 0 clears the totals.  One host
  * thread only.
  */

@@ -208,7 +208,7 @@ def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
 
 
 LAUNCH_ENQUEUED_ITERS, LAUNCH_GRAPHS, LAUNCH_RESET_PLAN = 0, 1, 2
-LAUNCH_OVERLAP_BACKWARD, LAUNCH_KEEP_SOLUTIONS, LAUNCH_JOINT_SWEEPS = 3, 4, 5
+LAUNCH_OVERLAP_BACKWARD, LAUNCH_KEEP_SOLUTIONS, LAUNCH_JOINT_SWEEPS, LAUNCH_SUBTREE_CUT = 3, 4, 5, 6
 
 
 def launch_param_shots(sweep: int, cls: int) -> int:
@@ -329,6 +329,19 @@ def sbfwi_gradient(f: FactorsHandle, ck: CkptHandle, observed, traces, mode, mis
                                _stream(stream)))
 
 
+def sbfwi_misfit(observed, traces, dt, misfit, residual=None, stream=None):
+    """misfit [1] = 1/2 dt sum (traces - observed)^2; residual (optional, like traces) = dt (traces - observed)."""
+    import torch
+    if observed.shape != traces.shape or (residual is not None and residual.shape != traces.shape):
+        raise ValueError("observed, traces and residual must have the same shape")
+    if misfit.numel() < 1:
+        raise ValueError("misfit must hold one value")
+    check(lib().sbfwi_misfit(_dptr(observed, torch.float64, "observed"), _dptr(traces, torch.float64, "traces"),
+                             int(traces.numel()), float(dt),
+                             _dptr(residual, torch.float64, "residual") if residual is not None else None,
+                             _dptr(misfit, torch.float64, "misfit"), _stream(stream)))
+
+
 def sbfwi_ckpt_info(ck: CkptHandle) -> dict:
     buf = np.zeros(5, dtype=np.int64)
     check(lib().sbfwi_ckpt_info(ck, buf.ctypes.data_as(C.c_void_p)))
@@ -345,7 +358,7 @@ def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:
 PROFILE_KERNELS = ["condense", "recover", "coarse_solve", "source_gather", "nodal_update", "adj_condense",
                    "adj_recover", "adj_gather", "adj_nodal_update", "grad_exact", "grad_paper", "factor",
                    "solve_v", "solve_t", "solve_x", "solve_init", "recover_store", "fem_step", "joint",
-                   "joint_store"]
+                   "joint_store", "adj_joint"]
 
 
 def sbfwi_profile(kernels):
@@ -355,7 +368,7 @@ def sbfwi_profile(kernels):
 
 
 def sbfwi_profile_read(reset=False) -> dict:
-    buf = np.zeros(40, dtype=np.float64)
+    buf = np.zeros(2 * len(PROFILE_KERNELS), dtype=np.float64)
     check(lib().sbfwi_profile_read(buf.ctypes.data_as(C.c_void_p), int(bool(reset))))
     return {name: {"launches": int(buf[2 * i]), "ms": float(buf[2 * i + 1])}
             for i, name in enumerate(PROFILE_KERNELS) if buf[2 * i] > 0}

@@ -41,6 +41,7 @@ SIGNATURES = {
     "sbfwi_adjoint": (i32, [vp, vp, vp, i32, vp, vp]),
     "sbfwi_gradient": (i32, [vp, vp, vp, vp, i32, vp, vp, vp]),
     "sbfwi_ckpt_info": (i32, [vp, vp]),
+    "sbfwi_misfit": (i32, [vp, vp, i64, dbl, vp, vp, vp]),
     "sbfwi_factors_info": (i32, [vp, vp]),
     "sbfwi_solver_stats": (i32, [vp, vp, i32]),
     "sbfwi_fem_forward": (i32, [i32, i32, dbl, dbl, vp, dbl, dbl, i32, i64, vp, vp, i32, vp, vp, vp]),

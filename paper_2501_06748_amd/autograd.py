@@ -23,7 +23,7 @@ from dataclasses import dataclass
 import torch
 from torch.autograd.function import once_differentiable
 
-from . import (GRAD_EXACT, sbfwi_adjoint, sbfwi_factor_elements, sbfwi_forward, sbfwi_mesh_info,
+from . import (GRAD_EXACT, sbfwi_adjoint, sbfwi_misfit, sbfwi_factor_elements, sbfwi_forward, sbfwi_mesh_info,
                sbfwi_set_solver)
 
 
@@ -92,6 +92,25 @@ def simulate(rho: torch.Tensor, prob: WaveProblem) -> torch.Tensor:
     return _Traces.apply(rho, prob)
 
 
+class _Misfit(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, traces, observed, dt):
+        tr, ob = traces.detach().contiguous(), observed.detach().contiguous()
+        val = torch.zeros(1, dtype=torch.float64, device=tr.device)
+        res = torch.empty_like(tr)
+        sbfwi_misfit(ob, tr, dt, val, residual=res)
+        ctx.save_for_backward(res)
+        return val[0]
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, g):
+        (res,) = ctx.saved_tensors
+        return res * g, -res * g, None
+
+
 def misfit(traces: torch.Tensor, observed: torch.Tensor, dt: float) -> torch.Tensor:
-    """Waveform misfit of eq. misfit with the rectangle rule: 1/2 sum dt (u - d)^2."""
-    return 0.5 * dt * ((traces - observed) ** 2).sum()
+    """Waveform misfit of eq. misfit with the rectangle rule, 1/2 sum dt (u - d)^2,
+    computed by the library (sbfwi_misfit, which also returns the residual
+    dt (u - d) that the backward passes on)."""
+    return _Misfit.apply(traces.to(torch.float64), observed.to(torch.float64), float(dt))

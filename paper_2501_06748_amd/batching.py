@@ -43,6 +43,7 @@ def main(argv=None):
     ap.add_argument("--nt", type=int, default=4000)
     ap.add_argument("--shots", type=int, default=16)
     ap.add_argument("--coarse-solver", type=int, default=1)
+    ap.add_argument("--skip-plain", action="store_true", help="run the batched path only (profiling)")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import workloads as W
@@ -82,7 +83,7 @@ def main(argv=None):
     mis_plain = 0.0
     gs = torch.zeros_like(g_plain)
     mis = torch.zeros(1, dtype=torch.float64, device=dev)
-    for s in range(S):
+    for s in range(0 if args.skip_plain else S):
         tr = torch.zeros((1, R, N), dtype=torch.float64, device=dev)
         ck = sbfwi_forward(f, src[s:s + 1], wav[s:s + 1].contiguous(), rec, tr, n_ckpt=-1)
         sbfwi_gradient(f, ck, observed[s:s + 1].contiguous(), tr, GRAD_EXACT, mis, gs)
@@ -113,11 +114,27 @@ def main(argv=None):
     f.close()
     _log(f"[batching] batched path done in {t_batch:.2f} s (plain {t_plain:.2f} s)")
 
-    out["plain"] = {"seconds": t_plain, "units_per_s": units / t_plain, "misfit": mis_plain}
+    # HBM roofline of the whole batched evaluation on the method's byte model: per element,
+    # level, time step and shot 48 n_b^2 / S + 192 n_b bytes (forward, checkpoint recompute,
+    # adjoint and gradient; S shots share each streamed factor block), with S the run's shot
+    # count (ideal sharing) and with S the autotuned recover shots per block of each n_b class
+    nb = m.n_b().astype(np.float64)
+    nr = m.n_r.astype(np.float64)
+    cls = np.where(nb <= 8, 0, np.where(nb <= 16, 1, 2))
+    s_blk = np.asarray([max(plan["recover"]["shots_per_block"][c], 1) for c in cls], dtype=np.float64)
+    eval_ideal = float((nr * N * S * (48 * nb * nb / S + 192 * nb)).sum())
+    eval_plan = float((nr * N * S * (48 * nb * nb / s_blk + 192 * nb)).sum())
     out["batched"] = {"seconds": t_batch, "units_per_s": units / t_batch, "misfit": float(mis.item()),
-                      "autotune_seconds": t_tune, "plan": plan, "coarse_solver": stats}
-    out["speedup"] = t_plain / t_batch
-    out["gradient_rel_l2"] = float(torch.linalg.norm(g_b - g_plain) / torch.linalg.norm(g_plain))
+                      "autotune_seconds": t_tune, "plan": plan, "coarse_solver": stats,
+                      "roofline": {"bound": "hbm", "peak_GBs": 8000.0,
+                                   "algorithmic_bytes_shared_by_all_shots": eval_ideal,
+                                   "frac": eval_ideal / t_batch / 8e12,
+                                   "algorithmic_bytes_at_plan_shots_per_block": eval_plan,
+                                   "frac_at_plan": eval_plan / t_batch / 8e12}}
+    if not args.skip_plain:
+        out["plain"] = {"seconds": t_plain, "units_per_s": units / t_plain, "misfit": mis_plain}
+        out["speedup"] = t_plain / t_batch
+        out["gradient_rel_l2"] = float(torch.linalg.norm(g_b - g_plain) / torch.linalg.norm(g_plain))
     print(json.dumps(out))
 
 

@@ -95,13 +95,23 @@ __device__ __forceinline__ double denseT_mv(const double* F, const double* vec, 
 // unconditionally and the waits for the prefetched level count exactly.
 __device__ double g_adj_sink[WT];
 
+// u~ = u-bar + c1 v-bar + a0 a-bar from a level's seeds, with explicit
+// multiply-adds so that every sweep that forms it rounds it alike.
+__device__ __forceinline__ double adj_utilde(const FactorsDev& f, double ub, double vb, double ab) {
+  return fma(f.a0, ab, fma(f.c1, vb, ub));
+}
+
 // U^T sweep: z_j, and the coupling psi~_{n-1}^T z_{n-1} to the coarse rows.
 // The next level's F block, seeds and psi~ band entries are loaded at the top
 // of each level and consumed at its end; lanes without an item load word 0 of
 // their arrays and store to g_adj_sink.
-template <int NBT, int S>
+// JOINT: u~ of every level comes from ukeep (LDS, level-major, written by the
+// transposed recover sweep of the later step in the same block) instead of the
+// seeds in HBM.
+template <int NBT, int S, bool JOINT = false>
 __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
-                                                  const AdjArgs& a, AdjLds<NBT, S>& L) {
+                                                  const AdjArgs& a, AdjLds<NBT, S>& L,
+                                                  const double* ukeep = nullptr) {
   constexpr int IPT = (NBT * S + WT - 1) / WT;
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
@@ -126,9 +136,13 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
     for (int u = 0; u < IPT; ++u) {
       const int i = ii[u];
       const int64_t g = ok[u] ? (io + (int64_t)j * nb + i) * a.NS + s0 + si[u] : 0;
-      uu[u] = a.ub[g];
-      vv[u] = a.vb[g];
-      aa[u] = a.ab[g];
+      if (JOINT) {   // u~ from ukeep: no seed loads
+        uu[u] = vv[u] = aa[u] = 0.0;
+      } else {
+        uu[u] = a.ub[g];
+        vv[u] = a.vb[g];
+        aa[u] = a.ab[g];
+      }
       const double* bp = f.ps_band + 3 * (po + (int64_t)(j > 0 ? j - 1 : 0) * nb);
       bd[0][u] = bp[2 * nb + md(i - 1, nb)];
       bd[1][u] = bp[nb + i];
@@ -150,7 +164,7 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
-      double y = ok[u] ? cu[u] + f.c1 * cv[u] + f.a0 * ca[u] : 0.0;
+      double y = JOINT ? ukeep[j * items + it] : (ok[u] ? adj_utilde(f, cu[u], cv[u], ca[u]) : 0.0);
       if (j == 1) {
         const double* P0 = f.psit0 + m.dense_off[e];
         double acc = 0.0;
@@ -195,9 +209,12 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
 // Level loop of the L^T sweep (j = n-1 .. 0) with the adjoint Newmark chain;
 // the next level's F block, z, seeds and the theta / P band entries are loaded
 // at the top of each level and consumed at its end.
+// ukeep (LDS, may be NULL): receives u~ of the new seeds of every level,
+// ukeep[j * items + it], for the transposed condense of the earlier step.
 template <int NBT, int S, bool LAM>
 __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev& m, const FactorsDev& f,
-                                                   const AdjArgs& a, AdjLds<NBT, S>& L, double (&reg)[(NBT * NBT + WT - 1) / WT]) {
+                                                   const AdjArgs& a, AdjLds<NBT, S>& L,
+                                                   double (&reg)[(NBT * NBT + WT - 1) / WT], double* ukeep) {
   constexpr int IPT = (NBT * S + WT - 1) / WT;
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
@@ -270,9 +287,11 @@ __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev&
       const double wb = (cp[0][u] * L.y[md(i - 1, nb) * S + s] + cp[1][u] * L.y[i * S + s] +
                          cp[2][u] * L.y[md(i + 1, nb) * S + s]) - ca[u];
       double* sink = g_adj_sink + threadIdx.x;
-      *(ok[u] ? a.ub + g : sink) = -f.c1 * vb + f.a0 * wb;
-      *(ok[u] ? a.vb + g : sink) = f.c2 * vb + f.a1 * wb;
-      *(ok[u] ? a.ab + g : sink) = f.c3 * vb + f.a2 * wb;
+      const double nub = -f.c1 * vb + f.a0 * wb, nvb = f.c2 * vb + f.a1 * wb, nab = f.c3 * vb + f.a2 * wb;
+      *(ok[u] ? a.ub + g : sink) = nub;
+      *(ok[u] ? a.vb + g : sink) = nvb;
+      *(ok[u] ? a.ab + g : sink) = nab;
+      if (ukeep && own[u]) ukeep[j * items + it] = ok[u] ? adj_utilde(f, nub, nvb, nab) : 0.0;
       if (LAM) *(ok[u] ? a.lam + (xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s : sink) = own[u] ? L.y[it] : 0.0;
     }
     __syncthreads();
@@ -296,7 +315,7 @@ __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev&
 // L^T sweep, adjoint Newmark chain at the interior levels, and P_n^T lambda_n.
 template <int NBT, int S>
 __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
-                                                 const AdjArgs& a, AdjLds<NBT, S>& L) {
+                                                 const AdjArgs& a, AdjLds<NBT, S>& L, double* ukeep = nullptr) {
   const int ns = min(S, a.NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1, nbnb = nb * nb;
   const int64_t io = m.int_off[e], lo = m.loop_off[e], po = m.par_off[e], xo = m.x_off[e];
@@ -331,8 +350,8 @@ __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m
     }
   }
   __syncthreads();
-  if (a.lam) adj_recover_levels<NBT, S, true>(e, s0, m, f, a, L, reg);
-  else adj_recover_levels<NBT, S, false>(e, s0, m, f, a, L, reg);
+  if (a.lam) adj_recover_levels<NBT, S, true>(e, s0, m, f, a, L, reg, ukeep);
+  else adj_recover_levels<NBT, S, false>(e, s0, m, f, a, L, reg, ukeep);
   if (!a.lam) return;
   // lambda_{-1} = -theta_{-1}^-T theta_0^T lambda_0
   const double* th0 = f.th_band + 3 * po;
@@ -361,6 +380,23 @@ __global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restri
                                                          FactorsDev f, AdjArgs a) {
   __shared__ AdjLds<NBT, S> L;
   adj_recover_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+}
+
+// Joint transposed sweep of one (element, group of S shots): the transposed
+// recover of adjoint step k (down the levels), which keeps u~ of every level's
+// new seeds in LDS, then the transposed condense of step k - 1 (up the levels)
+// from them; the same expressions as the separate sweeps, so the same bits,
+// with the seeds read once per step instead of twice and one launch fewer.
+template <int NBT, int S>
+__global__ void __launch_bounds__(WT) adj_joint_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                       FactorsDev f, AdjArgs a) {
+  __shared__ AdjLds<NBT, S> L;
+  extern __shared__ double ukeep[];   // [interior levels][n_b * S] of the element
+  const int e = elems[blockIdx.x];
+  const int s0 = blockIdx.y * S;
+  adj_recover_body<NBT, S>(e, s0, m, f, a, L, ukeep);
+  __syncthreads();
+  adj_condense_body<NBT, S, true>(e, s0, m, f, a, L, ukeep);
 }
 
 // One persistent launch over all n_b classes (work items in order of
@@ -738,7 +774,7 @@ __global__ void misfit_kernel(const double* __restrict__ tr, const double* __res
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
     double r = tr[i] - ob[i];
-    res[i] = dt * r;
+    if (res) res[i] = dt * r;
     acc += r * r;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
@@ -826,6 +862,56 @@ void launch_adj_sweep(bool condense, sbfwi_factors_s* fac, const AdjArgs& a, hip
   launch_adj_plan(condense, fac->m, fac->d, fac->plan, a, st);
 }
 
+// LDS bound of a joint transposed-sweep block; larger classes run the two sweeps in turn.
+constexpr size_t kAdjJointLdsMax = 48 * 1024;
+
+template <int NBT, int S>
+bool launch_adj_joint_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+  const int64_t cnt = (int64_t)m->h_class_elems[cl].size();
+  if (cnt == 0) return true;
+  const size_t dyn = (size_t)m->class_nmax[cl] * NBT * S * sizeof(double);
+  if (sizeof(AdjLds<NBT, S>) + dyn > kAdjJointLdsMax) return false;
+  dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  hipLaunchKernelGGL((adj_joint_kernel<NBT, S>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+  return true;
+}
+
+template <int NBT>
+bool launch_adj_joint_s(sbfwi_mesh_s* m, int cl, int S, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
+  switch (S) {
+    case 1: return launch_adj_joint_cls<NBT, 1>(m, cl, f, a, st);
+    case 2: return launch_adj_joint_cls<NBT, 2>(m, cl, f, a, st);
+    case 4: return launch_adj_joint_cls<NBT, 4>(m, cl, f, a, st);
+    case 8: return launch_adj_joint_cls<NBT, 8>(m, cl, f, a, st);
+    default: return launch_adj_joint_cls<NBT, 16>(m, cl, f, a, st);
+  }
+}
+
+// Transposed recover of step k and transposed condense of step k - 1: one joint
+// launch per n_b class with the recover's shots per block, or the two sweeps in
+// turn where the LDS would not fit or the plan runs a persistent launch.
+void launch_adj_joint(sbfwi_factors_s* fac, const AdjArgs& a, hipStream_t st) {
+  sbfwi_mesh_s* m = fac->m;
+  const SweepPlan& plan = fac->plan;
+  if (plan.fusedS[SW_ADJ_RECOVER] > 0 || plan.fusedS[SW_ADJ_CONDENSE] > 0) {
+    launch_adj_sweep(false, fac, a, st);
+    launch_adj_sweep(true, fac, a, st);
+    return;
+  }
+  ProfScope ps(PK_ADJ_JOINT, st);
+  const int def = sbfwi_default_shots_per_block(a.NS);
+  for (int cl = 0; cl < 3; ++cl) {
+    const int S = plan.S[SW_ADJ_RECOVER][cl] > 0 ? plan.S[SW_ADJ_RECOVER][cl] : def;
+    const bool ok = cl == 0 ? launch_adj_joint_s<8>(m, cl, S, fac->d, a, st)
+                            : cl == 1 ? launch_adj_joint_s<16>(m, cl, S, fac->d, a, st)
+                                      : launch_adj_joint_s<24>(m, cl, S, fac->d, a, st);
+    if (ok) continue;
+    const int Sc = plan.S[SW_ADJ_CONDENSE][cl] > 0 ? plan.S[SW_ADJ_CONDENSE][cl] : def;
+    launch_adj_cls(false, m, cl, S, fac->d, a, st);
+    launch_adj_cls(true, m, cl, Sc, fac->d, a, st);
+  }
+}
+
 template <int NBT, int S>
 void launch_grad_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, int NS, const double* X, const double* lam,
                      const double* acc, double* grad, int64_t stride, hipStream_t st) {
@@ -888,6 +974,13 @@ int sbfwi_misfit_residual(const double* traces, const double* observed, int64_t 
   hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(1024), 0, s, traces, observed, count, dt, residual, misfit);
   SBFWI_HIP(hipGetLastError());
   return SBFWI_OK;
+}
+
+extern "C" int sbfwi_misfit(const double* observed, const double* traces, int64_t count, double dt,
+                            double* residual, double* misfit, hipStream_t s) {
+  if (!misfit || (count > 0 && (!observed || !traces))) return sbfwi_fail(SBFWI_EINVAL, "NULL argument");
+  if (count < 0 || !(dt > 0)) return sbfwi_fail(SBFWI_EINVAL, "count must be >= 0 and dt positive");
+  return sbfwi_misfit_residual(traces, observed, count, dt, residual, misfit, s);
 }
 
 // The backward pass.  Checkpoint segments are recomputed (forward steps that
@@ -975,6 +1068,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   };
   const bool ov = sr != nullptr && !ck->full_store;
   const bool gs = sg != nullptr && mode == SBFWI_GRAD_EXACT;
+  bool adj_condensed = false;   // the transposed condense of the next adjoint step is done
   int64_t n_grad = 0;   // contractions launched on sg
   if (ov || gs) {   // the side streams start after everything enqueued on st so far
     SBFWI_HIP(hipEventRecord(ev[4], st));
@@ -1022,7 +1116,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
           if (n_grad >= 2) SBFWI_HIP(hipStreamWaitEvent(st, ev[7 + q], 0));
           a.lam = w.lam + (int64_t)q * m->n_x * NS;
         }
-        launch_adj_sweep(true, f, a, st);
+        if (!adj_condensed) launch_adj_sweep(true, f, a, st);
         {
         ProfScope ps(PK_ADJ_RHS, st);
         hipLaunchKernelGGL(adj_rhs_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a, w.rhs, ck->n_rec,
@@ -1030,7 +1124,14 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         }
         SBFWI_HIP(hipGetLastError());
         SBFWI_CHECK(sbfwi_coarse_solve(f, &w.cw, 1, w.rhs, w.lamB, k, st));
-        launch_adj_sweep(false, f, a, st);
+        // the transposed recover of step k, joined with the transposed condense of step k - 1
+        if (k > 1 && f->joint_sweeps) {
+          launch_adj_joint(f, a, st);
+          adj_condensed = true;
+        } else {
+          launch_adj_sweep(false, f, a, st);
+          adj_condensed = false;
+        }
         {
           ProfScope ps(PK_ADJ_NODAL, st);
           hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);

@@ -197,6 +197,12 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
     f->keep_solutions = value;
     return SBFWI_OK;
   }
+  if (param == 6) {
+    if (value < 1) return sbfwi_fail(SBFWI_EINVAL, "the subtree cut needs at least 1 supernode per level");
+    if (!f->dnum) return sbfwi_fail(SBFWI_EINVAL, "the subtree cut applies to the direct coarse solver");
+    SBFWI_HIP(hipDeviceSynchronize());   // no solve may be reading the programs being replaced
+    return sbfwi_direct_programs(f->m, value);
+  }
   if (param == 5) {
     if (value != 0 && value != 1) return sbfwi_fail(SBFWI_EINVAL, "joint sweep flag must be 0 or 1");
     f->joint_sweeps = value;

@@ -363,7 +363,8 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   // row blocks: forward FW_J (|J| + |B_J|) x |J|, backward BM_J |J| x (|J| + |B_J|)
   ds->fw_off.assign(nS + 1, 0);
   ds->bm_off.assign(nS + 1, 0);
-  std::vector<int64_t> fr_off(nS + 1, 0);   // front rows (J then B_J) of every supernode
+  std::vector<int64_t>& fr_off = ds->fr_off;   // front rows (J then B_J) of every supernode
+  fr_off.assign(nS + 1, 0);
   for (int J = 0; J < nS; ++J) {
     const int64_t nj = ds->sn_ptr[J + 1] - ds->sn_ptr[J], nb = ds->b_ptr[J + 1] - ds->b_ptr[J];
     ds->fw_off[J + 1] = ds->fw_off[J] + (nj + nb) * nj;
@@ -375,7 +376,10 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
   }
   // the children's update entries that land in each front row of J (B_c lies in J and B_J),
   // listed child by child
-  std::vector<int64_t> gl_ptr(fr_off[nS] + 1, 0), gl;
+  std::vector<int64_t>& gl_ptr = ds->gl_ptr;
+  std::vector<int64_t>& gl = ds->gl;
+  gl_ptr.assign(fr_off[nS] + 1, 0);
+  gl.clear();
   auto front_row = [&](int J, int64_t p) -> int64_t {   // front row of position p in J, or -1
     const int64_t j0 = ds->sn_ptr[J], j1 = ds->sn_ptr[J + 1];
     if (p >= j0 && p < j1) return p - j0;
@@ -408,11 +412,35 @@ int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* node_xy) {
     std::vector<int32_t> fill(ds->lvl_ptr.begin(), ds->lvl_ptr.end() - 1);
     for (int J = 0; J < nS; ++J) ds->lvl_sn[fill[ds->level[J]]++] = J;
   }
-  // cut level: the shallowest level with at least kSubtrees supernodes; the
+  return sbfwi_direct_programs(m, kSubtrees);
+}
+
+// Solve programs of the mesh's dissection with the subtree launches cut at the
+// shallowest level that has at least min_subtrees supernodes (none if no level
+// has that many); replaces programs built before.
+int sbfwi_direct_programs(sbfwi_mesh_s* m, int min_subtrees) {
+  DirectSym* ds = m->dsym;
+  if (!ds) return sbfwi_fail(SBFWI_EINVAL, "mesh has no dissection order");
+  if (min_subtrees < 1) return sbfwi_fail(SBFWI_EINVAL, "the subtree cut needs at least 1 supernode per level");
+  const int64_t n = m->n_nodes;
+  const int nS = ds->nS;
+  const std::vector<int64_t>& fr_off = ds->fr_off;
+  const std::vector<int64_t>& gl_ptr = ds->gl_ptr;
+  const std::vector<int64_t>& gl = ds->gl;
+  for (int t = 0; t < 2; ++t) {
+    sbfwi_dev_free(ds->prog[t].vrec);
+    sbfwi_dev_free(ds->prog[t].rrec);
+    sbfwi_dev_free(ds->prog[t].steps);
+    sbfwi_dev_free(ds->prog[t].blk);
+    ds->prog[t] = DProgDev();
+    ds->launches[t].clear();
+  }
+  ds->max_slots = 0;
+  // cut level: the shallowest level with at least min_subtrees supernodes; the
   // subtrees rooted there are solved by one block each
   ds->cut = ds->depth + 1;
   for (int l = 0; l <= ds->depth; ++l)
-    if (ds->lvl_ptr[l + 1] - ds->lvl_ptr[l] >= kSubtrees) {
+    if (ds->lvl_ptr[l + 1] - ds->lvl_ptr[l] >= min_subtrees) {
       ds->cut = l;
       break;
     }

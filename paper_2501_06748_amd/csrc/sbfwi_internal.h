@@ -104,6 +104,7 @@ struct DirectSym {
   std::vector<int64_t> pos, inv, sn_ptr, b_ptr, bpos, fw_off, bm_off;
   std::vector<int32_t> level, lvl_ptr, lvl_sn, snp;
   std::vector<std::vector<int32_t>> children;
+  std::vector<int64_t> fr_off, gl_ptr, gl;   // front rows and the children's update entries per row
   int cut = 0, n_sub = 0;             // subtree blocks: cut level and their count
   int max_slots = 0;                  // largest LDS vector of any block (slots)
   std::vector<DLaunch> launches[2];   // forward, backward programs in launch order
@@ -241,12 +242,12 @@ struct sbfwi_ckpt_s {
 constexpr double kEnvelopeSafety = 10.0;
 
 // ---- live kernel timing (profiler.cpp) ----
-#define SBFWI_PROF_KERNELS 20
+#define SBFWI_PROF_KERNELS 21
 enum {
   PK_CONDENSE = 0, PK_RECOVER = 1, PK_SOLVE = 2, PK_RHS = 3, PK_NODAL = 4, PK_ADJ_CONDENSE = 5,
   PK_ADJ_RECOVER = 6, PK_ADJ_RHS = 7, PK_ADJ_NODAL = 8, PK_GRAD_EXACT = 9, PK_GRAD_PAPER = 10,
   PK_FACTOR = 11, PK_SOLVE_V = 12, PK_SOLVE_T = 13, PK_SOLVE_X = 14, PK_SOLVE_INIT = 15,
-  PK_RECOVER_STORE = 16, PK_FEM_STEP = 17, PK_JOINT = 18, PK_JOINT_STORE = 19
+  PK_RECOVER_STORE = 16, PK_FEM_STEP = 17, PK_JOINT = 18, PK_JOINT_STORE = 19, PK_ADJ_JOINT = 20
 };
 // Brackets the launches made during its lifetime with events on stream s when
 // kernel id is enabled by sbfwi_profile.
@@ -387,6 +388,9 @@ int sbfwi_step_zero(sbfwi_mesh_s* m, StepWork* w, hipStream_t s);
 // in ms of the per-class and of the fused variants.
 // Direct coarse solver (direct.hip).
 int sbfwi_direct_symbolic(sbfwi_mesh_s* m, const double* host_node_xy);
+// (Re)builds the solve programs with the subtree launches cut at the shallowest
+// level holding at least min_subtrees supernodes (the device must be idle).
+int sbfwi_direct_programs(sbfwi_mesh_s* m, int min_subtrees);
 void sbfwi_direct_sym_free(DirectSym* ds);
 int sbfwi_direct_factor(sbfwi_factors_s* f, hipStream_t s);
 void sbfwi_direct_num_free(DirectNum* dn);

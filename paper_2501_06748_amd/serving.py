@@ -390,7 +390,7 @@ def run_stream(server, requests, time_scale=1.0):
             time.sleep(delay)
         server.submit(r)
     res = {}
-    step = max(1, len(requests) // 8)
+    step = 1 if len(requests) <= 64 else len(requests) // 8
     for k in range(step, len(requests) + step, step):     # progress lines while waiting
         res = server.wait(min(k, len(requests)))
         print(f"[serving] {len(res)}/{len(requests)} requests done at {server.now():.1f} s", file=sys.stderr,

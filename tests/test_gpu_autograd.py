@@ -167,3 +167,28 @@ def test_lbfgs_on_scaling_field():
     assert all(h1 <= h0 for h0, h1 in zip(res.history, res.history[1:]))
     assert res.history[-1] < 0.25 * res.history[0]
     assert float(res.x.min()) >= 1e-6 and float(res.x.max()) <= 2.0
+
+
+def test_library_misfit_matches_the_oracle():
+    """sbfwi_misfit (what autograd.misfit calls) against the oracle's misfit on seeded
+    traces, and its residual against dt (u - d); the autograd Function's gradient with
+    respect to the traces is that residual."""
+    import torch
+    import paper_2501_06748_amd as sb
+    from paper_2501_06748_amd.autograd import misfit
+    rng = np.random.default_rng(17)
+    tr = rng.standard_normal((3, 7, 41))
+    ob = rng.standard_normal((3, 7, 41))
+    dt = 2e-8
+    t = torch.tensor(tr, device="cuda", requires_grad=True)
+    o = torch.tensor(ob, device="cuda")
+    val = torch.zeros(1, dtype=torch.float64, device="cuda")
+    res = torch.empty_like(o)
+    sb.sbfwi_misfit(o, t.detach(), dt, val, residual=res)
+    J = misfit(t, o, dt)
+    J.backward()
+    ref = ostp.misfit(tr, ob, dt)
+    assert float(val.item()) == pytest.approx(ref, rel=1e-13)
+    assert float(J.item()) == pytest.approx(ref, rel=1e-13)
+    assert np.allclose(res.cpu().numpy(), dt * (tr - ob), rtol=1e-15, atol=0)
+    assert np.allclose(t.grad.cpu().numpy(), dt * (tr - ob), rtol=1e-15, atol=0)

@@ -112,3 +112,40 @@ def test_solve_program_structure():
     assert len(fwd) == len(bwd) and fwd[0]["subtrees"] == 1 and bwd[-1]["subtrees"] == 1
     assert all(L["subtrees"] == 0 for L in fwd[1:]) and fwd[-1]["blocks"] >= 1
     assert all(1 <= L["lanes"] <= 64 and L["slots"] >= 1 for L in fwd + bwd)
+
+
+@pytest.mark.parametrize("cut", [1, 2, 4, 8, 10 ** 9])
+def test_subtree_cut_levels_against_the_oracle(cut):
+    """The solve programs rebuilt with the subtree launches at other depths
+    (sbfwi_set_launch param 6) on a 12 x 6 plate whose dissection tree has five
+    levels (1, 2, 4, 8, 8 supernodes): cut 1 makes the whole tree one subtree
+    walked by one block in each direction, 2, 4 and 8 root the subtrees at
+    levels 1, 2 and 3, and a cut no level reaches gives one launch per level.
+    Forward traces and the exact gradient (which runs the transposed programs)
+    match the oracle."""
+    import paper_2501_06748_amd as sb
+    wl = W.config_small(nx=12, ny=6, segs=2, n_r=7, n_steps=24, n_shots=2)
+    rho = wl.models["random30"]
+    om = _om(wl, rho)
+    obs = ostp.forward(_om(wl, rho * 0.95), wl.src_nodes, wl.wavelets, wl.rec_nodes, 24)
+    g = GpuModel(wl, rho, coarse_solver=1)
+    sb.sbfwi_set_launch(g.f, sb.LAUNCH_SUBTREE_CUT, cut)
+    fwd, bwd = sb.sbfwi_direct_launches(g.mesh, 0), sb.sbfwi_direct_launches(g.mesh, 1)
+    subtrees = sum(L["subtrees"] for L in fwd) + sum(L["subtrees"] for L in bwd)
+    log(f"subtree cut {cut}: {len(fwd)} forward / {len(bwd)} backward launches, "
+        f"first forward {fwd[0]}, subtree launches {subtrees}")
+    info = sb.sbfwi_direct_info(g.mesh)
+    if cut == 1:
+        assert len(fwd) == 1 and len(bwd) == 1 and fwd[0]["subtrees"] == 1 and fwd[0]["blocks"] == 1
+    elif cut > info["max_per_level"]:
+        assert subtrees == 0 and len(fwd) == info["depth"] + 1
+    else:
+        assert fwd[0]["subtrees"] == 1 and bwd[-1]["subtrees"] == 1 and fwd[0]["blocks"] >= cut
+    tr, mis, grad, _ = g.gradient(obs, n_steps=24, n_ckpt=5)
+    sb.sbfwi_set_launch(g.f, sb.LAUNCH_SUBTREE_CUT, 512)
+    gref, Jref = oadj.exact_gradient(om, wl.src_nodes, wl.wavelets, wl.rec_nodes, obs, 24)
+    tref = ostp.forward(om, wl.src_nodes, wl.wavelets, wl.rec_nodes, 24)
+    et, eg = rel_l2(tr, tref), rel_l2(grad, gref)
+    log(f"  traces {et:.2e}, gradient {eg:.2e}")
+    assert et <= 1e-10 and eg <= 1e-8
+    assert mis == pytest.approx(Jref, rel=1e-10, abs=0)
