@@ -49,28 +49,29 @@ def kernel_bytes(mesh, NS, nnz):
     blk = n * nb * nb + nb * nb                   # stored pivot inverses + one per-element dense block
     band = lambda levels: 3 * nb * levels         # cyclic tridiagonal blocks
     out = {
-        # reads phi~^-1 (n blocks), G, bands P (n+1), theta (n+1); state u,v,a (n levels) and the
-        # nodal state on the loop; writes q (n levels), y_n and f_hat on the loop
-        "condense": blk + band(n + 1) + band(n + 2) + NS * (3 * n * nb + 3 * nb + n * nb + 2 * nb),
-        # reads phi~^-1, psi~_0, bands psi (n-1); q, u, v, a, u_n; writes u, v, a
-        "recover": blk + band(n - 1) + NS * (n * nb + 3 * n * nb + nb + 3 * n * nb),
+        # reads phi~^-1 (n blocks), G, bands P (n+1), theta (n+1); the interior w (n levels) and
+        # the nodal w on the loop; writes q (n levels), y_n and f_hat on the loop
+        "condense": blk + band(n + 1) + band(n + 2) + NS * (n * nb + nb + n * nb + 2 * nb),
+        # reads phi~^-1, psi~_0, bands psi (n-1); q, r, w, u_n; writes r, w
+        "recover": blk + band(n - 1) + NS * (3 * n * nb + nb + 2 * n * nb),
         # the checkpoint recompute's variant also stores the unknowns with ghosts (n+3 levels)
         # and the accelerations (n+1 levels) for the adjoint
-        "recover_store": blk + band(n - 1) + NS * (n * nb + 3 * n * nb + nb + 3 * n * nb)
+        "recover_store": blk + band(n - 1) + NS * (3 * n * nb + nb + 2 * n * nb)
                          + NS * ((n + 3) + (n + 1)) * nb,
-        # reads phi~^-1, psi~_0, bands psi; seeds (3 n); writes z (n) and the coupling (1)
-        "adj_condense": blk + band(n - 1) + NS * (3 * n * nb + n * nb + nb),
-        # reads G, phi~^-1, theta (n+2), P (n+1), theta_-1^-1; lambda_B, z, seeds (2 n);
-        # writes seeds (3 n), P_n^T lambda_n, adjoint rows (n+3)
+        # reads phi~^-1, psi~_0, bands psi; seeds u~ (n); writes z (n) and the coupling (1)
+        "adj_condense": blk + band(n - 1) + NS * (n * nb + n * nb + nb),
+        # reads G, phi~^-1, theta (n+2), P (n+1), theta_-1^-1; lambda_B, z, seeds v-bar, a-bar (2 n);
+        # writes seeds u~, v-bar, a-bar (3 n), P_n^T lambda_n, adjoint rows (n+3)
         "adj_recover": blk + 2 * nb * nb + band(n + 2) + band(n + 1) +
                        NS * (nb + n * nb + 2 * n * nb + 3 * n * nb + nb + (n + 3) * nb),
         # reads unknowns and adjoint rows (n+3 levels each), accelerations (n+1), alpha; grad RMW
         "grad_exact": 32 * nb + 2 * (n + 1) * nb + NS * (2 * (n + 3) * nb + (n + 1) * nb),
     }
-    # joint sweeps: the condense of the next step takes its state from the recover sweep in LDS
-    out["joint"] = out["recover"] + out["condense"] - NS * 3 * n * nb
-    out["joint_store"] = out["recover_store"] + out["condense"] - NS * 3 * n * nb
-    out["adj_joint"] = out["adj_recover"] + out["adj_condense"] - NS * 3 * n * nb
+    # joint sweeps: the condense of the next step takes its w (u~) from the recover sweep in
+    # LDS; the joint transposed sweep does not write u~ either
+    out["joint"] = out["recover"] + out["condense"] - NS * n * nb
+    out["joint_store"] = out["recover_store"] + out["condense"] - NS * n * nb
+    out["adj_joint"] = out["adj_recover"] + out["adj_condense"] - 2 * NS * n * nb
     res = {k: int(8 * v.sum()) for k, v in out.items()}
     nn = int(mesh.n_nodes)
     res["solve_v"] = 12 * nnz + 8 * nn + 8 * NS * nn * 7      # K, D^-1; phat, r, rhat, w in; v, s, shat out

@@ -12,6 +12,10 @@
 //   a-bar = c3 v-bar + a2 w-bar,
 // and the gradient gains -lambda^T (dA_stiff/drho) X^k + xi^2 lambda^T (dM0/drho) a^k
 // (the a0 M0 part of A and P combine into the acceleration a^k = a0 u^k - w^{k-1}).
+// u-bar enters the next step only through u~, so the interior levels keep u~
+// in its place: the transposed condense reads one seed instead of three, and
+// the joint transposed sweep, which hands u~ over in LDS, writes only v-bar and
+// a-bar.
 //
 // A^-T reuses the forward factors transposed.  With the paper's block
 // elimination A = L U (pivots theta_{-1}, phi~_0 .. phi~_{n-1}, psi_n, S), the
@@ -38,7 +42,7 @@ constexpr int WT = 64;
 
 struct AdjArgs {
   int NS;
-  double *ub, *vb, *ab;     // interior seeds
+  double *ut, *vb, *ab;     // interior seeds, u-bar kept as u~ = u-bar + c1 v-bar + a0 a-bar
   double *UB, *VB, *AB;     // nodal seeds
   double *z, *gB, *pl, *lamB, *lam;
 };
@@ -129,20 +133,14 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
     ok[u] = own[u] && si[u] < ns;
   }
   double reg[(NBT * NBT + WT - 1) / WT];
-  double cu[IPT], cv[IPT], ca[IPT], cb[3][IPT];
-  // seeds of level j and the entries of psi~_{j-1}^T's row i (psi_0's for j = 0: unused)
-  auto load_level = [&](int j, double (&uu)[IPT], double (&vv)[IPT], double (&aa)[IPT], double (&bd)[3][IPT]) {
+  double cu[IPT], cb[3][IPT];
+  // u~ of level j and the entries of psi~_{j-1}^T's row i (psi_0's for j = 0: unused)
+  auto load_level = [&](int j, double (&uu)[IPT], double (&bd)[3][IPT]) {
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int i = ii[u];
       const int64_t g = ok[u] ? (io + (int64_t)j * nb + i) * a.NS + s0 + si[u] : 0;
-      if (JOINT) {   // u~ from ukeep: no seed loads
-        uu[u] = vv[u] = aa[u] = 0.0;
-      } else {
-        uu[u] = a.ub[g];
-        vv[u] = a.vb[g];
-        aa[u] = a.ab[g];
-      }
+      uu[u] = JOINT ? 0.0 : a.ut[g];   // with JOINT u~ comes from ukeep: no seed loads
       const double* bp = f.ps_band + 3 * (po + (int64_t)(j > 0 ? j - 1 : 0) * nb);
       bd[0][u] = bp[2 * nb + md(i - 1, nb)];
       bd[1][u] = bp[nb + i];
@@ -151,20 +149,20 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
   };
   prefetch<NBT>(reg, Fe, nbnb);
   commit<NBT>(reg, L.F[0], nb);
-  load_level(0, cu, cv, ca, cb);
+  load_level(0, cu, cb);
   int cur = 0;
   __syncthreads();
   __builtin_amdgcn_s_waitcnt(0);   // nothing in flight at the loop entry
   for (int j = 0; j < n; ++j) {
     const int jn = j + 1 < n ? j + 1 : n - 1;   // the last level reloads its own data (unused)
     prefetch<NBT>(reg, Fe + (int64_t)jn * nbnb, nbnb);
-    double nu[IPT], nv[IPT], na[IPT], nbd[3][IPT];
-    load_level(jn, nu, nv, na, nbd);
+    double nu[IPT], nbd[3][IPT];
+    load_level(jn, nu, nbd);
     // y = u~_j - psi~_{j-1}^T z_{j-1}
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
-      double y = JOINT ? ukeep[j * items + it] : (ok[u] ? adj_utilde(f, cu[u], cv[u], ca[u]) : 0.0);
+      double y = JOINT ? ukeep[j * items + it] : (ok[u] ? cu[u] : 0.0);
       if (j == 1) {
         const double* P0 = f.psit0 + m.dense_off[e];
         double acc = 0.0;
@@ -192,8 +190,6 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       cu[u] = nu[u];
-      cv[u] = nv[u];
-      ca[u] = na[u];
 #pragma unroll
       for (int k = 0; k < 3; ++k) cb[k][u] = nbd[k][u];
     }
@@ -209,9 +205,10 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
 // Level loop of the L^T sweep (j = n-1 .. 0) with the adjoint Newmark chain;
 // the next level's F block, z, seeds and the theta / P band entries are loaded
 // at the top of each level and consumed at its end.
-// ukeep (LDS, may be NULL): receives u~ of the new seeds of every level,
-// ukeep[j * items + it], for the transposed condense of the earlier step.
-template <int NBT, int S, bool LAM>
+// KEEP: ukeep (LDS) receives u~ of the new seeds of every level, ukeep[j *
+// items + it], for the transposed condense of the earlier step, in place of
+// the u~ seeds in HBM.
+template <int NBT, int S, bool LAM, bool KEEP>
 __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                                    const AdjArgs& a, AdjLds<NBT, S>& L,
                                                    double (&reg)[(NBT * NBT + WT - 1) / WT], double* ukeep) {
@@ -288,10 +285,14 @@ __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev&
                          cp[2][u] * L.y[md(i + 1, nb) * S + s]) - ca[u];
       double* sink = g_adj_sink + threadIdx.x;
       const double nub = -f.c1 * vb + f.a0 * wb, nvb = f.c2 * vb + f.a1 * wb, nab = f.c3 * vb + f.a2 * wb;
-      *(ok[u] ? a.ub + g : sink) = nub;
+      const double ut = adj_utilde(f, nub, nvb, nab);
+      if (KEEP) {   // u~ to the transposed condense in the same block
+        if (own[u]) ukeep[j * items + it] = ok[u] ? ut : 0.0;
+      } else {
+        *(ok[u] ? a.ut + g : sink) = ut;
+      }
       *(ok[u] ? a.vb + g : sink) = nvb;
       *(ok[u] ? a.ab + g : sink) = nab;
-      if (ukeep && own[u]) ukeep[j * items + it] = ok[u] ? adj_utilde(f, nub, nvb, nab) : 0.0;
       if (LAM) *(ok[u] ? a.lam + (xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s : sink) = own[u] ? L.y[it] : 0.0;
     }
     __syncthreads();
@@ -313,7 +314,8 @@ __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev&
 }
 
 // L^T sweep, adjoint Newmark chain at the interior levels, and P_n^T lambda_n.
-template <int NBT, int S>
+// KEEP: u~ of the new seeds goes to ukeep (LDS) instead of the seeds in HBM.
+template <int NBT, int S, bool KEEP = false>
 __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                                  const AdjArgs& a, AdjLds<NBT, S>& L, double* ukeep = nullptr) {
   const int ns = min(S, a.NS - s0);
@@ -350,8 +352,8 @@ __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m
     }
   }
   __syncthreads();
-  if (a.lam) adj_recover_levels<NBT, S, true>(e, s0, m, f, a, L, reg, ukeep);
-  else adj_recover_levels<NBT, S, false>(e, s0, m, f, a, L, reg, ukeep);
+  if (a.lam) adj_recover_levels<NBT, S, true, KEEP>(e, s0, m, f, a, L, reg, ukeep);
+  else adj_recover_levels<NBT, S, false, KEEP>(e, s0, m, f, a, L, reg, ukeep);
   if (!a.lam) return;
   // lambda_{-1} = -theta_{-1}^-T theta_0^T lambda_0
   const double* th0 = f.th_band + 3 * po;
@@ -386,7 +388,8 @@ __global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restri
 // recover of adjoint step k (down the levels), which keeps u~ of every level's
 // new seeds in LDS, then the transposed condense of step k - 1 (up the levels)
 // from them; the same expressions as the separate sweeps, so the same bits,
-// with the seeds read once per step instead of twice and one launch fewer.
+// with u~ handed over in LDS instead of written and read back, and one launch
+// fewer.
 template <int NBT, int S>
 __global__ void __launch_bounds__(WT) adj_joint_kernel(const int32_t* __restrict__ elems, MeshDev m,
                                                        FactorsDev f, AdjArgs a) {
@@ -394,7 +397,7 @@ __global__ void __launch_bounds__(WT) adj_joint_kernel(const int32_t* __restrict
   extern __shared__ double ukeep[];   // [interior levels][n_b * S] of the element
   const int e = elems[blockIdx.x];
   const int s0 = blockIdx.y * S;
-  adj_recover_body<NBT, S>(e, s0, m, f, a, L, ukeep);
+  adj_recover_body<NBT, S, true>(e, s0, m, f, a, L, ukeep);
   __syncthreads();
   adj_condense_body<NBT, S, true>(e, s0, m, f, a, L, ukeep);
 }
@@ -746,20 +749,13 @@ __global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__
 // Paper kernel: g -= w * sum_s v~ v at every fine-grid point.  The back-propagated
 // run is driven by adj_src = dt (u - d), dt times the paper's residual source, so
 // the rectangle rule's dt of the kernel's time integral is already in v~ (w = 1).
-__global__ void grad_paper_kernel(MeshDev m, int NS, double w, int64_t n_params, const int32_t* __restrict__ par_elem,
-                                  const double* __restrict__ vint, const double* __restrict__ Vnod,
+__global__ void grad_paper_kernel(int NS, double w, int64_t n_params, const double* __restrict__ vb,
                                   const double* __restrict__ vf, double* __restrict__ grad, int per_shot) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_params) return;
-  const int e = par_elem[p];
-  const int nb = m.nb[e], n = m.nr[e] - 1;
-  const int64_t po = m.par_off[e];
-  const int loc = (int)(p - po);
-  const int lev = loc / nb, k = loc % nb;
   double g = 0.0;
   for (int s = 0; s < NS; ++s) {
-    double vl = lev < n ? vint[(m.int_off[e] + (int64_t)lev * nb + k) * NS + s]
-                        : Vnod[m.loop_nodes[m.loop_off[e] + k] * NS + s];
+    const double vl = vb[p * NS + s];
     if (per_shot)
       grad[s * n_params + p] -= w * (vl * vf[p * NS + s]);
     else
@@ -951,6 +947,7 @@ void launch_grad(sbfwi_mesh_s* m, const FactorsDev& f, int NS, const double* X, 
 struct AdjWork {
   double *seeds = nullptr, *z = nullptr, *gB = nullptr, *pl = nullptr, *rhs = nullptr, *lamB = nullptr,
          *lam = nullptr;
+  double* bvf = nullptr;   // paper kernel: velocity of the back-propagated field at every level
   int32_t* par_elem = nullptr;
   CoarseWork cw;
 };
@@ -963,6 +960,7 @@ void adj_free(AdjWork* w) {
   sbfwi_dev_free(w->rhs);
   sbfwi_dev_free(w->lamB);
   sbfwi_dev_free(w->lam);
+  sbfwi_dev_free(w->bvf);
   sbfwi_dev_free(w->par_elem);
   sbfwi_coarse_work_free(&w->cw);
 }
@@ -1022,7 +1020,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     int64_t ni = m->n_int * NS;
     SBFWI_CHECK(sbfwi_alloc(&w.seeds, 3 * ni + 3 * nn));
     SBFWI_HIP(hipMemsetAsync(w.seeds, 0, sizeof(double) * (3 * ni + 3 * nn), st));
-    a.ub = w.seeds; a.vb = a.ub + ni; a.ab = a.vb + ni;
+    a.ut = w.seeds; a.vb = a.ut + ni; a.ab = a.vb + ni;
     a.UB = a.ab + ni; a.VB = a.UB + nn; a.AB = a.VB + nn;
     SBFWI_CHECK(sbfwi_alloc(&w.z, ni));
     SBFWI_CHECK(sbfwi_alloc(&w.gB, m->n_loop * NS));
@@ -1036,6 +1034,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   } else {
     SBFWI_CHECK(sbfwi_step_work_alloc(&bw, m, NS));
     SBFWI_CHECK(sbfwi_step_zero(m, &bw, st));
+    SBFWI_CHECK(sbfwi_alloc(&w.bvf, m->n_params * NS));
   }
   SourceTable bsrc;  // paper kernel: receivers as sources, time-reversed
   bsrc.n_src = ck->n_rec;
@@ -1148,11 +1147,12 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         SBFWI_HIP(hipGetLastError());
       } else {
         const int64_t kp = N + 1 - k;  // back-propagation step paired with forward step k
-        SBFWI_CHECK(sbfwi_forward_step(f, &bw, kp, bsrc, 0, nullptr, nullptr, N, nullptr, nullptr, 0, st, nullptr,
+        // its velocity at every level into w.bvf (a level field)
+        SBFWI_CHECK(sbfwi_forward_step(f, &bw, kp, bsrc, 0, nullptr, nullptr, N, nullptr, w.bvf, 1, st, nullptr,
                                        nullptr, kp < N));
         ProfScope ps(PK_GRAD_PAPER, st);
-        hipLaunchKernelGGL(grad_paper_kernel, dim3(gp), dim3(256), 0, st, m->d, NS, 1.0, m->n_params,
-                           w.par_elem, (const double*)bw.v, (const double*)bw.V, Fs, grad, per_shot);
+        hipLaunchKernelGGL(grad_paper_kernel, dim3(gp), dim3(256), 0, st, NS, 1.0, m->n_params,
+                           (const double*)w.bvf, Fs, grad, per_shot);
         SBFWI_HIP(hipGetLastError());
       }
     }
@@ -1218,7 +1218,7 @@ int sbfwi_adjoint_impl(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   if (sg) (void)hipStreamDestroy(sg);
   adj_free(&w);
   if (!ck->full_store) sbfwi_step_work_free(&fw);
-  if (bw.u) sbfwi_step_work_free(&bw);
+  if (bw.r) sbfwi_step_work_free(&bw);
   for (int b = 0; b < 2; ++b) {
     sbfwi_dev_free(xseg[b]);
     sbfwi_dev_free(fseg[b]);
@@ -1304,7 +1304,7 @@ int sbfwi_tune_adj_sweeps(sbfwi_factors_s* f, int NS, hipStream_t st, double* ou
   if (rc == SBFWI_OK) rc = sbfwi_alloc(&w.lamB, nn);
   if (rc == SBFWI_OK) rc = sbfwi_alloc(&w.lam, m->n_x * NS);
   if (rc == SBFWI_OK) {
-    a.ub = w.seeds; a.vb = a.ub + ni; a.ab = a.vb + ni;
+    a.ut = w.seeds; a.vb = a.ut + ni; a.ab = a.vb + ni;
     a.UB = a.ab + ni; a.VB = a.UB + nn; a.AB = a.VB + nn;
     a.z = w.z; a.gB = w.gB; a.pl = w.pl; a.lamB = w.lamB; a.lam = w.lam;
     // zero inputs: the timings do not depend on the values

@@ -2,7 +2,7 @@
 //
 // Storage conventions (all FP64, shots innermost so that one radial level of
 // one element for all shots of a launch is a contiguous, coalesced run):
-//   interior state u, v, a and the swept sources q: ((int_off[e] + j*nb + i)*NS + s),
+//   interior state r, w and the swept sources q: ((int_off[e] + j*nb + i)*NS + s),
 //       level j = 0 .. N_r-2 (the boundary level N_r-1 is the shared nodal state);
 //   nodal state and coarse vectors: (node*NS + s);
 //   per-slot element vectors (effective sources, boundary sweeps): ((loop_off[e] + i)*NS + s);
@@ -329,8 +329,9 @@ int sbfwi_coarse_solve_parts(sbfwi_factors_s* f, CoarseWork* w, int transpose, c
 
 struct StepWork {
   int NS = 0;
-  double *u = nullptr, *v = nullptr, *a = nullptr;      // interior state
+  double *r = nullptr, *w = nullptr;                    // interior state: r = c1 u - c2 v - c3 a, w = a0 u + a1 v + a2 a
   double *U = nullptr, *V = nullptr, *A = nullptr;      // nodal state
+  double* W = nullptr;                                  // nodal w = a0 U + a1 V + a2 A
   double* corr = nullptr;                               // predictor correction of the coarse solve
   double *q = nullptr, *yn = nullptr, *fhat = nullptr, *F = nullptr, *Unew = nullptr;
   double* ustore = nullptr;   // optional: every step's coarse solution, [n_steps][n_nodes*NS]

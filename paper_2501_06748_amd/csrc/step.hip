@@ -16,6 +16,16 @@
 //   u_j = q_j - phi~_j^-1 (psi~_j u_{j+1})   (j = n-1 .. 0),
 // the paper's u_j = phi~_j^-1 (p~_j - psi~_j u_{j+1}); then the Newmark update of
 // velocity and acceleration at every level (eq. Newmark).
+//
+// Interior state.  A step uses the old interior u, v, a only through two linear
+// combinations: w = a0 u + a1 v + a2 a (the condense's source, and a^{k+1} =
+// a0 u^{k+1} - w) and r = c1 u - c2 v - c3 a (v^{k+1} = c1 u^{k+1} - r).  The
+// new pair follows from u^{k+1}, v^{k+1}, a^{k+1} by the same two combinations,
+// so every interior level keeps (r, w) only: two words per node and shot
+// instead of three, read and written once per step (the condense reads w
+// alone).  u, v and a of a level are formed where a store needs them.  The
+// boundary level keeps the nodal u, v, a, and the nodal update also writes the
+// boundary level's w for the next condense.
 #include <atomic>
 #include <functional>
 
@@ -31,8 +41,9 @@ __device__ __forceinline__ int md(int i, int nb) { return i < 0 ? i + nb : (i >=
 
 struct StepArgs {
   int NS;                 // shots in the run (stride of the shot index)
-  double *u, *v, *a;      // interior state
+  double *r, *w;          // interior state (r, w) of every level
   double *U, *V, *A;      // nodal state
+  double* W;              // nodal w = a0 U + a1 V + a2 A
   double *q, *yn, *fhat, *Unew;
   double *xs, *fs;        // optional stores (unknowns with ghosts, level field)
   int field_kind;         // fs: 0 = a^k, 1 = v^k
@@ -101,6 +112,11 @@ __device__ __forceinline__ double newmark_w(const FactorsDev& f, double u, doubl
   return fma(f.a2, a, fma(f.a1, v, f.a0 * u));
 }
 
+// r = c1 u - c2 v - c3 a, so that v^{k+1} = c1 u^{k+1} - r^k (eq. Newmark).
+__device__ __forceinline__ double newmark_r(const FactorsDev& f, double u, double v, double a) {
+  return fma(-f.c3, a, fma(-f.c2, v, f.c1 * u));
+}
+
 // JOINT: the interior levels' w comes from wkeep (LDS, level-major, written by
 // the recover sweep of the previous step in the same block) instead of the
 // state in HBM; the boundary level always takes the nodal state.
@@ -134,24 +150,18 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
   // n_b <= 21: a level's three band rows of P (and of theta) fit the 64 lanes,
   // one load each, and every item takes its entries by cross-lane shuffles
   constexpr bool kBandShfl = 3 * NBT <= WT;
-  double cu[IPT], cv[IPT], ca[IPT], cp[3][IPT], ct[3][IPT];
-  auto load_level = [&](int j, double (&uu)[IPT], double (&vv)[IPT], double (&aa)[IPT], double (&pb)[3][IPT],
-                        double (&tb)[3][IPT]) {
+  double cw[IPT], cp[3][IPT], ct[3][IPT];
+  auto load_level = [&](int j, double (&ww)[IPT], double (&pb)[3][IPT], double (&tb)[3][IPT]) {
     const bool nodal = j == n;
-    const double* su = nodal ? a.U : a.u;
-    const double* sv = nodal ? a.V : a.v;
-    const double* sa = nodal ? a.A : a.a;
+    const double* sw = nodal ? a.W : a.w;
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int64_t row = nodal ? lnode[u] : io + (int64_t)j * nb + ii[u];
       const int64_t g = ok[u] ? row * a.NS + s0 + si[u] : 0;
-      if (JOINT && !nodal) {   // interior w from wkeep: no state loads
-        uu[u] = vv[u] = aa[u] = 0.0;
-      } else {
-        uu[u] = su[g];
-        vv[u] = sv[g];
-        aa[u] = sa[g];
-      }
+      if (JOINT && !nodal)   // interior w from wkeep: no state loads
+        ww[u] = 0.0;
+      else
+        ww[u] = sw[g];
       if constexpr (!kBandShfl) {
         const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb) + ii[u];   // node 0 for lanes without an item
         const double* tp = f.th_band + 3 * (po + (int64_t)j * nb) + ii[u];
@@ -175,7 +185,7 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
     for (int u = 0; u < IPT; ++u) {
       const int it = threadIdx.x + u * WT;
       if (own[u])
-        L.w[it] = JOINT && j < n ? wkeep[j * items + it] : (ok[u] ? newmark_w(f, cu[u], cv[u], ca[u]) : 0.0);
+        L.w[it] = JOINT && j < n ? wkeep[j * items + it] : (ok[u] ? cw[u] : 0.0);
     }
     __syncthreads();
 #pragma unroll
@@ -202,15 +212,15 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
   };
   prefetch<NBT>(reg, Fe, nbnb);
   commit<NBT>(reg, L.F[0], nb);
-  load_level(0, cu, cv, ca, cp, ct);
+  load_level(0, cw, cp, ct);
   int cur = 0;
   __syncthreads();
   __builtin_amdgcn_s_waitcnt(0);   // nothing in flight at the loop entry
   for (int j = 0; j < n; ++j) {
     const int jf = j + 1 < n ? j + 1 : n - 1;   // the last interior level reloads its own block (unused)
     prefetch<NBT>(reg, Fe + (int64_t)jf * nbnb, nbnb);
-    double nu[IPT], nv[IPT], na[IPT], np[3][IPT], nt[3][IPT];
-    load_level(j + 1, nu, nv, na, np, nt);
+    double nw[IPT], np[3][IPT], nt[3][IPT];
+    load_level(j + 1, nw, np, nt);
     level_rhs(j);
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
@@ -227,9 +237,7 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
     cur ^= 1;
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
-      cu[u] = nu[u];
-      cv[u] = nv[u];
-      ca[u] = na[u];
+      cw[u] = nw[u];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         cp[k][u] = np[k][u];
@@ -255,7 +263,7 @@ __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, c
 }
 
 // Level loop of the recovery sweep (j = n-1 .. 0).  The next level's F block,
-// state (q, u, v, a) and psi~ band are loaded at the top of each level and
+// state (q, r, w) and psi~ band are loaded at the top of each level and
 // consumed at its end, so the sweep streams without waiting on the level
 // recursion; the loads of lanes without an item read word 0 and the stores
 // of such lanes go to g_sink.
@@ -281,23 +289,21 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
     ok[u] = own[u] && si[u] < ns;
   }
   double reg[(NBT * NBT + WT - 1) / WT];
-  double cq[IPT], cu[IPT], cv[IPT], ca[IPT], cb[3][IPT];
-  auto load_level = [&](int j, double (&q)[IPT], double (&uu)[IPT], double (&vv)[IPT], double (&aa)[IPT],
-                        double (&bd)[3][IPT]) {
+  double cq[IPT], cr[IPT], cw[IPT], cb[3][IPT];
+  auto load_level = [&](int j, double (&q)[IPT], double (&rr)[IPT], double (&ww)[IPT], double (&bd)[3][IPT]) {
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int64_t g = ok[u] ? (io + (int64_t)j * nb + ii[u]) * a.NS + s0 + si[u] : 0;
       q[u] = a.q[g];
-      uu[u] = a.u[g];
-      vv[u] = a.v[g];
-      aa[u] = a.a[g];
+      rr[u] = a.r[g];
+      ww[u] = a.w[g];
       const double* bp = f.ps_band + 3 * (po + (int64_t)j * nb) + ii[u];   // node 0 for lanes without an item
       bd[0][u] = bp[0];
       bd[1][u] = bp[nb];
       bd[2][u] = bp[2 * nb];
     }
   };
-  load_level(n - 1, cq, cu, cv, ca, cb);
+  load_level(n - 1, cq, cr, cw, cb);
   int cur = 0;
   __syncthreads();
   // nothing in flight at the loop entry: the compiler then counts the waits
@@ -306,8 +312,8 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
   for (int j = n - 1; j >= 0; --j) {
     const int jn = j > 0 ? j - 1 : 0;   // the last level reloads level 0 (unused)
     prefetch<NBT>(reg, Fe + (int64_t)jn * nbnb, nbnb);
-    double nq[IPT], nu[IPT], nv[IPT], na[IPT], nbd[3][IPT];
-    load_level(jn, nq, nu, nv, na, nbd);
+    double nq[IPT], nr[IPT], nw[IPT], nbd[3][IPT];
+    load_level(jn, nq, nr, nw, nbd);
     // t = psi~_j u_{j+1}
     if (j > 0) {
 #pragma unroll
@@ -332,18 +338,16 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
       const int it = threadIdx.x + u * WT, i = ii[u], s = si[u];
       const int64_t g = (io + (int64_t)j * nb + i) * a.NS + s0 + s;
       const double uj = ok[u] ? cq[u] - dense_mv<NBT>(L.F[cur], L.t, nb, i, s, S) : 0.0;
-      const double uo = cu[u], vo = cv[u], ao = ca[u];
-      const double w = newmark_w(f, uo, vo, ao);
-      const double vn = f.c1 * (uj - uo) + f.c2 * vo + f.c3 * ao;
-      const double an = f.a0 * uj - w;
-      if (wkeep && own[u]) wkeep[j * items + it] = ok[u] ? newmark_w(f, uj, vn, an) : 0.0;
+      const double vn = f.c1 * uj - cr[u];
+      const double an = f.a0 * uj - cw[u];
+      const double wn = newmark_w(f, uj, vn, an);
+      if (wkeep && own[u]) wkeep[j * items + it] = ok[u] ? wn : 0.0;
       double* sink = g_sink + threadIdx.x;
-      *(ok[u] ? a.u + g : sink) = uj;
-      *(ok[u] ? a.v + g : sink) = vn;
-      *(ok[u] ? a.a + g : sink) = an;
+      *(ok[u] ? a.r + g : sink) = newmark_r(f, uj, vn, an);
+      *(ok[u] ? a.w + g : sink) = wn;
       if (STORE) {
         const int64_t gp = (po + (int64_t)j * nb + i) * a.NS + s0 + s;
-        *(ok[u] ? a.xs + (xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s : sink) = uj;
+        *(ok[u] && a.xs ? a.xs + (xo + (int64_t)(j + 1) * nb + i) * a.NS + s0 + s : sink) = uj;
         *(ok[u] ? a.fs + gp : sink) = a.field_kind == 0 ? an : vn;
         *(ok[u] && a.vs ? a.vs + gp : sink) = vn;
       }
@@ -360,9 +364,8 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       cq[u] = nq[u];
-      cu[u] = nu[u];
-      cv[u] = nv[u];
-      ca[u] = na[u];
+      cr[u] = nr[u];
+      cw[u] = nw[u];
       cb[0][u] = nbd[0][u];
       cb[1][u] = nbd[1][u];
       cb[2][u] = nbd[2][u];
@@ -371,7 +374,8 @@ __device__ __forceinline__ void recover_levels(int e, int s0, const MeshDev& m, 
 }
 
 // STORE: the checkpoint recompute's launches, which also store the unknowns
-// with ghosts and the level field for the adjoint (a.xs, a.fs, a.vs).
+// with ghosts and the level field for the adjoint (a.xs, a.fs, a.vs; a.xs may
+// be NULL when only the level field is wanted).
 template <int NBT, int S, bool STORE>
 __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                              const StepArgs& a, StepLds<NBT, S>& L,
@@ -391,7 +395,7 @@ __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, co
     L.x[it] = un;
     L.w[it] = un;  // keep u_n for the ghost
     if (STORE && s < ns) {
-      a.xs[(xo + (int64_t)(n + 1) * nb + i) * a.NS + s0 + s] = un;
+      if (a.xs) a.xs[(xo + (int64_t)(n + 1) * nb + i) * a.NS + s0 + s] = un;
       double fv = a.field_kind == 0 ? a.A[m.loop_nodes[lo + i] * a.NS + s0 + s]
                                     : a.V[m.loop_nodes[lo + i] * a.NS + s0 + s];
       a.fs[(po + (int64_t)n * nb + i) * a.NS + s0 + s] = fv;
@@ -400,7 +404,7 @@ __device__ __forceinline__ void recover_body(int e, int s0, const MeshDev& m, co
   }
   __syncthreads();
   recover_levels<NBT, S, STORE>(e, s0, m, f, a, L, wkeep);
-  if (!STORE) return;
+  if (!STORE || !a.xs) return;
   // ghosts: u_{-1} = theta_{-1}^-1 (-(phi_{-1} u_0 + psi_{-1} u_1)),
   //         u_{n+1} = psi_n^-1 (y_n - phi~_n u_n)
   const int64_t dofs = m.dense_off[e];
@@ -459,8 +463,9 @@ __global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__
 // (down the levels), which keeps every level's new w in LDS, then the condense
 // sweep of step k + 1 (up the levels) from that w and the nodal state already
 // updated by step k.  Every value is computed by the same expressions as in the
-// two separate sweeps, so the results are bit-identical; the state u, v, a is
-// read and written once per step instead of read twice, and one launch is saved.
+// two separate sweeps, so the results are bit-identical; the interior state is
+// read and written once per step (the condense takes its w from LDS), and one
+// launch is saved.
 template <int NBT, int S, bool STORE>
 __global__ void __launch_bounds__(WT) joint_kernel(const int32_t* __restrict__ elems, MeshDev m, FactorsDev f,
                                                    StepArgs a) {
@@ -524,14 +529,15 @@ __global__ void rhs_kernel(MeshDev m, int NS, const double* __restrict__ fhat, d
   Unew[g] = U[g] + dt * V[g] + 0.5 * dt * dt * A[g] + corr[g];
 }
 
-// Nodal Newmark update, predictor correction and receiver sampling.  With env
+// Nodal Newmark update (W: the nodal w of the old state in, of the new one
+// out), predictor correction and receiver sampling.  With env
 // (growth envelope of the run, [n_steps][NS]) every new nodal displacement is
 // checked against the bound of its step and shot: a non-finite value sets status
 // bit 32, a finite one beyond the bound bit 16, and the first such step is kept
 // in status[1].
 __global__ void nodal_kernel(int64_t n_nodes, int NS, FactorsDev f, const double* __restrict__ Unew,
                              double* __restrict__ U, double* __restrict__ V, double* __restrict__ A,
-                             double* __restrict__ corr,
+                             double* __restrict__ W, double* __restrict__ corr,
                              int n_rec, const int64_t* __restrict__ rec_node, double* __restrict__ traces,
                              int64_t n_steps, int64_t k, const int64_t* __restrict__ kdev,
                              double* __restrict__ ustore, const double* __restrict__ env,
@@ -546,11 +552,13 @@ __global__ void nodal_kernel(int64_t n_nodes, int NS, FactorsDev f, const double
       atomicCAS(&status[1], -1, (int)k);
     }
     if (ustore) ustore[(k - 1) * nn + g] = un;
-    double w = newmark_w(f, uo, vo, ao);
     corr[g] = un - (uo + f.dt * vo + 0.5 * f.dt * f.dt * ao);
-    V[g] = f.c1 * (un - uo) + f.c2 * vo + f.c3 * ao;
-    A[g] = f.a0 * un - w;
+    const double vn = f.c1 * (un - uo) + f.c2 * vo + f.c3 * ao;
+    const double an = f.a0 * un - W[g];
+    V[g] = vn;
+    A[g] = an;
     U[g] = un;
+    W[g] = newmark_w(f, un, vn, an);
   } else if (traces && g < nn + (int64_t)n_rec * NS) {
     int64_t t = g - nn;
     int s = (int)(t / n_rec), r = (int)(t % n_rec);
@@ -566,7 +574,7 @@ void launch_cr(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, cons
   dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
   if (condense)
     hipLaunchKernelGGL((condense_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
-  else if (a.xs)
+  else if (a.xs || a.fs)
     hipLaunchKernelGGL((recover_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
   else
     hipLaunchKernelGGL((recover_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
@@ -588,7 +596,7 @@ template <int S>
 void launch_fused(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, const StepArgs& a, hipStream_t st) {
   const int groups = (a.NS + S - 1) / S;
   const int64_t n_work = m->n_elem * groups;
-  const int which = condense ? 0 : (a.xs ? 2 : 1);
+  const int which = condense ? 0 : (a.xs || a.fs ? 2 : 1);
   auto kern = which == 0 ? sweep_fused_kernel<S, true, false>
                          : which == 1 ? sweep_fused_kernel<S, false, false> : sweep_fused_kernel<S, false, true>;
   static std::atomic<int> per_cu[3] = {0, 0, 0};   // occupancy, queried once per kernel
@@ -625,7 +633,7 @@ void launch_step_sweep(bool condense, sbfwi_mesh_s* m, const FactorsDev& f, cons
 }
 
 void launch_sweep(bool condense, sbfwi_factors_s* fac, const StepArgs& a, hipStream_t st) {
-  ProfScope ps(condense ? PK_CONDENSE : (a.xs ? PK_RECOVER_STORE : PK_RECOVER), st);
+  ProfScope ps(condense ? PK_CONDENSE : (a.xs || a.fs ? PK_RECOVER_STORE : PK_RECOVER), st);
   launch_step_sweep(condense, fac->m, fac->d, fac->plan, a, st);
 }
 
@@ -641,7 +649,7 @@ bool launch_joint_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, const StepAr
   const size_t dyn = (size_t)m->class_nmax[cl] * NBT * S * sizeof(double);
   if (sizeof(StepLds<NBT, S>) + dyn > kJointLdsMax) return false;
   dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
-  if (a.xs)
+  if (a.xs || a.fs)
     hipLaunchKernelGGL((joint_kernel<NBT, S, true>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
   else
     hipLaunchKernelGGL((joint_kernel<NBT, S, false>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
@@ -670,7 +678,7 @@ void launch_joint(sbfwi_factors_s* fac, const StepArgs& a, hipStream_t st) {
     launch_sweep(true, fac, a, st);
     return;
   }
-  ProfScope ps(a.xs ? PK_JOINT_STORE : PK_JOINT, st);
+  ProfScope ps(a.xs || a.fs ? PK_JOINT_STORE : PK_JOINT, st);
   const int def = sbfwi_default_shots_per_block(a.NS);
   for (int cl = 0; cl < 3; ++cl) {
     const int S = plan.S[SW_RECOVER][cl] > 0 ? plan.S[SW_RECOVER][cl] : def;
@@ -694,19 +702,19 @@ void launch_joint(sbfwi_factors_s* fac, const StepArgs& a, hipStream_t st) {
 
 }  // namespace
 
-// interior u, v, a; nodal U, V, A and the predictor correction of the coarse solve
-int64_t sbfwi_state_size(sbfwi_mesh_s* m, int NS) { return (3 * m->n_int + 4 * m->n_nodes) * (int64_t)NS; }
+// interior r, w; nodal U, V, A, W and the predictor correction of the coarse solve
+int64_t sbfwi_state_size(sbfwi_mesh_s* m, int NS) { return (2 * m->n_int + 5 * m->n_nodes) * (int64_t)NS; }
 
 int sbfwi_step_work_alloc(StepWork* w, sbfwi_mesh_s* m, int NS) {
   w->NS = NS;
   int64_t ni = m->n_int * NS, nn = m->n_nodes * NS, nl = m->n_loop * NS;
-  SBFWI_CHECK(sbfwi_alloc(&w->u, 3 * ni + 4 * nn));  // u, v, a, U, V, A, corr contiguous
-  w->v = w->u + ni;
-  w->a = w->v + ni;
-  w->U = w->a + ni;
+  SBFWI_CHECK(sbfwi_alloc(&w->r, 2 * ni + 5 * nn));  // r, w, U, V, A, W, corr contiguous
+  w->w = w->r + ni;
+  w->U = w->w + ni;
   w->V = w->U + nn;
   w->A = w->V + nn;
-  w->corr = w->A + nn;
+  w->W = w->A + nn;
+  w->corr = w->W + nn;
   SBFWI_CHECK(sbfwi_alloc(&w->q, ni));
   SBFWI_CHECK(sbfwi_alloc(&w->yn, nl));
   SBFWI_CHECK(sbfwi_alloc(&w->fhat, nl));
@@ -718,7 +726,7 @@ int sbfwi_step_work_alloc(StepWork* w, sbfwi_mesh_s* m, int NS) {
 }
 
 void sbfwi_step_work_free(StepWork* w) {
-  sbfwi_dev_free(w->u);
+  sbfwi_dev_free(w->r);
   sbfwi_dev_free(w->q);
   sbfwi_dev_free(w->yn);
   sbfwi_dev_free(w->fhat);
@@ -733,7 +741,7 @@ void sbfwi_step_work_free(StepWork* w) {
 }
 
 int sbfwi_step_zero(sbfwi_mesh_s* m, StepWork* w, hipStream_t s) {
-  SBFWI_HIP(hipMemsetAsync(w->u, 0, sizeof(double) * sbfwi_state_size(m, w->NS), s));
+  SBFWI_HIP(hipMemsetAsync(w->r, 0, sizeof(double) * sbfwi_state_size(m, w->NS), s));
   w->condensed = false;
   return SBFWI_OK;
 }
@@ -741,9 +749,9 @@ int sbfwi_step_zero(sbfwi_mesh_s* m, StepWork* w, hipStream_t s) {
 int sbfwi_state_copy(sbfwi_mesh_s* m, StepWork* w, double* dst, int to_store, hipStream_t s) {
   size_t bytes = sizeof(double) * sbfwi_state_size(m, w->NS);
   if (to_store) {
-    SBFWI_HIP(hipMemcpyAsync(dst, w->u, bytes, hipMemcpyDeviceToDevice, s));
+    SBFWI_HIP(hipMemcpyAsync(dst, w->r, bytes, hipMemcpyDeviceToDevice, s));
   } else {
-    SBFWI_HIP(hipMemcpyAsync(w->u, dst, bytes, hipMemcpyDeviceToDevice, s));
+    SBFWI_HIP(hipMemcpyAsync(w->r, dst, bytes, hipMemcpyDeviceToDevice, s));
     w->condensed = false;   // a new state: its sources are not swept yet
   }
   return SBFWI_OK;
@@ -754,8 +762,8 @@ namespace {
 StepArgs step_args(StepWork* w, double* xs, double* fs, int field_kind, double* vs) {
   StepArgs a;
   a.NS = w->NS;
-  a.u = w->u; a.v = w->v; a.a = w->a;
-  a.U = w->U; a.V = w->V; a.A = w->A;
+  a.r = w->r; a.w = w->w;
+  a.U = w->U; a.V = w->V; a.A = w->A; a.W = w->W;
   a.q = w->q; a.yn = w->yn; a.fhat = w->fhat; a.Unew = w->Unew;
   a.xs = xs; a.fs = fs; a.field_kind = field_kind; a.vs = vs;
   return a;
@@ -784,7 +792,7 @@ int step_nodal(sbfwi_factors_s* f, StepWork* w, const StepArgs& a, int64_t k, co
   {
     ProfScope ps(PK_NODAL, st);
     hipLaunchKernelGGL(nodal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, m->n_nodes, w->NS,
-                       f->d, a.Unew, w->U, w->V, w->A, w->corr, n_rec, rec_node, traces, n_steps, k, kdev,
+                       f->d, a.Unew, w->U, w->V, w->A, w->W, w->corr, n_rec, rec_node, traces, n_steps, k, kdev,
                        w->ustore, w->env, f->d.status);
   }
   SBFWI_HIP(hipGetLastError());
@@ -915,8 +923,8 @@ int tune_step(sbfwi_factors_s* f, StepWork& w, int NS, hipStream_t st, hipEvent_
   sbfwi_mesh_s* m = f->m;
   StepArgs a;
   a.NS = NS;
-  a.u = w.u; a.v = w.v; a.a = w.a;
-  a.U = w.U; a.V = w.V; a.A = w.A;
+  a.r = w.r; a.w = w.w;
+  a.U = w.U; a.V = w.V; a.A = w.A; a.W = w.W;
   a.q = w.q; a.yn = w.yn; a.fhat = w.fhat; a.Unew = w.Unew;
   a.xs = nullptr; a.fs = nullptr; a.field_kind = 0; a.vs = nullptr;
   const int cands[5] = {1, 2, 4, 8, 16};

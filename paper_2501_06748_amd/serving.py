@@ -231,6 +231,7 @@ class ShotServer:
         self._stop = False
         self._threads = []
         self._hosts = {}                      # model key -> (mesh arrays, rho) built on the host
+        self.log = None                       # optional callable(str): a line per batch started and finished
 
     # footprint of (model, shots, steps): factors and run bytes from the library's plan
     def _footprint(self, mk, n_shots, n_steps):
@@ -318,6 +319,9 @@ class ShotServer:
         start = self.now()
         reqs = batch.requests
         mk = reqs[0].model.key
+        if self.log:
+            self.log(f"[serving] batch of {len(reqs)} shot(s), {reqs[0].n_steps} steps, model {mk}: "
+                     f"started at {start:.1f} s")
         ent = self._cache_entry(mk)
         err = ""
         try:
@@ -342,6 +346,9 @@ class ShotServer:
         except Exception as e:          # reported per request; the server keeps running
             err = f"{type(e).__name__}: {e}"
         done = self.now()
+        if self.log:
+            self.log(f"[serving] batch of {len(reqs)} shot(s), model {mk}: finished at {done:.1f} s"
+                     + (f" ({err})" if err else ""))
         with self._lock:
             for i, r in enumerate(reqs):
                 if err:
@@ -382,6 +389,11 @@ class ShotServer:
 
 def run_stream(server, requests, time_scale=1.0):
     """Submits requests at their arrival times (scaled) and waits for all results."""
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    if len(requests) <= 64:      # a line per arrival and per batch while the stream runs
+        server.log = log
     server.start()
     t0 = server.now()
     for r in sorted(requests, key=lambda q: q.arrival):
@@ -389,12 +401,13 @@ def run_stream(server, requests, time_scale=1.0):
         if delay > 0:
             time.sleep(delay)
         server.submit(r)
+        if server.log:
+            log(f"[serving] request {r.rid} arrived at {server.now():.1f} s")
     res = {}
     step = 1 if len(requests) <= 64 else len(requests) // 8
     for k in range(step, len(requests) + step, step):     # progress lines while waiting
         res = server.wait(min(k, len(requests)))
-        print(f"[serving] {len(res)}/{len(requests)} requests done at {server.now():.1f} s", file=sys.stderr,
-              flush=True)
+        log(f"[serving] {len(res)}/{len(requests)} requests done at {server.now():.1f} s")
     server.stop()
     return res
 
