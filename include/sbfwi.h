@@ -181,6 +181,10 @@ int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
  *             per subtree, walking its levels) rooted at the shallowest level of the dissection
  *             tree with at least value supernodes (default 512; a value above every level's
  *             count gives one launch per level).  Waits for the device to be idle first.
+ *   param 7:  (central-difference scheme) 1 = the transposed sweeps of the n_b <= 16
+ *             classes form the rows theta_j, psi_j, P_j of every level from the element's
+ *             nodal densities instead of reading them from the factors (default); 0 = read
+ *             them.  Both give the same bits.
  *   param 10 + 3 k + c: shots per block (0 = default, 1, 2, 4, 8, 16) of sweep k (0 condense,
  *             1 recover, 2 transposed condense, 3 transposed recover) for n_b class c
  *             (n_b <= 8, <= 16, <= 24).

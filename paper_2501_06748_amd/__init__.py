@@ -209,6 +209,7 @@ def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
 
 LAUNCH_ENQUEUED_ITERS, LAUNCH_GRAPHS, LAUNCH_RESET_PLAN = 0, 1, 2
 LAUNCH_OVERLAP_BACKWARD, LAUNCH_KEEP_SOLUTIONS, LAUNCH_JOINT_SWEEPS, LAUNCH_SUBTREE_CUT = 3, 4, 5, 6
+LAUNCH_ROWS_ON_THE_FLY = 7
 
 
 def launch_param_shots(sweep: int, cls: int) -> int:

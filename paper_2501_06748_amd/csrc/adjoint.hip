@@ -32,6 +32,7 @@
 // sums over shots, so the accumulation is deterministic.
 #include <atomic>
 
+#include "fd_bands.h"
 #include "sbfwi_internal.h"
 
 namespace {
@@ -112,7 +113,9 @@ __device__ __forceinline__ double adj_utilde(const FactorsDev& f, double ub, dou
 // JOINT: u~ of every level comes from ukeep (LDS, level-major, written by the
 // transposed recover sweep of the later step in the same block) instead of the
 // seeds in HBM.
-template <int NBT, int S, bool JOINT = false>
+// FLY (central differences, n_b <= 21): psi_{j-1} formed from the density rows
+// (fd_bands.h) instead of loaded.
+template <int NBT, int S, bool JOINT = false, bool FLY = false>
 __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                                   const AdjArgs& a, AdjLds<NBT, S>& L,
                                                   const double* ukeep = nullptr) {
@@ -134,17 +137,33 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
   }
   double reg[(NBT * NBT + WT - 1) / WT];
   double cu[IPT], cb[3][IPT];
+  static_assert(!FLY || 3 * NBT <= WT, "rows on the fly need 3 n_b <= 64");
+  // FLY: the call for level j forms row j and hands over row j - 1 (prev)
+  FdSweepRows fr;
+  double prev = 0.0;
+  if constexpr (FLY) fr.init_up(f.bkap + lo * 3 * kFdKappa, f.rho + po, m.xi0, n, nb);
   // u~ of level j and the entries of psi~_{j-1}^T's row i (psi_0's for j = 0: unused)
   auto load_level = [&](int j, double (&uu)[IPT], double (&bd)[3][IPT]) {
+    double psv = 0.0;
+    if constexpr (FLY) {
+      psv = prev;
+      prev = fr.next_up().ps;
+    }
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int i = ii[u];
       const int64_t g = ok[u] ? (io + (int64_t)j * nb + i) * a.NS + s0 + si[u] : 0;
       uu[u] = JOINT ? 0.0 : a.ut[g];   // with JOINT u~ comes from ukeep: no seed loads
-      const double* bp = f.ps_band + 3 * (po + (int64_t)(j > 0 ? j - 1 : 0) * nb);
-      bd[0][u] = bp[2 * nb + md(i - 1, nb)];
-      bd[1][u] = bp[nb + i];
-      bd[2][u] = bp[md(i + 1, nb)];
+      if constexpr (FLY) {
+        bd[0][u] = __shfl(psv, 2 * nb + md(i - 1, nb), WT);
+        bd[1][u] = __shfl(psv, nb + i, WT);
+        bd[2][u] = __shfl(psv, md(i + 1, nb), WT);
+      } else {
+        const double* bp = f.ps_band + 3 * (po + (int64_t)(j > 0 ? j - 1 : 0) * nb);
+        bd[0][u] = bp[2 * nb + md(i - 1, nb)];
+        bd[1][u] = bp[nb + i];
+        bd[2][u] = bp[md(i + 1, nb)];
+      }
     }
   };
   prefetch<NBT>(reg, Fe, nbnb);
@@ -208,7 +227,8 @@ __device__ __forceinline__ void adj_condense_body(int e, int s0, const MeshDev& 
 // KEEP: ukeep (LDS) receives u~ of the new seeds of every level, ukeep[j *
 // items + it], for the transposed condense of the earlier step, in place of
 // the u~ seeds in HBM.
-template <int NBT, int S, bool LAM, bool KEEP>
+// FLY: theta_{j+1} and P_j formed from the density rows instead of loaded.
+template <int NBT, int S, bool LAM, bool KEEP, bool FLY>
 __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                                    const AdjArgs& a, AdjLds<NBT, S>& L,
                                                    double (&reg)[(NBT * NBT + WT - 1) / WT], double* ukeep) {
@@ -229,9 +249,25 @@ __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev&
     ok[u] = own[u] && si[u] < ns;
   }
   double cz[IPT], cv[IPT], ca[IPT], ct[3][IPT], cp[3][IPT];
+  static_assert(!FLY || 3 * NBT <= WT, "rows on the fly need 3 n_b <= 64");
+  // FLY: rows from n down; the call for level j forms row j (P_j) and hands over
+  // theta of row j + 1 (thn) formed by the call before
+  FdSweepRows fr;
+  double thn = 0.0;
+  if constexpr (FLY) {
+    fr.init_down(f.bkap + lo * 3 * kFdKappa, f.rho + po, m.xi0, n, nb);
+    thn = fr.next_down().th;
+  }
   // level j: z, v-bar and a-bar seeds, row i of theta_{j+1}^T and of P_j^T
   auto load_level = [&](int j, double (&zz)[IPT], double (&vv)[IPT], double (&aa)[IPT], double (&tb)[3][IPT],
                         double (&pb)[3][IPT]) {
+    double thv = 0.0, pmv = 0.0;
+    if constexpr (FLY) {
+      const FdRow o = fr.next_down();
+      thv = thn;
+      pmv = o.pm;
+      thn = o.th;
+    }
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       const int i = ii[u], im = md(i - 1, nb), ip = md(i + 1, nb);
@@ -239,14 +275,23 @@ __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev&
       zz[u] = a.z[g];
       vv[u] = a.vb[g];
       aa[u] = a.ab[g];
-      const double* tp = f.th_band + 3 * (po + (int64_t)(j + 1) * nb);
-      const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb);
-      tb[0][u] = tp[2 * nb + im];
-      tb[1][u] = tp[nb + i];
-      tb[2][u] = tp[ip];
-      pb[0][u] = pp[2 * nb + im];
-      pb[1][u] = pp[nb + i];
-      pb[2][u] = pp[ip];
+      if constexpr (FLY) {
+        tb[0][u] = __shfl(thv, 2 * nb + im, WT);
+        tb[1][u] = __shfl(thv, nb + i, WT);
+        tb[2][u] = __shfl(thv, ip, WT);
+        pb[0][u] = __shfl(pmv, 2 * nb + im, WT);
+        pb[1][u] = __shfl(pmv, nb + i, WT);
+        pb[2][u] = __shfl(pmv, ip, WT);
+      } else {
+        const double* tp = f.th_band + 3 * (po + (int64_t)(j + 1) * nb);
+        const double* pp = f.pm_band + 3 * (po + (int64_t)j * nb);
+        tb[0][u] = tp[2 * nb + im];
+        tb[1][u] = tp[nb + i];
+        tb[2][u] = tp[ip];
+        pb[0][u] = pp[2 * nb + im];
+        pb[1][u] = pp[nb + i];
+        pb[2][u] = pp[ip];
+      }
     }
   };
   load_level(n - 1, cz, cv, ca, ct, cp);
@@ -315,7 +360,7 @@ __device__ __forceinline__ void adj_recover_levels(int e, int s0, const MeshDev&
 
 // L^T sweep, adjoint Newmark chain at the interior levels, and P_n^T lambda_n.
 // KEEP: u~ of the new seeds goes to ukeep (LDS) instead of the seeds in HBM.
-template <int NBT, int S, bool KEEP = false>
+template <int NBT, int S, bool KEEP = false, bool FLY = false>
 __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                                  const AdjArgs& a, AdjLds<NBT, S>& L, double* ukeep = nullptr) {
   const int ns = min(S, a.NS - s0);
@@ -352,8 +397,8 @@ __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m
     }
   }
   __syncthreads();
-  if (a.lam) adj_recover_levels<NBT, S, true, KEEP>(e, s0, m, f, a, L, reg, ukeep);
-  else adj_recover_levels<NBT, S, false, KEEP>(e, s0, m, f, a, L, reg, ukeep);
+  if (a.lam) adj_recover_levels<NBT, S, true, KEEP, FLY>(e, s0, m, f, a, L, reg, ukeep);
+  else adj_recover_levels<NBT, S, false, KEEP, FLY>(e, s0, m, f, a, L, reg, ukeep);
   if (!a.lam) return;
   // lambda_{-1} = -theta_{-1}^-T theta_0^T lambda_0
   const double* th0 = f.th_band + 3 * po;
@@ -370,18 +415,18 @@ __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m
 
 
 // One block per (element of an n_b class, group of S shots).
-template <int NBT, int S>
+template <int NBT, int S, bool FLY>
 __global__ void __launch_bounds__(WT) adj_condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
                                                           FactorsDev f, AdjArgs a) {
   __shared__ AdjLds<NBT, S> L;
-  adj_condense_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+  adj_condense_body<NBT, S, false, FLY>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
 }
 
-template <int NBT, int S>
+template <int NBT, int S, bool FLY>
 __global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
                                                          FactorsDev f, AdjArgs a) {
   __shared__ AdjLds<NBT, S> L;
-  adj_recover_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+  adj_recover_body<NBT, S, false, FLY>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
 }
 
 // Joint transposed sweep of one (element, group of S shots): the transposed
@@ -390,16 +435,16 @@ __global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restri
 // from them; the same expressions as the separate sweeps, so the same bits,
 // with u~ handed over in LDS instead of written and read back, and one launch
 // fewer.
-template <int NBT, int S>
+template <int NBT, int S, bool FLY>
 __global__ void __launch_bounds__(WT) adj_joint_kernel(const int32_t* __restrict__ elems, MeshDev m,
                                                        FactorsDev f, AdjArgs a) {
   __shared__ AdjLds<NBT, S> L;
   extern __shared__ double ukeep[];   // [interior levels][n_b * S] of the element
   const int e = elems[blockIdx.x];
   const int s0 = blockIdx.y * S;
-  adj_recover_body<NBT, S, true>(e, s0, m, f, a, L, ukeep);
+  adj_recover_body<NBT, S, true, FLY>(e, s0, m, f, a, L, ukeep);
   __syncthreads();
-  adj_condense_body<NBT, S, true>(e, s0, m, f, a, L, ukeep);
+  adj_condense_body<NBT, S, true, FLY>(e, s0, m, f, a, L, ukeep);
 }
 
 // One persistent launch over all n_b classes (work items in order of
@@ -788,10 +833,21 @@ void launch_adj(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, con
   int64_t cnt = (int64_t)m->h_class_elems[cl].size();
   if (cnt == 0) return;
   dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  if constexpr (3 * NBT <= WT) {
+    if (sbfwi_fly_rows(f)) {
+      if (condense)
+        hipLaunchKernelGGL((adj_condense_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f,
+                           a);
+      else
+        hipLaunchKernelGGL((adj_recover_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f,
+                           a);
+      return;
+    }
+  }
   if (condense)
-    hipLaunchKernelGGL((adj_condense_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((adj_condense_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
   else
-    hipLaunchKernelGGL((adj_recover_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((adj_recover_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
 }
 
 template <int NBT>
@@ -868,7 +924,13 @@ bool launch_adj_joint_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, const Ad
   const size_t dyn = (size_t)m->class_nmax[cl] * NBT * S * sizeof(double);
   if (sizeof(AdjLds<NBT, S>) + dyn > kAdjJointLdsMax) return false;
   dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
-  hipLaunchKernelGGL((adj_joint_kernel<NBT, S>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+  if constexpr (3 * NBT <= WT) {
+    if (sbfwi_fly_rows(f)) {
+      hipLaunchKernelGGL((adj_joint_kernel<NBT, S, true>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+      return true;
+    }
+  }
+  hipLaunchKernelGGL((adj_joint_kernel<NBT, S, false>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
   return true;
 }
 

@@ -208,6 +208,11 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
     f->joint_sweeps = value;
     return SBFWI_OK;
   }
+  if (param == 7) {
+    if (value != 0 && value != 1) return sbfwi_fail(SBFWI_EINVAL, "row formation flag must be 0 or 1");
+    f->d.fly = value;
+    return SBFWI_OK;
+  }
 
   if (param >= 10 && param < 10 + 3 * SW_N) {
     if (!valid_shots_per_block(value)) return sbfwi_fail(SBFWI_EINVAL, "shots per block must be 0, 1, 2, 4, 8 or 16");
@@ -229,7 +234,8 @@ extern "C" int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int 
   const int64_t NS = n_shots;
   const int64_t n_slices = (m->n_nodes + ELL_SLICE - 1) / ELL_SLICE;
   // the allocations of factor.hip, step.hip, coarse.hip, adjoint.hip and api.cpp
-  const int64_t factors = 8 * (m->n_finv + 9 * m->n_params + 9 * m->n_loop + 6 * m->n_dense + 32 * m->n_loop +
+  // (the central-difference scheme's kappa and density copy: 27 n_loop + n_params)
+  const int64_t factors = 8 * (m->n_finv + 10 * m->n_params + 36 * m->n_loop + 6 * m->n_dense + 32 * m->n_loop +
                                2 * m->nnz + 2 * m->d.n_ell + m->n_nodes) + 32;
   const int64_t coarse = 8 * (9 * m->n_nodes * NS + 4 * n_slices * 3 * NS + 3 * 11 * 16) +
                          4 * (64 + 32 * (n_slices / 16 + 2));
@@ -248,7 +254,9 @@ extern "C" int sbfwi_plan_bytes(sbfwi_mesh m, int n_shots, int64_t n_steps, int 
   }
   int64_t bwd = 0;
   if (n_ckpt != 0) {
-    bwd = 8 * NS * (3 * m->n_int + 3 * m->n_nodes + m->n_int + 2 * m->n_loop + 2 * m->n_nodes + m->n_x) +
+    // (+ the paper kernel's back-propagated velocity field, n_params per shot)
+    bwd = 8 * NS * (3 * m->n_int + 3 * m->n_nodes + m->n_int + 2 * m->n_loop + 2 * m->n_nodes + m->n_x +
+                    m->n_params) +
           coarse + 4 * m->n_params;
     // the segment recompute: its work buffers and two segment stores (the second one
     // when the recompute of the next segment overlaps the adjoint of the current one)

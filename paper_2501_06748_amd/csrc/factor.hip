@@ -25,6 +25,7 @@
 // rho_j = theta_j phi~_{j-1}^-1 is applied as theta_j (phi~_{j-1}^-1 .), which
 // halves the factor storage and lets the same stored block serve the forward
 // and the transposed sweeps.
+#include "fd_bands.h"
 #include "sbfwi_internal.h"
 
 namespace {
@@ -115,6 +116,22 @@ __device__ double row_band_rg(const ElemCtx& c, int which, int r, int t, int i) 
   return -(k + c.a0 * m);
 }
 
+// theta_r, psi_r, P_r (entry (t, i), level r = 0 .. n) of the central-difference
+// rows through the helpers the sweeps use to form them on the fly.
+__device__ FdRow fd_row_at(const ElemCtx& c, int r, int t, int i) {
+  const int nb = c.nb;
+  double k[kFdKappa];
+  auto al = [&](int tau, int seg, int end, int ab) { return c.alpha[tau * nb * 8 + seg * 8 + end * 4 + ab]; };
+  fd_kappa(al, nb, t, i, k);
+  auto ent = [&](int lev) {
+    const double* rr = c.rho + (int64_t)(c.lfe ? c.n : lev) * nb;
+    return fd_entry(k, rr[md(i - 1, nb)], rr[i], rr[md(i + 1, nb)]);
+  };
+  const FdEntry v = ent(r);
+  const double e0m = r > 0 ? ent(r - 1).e0 : 0.0, e0p = r < c.n ? ent(r + 1).e0 : 0.0;
+  return fd_row(c.xi0, fd_step(c.xi0, c.n), r, c.n, e0m, v, e0p);
+}
+
 // Band entries of the rows: which = 0 theta, 1 phi, 2 psi, 3 P, for row r = -1 .. n+1.
 template <int SCH>
 __device__ double row_band(const ElemCtx& c, int which, int r, int t, int i) {
@@ -128,16 +145,14 @@ __device__ double row_band(const ElemCtx& c, int which, int r, int t, int i) {
     if (which == 2) return x * e_band(c, 0, lev, t, i) / (2.0 * h);
     return 0.0;
   }
-  double x = xi_of(c, r);
-  double e0 = e_band(c, 0, r, t, i);
-  if (which == 3) return -x * x * e_band(c, 3, r, t, i);
   if (which == 1) {
+    const double x = xi_of(c, r);
+    const double e0 = e_band(c, 0, r, t, i);
     return -2.0 * x * x * e0 / (h * h) - e_band(c, 2, r, t, i) + x * d_band(c, 1, r, t, i, true) -
            c.a0 * x * x * e_band(c, 3, r, t, i);
   }
-  double C = e0 + e_band_T(c, 1, r, t, i) - e_band(c, 1, r, t, i) + x * d_band(c, 0, r, t, i, false);
-  if (which == 0) return x * x * e0 / (h * h) - x * C / (2.0 * h);
-  return x * x * e0 / (h * h) + x * C / (2.0 * h);
+  const FdRow o = fd_row_at(c, r, t, i);
+  return which == 0 ? o.th : (which == 2 ? o.ps : o.pm);
 }
 
 template <int NBT>
@@ -337,6 +352,15 @@ __global__ void __launch_bounds__(FT) factor_kernel(
   ec.scheme = SCH;
   ec.rgw = SCH != SBFWI_SCHEME_PAPER_FD ? ff.rgw + ff.rgw_off[nr] : nullptr;
   const int64_t po = mm.par_off[e];
+  // central differences: kappa of every band entry, for the sweeps that form theta_j,
+  // psi_j, P_j on the fly, at ((loop slot) * 3 + t) * kFdKappa
+  if constexpr (SCH == SBFWI_SCHEME_PAPER_FD) {
+    auto al = [&](int tau, int seg, int end, int ab) { return L.alpha[tau * nb * 8 + seg * 8 + end * 4 + ab]; };
+    for (int q = threadIdx.x; q < 3 * nb; q += FT) {
+      const int t = q / nb, i = q % nb;
+      fd_kappa(al, nb, t, i, ff.bkap + ((lo + i) * 3 + t) * kFdKappa);
+    }
+  }
   // persistent bands: theta_j, psi_j, P_j for j = 0..n; theta_{n+1}, phi_{-1}, psi_{-1}
   for (int q = threadIdx.x; q < 3 * nb * nr; q += FT) {
     int j = q / (3 * nb), rem = q % (3 * nb), t = rem / nb, i = rem % nb;
@@ -839,7 +863,7 @@ __global__ void transpose_diag_kernel(int64_t nnz, int64_t n_nodes, const int64_
 void sbfwi_factors_free(sbfwi_factors_s* f) {
   if (!f) return;
   FactorsDev& d = f->d;
-  void* ptrs[] = {d.finv, d.th_band, d.ps_band, d.pm_band, d.th_np1, d.phim1, d.psim1,
+  void* ptrs[] = {d.finv, d.th_band, d.ps_band, d.pm_band, d.th_np1, d.phim1, d.psim1, d.bkap, d.rho,
                   d.G, d.S, d.psit0, d.psin_inv, d.phit_n, d.thm1_inv, d.gbasis,
                   d.Kval, d.KTval, d.Kell, d.KTell, d.diag_inv, d.status, d.rgw, d.Me, d.Mval};
   sbfwi_dev_free(d.rgw_off);
@@ -948,6 +972,10 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   A(&d.phit_n, m->n_dense);
   A(&d.thm1_inv, m->n_dense);
   A(&d.gbasis, 32 * m->n_loop);
+  if (scheme == SBFWI_SCHEME_PAPER_FD) {   // what the sweeps need to form the rows on the fly
+    A(&d.bkap, 3 * kFdKappa * m->n_loop);
+    A(&d.rho, m->n_params);
+  }
   A(&d.Kval, m->nnz);
   A(&d.KTval, m->nnz);
   A(&d.Kell, m->d.n_ell);
@@ -976,6 +1004,10 @@ int sbfwi_factor_impl(sbfwi_mesh_s* m, const double* rho, double c, double dt, d
   };
   hipError_t he = hipMemsetAsync(d.status, 0, 8 * sizeof(int), s);
   if (he != hipSuccess) return hip_fail(he, "hipMemsetAsync");
+  if (d.rho) {
+    he = hipMemcpyAsync(d.rho, rho, sizeof(double) * m->n_params, hipMemcpyDeviceToDevice, s);
+    if (he != hipSuccess) return hip_fail(he, "density copy");
+  }
   {
     ProfScope ps_factor(PK_FACTOR, s);   // the element factorisation kernels
     for (int cl = 0; cl < 3; ++cl) {

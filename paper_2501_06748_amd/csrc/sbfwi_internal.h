@@ -22,6 +22,10 @@
 
 #define SBFWI_MAX_NB 24
 
+// Sweeps form the central-difference rows from the densities (fd_bands.h).
+struct FactorsDev;
+inline bool sbfwi_fly_rows(const FactorsDev& f);
+
 // The low-frequency expansion schemes (nodal time loop, K_e and M_e per element).
 inline bool sbfwi_is_lfe(int scheme) {
   return scheme == SBFWI_SCHEME_LFE || scheme == SBFWI_SCHEME_LFE_CONDENSED;
@@ -151,6 +155,10 @@ struct FactorsDev {
   double* phit_n = nullptr;    // [n_dense] phi~_n
   double* thm1_inv = nullptr;  // [n_dense] theta_{-1}^-1
   double* gbasis = nullptr;    // [32 n_loop] d(E0,E1,E2,M0 segment block)/d(nodal density)
+  // central differences only: the rows theta_j, psi_j, P_j formed on the fly by the sweeps
+  double* bkap = nullptr;      // [n_loop][3][kFdKappa] kappa of every band entry (fd_bands.h)
+  double* rho = nullptr;       // [n_params] the model's nodal densities
+  int fly = 1;                 // the sweeps form those rows on the fly (when bkap exists)
   double* Kval = nullptr;      // [nnz] coarse matrix on the CSR pattern
   double* KTval = nullptr;     // [nnz] its transpose on the same (symmetric) pattern
   double* Kell = nullptr;      // [n_ell] K_g in the sliced ELL layout
@@ -165,6 +173,8 @@ struct FactorsDev {
   double* Me = nullptr;        // [n_dense] M_e (S holds K_e)
   double* Mval = nullptr;      // [nnz] M_g on the CSR pattern (Kval holds K_g + a0 M_g)
 };
+
+inline bool sbfwi_fly_rows(const FactorsDev& f) { return f.bkap != nullptr && f.fly != 0; }
 
 // Low-frequency expansion path (lfe.hip): forward run (vstore, optional, keeps
 // every step's nodal velocity) and the paper-kernel gradient from the kept

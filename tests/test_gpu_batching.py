@@ -1,8 +1,10 @@
 """Batching pattern: ragged meshes, many shots, launch plans, graph replay.
 
 Every sweep launch shape (shots per block 1..16 per n_b class, or one
-persistent launch over all classes) computes each (element, shot) with the
-same arithmetic, so results must be bit-identical to the default plan; the
+persistent launch over all classes, joint or separate sweeps, rows of the
+central-difference scheme formed on the fly or read) computes each (element,
+shot) with the same arithmetic, so results must be bit-identical to the
+default plan; the
 same holds for the autotuned plan and for graph replay of the forward steps.
 The batched multi-shot run must agree with one run per shot, and the ragged
 multi-shot run with the oracle.
@@ -62,9 +64,16 @@ def test_sweep_plans_bit_identical(name):
     variants += [("separate sweeps", [(sb_.LAUNCH_JOINT_SWEEPS, 0)]),
                  ("separate sweeps S=2", [(sb_.LAUNCH_JOINT_SWEEPS, 0)] +
                   [(sb_.launch_param_shots(k, c), 2) for k in range(4) for c in range(3)])]
+    # the transposed sweeps read the rows theta, psi, P from the factors instead of
+    # forming them from the densities (the default for n_b <= 16)
+    variants += [("rows read", [(sb_.LAUNCH_ROWS_ON_THE_FLY, 0)]),
+                 ("rows read, separate sweeps", [(sb_.LAUNCH_ROWS_ON_THE_FLY, 0), (sb_.LAUNCH_JOINT_SWEEPS, 0)]),
+                 ("rows read S=1", [(sb_.LAUNCH_ROWS_ON_THE_FLY, 0)] +
+                  [(sb_.launch_param_shots(k, c), 1) for k in range(4) for c in range(3)])]
     for label, params in variants:
         sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_RESET_PLAN, 0)
         sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_JOINT_SWEEPS, 1)
+        sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_ROWS_ON_THE_FLY, 1)
         for p, v in params:
             sb_.sbfwi_set_launch(g.f, p, v)
         tr, mis, gr, _ = g.gradient(obs, n_steps=steps)
@@ -73,6 +82,7 @@ def test_sweep_plans_bit_identical(name):
         assert same
     sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_RESET_PLAN, 0)
     sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_JOINT_SWEEPS, 1)
+    sb_.sbfwi_set_launch(g.f, sb_.LAUNCH_ROWS_ON_THE_FLY, 1)
 
 
 def test_autotuned_plan_and_graph_replay_bit_identical():
