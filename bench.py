@@ -58,11 +58,13 @@ def kernel_bytes(mesh, NS, nnz):
         # and the accelerations (n+1 levels) for the adjoint
         "recover_store": blk + band(n - 1) + NS * (3 * n * nb + nb + 2 * n * nb)
                          + NS * ((n + 3) + (n + 1)) * nb,
-        # reads phi~^-1, psi~_0, bands psi; seeds u~ (n); writes z (n) and the coupling (1)
-        "adj_condense": blk + band(n - 1) + NS * (n * nb + n * nb + nb),
-        # reads G, phi~^-1, theta (n+2), P (n+1), theta_-1^-1; lambda_B, z, seeds v-bar, a-bar (2 n);
-        # writes seeds u~, v-bar, a-bar (3 n), P_n^T lambda_n, adjoint rows (n+3)
-        "adj_recover": blk + 2 * nb * nb + band(n + 2) + band(n + 1) +
+        # reads phi~^-1, psi~_0, the density rows (n+1) and the rows' coefficients (27 per node)
+        # instead of the bands psi, psi_{n-1}; seeds u~ (n); writes z (n) and the coupling (1)
+        "adj_condense": blk + (n + 1) * nb + 27 * nb + band(1) + NS * (n * nb + n * nb + nb),
+        # reads G, phi~^-1, the density rows and coefficients instead of theta, P, theta_-1^-1,
+        # P_n, theta_0; lambda_B, z, seeds v-bar, a-bar (2 n); writes seeds u~, v-bar, a-bar (3 n),
+        # P_n^T lambda_n, adjoint rows (n+3)
+        "adj_recover": blk + 2 * nb * nb + (n + 1) * nb + 27 * nb + band(2) +
                        NS * (nb + n * nb + 2 * n * nb + 3 * n * nb + nb + (n + 3) * nb),
         # reads unknowns and adjoint rows (n+3 levels each), accelerations (n+1), alpha; grad RMW
         "grad_exact": 32 * nb + 2 * (n + 1) * nb + NS * (2 * (n + 3) * nb + (n + 1) * nb),
