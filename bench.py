@@ -222,6 +222,10 @@ def main():
                     help="1: backward pass overlaps the segment recompute with the adjoint steps (default)")
     ap.add_argument("--autotune", type=int, default=0,
                     help="1: sweep launch plan autotuned once per mesh and shot count, before the timed region")
+    ap.add_argument("--tail-gib", type=float, default=-1.0,
+                    help="tail store of the forward run in GiB (the fields of its last checkpoint segments, "
+                         "so that the backward pass recomputes only the segments before them); -1 = the device "
+                         "memory left free by everything else the evaluation needs, less 8 GiB")
     ap.add_argument("--counter-probe", type=int, default=0, metavar="K",
                     help="run K gradient steps of the workload (--nt steps each) plus a 1 GiB device copy, "
                          "print nothing else and exit: the program profiled by hardware-counter runs")
@@ -255,6 +259,16 @@ def main():
     plan = None
 
     overlap = args.overlap
+    # tail store budget: what the device has free beyond the evaluation's own footprint
+    if args.tail_gib >= 0:
+        tail_kib = int(args.tail_gib * (1 << 20))
+    else:
+        pb = sb.sbfwi_plan_bytes(mh, S, N, -1)
+        need = pb["factors"] + pb["checkpoints"] + max(pb["forward_work"], pb["backward_work"])
+        free, _ = torch.cuda.mem_get_info()
+        tail_kib = max(0, (free - need - (8 << 30)) >> 10)
+    tail_kib = min(tail_kib, (1 << 31) - 1)
+    tail_steps = {"steps": 0}
 
     # observed data: bilinear finite elements on the data grid (sharp voids at the density floor)
     fg = W.fem_grid(wl)
@@ -273,6 +287,7 @@ def main():
         if args.graphs:
             sb.sbfwi_set_launch(f, sb.LAUNCH_GRAPHS, 1)
         sb.sbfwi_set_launch(f, 3, overlap)
+        sb.sbfwi_set_launch(f, sb.LAUNCH_TAIL_STORE_KIB, tail_kib)
         if plan is not None:
             sb.apply_plan(f, plan)
         return f
@@ -333,6 +348,7 @@ def main():
             sb.sbfwi_profile(prof_bwd)
         sb.sbfwi_gradient(f, ck, observed, traces, sb.GRAD_EXACT, misfit, grad)
         stats = sb.sbfwi_solver_stats(f)
+        tail_steps["steps"] = sb.sbfwi_ckpt_info(ck)["tail_steps"]
         ck.close()
         f.close()
         return stats
@@ -453,6 +469,7 @@ def main():
                    else "BiCGStab, rtol 1e-13",
                    "graphs": bool(args.graphs), "launch_plan": "autotuned" if plan is not None else "default",
                    "overlapped_backward": bool(args.overlap),
+                   "tail_store_steps": tail_steps["steps"],
                    "scheme": "radial Galerkin" if args.scheme == 1 else "paper finite differences",
                    "units_per_step": units},
         "roofline": roof,

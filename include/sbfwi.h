@@ -185,6 +185,15 @@ int sbfwi_set_solver(sbfwi_factors f, double rtol, int max_iter);
  *             classes form the rows theta_j, psi_j, P_j of every level from the element's
  *             nodal densities instead of reading them from the factors (default); 0 = read
  *             them.  Both give the same bits.
+ *   param 8:  tail store budget in KiB (default 0): a forward run with checkpoints (not full
+ *             storage) also keeps, for as many whole checkpoint segments at the end of the
+ *             run as this budget holds, every step's unknowns and accelerations, as the
+ *             backward pass would recompute them (skipped if the store cannot be allocated);
+ *             the exact gradient then recomputes only the segments before them.  The
+ *             footprint of sbfwi_plan_bytes does not include it; sbfwi_ckpt_info reports it.
+ *             When the run is destroyed its tail store is kept for the next run on that
+ *             device that fits in it (allocations of this size take seconds) until
+ *             sbfwi_finalize.
  *   param 10 + 3 k + c: shots per block (0 = default, 1, 2, 4, 8, 16) of sweep k (0 condense,
  *             1 recover, 2 transposed condense, 3 transposed recover) for n_b class c
  *             (n_b <= 8, <= 16, <= 24).
@@ -325,11 +334,12 @@ int sbfwi_gradient(sbfwi_factors f, sbfwi_ckpt ck, const double* observed,
 int sbfwi_misfit(const double* observed, const double* traces, int64_t count, double dt, double* residual,
                  double* misfit, hipStream_t s);
 
-/* Checkpointed run (host values): host_out[0] footprint in bytes, [1] checkpoint interval,
- * [2] shots, [3] receivers, [4] steps of the run -- the leading sizes of the adj_src,
- * observed and traces arrays that sbfwi_adjoint and sbfwi_gradient read, and of the
+/* Checkpointed run (host values, host_out holds 6): [0] footprint in bytes, [1] checkpoint
+ * interval, [2] shots, [3] receivers, [4] steps of the run -- the leading sizes of the
+ * adj_src, observed and traces arrays that sbfwi_adjoint and sbfwi_gradient read, and of the
  * per-shot gradients they write (the ABI takes no sizes for those arrays: a caller
- * passing shorter arrays makes the library read and write past them). */
+ * passing shorter arrays makes the library read and write past them) -- and [5] the steps
+ * at the end of the run kept by the tail store (sbfwi_set_launch param 8). */
 int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* host_out);
 
 /* Nested-dissection structure used by the direct coarse solver (host values):
@@ -427,9 +437,9 @@ int sbfwi_fem_forward_noalloc(int nx, int ny, double lx, double ly, const double
 
 /*
  * sbfwi_finalize -- releases the runtime objects the library owns outside the
- * handles: the per-thread streams of its synchronous copies and the events of
- * the live kernel timing (pending timings are discarded, timing is switched
- * off).  Waits for the device first.  Handles stay valid; later calls create
+ * handles: the per-thread streams of its synchronous copies, the events of the
+ * live kernel timing (pending timings are discarded, timing is switched off)
+ * and a tail store kept from a destroyed run (sbfwi_set_launch param 8).  Waits for the device first.  Handles stay valid; later calls create
  * what they need again.  Call it after the last handle is destroyed and before
  * the process tears down the HIP runtime, so that no library-owned stream or
  * event outlives the caller's own teardown.  Not to be called while another

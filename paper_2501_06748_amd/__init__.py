@@ -209,7 +209,7 @@ def sbfwi_autotune(f: FactorsHandle, n_shots: int, stream=None) -> dict:
 
 LAUNCH_ENQUEUED_ITERS, LAUNCH_GRAPHS, LAUNCH_RESET_PLAN = 0, 1, 2
 LAUNCH_OVERLAP_BACKWARD, LAUNCH_KEEP_SOLUTIONS, LAUNCH_JOINT_SWEEPS, LAUNCH_SUBTREE_CUT = 3, 4, 5, 6
-LAUNCH_ROWS_ON_THE_FLY = 7
+LAUNCH_ROWS_ON_THE_FLY, LAUNCH_TAIL_STORE_KIB = 7, 8
 
 
 def launch_param_shots(sweep: int, cls: int) -> int:
@@ -344,10 +344,10 @@ def sbfwi_misfit(observed, traces, dt, misfit, residual=None, stream=None):
 
 
 def sbfwi_ckpt_info(ck: CkptHandle) -> dict:
-    buf = np.zeros(5, dtype=np.int64)
+    buf = np.zeros(6, dtype=np.int64)
     check(lib().sbfwi_ckpt_info(ck, buf.ctypes.data_as(C.c_void_p)))
     return {"bytes": int(buf[0]), "interval": int(buf[1]), "n_shots": int(buf[2]), "n_rec": int(buf[3]),
-            "n_steps": int(buf[4])}
+            "n_steps": int(buf[4]), "tail_steps": int(buf[5])}
 
 
 def sbfwi_solver_stats(f: FactorsHandle, reset=False) -> dict:

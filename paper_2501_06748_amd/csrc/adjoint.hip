@@ -1129,6 +1129,9 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   };
   const bool ov = sr != nullptr && !ck->full_store;
   const bool gs = sg != nullptr && mode == SBFWI_GRAD_EXACT;
+  // segments tseg0 .. nseg - 1 come from the tail store of the forward run (exact mode):
+  // no recompute
+  const int64_t tseg0 = (ck->tail_x && kind == 0) ? ck->tail_k0 / C : nseg;
   bool adj_condensed = false;   // the transposed condense of the next adjoint step is done
   int64_t n_grad = 0;   // contractions launched on sg
   if (ov || gs) {   // the side streams start after everything enqueued on st so far
@@ -1136,13 +1139,14 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     if (ov) SBFWI_HIP(hipStreamWaitEvent(sr, ev[4], 0));
     if (gs) SBFWI_HIP(hipStreamWaitEvent(sg, ev[4], 0));
   }
-  if (ov) {
+  if (ov && nseg - 1 < tseg0) {
     SBFWI_CHECK(recompute(nseg - 1, (int)((nseg - 1) % 2), sr));
     SBFWI_HIP(hipEventRecord(ev[(nseg - 1) % 2], sr));
   }
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t k0 = seg * C, k1 = std::min(k0 + C, N);
     const int b = ov ? (int)(seg % 2) : 0;
+    const bool tail = seg >= tseg0;
     // recompute of segment seg - 1 (into the other store), paced by this segment's
     // adjoint steps: its step j waits until the adjoint's step j has been reached,
     // so that every adjoint step (and its latency-bound coarse solve) runs beside
@@ -1151,14 +1155,14 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     const int nb = (int)((seg + 1) % 2);
     int64_t kr = 0, kr1 = 0;   // next and last step of the paced recompute
     if (ov) {
-      if (seg >= 1) {   // once the adjoint of seg + 1 is done with that store
+      if (seg >= 1 && seg - 1 < tseg0) {   // once the adjoint of seg + 1 is done with that store
         if (seg + 1 <= nseg - 1) SBFWI_HIP(hipStreamWaitEvent(sr, ev[2 + nb], 0));
         SBFWI_CHECK(recompute_begin(seg - 1, sr));
         kr = (seg - 1) * C + 1;
         kr1 = seg * C;
       }
-      SBFWI_HIP(hipStreamWaitEvent(st, ev[b], 0));
-    } else if (!ck->full_store) {
+      if (!tail) SBFWI_HIP(hipStreamWaitEvent(st, ev[b], 0));
+    } else if (!ck->full_store && !tail) {
       SBFWI_CHECK(recompute(seg, 0, st));
     }
     for (int64_t k = k1; k > k0; --k) {
@@ -1168,8 +1172,11 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         SBFWI_CHECK(recompute_step(seg - 1, nb, kr, sr));
         ++kr;
       }
-      const double* X = ck->full_store ? ck->xstore + (k - 1) * m->n_x * NS : xseg[b] + (k - k0 - 1) * m->n_x * NS;
+      const double* X = ck->full_store ? ck->xstore + (k - 1) * m->n_x * NS
+                        : tail        ? ck->tail_x + (k - ck->tail_k0 - 1) * m->n_x * NS
+                                      : xseg[b] + (k - k0 - 1) * m->n_x * NS;
       const double* Fs = ck->full_store ? (kind == 0 ? ck->fstore : ck->vstore) + (k - 1) * m->n_params * NS
+                         : tail         ? ck->tail_f + (k - ck->tail_k0 - 1) * m->n_params * NS
                                         : fseg[b] + (k - k0 - 1) * m->n_params * NS;
       if (mode == SBFWI_GRAD_EXACT) {
         const int q = (int)(k % 2);

@@ -73,6 +73,59 @@ void sbfwi_dev_free(void* p) {
 
 void sbfwi_factors_free(sbfwi_factors_s* f);
 
+// The tail store of a checkpointed run (hundreds of GiB: an allocation of that size
+// takes seconds) is kept when its run is destroyed and handed to the next run on the
+// same device that fits in it; sbfwi_finalize releases it.
+static std::mutex g_tail_mu;
+static struct {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+} g_tail;
+
+static void* tail_take(size_t bytes) {
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lk(g_tail_mu);
+    if (g_tail.p && g_tail.device == dev && g_tail.bytes >= bytes) {
+      void* p = g_tail.p;
+      g_tail = {};
+      return p;
+    }
+  }
+  return sbfwi_dev_alloc(bytes);
+}
+
+static void tail_give(void* p, size_t bytes) {
+  if (!p) return;
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  void* drop = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_tail_mu);
+    if (g_tail.p && g_tail.bytes >= bytes && g_tail.device == dev) {
+      drop = p;   // keep the larger one
+    } else {
+      drop = g_tail.p;
+      g_tail.p = p;
+      g_tail.bytes = bytes;
+      g_tail.device = dev;
+    }
+  }
+  sbfwi_dev_free(drop);
+}
+
+static void tail_release() {
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_tail_mu);
+    p = g_tail.p;
+    g_tail = {};
+  }
+  sbfwi_dev_free(p);
+}
+
 // One non-blocking stream per host thread for the library's synchronous copies,
 // created on first use and registered so that sbfwi_finalize can destroy them
 // all; a thread's cached stream is recreated after a finalize (generation count).
@@ -95,8 +148,11 @@ static hipStream_t aux_stream() {
 
 int sbfwi_prof_release();
 
+static void tail_release();
+
 extern "C" int sbfwi_finalize(void) {
   SBFWI_HIP(hipDeviceSynchronize());
+  tail_release();
   int rc = sbfwi_prof_release();
   std::lock_guard<std::mutex> lk(g_aux_mu);
   g_aux_gen.fetch_add(1);
@@ -206,6 +262,11 @@ extern "C" int sbfwi_set_launch(sbfwi_factors f, int param, int value) {
   if (param == 5) {
     if (value != 0 && value != 1) return sbfwi_fail(SBFWI_EINVAL, "joint sweep flag must be 0 or 1");
     f->joint_sweeps = value;
+    return SBFWI_OK;
+  }
+  if (param == 8) {
+    if (value < 0) return sbfwi_fail(SBFWI_EINVAL, "tail store budget must be >= 0 KiB");
+    f->tail_kib = value;
     return SBFWI_OK;
   }
   if (param == 7) {
@@ -328,6 +389,7 @@ static void ckpt_free(sbfwi_ckpt_s* ck) {
   sbfwi_dev_free(ck->rec_node);
   sbfwi_dev_free(ck->states);
   sbfwi_dev_free(ck->xstore);
+  tail_give(ck->tail_x, ck->tail_bytes);   // tail_f lies in the same allocation
   sbfwi_dev_free(ck->fstore);
   sbfwi_dev_free(ck->vstore);
   sbfwi_dev_free(ck->ustore);
@@ -343,6 +405,7 @@ extern "C" int sbfwi_ckpt_info(sbfwi_ckpt ck, int64_t* out) {
   out[2] = ck->n_shots;
   out[3] = ck->n_rec;
   out[4] = ck->n_steps;
+  out[5] = ck->n_steps - (ck->tail_x ? ck->tail_k0 : ck->n_steps);
   return SBFWI_OK;
 }
 
@@ -418,6 +481,23 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
         else
           (void)hipGetLastError();
       }
+      // the tail store: as many whole segments at the end of the run as the budget holds
+      // (skipped if it does not fit)
+      ck->tail_k0 = n_steps;
+      const int64_t per_step = 8 * (m->n_x + m->n_params) * n_shots;
+      const int64_t segs = std::min(f->tail_kib * 1024 / per_step / ck->interval, ck->n_saved);
+      if (segs > 0) {
+        const int64_t k0 = std::max<int64_t>(0, (ck->n_saved - segs) * ck->interval), ns = n_steps - k0;
+        ck->tail_x = (double*)tail_take((size_t)(ns * per_step));
+        if (ck->tail_x) {
+          ck->tail_f = ck->tail_x + ns * m->n_x * n_shots;
+          ck->tail_bytes = (size_t)(ns * per_step);
+          ck->tail_k0 = k0;
+          ck->bytes += ns * per_step;
+        } else {
+          (void)hipGetLastError();
+        }
+      }
     }
   }
   w.ustore = ck ? ck->ustore : nullptr;
@@ -427,7 +507,7 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
   src.node_stride = 1;
   src.amp = wavelet;
   src.amp_steps = n_steps;
-  const bool graphs = f->use_graphs && !(ck && ck->full_store);
+  const bool graphs = f->use_graphs && !(ck && (ck->full_store || ck->tail_x));
   if (graphs) SBFWI_CHECK(sbfwi_graph_step_reset(&w, 1, s));
   for (int64_t k = 1; k <= n_steps; ++k) {
     double *xs = nullptr, *fs = nullptr, *vs = nullptr;
@@ -441,6 +521,9 @@ static int forward_run(sbfwi_factors_s* f, int n_shots, int64_t n_steps, const i
       xs = ck->xstore + (k - 1) * m->n_x * n_shots;
       fs = ck->fstore + (k - 1) * m->n_params * n_shots;
       vs = ck->vstore + (k - 1) * m->n_params * n_shots;
+    } else if (ck && ck->tail_x && k > ck->tail_k0) {
+      xs = ck->tail_x + (k - ck->tail_k0 - 1) * m->n_x * n_shots;
+      fs = ck->tail_f + (k - ck->tail_k0 - 1) * m->n_params * n_shots;
     }
     SBFWI_CHECK(sbfwi_forward_step(f, &w, k, src, n_rec, rec_node, traces, n_steps, xs, fs, 0, s, vs, nullptr,
                                    k < n_steps));

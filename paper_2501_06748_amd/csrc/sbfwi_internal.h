@@ -221,6 +221,7 @@ struct sbfwi_factors_s {
   int use_graphs = 0;            // forward runs replay each time step from HIP graphs
   int overlap_adjoint = 1;       // recompute the next checkpoint segment while the adjoint runs the current one
   int keep_solutions = 1;        // forward runs with checkpoints keep every step's coarse solution
+  int64_t tail_kib = 0;          // forward runs with checkpoints keep the fields of the last segments (KiB)
   int joint_sweeps = 1;          // recover of step k and condense of step k + 1 in one sweep
   int scheme = 0;                // radial scheme (SBFWI_SCHEME_*)
   SweepPlan plan;
@@ -244,6 +245,13 @@ struct sbfwi_ckpt_s {
   double* fstore = nullptr;      // full storage: [n_steps][n_params*NS] accelerations a^k
   double* vstore = nullptr;      // full storage: [n_steps][n_params*NS] velocities v^k
   double* ustore = nullptr;      // optional: [n_steps][n_nodes*NS] coarse solutions (the recompute skips its solves)
+  // optional tail store: steps tail_k0 + 1 .. n_steps (whole checkpoint segments at the end of
+  // the run) keep the unknowns with ghosts and the accelerations, as a recompute would store
+  // them, so that the exact backward pass does not recompute those segments
+  int64_t tail_k0 = 0;
+  double* tail_x = nullptr;      // [n_steps - tail_k0][n_x*NS], then in the same allocation
+  double* tail_f = nullptr;      // [n_steps - tail_k0][n_params*NS]
+  size_t tail_bytes = 0;
 };
 
 // Growth envelope of a forward run (api.cpp): the nodal displacement of shot s at

@@ -92,6 +92,43 @@ def test_overlapped_recompute_is_bit_identical(n_ckpt):
     assert err <= 1e-8
 
 
+def test_tail_store_is_bit_identical():
+    """With the tail store the forward run keeps the fields of its last checkpoint
+    segments and the exact backward pass recomputes only the segments before them:
+    the same bits as recomputing every segment, for no, some and all segments in
+    the tail, with the recompute overlapped and one segment after the other; the
+    paper kernel (which does not use the tail) is unchanged too."""
+    wl = W.config_small(nx=4, ny=2, segs=2, n_r=7, n_steps=40, n_shots=3)
+    rho = wl.models["random30"]
+    obs = ostp.forward(_om(wl, rho * 0.95), wl.src_nodes, wl.wavelets, wl.rec_nodes, 40)
+    g = GpuModel(wl, rho, coarse_solver=1)
+    sb = g.sb
+    n_ckpt = 5                                            # segments of 8 steps
+    _, mis0, grad0, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt)
+    _, misp0, gradp0, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt, mode=1)
+    nb, nr = wl.mesh.n_b().astype(np.int64), wl.mesh.n_r.astype(np.int64)
+    per_step = 8 * wl.n_shots * int((nb * (2 * nr + 2)).sum())   # unknowns with ghosts + accelerations
+    seen = set()
+    for segs in (1, 3, 5, 9):
+        kib = (segs * 8 * per_step + 1023) // 1024
+        sb.sbfwi_set_launch(g.f, sb.LAUNCH_TAIL_STORE_KIB, kib)
+        tr, ck = g.forward(n_steps=40, n_ckpt=n_ckpt)
+        tail = sb.sbfwi_ckpt_info(ck)["tail_steps"]
+        ck.close()
+        assert tail == min(segs, 5) * 8, (segs, tail)
+        seen.add(tail)
+        for overlap in (1, 0):
+            sb.sbfwi_set_launch(g.f, sb.LAUNCH_OVERLAP_BACKWARD, overlap)
+            _, mis1, grad1, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt)
+            log(f"tail of {tail} steps, overlap {overlap}: bit-identical {np.array_equal(grad1, grad0)}")
+            assert np.array_equal(grad1, grad0) and mis1 == mis0
+        _, misp1, gradp1, _ = g.gradient(obs, n_steps=40, n_ckpt=n_ckpt, mode=1)
+        assert np.array_equal(gradp1, gradp0) and misp1 == misp0
+        sb.sbfwi_set_launch(g.f, sb.LAUNCH_OVERLAP_BACKWARD, 1)
+    assert seen == {8, 24, 40}
+    sb.sbfwi_set_launch(g.f, sb.LAUNCH_TAIL_STORE_KIB, 0)
+
+
 def test_solve_program_structure():
     """The solve programs evaluate every row once: the forward program |J| + |B_J|
     rows per supernode (y and the update vector), the backward one |J|; one launch
