@@ -96,7 +96,10 @@ def method_bytes(mesh, NS):
     next) the whole step, and so does the joint transposed sweep (two blocks and
     the adjoint state's 48 n_b); the gradient contraction the rest of the
     adjoint's 80 n_b: 32 n_b.  Returns bytes per launch and per unit of the whole
-    evaluation (fwd + recompute + adjoint + gradient = 48 n_b^2/S + 192 n_b)."""
+    evaluation (fwd + recompute + adjoint + gradient = 48 n_b^2/S + 192 n_b).
+    The model counts the state as u, v, a; the sweeps keep two combinations of
+    them (r, w), so they move fewer state bytes than it counts, and more for
+    the banded rows and the swept sources it leaves out (kernel_bytes)."""
     nb = mesh.n_b().astype("float64")
     units = mesh.n_r.astype("float64") * NS            # units of one launch, per element
     blk = nb * nb / NS

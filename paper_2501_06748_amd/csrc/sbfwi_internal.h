@@ -239,7 +239,7 @@ struct sbfwi_ckpt_s {
   int64_t* src_node = nullptr;   // device copies [n_shots]
   double* wavelet = nullptr;     // [n_shots][n_steps]
   int64_t* rec_node = nullptr;   // [n_rec]
-  double* states = nullptr;      // [n_saved][state size]: interior u, v, a then nodal U, V, A
+  double* states = nullptr;      // [n_saved][state size]: interior r, w then nodal U, V, A, W, corr
   bool full_store = false;       // every step's unknowns kept by the forward run
   double* xstore = nullptr;      // full storage: [n_steps][n_x*NS]
   double* fstore = nullptr;      // full storage: [n_steps][n_params*NS] accelerations a^k

@@ -124,8 +124,8 @@ template <int NBT, int S, bool JOINT = false>
 __device__ __forceinline__ void condense_body(int e, int s0, const MeshDev& m, const FactorsDev& f,
                                               const StepArgs& a, StepLds<NBT, S>& L,
                                               const double* wkeep = nullptr) {
-  // Levels j = 0 .. n-1 stream: the next level's F block, state (u, v, a; on the
-  // boundary level the nodal state) and bands P, theta are loaded at the top of
+  // Levels j = 0 .. n-1 stream: the next level's F block, w (on the boundary
+  // level the nodal W) and bands P, theta are loaded at the top of
   // each level and consumed at its end; lanes without an item load word 0 of
   // their arrays and store to g_sink.
   constexpr int IPT = (NBT * S + WT - 1) / WT;
