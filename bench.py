@@ -116,9 +116,9 @@ def method_bytes(mesh, NS):
 # kernel instances as rocprofv3 names them (uniform 16-node elements, 4 shots per block)
 ROCPROF_NAME = {"joint": "joint_kernel<16, 4, false>", "joint_store": "joint_kernel<16, 4, true>",
                 "condense": "condense_kernel<16, 4>", "recover": "recover_kernel<16, 4, false>",
-                "recover_store": "recover_kernel<16, 4, true>", "adj_joint": "adj_joint_kernel<16, 4>",
-                "adj_condense": "adj_condense_kernel<16, 4>",
-                "adj_recover": "adj_recover_kernel<16, 4>", "grad_exact": "grad_exact_kernel<16, 4>"}
+                "recover_store": "recover_kernel<16, 4, true>", "adj_joint": "adj_joint_kernel<16, 4, true>",
+                "adj_condense": "adj_condense_kernel<16, 4, true>",
+                "adj_recover": "adj_recover_kernel<16, 4, true>", "grad_exact": "grad_exact_kernel<16, 4>"}
 
 
 def fem_bytes(nx, ny, S, R):
