@@ -416,17 +416,23 @@ __device__ __forceinline__ void adj_recover_body(int e, int s0, const MeshDev& m
 
 // One block per (element of an n_b class, group of S shots).
 template <int NBT, int S, bool FLY>
-__global__ void __launch_bounds__(WT) adj_condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                          FactorsDev f, AdjArgs a) {
+__global__ void __launch_bounds__(WT) adj_condense_kernel(const int32_t* __restrict__ elems, int64_t n_el,
+                                                          MeshDev m, FactorsDev f, AdjArgs a) {
   __shared__ AdjLds<NBT, S> L;
-  adj_condense_body<NBT, S, false, FLY>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+  int64_t ei;
+  int g;
+  if (!sweep_item(n_el, (a.NS + S - 1) / S, ei, g)) return;
+  adj_condense_body<NBT, S, false, FLY>(elems[ei], g * S, m, f, a, L);
 }
 
 template <int NBT, int S, bool FLY>
-__global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                         FactorsDev f, AdjArgs a) {
+__global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restrict__ elems, int64_t n_el,
+                                                         MeshDev m, FactorsDev f, AdjArgs a) {
   __shared__ AdjLds<NBT, S> L;
-  adj_recover_body<NBT, S, false, FLY>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+  int64_t ei;
+  int g;
+  if (!sweep_item(n_el, (a.NS + S - 1) / S, ei, g)) return;
+  adj_recover_body<NBT, S, false, FLY>(elems[ei], g * S, m, f, a, L);
 }
 
 // Joint transposed sweep of one (element, group of S shots): the transposed
@@ -436,12 +442,15 @@ __global__ void __launch_bounds__(WT) adj_recover_kernel(const int32_t* __restri
 // with u~ handed over in LDS instead of written and read back, and one launch
 // fewer.
 template <int NBT, int S, bool FLY>
-__global__ void __launch_bounds__(WT) adj_joint_kernel(const int32_t* __restrict__ elems, MeshDev m,
+__global__ void __launch_bounds__(WT) adj_joint_kernel(const int32_t* __restrict__ elems, int64_t n_el, MeshDev m,
                                                        FactorsDev f, AdjArgs a) {
   __shared__ AdjLds<NBT, S> L;
   extern __shared__ double ukeep[];   // [interior levels][n_b * S] of the element
-  const int e = elems[blockIdx.x];
-  const int s0 = blockIdx.y * S;
+  int64_t ei;
+  int g;
+  if (!sweep_item(n_el, (a.NS + S - 1) / S, ei, g)) return;
+  const int e = elems[ei];
+  const int s0 = g * S;
   adj_recover_body<NBT, S, true, FLY>(e, s0, m, f, a, L, ukeep);
   __syncthreads();
   adj_condense_body<NBT, S, true, FLY>(e, s0, m, f, a, L, ukeep);
@@ -832,22 +841,24 @@ template <int NBT, int S>
 void launch_adj(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, const AdjArgs& a, hipStream_t st) {
   int64_t cnt = (int64_t)m->h_class_elems[cl].size();
   if (cnt == 0) return;
-  dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  dim3 grid((unsigned)sweep_blocks(cnt, (a.NS + S - 1) / S));
   if constexpr (3 * NBT <= WT) {
     if (sbfwi_fly_rows(f)) {
       if (condense)
-        hipLaunchKernelGGL((adj_condense_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f,
-                           a);
+        hipLaunchKernelGGL((adj_condense_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], cnt, m->d,
+                           f, a);
       else
-        hipLaunchKernelGGL((adj_recover_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f,
-                           a);
+        hipLaunchKernelGGL((adj_recover_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], cnt, m->d,
+                           f, a);
       return;
     }
   }
   if (condense)
-    hipLaunchKernelGGL((adj_condense_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((adj_condense_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], cnt, m->d, f,
+                       a);
   else
-    hipLaunchKernelGGL((adj_recover_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((adj_recover_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], cnt, m->d, f,
+                       a);
 }
 
 template <int NBT>
@@ -923,14 +934,16 @@ bool launch_adj_joint_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, const Ad
   if (cnt == 0) return true;
   const size_t dyn = (size_t)m->class_nmax[cl] * NBT * S * sizeof(double);
   if (sizeof(AdjLds<NBT, S>) + dyn > kAdjJointLdsMax) return false;
-  dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  dim3 grid((unsigned)sweep_blocks(cnt, (a.NS + S - 1) / S));
   if constexpr (3 * NBT <= WT) {
     if (sbfwi_fly_rows(f)) {
-      hipLaunchKernelGGL((adj_joint_kernel<NBT, S, true>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+      hipLaunchKernelGGL((adj_joint_kernel<NBT, S, true>), grid, dim3(WT), dyn, st, m->class_elems[cl], cnt, m->d, f,
+                         a);
       return true;
     }
   }
-  hipLaunchKernelGGL((adj_joint_kernel<NBT, S, false>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+  hipLaunchKernelGGL((adj_joint_kernel<NBT, S, false>), grid, dim3(WT), dyn, st, m->class_elems[cl], cnt, m->d, f,
+                     a);
   return true;
 }
 

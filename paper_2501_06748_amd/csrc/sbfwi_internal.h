@@ -22,6 +22,23 @@
 
 #define SBFWI_MAX_NB 24
 
+// Work item of block blockIdx.x in a sweep launch over n elements of a class and
+// G groups of shots: the grid has sweep_blocks(n, G) blocks, and the G groups of
+// one element sit kXcds block ids apart.  The dispatcher hands consecutive
+// blocks to the XCDs in turn, so an element's groups run on one XCD at about the
+// same time and share its L2 for the element's pivot blocks and for the state
+// lines, whose shots are adjacent.  Returns false for the padding blocks (the
+// whole block leaves).  With one group, block b takes element b.
+constexpr int kXcds = 8;
+__host__ __device__ inline int64_t sweep_blocks(int64_t n, int G) { return (n + kXcds - 1) / kXcds * kXcds * G; }
+__device__ inline bool sweep_item(int64_t n, int G, int64_t& ei, int& g) {
+  const int64_t b = blockIdx.x, tile = b / (kXcds * G);
+  const int r = (int)(b % (kXcds * G));
+  g = r / kXcds;
+  ei = tile * kXcds + r % kXcds;
+  return ei < n;
+}
+
 // Sweeps form the central-difference rows from the densities (fd_bands.h).
 struct FactorsDev;
 inline bool sbfwi_fly_rows(const FactorsDev& f);

@@ -444,19 +444,26 @@ __global__ void advance_step_kernel(int64_t* kdev) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *kdev = *kdev + 1;
 }
 
-// One block per (element of an n_b class, group of S shots).
+// One block per (element of an n_b class, group of S shots), blocks ordered by
+// sweep_item.
 template <int NBT, int S>
-__global__ void __launch_bounds__(WT) condense_kernel(const int32_t* __restrict__ elems, MeshDev m,
+__global__ void __launch_bounds__(WT) condense_kernel(const int32_t* __restrict__ elems, int64_t n_el, MeshDev m,
                                                       FactorsDev f, StepArgs a) {
   __shared__ StepLds<NBT, S> L;
-  condense_body<NBT, S>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+  int64_t ei;
+  int g;
+  if (!sweep_item(n_el, (a.NS + S - 1) / S, ei, g)) return;
+  condense_body<NBT, S>(elems[ei], g * S, m, f, a, L);
 }
 
 template <int NBT, int S, bool STORE>
-__global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__ elems, MeshDev m,
+__global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__ elems, int64_t n_el, MeshDev m,
                                                      FactorsDev f, StepArgs a) {
   __shared__ StepLds<NBT, S> L;
-  recover_body<NBT, S, STORE>(elems[blockIdx.x], blockIdx.y * S, m, f, a, L);
+  int64_t ei;
+  int g;
+  if (!sweep_item(n_el, (a.NS + S - 1) / S, ei, g)) return;
+  recover_body<NBT, S, STORE>(elems[ei], g * S, m, f, a, L);
 }
 
 // Joint sweep of one (element, group of S shots): the recover sweep of step k
@@ -467,12 +474,15 @@ __global__ void __launch_bounds__(WT) recover_kernel(const int32_t* __restrict__
 // read and written once per step (the condense takes its w from LDS), and one
 // launch is saved.
 template <int NBT, int S, bool STORE>
-__global__ void __launch_bounds__(WT) joint_kernel(const int32_t* __restrict__ elems, MeshDev m, FactorsDev f,
-                                                   StepArgs a) {
+__global__ void __launch_bounds__(WT) joint_kernel(const int32_t* __restrict__ elems, int64_t n_el, MeshDev m,
+                                                   FactorsDev f, StepArgs a) {
   __shared__ StepLds<NBT, S> L;
   extern __shared__ double wkeep[];   // [interior levels][n_b * S] of the element
-  const int e = elems[blockIdx.x];
-  const int s0 = blockIdx.y * S;
+  int64_t ei;
+  int g;
+  if (!sweep_item(n_el, (a.NS + S - 1) / S, ei, g)) return;
+  const int e = elems[ei];
+  const int s0 = g * S;
   recover_body<NBT, S, STORE>(e, s0, m, f, a, L, wkeep);
   __syncthreads();
   condense_body<NBT, S, true>(e, s0, m, f, a, L, wkeep);
@@ -571,13 +581,14 @@ void launch_cr(bool condense, sbfwi_mesh_s* m, int cl, const FactorsDev& f, cons
                hipStream_t st) {
   int64_t cnt = (int64_t)m->h_class_elems[cl].size();
   if (cnt == 0) return;
-  dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  dim3 grid((unsigned)sweep_blocks(cnt, (a.NS + S - 1) / S));
   if (condense)
-    hipLaunchKernelGGL((condense_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((condense_kernel<NBT, S>), grid, dim3(WT), 0, st, m->class_elems[cl], cnt, m->d, f, a);
   else if (a.xs || a.fs)
-    hipLaunchKernelGGL((recover_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((recover_kernel<NBT, S, true>), grid, dim3(WT), 0, st, m->class_elems[cl], cnt, m->d, f, a);
   else
-    hipLaunchKernelGGL((recover_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((recover_kernel<NBT, S, false>), grid, dim3(WT), 0, st, m->class_elems[cl], cnt, m->d, f,
+                       a);
 }
 
 template <int NBT>
@@ -648,11 +659,12 @@ bool launch_joint_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, const StepAr
   if (cnt == 0) return true;
   const size_t dyn = (size_t)m->class_nmax[cl] * NBT * S * sizeof(double);
   if (sizeof(StepLds<NBT, S>) + dyn > kJointLdsMax) return false;
-  dim3 grid((unsigned)cnt, (unsigned)((a.NS + S - 1) / S));
+  dim3 grid((unsigned)sweep_blocks(cnt, (a.NS + S - 1) / S));
   if (a.xs || a.fs)
-    hipLaunchKernelGGL((joint_kernel<NBT, S, true>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((joint_kernel<NBT, S, true>), grid, dim3(WT), dyn, st, m->class_elems[cl], cnt, m->d, f, a);
   else
-    hipLaunchKernelGGL((joint_kernel<NBT, S, false>), grid, dim3(WT), dyn, st, m->class_elems[cl], m->d, f, a);
+    hipLaunchKernelGGL((joint_kernel<NBT, S, false>), grid, dim3(WT), dyn, st, m->class_elems[cl], cnt, m->d, f,
+                       a);
   return true;
 }
 
