@@ -118,7 +118,7 @@ ROCPROF_NAME = {"joint": "joint_kernel<16, 4, false>", "joint_store": "joint_ker
                 "condense": "condense_kernel<16, 4>", "recover": "recover_kernel<16, 4, false>",
                 "recover_store": "recover_kernel<16, 4, true>", "adj_joint": "adj_joint_kernel<16, 4, true>",
                 "adj_condense": "adj_condense_kernel<16, 4, true>",
-                "adj_recover": "adj_recover_kernel<16, 4, true>", "grad_exact": "grad_exact_kernel<16, 4>"}
+                "adj_recover": "adj_recover_kernel<16, 4, true>", "grad_exact": "grad_exact_kernel<16, 4, false>"}
 
 
 def fem_bytes(nx, ny, S, R):

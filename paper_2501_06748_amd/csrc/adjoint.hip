@@ -561,15 +561,13 @@ __device__ __forceinline__ void flush_chunk(const double (&Gb)[GCH][NBT * S], in
 // loaded while the current level is computed; the results of GCH levels
 // collect in LDS and are added to the gradient together.
 template <int NBT, int S>
-__global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                        FactorsDev f, int NS, const double* __restrict__ X,
-                                                        const double* __restrict__ lam,
-                                                        const double* __restrict__ acc_a,
-                                                        double* __restrict__ grad, int s0, int64_t shot_stride) {
+__device__ __forceinline__ void grad_exact_group(int e, const MeshDev& m, const FactorsDev& f, int NS,
+                                                 const double* __restrict__ X, const double* __restrict__ lam,
+                                                 const double* __restrict__ acc_a, double* __restrict__ grad,
+                                                 int s0, int64_t shot_stride) {
   static_assert(NBT * S <= WT, "one (node, shot) item per lane");
   constexpr int GCH = 16;
   __shared__ double Gb[GCH][NBT * S]; // gradient per level of the chunk and item
-  const int e = elems[blockIdx.x];
   const int ns = min(S, NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1;
   const int64_t po = m.par_off[e], lo = m.loop_off[e], xo = m.x_off[e];
@@ -680,7 +678,7 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
 }
 
 // Exact gradient of the radial Galerkin scheme for one step, in the lane
-// organisation of grad_exact_kernel.  The level matrices E_m enter the
+// organisation of grad_exact_group.  The level matrices E_m enter the
 // Galerkin blocks of the two intervals around level m (as the interpolation
 // end 1 of interval m - 1 and end 0 of interval m), so the band entries of
 // the sensitivities at level m are
@@ -696,15 +694,13 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
 // row's adjoint, which equals the identity row's adjoint of the unused level
 // n + 1.)
 template <int NBT, int S>
-__global__ void __launch_bounds__(WT) grad_rg_kernel(const int32_t* __restrict__ elems, MeshDev m,
-                                                     FactorsDev f, int NS, const double* __restrict__ X,
-                                                     const double* __restrict__ lam,
-                                                     const double* __restrict__ acc_a,
-                                                     double* __restrict__ grad, int s0, int64_t shot_stride) {
+__device__ __forceinline__ void grad_rg_group(int e, const MeshDev& m, const FactorsDev& f, int NS,
+                                              const double* __restrict__ X, const double* __restrict__ lam,
+                                              const double* __restrict__ acc_a, double* __restrict__ grad, int s0,
+                                              int64_t shot_stride) {
   static_assert(NBT * S <= WT, "one (node, shot) item per lane");
   constexpr int GCH = 16;
   __shared__ double Gb[GCH][NBT * S]; // gradient per level of the chunk and item
-  const int e = elems[blockIdx.x];
   const int ns = min(S, NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1;
   const int64_t po = m.par_off[e], lo = m.loop_off[e], xo = m.x_off[e];
@@ -983,21 +979,40 @@ void launch_adj_joint(sbfwi_factors_s* fac, const AdjArgs& a, hipStream_t st) {
   }
 }
 
+// One block per element of a class: the shot groups of the element in turn, so
+// each gradient entry has one writer and receives its additions in a fixed
+// order (each group's memory-side adds complete before the next group's), and
+// the groups' reads of the element's rows share the caches.
+template <int NBT, int S, bool RG>
+__global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restrict__ elems, MeshDev m,
+                                                        FactorsDev f, int NS, const double* __restrict__ X,
+                                                        const double* __restrict__ lam,
+                                                        const double* __restrict__ acc_a, double* __restrict__ grad,
+                                                        int64_t shot_stride) {
+  const int e = elems[blockIdx.x];
+  for (int s0 = 0; s0 < NS; s0 += S) {
+    if (s0 > 0) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    if constexpr (RG)
+      grad_rg_group<NBT, S>(e, m, f, NS, X, lam, acc_a, grad, s0, shot_stride);
+    else
+      grad_exact_group<NBT, S>(e, m, f, NS, X, lam, acc_a, grad, s0, shot_stride);
+  }
+}
+
 template <int NBT, int S>
 void launch_grad_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, int NS, const double* X, const double* lam,
                      const double* acc, double* grad, int64_t stride, hipStream_t st) {
   int64_t cnt = (int64_t)m->h_class_elems[cl].size();
   if (cnt == 0) return;
-  // shot groups run one after another on the stream, so every gradient entry
-  // has a single writer at a time and the sum over shots is deterministic
-  for (int s0 = 0; s0 < NS; s0 += S) {
-    if (f.scheme == SBFWI_SCHEME_RADIAL_GALERKIN)
-      hipLaunchKernelGGL((grad_rg_kernel<NBT, S>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl], m->d,
-                         f, NS, X, lam, acc, grad, s0, stride);
-    else
-      hipLaunchKernelGGL((grad_exact_kernel<NBT, S>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl],
-                         m->d, f, NS, X, lam, acc, grad, s0, stride);
-  }
+  if (f.scheme == SBFWI_SCHEME_RADIAL_GALERKIN)
+    hipLaunchKernelGGL((grad_exact_kernel<NBT, S, true>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl],
+                       m->d, f, NS, X, lam, acc, grad, stride);
+  else
+    hipLaunchKernelGGL((grad_exact_kernel<NBT, S, false>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl],
+                       m->d, f, NS, X, lam, acc, grad, stride);
 }
 
 template <int S>
