@@ -37,12 +37,14 @@
 // every block assembles a supernode's vector in LDS once and then runs its
 // rows against it.  No atomics: results are bit-reproducible.
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <atomic>
 #include <numeric>
 #include <mutex>
 #include <thread>
 
+#include "dense_host.h"
 #include "sbfwi_internal.h"
 
 namespace {
@@ -295,7 +297,7 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
 // Runs fn(i) for i in [0, n) on up to `threads` host threads (dynamic assignment).
 template <typename Fn>
 void parallel_for(int64_t n, Fn&& fn) {
-  int threads = (int)std::min<int64_t>(n, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  int threads = (int)std::min<int64_t>(n, dense_threads());
   if (threads <= 1) {
     for (int64_t i = 0; i < n; ++i) fn(i);
     return;
@@ -659,41 +661,17 @@ void sbfwi_direct_sym_free(DirectSym* ds) {
 
 namespace {
 
-// Unit-lower-triangular inverse of the strictly-lower part of the leading n x n
-// block of A (row-major, leading dimension lda) into row-major out (n x n).
-void inv_unit_lower(const double* A, int64_t lda, int n, double* X) {
-  std::fill(X, X + (size_t)n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    X[(size_t)j * n + j] = 1.0;
-    for (int i = j + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s -= A[i * lda + k] * X[(size_t)k * n + j];
-      X[(size_t)i * n + j] = s;
-    }
-  }
-}
-
-// Inverse of the upper triangle (with diagonal) of the leading n x n block of A.
-void inv_upper(const double* A, int64_t lda, int n, double* X) {
-  std::fill(X, X + (size_t)n * n, 0.0);
-  for (int j = n - 1; j >= 0; --j) {
-    X[(size_t)j * n + j] = 1.0 / A[j * lda + j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= j; ++k) s -= A[i * lda + k] * X[(size_t)k * n + j];
-      X[(size_t)i * n + j] = s / A[i * lda + i];
-    }
-  }
-}
-
 // Per-supernode results of the elimination (row-major): P = L11^-1, Q = U11^-1,
 // L21 (nb x nj), U12 (nj x nb).
 struct FrontOut {
   std::vector<double> P, Q, L21, U12, upd;
 };
 
+// Assembles and eliminates the front of J; the dense work is shared among the
+// team's threads (team may be null).
 int eliminate_front(const DirectSym* ds, sbfwi_mesh_s* m, const std::vector<double>& K,
-                    const std::vector<double>& KT, std::vector<FrontOut>& fo, int J, std::vector<int64_t>& loc) {
+                    const std::vector<double>& KT, std::vector<FrontOut>& fo, int J, std::vector<int64_t>& loc,
+                    DenseTeam* team) {
   const int64_t j0 = ds->sn_ptr[J], j1 = ds->sn_ptr[J + 1];
   const int nj = (int)(j1 - j0);
   const int64_t b0 = ds->b_ptr[J];
@@ -730,24 +708,23 @@ int eliminate_front(const DirectSym* ds, sbfwi_mesh_s* m, const std::vector<doub
   for (int64_t p = j0; p < j1; ++p) loc[p] = -1;
   for (int r = 0; r < nb; ++r) loc[ds->bpos[b0 + r]] = -1;
   if (rc != SBFWI_OK) return rc;
-  for (int k = 0; k < nj; ++k) {
-    const double piv = F[(size_t)k * mf + k];
-    if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv))
-      return sbfwi_fail(SBFWI_ESINGULAR, "coarse matrix: zero pivot in the direct factorisation");
-    const double* rk = &F[(size_t)k * mf];
-    for (int64_t i = k + 1; i < mf; ++i) {
-      double* ri = &F[(size_t)i * mf];
-      const double l = ri[k] / piv;
-      ri[k] = l;
-      if (l != 0.0)
-        for (int64_t j = k + 1; j < mf; ++j) ri[j] -= l * rk[j];
-    }
-  }
+  if (dense_lu(F.data(), mf, nj, team) >= 0)
+    return sbfwi_fail(SBFWI_ESINGULAR, "coarse matrix: zero pivot in the direct factorisation");
   FrontOut& o = fo[J];
-  o.P.resize((size_t)nj * nj);
-  o.Q.resize((size_t)nj * nj);
-  inv_unit_lower(F.data(), mf, nj, o.P.data());
-  inv_upper(F.data(), mf, nj, o.Q.data());
+  o.P.assign((size_t)nj * nj, 0.0);
+  o.Q.assign((size_t)nj * nj, 0.0);
+  const int T = team ? team->size() : 1;
+  auto invert = [&](int t) {   // P = L11^-1 and Q = U11^-1, blocks of 16 columns dealt round the threads
+    for (int c0 = 16 * t; c0 < nj; c0 += 16 * T) {
+      const int c1 = std::min(nj, c0 + 16);
+      dense_inv_unit_lower(F.data(), mf, nj, o.P.data(), c0, c1);
+      dense_inv_upper(F.data(), mf, nj, o.Q.data(), c0, c1);
+    }
+  };
+  if (T > 1)
+    team->run(invert);
+  else
+    invert(0);
   o.L21.resize((size_t)nb * nj);
   o.U12.resize((size_t)nj * nb);
   for (int r = 0; r < nb; ++r)
@@ -761,21 +738,138 @@ int eliminate_front(const DirectSym* ds, sbfwi_mesh_s* m, const std::vector<doub
   return SBFWI_OK;
 }
 
-// rows [r0, r1) of out = [A | -A R]: A (nj x nj), R (nj x nc), both row-major; out rows have nj + nc entries
-void fold_rows(const double* A, const double* R, int nj, int64_t nc, int r0, int r1, double* out) {
-  const int64_t len = nj + nc;
-  for (int i = r0; i < r1; ++i) {
-    double* o = out + (size_t)i * len;
-    for (int k = 0; k < nj; ++k) o[k] = A[(size_t)i * nj + k];
-    double* t = o + nj;
-    for (int64_t c = 0; c < nc; ++c) t[c] = 0.0;
-    for (int k = 0; k < nj; ++k) {
-      const double a = A[(size_t)i * nj + k];
-      if (a == 0.0) continue;
-      const double* rk = R + (size_t)k * nc;
-      for (int64_t c = 0; c < nc; ++c) t[c] -= a * rk[c];
+// Eliminates the fronts level by level from the leaves (the fronts of one
+// level are independent).
+int eliminate_levels(const DirectSym* ds, sbfwi_mesh_s* m, const std::vector<double>& K,
+                     const std::vector<double>& KT, std::vector<FrontOut>& fo) {
+  const int64_t n = m->n_nodes;
+  const int T = dense_threads();
+  std::unique_ptr<DenseTeam> team;
+  std::vector<int64_t> team_loc;
+  for (int l = ds->depth; l >= 0; --l) {
+    const int q0 = ds->lvl_ptr[l], cnt = ds->lvl_ptr[l + 1] - q0;
+    if (cnt <= 4 && 2 * cnt <= T) {   // a few fronts (near the root, the largest): one at a time, every thread on it
+      if (!team) {
+        team.reset(new DenseTeam(T));
+        team_loc.assign(n, -1);
+      }
+      for (int q = q0; q < q0 + cnt; ++q) SBFWI_CHECK(eliminate_front(ds, m, K, KT, fo, ds->lvl_sn[q], team_loc, team.get()));
+      continue;
     }
+    // many fronts: one thread per front
+    std::atomic<int> rc{SBFWI_OK};
+    parallel_for(cnt, [&](int64_t q) {
+      thread_local std::vector<int64_t> loc;
+      if ((int64_t)loc.size() != n) loc.assign(n, -1);
+      int r = eliminate_front(ds, m, K, KT, fo, ds->lvl_sn[q0 + q], loc, nullptr);
+      if (r != SBFWI_OK) rc = r;
+    });
+    if (rc != SBFWI_OK)   // the message was recorded on a worker thread
+      return sbfwi_fail(rc.load(), rc == SBFWI_ESINGULAR ? "coarse matrix: zero pivot in the direct factorisation"
+                                                         : "direct factorisation: dissection misses a coupling");
   }
+  return SBFWI_OK;
+}
+
+// Row blocks of every supernode, K_g (index 0) and K_g^T (index 1), in host
+// buffers (not initialised: every entry is written once).
+struct RowBlocks {
+  std::unique_ptr<double[]> fw[2], bm[2];
+  int64_t nfw = 0, nbm = 0;
+};
+
+// Row blocks from the eliminated fronts: forward FW_J = [P_J ; L21_J P_J] and
+// FW^t_J = [Q_J^T ; U12_J^T Q_J^T]; backward BM_J = [Q_J | -Q_J U12_J] and
+// BM^t_J = [P_J^T | -P_J^T L21_J^T].  The right blocks of BM_J and BM^t_J are
+// the negated transposes of the lower blocks of FW^t_J and FW_J: each entry
+// takes the same products in the same order (a running sum from zero, steps
+// with a zero factor skipped), and 0 - s equals the running difference from
+// zero bit for bit.  The work is cut into tasks of a few rows each (the fronts
+// near the root hold most of it), largest first; every row is formed as a
+// whole by one task.
+void row_blocks(const DirectSym* ds, const std::vector<FrontOut>& fo, RowBlocks& rb) {
+  const int nS = ds->nS;
+  rb.nfw = ds->fw_off[nS];
+  rb.nbm = ds->bm_off[nS];
+  for (int t = 0; t < 2; ++t) {
+    rb.fw[t].reset(new double[std::max<int64_t>(rb.nfw, 1)]);
+    rb.bm[t].reset(new double[std::max<int64_t>(rb.nbm, 1)]);
+  }
+  auto nj_of = [&](int J) { return (int)(ds->sn_ptr[J + 1] - ds->sn_ptr[J]); };
+  auto nb_of = [&](int J) { return (int)(ds->b_ptr[J + 1] - ds->b_ptr[J]); };
+  struct Task {
+    int J, r0, r1;
+    int64_t cost;
+  };
+  constexpr int64_t kTaskWork = 1 << 17;   // multiply-adds (or moves) per task, about
+  auto make_tasks = [&](bool products) {
+    std::vector<Task> tasks;
+    for (int J = 0; J < nS; ++J) {
+      const int nj = nj_of(J), nb = nb_of(J);
+      const int rows = products ? nb : nj;
+      const int64_t row_cost = products ? 2 * (int64_t)nj * nj : 2 * (int64_t)(nj + nb);
+      const int chunk = (int)std::max<int64_t>(1, kTaskWork / std::max<int64_t>(row_cost, 1));
+      for (int r = 0; r < rows; r += chunk) {
+        const int r1 = std::min(rows, r + chunk);
+        tasks.push_back({J, r, r1, row_cost * (r1 - r)});
+      }
+    }
+    std::stable_sort(tasks.begin(), tasks.end(), [](const Task& a, const Task& b) { return a.cost > b.cost; });
+    return tasks;
+  };
+  // leading blocks of FW and FW^t: P_J and Q_J^T
+  parallel_for(nS, [&](int64_t Jq) {
+    const int J = (int)Jq, nj = nj_of(J);
+    const FrontOut& o = fo[J];
+    double* fw = rb.fw[0].get() + ds->fw_off[J];
+    double* fwt = rb.fw[1].get() + ds->fw_off[J];
+    std::copy(o.P.begin(), o.P.end(), fw);
+    for (int i = 0; i < nj; ++i)
+      for (int k = 0; k < nj; ++k) fwt[(size_t)i * nj + k] = o.Q[(size_t)k * nj + i];
+  });
+  // lower blocks: L21 P and U12^T Q^T, rows r0 .. r1 of each
+  const std::vector<Task> prod = make_tasks(true);
+  parallel_for((int64_t)prod.size(), [&](int64_t ti) {
+    const Task& t = prod[ti];
+    const int J = t.J, nj = nj_of(J), nb = nb_of(J), rows = t.r1 - t.r0;
+    const FrontOut& o = fo[J];
+    double* fw = rb.fw[0].get() + ds->fw_off[J];
+    double* fwt = rb.fw[1].get() + ds->fw_off[J];
+    double* c0 = fw + (int64_t)(nj + t.r0) * nj;
+    double* c1 = fwt + (int64_t)(nj + t.r0) * nj;
+    std::fill(c0, c0 + (int64_t)rows * nj, 0.0);
+    std::fill(c1, c1 + (int64_t)rows * nj, 0.0);
+    dense_mac(false, c0, nj, o.L21.data() + (size_t)t.r0 * nj, nj, 1, o.P.data(), nj, rows, nj, 0, nj);
+    dense_mac(false, c1, nj, o.U12.data() + t.r0, 1, nb, fwt, nj, rows, nj, 0, nj);
+  });
+  // BM and BM^t, rows r0 .. r1 of each
+  const std::vector<Task> back = make_tasks(false);
+  parallel_for((int64_t)back.size(), [&](int64_t ti) {
+    const Task& t = back[ti];
+    const int J = t.J, nj = nj_of(J), nb = nb_of(J);
+    const int64_t len = nj + nb;
+    const FrontOut& o = fo[J];
+    const double* fwl = rb.fw[0].get() + ds->fw_off[J] + (int64_t)nj * nj;    // L21 P, nb x nj
+    const double* fwtl = rb.fw[1].get() + ds->fw_off[J] + (int64_t)nj * nj;   // U12^T Q^T, nb x nj
+    double* bm = rb.bm[0].get() + ds->bm_off[J];
+    double* bmt = rb.bm[1].get() + ds->bm_off[J];
+    for (int i = t.r0; i < t.r1; ++i) {
+      double* b0 = bm + i * len;
+      double* b1 = bmt + i * len;
+      for (int k = 0; k < nj; ++k) {
+        b0[k] = o.Q[(size_t)i * nj + k];
+        b1[k] = o.P[(size_t)k * nj + i];
+      }
+    }
+    for (int c = 0; c < nb; ++c) {
+      const double* x0 = fwtl + (int64_t)c * nj;
+      const double* x1 = fwl + (int64_t)c * nj;
+      for (int i = t.r0; i < t.r1; ++i) {
+        bm[i * len + nj + c] = 0.0 - x0[i];
+        bmt[i * len + nj + c] = 0.0 - x1[i];
+      }
+    }
+  });
 }
 
 }  // namespace
@@ -784,72 +878,25 @@ int sbfwi_direct_factor(sbfwi_factors_s* f, hipStream_t s) {
   sbfwi_mesh_s* m = f->m;
   DirectSym* ds = m->dsym;
   if (!ds) return sbfwi_fail(SBFWI_EINVAL, "mesh has no dissection order");
-  const int64_t nnz = m->nnz, n = m->n_nodes;
+  const int64_t nnz = m->nnz;
   std::vector<double> K(nnz), KT(nnz);
   SBFWI_HIP(hipMemcpyAsync(K.data(), f->d.Kval, nnz * sizeof(double), hipMemcpyDeviceToHost, s));
   SBFWI_HIP(hipMemcpyAsync(KT.data(), f->d.KTval, nnz * sizeof(double), hipMemcpyDeviceToHost, s));
   SBFWI_HIP(hipStreamSynchronize(s));
-  const int nS = ds->nS;
-  std::vector<FrontOut> fo(nS);
-  // eliminate level by level from the leaves (the fronts of one level are independent)
-  for (int l = ds->depth; l >= 0; --l) {
-    const int q0 = ds->lvl_ptr[l], cnt = ds->lvl_ptr[l + 1] - q0;
-    std::atomic<int> rc{SBFWI_OK};
-    parallel_for(cnt, [&](int64_t q) {
-      thread_local std::vector<int64_t> loc;
-      if ((int64_t)loc.size() != n) loc.assign(n, -1);
-      int r = eliminate_front(ds, m, K, KT, fo, ds->lvl_sn[q0 + q], loc);
-      if (r != SBFWI_OK) rc = r;
-    });
-    if (rc != SBFWI_OK)   // the message was recorded on a worker thread
-      return sbfwi_fail(rc.load(), rc == SBFWI_ESINGULAR ? "coarse matrix: zero pivot in the direct factorisation"
-                                                         : "direct factorisation: dissection misses a coupling");
-  }
-  // row blocks: forward FW_J = [P_J ; L21_J P_J], backward BM_J = [Q_J | -Q_J U12_J];
-  // for K^T: [Q_J^T ; U12_J^T Q_J^T] and [P_J^T | -P_J^T L21_J^T]
-  const int64_t nfw = ds->fw_off[nS], nbm = ds->bm_off[nS];
-  std::vector<double> FW(nfw), BM(nbm), FWt(nfw), BMt(nbm);
-  parallel_for(nS, [&](int64_t Jq) {
-    const int J = (int)Jq;
-    const int nj = (int)(ds->sn_ptr[J + 1] - ds->sn_ptr[J]);
-    const int nb = (int)(ds->b_ptr[J + 1] - ds->b_ptr[J]);
-    const FrontOut& o = fo[J];
-    std::vector<double> Pt((size_t)nj * nj), Qt((size_t)nj * nj), L21t((size_t)nj * nb);
-    for (int i = 0; i < nj; ++i)
-      for (int k = 0; k < nj; ++k) {
-        Pt[(size_t)i * nj + k] = o.Q[(size_t)k * nj + i];   // (U11^-1)^T
-        Qt[(size_t)i * nj + k] = o.P[(size_t)k * nj + i];   // (L11^-1)^T
-      }
-    for (int r = 0; r < nb; ++r)
-      for (int k = 0; k < nj; ++k) L21t[(size_t)k * nb + r] = o.L21[(size_t)r * nj + k];
-    double* fw = &FW[ds->fw_off[J]];
-    double* fwt = &FWt[ds->fw_off[J]];
-    std::copy(o.P.begin(), o.P.end(), fw);
-    std::copy(Pt.begin(), Pt.end(), fwt);
-    for (int r = 0; r < nb; ++r) {   // C P with C = L21 (K_g) or U12^T (K_g^T)
-      double* a = fw + (size_t)(nj + r) * nj;
-      double* at = fwt + (size_t)(nj + r) * nj;
-      for (int k = 0; k < nj; ++k) a[k] = at[k] = 0.0;
-      for (int mm = 0; mm < nj; ++mm) {
-        const double c = o.L21[(size_t)r * nj + mm], ct = o.U12[(size_t)mm * nb + r];
-        const double* pr = &o.P[(size_t)mm * nj];
-        const double* ptr = &Pt[(size_t)mm * nj];
-        if (c != 0.0)
-          for (int k = 0; k < nj; ++k) a[k] += c * pr[k];
-        if (ct != 0.0)
-          for (int k = 0; k < nj; ++k) at[k] += ct * ptr[k];
-      }
-    }
-    fold_rows(o.Q.data(), o.U12.data(), nj, nb, 0, nj, &BM[ds->bm_off[J]]);
-    fold_rows(Qt.data(), L21t.data(), nj, nb, 0, nj, &BMt[ds->bm_off[J]]);
-  });
+  std::vector<FrontOut> fo(ds->nS);
+  SBFWI_CHECK(eliminate_levels(ds, m, K, KT, fo));
+  RowBlocks rb;
+  row_blocks(ds, fo, rb);
+  std::vector<FrontOut>().swap(fo);
   DirectNum* dn = new DirectNum();
   f->dnum = dn;
-  SBFWI_CHECK(sbfwi_upload(&dn->FW[0], FW));
-  SBFWI_CHECK(sbfwi_upload(&dn->BM[0], BM));
-  SBFWI_CHECK(sbfwi_upload(&dn->FW[1], FWt));
-  SBFWI_CHECK(sbfwi_upload(&dn->BM[1], BMt));
-  f->bytes += 8 * 2 * (nfw + nbm);
+  for (int t = 0; t < 2; ++t) {
+    SBFWI_CHECK(sbfwi_alloc(&dn->FW[t], rb.nfw));
+    SBFWI_CHECK(sbfwi_alloc(&dn->BM[t], rb.nbm));
+    SBFWI_CHECK(sbfwi_copy_sync(dn->FW[t], rb.fw[t].get(), rb.nfw * sizeof(double), hipMemcpyHostToDevice));
+    SBFWI_CHECK(sbfwi_copy_sync(dn->BM[t], rb.bm[t].get(), rb.nbm * sizeof(double), hipMemcpyHostToDevice));
+  }
+  f->bytes += 8 * 2 * (rb.nfw + rb.nbm);
   return SBFWI_OK;
 }
 
