@@ -21,7 +21,10 @@
 // in elimination order lies in J and from the children's update matrices;
 // its first |J| pivots are eliminated without pivoting (K_g is dominated by
 // the a0-weighted mass term), giving L11, U11, L21 = F21 U11^-1,
-// U12 = L11^-1 F12 and the update F22 - L21 U12 for J's parent.
+// U12 = L11^-1 F12 and the update F22 - L21 U12 for J's parent.  Levels with
+// many fronts take one host thread per front; the few large fronts near the
+// root take every thread in turn (dense kernels in dense_host.cpp, with the
+// textbook loops' operation order, so the factors do not depend on it).
 //
 // Solve (device, multifrontal).  Forward, L y = b, leaves first: with the
 // children's update vectors u_c (over their B sets), the front vector of J is
