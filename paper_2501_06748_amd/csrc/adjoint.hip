@@ -479,34 +479,64 @@ __global__ void __launch_bounds__(WT) adj_sweep_fused_kernel(const int32_t* __re
   }
 }
 
-// rhs_B = u~_B - sum_e psi_{n-1}^T z_{n-1} + adjoint source at the receivers.
-__global__ void adj_rhs_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a, double* __restrict__ rhs,
-                               int n_rec, const int64_t* __restrict__ rec_node, const double* __restrict__ adj,
-                               int64_t n_steps, int64_t k) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= m.n_nodes * NS) return;
-  int64_t node = g / NS;
-  int s = (int)(g % NS);
-  double acc = a.UB[g] + f.c1 * a.VB[g] + f.a0 * a.AB[g];
+// rhs_B = u~_B - sum_e psi_{n-1}^T z_{n-1} + adjoint source at the receivers,
+// for item g = (node, shot) from the nodal adjoint state (ub, vb, ab) of the item.
+__device__ __forceinline__ double adj_rhs_at(int64_t g, int NS, const MeshDev& m, const FactorsDev& f,
+                                             const AdjArgs& a, double ub, double vb, double ab, int n_rec,
+                                             const int64_t* __restrict__ rec_node, const double* __restrict__ adj,
+                                             int64_t n_steps, int64_t k) {
+  const int64_t node = g / NS;
+  const int s = (int)(g % NS);
+  double acc = ub + f.c1 * vb + f.a0 * ab;
   for (int64_t t = m.node_ptr[node]; t < m.node_ptr[node + 1]; ++t) acc -= a.gB[m.node_slot[t] * NS + s];
   if (adj)
     for (int r = 0; r < n_rec; ++r)
       if (rec_node[r] == node) acc += adj[((int64_t)s * n_rec + r) * n_steps + k - 1];
-  rhs[g] = acc;
+  return acc;
 }
 
-// Nodal adjoint Newmark chain.
-__global__ void adj_nodal_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= m.n_nodes * NS) return;
-  int64_t node = g / NS;
-  int s = (int)(g % NS);
+// Nodal adjoint Newmark chain of item g: the new (ub, vb, ab), stored.
+__device__ __forceinline__ void adj_nodal_at(int64_t g, int NS, const MeshDev& m, const FactorsDev& f,
+                                             const AdjArgs& a, double& ub, double& vb, double& ab) {
+  const int64_t node = g / NS;
+  const int s = (int)(g % NS);
   double wb = -a.AB[g];
   for (int64_t t = m.node_ptr[node]; t < m.node_ptr[node + 1]; ++t) wb += a.pl[m.node_slot[t] * NS + s];
-  double vb = a.VB[g];
-  a.UB[g] = -f.c1 * vb + f.a0 * wb;
-  a.VB[g] = f.c2 * vb + f.a1 * wb;
-  a.AB[g] = f.c3 * vb + f.a2 * wb;
+  const double v = a.VB[g];
+  ub = -f.c1 * v + f.a0 * wb;
+  vb = f.c2 * v + f.a1 * wb;
+  ab = f.c3 * v + f.a2 * wb;
+  a.UB[g] = ub;
+  a.VB[g] = vb;
+  a.AB[g] = ab;
+}
+
+__global__ void adj_rhs_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a, double* __restrict__ rhs,
+                               int n_rec, const int64_t* __restrict__ rec_node, const double* __restrict__ adj,
+                               int64_t n_steps, int64_t k) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m.n_nodes * NS) return;
+  rhs[g] = adj_rhs_at(g, NS, m, f, a, a.UB[g], a.VB[g], a.AB[g], n_rec, rec_node, adj, n_steps, k);
+}
+
+__global__ void adj_nodal_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m.n_nodes * NS) return;
+  double ub, vb, ab;
+  adj_nodal_at(g, NS, m, f, a, ub, vb, ab);
+}
+
+// The nodal chain of adjoint step k + 1 and the right-hand side of step k in
+// one pass over the items (nothing between them reads or writes the nodal
+// adjoint state once the joint transposed sweep has condensed step k).
+__global__ void adj_nodal_rhs_kernel(MeshDev m, int NS, FactorsDev f, AdjArgs a, double* __restrict__ rhs,
+                                     int n_rec, const int64_t* __restrict__ rec_node,
+                                     const double* __restrict__ adj, int64_t n_steps, int64_t k) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m.n_nodes * NS) return;
+  double ub, vb, ab;
+  adj_nodal_at(g, NS, m, f, a, ub, vb, ab);
+  rhs[g] = adj_rhs_at(g, NS, m, f, a, ub, vb, ab, n_rec, rec_node, adj, n_steps, k);
 }
 
 // Lanes of one wavefront exchanging values through LDS: the LDS operations of
@@ -1161,6 +1191,7 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
   // no recompute
   const int64_t tseg0 = (ck->tail_x && kind == 0) ? ck->tail_k0 / C : nseg;
   bool adj_condensed = false;   // the transposed condense of the next adjoint step is done
+  bool nodal_due = false;       // the last step's nodal chain is still to run
   int64_t n_grad = 0;   // contractions launched on sg
   if (ov || gs) {   // the side streams start after everything enqueued on st so far
     SBFWI_HIP(hipEventRecord(ev[4], st));
@@ -1214,9 +1245,14 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
         }
         if (!adj_condensed) launch_adj_sweep(true, f, a, st);
         {
-        ProfScope ps(PK_ADJ_RHS, st);
-        hipLaunchKernelGGL(adj_rhs_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a, w.rhs, ck->n_rec,
-                           ck->rec_node, adj_src, N, k);
+          ProfScope ps(PK_ADJ_RHS, st);
+          if (nodal_due)   // step k + 1's nodal chain, deferred to here
+            hipLaunchKernelGGL(adj_nodal_rhs_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a, w.rhs,
+                               ck->n_rec, ck->rec_node, adj_src, N, k);
+          else
+            hipLaunchKernelGGL(adj_rhs_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a, w.rhs, ck->n_rec,
+                               ck->rec_node, adj_src, N, k);
+          nodal_due = false;
         }
         SBFWI_HIP(hipGetLastError());
         SBFWI_CHECK(sbfwi_coarse_solve(f, &w.cw, 1, w.rhs, w.lamB, k, st));
@@ -1228,7 +1264,11 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
           launch_adj_sweep(false, f, a, st);
           adj_condensed = false;
         }
-        {
+        // the nodal chain of step k: joined with the right-hand side of step k - 1 when
+        // that step's transposed condense is already done (the joint sweep)
+        if (adj_condensed) {
+          nodal_due = true;
+        } else {
           ProfScope ps(PK_ADJ_NODAL, st);
           hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
         }
@@ -1260,6 +1300,11 @@ static int adjoint_run(sbfwi_factors_s* f, sbfwi_ckpt_s* ck, const double* adj_s
     // the segment's contractions read its store too: st waits for the last one
     if (gs && n_grad > 0) SBFWI_HIP(hipStreamWaitEvent(st, ev[7 + (int)((k0 + 1) % 2)], 0));
     if (ov) SBFWI_HIP(hipEventRecord(ev[2 + b], st));
+  }
+  if (nodal_due) {   // (step 1 never defers its chain; kept for safety)
+    ProfScope ps(PK_ADJ_NODAL, st);
+    hipLaunchKernelGGL(adj_nodal_kernel, dim3(gn), dim3(256), 0, st, m->d, NS, f->d, a);
+    SBFWI_HIP(hipGetLastError());
   }
   return SBFWI_OK;
 }
