@@ -241,8 +241,9 @@ def main():
                          "print nothing else and exit: the program profiled by hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(shots shard across GPUs by design, but it is not implemented)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(shots would shard across GPUs, with one all-reduce of the gradient; not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
