@@ -341,7 +341,7 @@ def main():
                "fem_step": {"launches": fem_prof["launches"], "avg_us": round(fem_avg * 1e6, 2),
                             "algorithmic_bytes_per_launch": fem_b, "GB/s": round(fem_gbs, 1),
                             "frac_hbm_peak": round(fem_gbs / HBM_PEAK_GBS, 3),
-                            "traffic": measured_traffic("fem_step", wl.name)}}
+                            "traffic": measured_traffic("fem_step", f"paper-{fg.nx}x{fg.ny}-{S}shots")}}
     if args.autotune:
         ft = factor(rho_true)
         plan = sb.sbfwi_autotune(ft, S)

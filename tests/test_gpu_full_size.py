@@ -32,17 +32,23 @@ import make_paper_gradient as golden  # noqa: E402
 
 
 @pytest.mark.skipif(not os.path.exists(golden.OUT), reason="golden file not written")
-def test_full_size_gradient_matches_the_oracle():
+@pytest.mark.parametrize("tail_gib", [0, 2])
+def test_full_size_gradient_matches_the_oracle(tail_gib):
+    """tail_gib 2: the forward run also keeps the unknowns and accelerations of
+    its last two segments (steps 4-8, 277 MB a step), as bench.py's tail store
+    does, and the backward pass recomputes only the first segment."""
     wl, wav, obs, elems = golden.case()
     g_elems, J_ref, tr_ref, g_ref = golden.load()
     assert np.array_equal(g_elems, elems)
     wl.wavelets = wav
     log(f"full size: {wl.mesh.n_elem} elements, {wl.mesh.n_nodes} nodes, 4 shots, {golden.STEPS} steps, "
-        f"direct solver, kept solutions, overlapped recompute")
+        f"direct solver, kept solutions, overlapped recompute, tail store {tail_gib} GiB")
     g = GpuModel(wl, wl.models["random30"], coarse_solver=1)
+    g.sb.sbfwi_set_launch(g.f, g.sb.LAUNCH_TAIL_STORE_KIB, tail_gib << 20)
     tr, mis, grad, ck = g.gradient(obs, n_steps=golden.STEPS, n_ckpt=-1)
     info = g.sb.sbfwi_ckpt_info(ck)
     assert info["interval"] == 3                     # segments 1-3, 4-6, 7-8
+    assert info["tail_steps"] == (5 if tail_gib else 0)
     launches = g.sb.sbfwi_direct_launches(g.mesh, 1)
     assert launches[-1]["subtrees"] == 1             # the transposed solve's subtree launch ran
     et = rel_l2(tr, tr_ref)
