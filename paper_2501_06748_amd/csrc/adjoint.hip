@@ -750,12 +750,15 @@ __device__ __forceinline__ void grad_rg_group(int e, const MeshDev& m, const Fac
     const double v = X[ok ? (xo + (int64_t)(l + 1) * nb + i) * NS + s0 + s : 0];
     return ok ? v : 0.0;
   };
-  auto ldl = [&](int r) -> double {   // signed adjoint of Galerkin row r (0 .. n)
+  auto ldl = [&](int r) -> double {   // adjoint of Galerkin row r (0 .. n) as stored
     const bool ok = act && r >= 0 && r <= n;
     const int fr = r < n ? r : n + 1;
     const double v = lam[ok ? (xo + (int64_t)(fr + 1) * nb + i) * NS + s0 + s : 0];
-    return ok ? (r < n ? v : -v) : 0.0;
+    return ok ? v : 0.0;
   };
+  // the boundary row's adjoint is stored with the opposite sign; the sign is
+  // applied where the value is used, so that no load waits inside a branch
+  auto sgn = [&](int r, double v) { return r == n ? -v : v; };
   auto lda = [&](int l) -> double {
     const bool ok = act && l >= 0 && l <= n;
     const double v = acc_a[ok ? (po + (int64_t)l * nb + i) * NS + s0 + s : 0];
@@ -770,8 +773,16 @@ __device__ __forceinline__ void grad_rg_group(int e, const MeshDev& m, const Fac
     const double* wl = W + (int64_t)(lev >= 1 ? lev - 1 : 0) * kRgW;
     const double* wr = W + (int64_t)(lev < n ? lev : n - 1) * kRgW;
     const bool hl = lev >= 1, hr = lev < n;
-    auto wL = [&](int o) { return hl ? wl[o] : 0.0; };
-    auto wR = [&](int o) { return hr ? wr[o] : 0.0; };
+    // both tables exist for every level (an element has at least one interval):
+    // unconditional loads, then a select, so that no branch orders the waits
+    auto wL = [&](int o) {
+      const double v = wl[o];
+      return hl ? v : 0.0;
+    };
+    auto wR = [&](int o) {
+      const double v = wr[o];
+      return hr ? v : 0.0;
+    };
     double Qk[4][3];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -781,7 +792,7 @@ __device__ __forceinline__ void grad_rg_group(int e, const MeshDev& m, const Fac
       Qk[k][2] = wR(b + 4 + 0 + 0) * xb + wR(b + 4 + 2 + 0) * xc;
     }
     const double Ap[3] = {wL(32 + 0 + 1) * aa, (wL(32 + 2 + 1) + wR(32 + 0 + 0)) * ab, wR(32 + 2 + 0) * ac};
-    const double Lp[3] = {la, lb, lc};
+    const double Lp[3] = {sgn(lev - 1, la), sgn(lev, lb), sgn(lev + 1, lc)};
     // node i + 1's quantities from its lane (every lane takes part in the exchange)
     double Lq[3], Qq[3], Zaq[3], Zbq[3], Yq[3], Aq[3];
 #pragma unroll
