@@ -727,14 +727,13 @@ template <int NBT, int S>
 __device__ __forceinline__ void grad_rg_group(int e, const MeshDev& m, const FactorsDev& f, int NS,
                                               const double* __restrict__ X, const double* __restrict__ lam,
                                               const double* __restrict__ acc_a, double* __restrict__ grad, int s0,
-                                              int64_t shot_stride) {
+                                              int64_t shot_stride, const double* W) {
   static_assert(NBT * S <= WT, "one (node, shot) item per lane");
   constexpr int GCH = 16;
   __shared__ double Gb[GCH][NBT * S]; // gradient per level of the chunk and item
   const int ns = min(S, NS - s0);
   const int nb = m.nb[e], n = m.nr[e] - 1;
   const int64_t po = m.par_off[e], lo = m.loop_off[e], xo = m.x_off[e];
-  const double* W = f.rgw + f.rgw_off[n + 1];
   const int it = threadIdx.x;
   const bool own = it < nb * S;
   const int i = own ? it / S : 0, s = it % S;
@@ -1031,13 +1030,20 @@ __global__ void __launch_bounds__(WT) grad_exact_kernel(const int32_t* __restric
                                                         const double* __restrict__ acc_a, double* __restrict__ grad,
                                                         int64_t shot_stride) {
   const int e = elems[blockIdx.x];
+  extern __shared__ double rg_w[];   // Galerkin: the weights of the element's n intervals, [n][kRgW]
+  if constexpr (RG) {
+    const int n = m.nr[e] - 1;
+    const double* W = f.rgw + f.rgw_off[n + 1];
+    for (int q = threadIdx.x; q < n * kRgW; q += WT) rg_w[q] = W[q];
+    __syncthreads();
+  }
   for (int s0 = 0; s0 < NS; s0 += S) {
     if (s0 > 0) {
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
     if constexpr (RG)
-      grad_rg_group<NBT, S>(e, m, f, NS, X, lam, acc_a, grad, s0, shot_stride);
+      grad_rg_group<NBT, S>(e, m, f, NS, X, lam, acc_a, grad, s0, shot_stride, rg_w);
     else
       grad_exact_group<NBT, S>(e, m, f, NS, X, lam, acc_a, grad, s0, shot_stride);
   }
@@ -1049,8 +1055,9 @@ void launch_grad_cls(sbfwi_mesh_s* m, int cl, const FactorsDev& f, int NS, const
   int64_t cnt = (int64_t)m->h_class_elems[cl].size();
   if (cnt == 0) return;
   if (f.scheme == SBFWI_SCHEME_RADIAL_GALERKIN)
-    hipLaunchKernelGGL((grad_exact_kernel<NBT, S, true>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl],
-                       m->d, f, NS, X, lam, acc, grad, stride);
+    hipLaunchKernelGGL((grad_exact_kernel<NBT, S, true>), dim3((unsigned)cnt), dim3(WT),
+                       (size_t)m->class_nmax[cl] * kRgW * sizeof(double), st, m->class_elems[cl], m->d, f, NS, X,
+                       lam, acc, grad, stride);
   else
     hipLaunchKernelGGL((grad_exact_kernel<NBT, S, false>), dim3((unsigned)cnt), dim3(WT), 0, st, m->class_elems[cl],
                        m->d, f, NS, X, lam, acc, grad, stride);
