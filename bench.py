@@ -236,6 +236,9 @@ def main():
                     help="tail store of the forward run in GiB (the fields of its last checkpoint segments, "
                          "so that the backward pass recomputes only the segments before them); -1 = the device "
                          "memory left free by everything else the evaluation needs, less 8 GiB")
+    ap.add_argument("--subtree-cut", type=int, default=0,
+                    help="direct solver: subtree launches rooted at the shallowest dissection level with at "
+                         "least this many supernodes (0 = the library's default, 512)")
     ap.add_argument("--counter-probe", type=int, default=0, metavar="K",
                     help="run K gradient steps of the workload (--nt steps each) plus a 1 GiB device copy, "
                          "print nothing else and exit: the program profiled by hardware-counter runs")
@@ -299,6 +302,8 @@ def main():
             sb.sbfwi_set_launch(f, sb.LAUNCH_GRAPHS, 1)
         sb.sbfwi_set_launch(f, 3, overlap)
         sb.sbfwi_set_launch(f, sb.LAUNCH_TAIL_STORE_KIB, tail_kib)
+        if args.subtree_cut:
+            sb.sbfwi_set_launch(f, sb.LAUNCH_SUBTREE_CUT, args.subtree_cut)
         if plan is not None:
             sb.apply_plan(f, plan)
         return f
