@@ -184,15 +184,23 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
       }
 #pragma unroll
       for (int s = 0; s < NSM; ++s) ps[s] = 0.0;
-      if (FWD && lane == 0) {
-        if (w.ngl > 0)
+      if (FWD && lane == 0 && w.ngl > 0) {
+        // every shot's entries are loaded before any is used (shots past ns reread shot
+        // s0, a second entry is read again from the first when there is none), so that
+        // the loads are in flight together
+        const int64_t g1 = w.ngl > 1 ? w.g1 : w.g0;
+        double t0[NSM], t1[NSM];
 #pragma unroll
-          for (int s = 0; s < NSM; ++s)
-            if (s < ns) ps[s] += upd[w.g0 * NS + s0 + s];
-        if (w.ngl > 1)
+        for (int s = 0; s < NSM; ++s) {
+          t0[s] = upd[w.g0 * NS + s0 + (s < ns ? s : 0)];
+          t1[s] = upd[g1 * NS + s0 + (s < ns ? s : 0)];
+        }
 #pragma unroll
-          for (int s = 0; s < NSM; ++s)
-            if (s < ns) ps[s] += upd[w.g1 * NS + s0 + s];
+        for (int s = 0; s < NSM; ++s)
+          if (s < ns) {
+            ps[s] += t0[s];
+            if (w.ngl > 1) ps[s] += t1[s];
+          }
       }
     };
     load_row(S.r0 + threadIdx.x / G, rr, a, pass);
@@ -200,17 +208,26 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
       const DVRec v = p.vrec[q];
       double acc[NSM];
       const double* src = FWD ? in : (v.ngl ? upd : in);
+      // as in load_row: all shots' loads issued before any value is used
+      double t[NSM];
 #pragma unroll
-      for (int s = 0; s < NSM; ++s) acc[s] = s < ns ? src[v.src * NS + s0 + s] : 0.0;
-      if (FWD) {
-        if (v.ngl > 0)
+      for (int s = 0; s < NSM; ++s) t[s] = src[v.src * NS + s0 + (s < ns ? s : 0)];
 #pragma unroll
-          for (int s = 0; s < NSM; ++s)
-            if (s < ns) acc[s] -= upd[v.g0 * NS + s0 + s];
-        if (v.ngl > 1)
+      for (int s = 0; s < NSM; ++s) acc[s] = s < ns ? t[s] : 0.0;
+      if (FWD && v.ngl > 0) {
+        const int64_t g1 = v.ngl > 1 ? v.g1 : v.g0;
+        double t0[NSM], t1[NSM];
 #pragma unroll
-          for (int s = 0; s < NSM; ++s)
-            if (s < ns) acc[s] -= upd[v.g1 * NS + s0 + s];
+        for (int s = 0; s < NSM; ++s) {
+          t0[s] = upd[v.g0 * NS + s0 + (s < ns ? s : 0)];
+          t1[s] = upd[g1 * NS + s0 + (s < ns ? s : 0)];
+        }
+#pragma unroll
+        for (int s = 0; s < NSM; ++s)
+          if (s < ns) {
+            acc[s] -= t0[s];
+            if (v.ngl > 1) acc[s] -= t1[s];
+          }
       }
 #pragma unroll
       for (int s = 0; s < NSM; ++s) vec[v.slot * NSM + s] = acc[s];
