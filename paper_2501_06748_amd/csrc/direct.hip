@@ -195,12 +195,12 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
           t0[s] = upd[w.g0 * NS + s0 + (s < ns ? s : 0)];
           t1[s] = upd[g1 * NS + s0 + (s < ns ? s : 0)];
         }
+        const bool two = w.ngl > 1;
 #pragma unroll
-        for (int s = 0; s < NSM; ++s)
-          if (s < ns) {
-            ps[s] += t0[s];
-            if (w.ngl > 1) ps[s] += t1[s];
-          }
+        for (int s = 0; s < NSM; ++s) {   // selects, not branches: both loads are used
+          const double p1 = ps[s] + t0[s], p2 = p1 + t1[s];
+          ps[s] = s < ns ? (two ? p2 : p1) : ps[s];
+        }
       }
     };
     load_row(S.r0 + threadIdx.x / G, rr, a, pass);
@@ -208,26 +208,27 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
       const DVRec v = p.vrec[q];
       double acc[NSM];
       const double* src = FWD ? in : (v.ngl ? upd : in);
-      // as in load_row: all shots' loads issued before any value is used
+      // as in load_row: every load issued before any value is used (a missing
+      // child entry reads entry 0, which always exists, and is not used)
       double t[NSM];
 #pragma unroll
       for (int s = 0; s < NSM; ++s) t[s] = src[v.src * NS + s0 + (s < ns ? s : 0)];
-#pragma unroll
-      for (int s = 0; s < NSM; ++s) acc[s] = s < ns ? t[s] : 0.0;
-      if (FWD && v.ngl > 0) {
-        const int64_t g1 = v.ngl > 1 ? v.g1 : v.g0;
+      if (FWD) {
+        const int64_t g0 = v.ngl > 0 ? v.g0 : 0, g1 = v.ngl > 1 ? v.g1 : g0;
         double t0[NSM], t1[NSM];
 #pragma unroll
         for (int s = 0; s < NSM; ++s) {
-          t0[s] = upd[v.g0 * NS + s0 + (s < ns ? s : 0)];
+          t0[s] = upd[g0 * NS + s0 + (s < ns ? s : 0)];
           t1[s] = upd[g1 * NS + s0 + (s < ns ? s : 0)];
         }
 #pragma unroll
-        for (int s = 0; s < NSM; ++s)
-          if (s < ns) {
-            acc[s] -= t0[s];
-            if (v.ngl > 1) acc[s] -= t1[s];
-          }
+        for (int s = 0; s < NSM; ++s) {
+          const double a1 = t[s] - t0[s], a2 = a1 - t1[s];
+          acc[s] = s < ns ? (v.ngl > 1 ? a2 : (v.ngl > 0 ? a1 : t[s])) : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < NSM; ++s) acc[s] = s < ns ? t[s] : 0.0;
       }
 #pragma unroll
       for (int s = 0; s < NSM; ++s) vec[v.slot * NSM + s] = acc[s];
