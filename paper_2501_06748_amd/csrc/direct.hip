@@ -173,8 +173,13 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
   for (int64_t st = sa; st < sb; ++st) {
     const DStep S = p.steps[st];
     DRRec rr{}, nrr{};
-    double a[U], pass[NSM], na[U], npass[NSM];
-    auto load_row = [&](int64_t r, DRRec& w, double (&x)[U], double (&ps)[NSM]) {
+    // with up to 8 shots the pass-through entries are kept as loaded and added at
+    // the row's write, so that no wait for them comes before the other loads of the
+    // step are issued (with 16 the registers would not suffice)
+    constexpr bool kDefer = NSM <= 8;
+    constexpr int NP2 = kDefer ? NSM : 1;
+    double a[U], pass[NSM], pass2[NP2], na[U], npass[NSM], npass2[NP2];
+    auto load_row = [&](int64_t r, DRRec& w, double (&x)[U], double (&ps)[NSM], double (&ps2)[NP2]) {
       w = r < S.r1 ? p.rrec[r] : DRRec{};
       const double* v = vals + w.val;
 #pragma unroll
@@ -184,6 +189,8 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
       }
 #pragma unroll
       for (int s = 0; s < NSM; ++s) ps[s] = 0.0;
+#pragma unroll
+      for (int s = 0; s < NP2; ++s) ps2[s] = 0.0;
       if (FWD && lane == 0 && w.ngl > 0) {
         // every shot's entries are loaded before any is used (shots past ns reread shot
         // s0, a second entry is read again from the first when there is none), so that
@@ -195,17 +202,30 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
           t0[s] = upd[w.g0 * NS + s0 + (s < ns ? s : 0)];
           t1[s] = upd[g1 * NS + s0 + (s < ns ? s : 0)];
         }
-        const bool two = w.ngl > 1;
+        if constexpr (kDefer) {
 #pragma unroll
-        for (int s = 0; s < NSM; ++s) {   // selects, not branches: both loads are used
-          const double p1 = ps[s] + t0[s], p2 = p1 + t1[s];
-          ps[s] = s < ns ? (two ? p2 : p1) : ps[s];
+          for (int s = 0; s < NSM; ++s) {
+            ps[s] = t0[s];
+            ps2[s] = t1[s];
+          }
+        } else {
+          const bool two = w.ngl > 1;
+#pragma unroll
+          for (int s = 0; s < NSM; ++s) {   // selects, not branches: both loads are used
+            const double p1 = ps[s] + t0[s], p2 = p1 + t1[s];
+            ps[s] = s < ns ? (two ? p2 : p1) : ps[s];
+          }
         }
       }
     };
-    load_row(S.r0 + threadIdx.x / G, rr, a, pass);
-    for (int64_t q = S.v0 + threadIdx.x; q < S.v1; q += DT) {
-      const DVRec v = p.vrec[q];
+    // this thread's first slot record is requested with the first row record, before
+    // the row's values, so that the gather's entries and the row's values are in
+    // flight together
+    const int64_t q0 = S.v0 + threadIdx.x;
+    const DVRec v0 = p.vrec[q0 < S.v1 ? q0 : S.v0];
+    load_row(S.r0 + threadIdx.x / G, rr, a, pass, pass2);
+    for (int64_t q = q0; q < S.v1; q += DT) {
+      const DVRec v = q == q0 ? v0 : p.vrec[q];
       double acc[NSM];
       const double* src = FWD ? in : (v.ngl ? upd : in);
       // as in load_row: every load issued before any value is used (a missing
@@ -240,9 +260,9 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
       // the next pass's row is loaded while this one is computed (short chunks only: the
       // subtree launches' wide chunks would not leave room for a second set of registers)
       if constexpr (U <= 8) {
-        if (base + DT / G < S.r1) load_row(r + DT / G, nrr, na, npass);
+        if (base + DT / G < S.r1) load_row(r + DT / G, nrr, na, npass, npass2);
       } else {
-        if (base != S.r0) load_row(r, rr, a, pass);
+        if (base != S.r0) load_row(r, rr, a, pass, pass2);
       }
       double acc[NSM];
 #pragma unroll
@@ -286,7 +306,12 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
           } else {
 #pragma unroll
             for (int s = 0; s < NSM; ++s) {
-              acc[s] += pass[s];
+              double add = pass[s];
+              if constexpr (kDefer) {   // the running sum load_row forms otherwise: (0 + e0) + e1
+                const double p1 = 0.0 + pass[s], p2 = p1 + pass2[s];
+                add = rr.ngl > 1 ? p2 : (rr.ngl > 0 ? p1 : 0.0);
+              }
+              acc[s] += add;
               if (s < ns) upd[rr.out * NS + s0 + s] = acc[s];
             }
           }
@@ -307,6 +332,8 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
         for (int u = 0; u < U; ++u) a[u] = na[u];
 #pragma unroll
         for (int s = 0; s < NSM; ++s) pass[s] = npass[s];
+#pragma unroll
+        for (int s = 0; s < NP2; ++s) pass2[s] = npass2[s];
       }
     }
     __syncthreads();   // the next step reads this one's results and reuses the LDS vectors
