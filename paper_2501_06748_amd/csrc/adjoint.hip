@@ -488,7 +488,7 @@ __device__ __forceinline__ double adj_rhs_at(int64_t g, int NS, const MeshDev& m
   const int64_t node = g / NS;
   const int s = (int)(g % NS);
   double acc = ub + f.c1 * vb + f.a0 * ab;
-  for (int64_t t = m.node_ptr[node]; t < m.node_ptr[node + 1]; ++t) acc -= a.gB[m.node_slot[t] * NS + s];
+  acc = node_gather<true>(acc, m.node_slot, m.node_ptr[node], m.node_ptr[node + 1], a.gB, NS, s);
   if (adj)
     for (int r = 0; r < n_rec; ++r)
       if (rec_node[r] == node) acc += adj[((int64_t)s * n_rec + r) * n_steps + k - 1];
@@ -501,7 +501,7 @@ __device__ __forceinline__ void adj_nodal_at(int64_t g, int NS, const MeshDev& m
   const int64_t node = g / NS;
   const int s = (int)(g % NS);
   double wb = -a.AB[g];
-  for (int64_t t = m.node_ptr[node]; t < m.node_ptr[node + 1]; ++t) wb += a.pl[m.node_slot[t] * NS + s];
+  wb = node_gather<false>(wb, m.node_slot, m.node_ptr[node], m.node_ptr[node + 1], a.pl, NS, s);
   const double v = a.VB[g];
   ub = -f.c1 * v + f.a0 * wb;
   vb = f.c2 * v + f.a1 * wb;

@@ -39,6 +39,30 @@ __device__ inline bool sweep_item(int64_t n, int G, int64_t& ei, int& g) {
   return ei < n;
 }
 
+// acc + sum (SUB: minus) of arr[slot * NS + s] over the loop slots
+// node_slot[t0 .. t1) of a node, added in that order.  The first four slots and
+// their values are loaded together (an absent one reads slot entry t0, or 0 for
+// an empty range, and is not added), so that a node's entries cost one chain of
+// two loads rather than one per slot.
+template <bool SUB>
+__device__ inline double node_gather(double acc, const int64_t* __restrict__ node_slot, int64_t t0, int64_t t1,
+                                     const double* __restrict__ arr, int NS, int s) {
+  constexpr int C = 4;
+  int64_t sl[C];
+  double v[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) sl[c] = node_slot[t0 + c < t1 ? t0 + c : (t1 > t0 ? t0 : 0)];
+#pragma unroll
+  for (int c = 0; c < C; ++c) v[c] = arr[sl[c] * NS + s];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const double n = SUB ? acc - v[c] : acc + v[c];
+    acc = t0 + c < t1 ? n : acc;
+  }
+  for (int64_t t = t0 + C; t < t1; ++t) acc = SUB ? acc - arr[node_slot[t] * NS + s] : acc + arr[node_slot[t] * NS + s];
+  return acc;
+}
+
 // Sweeps form the central-difference rows from the densities (fd_bands.h).
 struct FactorsDev;
 inline bool sbfwi_fly_rows(const FactorsDev& f);

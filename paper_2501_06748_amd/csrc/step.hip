@@ -527,7 +527,7 @@ __global__ void rhs_kernel(MeshDev m, int NS, const double* __restrict__ fhat, d
   int64_t node = g / NS;
   int s = (int)(g % NS);
   double acc = 0.0;
-  for (int64_t t = m.node_ptr[node]; t < m.node_ptr[node + 1]; ++t) acc += fhat[m.node_slot[t] * NS + s];
+  acc = node_gather<false>(acc, m.node_slot, m.node_ptr[node], m.node_ptr[node + 1], fhat, NS, s);
   if (src.amp) {
     int64_t idx = src.reversed ? (src.amp_steps - k) : (k - 1);
     for (int c = 0; c < src.n_src; ++c) {
