@@ -172,13 +172,14 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
   bool bad = false;
   for (int64_t st = sa; st < sb; ++st) {
     const DStep S = p.steps[st];
-    DRRec rr{}, nrr{};
-    // with up to 8 shots the pass-through entries are kept as loaded and added at
-    // the row's write, so that no wait for them comes before the other loads of the
-    // step are issued (with 16 the registers would not suffice)
-    constexpr bool kDefer = NSM <= 8;
+    DRRec rr{};
+    // the pass-through entries are kept as loaded and added at the row's write, so
+    // that no wait for them comes before the other loads of the step are issued
+    // (not with 16 shots in a subtree launch's wide rows: the registers would not
+    // leave two waves per SIMD)
+    constexpr bool kDefer = NSM < 16 || U <= 8;
     constexpr int NP2 = kDefer ? NSM : 1;
-    double a[U], pass[NSM], pass2[NP2], na[U], npass[NSM], npass2[NP2];
+    double a[U], pass[NSM], pass2[NP2];
     auto load_row = [&](int64_t r, DRRec& w, double (&x)[U], double (&ps)[NSM], double (&ps2)[NP2]) {
       w = r < S.r1 ? p.rrec[r] : DRRec{};
       const double* v = vals + w.val;
@@ -257,13 +258,8 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
     for (int64_t base = S.r0; base < S.r1; base += DT / G) {
       const int64_t r = base + threadIdx.x / G;
       const bool valid = r < S.r1;
-      // the next pass's row is loaded while this one is computed (short chunks only: the
-      // subtree launches' wide chunks would not leave room for a second set of registers)
-      if constexpr (U <= 8) {
-        if (base + DT / G < S.r1) load_row(r + DT / G, nrr, na, npass, npass2);
-      } else {
-        if (base != S.r0) load_row(r, rr, a, pass, pass2);
-      }
+      // a later pass loads its rows here (a level launch's block has one pass)
+      if (base != S.r0) load_row(r, rr, a, pass, pass2);
       double acc[NSM];
 #pragma unroll
       for (int s = 0; s < NSM; ++s) acc[s] = 0.0;
@@ -325,15 +321,6 @@ __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk
         }
 #pragma unroll
         for (int s = 0; s < NSM; ++s) bad = bad || (s < ns && !isfinite(acc[s]));
-      }
-      if constexpr (U <= 8) {
-        rr = nrr;
-#pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = na[u];
-#pragma unroll
-        for (int s = 0; s < NSM; ++s) pass[s] = npass[s];
-#pragma unroll
-        for (int s = 0; s < NP2; ++s) pass2[s] = npass2[s];
       }
     }
     __syncthreads();   // the next step reads this one's results and reuses the LDS vectors
