@@ -146,11 +146,13 @@ struct Dissect {
 // 16 for the subtree launches, whose steps hold many short rows; a fixed
 // butterfly to sum) and write it: forward to y by position (kind 0) or, plus
 // the children's update entries of the row, to the update vector (kind 1);
-// backward to x by position and by node.  A thread's first row record, its
-// first chunk of values and its pass-through entries are loaded before the
-// vector is assembled, and each later pass's while the previous one
-// computes.  Shots s0 .. s0 + NSM - 1 of NS are handled.  A block barrier separates the steps, whose later ones
-// read what earlier ones wrote.
+// backward to x by position and by node.  A step costs three memory round
+// trips: the step record; a thread's first slot record and first row record;
+// then the row's values, its pass-through entries and the slot's entries of
+// every shot, all requested before any is used.  A later pass of a subtree
+// step loads its rows as it starts.  Shots s0 .. s0 + NSM - 1 of NS are
+// handled.  A block barrier separates the steps, whose later ones read what
+// earlier ones wrote.
 template <int NSM, bool FWD, int U>
 __global__ void __launch_bounds__(DT) direct_prog_kernel(DProgDev p, int64_t blk0, int64_t st0, int G,
                                                          const double* __restrict__ vals, int NS, int s0,
